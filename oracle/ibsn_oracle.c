@@ -1,0 +1,760 @@
+/*
+ * ibsn_oracle.c -- plain FP64 CPU reference of the Inexact Bregman Sparse Newton
+ * (IBSN) method for exact optimal transport.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or calls
+ * this file; only the tests, the smoke check and the benchmark's CPU-baseline leg
+ * do.  It shares no code, header, table or helper with the HIP implementation.
+ *
+ * Problem (eq. (1)): min <C,X> over X>=0 with X1=a, X^T1=b.
+ * Outer loop (eq. (3), Algorithm 2): X^{k+1} ~ argmin <C,X> + eta*D_phi(X,X^k).
+ * Semi-dual subproblem (eq. (6)):
+ *     L^k(gamma) = -b^T gamma + eta * sum_i a_i log sum_j X^k_ij exp((gamma_j-C_ij)/eta).
+ *
+ * Prox centre held implicitly.  X^0 = a b^T (Algorithm 2 input) and
+ * X^{k+1} = diag(a) P^k(gamma) (eq. (7)) give, for every k,
+ *     log X^k_ij = r_i + s_j - k*C_ij/eta,
+ * with r = log a, s = log b at k = 0 and r <- log a - lse(gamma), s <- s + gamma/eta
+ * at each outer update.  The row constant r_i cancels in P (eq. (7)), so every dense
+ * pass works on
+ *     theta_ij = fma(-sigma, C_ij, w_j),   sigma = (k+1)/eta,   w_j = s_j + gamma_j/eta,
+ * and the row log-normaliser of the subproblem is r_i + lse_i with lse_i = LSE_j theta_ij.
+ *
+ * Row state.  A "row state" (M_i, S_i) represents P_ij = exp(theta_ij - M_i) / S_i.
+ * A fresh evaluation sets M_i = max_j theta_ij and S_i = sum_j exp(theta_ij - M_i), so
+ * P is eq. (7) written with the usual max shift (the common factor exp(-M_i) cancels).
+ * Keeping M_i (an exact copy of one theta value) and S_i (an O(1..n) number) apart,
+ * instead of their sum lse_i, keeps theta_ij - M_i exact for the entries that matter
+ * even when sigma*C is large.
+ *
+ * Conventions fixed where the paper is silent (each one is listed with its reason in
+ * the design notes of the repository):
+ *  - i* = lowest index among the maxima of a (Algorithm 1 input).
+ *  - threshold test P_ij >= rho is inclusive (Algorithm 1, step 3).
+ *  - norms of g in rho and in the shift are Euclidean (notation paragraph).
+ *  - CG starts from 0 and stops when ||r|| <= min(0.1, ||g||)*||g|| or at cg_maxit.
+ *  - Armijo decrease L(gamma+t*Delta)-L(gamma) is evaluated in difference form,
+ *    see orc_trial().
+ *  - Sinkhorn warm-up re-centres gamma after every gamma-step (centering does not
+ *    change P, g or the Newton iterates: L(gamma + c1) = L(gamma) since 1^T b = 1 = 1^T a).
+ *  - Column sums are accumulated over 64 fixed row chunks, in chunk order, so results
+ *    do not depend on the number of OpenMP threads.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NCHUNK 64
+
+/* status codes */
+#define ORC_OK 0
+#define ORC_WARN_MAXITER 1
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_CAP (-2)
+#define ORC_ERR_NUMERIC (-4)
+
+/* cost element: kind 0 = float64, kind 1 = float32 (widened exactly to double) */
+static inline double cost_at(const void *C, int kind, int64_t ldc, int64_t i, int64_t j)
+{
+    if (kind == 1)
+        return (double)((const float *)C)[i * ldc + j];
+    return ((const double *)C)[i * ldc + j];
+}
+
+static inline double theta_at(const void *C, int kind, int64_t ldc, int64_t i, int64_t j,
+                              double sigma, const double *w)
+{
+    return fma(-sigma, cost_at(C, kind, ldc, i, j), w[j]);
+}
+
+/* w_j = s_j + gamma_j / eta */
+static void make_w(int64_t n, const double *s, const double *gamma, double eta, double *w)
+{
+    for (int64_t j = 0; j < n; ++j)
+        w[j] = s[j] + gamma[j] / eta;
+}
+
+static double dot(int64_t n, const double *x, const double *y)
+{
+    double acc = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        acc += x[j] * y[j];
+    return acc;
+}
+
+static double nrm2(int64_t n, const double *x) { return sqrt(dot(n, x, x)); }
+
+/* ------------------------------------------------------------------------- */
+/* Eval pass: eq. (5) (best zeta as a row LSE), eq. (6) (objective), eq. (7) (P)  */
+/* and eq. (8) (gradient g = P^T a - b).                                          */
+/* ------------------------------------------------------------------------- */
+int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
+             const double *r, const double *s, const double *gamma, const double *a,
+             const double *b, double *M, double *S, double *c, double *g, double *L,
+             double *plan /* m*n (row-major) or NULL */)
+{
+    if (m < 1 || n < 1 || !(eta > 0))
+        return ORC_ERR_ARG;
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n);
+    make_w(n, s, gamma, eta, w);
+
+    /* row max and row sum of exp(theta - max) */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double mx = -INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            double th = theta_at(C, kind, ldc, i, j, sigma, w);
+            if (th > mx)
+                mx = th;
+        }
+        double sum = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            sum += exp(theta_at(C, kind, ldc, i, j, sigma, w) - mx);
+        M[i] = mx;
+        S[i] = sum;
+    }
+
+    /* column marginals c_j = sum_i a_i P_ij */
+    double *part = calloc((size_t)ORC_NCHUNK * n, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < ORC_NCHUNK; ++q) {
+        int64_t i0 = m * q / ORC_NCHUNK, i1 = m * (q + 1) / ORC_NCHUNK;
+        double *pc = part + (size_t)q * n;
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                double p = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]) / S[i];
+                pc[j] += a[i] * p;
+                if (plan)
+                    plan[i * n + j] = a[i] * p;
+            }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int q = 0; q < ORC_NCHUNK; ++q)
+            acc += part[(size_t)q * n + j];
+        c[j] = acc;
+        g[j] = acc - b[j];
+    }
+    free(part);
+
+    /* L = -b^T gamma + eta * sum_i a_i (r_i + M_i + log S_i) */
+    if (L) {
+        double t = 0.0;
+        for (int64_t i = 0; i < m; ++i)
+            t += a[i] * (r[i] + M[i] + log(S[i]));
+        *L = -dot(n, b, gamma) + eta * t;
+    }
+    free(w);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Armijo trial pass (Algorithm 2, step 9).                                        */
+/* Exact algebra for the change of the objective along gamma + t*Delta:            */
+/*   L(gamma+t Delta) - L(gamma) = -t b^T Delta + eta * sum_i a_i delta_i,         */
+/*   delta_i = log( sum_j q_ij e^{tau_j} / sum_j q_ij ),  q_ij = exp(theta_ij-M_i),  */
+/*   tau_j = t*Delta_j/eta.                                                          */
+/* delta_i = log1p(sum_j q_ij expm1(tau_j) / sum_j q_ij) keeps full relative        */
+/* precision when t*Delta is tiny (near convergence), where a difference of two      */
+/* separately rounded objective values would be pure rounding noise.                 */
+/* The trial's plan is P'_ij = q_ij e^{tau_j} / sum_l q_il e^{tau_l} (eq. (7) at the */
+/* new point, written relative to the current one); its column sums give c', g'.     */
+/* The new row state is M'_i = M_i + tau_max + log max_j(q_ij E_j),                  */
+/* S'_i = sum_j q_ij E_j / max_j(q_ij E_j), with E_j = exp(tau_j - tau_max).         */
+/* ------------------------------------------------------------------------- */
+int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
+              const double *s, const double *gamma, const double *a, const double *b,
+              const double *M, const double *Delta, double t, double *dL /* out */,
+              double *M_new, double *S_new, double *c_new, double *g_new)
+{
+    if (m < 1 || n < 1 || !(eta > 0))
+        return ORC_ERR_ARG;
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n);
+    double *tau = malloc(sizeof(double) * n);
+    double *E = malloc(sizeof(double) * n);
+    double *F = malloc(sizeof(double) * n);
+    double *delta = malloc(sizeof(double) * m);
+    double *Z = malloc(sizeof(double) * m);
+    double *mx = malloc(sizeof(double) * m);
+    make_w(n, s, gamma, eta, w);
+    double tau_max = -INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+        tau[j] = t * Delta[j] / eta;
+        if (tau[j] > tau_max)
+            tau_max = tau[j];
+    }
+    const int small_step = tau_max <= 500.0;
+    for (int64_t j = 0; j < n; ++j) {
+        E[j] = exp(tau[j] - tau_max);
+        F[j] = small_step ? expm1(tau[j]) : 0.0;
+    }
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double A = 0.0, B = 0.0, Zi = 0.0, qmax = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double q = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]);
+            A += q;
+            B += q * F[j];
+            double qe = q * E[j];
+            Zi += qe;
+            if (qe > qmax)
+                qmax = qe;
+        }
+        /* a step that pushes every entry of a row below the FP64 range leaves no
+           usable plan: mark the trial as not a decrease */
+        delta[i] = !(Zi > 0.0) ? INFINITY : (small_step ? log1p(B / A) : tau_max + log(Zi / A));
+        Z[i] = Zi;
+        mx[i] = qmax;
+    }
+
+    double *part = calloc((size_t)ORC_NCHUNK * n, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < ORC_NCHUNK; ++q) {
+        int64_t i0 = m * q / ORC_NCHUNK, i1 = m * (q + 1) / ORC_NCHUNK;
+        double *pc = part + (size_t)q * n;
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                double qv = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]);
+                pc[j] += a[i] * (qv * E[j] / Z[i]);
+            }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int q = 0; q < ORC_NCHUNK; ++q)
+            acc += part[(size_t)q * n + j];
+        c_new[j] = acc;
+        g_new[j] = acc - b[j];
+    }
+    free(part);
+
+    double sd = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        sd += a[i] * delta[i];
+    *dL = -t * dot(n, b, Delta) + eta * sd;
+    for (int64_t i = 0; i < m; ++i) {
+        M_new[i] = M[i] + (tau_max + log(mx[i]));
+        S_new[i] = Z[i] / mx[i];
+    }
+    free(w); free(tau); free(E); free(F); free(delta); free(Z); free(mx);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 1: Hessian sparsification.  P_ij = exp(theta_ij - M_i)/S_i.           */
+/* For i != i*: keep P_ij >= rho and divide the kept entries by their sum.          */
+/* Row i* is copied whole.  Output CSR (row_ptr[m+1], col[nnz], val[nnz]) in row    */
+/* order, columns ascending, and d = P_rho^T a.                                     */
+/* Returns nnz, or -(needed nnz) - 1 when cap is too small (nothing else written    */
+/* except row_ptr).  A row whose entries all fall below rho is left empty.          */
+/* ------------------------------------------------------------------------- */
+int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
+                     double eta, const double *s, const double *gamma, const double *a,
+                     const double *M, const double *S, double rho, int64_t istar, int64_t cap,
+                     int64_t *row_ptr, int32_t *col, double *val, double *d)
+{
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n);
+    make_w(n, s, gamma, eta, w);
+    int64_t *cnt = malloc(sizeof(int64_t) * m);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        if (i == istar) {
+            cnt[i] = n;
+            continue;
+        }
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            double p = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]) / S[i];
+            if (p >= rho)
+                ++c;
+        }
+        cnt[i] = c;
+    }
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < m; ++i)
+        row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    int64_t nnz = row_ptr[m];
+    free(cnt);
+    if (nnz > cap) {
+        free(w);
+        return -nnz - 1;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t o = row_ptr[i];
+        double kappa = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double p = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]) / S[i];
+            if (i == istar || p >= rho) {
+                col[o] = (int32_t)j;
+                val[o] = p;
+                kappa += p;
+                ++o;
+            }
+        }
+        if (i != istar && kappa > 0.0)
+            for (int64_t e = row_ptr[i]; e < o; ++e)
+                val[e] = val[e] / kappa;
+    }
+    /* d = P_rho^T a (serial scatter in row order) */
+    for (int64_t j = 0; j < n; ++j)
+        d[j] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            d[col[e]] += a[i] * val[e];
+    free(w);
+    return nnz;
+}
+
+/* H_rho v = (diag(P_rho^T a) v - P_rho^T diag(a) P_rho v)/eta  (Algorithm 1, step 4),
+   plus shift*v (Algorithm 2, step 8).  H_rho is never formed. */
+void orc_hvp(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+             const double *d, const double *a, double eta, double shift, const double *v,
+             double *y)
+{
+    double *u = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *wv = calloc((size_t)n, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            acc += val[e] * v[col[e]];
+        u[i] = acc;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            wv[col[e]] += val[e] * (a[i] * u[i]);
+    for (int64_t j = 0; j < n; ++j)
+        y[j] = (d[j] * v[j] - wv[j]) / eta + shift * v[j];
+    free(u);
+    free(wv);
+}
+
+/* Conjugate gradients for (H_rho + shift I) x = rhs, x0 = 0 (Algorithm 2, step 8;
+   CG on the complement of the kernel span{1}, Theorem 3.2 and the text after it).
+   Stops when ||r|| <= tol or after maxit iterations.  Returns the iteration count. */
+int orc_cg(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+           const double *d, const double *a, double eta, double shift, const double *rhs,
+           double tol, int maxit, double *x)
+{
+    double *r = malloc(sizeof(double) * n), *p = malloc(sizeof(double) * n),
+           *Ap = malloc(sizeof(double) * n);
+    for (int64_t j = 0; j < n; ++j) {
+        x[j] = 0.0;
+        r[j] = rhs[j];
+        p[j] = rhs[j];
+    }
+    double rr = dot(n, r, r);
+    int it = 0;
+    while (sqrt(rr) > tol && it < maxit) {
+        orc_hvp(m, n, row_ptr, col, val, d, a, eta, shift, p, Ap);
+        double pAp = dot(n, p, Ap);
+        if (!(pAp > 0.0))
+            break;
+        double alpha = rr / pAp;
+        for (int64_t j = 0; j < n; ++j) {
+            x[j] += alpha * p[j];
+            r[j] -= alpha * Ap[j];
+        }
+        double rr_new = dot(n, r, r);
+        double beta = rr_new / rr;
+        for (int64_t j = 0; j < n; ++j)
+            p[j] = r[j] + beta * p[j];
+        rr = rr_new;
+        ++it;
+    }
+    free(r); free(p); free(Ap);
+    return it;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inexact stop test and certificate.                                              */
+/* X_ij = a_i P_ij with P from the row state.  Algorithm 3 (rounding onto Omega,    */
+/* literal: y uses the column sums of X), then                                      */
+/*   D_phi(Xhat, X) = sum Xhat log(Xhat/X) - Xhat + X          (eq. (3)),           */
+/* evaluated with log X_ij = log a_i + theta_ij - M_i - log S_i so that an X that    */
+/* underflows does not make the term infinite; 0 log 0 = 0.                          */
+/* Certificate: for a dual vector v, zeta_i = min_j (C_ij - v_j) (c-transform,       */
+/* appendix C.1) makes (zeta, v) feasible for the dual LP, so a^T zeta + b^T v is a  */
+/* lower bound on the optimum; <C,Xhat> is an upper bound.  Two vectors are tried:   */
+/* gamma itself (the paper's choice) and the entropic potential of the current plan, */
+/* psi_j = (w_j - log b_j)/sigma (X_ij = a_i b_j exp(sigma (f_i + psi_j - C_ij))),    */
+/* and the larger bound is reported.  The relative KKT residual of appendix C.1 is   */
+/* evaluated for (X, gamma, zeta^c(gamma)).                                          */
+/* out[0] = D_phi, out[1] = <C,Xhat>, out[2] = best dual bound, out[3] = <C,X>,     */
+/* out[4] = Delta_kkt, out[5] = min Xhat, out[6] = ||e_r||_1, out[7] = <X,U>,        */
+/* out[8] = dual bound from gamma, out[9] = dual bound from psi.                      */
+/* ------------------------------------------------------------------------- */
+int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
+             const double *s, const double *gamma, const double *a, const double *b,
+             const double *M, const double *S, double *out, double *xhat /* m*n or NULL */)
+{
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n);
+    make_w(n, s, gamma, eta, w);
+    double *z = malloc(sizeof(double) * m), *er = malloc(sizeof(double) * m);
+    double *colX = calloc((size_t)n, sizeof(double)), *colF = calloc((size_t)n, sizeof(double));
+    double *y = malloc(sizeof(double) * n), *ec = malloc(sizeof(double) * n);
+    double *X = malloc(sizeof(double) * (size_t)m * n);
+    double *logX = malloc(sizeof(double) * (size_t)m * n);
+    double *zc = malloc(sizeof(double) * m);
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double la = log(a[i]), ls = log(S[i]);
+        for (int64_t j = 0; j < n; ++j) {
+            double th = theta_at(C, kind, ldc, i, j, sigma, w);
+            X[i * n + j] = a[i] * (exp(th - M[i]) / S[i]);
+            logX[i * n + j] = la + (th - M[i]) - ls;
+        }
+    }
+    /* Algorithm 3, steps 2-4: z_i = min(a_i / sum_j X_ij, 1) */
+    for (int64_t i = 0; i < m; ++i) {
+        double rs = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            rs += X[i * n + j];
+        z[i] = fmin(a[i] / rs, 1.0);
+    }
+    /* steps 6-8: y_j = min(b_j / sum_i X_ij, 1) */
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            colX[j] += X[i * n + j];
+    for (int64_t j = 0; j < n; ++j)
+        y[j] = fmin(b[j] / colX[j], 1.0);
+    /* steps 5, 9: F = diag(z) X diag(y); step 10: e_r = a - F1, e_c = b - F^T 1 */
+    double er1 = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double rs = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double f = z[i] * X[i * n + j] * y[j];
+            rs += f;
+            colF[j] += f;
+        }
+        er[i] = a[i] - rs;
+        er1 += fabs(er[i]);
+    }
+    for (int64_t j = 0; j < n; ++j)
+        ec[j] = b[j] - colF[j];
+
+    /* step 11 and the divergence / certificate sums */
+    double dphi = 0.0, cxh = 0.0, cx = 0.0, xmin = INFINITY, xu = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double zmin = INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            double u = cost_at(C, kind, ldc, i, j) - gamma[j];
+            if (u < zmin)
+                zmin = u;
+        }
+        zc[i] = zmin;
+        for (int64_t j = 0; j < n; ++j) {
+            double x = X[i * n + j];
+            double f = z[i] * x * y[j];
+            double xh = er1 > 0.0 ? f + er[i] * ec[j] / er1 : f;
+            double cij = cost_at(C, kind, ldc, i, j);
+            if (xhat)
+                xhat[i * n + j] = xh;
+            if (xh > 0.0)
+                dphi += xh * (log(xh) - logX[i * n + j]) - xh + x;
+            else
+                dphi += x;
+            cxh += cij * xh;
+            cx += cij * x;
+            if (xh < xmin)
+                xmin = xh;
+            xu += x * ((cij - gamma[j]) - zmin);
+        }
+    }
+    double dual_g = dot(m, a, zc) + dot(n, b, gamma);
+    double *psi = malloc(sizeof(double) * n);
+    for (int64_t j = 0; j < n; ++j)
+        psi[j] = (w[j] - log(b[j])) / sigma;
+    double dual_p = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double zmin = INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            double u = cost_at(C, kind, ldc, i, j) - psi[j];
+            if (u < zmin)
+                zmin = u;
+        }
+        dual_p += a[i] * zmin;
+    }
+    dual_p += dot(n, b, psi);
+    free(psi);
+    double dual = fmax(dual_g, dual_p);
+
+    /* Delta_kkt (appendix C.1) for (X, gamma, zeta^c); U >= 0 by construction */
+    double rr = 0.0, cc = 0.0, xf = 0.0, cf = 0.0, neg = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double rs = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double x = X[i * n + j];
+            rs += x;
+            xf += x * x;
+            if (x < 0.0)
+                neg += x * x;
+            double cij = cost_at(C, kind, ldc, i, j);
+            cf += cij * cij;
+        }
+        rr += (rs - a[i]) * (rs - a[i]);
+    }
+    for (int64_t j = 0; j < n; ++j)
+        cc += (colX[j] - b[j]) * (colX[j] - b[j]);
+    double dp = fmax(sqrt(rr) / (1.0 + nrm2(m, a)), sqrt(cc) / (1.0 + nrm2(n, b)));
+    dp = fmax(dp, sqrt(neg) / (1.0 + sqrt(xf)));
+    double dc = fabs(xu) / (1.0 + sqrt(cf));
+
+    out[0] = dphi;
+    out[1] = cxh;
+    out[2] = dual;
+    out[3] = cx;
+    out[4] = fmax(dp, dc);
+    out[5] = xmin;
+    out[6] = er1;
+    out[7] = xu;
+    out[8] = dual_g;
+    out[9] = dual_p;
+    free(w); free(z); free(er); free(colX); free(colF); free(y); free(ec); free(X); free(logX);
+    free(zc);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Full IBSN (Algorithm 2) with the practical schedule of Section 5 "Setup".        */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double sigma_armijo, beta;        /* 1e-4, 0.8 */
+    double sinkhorn_tol;              /* 1e-3 */
+    int sinkhorn_maxit;               /* 10000 */
+    double mu0, mu_floor;             /* 1e-4, 1e-11 */
+    double gap_tol, marg_tol, kkt_tol; /* 1e-8, 1e-9, 0 (off) */
+    int max_outer, max_newton, max_backtrack, cg_maxit; /* cg_maxit <= 0 -> min(n, 1000) */
+    double cg_forcing_max;            /* 0.1 */
+    int rho_mode;                     /* 0 paper rule, 1 rho = 0 (no sparsification) */
+} orc_options;
+
+typedef struct {
+    int64_t outer, newton, cg, sinkhorn, backtracks, stop_tests;
+    double grad_norm, primal, dual, rel_gap, kkt, dphi, marg_l1;
+    int status;
+} orc_report;
+
+void orc_default_options(orc_options *o)
+{
+    o->sigma_armijo = 1e-4;
+    o->beta = 0.8;
+    o->sinkhorn_tol = 1e-3;
+    o->sinkhorn_maxit = 10000;
+    o->mu0 = 1e-4;
+    o->mu_floor = 1e-11;
+    o->gap_tol = 1e-8;
+    o->marg_tol = 1e-9;
+    o->kkt_tol = 0.0;
+    o->max_outer = 300;
+    o->max_newton = 1000;
+    o->max_backtrack = 60;
+    o->cg_maxit = 0;
+    o->cg_forcing_max = 0.1;
+    o->rho_mode = 0;
+}
+
+static double nrm1(int64_t n, const double *x)
+{
+    double acc = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        acc += fabs(x[j]);
+    return acc;
+}
+
+static void center(int64_t n, double *gamma)
+{
+    double mean = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        mean += gamma[j];
+    mean /= (double)n;
+    for (int64_t j = 0; j < n; ++j)
+        gamma[j] -= mean;
+}
+
+/* gamma_io: in = warm start (or NULL -> 0), out = final dual.
+   r_io, s_io, k_io: optional outer state (resume when *k_io > 0 and r_io, s_io given).
+   plan_out: rounded plan Xhat (m*n) or NULL.  trace: optional per-outer log
+   [outer][6] = {newton, cg, rel_gap, grad_norm, dphi, kkt}. */
+int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const double *a,
+              const double *b, double eta, const orc_options *opt_in, double *gamma_io,
+              double *r_io, double *s_io, int64_t *k_io, double *plan_out, orc_report *rep,
+              double *trace, int64_t trace_cap)
+{
+    if (m < 1 || n < 1 || !(eta > 0))
+        return ORC_ERR_ARG;
+    orc_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        orc_default_options(&opt);
+    int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)(n < 1000 ? n : 1000);
+
+    double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * n);
+    double *gamma = malloc(sizeof(double) * n);
+    double *M = malloc(sizeof(double) * m), *S = malloc(sizeof(double) * m);
+    double *c = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n);
+    double *Mt = malloc(sizeof(double) * m), *St = malloc(sizeof(double) * m);
+    double *ct = malloc(sizeof(double) * n), *gt = malloc(sizeof(double) * n);
+    double *Delta = malloc(sizeof(double) * n), *rhs = malloc(sizeof(double) * n);
+    double *d = malloc(sizeof(double) * n);
+    int64_t *row_ptr = malloc(sizeof(int64_t) * (m + 1));
+    int64_t k = 0;
+    if (k_io && *k_io > 0 && r_io && s_io) {
+        k = *k_io;
+        memcpy(r, r_io, sizeof(double) * m);
+        memcpy(s, s_io, sizeof(double) * n);
+    } else {
+        for (int64_t i = 0; i < m; ++i)
+            r[i] = log(a[i]);
+        for (int64_t j = 0; j < n; ++j)
+            s[j] = log(b[j]);
+    }
+    for (int64_t j = 0; j < n; ++j)
+        gamma[j] = gamma_io ? gamma_io[j] : 0.0;
+    if (k == 0)
+        center(n, gamma); /* Lemma 4.1 needs 1^T gamma^{0,0} = 0; a resumed state already has it */
+
+    int64_t istar = 0;
+    for (int64_t i = 1; i < m; ++i)
+        if (a[i] > a[istar])
+            istar = i;
+
+    orc_report R;
+    memset(&R, 0, sizeof(R));
+    R.status = ORC_WARN_MAXITER;
+    double stop_out[10] = {0};
+    double L;
+    int64_t k0 = k;
+    for (; k < k0 + opt.max_outer; ++k) {
+        double mu = fmax(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
+        /* Algorithm 2, step 3: Sinkhorn warm-up (semi-dual form: the zeta-step is the row
+           LSE of the eval pass, the gamma-step rescales the columns to b) */
+        orc_eval(m, n, C, kind, ldc, k, eta, r, s, gamma, a, b, M, S, c, g, &L, NULL);
+        for (int it = 0; it < opt.sinkhorn_maxit && nrm2(n, g) >= opt.sinkhorn_tol; ++it) {
+            for (int64_t j = 0; j < n; ++j)
+                gamma[j] += eta * (log(b[j]) - log(c[j]));
+            center(n, gamma); /* step 4 */
+            orc_eval(m, n, C, kind, ldc, k, eta, r, s, gamma, a, b, M, S, c, g, &L, NULL);
+            ++R.sinkhorn;
+        }
+        int stopped = 0;
+        int64_t newton_k = 0, cg_k = 0;
+        for (int v = 0; v < opt.max_newton; ++v) {
+            double gn = nrm2(n, g);
+            double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / ((double)m * (double)n); /* step 6 */
+            int64_t nnz = orc_sparsify(m, n, C, kind, ldc, k, eta, s, gamma, a, M, S, rho, istar,
+                                       0, row_ptr, NULL, NULL, NULL);
+            nnz = -nnz - 1;
+            int32_t *col = malloc(sizeof(int32_t) * (nnz > 0 ? nnz : 1));
+            double *val = malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
+            orc_sparsify(m, n, C, kind, ldc, k, eta, s, gamma, a, M, S, rho, istar, nnz, row_ptr,
+                         col, val, d); /* step 7 */
+            for (int64_t j = 0; j < n; ++j)
+                rhs[j] = -g[j];
+            double tol = fmin(opt.cg_forcing_max, gn) * gn;
+            int it = orc_cg(m, n, row_ptr, col, val, d, a, eta, gn, rhs, tol, cg_maxit,
+                            Delta); /* step 8 */
+            cg_k += it;
+            free(col);
+            free(val);
+            double gd = dot(n, g, Delta);
+            double t = 1.0, dL = 0.0;
+            int bt = 0, accepted = 0;
+            for (;;) { /* step 9: Armijo backtracking on a finite decrease */
+                orc_trial(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, Delta, t, &dL, Mt, St, ct,
+                          gt);
+                if (isfinite(dL) && dL <= opt.sigma_armijo * t * gd) {
+                    accepted = 1;
+                    break;
+                }
+                if (bt >= opt.max_backtrack)
+                    break;
+                t *= opt.beta;
+                ++bt;
+            }
+            R.backtracks += bt;
+            if (!accepted) /* no acceptable step: keep gamma and end the inner loop */
+                break;
+            for (int64_t j = 0; j < n; ++j) /* step 10 */
+                gamma[j] += t * Delta[j];
+            memcpy(M, Mt, sizeof(double) * m);
+            memcpy(S, St, sizeof(double) * m);
+            memcpy(c, ct, sizeof(double) * n);
+            memcpy(g, gt, sizeof(double) * n);
+            L += dL;
+            ++newton_k;
+            /* step 12 with the practical schedule: gradient gate, then D_phi test */
+            if (nrm2(n, g) < mu) {
+                orc_stop(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, S, stop_out, NULL);
+                ++R.stop_tests;
+                if (stop_out[0] <= (double)(m < n ? m : n) * mu) {
+                    stopped = 1;
+                    break;
+                }
+            }
+        }
+        if (!stopped) {
+            orc_stop(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, S, stop_out, NULL);
+            ++R.stop_tests;
+        }
+        R.newton += newton_k;
+        R.cg += cg_k;
+        double primal = stop_out[1], dual = stop_out[2];
+        double relgap = (primal - dual) / fabs(primal);
+        double marg = nrm1(n, g);
+        if (trace && (k - k0) < trace_cap) {
+            double *tr = trace + (k - k0) * 6;
+            tr[0] = (double)newton_k;
+            tr[1] = (double)cg_k;
+            tr[2] = relgap;
+            tr[3] = nrm2(n, g);
+            tr[4] = stop_out[0];
+            tr[5] = stop_out[4];
+        }
+        R.primal = primal;
+        R.dual = dual;
+        R.rel_gap = relgap;
+        R.kkt = stop_out[4];
+        R.dphi = stop_out[0];
+        R.grad_norm = nrm2(n, g);
+        R.marg_l1 = marg;
+        int done = (relgap <= opt.gap_tol && (opt.marg_tol <= 0 || marg <= opt.marg_tol)) ||
+                   (opt.kkt_tol > 0 && stop_out[4] <= opt.kkt_tol);
+        if (plan_out && (done || k + 1 == k0 + opt.max_outer))
+            orc_stop(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, S, stop_out, plan_out);
+        /* Algorithm 2, step 13: X^{k+1} = X^{k,v+1}: r = log a - lse, s = w, k = k+1 */
+        for (int64_t i = 0; i < m; ++i)
+            r[i] = log(a[i]) - (M[i] + log(S[i]));
+        for (int64_t j = 0; j < n; ++j)
+            s[j] = s[j] + gamma[j] / eta;
+        if (done) {
+            R.status = ORC_OK;
+            ++k;
+            break;
+        }
+    }
+    R.outer = k - k0;
+    if (gamma_io)
+        memcpy(gamma_io, gamma, sizeof(double) * n);
+    if (r_io)
+        memcpy(r_io, r, sizeof(double) * m);
+    if (s_io)
+        memcpy(s_io, s, sizeof(double) * n);
+    if (k_io)
+        *k_io = k;
+    if (rep)
+        *rep = R;
+    free(r); free(s); free(gamma); free(M); free(S); free(c); free(g); free(Mt); free(St);
+    free(ct); free(gt); free(Delta); free(rhs); free(d); free(row_ptr);
+    return R.status;
+}
