@@ -1,0 +1,200 @@
+/*
+ * ibsn.h -- C ABI of libibsn.so, the MI355X (gfx950) hot path of the Inexact
+ * Bregman Sparse Newton (IBSN) method for exact optimal transport.
+ *
+ * The problem (eq. (1)) is   min <C,X>  s.t.  X 1 = a,  X^T 1 = b,  X >= 0,
+ * with C >= 0 (m x n), a > 0 (m), b > 0 (n), 1^T a = 1^T b = 1.  IBSN solves it by
+ * the Bregman proximal point iteration of eq. (3) and Algorithm 2; each proximal
+ * subproblem is solved in its semi-dual form (eq. (6)) by a Sinkhorn warm-up and a
+ * sparsified (Algorithm 1), gradient-shifted Newton-CG method with Armijo steps.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array pointers are DEVICE pointers (HIP, the context's device) unless the
+ *    argument is marked "host".  All floating point arrays are IEEE FP64, C order.
+ *  - The caller owns every array it passes (inputs and outputs); the library never
+ *    frees them.  The library owns its context workspace and ibsn_csr handles.
+ *  - Calls are enqueued on the context's stream and are asynchronous, except that a
+ *    call returning a host value (marked "host out") synchronises that stream.
+ *  - One context per host thread; a context may be used from one thread at a time.
+ *  - Return value: IBSN_OK (0), a positive warning (results valid), or a negative
+ *    error (nothing is written past the point of the error; ibsn_last_error() holds
+ *    a message).
+ *
+ * Prox centre (row a1 of the path)
+ * --------------------------------
+ * X^0 = a b^T and X^{k+1} = diag(a) P^k(gamma) (eq. (7)) give, for every k,
+ *     log X^k_ij = r_i + s_j - k C_ij / eta,
+ * so the centre is held implicitly as (k, r, s): r = log a, s = log b at k = 0 and
+ * r <- log a - lse, s <- s + gamma/eta, k <- k+1 at an outer update.
+ * Every dense pass forms  theta_ij = fma(-sigma, C_ij, w_j)  with
+ * sigma = (k+1)/eta and w_j = s_j + gamma_j/eta.
+ *
+ * Row state
+ * ---------
+ * A pair of m-vectors (M, S) represents P_ij = exp(theta_ij - M_i) / S_i, the plan of
+ * eq. (7) with a per-row shift.  ibsn_subproblem_eval() sets M_i = max_j theta_ij and
+ * S_i = sum_j exp(theta_ij - M_i); ibsn_trial() returns the state of the trial point.
+ * lse_i = M_i + log S_i is the row log-sum-exp of eq. (5).
+ */
+#ifndef IBSN_H
+#define IBSN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IBSN_OK = 0,
+    IBSN_WARN_MAXITER = 1,        /* ibsn_solve: max_outer reached before the stop rule */
+    IBSN_ERR_INVALID_ARG = -1,    /* a size, pointer or value violates the stated contract */
+    IBSN_ERR_HIP = -2,            /* a HIP runtime call failed                            */
+    IBSN_ERR_OOM = -3,            /* workspace allocation failed                          */
+    IBSN_ERR_NUMERIC = -4,        /* NaN or Inf met where a finite value is required       */
+    IBSN_ERR_UNSUPPORTED = -5     /* shape outside the compiled kernel range               */
+};
+
+/* Largest n the dense row kernels hold in registers (FP64 cost: 20480; FP32: 40960). */
+#define IBSN_MAX_N_F64 20480
+#define IBSN_MAX_N_F32 40960
+
+typedef struct ibsn_ctx ibsn_ctx;
+typedef struct ibsn_csr ibsn_csr;
+
+/* Create a context on HIP device `device` using stream `hip_stream` (a hipStream_t;
+   NULL = the null stream).  Workspace is allocated lazily and grown on demand. */
+int ibsn_create(ibsn_ctx **out, int device, void *hip_stream);
+void ibsn_destroy(ibsn_ctx *ctx);
+/* Host string describing the last error on ctx; valid until the next call on ctx. */
+const char *ibsn_last_error(const ibsn_ctx *ctx);
+/* Number of compute units of the context's device (host value). */
+int ibsn_num_cus(const ibsn_ctx *ctx);
+
+typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1 } ibsn_cost_kind;
+
+/* OT problem, eq. (1).  C is row-major with leading dimension ldc >= n (elements);
+   an FP32 cost is widened exactly to FP64 before use.  No rescaling of C is done:
+   normalising max C to 1 (Section 5, "Setup") is the caller's job.
+   Contract (checked by ibsn_solve, assumed by the pass-level calls):
+   m >= 1, n >= 1, eta > 0 finite, a > 0, b > 0, |sum a - 1|, |sum b - 1| <= 1e-12*max(m,n). */
+typedef struct {
+    int64_t m, n;
+    int32_t cost_kind;        /* ibsn_cost_kind */
+    const void *C;
+    int64_t ldc;
+    const double *a, *b;      /* device, m and n */
+    double eta;
+} ibsn_problem;
+
+/* Implicit prox centre X^k (see above): device r (m), s (n). */
+typedef struct {
+    int64_t k;
+    const double *r, *s;
+} ibsn_center;
+
+/* Subproblem evaluation (eq. (5)-(8)): the row LSE pass over the m x n kernel.
+   In: gamma (n).  Out: M, S (m) row state; lse (m, optional) = M + log S;
+   colmarg (n) = P^T a; grad (n) = P^T a - b (the paper's sign; the marginal
+   residual X^T 1 - b of the plan X = diag(a) P); obj_host (host out, optional)
+   = L^k(gamma) of eq. (6); plan (m x n row-major, optional) = diag(a) P.
+   Optional outputs may be NULL.  obj_host != NULL synchronises the stream. */
+int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                         const double *gamma, double *M, double *S, double *lse,
+                         double *colmarg, double *grad, double *obj_host, double *plan);
+
+/* Armijo trial (Algorithm 2, step 9) at gamma + t*Delta from the row state (M) of gamma.
+   Host out dL = L^k(gamma + t Delta) - L^k(gamma), evaluated in difference form
+   (-t b^T Delta + eta sum_i a_i log(sum_j q_ij e^{tau_j} / sum_j q_ij), q = exp(theta - M),
+   tau = t Delta / eta) so that it keeps its relative precision for tiny steps.
+   Device out: M_new, S_new (m) row state of the trial point, colmarg_new, grad_new (n).
+   Synchronises the stream (dL is a host value). */
+int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+               const double *gamma, const double *M, const double *Delta, double t,
+               double *dL_host, double *M_new, double *S_new, double *colmarg_new,
+               double *grad_new);
+
+/* Hessian sparsification, Algorithm 1, from the row state (M, S) at gamma:
+   P_ij = exp(theta_ij - M_i)/S_i; rows i != istar keep P_ij >= rho (inclusive) divided
+   by their kept sum; row istar is kept whole.  istar < 0 selects argmax a (lowest
+   index on ties).  *out receives a library-owned handle (free with ibsn_csr_free);
+   it also holds d = P_rho^T a and the transpose used by ibsn_hvp.  A row whose
+   entries all fall below rho is left empty.  Needs 24*m*n bytes of workspace. */
+int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                  const double *gamma, const double *M, const double *S, double rho,
+                  int64_t istar, ibsn_csr **out);
+
+/* Host out: nnz and istar of a sparsified factor (synchronises). */
+int ibsn_csr_info(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *nnz, int64_t *istar);
+
+/* Copy the factor out as standard CSR in row order, columns ascending:
+   row_ptr (m+1, int64), col (nnz, int32), val (nnz), d (n) -- device buffers the
+   caller sized from ibsn_csr_info. */
+int ibsn_csr_export(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *row_ptr, int32_t *col,
+                    double *val, double *d);
+void ibsn_csr_free(ibsn_csr *csr);
+
+/* Sparse Hessian-vector product (Algorithm 1, step 4 and Algorithm 2, step 8):
+   y = (diag(P_rho^T a) v - P_rho^T diag(a) P_rho v)/eta + shift*v, for v, y in R^n.
+   H_rho is never formed.  a must be the problem's a (m). */
+int ibsn_hvp(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,
+             const double *v, double *y);
+
+/* Conjugate gradients (Algorithm 2, step 8) for (H_rho + shift I) x = rhs from x = 0,
+   stopping at ||r||_2 <= tol or after maxit iterations.  Host out: iterations. */
+int ibsn_cg(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,
+            const double *rhs, double tol, int maxit, double *x, int *iters_host);
+
+/* Inexact stop test and certificate for the plan X = diag(a) P of the row state (M, S):
+   Algorithm 3 rounding, D_phi(Xhat, X) (eq. (3)), <C,Xhat>, and the dual lower bound
+   max over v in {gamma, psi} of a^T zeta^c(v) + b^T v with zeta^c_i = min_j (C_ij - v_j)
+   (the c-transform of appendix C.1) and psi_j = (w_j - log b_j)/sigma.
+   Host out (10 values): [0] D_phi, [1] <C,Xhat>, [2] best dual bound, [3] <C,X>,
+   [4] Delta_kkt (appendix C.1, for (X, gamma, zeta^c(gamma))), [5] min Xhat,
+   [6] ||e_r||_1, [7] <X, U(gamma, zeta^c)>, [8] bound from gamma, [9] bound from psi.
+   xhat (m x n, optional) receives the rounded plan.  Synchronises. */
+int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+              const double *gamma, const double *M, const double *S, double *out_host,
+              double *xhat);
+
+/* Solver options; ibsn_default_options() fills the paper's values where it gives
+   them (sigma, beta: Algorithm 2 input; Sinkhorn tolerance and mu_k schedule:
+   Section 5 "Setup"; 300 outer iterations: Table 1). */
+typedef struct {
+    double sigma_armijo, beta;           /* 1e-4, 0.8 */
+    double sinkhorn_tol;                 /* 1e-3 (Euclidean norm of g) */
+    int32_t sinkhorn_maxit;              /* 10000 */
+    double mu0, mu_floor;                /* mu_k = max(mu0/(k+1)^2, mu_floor): 1e-4, 1e-11 */
+    double gap_tol, marg_tol, kkt_tol;   /* 1e-8 relative gap, 1e-9 ||X^T1-b||_1, 0 = off */
+    int32_t max_outer, max_newton, max_backtrack, cg_maxit; /* 300, 1000, 60, 0 = min(n,1000) */
+    double cg_forcing_max;               /* CG stops at ||r|| <= min(0.1, ||g||) ||g|| */
+    int32_t rho_mode;                    /* 0: rho = eta ||g|| / (m n); 1: rho = 0 */
+} ibsn_options;
+
+void ibsn_default_options(ibsn_options *opt);
+
+typedef struct {
+    int64_t outer, newton, cg, sinkhorn, backtracks, stop_tests, passes;
+    double grad_norm, primal, dual, rel_gap, kkt, dphi, marg_l1;
+    double t_eval, t_sparsify, t_cg, t_linesearch, t_stop, t_total;  /* seconds */
+    int32_t status;
+} ibsn_report;
+
+/* Full IBSN solve (Algorithm 2 with the practical stop schedule of Section 5).
+   gamma_io (n, device): in = warm start (NULL = 0; it is centred), out = final dual.
+   r_io (m), s_io (n), k_io (host): optional outer state; when k_io != NULL and
+   *k_io > 0 the solve resumes from (k, r, s); on return they hold the final state.
+   plan_out (m x n, optional): rounded plan Xhat of the final iterate.
+   rep (host, optional).  Stops when the certified relative gap <= gap_tol and
+   ||X^T 1 - b||_1 <= marg_tol (marg_tol <= 0: not required), or Delta_kkt <= kkt_tol
+   (kkt_tol > 0), or after max_outer outer iterations (returns IBSN_WARN_MAXITER). */
+int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt,
+               double *gamma_io, double *r_io, double *s_io, int64_t *k_io, double *plan_out,
+               ibsn_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBSN_H */

@@ -1,0 +1,955 @@
+// ibsn_api.hip -- the C ABI of libibsn.so (include/ibsn.h): context and workspace
+// management, argument checks, the pass-level entry points and the IBSN solver loop
+// (Algorithm 2 with the practical stop schedule of Section 5).
+//
+// The host only sequences kernels and reads back the scalars a decision needs
+// (||g||, the Armijo decrease, D_phi and the certificate, the CG done flag).  All
+// arithmetic on problem data runs in the kernels of dense_passes.hip, sparse_ops.hip
+// and solver_kernels.hip.
+#include "../../include/ibsn.h"
+#include "ibsn_internal.h"
+#include "solver_kernels.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+using namespace ibsn;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ibsn_csr {
+    ibsn_ctx *ctx = nullptr;
+    int64_t m = 0, n = 0;
+    int64_t nnz = 0;       // host copy (valid after sparsify)
+    int64_t istar = -1;    // host copy
+    DevBuf col, val, len, colptr, colcnt, rowidx, cval, blkcnt, d, istar_dev, nnz_dev;
+    int rb = 0;
+};
+
+struct ibsn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 256;
+    size_t max_lds = 65536;
+    std::string err;
+    // workspace
+    DevBuf w, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
+    DevBuf stopout, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_partial, cg_scal, cg_counter;
+    double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
+    ibsn_csr *solver_csr = nullptr;
+};
+
+namespace {
+
+int fail(ibsn_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define CKH(call)                                                                           \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, IBSN_ERR_HIP, "%s failed: %s (%s:%d)", #call,                  \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                          \
+    } while (0)
+
+#define CKI(call)                 \
+    do {                          \
+        int r_ = (call);          \
+        if (r_ < 0)               \
+            return r_;            \
+    } while (0)
+
+int ensure(ibsn_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 16;
+    if (b.bytes >= bytes)
+        return IBSN_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess)
+            return fail(ctx, IBSN_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, IBSN_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    return IBSN_OK;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p)
+        (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+T *P(DevBuf &b)
+{
+    return reinterpret_cast<T *>(b.p);
+}
+
+int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (!p)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "problem is NULL");
+    if (p->m < 1 || p->n < 1)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "m=%lld, n=%lld: both must be >= 1",
+                    (long long)p->m, (long long)p->n);
+    if (p->m > 0x7fffffffLL || p->n > 0x7fffffffLL || p->m * p->n > (int64_t)1 << 40)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "m*n too large");
+    if (!(p->eta > 0.0) || !std::isfinite(p->eta))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "eta=%g must be finite and > 0", p->eta);
+    if (p->cost_kind != IBSN_COST_F64 && p->cost_kind != IBSN_COST_F32)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "cost_kind=%d unknown", p->cost_kind);
+    if (!p->C || !p->a || !p->b)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "C, a and b must be device pointers");
+    if (p->ldc < p->n)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "ldc=%lld < n=%lld", (long long)p->ldc,
+                    (long long)p->n);
+    const int64_t maxn = p->cost_kind == IBSN_COST_F64 ? IBSN_MAX_N_F64 : IBSN_MAX_N_F32;
+    if (p->n > maxn)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld exceeds the register-tiled row kernels "
+                    "(max %lld for this cost type)", (long long)p->n, (long long)maxn);
+    const size_t es = p->cost_kind == IBSN_COST_F64 ? 8 : 4;
+    if (((uintptr_t)p->C % es) != 0)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "C must be aligned to its element size");
+    if ((size_t)p->n * sizeof(double) > ctx->max_lds)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld needs %zu bytes of LDS (device max %zu)",
+                    (long long)p->n, (size_t)p->n * 8, ctx->max_lds);
+    return IBSN_OK;
+}
+
+int check_center(ibsn_ctx *ctx, const ibsn_center *c)
+{
+    if (!c || !c->s)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "center (k, r, s) with device s is required");
+    if (c->k < 0)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "center k=%lld < 0", (long long)c->k);
+    return IBSN_OK;
+}
+
+int plan_for(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *rp)
+{
+    if (!plan_rows(p->m, p->n, p->cost_kind, ctx->num_cus, rp))
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "no row tile for n=%lld", (long long)p->n);
+    return IBSN_OK;
+}
+
+// per-call workspace sized for (m, n, grid)
+int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
+{
+    const size_t n = (size_t)p->n, m = (size_t)p->m, G = (size_t)rp.grid;
+    CKI(ensure(ctx, ctx->w, n * 8));
+    CKI(ensure(ctx, ctx->colpart, G * n * 8));
+    CKI(ensure(ctx, ctx->colpart2, G * n * 8));
+    CKI(ensure(ctx, ctx->rowpart, G * STOP2_NSLOT * 8));
+    CKI(ensure(ctx, ctx->rowpart2, G * 8));
+    CKI(ensure(ctx, ctx->scal, SC_NSLOT * 8));
+    CKI(ensure(ctx, ctx->colv, n * 8));
+    CKI(ensure(ctx, ctx->cvec, n * 8));
+    CKI(ensure(ctx, ctx->gvec, n * 8));
+    CKI(ensure(ctx, ctx->yv, n * 8));
+    CKI(ensure(ctx, ctx->ecv, n * 8));
+    CKI(ensure(ctx, ctx->psiv, n * 8));
+    CKI(ensure(ctx, ctx->zv, m * 8));
+    CKI(ensure(ctx, ctx->stopout, 16 * 8));
+    return IBSN_OK;
+}
+
+DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k)
+{
+    DenseArgs d;
+    d.C = p->C;
+    d.ldc = p->ldc;
+    d.m = p->m;
+    d.n = p->n;
+    d.cost_kind = p->cost_kind;
+    d.sigma = (double)(k + 1) / p->eta;
+    d.w = P<double>(ctx->w);
+    d.a = p->a;
+    return d;
+}
+
+int read_scal(ibsn_ctx *ctx, int count = SC_NSLOT)
+{
+    CKH(hipMemcpyAsync(ctx->host_scal, ctx->scal.p, sizeof(double) * count, hipMemcpyDeviceToHost,
+                       ctx->stream));
+    CKH(hipStreamSynchronize(ctx->stream));
+    return IBSN_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// pass-level building blocks (also used by the solver)
+// ---------------------------------------------------------------------------------
+// eval at the current ctx->w (already formed); writes M, S, lse, c, g, plan; objective to
+// scal[SC_OBJ] when r != null (needs gamma for b^T gamma); norms of g to scal.
+int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, const double *r,
+             const double *gamma, double *M, double *S, double *lse, double *c, double *g,
+             double *plan)
+{
+    hipStream_t st = ctx->stream;
+    DenseArgs d = dense_args(ctx, p, k);
+    CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart), P<double>(ctx->rowpart),
+                    st));
+    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, c, p->b, g, st));
+    CKH(sk_gnorms(p->n, g, P<double>(ctx->scal), st));
+    if (r && gamma) {
+        CKH(sk_dot_slot(p->n, p->b, gamma, SC_BG, P<double>(ctx->scal), st));
+        CKH(sk_sum_parts(rp.grid, 1, 0, P<double>(ctx->rowpart), p->eta, -1.0, SC_BG, SC_OBJ, 0,
+                         P<double>(ctx->scal), st));
+    }
+    return IBSN_OK;
+}
+
+// trial at gamma + t Delta: writes Mn, Sn, cn, gn; scal[SC_DL] = dL (needs scal[SC_BD]).
+int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, const double *M,
+              const double *Delta, double t, double *Mn, double *Sn, double *cn, double *gn)
+{
+    hipStream_t st = ctx->stream;
+    DenseArgs d = dense_args(ctx, p, k);
+    double *scal = P<double>(ctx->scal);
+    CKH(sk_trial_prep(p->n, t, p->eta, Delta, P<double>(ctx->colv), scal, st));
+    CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
+                     P<double>(ctx->rowpart), st));
+    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, cn, p->b, gn, st));
+    CKH(sk_gnorms(p->n, gn, scal, st));
+    // dL = eta * sum_i a_i delta_i - t * b^T Delta
+    CKH(sk_sum_parts(rp.grid, 1, 0, P<double>(ctx->rowpart), p->eta, -t, SC_BD, SC_DL, 0, scal,
+                     st));
+    return IBSN_OK;
+}
+
+// stop test + certificate at the state (w, M, S); out (device, 10 doubles)
+int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
+             const double *gamma, const double *M, const double *S, double *xhat)
+{
+    hipStream_t st = ctx->stream;
+    DenseArgs d = dense_args(ctx, p, k);
+    double *scal = P<double>(ctx->scal);
+    double *colX = P<double>(ctx->cvec);   // reuse as column sums of X
+    double *colF = P<double>(ctx->colv);
+    CKH(launch_stop1(rp, d, M, S, P<double>(ctx->zv), P<double>(ctx->colpart),
+                     P<double>(ctx->colpart2), P<double>(ctx->rowpart2), st));
+    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, colX, nullptr, nullptr, st));
+    CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, p->n, colF, nullptr, nullptr, st));
+    CKH(sk_stop_prep(p->n, d.sigma, p->b, d.w, gamma, colX, colF, P<double>(ctx->yv),
+                     P<double>(ctx->ecv), P<double>(ctx->psiv), scal, st));
+    // er1 is needed as a kernel argument: read it back
+    CKI(read_scal(ctx));
+    Stop2Vec v;
+    v.gamma = gamma;
+    v.psi = P<double>(ctx->psiv);
+    v.y = P<double>(ctx->yv);
+    v.ec = P<double>(ctx->ecv);
+    v.z = P<double>(ctx->zv);
+    v.er1 = ctx->host_scal[SC_ER1];
+    CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));
+    CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), p->m, p->a, p->n, p->b,
+                      P<double>(ctx->rowpart2), rp.grid, scal, P<double>(ctx->stopout), st));
+    return IBSN_OK;
+}
+
+int csr_alloc(ibsn_ctx *ctx, ibsn_csr *c, int64_t m, int64_t n)
+{
+    const size_t mn = (size_t)m * (size_t)n;
+    c->m = m;
+    c->n = n;
+    c->rb = (int)std::min<int64_t>(m, 256);
+    CKI(ensure(ctx, c->col, mn * 4));
+    CKI(ensure(ctx, c->val, mn * 8));
+    CKI(ensure(ctx, c->len, (size_t)m * 4));
+    CKI(ensure(ctx, c->colptr, ((size_t)n + 1) * 8));
+    CKI(ensure(ctx, c->colcnt, (size_t)n * 8));
+    CKI(ensure(ctx, c->rowidx, mn * 4));
+    CKI(ensure(ctx, c->cval, mn * 8));
+    CKI(ensure(ctx, c->blkcnt, (size_t)c->rb * n * 4));
+    CKI(ensure(ctx, c->d, (size_t)n * 8));
+    CKI(ensure(ctx, c->istar_dev, 16));
+    CKI(ensure(ctx, c->nnz_dev, 16));
+    return IBSN_OK;
+}
+
+void csr_release(ibsn_csr *c)
+{
+    DevBuf *bufs[] = {&c->col, &c->val, &c->len, &c->colptr, &c->colcnt, &c->rowidx,
+                      &c->cval, &c->blkcnt, &c->d, &c->istar_dev, &c->nnz_dev};
+    for (DevBuf *b : bufs)
+        release(*b);
+}
+
+// sparsify into c at the state (w formed), rho; istar on device in c->istar_dev
+int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
+                 const double *M, const double *S, double rho, ibsn_csr *c)
+{
+    hipStream_t st = ctx->stream;
+    DenseArgs d = dense_args(ctx, p, k);
+    CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
+                        P<double>(c->val), P<int32_t>(c->len), P<double>(ctx->colpart), st));
+    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(c->d), nullptr,
+                         nullptr, st));
+    CscWork cw;
+    cw.colptr = P<int64_t>(c->colptr);
+    cw.colcnt = P<int64_t>(c->colcnt);
+    cw.rowidx = P<int32_t>(c->rowidx);
+    cw.cval = P<double>(c->cval);
+    cw.blkcnt = P<int32_t>(c->blkcnt);
+    cw.rb = c->rb;
+    CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), P<double>(c->val), P<int32_t>(c->len), cw,
+                         P<int64_t>(c->nnz_dev), st));
+    int64_t hv[2];
+    CKH(hipMemcpyAsync(hv, c->nnz_dev.p, 8, hipMemcpyDeviceToHost, st));
+    CKH(hipMemcpyAsync(hv + 1, c->istar_dev.p, 4, hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    c->nnz = hv[0];
+    c->istar = (int64_t)(int32_t)(hv[1] & 0xffffffff);
+    return IBSN_OK;
+}
+
+int lanes_for(int64_t count, int64_t groups)
+{
+    const double avg = groups > 0 ? (double)count / (double)groups : 0.0;
+    return avg >= 96.0 ? 64 : (avg >= 12.0 ? 16 : 4);
+}
+
+int run_hvp(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
+            const double *v, double *y, double *au)
+{
+    hipStream_t st = ctx->stream;
+    const int lr = lanes_for(c->nnz - c->n, c->m > 1 ? c->m - 1 : 1);
+    const int lc = lanes_for(c->nnz, c->n);
+    CKH(launch_row_gather(c->m, c->n, (const int32_t *)c->col.p, (const double *)c->val.p,
+                          (const int32_t *)c->len.p, (const int *)c->istar_dev.p, a, v, au, lr,
+                          st));
+    CKH(launch_col_gather(c->n, (const int64_t *)c->colptr.p, (const int32_t *)c->rowidx.p,
+                          (const double *)c->cval.p, au, (const double *)c->d.p, v, eta, shift, y,
+                          lc, st));
+    return IBSN_OK;
+}
+
+int ensure_cg(ibsn_ctx *ctx, int64_t m, int64_t n)
+{
+    CKI(ensure(ctx, ctx->cg_x, n * 8));
+    CKI(ensure(ctx, ctx->cg_r, n * 8));
+    CKI(ensure(ctx, ctx->cg_p, n * 8));
+    CKI(ensure(ctx, ctx->cg_Ap, n * 8));
+    CKI(ensure(ctx, ctx->cg_au, m * 8));
+    CKI(ensure(ctx, ctx->cg_partial, ((size_t)n * 64 / 256 + 260) * 8));
+    CKI(ensure(ctx, ctx->cg_scal, 16 * 8));
+    const bool fresh = ctx->cg_counter.p == nullptr;
+    CKI(ensure(ctx, ctx->cg_counter, 64));
+    if (fresh)
+        CKH(hipMemsetAsync(ctx->cg_counter.p, 0, 64, ctx->stream));
+    return IBSN_OK;
+}
+
+// CG for (H_rho + shift I) x = rhs from 0; result in ctx->cg_x; *iters on host.
+int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
+           const double *rhs, double tol, int maxit, int *iters)
+{
+    hipStream_t st = ctx->stream;
+    CKI(ensure_cg(ctx, c->m, c->n));
+    CgState s;
+    s.x = P<double>(ctx->cg_x);
+    s.r = P<double>(ctx->cg_r);
+    s.p = P<double>(ctx->cg_p);
+    s.Ap = P<double>(ctx->cg_Ap);
+    s.au = P<double>(ctx->cg_au);
+    s.partial = P<double>(ctx->cg_partial);
+    s.scal = P<double>(ctx->cg_scal);
+    s.counter = P<unsigned>(ctx->cg_counter);
+    CKH(launch_cg_init(c->n, rhs, tol, maxit, s, st));
+    const int lr = lanes_for(c->nnz - c->n, c->m > 1 ? c->m - 1 : 1);
+    const int lc = lanes_for(c->nnz, c->n);
+    int launched = 0, chunk = 8;
+    double hs[CG_NSLOT];
+    for (;;) {
+        for (int q = 0; q < chunk && launched < maxit; ++q, ++launched)
+            CKH(launch_cg_iteration(c->m, c->n, (const int32_t *)c->col.p, (const double *)c->val.p,
+                                    (const int32_t *)c->len.p, (const int *)c->istar_dev.p,
+                                    (const int64_t *)c->colptr.p, (const int32_t *)c->rowidx.p,
+                                    (const double *)c->cval.p, (const double *)c->d.p, a, eta,
+                                    shift, s, lr, lc, st));
+        CKH(hipMemcpyAsync(hs, s.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
+        CKH(hipStreamSynchronize(st));
+        if (hs[CG_DONE] != 0.0 || launched >= maxit)
+            break;
+        chunk = std::min(chunk * 2, 64);
+    }
+    *iters = (int)hs[CG_IT];
+    return IBSN_OK;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+// =================================================================================
+// exported API
+// =================================================================================
+extern "C" {
+
+int ibsn_create(ibsn_ctx **out, int device, void *hip_stream)
+{
+    if (!out)
+        return IBSN_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return IBSN_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess)
+        return IBSN_ERR_HIP;
+    ibsn_ctx *ctx = new ibsn_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        ctx->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        ctx->max_lds = prop.sharedMemPerBlock;
+    }
+    if (hipHostMalloc((void **)&ctx->host_scal, sizeof(double) * (SC_NSLOT + 16)) != hipSuccess) {
+        delete ctx;
+        return IBSN_ERR_HIP;
+    }
+    *out = ctx;
+    return IBSN_OK;
+}
+
+void ibsn_destroy(ibsn_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream)
+        (void)hipStreamSynchronize(ctx->stream);
+    else
+        (void)hipDeviceSynchronize();
+    if (ctx->solver_csr) {
+        csr_release(ctx->solver_csr);
+        delete ctx->solver_csr;
+    }
+    DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
+                      &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
+                      &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->cg_x, &ctx->cg_r, &ctx->cg_p,
+                      &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_partial, &ctx->cg_scal,
+                      &ctx->cg_counter};
+    for (DevBuf *b : bufs)
+        release(*b);
+    if (ctx->host_scal)
+        (void)hipHostFree(ctx->host_scal);
+    delete ctx;
+}
+
+const char *ibsn_last_error(const ibsn_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ibsn_num_cus(const ibsn_ctx *ctx) { return ctx ? ctx->num_cus : 0; }
+
+void ibsn_default_options(ibsn_options *o)
+{
+    if (!o)
+        return;
+    o->sigma_armijo = 1e-4;
+    o->beta = 0.8;
+    o->sinkhorn_tol = 1e-3;
+    o->sinkhorn_maxit = 10000;
+    o->mu0 = 1e-4;
+    o->mu_floor = 1e-11;
+    o->gap_tol = 1e-8;
+    o->marg_tol = 1e-9;
+    o->kkt_tol = 0.0;
+    o->max_outer = 300;
+    o->max_newton = 1000;
+    o->max_backtrack = 60;
+    o->cg_maxit = 0;
+    o->cg_forcing_max = 0.1;
+    o->rho_mode = 0;
+}
+
+int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                         const double *gamma, double *M, double *S, double *lse, double *colmarg,
+                         double *grad, double *obj_host, double *plan)
+{
+    CKI(check_problem(ctx, prob));
+    CKI(check_center(ctx, ctr));
+    if (!gamma || !M || !S || !colmarg || !grad)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "gamma, M, S, colmarg and grad are required");
+    if (obj_host && !ctr->r)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "the objective needs the centre's r");
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    CKH(launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w), ctx->stream));
+    CKI(run_eval(ctx, prob, rp, ctr->k, obj_host ? ctr->r : nullptr, gamma, M, S, lse, colmarg,
+                 grad, plan));
+    if (obj_host) {
+        CKI(read_scal(ctx));
+        *obj_host = ctx->host_scal[SC_OBJ];
+    }
+    return IBSN_OK;
+}
+
+int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, const double *gamma,
+               const double *M, const double *Delta, double t, double *dL_host, double *M_new,
+               double *S_new, double *colmarg_new, double *grad_new)
+{
+    CKI(check_problem(ctx, prob));
+    CKI(check_center(ctx, ctr));
+    if (!gamma || !M || !Delta || !dL_host || !M_new || !S_new || !colmarg_new || !grad_new)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "all arrays of ibsn_trial are required");
+    if (!(t > 0.0) || !std::isfinite(t))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "step t=%g must be finite and > 0", t);
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    CKH(launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w), ctx->stream));
+    CKH(sk_dot_slot(prob->n, prob->b, Delta, SC_BD, P<double>(ctx->scal), ctx->stream));
+    CKI(run_trial(ctx, prob, rp, ctr->k, M, Delta, t, M_new, S_new, colmarg_new, grad_new));
+    CKI(read_scal(ctx));
+    *dL_host = ctx->host_scal[SC_DL];
+    return IBSN_OK;
+}
+
+int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                  const double *gamma, const double *M, const double *S, double rho,
+                  int64_t istar, ibsn_csr **out)
+{
+    CKI(check_problem(ctx, prob));
+    CKI(check_center(ctx, ctr));
+    if (!gamma || !M || !S || !out)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "gamma, M, S and out are required");
+    if (!(rho >= 0.0) || !std::isfinite(rho))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "rho=%g must be finite and >= 0", rho);
+    if (istar >= prob->m)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "istar=%lld >= m", (long long)istar);
+    *out = nullptr;
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    ibsn_csr *c = new ibsn_csr();
+    c->ctx = ctx;
+    int rc = csr_alloc(ctx, c, prob->m, prob->n);
+    if (rc < 0) {
+        csr_release(c);
+        delete c;
+        return rc;
+    }
+    if (istar < 0) {
+        rc = sk_problem_scalars(prob->m, prob->n, prob->a, prob->b, P<double>(ctx->scal),
+                                P<int>(c->istar_dev), ctx->stream) == hipSuccess
+                 ? IBSN_OK
+                 : fail(ctx, IBSN_ERR_HIP, "argmax a failed");
+    } else {
+        const int iv = (int)istar;
+        rc = hipMemcpyAsync(c->istar_dev.p, &iv, 4, hipMemcpyHostToDevice, ctx->stream) ==
+                     hipSuccess
+                 ? IBSN_OK
+                 : fail(ctx, IBSN_ERR_HIP, "istar copy failed");
+        if (rc == IBSN_OK)
+            rc = hipStreamSynchronize(ctx->stream) == hipSuccess ? IBSN_OK : IBSN_ERR_HIP;
+    }
+    if (rc == IBSN_OK) {
+        if (launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w),
+                          ctx->stream) != hipSuccess)
+            rc = fail(ctx, IBSN_ERR_HIP, "make_w failed");
+    }
+    if (rc == IBSN_OK)
+        rc = run_sparsify(ctx, prob, rp, ctr->k, M, S, rho, c);
+    if (rc < 0) {
+        csr_release(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return IBSN_OK;
+}
+
+int ibsn_csr_info(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *nnz, int64_t *istar)
+{
+    if (!ctx || !csr)
+        return IBSN_ERR_INVALID_ARG;
+    if (nnz)
+        *nnz = csr->nnz;
+    if (istar)
+        *istar = csr->istar;
+    return IBSN_OK;
+}
+
+int ibsn_csr_export(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *row_ptr, int32_t *col,
+                    double *val, double *d)
+{
+    if (!ctx || !csr || !row_ptr || !col || !val || !d)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "all export buffers are required");
+    CKH(hipSetDevice(ctx->device));
+    CKH(launch_export_csr(csr->m, csr->n, (const int32_t *)csr->col.p, (const double *)csr->val.p,
+                          (const int32_t *)csr->len.p, row_ptr, col, val, ctx->stream));
+    CKH(hipMemcpyAsync(d, csr->d.p, sizeof(double) * csr->n, hipMemcpyDeviceToDevice,
+                       ctx->stream));
+    return IBSN_OK;
+}
+
+void ibsn_csr_free(ibsn_csr *csr)
+{
+    if (!csr)
+        return;
+    if (csr->ctx) {
+        (void)hipSetDevice(csr->ctx->device);
+        if (csr->ctx->stream)
+            (void)hipStreamSynchronize(csr->ctx->stream);
+    }
+    csr_release(csr);
+    delete csr;
+}
+
+int ibsn_hvp(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,
+             const double *v, double *y)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (!csr || !a || !v || !y)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "csr, a, v and y are required");
+    if (!(eta > 0.0) || !std::isfinite(shift))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "eta must be > 0 and shift finite");
+    CKH(hipSetDevice(ctx->device));
+    CKI(ensure_cg(ctx, csr->m, csr->n));
+    return run_hvp(ctx, csr, a, eta, shift, v, y, P<double>(ctx->cg_au));
+}
+
+int ibsn_cg(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,
+            const double *rhs, double tol, int maxit, double *x, int *iters_host)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (!csr || !a || !rhs || !x)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "csr, a, rhs and x are required");
+    if (!(eta > 0.0) || !(shift >= 0.0) || !(tol >= 0.0) || maxit < 0)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "need eta > 0, shift >= 0, tol >= 0, maxit >= 0");
+    CKH(hipSetDevice(ctx->device));
+    int it = 0;
+    CKI(run_cg(ctx, csr, a, eta, shift, rhs, tol, maxit, &it));
+    CKH(hipMemcpyAsync(x, ctx->cg_x.p, sizeof(double) * csr->n, hipMemcpyDeviceToDevice,
+                       ctx->stream));
+    CKH(hipStreamSynchronize(ctx->stream));
+    if (iters_host)
+        *iters_host = it;
+    return IBSN_OK;
+}
+
+int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, const double *gamma,
+              const double *M, const double *S, double *out_host, double *xhat)
+{
+    CKI(check_problem(ctx, prob));
+    CKI(check_center(ctx, ctr));
+    if (!gamma || !M || !S || !out_host)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "gamma, M, S and out_host are required");
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    CKH(sk_dot_slot(prob->m, prob->a, nullptr, SC_SUMA, P<double>(ctx->scal), ctx->stream));
+    CKH(launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w), ctx->stream));
+    CKI(run_stop(ctx, prob, rp, ctr->k, gamma, M, S, xhat));
+    CKH(hipMemcpyAsync(out_host, ctx->stopout.p, sizeof(double) * 10, hipMemcpyDeviceToHost,
+                       ctx->stream));
+    CKH(hipStreamSynchronize(ctx->stream));
+    return IBSN_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// the solver (Algorithm 2)
+// ---------------------------------------------------------------------------------
+int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_in,
+               double *gamma_io, double *r_io, double *s_io, int64_t *k_io, double *plan_out,
+               ibsn_report *rep)
+{
+    CKI(check_problem(ctx, prob));
+    ibsn_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        ibsn_default_options(&opt);
+    if (opt.max_outer < 1 || opt.max_newton < 1 || opt.max_backtrack < 0 ||
+        !(opt.beta > 0 && opt.beta < 1) || !(opt.sigma_armijo > 0 && opt.sigma_armijo < 1))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "invalid options");
+    const bool resume = k_io && *k_io > 0;
+    if (resume && (!r_io || !s_io))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "resume (k > 0) needs r_io and s_io");
+    CKH(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int64_t m = prob->m, n = prob->n;
+    const double eta = prob->eta;
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    const int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)std::min<int64_t>(n, 1000);
+
+    // solver state buffers
+    DevBuf rB, sB, gB, MB, SB, MtB, StB, ctB, gtB, DB, cB, gvB;
+    auto cleanup = [&]() {
+        DevBuf *b[] = {&rB, &sB, &gB, &MB, &SB, &MtB, &StB, &ctB, &gtB, &DB, &cB, &gvB};
+        for (DevBuf *x : b)
+            release(*x);
+    };
+    int rc = IBSN_OK;
+#define CKS(call)                  \
+    do {                           \
+        rc = (call);               \
+        if (rc < 0) {              \
+            cleanup();             \
+            return rc;             \
+        }                          \
+    } while (0)
+#define CKSH(call)                                                                             \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            cleanup();                                                                         \
+            return fail(ctx, IBSN_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+        }                                                                                      \
+    } while (0)
+    CKS(ensure(ctx, rB, m * 8));
+    CKS(ensure(ctx, sB, n * 8));
+    CKS(ensure(ctx, gB, n * 8));
+    CKS(ensure(ctx, MB, m * 8));
+    CKS(ensure(ctx, SB, m * 8));
+    CKS(ensure(ctx, MtB, m * 8));
+    CKS(ensure(ctx, StB, m * 8));
+    CKS(ensure(ctx, ctB, n * 8));
+    CKS(ensure(ctx, gtB, n * 8));
+    CKS(ensure(ctx, DB, n * 8));
+    if (!ctx->solver_csr) {
+        ctx->solver_csr = new ibsn_csr();
+        ctx->solver_csr->ctx = ctx;
+    }
+    ibsn_csr *csr = ctx->solver_csr;
+    CKS(csr_alloc(ctx, csr, m, n));
+    double *r = P<double>(rB), *s = P<double>(sB), *gamma = P<double>(gB);
+    double *M = P<double>(MB), *S = P<double>(SB), *Mt = P<double>(MtB), *St = P<double>(StB);
+    CKS(ensure(ctx, cB, n * 8));
+    CKS(ensure(ctx, gvB, n * 8));
+    double *c = P<double>(cB), *g = P<double>(gvB);
+    double *ct = P<double>(ctB), *gt = P<double>(gtB), *Delta = P<double>(DB);
+    double *scal = P<double>(ctx->scal);
+
+    // problem checks and per-problem scalars (istar, sums)
+    CKSH(sk_problem_scalars(m, n, prob->a, prob->b, scal, P<int>(csr->istar_dev), st));
+    CKS(read_scal(ctx));
+    {
+        const double *h = ctx->host_scal;
+        const double tol = 1e-12 * (double)std::max(m, n);
+        if (h[SC_BAD] != 0.0 || !(h[SC_MINA] > 0.0) || !(h[SC_MINB] > 0.0) ||
+            std::fabs(h[SC_SUMA] - 1.0) > tol || std::fabs(h[SC_SUMB] - 1.0) > tol) {
+            cleanup();
+            return fail(ctx, IBSN_ERR_INVALID_ARG,
+                        "marginals must be positive, finite and sum to 1 (sum a=%.17g, sum b=%.17g, "
+                        "min a=%g, min b=%g)",
+                        h[SC_SUMA], h[SC_SUMB], h[SC_MINA], h[SC_MINB]);
+        }
+    }
+    int64_t k = 0;
+    if (resume) {
+        k = *k_io;
+        CKSH(hipMemcpyAsync(r, r_io, m * 8, hipMemcpyDeviceToDevice, st));
+        CKSH(hipMemcpyAsync(s, s_io, n * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+        CKSH(sk_init_center(m, n, prob->a, prob->b, r, s, st));
+    }
+    if (gamma_io)
+        CKSH(hipMemcpyAsync(gamma, gamma_io, n * 8, hipMemcpyDeviceToDevice, st));
+    else
+        CKSH(hipMemsetAsync(gamma, 0, n * 8, st));
+    if (!resume)
+        CKSH(sk_center(n, gamma, st));
+
+    ibsn_report R;
+    memset(&R, 0, sizeof(R));
+    R.status = IBSN_WARN_MAXITER;
+    const double t0 = now_s();
+    double stop_h[10] = {0};
+    const int64_t k0 = k;
+    const double mn = (double)m * (double)n;
+    for (; k < k0 + opt.max_outer; ++k) {
+        const double mu = std::max(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
+        // fresh evaluation of the new subproblem at the current gamma
+        double ta = now_s();
+        CKSH(launch_make_w(s, gamma, 0.0, eta, n, P<double>(ctx->w), st));
+        CKS(run_eval(ctx, prob, rp, k, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
+        ++R.passes;
+        CKS(read_scal(ctx));
+        // Sinkhorn warm-up (Algorithm 2, steps 3-4)
+        for (int it = 0; it < opt.sinkhorn_maxit && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol;
+             ++it) {
+            CKSH(sk_sinkhorn_step(n, eta, prob->b, c, gamma, st));
+            CKSH(launch_make_w(s, gamma, 0.0, eta, n, P<double>(ctx->w), st));
+            CKS(run_eval(ctx, prob, rp, k, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
+            ++R.passes;
+            ++R.sinkhorn;
+            CKS(read_scal(ctx));
+        }
+        if (!std::isfinite(ctx->host_scal[SC_GN])) {
+            cleanup();
+            return fail(ctx, IBSN_ERR_NUMERIC, "non-finite gradient at outer iteration %lld",
+                        (long long)k);
+        }
+        R.t_eval += now_s() - ta;
+        bool stopped = false;
+        for (int v = 0; v < opt.max_newton; ++v) {
+            const double gn = ctx->host_scal[SC_GN];
+            const double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / mn;   // step 6
+            ta = now_s();
+            // w still holds s + gamma/eta of the current iterate
+            CKS(run_sparsify(ctx, prob, rp, k, M, S, rho, csr));   // step 7
+            ++R.passes;
+            R.t_sparsify += now_s() - ta;
+            ta = now_s();
+            CKSH(sk_neg(n, g, Delta, st));   // rhs = -g
+            int cgit = 0;
+            const double tol = std::min(opt.cg_forcing_max, gn) * gn;
+            CKS(run_cg(ctx, csr, prob->a, eta, gn, Delta, tol, cg_maxit, &cgit));   // step 8
+            CKSH(hipMemcpyAsync(Delta, ctx->cg_x.p, n * 8, hipMemcpyDeviceToDevice, st));
+            R.cg += cgit;
+            R.t_cg += now_s() - ta;
+            ta = now_s();
+            CKSH(sk_dot_slot(n, g, Delta, SC_GD, scal, st));
+            CKSH(sk_dot_slot(n, prob->b, Delta, SC_BD, scal, st));
+            double t = 1.0;
+            int bt = 0;
+            bool accepted = false;
+            for (;;) {   // step 9: Armijo backtracking on a finite decrease
+                CKS(run_trial(ctx, prob, rp, k, M, Delta, t, Mt, St, ct, gt));
+                ++R.passes;
+                CKS(read_scal(ctx));
+                const double gd = ctx->host_scal[SC_GD];
+                const double dL = ctx->host_scal[SC_DL];
+                if (std::isfinite(dL) && dL <= opt.sigma_armijo * t * gd) {
+                    accepted = true;
+                    break;
+                }
+                if (bt >= opt.max_backtrack)
+                    break;
+                t *= opt.beta;
+                ++bt;
+            }
+            R.backtracks += bt;
+            if (!accepted) {
+                // no acceptable step: keep gamma, restore the norms of the current g and
+                // end the inner loop
+                CKSH(sk_gnorms(n, g, scal, st));
+                CKS(read_scal(ctx));
+                R.t_linesearch += now_s() - ta;
+                break;
+            }
+            // step 10: gamma += t Delta; the accepted trial is the new iterate
+            CKSH(sk_axpy(n, t, Delta, gamma, st));
+            std::swap(M, Mt);
+            std::swap(S, St);
+            std::swap(c, ct);
+            std::swap(g, gt);
+            CKSH(launch_make_w(s, gamma, 0.0, eta, n, P<double>(ctx->w), st));
+            ++R.newton;
+            R.t_linesearch += now_s() - ta;
+            // step 12 with the practical schedule: gradient gate, then D_phi test
+            if (ctx->host_scal[SC_GN] < mu) {
+                ta = now_s();
+                CKS(run_stop(ctx, prob, rp, k, gamma, M, S, nullptr));
+                R.passes += 2;
+                ++R.stop_tests;
+                CKSH(hipMemcpyAsync(stop_h, ctx->stopout.p, sizeof(stop_h), hipMemcpyDeviceToHost,
+                                    st));
+                CKSH(hipStreamSynchronize(st));
+                R.t_stop += now_s() - ta;
+                if (stop_h[0] <= (double)std::min(m, n) * mu) {
+                    stopped = true;
+                    break;
+                }
+            }
+        }
+        if (!stopped) {
+            ta = now_s();
+            CKS(run_stop(ctx, prob, rp, k, gamma, M, S, nullptr));
+            R.passes += 2;
+            ++R.stop_tests;
+            CKSH(hipMemcpyAsync(stop_h, ctx->stopout.p, sizeof(stop_h), hipMemcpyDeviceToHost, st));
+            CKSH(hipStreamSynchronize(st));
+            R.t_stop += now_s() - ta;
+        }
+        const double primal = stop_h[1], dual = stop_h[2];
+        R.primal = primal;
+        R.dual = dual;
+        R.rel_gap = (primal - dual) / std::fabs(primal);
+        R.kkt = stop_h[4];
+        R.dphi = stop_h[0];
+        R.grad_norm = ctx->host_scal[SC_GN];
+        R.marg_l1 = ctx->host_scal[SC_G1];
+        const bool done = (R.rel_gap <= opt.gap_tol && (opt.marg_tol <= 0 || R.marg_l1 <= opt.marg_tol)) ||
+                          (opt.kkt_tol > 0 && R.kkt <= opt.kkt_tol);
+        if (plan_out && (done || k + 1 == k0 + opt.max_outer)) {
+            CKS(run_stop(ctx, prob, rp, k, gamma, M, S, plan_out));
+            R.passes += 2;
+        }
+        // step 13: X^{k+1} = X^{k,v+1}, i.e. r = log a - lse, s = w; k = k+1
+        CKSH(sk_outer_update(m, n, prob->a, M, S, P<double>(ctx->w), r, s, st));
+        if (done) {
+            R.status = IBSN_OK;
+            ++k;
+            break;
+        }
+    }
+    R.outer = k - k0;
+    CKSH(hipStreamSynchronize(st));
+    R.t_total = now_s() - t0;
+    if (gamma_io)
+        CKSH(hipMemcpyAsync(gamma_io, gamma, n * 8, hipMemcpyDeviceToDevice, st));
+    if (r_io)
+        CKSH(hipMemcpyAsync(r_io, r, m * 8, hipMemcpyDeviceToDevice, st));
+    if (s_io)
+        CKSH(hipMemcpyAsync(s_io, s, n * 8, hipMemcpyDeviceToDevice, st));
+    if (k_io)
+        *k_io = k;
+    CKSH(hipStreamSynchronize(st));
+    if (rep)
+        *rep = R;
+    cleanup();
+    return R.status;
+#undef CKS
+#undef CKSH
+}
+
+}  // extern "C"

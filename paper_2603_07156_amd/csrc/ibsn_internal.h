@@ -1,0 +1,129 @@
+// ibsn_internal.h -- launchers shared by the HIP translation units of libibsn.so.
+// Not installed; the public ABI is include/ibsn.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibsn {
+
+// Work split of the dense row passes: `grid` workgroups, workgroup g owns rows
+// [m*g/grid, m*(g+1)/grid), and writes one n-long column partial row.
+struct RowPlan {
+    int nt;        // threads per workgroup
+    int q;         // vector slots per thread (row held as q*vec values per thread)
+    int vec;       // elements per vector load (2 for FP64 cost, 4 for FP32)
+    int grid;      // number of workgroups
+};
+
+// Choose the register tile for a row of n entries; returns false if n is too large.
+bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *plan);
+
+struct DenseArgs {
+    const void *C;
+    int64_t ldc;
+    int64_t m, n;
+    int cost_kind;
+    double sigma;           // (k+1)/eta
+    const double *w;        // n: s + gamma/eta
+    const double *a;        // m
+};
+
+// ---- eval (fresh row LSE) ------------------------------------------------------
+// Writes M, S (and lse if non-null), plan (optional), colpart[grid][n] = column
+// partials of a_i P_ij, rowpart[grid] = sum_i a_i ((r_i + M_i) + log S_i).
+hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, double *M, double *S,
+                       double *lse, double *plan, double *colpart, double *rowpart,
+                       hipStream_t st);
+
+// ---- Armijo trial --------------------------------------------------------------
+// big = 0: colv = expm1(tau) (small-step form); big = 1: colv = exp(tau - tau_max).
+// Writes M_new, S_new, colpart (a_i P'_ij), rowpart = sum a_i delta_i.
+// Launches both forms; each returns at once unless scal[SC_BIG] selects it, so the
+// choice needs no host round trip.  tau_shift is read from scal[SC_TAUSHIFT].
+hipError_t launch_trial(const RowPlan &p, const DenseArgs &d, const double *M, const double *colv,
+                        const double *scal, double *M_new, double *S_new, double *colpart,
+                        double *rowpart, hipStream_t st);
+
+// ---- sparsify (Algorithm 1) ----------------------------------------------------
+// Slotted CSR: row i's kept entries at [i*n, i*n + len_i), columns ascending.
+// colpart = column partials of a_i [P_rho]_ij (for d = P_rho^T a).
+hipError_t launch_sparsify(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
+                           double rho, const int *istar, int32_t *col, double *val, int32_t *len,
+                           double *colpart, hipStream_t st);
+
+// ---- stop test, pass 1 (Algorithm 3 rows/columns) -------------------------------
+// z_i = min(a_i / sum_j X_ij, 1); colpart  = column partials of X;
+// colpart2 = column partials of z_i X_ij; rowpart = sum_i (sum_j X_ij - a_i)^2.
+hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
+                        double *z, double *colpart, double *colpart2, double *rowpart,
+                        hipStream_t st);
+
+// ---- stop test, pass 2 (rounded plan, D_phi, certificate) -----------------------
+struct Stop2Vec {
+    const double *gamma, *psi, *y, *ec, *z;   // n, n, n, n, m
+    double er1;                               // ||e_r||_1
+};
+// rowpart[grid * 10]: per-workgroup sums (see STOP2_* slots).
+enum { STOP2_DPHI = 0, STOP2_CXH, STOP2_AZG, STOP2_AZP, STOP2_CX, STOP2_XU, STOP2_XHMIN,
+       STOP2_XF, STOP2_CF, STOP2_NEG, STOP2_NSLOT };
+hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
+                        const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st);
+
+// ---- column reduction ----------------------------------------------------------
+// out_j = sum_g part[g][j] in a fixed order; if sub != null, out2_j = out_j - sub_j.
+hipError_t launch_colreduce(const double *part, int G, int64_t n, double *out, const double *sub,
+                            double *out2, hipStream_t st);
+
+// ---- small vector / scalar kernels ----------------------------------------------
+hipError_t launch_make_w(const double *s, const double *gamma, double inv_eta_unused, double eta,
+                         int64_t n, double *w, hipStream_t st);
+// out[0] = sum_i x_i (fixed order) for up to n values, single workgroup
+hipError_t launch_sum(const double *x, int64_t n, double *out, hipStream_t st);
+// out[0] = sum_i x_i * y_i (fixed order), single workgroup
+hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, hipStream_t st);
+
+// Sparse structures -------------------------------------------------------------
+struct CscWork {
+    int64_t *colptr;     // n+1
+    int64_t *colcnt;     // n
+    int32_t *rowidx;     // capacity m*n
+    double *cval;        // capacity m*n
+    int32_t *blkcnt;     // rb * n
+    int rb;              // row blocks used for the deterministic transpose
+};
+hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
+                            const int32_t *len, CscWork &w, int64_t *nnz_dev, hipStream_t st);
+
+// HVP pieces: au_i = a_i * sum_{e} val * v[col]  (slotted CSR rows)
+hipError_t launch_row_gather(int64_t m, int64_t n, const int32_t *col, const double *val,
+                             const int32_t *len, const int *istar, const double *a, const double *v,
+                             double *au, int lpc, hipStream_t st);
+// y_j = (d_j v_j - sum_{CSC col j} cval * au[row]) / eta + shift * v_j
+hipError_t launch_col_gather(int64_t n, const int64_t *colptr, const int32_t *rowidx,
+                             const double *cval, const double *au, const double *d,
+                             const double *v, double eta, double shift, double *y, int lpc,
+                             hipStream_t st);
+
+// CG on device: see cg.hip
+struct CgState {
+    double *x, *r, *p, *Ap, *au;   // n, n, n, n, m
+    double *partial;               // >= number of workgroups of the vector kernels
+    double *scal;                  // device scalars (see CG_* slots)
+    unsigned *counter;             // 2 counters, zero-initialised
+};
+enum { CG_RR = 0, CG_PAP, CG_ALPHA, CG_BETA, CG_TOL, CG_DONE, CG_IT, CG_MAXIT, CG_NSLOT };
+hipError_t launch_cg_init(int64_t n, const double *rhs, double tol, int maxit, CgState &s,
+                          hipStream_t st);
+hipError_t launch_cg_iteration(int64_t m, int64_t n, const int32_t *col, const double *val,
+                               const int32_t *len, const int *istar, const int64_t *colptr,
+                               const int32_t *rowidx, const double *cval, const double *d,
+                               const double *a, double eta, double shift, CgState &s, int lpc_row,
+                               int lpc_col, hipStream_t st);
+
+// export slotted CSR to standard CSR
+hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const double *val,
+                             const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,
+                             hipStream_t st);
+
+}  // namespace ibsn

@@ -1,0 +1,48 @@
+// solver_kernels.h -- device scalar slots and launchers of solver_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibsn {
+
+// slots of the device scalar array (doubles)
+enum {
+    SC_GN2 = 0, SC_GN, SC_G1,               // ||g||^2, ||g||, ||g||_1
+    SC_BIG, SC_TAUSHIFT,                    // Armijo trial form
+    SC_OBJ, SC_DL, SC_GD, SC_BD, SC_ROWSUM, // objective, dL, g^T Delta, b^T Delta, part sum
+    SC_BG, SC_BP, SC_ER1, SC_COLRES,        // stop test
+    SC_SUMA, SC_SUMB, SC_MINA, SC_MINB, SC_BAD, SC_ISTAR,
+    SC_NNZ,                                 // (as double) nnz of the last factor
+    SC_NSLOT = 32
+};
+
+hipError_t sk_gnorms(int64_t n, const double *g, double *scal, hipStream_t st);
+hipError_t sk_sinkhorn_step(int64_t n, double eta, const double *b, const double *c,
+                            double *gamma, hipStream_t st);
+hipError_t sk_center(int64_t n, double *gamma, hipStream_t st);
+hipError_t sk_trial_prep(int64_t n, double t, double eta, const double *Delta, double *colv,
+                         double *scal, hipStream_t st);
+// scal[slot] = alpha * (op-reduce_g part[g*stride+off]) + beta * scal[src] (src < 0: none);
+// op 0 = sum, 1 = max, 2 = min
+hipError_t sk_sum_parts(int G, int stride, int off, const double *part, double alpha, double beta,
+                        int src, int slot, int op, double *scal, hipStream_t st);
+hipError_t sk_dot_slot(int64_t n, const double *x, const double *y, int slot, double *scal,
+                       hipStream_t st);
+hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *w,
+                        const double *gamma, const double *colX, const double *colF, double *y,
+                        double *ec, double *psi, double *scal, hipStream_t st);
+hipError_t sk_stop_final(int G, const double *part, int64_t m, const double *a, int64_t n,
+                         const double *b, const double *rowres_part, int G1, double *scal,
+                         double *out, hipStream_t st);
+hipError_t sk_problem_scalars(int64_t m, int64_t n, const double *a, const double *b,
+                              double *scal, int *istar, hipStream_t st);
+hipError_t sk_outer_update(int64_t m, int64_t n, const double *a, const double *M, const double *S,
+                           const double *w, double *r, double *s, hipStream_t st);
+hipError_t sk_init_center(int64_t m, int64_t n, const double *a, const double *b, double *r,
+                          double *s, hipStream_t st);
+hipError_t sk_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t st);
+hipError_t sk_neg(int64_t n, const double *x, double *y, hipStream_t st);
+hipError_t sk_zero_i32(int64_t count, int32_t *x, hipStream_t st);
+
+}  // namespace ibsn

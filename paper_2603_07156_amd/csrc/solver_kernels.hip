@@ -1,0 +1,448 @@
+// solver_kernels.hip -- n- and m-vector steps of the IBSN iteration (Algorithm 2) that
+// sit between the dense passes: norms of g, the Sinkhorn gamma-step with centring,
+// the Armijo column factors, the rounding vectors of Algorithm 3, the certificate
+// finalisation and the outer update of the implicit prox centre.
+//
+// Each reduction runs in one workgroup of 1024 threads with a fixed summation order
+// (thread-strided partial sums, then a butterfly and an ordered fold), so results do
+// not depend on timing.  Scalars are exchanged through a small device array `scal`.
+#include "ibsn_internal.h"
+#include "solver_kernels.h"
+
+#include <math.h>
+
+namespace ibsn {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int NT = 1024;
+constexpr int NW = NT / WAVE;
+
+template <int OP>
+__device__ __forceinline__ double comb(double x, double y)
+{
+    if constexpr (OP == 0)
+        return x + y;
+    else if constexpr (OP == 1)
+        return fmax(x, y);
+    else
+        return fmin(x, y);
+}
+
+// reduction over the 1024 threads; result in every thread
+template <int OP>
+__device__ __forceinline__ double wg_red(double v, double *lds)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1)
+        v = comb<OP>(v, __shfl_xor(v, o, WAVE));
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        lds[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    double r = lds[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k)
+        r = comb<OP>(r, lds[k]);
+    return r;
+}
+
+// scal[SC_GN2] = ||g||^2, scal[SC_G1] = ||g||_1, scal[SC_GN] = ||g||
+__global__ __launch_bounds__(NT) void k_gnorms(int n, const double *__restrict__ g,
+                                               double *__restrict__ scal)
+{
+    __shared__ double lds[NW];
+    double s2 = 0.0, s1 = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double v = g[j];
+        s2 = fma(v, v, s2);
+        s1 += fabs(v);
+    }
+    s2 = wg_red<0>(s2, lds);
+    s1 = wg_red<0>(s1, lds);
+    if (threadIdx.x == 0) {
+        scal[SC_GN2] = s2;
+        scal[SC_GN] = sqrt(s2);
+        scal[SC_G1] = s1;
+    }
+}
+
+// Sinkhorn gamma-step on Z^k with zeta = zeta(gamma) (eq. (4), (5)):
+// gamma_j += eta (log b_j - log c_j), then gamma -= mean(gamma) (Algorithm 2, step 4).
+__global__ __launch_bounds__(NT) void k_sinkhorn_step(int n, double eta, const double *__restrict__ b,
+                                                      const double *__restrict__ c,
+                                                      double *__restrict__ gamma)
+{
+    __shared__ double lds[NW];
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double v = gamma[j] + eta * (log(b[j]) - log(c[j]));
+        gamma[j] = v;
+        s += v;
+    }
+    s = wg_red<0>(s, lds);
+    const double mean = s / (double)n;
+    for (int j = threadIdx.x; j < n; j += NT)
+        gamma[j] -= mean;
+}
+
+__global__ __launch_bounds__(NT) void k_center(int n, double *__restrict__ gamma)
+{
+    __shared__ double lds[NW];
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT)
+        s += gamma[j];
+    s = wg_red<0>(s, lds);
+    const double mean = s / (double)n;
+    for (int j = threadIdx.x; j < n; j += NT)
+        gamma[j] -= mean;
+}
+
+// Armijo column factors for step t along Delta: tau = t Delta / eta.
+// small step (max tau <= 500): colv = expm1(tau), shift 0;
+// big step: colv = exp(tau - max tau), shift = max tau.
+// Also scal[SC_BD] = b^T Delta is not touched here (computed once per direction).
+__global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta,
+                                                   const double *__restrict__ Delta,
+                                                   double *__restrict__ colv,
+                                                   double *__restrict__ scal)
+{
+    __shared__ double lds[NW];
+    double mx = -INFINITY;
+    for (int j = threadIdx.x; j < n; j += NT)
+        mx = fmax(mx, t * Delta[j] / eta);
+    mx = wg_red<1>(mx, lds);
+    const bool big = mx > 500.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double tau = t * Delta[j] / eta;
+        colv[j] = big ? exp(tau - mx) : expm1(tau);
+    }
+    if (threadIdx.x == 0) {
+        scal[SC_BIG] = big ? 1.0 : 0.0;
+        scal[SC_TAUSHIFT] = big ? mx : 0.0;
+    }
+}
+
+// sum of G per-workgroup values (fixed order) combined into an objective-type scalar:
+// scal[slot] = alpha * sum_g part[g*stride + off] + beta * scal[src]
+__global__ __launch_bounds__(NT) void k_sum_parts(int G, int stride, int off,
+                                                  const double *__restrict__ part, double alpha,
+                                                  double beta, int src, int slot, int op,
+                                                  double *__restrict__ scal)
+{
+    __shared__ double lds[NW];
+    double s = op == 0 ? 0.0 : (op == 1 ? -INFINITY : INFINITY);
+    for (int g = threadIdx.x; g < G; g += NT) {
+        const double v = part[(int64_t)g * stride + off];
+        s = op == 0 ? s + v : (op == 1 ? fmax(s, v) : fmin(s, v));
+    }
+    if (op == 0)
+        s = wg_red<0>(s, lds);
+    else if (op == 1)
+        s = wg_red<1>(s, lds);
+    else
+        s = wg_red<2>(s, lds);
+    if (threadIdx.x == 0)
+        scal[slot] = alpha * s + (src >= 0 ? beta * scal[src] : 0.0);
+}
+
+// dot product into scal[slot]: x.y (or sum x if y == null)
+__global__ __launch_bounds__(NT) void k_dot_slot(int n, const double *__restrict__ x,
+                                                 const double *__restrict__ y, int slot,
+                                                 double *__restrict__ scal)
+{
+    __shared__ double lds[NW];
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT)
+        s = y ? fma(x[j], y[j], s) : s + x[j];
+    s = wg_red<0>(s, lds);
+    if (threadIdx.x == 0)
+        scal[slot] = s;
+}
+
+// Algorithm 3 vectors after pass 1: y_j = min(b_j / colX_j, 1), e_c = b - y.colF,
+// ||e_r||_1 = sum a - sum_j y_j colF_j (sum of the rows of F), psi_j = (w_j - log b_j)/sigma,
+// column residual sum_j (colX_j - b_j)^2, b^T gamma, b^T psi.
+__global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const double *__restrict__ b,
+                                                  const double *__restrict__ w,
+                                                  const double *__restrict__ gamma,
+                                                  const double *__restrict__ colX,
+                                                  const double *__restrict__ colF,
+                                                  double *__restrict__ y, double *__restrict__ ec,
+                                                  double *__restrict__ psi,
+                                                  double *__restrict__ scal)
+{
+    __shared__ double lds[NW];
+    double syf = 0.0, cc = 0.0, bg = 0.0, bp = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double bj = b[j], cx = colX[j], cf = colF[j];
+        const double yj = fmin(bj / cx, 1.0);
+        const double fj = yj * cf;
+        y[j] = yj;
+        ec[j] = bj - fj;
+        syf += fj;
+        cc = fma(cx - bj, cx - bj, cc);
+        const double pj = (w[j] - log(bj)) / sigma;
+        psi[j] = pj;
+        bg = fma(bj, gamma[j], bg);
+        bp = fma(bj, pj, bp);
+    }
+    syf = wg_red<0>(syf, lds);
+    cc = wg_red<0>(cc, lds);
+    bg = wg_red<0>(bg, lds);
+    bp = wg_red<0>(bp, lds);
+    if (threadIdx.x == 0) {
+        scal[SC_ER1] = scal[SC_SUMA] - syf;
+        scal[SC_COLRES] = cc;
+        scal[SC_BG] = bg;
+        scal[SC_BP] = bp;
+    }
+}
+
+// Certificate and KKT finalisation into out[10] (see ibsn_stop in ibsn.h).
+__global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restrict__ part, int m,
+                                                   const double *__restrict__ a, int n,
+                                                   const double *__restrict__ b,
+                                                   const double *__restrict__ rowres_part, int G1,
+                                                   double *__restrict__ scal,
+                                                   double *__restrict__ out)
+{
+    __shared__ double lds[NW];
+    double v[STOP2_NSLOT];
+#pragma unroll
+    for (int k = 0; k < STOP2_NSLOT; ++k)
+        v[k] = (k == STOP2_XHMIN) ? INFINITY : 0.0;
+    for (int g = threadIdx.x; g < G; g += NT) {
+        const double *p = part + (int64_t)g * STOP2_NSLOT;
+#pragma unroll
+        for (int k = 0; k < STOP2_NSLOT; ++k)
+            v[k] = (k == STOP2_XHMIN) ? fmin(v[k], p[k]) : v[k] + p[k];
+    }
+#pragma unroll
+    for (int k = 0; k < STOP2_NSLOT; ++k)
+        v[k] = (k == STOP2_XHMIN) ? wg_red<2>(v[k], lds) : wg_red<0>(v[k], lds);
+    double rr = 0.0;
+    for (int g = threadIdx.x; g < G1; g += NT)
+        rr += rowres_part[g];
+    rr = wg_red<0>(rr, lds);
+    double na = 0.0, nb = 0.0;
+    for (int i = threadIdx.x; i < m; i += NT)
+        na = fma(a[i], a[i], na);
+    for (int j = threadIdx.x; j < n; j += NT)
+        nb = fma(b[j], b[j], nb);
+    na = wg_red<0>(na, lds);
+    nb = wg_red<0>(nb, lds);
+    if (threadIdx.x == 0) {
+        const double dual_g = v[STOP2_AZG] + scal[SC_BG];
+        const double dual_p = v[STOP2_AZP] + scal[SC_BP];
+        double dp = fmax(sqrt(rr) / (1.0 + sqrt(na)), sqrt(scal[SC_COLRES]) / (1.0 + sqrt(nb)));
+        dp = fmax(dp, 0.0 / (1.0 + sqrt(v[STOP2_XF])));
+        const double dc = fabs(v[STOP2_XU]) / (1.0 + sqrt(v[STOP2_CF]));
+        out[0] = v[STOP2_DPHI];
+        out[1] = v[STOP2_CXH];
+        out[2] = fmax(dual_g, dual_p);
+        out[3] = v[STOP2_CX];
+        out[4] = fmax(dp, dc);
+        out[5] = v[STOP2_XHMIN];
+        out[6] = scal[SC_ER1];
+        out[7] = v[STOP2_XU];
+        out[8] = dual_g;
+        out[9] = dual_p;
+    }
+}
+
+// outer update of the implicit centre (Algorithm 2, step 13 with eq. (7)):
+// r_i = log a_i - (M_i + log S_i); s_j = w_j (= s_j + gamma_j / eta)
+__global__ __launch_bounds__(256) void k_outer_update(int m, int n, const double *__restrict__ a,
+                                                      const double *__restrict__ M,
+                                                      const double *__restrict__ S,
+                                                      const double *__restrict__ w,
+                                                      double *__restrict__ r,
+                                                      double *__restrict__ s)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < m)
+        r[t] = log(a[t]) - (M[t] + log(S[t]));
+    if (t < n)
+        s[t] = w[t];
+}
+
+// r = log a, s = log b (X^0 = a b^T)
+__global__ __launch_bounds__(256) void k_init_center(int m, int n, const double *__restrict__ a,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ r,
+                                                     double *__restrict__ s)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < m)
+        r[t] = log(a[t]);
+    if (t < n)
+        s[t] = log(b[t]);
+}
+
+// y = alpha x + y (n)
+__global__ __launch_bounds__(256) void k_axpy(int n, double alpha, const double *__restrict__ x,
+                                              double *__restrict__ y)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n)
+        y[j] = fma(alpha, x[j], y[j]);
+}
+
+__global__ __launch_bounds__(256) void k_neg(int n, const double *__restrict__ x,
+                                             double *__restrict__ y)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n)
+        y[j] = -x[j];
+}
+
+// Problem checks and per-problem scalars: istar = argmax a (lowest index on ties),
+// sum a, sum b, min a, min b, count of non-finite entries of a, b.
+__global__ __launch_bounds__(NT) void k_problem_scalars(int m, int n, const double *__restrict__ a,
+                                                        const double *__restrict__ b,
+                                                        double *__restrict__ scal,
+                                                        int *__restrict__ istar)
+{
+    __shared__ double lds[NW];
+    __shared__ int ilds[NT];
+    double sa = 0.0, sb = 0.0, mina = INFINITY, minb = INFINITY, bad = 0.0, best = -INFINITY;
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < m; i += NT) {
+        const double v = a[i];
+        sa += v;
+        mina = fmin(mina, v);
+        if (!isfinite(v))
+            bad += 1.0;
+        if (v > best) {
+            best = v;
+            bi = i;
+        }
+    }
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double v = b[j];
+        sb += v;
+        minb = fmin(minb, v);
+        if (!isfinite(v))
+            bad += 1.0;
+    }
+    sa = wg_red<0>(sa, lds);
+    sb = wg_red<0>(sb, lds);
+    mina = wg_red<2>(mina, lds);
+    minb = wg_red<2>(minb, lds);
+    bad = wg_red<0>(bad, lds);
+    const double gbest = wg_red<1>(best, lds);
+    ilds[threadIdx.x] = (best == gbest) ? bi : 0x7fffffff;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            ilds[threadIdx.x] = min(ilds[threadIdx.x], ilds[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scal[SC_SUMA] = sa;
+        scal[SC_SUMB] = sb;
+        scal[SC_MINA] = mina;
+        scal[SC_MINB] = minb;
+        scal[SC_BAD] = bad;
+        *istar = ilds[0];
+        scal[SC_ISTAR] = (double)ilds[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_i32(int64_t count, int32_t *__restrict__ x)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * 256)
+        x[t] = 0;
+}
+
+}  // namespace
+
+// ---- launchers --------------------------------------------------------------------
+#define L1(kern, ...)                                                          \
+    do {                                                                       \
+        hipLaunchKernelGGL(kern, dim3(1), dim3(NT), 0, st, __VA_ARGS__);       \
+        return hipGetLastError();                                              \
+    } while (0)
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t sk_gnorms(int64_t n, const double *g, double *scal, hipStream_t st)
+{
+    L1(k_gnorms, (int)n, g, scal);
+}
+hipError_t sk_sinkhorn_step(int64_t n, double eta, const double *b, const double *c,
+                            double *gamma, hipStream_t st)
+{
+    L1(k_sinkhorn_step, (int)n, eta, b, c, gamma);
+}
+hipError_t sk_center(int64_t n, double *gamma, hipStream_t st) { L1(k_center, (int)n, gamma); }
+hipError_t sk_trial_prep(int64_t n, double t, double eta, const double *Delta, double *colv,
+                         double *scal, hipStream_t st)
+{
+    L1(k_trial_prep, (int)n, t, eta, Delta, colv, scal);
+}
+hipError_t sk_sum_parts(int G, int stride, int off, const double *part, double alpha, double beta,
+                        int src, int slot, int op, double *scal, hipStream_t st)
+{
+    L1(k_sum_parts, G, stride, off, part, alpha, beta, src, slot, op, scal);
+}
+hipError_t sk_dot_slot(int64_t n, const double *x, const double *y, int slot, double *scal,
+                       hipStream_t st)
+{
+    L1(k_dot_slot, (int)n, x, y, slot, scal);
+}
+hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *w,
+                        const double *gamma, const double *colX, const double *colF, double *y,
+                        double *ec, double *psi, double *scal, hipStream_t st)
+{
+    L1(k_stop_prep, (int)n, sigma, b, w, gamma, colX, colF, y, ec, psi, scal);
+}
+hipError_t sk_stop_final(int G, const double *part, int64_t m, const double *a, int64_t n,
+                         const double *b, const double *rowres_part, int G1, double *scal,
+                         double *out, hipStream_t st)
+{
+    L1(k_stop_final, G, part, (int)m, a, (int)n, b, rowres_part, G1, scal, out);
+}
+hipError_t sk_problem_scalars(int64_t m, int64_t n, const double *a, const double *b,
+                              double *scal, int *istar, hipStream_t st)
+{
+    L1(k_problem_scalars, (int)m, (int)n, a, b, scal, istar);
+}
+hipError_t sk_outer_update(int64_t m, int64_t n, const double *a, const double *M, const double *S,
+                           const double *w, double *r, double *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_outer_update, dim3(nblk(m > n ? m : n)), dim3(256), 0, st, (int)m, (int)n,
+                       a, M, S, w, r, s);
+    return hipGetLastError();
+}
+hipError_t sk_init_center(int64_t m, int64_t n, const double *a, const double *b, double *r,
+                          double *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_center, dim3(nblk(m > n ? m : n)), dim3(256), 0, st, (int)m, (int)n,
+                       a, b, r, s);
+    return hipGetLastError();
+}
+hipError_t sk_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, (int)n, alpha, x, y);
+    return hipGetLastError();
+}
+hipError_t sk_neg(int64_t n, const double *x, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_neg, dim3(nblk(n)), dim3(256), 0, st, (int)n, x, y);
+    return hipGetLastError();
+}
+hipError_t sk_zero_i32(int64_t count, int32_t *x, hipStream_t st)
+{
+    int64_t b = (count + 255) / 256;
+    if (b > 4096)
+        b = 4096;
+    if (b < 1)
+        b = 1;
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)b), dim3(256), 0, st, count, x);
+    return hipGetLastError();
+}
+
+}  // namespace ibsn

@@ -1,0 +1,369 @@
+"""ctypes binding of libibsn.so (include/ibsn.h).
+
+Argument marshalling only: every function below checks its torch tensors (device,
+dtype, contiguity, length), passes their device pointers and the current HIP stream
+to the C ABI, and returns the outputs.  All arithmetic runs in the library's HIP
+kernels.  The library must be built (``python -m paper_2603_07156_amd.build``); a
+missing library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibsn.so")
+
+IBSN_OK = 0
+IBSN_WARN_MAXITER = 1
+IBSN_COST_F64 = 0
+IBSN_COST_F32 = 1
+MAX_N_F64 = 20480
+
+
+class IBSNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libibsn error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(ct.Structure):
+    _fields_ = [("m", ct.c_int64), ("n", ct.c_int64), ("cost_kind", ct.c_int32),
+                ("C", ct.c_void_p), ("ldc", ct.c_int64), ("a", ct.c_void_p), ("b", ct.c_void_p),
+                ("eta", ct.c_double)]
+
+
+class _Center(ct.Structure):
+    _fields_ = [("k", ct.c_int64), ("r", ct.c_void_p), ("s", ct.c_void_p)]
+
+
+class Options(ct.Structure):
+    _fields_ = [
+        ("sigma_armijo", ct.c_double), ("beta", ct.c_double),
+        ("sinkhorn_tol", ct.c_double), ("sinkhorn_maxit", ct.c_int32),
+        ("mu0", ct.c_double), ("mu_floor", ct.c_double),
+        ("gap_tol", ct.c_double), ("marg_tol", ct.c_double), ("kkt_tol", ct.c_double),
+        ("max_outer", ct.c_int32), ("max_newton", ct.c_int32), ("max_backtrack", ct.c_int32),
+        ("cg_maxit", ct.c_int32), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int32),
+    ]
+
+
+class Report(ct.Structure):
+    _fields_ = [
+        ("outer", ct.c_int64), ("newton", ct.c_int64), ("cg", ct.c_int64),
+        ("sinkhorn", ct.c_int64), ("backtracks", ct.c_int64), ("stop_tests", ct.c_int64),
+        ("passes", ct.c_int64),
+        ("grad_norm", ct.c_double), ("primal", ct.c_double), ("dual", ct.c_double),
+        ("rel_gap", ct.c_double), ("kkt", ct.c_double), ("dphi", ct.c_double),
+        ("marg_l1", ct.c_double),
+        ("t_eval", ct.c_double), ("t_sparsify", ct.c_double), ("t_cg", ct.c_double),
+        ("t_linesearch", ct.c_double), ("t_stop", ct.c_double), ("t_total", ct.c_double),
+        ("status", ct.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
+           "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
+           "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
+           "ibsn_default_options", "ibsn_solve")
+
+
+def load():
+    """Load libibsn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2603_07156_amd.build` (no CPU fallback exists)")
+    L = ct.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_double
+    P, C = ct.POINTER(_Problem), ct.POINTER(_Center)
+    L.ibsn_create.argtypes = [ct.POINTER(vp), ct.c_int, vp]
+    L.ibsn_destroy.argtypes = [vp]
+    L.ibsn_destroy.restype = None
+    L.ibsn_last_error.argtypes = [vp]
+    L.ibsn_last_error.restype = ct.c_char_p
+    L.ibsn_num_cus.argtypes = [vp]
+    L.ibsn_subproblem_eval.argtypes = [vp, P, C, vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), vp]
+    L.ibsn_trial.argtypes = [vp, P, C, vp, vp, vp, dbl, ct.POINTER(dbl), vp, vp, vp, vp]
+    L.ibsn_sparsify.argtypes = [vp, P, C, vp, vp, vp, dbl, i64, ct.POINTER(vp)]
+    L.ibsn_csr_info.argtypes = [vp, vp, ct.POINTER(i64), ct.POINTER(i64)]
+    L.ibsn_csr_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.ibsn_csr_free.argtypes = [vp]
+    L.ibsn_csr_free.restype = None
+    L.ibsn_hvp.argtypes = [vp, vp, vp, dbl, dbl, vp, vp]
+    L.ibsn_cg.argtypes = [vp, vp, vp, dbl, dbl, vp, dbl, ct.c_int, vp, ct.POINTER(ct.c_int)]
+    L.ibsn_stop.argtypes = [vp, P, C, vp, vp, vp, ct.POINTER(dbl), vp]
+    L.ibsn_default_options.argtypes = [ct.POINTER(Options)]
+    L.ibsn_default_options.restype = None
+    L.ibsn_solve.argtypes = [vp, P, ct.POINTER(Options), vp, vp, vp, ct.POINTER(i64), vp,
+                             ct.POINTER(Report)]
+    for name in EXPORTS:
+        if not hasattr(L, name):
+            raise ImportError(f"{LIB_PATH} does not export {name}")
+    _lib = L
+    return L
+
+
+def _ptr(t, n=None, dtype=torch.float64, name="tensor", device=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (HIP) tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ct.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An ibsn_ctx bound to a device and to that device's current torch stream."""
+
+    def __init__(self, device: int | torch.device = 0, stream: torch.cuda.Stream | None = None):
+        L = load()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ct.c_void_p()
+        rc = L.ibsn_create(ct.byref(h), self.device.index or 0, ct.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise IBSNError(rc, "ibsn_create failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc < 0:
+            raise IBSNError(rc, load().ibsn_last_error(self.h).decode())
+        return rc
+
+    @property
+    def num_cus(self):
+        return load().ibsn_num_cus(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ibsn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Problem:
+    """eq. (1) data on the device: C (m x n, float64 or float32, row-major), a, b, eta."""
+
+    C: torch.Tensor
+    a: torch.Tensor
+    b: torch.Tensor
+    eta: float
+
+    @property
+    def m(self):
+        return self.C.shape[0]
+
+    @property
+    def n(self):
+        return self.C.shape[1]
+
+    def raw(self):
+        if self.C.dim() != 2 or self.C.stride(1) != 1:
+            raise ValueError("C must be a row-major 2-D tensor")
+        if self.C.dtype == torch.float64:
+            kind = IBSN_COST_F64
+        elif self.C.dtype == torch.float32:
+            kind = IBSN_COST_F32
+        else:
+            raise TypeError("C must be float64 or float32")
+        if not self.C.is_cuda:
+            raise ValueError("C must be a device tensor")
+        dev = self.C.device
+        return _Problem(self.m, self.n, kind, ct.c_void_p(self.C.data_ptr()), self.C.stride(0),
+                        _ptr(self.a, self.m, name="a", device=dev),
+                        _ptr(self.b, self.n, name="b", device=dev), float(self.eta))
+
+
+@dataclass
+class Center:
+    """Implicit prox centre log X^k = r + s - k C / eta (r may be None if unused)."""
+
+    k: int
+    r: torch.Tensor | None
+    s: torch.Tensor
+
+    def raw(self, m, n):
+        return _Center(int(self.k), _ptr(self.r, m, name="r"), _ptr(self.s, n, name="s"))
+
+    @staticmethod
+    def initial(prob: Problem) -> "Center":
+        """X^0 = a b^T (Algorithm 2 input)."""
+        return Center(0, torch.log(prob.a), torch.log(prob.b))
+
+
+def _new(prob, count):
+    return torch.empty(count, dtype=torch.float64, device=prob.C.device)
+
+
+def subproblem_eval(ctx: Context, prob: Problem, center: Center, gamma: torch.Tensor,
+                    want_obj: bool = True, want_plan: bool = False, want_lse: bool = True):
+    """ibsn_subproblem_eval: returns dict(M, S, lse, c, g, L, plan)."""
+    m, n = prob.m, prob.n
+    M, S, c, g = _new(prob, m), _new(prob, m), _new(prob, n), _new(prob, n)
+    lse = _new(prob, m) if want_lse else None
+    plan = torch.empty((m, n), dtype=torch.float64, device=prob.C.device) if want_plan else None
+    obj = ct.c_double(float("nan"))
+    ctx.check(load().ibsn_subproblem_eval(
+        ctx.h, ct.byref(prob.raw()), ct.byref(center.raw(m, n)), _ptr(gamma, n, name="gamma"),
+        _ptr(M), _ptr(S), _ptr(lse), _ptr(c), _ptr(g), ct.byref(obj) if want_obj else None,
+        _ptr(plan)))
+    return dict(M=M, S=S, lse=lse, c=c, g=g, L=obj.value if want_obj else None, plan=plan)
+
+
+def trial(ctx: Context, prob: Problem, center: Center, gamma, M, Delta, t: float):
+    """ibsn_trial: Armijo trial at gamma + t Delta.  Returns dict(dL, M, S, c, g)."""
+    m, n = prob.m, prob.n
+    Mn, Sn, cn, gn = _new(prob, m), _new(prob, m), _new(prob, n), _new(prob, n)
+    dL = ct.c_double()
+    ctx.check(load().ibsn_trial(ctx.h, ct.byref(prob.raw()), ct.byref(center.raw(m, n)),
+                                _ptr(gamma, n, name="gamma"), _ptr(M, m, name="M"),
+                                _ptr(Delta, n, name="Delta"), float(t), ct.byref(dL), _ptr(Mn),
+                                _ptr(Sn), _ptr(cn), _ptr(gn)))
+    return dict(dL=dL.value, M=Mn, S=Sn, c=cn, g=gn)
+
+
+class Csr:
+    """Library-owned sparsified factor P_rho (Algorithm 1)."""
+
+    def __init__(self, ctx: Context, h, m, n, device):
+        self.ctx, self.h, self.m, self.n, self.device = ctx, h, m, n, device
+        nnz, istar = ct.c_int64(), ct.c_int64()
+        ctx.check(load().ibsn_csr_info(ctx.h, h, ct.byref(nnz), ct.byref(istar)))
+        self.nnz, self.istar = nnz.value, istar.value
+
+    def export(self):
+        """Standard CSR copy: (row_ptr int64, col int32, val f64, d f64) device tensors."""
+        row_ptr = torch.empty(self.m + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.device)
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self.ctx.check(load().ibsn_csr_export(self.ctx.h, self.h, _ptr(row_ptr, dtype=torch.int64),
+                                              _ptr(col, dtype=torch.int32), _ptr(val), _ptr(d)))
+        return row_ptr, col[: self.nnz], val[: self.nnz], d
+
+    def free(self):
+        if self.h:
+            load().ibsn_csr_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sparsify(ctx: Context, prob: Problem, center: Center, gamma, M, S, rho: float,
+             istar: int = -1) -> Csr:
+    """ibsn_sparsify (Algorithm 1) from the row state (M, S)."""
+    m, n = prob.m, prob.n
+    h = ct.c_void_p()
+    ctx.check(load().ibsn_sparsify(ctx.h, ct.byref(prob.raw()), ct.byref(center.raw(m, n)),
+                                   _ptr(gamma, n, name="gamma"), _ptr(M, m, name="M"),
+                                   _ptr(S, m, name="S"), float(rho), int(istar), ct.byref(h)))
+    return Csr(ctx, h, m, n, prob.C.device)
+
+
+def hvp(ctx: Context, csr: Csr, a, eta: float, shift: float, v):
+    """ibsn_hvp: (H_rho + shift I) v."""
+    y = torch.empty(csr.n, dtype=torch.float64, device=csr.device)
+    ctx.check(load().ibsn_hvp(ctx.h, csr.h, _ptr(a, csr.m, name="a"), float(eta), float(shift),
+                              _ptr(v, csr.n, name="v"), _ptr(y)))
+    return y
+
+
+def cg(ctx: Context, csr: Csr, a, eta: float, shift: float, rhs, tol: float, maxit: int):
+    """ibsn_cg: returns (x, iterations)."""
+    x = torch.empty(csr.n, dtype=torch.float64, device=csr.device)
+    it = ct.c_int()
+    ctx.check(load().ibsn_cg(ctx.h, csr.h, _ptr(a, csr.m, name="a"), float(eta), float(shift),
+                             _ptr(rhs, csr.n, name="rhs"), float(tol), int(maxit), _ptr(x),
+                             ct.byref(it)))
+    return x, it.value
+
+
+STOP_FIELDS = ("dphi", "primal", "dual", "cx", "kkt", "xhat_min", "er1", "xu", "dual_gamma",
+               "dual_psi")
+
+
+def stop(ctx: Context, prob: Problem, center: Center, gamma, M, S, want_xhat: bool = False):
+    """ibsn_stop: rounding (Algorithm 3), D_phi and the certificate."""
+    m, n = prob.m, prob.n
+    out = (ct.c_double * 10)()
+    xhat = torch.empty((m, n), dtype=torch.float64, device=prob.C.device) if want_xhat else None
+    ctx.check(load().ibsn_stop(ctx.h, ct.byref(prob.raw()), ct.byref(center.raw(m, n)),
+                               _ptr(gamma, n, name="gamma"), _ptr(M, m, name="M"),
+                               _ptr(S, m, name="S"), out, _ptr(xhat)))
+    res = dict(zip(STOP_FIELDS, list(out)))
+    if want_xhat:
+        res["xhat"] = xhat
+    return res
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().ibsn_default_options(ct.byref(o))
+    for key, v in kw.items():
+        if not hasattr(o, key):
+            raise KeyError(key)
+        setattr(o, key, v)
+    return o
+
+
+def solve(ctx: Context, prob: Problem, options: Options | None = None, gamma0=None, state=None,
+          want_plan: bool = False):
+    """ibsn_solve (Algorithm 2).  state = (r, s, k) resumes an outer state.
+    Returns dict(status, gamma, r, s, k, plan, report)."""
+    m, n = prob.m, prob.n
+    gamma = _new(prob, n)
+    if gamma0 is not None:
+        gamma.copy_(gamma0)
+    else:
+        gamma.zero_()
+    r, s = _new(prob, m), _new(prob, n)
+    k = ct.c_int64(0)
+    if state is not None:
+        r.copy_(state[0])
+        s.copy_(state[1])
+        k.value = int(state[2])
+    plan = torch.empty((m, n), dtype=torch.float64, device=prob.C.device) if want_plan else None
+    rep = Report()
+    opt = options if options is not None else default_options()
+    rc = ctx.check(load().ibsn_solve(ctx.h, ct.byref(prob.raw()), ct.byref(opt), _ptr(gamma),
+                                     _ptr(r), _ptr(s), ct.byref(k), _ptr(plan), ct.byref(rep)))
+    return dict(status=rc, gamma=gamma, r=r, s=s, k=k.value, plan=plan, report=rep.as_dict())
+
+
+# the C-ABI names
+ibsn_subproblem_eval = subproblem_eval
+ibsn_trial = trial
+ibsn_sparsify = sparsify
+ibsn_hvp = hvp
+ibsn_cg = cg
+ibsn_stop = stop
+ibsn_solve = solve

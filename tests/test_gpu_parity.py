@@ -1,0 +1,375 @@
+"""HIP path vs the CPU oracle, element by element, on identical seeded inputs.
+
+Every call goes through the C ABI of libibsn.so (via the ctypes binding).  Sizes span
+several row tiles and ragged tails; the 4096 and 10^4 cases use the launch
+configuration of the benchmark.  Tolerances are written next to each check; they are
+tighter than the parity bar of the task (1e-10 relative objective, 1e-9 absolute per
+plan entry, identical sparsity pattern except within 1e-12 of the threshold).
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2603_07156_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_2603_07156_amd import ibsn
+    return ibsn
+
+
+@pytest.fixture(scope="module")
+def ctx(ib):
+    return ib.Context(0)
+
+
+def dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def problem(ib, inst, C=None):
+    C = inst.C if C is None else C
+    return ib.Problem(dev(C), dev(inst.a), dev(inst.b), inst.eta)
+
+
+def outer_state(inst, k):
+    """(r, s, k, gamma) after k oracle outer iterations (k = 0: the initial centre)."""
+    if k == 0:
+        return np.log(inst.a), np.log(inst.b), 0, W.random_dual(inst.n, 17, 0.02)
+    opt = orc.default_options(max_outer=k, gap_tol=0.0, marg_tol=0.0)
+    res = orc.solve(inst.C, inst.a, inst.b, inst.eta, options=opt)
+    return res["r"], res["s"], res["k"], res["gamma"] + W.random_dual(inst.n, 3, 1e-4)
+
+
+def check_eval(ib, ctx, inst, r, s, k, gamma, C=None, want_plan=True):
+    Cc = inst.C if C is None else C
+    pr = problem(ib, inst, Cc)
+    ctr = ib.Center(k, dev(r), dev(s))
+    gv = ib.subproblem_eval(ctx, pr, ctr, dev(gamma), want_obj=True, want_plan=want_plan)
+    ov = orc.eval_pass(Cc, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, want_plan=want_plan)
+    # row maxima: the same single fma on identical inputs -> identical bits
+    np.testing.assert_array_equal(host(gv["M"]), ov.M)
+    np.testing.assert_allclose(host(gv["S"]), ov.S, rtol=1e-13)
+    np.testing.assert_allclose(host(gv["lse"]), ov.lse, rtol=1e-15, atol=1e-13)
+    np.testing.assert_allclose(host(gv["c"]), ov.c, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(host(gv["g"]), ov.g, rtol=0, atol=1e-12 * np.abs(ov.c).max())
+    scale = abs(inst.b @ gamma) + inst.eta * np.abs(inst.a * (r + ov.lse)).sum() + 1e-300
+    assert abs(gv["L"] - ov.L) <= 1e-12 * scale
+    if want_plan:
+        np.testing.assert_allclose(host(gv["plan"]), ov.plan, rtol=1e-12, atol=1e-15)
+    return gv, ov
+
+
+# ---------------------------------------------------------------------------
+# eval (row a2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 7), (5, 1), (3, 2), (37, 63), (40, 64), (41, 65),
+                                 (300, 257), (129, 511), (70, 513), (64, 1000), (33, 2047),
+                                 (17, 2049), (9, 4099), (8, 8191), (5, 10240)])
+def test_eval_shapes(ib, ctx, m, n):
+    inst = W.gmm_points(n, 5, m=m)
+    r, s, k, gamma = outer_state(inst, 0)
+    check_eval(ib, ctx, inst, r, s, k, gamma)
+
+
+@pytest.mark.parametrize("k", [0, 4, 25])
+def test_eval_outer_states(ib, ctx, k):
+    """Parity at later prox centres, where sigma = (k+1)/eta makes theta large."""
+    inst = W.uniform_points(300, 1, m=260)
+    r, s, kk, gamma = outer_state(inst, k)
+    check_eval(ib, ctx, inst, r, s, kk, gamma)
+
+
+def test_eval_fp32_cost(ib, ctx):
+    """FP32-stored cost: both sides widen the same float values to double."""
+    inst = W.gmm_points(1500, 9, m=200)
+    C32 = inst.C.astype(np.float32)
+    r, s, k, gamma = outer_state(inst, 0)
+    check_eval(ib, ctx, inst, r, s, k, gamma, C=C32)
+
+
+def test_eval_cfg2_size(ib, ctx):
+    """4096 x 4096 Gaussian-mixture instance (the GPU-vs-oracle workload)."""
+    inst = W.gmm_points(4096, 100)
+    r, s, k, gamma = outer_state(inst, 0)
+    check_eval(ib, ctx, inst, r, s, k, gamma, want_plan=False)
+
+
+def test_eval_full_size_10k(ib, ctx):
+    """10^4 x 10^4 (800 MB FP64 cost) in the benchmark's launch configuration."""
+    inst = W.uniform_points(10000, 1000)
+    r, s, k, gamma = np.log(inst.a), np.log(inst.b), 0, W.random_dual(10000, 2, 0.01)
+    check_eval(ib, ctx, inst, r, s, k, gamma, want_plan=False)
+
+
+def test_eval_deterministic(ib, ctx):
+    inst = W.uniform_points(700, 3, m=900)
+    pr = problem(ib, inst)
+    ctr = ib.Center.initial(pr)
+    gamma = dev(W.random_dual(700, 1, 0.01))
+    a = ib.subproblem_eval(ctx, pr, ctr, gamma)
+    b = ib.subproblem_eval(ctx, pr, ctr, gamma)
+    for key in ("M", "S", "c", "g"):
+        assert torch.equal(a[key], b[key])
+    assert a["L"] == b["L"]
+
+
+# ---------------------------------------------------------------------------
+# Armijo trial (row a6)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t", [1.0, 0.8, 1e-3, 1e-9])
+@pytest.mark.parametrize("k", [0, 6])
+def test_trial(ib, ctx, t, k):
+    inst = W.gmm_points(513, 12, m=301)
+    r, s, kk, gamma = outer_state(inst, k)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk)
+    Delta = W.random_dual(513, 44, 0.02)
+    pr = problem(ib, inst)
+    ctr = ib.Center(kk, dev(r), dev(s))
+    gt = ib.trial(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(Delta), t)
+    dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, Delta, t,
+                                        s=s, k=kk)
+    assert abs(gt["dL"] - dL) <= 1e-12 * abs(dL) + 1e-17 * t
+    np.testing.assert_allclose(host(gt["M"]) + np.log(host(gt["S"])), Mn + np.log(Sn), rtol=1e-15,
+                               atol=1e-12)
+    np.testing.assert_allclose(host(gt["c"]), cn, rtol=1e-12)
+    np.testing.assert_allclose(host(gt["g"]), gn, rtol=0, atol=1e-12 * np.abs(cn).max())
+
+
+def test_trial_big_step(ib, ctx):
+    """Steps with t*Delta/eta > 500 take the shifted form on both sides."""
+    inst = W.gmm_points(300, 2, m=200)
+    eta = 1e-3
+    inst = W.Instance(inst.C, inst.a, inst.b, eta, "big")
+    r, s, k, gamma = np.log(inst.a), np.log(inst.b), 0, np.zeros(300)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma)
+    Delta = W.random_dual(300, 7, 0.5)
+    pr = problem(ib, inst)
+    gt = ib.trial(ctx, pr, ib.Center(0, dev(r), dev(s)), dev(gamma), dev(ev.M), dev(Delta), 1.0)
+    dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, 1.0, s=s)
+    assert abs(gt["dL"] - dL) <= 1e-12 * abs(dL)
+    np.testing.assert_allclose(host(gt["c"]), cn, rtol=1e-11, atol=1e-300)
+
+
+# ---------------------------------------------------------------------------
+# sparsify (row a4), HVP and CG (row a5)
+# ---------------------------------------------------------------------------
+def compare_patterns(gcsr, ocsr, P, rho, istar):
+    row_ptr, col, val, d = (host(x) for x in gcsr.export())
+    assert gcsr.istar == ocsr.istar == istar
+    m = len(row_ptr) - 1
+    same = True
+    for i in range(m):
+        gc = col[row_ptr[i]:row_ptr[i + 1]]
+        oc = ocsr.col[ocsr.row_ptr[i]:ocsr.row_ptr[i + 1]]
+        assert np.all(np.diff(gc) > 0), "columns ascending within a row"
+        if not np.array_equal(gc, oc):
+            same = False
+            diff = np.setxor1d(gc, oc)
+            # allowed only inside the relative threshold band |P - rho| <= 1e-12 rho
+            assert np.all(np.abs(P[i, diff] - rho) <= 1e-12 * rho), (i, diff)
+        else:
+            np.testing.assert_allclose(val[row_ptr[i]:row_ptr[i + 1]],
+                                       ocsr.val[ocsr.row_ptr[i]:ocsr.row_ptr[i + 1]], rtol=1e-12)
+    return same, d
+
+
+@pytest.mark.parametrize("rho_rule", ["zero", "paper", "1e-6", "1e-4"])
+@pytest.mark.parametrize("k", [0, 5])
+def test_sparsify_and_hvp(ib, ctx, rho_rule, k):
+    inst = W.gmm_points(600, 8, m=420)
+    r, s, kk, gamma = outer_state(inst, k)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk, want_plan=True)
+    P = ev.plan / inst.a[:, None]
+    rho = {"zero": 0.0, "paper": inst.eta * np.linalg.norm(ev.g) / P.size,
+           "1e-6": 1e-6, "1e-4": 1e-4}[rho_rule]
+    pr = problem(ib, inst)
+    ctr = ib.Center(kk, dev(r), dev(s))
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=kk)
+    istar = int(np.argmax(inst.a))
+    same, d = compare_patterns(gcsr, ocsr, P, rho, istar)
+    assert same, "no entry of these inputs lies within the threshold band"
+    assert gcsr.nnz == ocsr.nnz
+    np.testing.assert_allclose(d, ocsr.d, rtol=1e-12)
+    for shift in (0.0, 1e-3):
+        v = W.random_dual(600, 21, 1.0)
+        yg = host(ib.hvp(ctx, gcsr, pr.a, inst.eta, shift, dev(v)))
+        yo = orc.hvp(ocsr, inst.a, inst.eta, shift, v)
+        np.testing.assert_allclose(yg, yo, rtol=1e-12, atol=1e-12 * np.abs(yo).max())
+    gcsr.free()
+
+
+def test_hvp_determinism_and_dense_row(ib, ctx):
+    """Row i* is dense (n entries); repeated products are bitwise identical."""
+    inst = W.gmm_points(2000, 4, m=1500)
+    r, s, k, gamma = outer_state(inst, 0)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k)
+    pr = problem(ib, inst)
+    ctr = ib.Center(k, dev(r), dev(s))
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), 1e-7)
+    row_ptr, col, val, d = (host(x) for x in gcsr.export())
+    i = gcsr.istar
+    assert row_ptr[i + 1] - row_ptr[i] == 2000
+    v = dev(W.random_dual(2000, 5, 1.0))
+    y1 = ib.hvp(ctx, gcsr, pr.a, inst.eta, 0.0, v)
+    y2 = ib.hvp(ctx, gcsr, pr.a, inst.eta, 0.0, v)
+    assert torch.equal(y1, y2)
+    # Theorem 3.2: H_rho 1 = 0
+    ones = torch.ones(2000, dtype=torch.float64, device="cuda")
+    h1 = host(ib.hvp(ctx, gcsr, pr.a, inst.eta, 0.0, ones))
+    assert np.abs(h1).max() <= 1e-12 / inst.eta
+    gcsr.free()
+
+
+def test_cg(ib, ctx):
+    inst = W.gmm_points(500, 13, m=380)
+    r, s, k, gamma = outer_state(inst, 3)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k)
+    gn = np.linalg.norm(ev.g)
+    rho = inst.eta * gn / (380 * 500)
+    pr = problem(ib, inst)
+    ctr = ib.Center(k, dev(r), dev(s))
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k)
+    shift = max(gn, 1e-2)
+    tol = 1e-12 * gn
+    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
+    xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
+    assert itg < 500 and ito < 500
+    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    assert abs(host(xg).sum()) <= 1e-10 * np.abs(xo).max()   # Lemma 4.1
+    # maxit is respected and 0 iterations returns x = 0
+    x0, it0 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 0)
+    assert it0 == 0 and float(x0.abs().max()) == 0.0
+    gcsr.free()
+
+
+# ---------------------------------------------------------------------------
+# stop test and certificate (rows a7, a10)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [0, 8])
+def test_stop(ib, ctx, k):
+    inst = W.gmm_points(333, 6, m=250)
+    r, s, kk, gamma = outer_state(inst, k)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk)
+    pr = problem(ib, inst)
+    ctr = ib.Center(kk, dev(r), dev(s))
+    gs = ib.stop(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), want_xhat=True)
+    os_ = orc.stop_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, ev.S, s=s, k=kk,
+                        want_xhat=True)
+    np.testing.assert_allclose(host(gs["xhat"]), os_["xhat"], rtol=1e-10, atol=1e-15)
+    for key, rtol, atol in [("primal", 1e-12, 0), ("dual", 1e-12, 1e-16), ("cx", 1e-12, 0),
+                            ("dual_gamma", 1e-12, 1e-16), ("dual_psi", 1e-12, 1e-16),
+                            ("dphi", 1e-9, 1e-15), ("kkt", 1e-9, 1e-16), ("er1", 1e-6, 1e-16)]:
+        assert abs(gs[key] - os_[key]) <= rtol * abs(os_[key]) + atol, (key, gs[key], os_[key])
+    Xh = host(gs["xhat"])
+    assert Xh.min() >= 0
+    np.testing.assert_allclose(Xh.sum(1), inst.a, atol=1e-15 * 333, rtol=0)
+    np.testing.assert_allclose(Xh.sum(0), inst.b, atol=1e-15 * 333, rtol=0)
+
+
+# ---------------------------------------------------------------------------
+# full solve (Algorithm 2) against exact optima and the oracle
+# ---------------------------------------------------------------------------
+def test_solve_n64_exact(ib, ctx):
+    from scipy.optimize import linear_sum_assignment
+    inst = W.uniform_points(64, 0)
+    rr, cc = linear_sum_assignment(inst.C)
+    fstar = inst.C[rr, cc].sum() / 64
+    pr = problem(ib, inst)
+    opt = ib.default_options(max_outer=20000, gap_tol=1e-8, marg_tol=0.0)
+    res = ib.solve(ctx, pr, opt, want_plan=True)
+    rep = res["report"]
+    assert res["status"] == 0, rep
+    assert rep["rel_gap"] <= 1e-8
+    assert rep["dual"] <= fstar * (1 + 1e-13) and rep["primal"] >= fstar * (1 - 1e-13)
+    assert (rep["primal"] - fstar) / fstar <= 1e-8
+    X = host(res["plan"])
+    np.testing.assert_allclose(X.sum(1), inst.a, atol=1e-15 * 64, rtol=0)
+    np.testing.assert_allclose(X.sum(0), inst.b, atol=1e-15 * 64, rtol=0)
+    assert abs((inst.C * X).sum() - rep["primal"]) <= 1e-15
+    # the oracle, run to the same stop rule, brackets the same optimum
+    o = orc.solve(inst.C, inst.a, inst.b, inst.eta,
+                  options=orc.default_options(max_outer=20000, gap_tol=1e-8, marg_tol=0.0))
+    assert abs(o["report"]["primal"] - rep["primal"]) <= 1e-8 * fstar
+
+
+def test_solve_general_weights_vs_highs(ib, ctx):
+    from scipy.optimize import linprog
+    m, n = 24, 20
+    inst = W.gmm_points(n, 101, m=m)
+    A_eq = np.zeros((m + n, m * n))
+    for i in range(m):
+        A_eq[i, i * n:(i + 1) * n] = 1.0
+    for j in range(n):
+        A_eq[m + j, j::n] = 1.0
+    fstar = linprog(inst.C.ravel(), A_eq=A_eq, b_eq=np.concatenate([inst.a, inst.b]),
+                    bounds=(0, None), method="highs").fun
+    pr = problem(ib, inst)
+    res = ib.solve(ctx, pr, ib.default_options(max_outer=20000, gap_tol=1e-10, marg_tol=0.0))
+    assert res["status"] == 0
+    assert abs(res["report"]["primal"] - fstar) <= 1e-8 * fstar
+
+
+def test_solve_resume_matches(ib, ctx):
+    inst = W.uniform_points(40, 8)
+    pr = problem(ib, inst)
+    full = ib.solve(ctx, pr, ib.default_options(max_outer=9, gap_tol=0.0, marg_tol=0.0))
+    part = ib.solve(ctx, pr, ib.default_options(max_outer=4, gap_tol=0.0, marg_tol=0.0))
+    rest = ib.solve(ctx, pr, ib.default_options(max_outer=5, gap_tol=0.0, marg_tol=0.0),
+                    gamma0=part["gamma"], state=(part["r"], part["s"], part["k"]))
+    assert rest["k"] == full["k"] == 9
+    assert torch.equal(rest["gamma"], full["gamma"])
+    assert torch.equal(rest["s"], full["s"])
+
+
+def test_solve_constant_cost(ib, ctx):
+    m, n = 9, 11
+    rng = np.random.default_rng(0)
+    a = rng.uniform(0.1, 1, m); a /= a.sum()
+    b = rng.uniform(0.1, 1, n); b /= b.sum()
+    inst = W.Instance(np.full((m, n), 0.5), a, b, 0.01, "const")
+    res = ib.solve(ctx, problem(ib, inst), want_plan=True)
+    assert res["status"] == 0 and res["report"]["outer"] == 1
+    np.testing.assert_allclose(host(res["plan"]), np.outer(a, b), rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# error behaviour of the ABI
+# ---------------------------------------------------------------------------
+def test_invalid_arguments(ib, ctx):
+    inst = W.uniform_points(16, 0)
+    pr = problem(ib, inst)
+    ctr = ib.Center.initial(pr)
+    g = torch.zeros(16, dtype=torch.float64, device="cuda")
+    bad = ib.Problem(pr.C, pr.a, pr.b, -1.0)
+    with pytest.raises(ib.IBSNError) as e:
+        ib.subproblem_eval(ctx, bad, ctr, g)
+    assert e.value.code == -1
+    with pytest.raises(ib.IBSNError) as e:   # marginals that do not sum to 1
+        ib.solve(ctx, ib.Problem(pr.C, pr.a * 2, pr.b, 0.01))
+    assert e.value.code == -1
+    big = torch.zeros((2, 20481), dtype=torch.float64, device="cuda")
+    with pytest.raises(ib.IBSNError) as e:
+        ib.subproblem_eval(ctx, ib.Problem(big, pr.a[:2] * 8, torch.full((20481,), 1 / 20481,
+                                                                            dtype=torch.float64,
+                                                                            device="cuda"), 0.01),
+                           ib.Center(0, None, torch.zeros(20481, dtype=torch.float64,
+                                                          device="cuda")),
+                           torch.zeros(20481, dtype=torch.float64, device="cuda"), want_obj=False)
+    assert e.value.code == -5
+    with pytest.raises(ValueError):   # host tensor rejected by the binding
+        ib.subproblem_eval(ctx, pr, ctr, torch.zeros(16, dtype=torch.float64))
