@@ -58,6 +58,7 @@ class Options(ct.Structure):
         ("gap_tol", ct.c_double), ("marg_tol", ct.c_double), ("kkt_tol", ct.c_double),
         ("max_outer", ct.c_int), ("max_newton", ct.c_int), ("max_backtrack", ct.c_int),
         ("cg_maxit", ct.c_int), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int),
+        ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int),
     ]
 
 
@@ -75,32 +76,36 @@ class Report(ct.Structure):
 
 
 def _declare(L):
+    i64, dbl, vp, i32 = ct.c_int64, ct.c_double, ct.c_void_p, ct.c_int
+    L.orc_quantum.restype = dbl
+    L.orc_quantum.argtypes = [dbl]
+    L.orc_cost_max.restype = dbl
+    L.orc_cost_max.argtypes = [i64, i64, vp, i32, i64]
+    L.orc_center_quantum.restype = dbl
+    L.orc_center_quantum.argtypes = [i64, _dp, _dp, dbl, i64, dbl]
+    L.orc_make_w.restype = None
+    L.orc_make_w.argtypes = [i64, _dp, _dp, dbl, dbl, _dp]
     L.orc_eval.restype = ct.c_int
-    L.orc_eval.argtypes = [ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int64,
-                           ct.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_eval.argtypes = [i64, i64, vp, i32, i64, i64, dbl, dbl, _dp, _dp, _dp, _dp, _dp, _dp,
+                           _dp, _dp, _dp, _dp, _dp]
     L.orc_trial.restype = ct.c_int
-    L.orc_trial.argtypes = [ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int64,
-                            ct.c_double, _dp, _dp, _dp, _dp, _dp, _dp, ct.c_double, _dp, _dp, _dp,
-                            _dp, _dp]
+    L.orc_trial.argtypes = [i64, i64, vp, i32, i64, i64, dbl, dbl, _dp, _dp, _dp, _dp, _dp, dbl,
+                            _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_sparsify.restype = ct.c_int64
-    L.orc_sparsify.argtypes = [ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_int, ct.c_int64,
-                               ct.c_int64, ct.c_double, _dp, _dp, _dp, _dp, _dp, ct.c_double,
-                               ct.c_int64, ct.c_int64, _i64p, _i32p, _dp, _dp]
+    L.orc_sparsify.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, dbl, i64,
+                               i64, _i64p, _i32p, _dp, _dp]
     L.orc_hvp.restype = None
-    L.orc_hvp.argtypes = [ct.c_int64, ct.c_int64, _i64p, _i32p, _dp, _dp, _dp, ct.c_double,
-                          ct.c_double, _dp, _dp]
+    L.orc_hvp.argtypes = [i64, i64, _i64p, _i32p, _dp, _dp, _dp, dbl, dbl, _dp, _dp]
     L.orc_cg.restype = ct.c_int
-    L.orc_cg.argtypes = [ct.c_int64, ct.c_int64, _i64p, _i32p, _dp, _dp, _dp, ct.c_double,
-                         ct.c_double, _dp, ct.c_double, ct.c_int, _dp]
+    L.orc_cg.argtypes = [i64, i64, _i64p, _i32p, _dp, _dp, _dp, dbl, dbl, _dp, dbl, i32, _dp]
     L.orc_stop.restype = ct.c_int
-    L.orc_stop.argtypes = [ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int64,
-                           ct.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_stop.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                           _dp]
     L.orc_default_options.restype = None
     L.orc_default_options.argtypes = [ct.POINTER(Options)]
     L.orc_solve.restype = ct.c_int
-    L.orc_solve.argtypes = [ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_int, ct.c_int64, _dp, _dp,
-                            ct.c_double, ct.POINTER(Options), _dp, _dp, _dp, _i64p, _dp,
-                            ct.POINTER(Report), _dp, ct.c_int64]
+    L.orc_solve.argtypes = [i64, i64, vp, i32, i64, _dp, _dp, dbl, ct.POINTER(Options), _dp, _dp,
+                            _dp, _i64p, _dp, ct.POINTER(Report), _dp, i64]
 
 
 def _p(x):
@@ -137,6 +142,8 @@ class EvalResult:
     g: np.ndarray
     L: float
     plan: np.ndarray | None
+    q: float
+    w: np.ndarray
 
     @property
     def lse(self):
@@ -148,32 +155,58 @@ def default_state(a, b):
     return np.log(_f64(a)), np.log(_f64(b)), 0
 
 
-def eval_pass(C, a, b, eta, gamma, r=None, s=None, k=0, want_plan=False) -> EvalResult:
+def cost_max(C):
+    C, kind = _cost(C)
+    return lib().orc_cost_max(C.shape[0], C.shape[1], C.ctypes.data, kind, C.shape[1])
+
+
+def center_quantum(C, s, gamma, eta, k):
+    """Grid spacing of an outer iteration (bound max|s + gamma/eta| + sigma max|C|)."""
+    s, gamma = _f64(s), _f64(gamma)
+    return lib().orc_center_quantum(len(s), _p(s), _p(gamma), float(eta), int(k), cost_max(C))
+
+
+def make_w(s, gamma, eta, q):
+    s, gamma = _f64(s), _f64(gamma)
+    w = np.empty(len(s))
+    lib().orc_make_w(len(s), _p(s), _p(gamma), float(eta), float(q), _p(w))
+    return w
+
+
+def _wq(C, b, eta, gamma, s, k, q):
+    s = np.log(_f64(b)) if s is None else _f64(s)
+    gamma = _f64(gamma)
+    if q is None:
+        q = center_quantum(C, s, gamma, eta, k)
+    return s, make_w(s, gamma, eta, q), q
+
+
+def eval_pass(C, a, b, eta, gamma, r=None, s=None, k=0, want_plan=False, q=None) -> EvalResult:
     C, kind = _cost(C)
     m, n = C.shape
     a, b, gamma = _f64(a), _f64(b), _f64(gamma)
     r = np.log(a) if r is None else _f64(r)
-    s = np.log(b) if s is None else _f64(s)
+    s, w, q = _wq(C, b, eta, gamma, s, k, q)
     M, S, c, g = np.empty(m), np.empty(m), np.empty(n), np.empty(n)
     L = ct.c_double()
     plan = np.empty((m, n)) if want_plan else None
-    rc = lib().orc_eval(m, n, C.ctypes.data, kind, n, k, eta, _p(r), _p(s), _p(gamma), _p(a),
+    rc = lib().orc_eval(m, n, C.ctypes.data, kind, n, k, eta, q, _p(w), _p(r), _p(gamma), _p(a),
                         _p(b), _p(M), _p(S), _p(c), _p(g), ct.byref(L), _p(plan))
     assert rc == 0, rc
-    return EvalResult(M, S, c, g, L.value, plan)
+    return EvalResult(M, S, c, g, L.value, plan, q, w)
 
 
-def trial_pass(C, a, b, eta, gamma, M, Delta, t, s=None, k=0):
-    """Armijo trial at gamma + t*Delta from the row state M of the current point.
+def trial_pass(C, a, b, eta, gamma, M, Delta, t, s=None, k=0, q=None):
+    """Armijo trial at the grid point w + grid(t*Delta/eta) from the row state M of w.
     Returns (dL, M_new, S_new, c_new, g_new)."""
     C, kind = _cost(C)
     m, n = C.shape
-    a, b, gamma, M, Delta = map(_f64, (a, b, gamma, M, Delta))
-    s = np.log(b) if s is None else _f64(s)
+    a, b, M, Delta = map(_f64, (a, b, M, Delta))
+    s, w, q = _wq(C, b, eta, gamma, s, k, q)
     Mn, Sn, cn, gn = np.empty(m), np.empty(m), np.empty(n), np.empty(n)
     dL = ct.c_double()
-    rc = lib().orc_trial(m, n, C.ctypes.data, kind, n, k, eta, _p(s), _p(gamma), _p(a), _p(b),
-                         _p(M), _p(Delta), float(t), ct.byref(dL), _p(Mn), _p(Sn), _p(cn), _p(gn))
+    rc = lib().orc_trial(m, n, C.ctypes.data, kind, n, k, eta, q, _p(w), _p(a), _p(b), _p(M),
+                         _p(Delta), float(t), ct.byref(dL), None, _p(Mn), _p(Sn), _p(cn), _p(gn))
     assert rc == 0, rc
     return dL.value, Mn, Sn, cn, gn
 
@@ -205,22 +238,26 @@ def istar_of(a):
     return int(np.argmax(np.asarray(a)))
 
 
-def sparsify(C, a, eta, gamma, M, S, rho, s, k=0, istar=None) -> CSR:
+def sparsify(C, a, eta, gamma, M, S, rho, s, k=0, istar=None, q=None) -> CSR:
     """Algorithm 1 from the row state (M, S) at (s, gamma, k)."""
     C, kind = _cost(C)
     m, n = C.shape
-    a, gamma, M, S, s = map(_f64, (a, gamma, M, S, s))
+    a, M, S = map(_f64, (a, M, S))
+    s = _f64(s)
+    gamma = _f64(gamma)
+    if q is None:
+        q = center_quantum(C, s, gamma, eta, k)
+    w = make_w(s, gamma, eta, q)
     istar = istar_of(a) if istar is None else int(istar)
     row_ptr = np.empty(m + 1, dtype=np.int64)
-    need = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(s), _p(gamma), _p(a),
-                              _p(M), _p(S), float(rho), istar, 0, _p(row_ptr), None, None, None)
+    need = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(a), _p(M), _p(S),
+                              float(rho), istar, 0, _p(row_ptr), None, None, None)
     nnz = -need - 1
     col = np.empty(max(nnz, 1), dtype=np.int32)
     val = np.empty(max(nnz, 1))
     d = np.empty(n)
-    got = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(s), _p(gamma), _p(a),
-                             _p(M), _p(S), float(rho), istar, nnz, _p(row_ptr), _p(col), _p(val),
-                             _p(d))
+    got = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(a), _p(M), _p(S),
+                             float(rho), istar, nnz, _p(row_ptr), _p(col), _p(val), _p(d))
     assert got == nnz
     return CSR(m, n, row_ptr, col[:nnz], val[:nnz], d, istar)
 
@@ -246,14 +283,16 @@ STOP_FIELDS = ("dphi", "primal", "dual", "cx", "kkt", "xhat_min", "er1", "xu", "
                "dual_psi")
 
 
-def stop_pass(C, a, b, eta, gamma, M, S, s=None, k=0, want_xhat=False):
+def stop_pass(C, a, b, eta, gamma, M, S, s=None, k=0, want_xhat=False, q=None):
+    """Rounding, D_phi and certificate for the plan of the row state (M, S) at w.
+    The certificate's dual is gamma as given."""
     C, kind = _cost(C)
     m, n = C.shape
     a, b, gamma, M, S = map(_f64, (a, b, gamma, M, S))
-    s = np.log(b) if s is None else _f64(s)
+    s, w, q = _wq(C, b, eta, gamma, s, k, q)
     out = np.empty(10)
     xhat = np.empty((m, n)) if want_xhat else None
-    rc = lib().orc_stop(m, n, C.ctypes.data, kind, n, k, eta, _p(s), _p(gamma), _p(a), _p(b),
+    rc = lib().orc_stop(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(gamma), _p(a), _p(b),
                         _p(M), _p(S), _p(out), _p(xhat))
     assert rc == 0
     res = dict(zip(STOP_FIELDS, out.tolist()))

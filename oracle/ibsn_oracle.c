@@ -15,28 +15,38 @@
  * X^{k+1} = diag(a) P^k(gamma) (eq. (7)) give, for every k,
  *     log X^k_ij = r_i + s_j - k*C_ij/eta,
  * with r = log a, s = log b at k = 0 and r <- log a - lse(gamma), s <- s + gamma/eta
- * at each outer update.  The row constant r_i cancels in P (eq. (7)), so every dense
- * pass works on
- *     theta_ij = fma(-sigma, C_ij, w_j),   sigma = (k+1)/eta,   w_j = s_j + gamma_j/eta,
- * and the row log-normaliser of the subproblem is r_i + lse_i with lse_i = LSE_j theta_ij.
+ * at each outer update.  The row constant r_i cancels in P (eq. (7)), so the plan of
+ * the subproblem at gamma is a row softmax of
+ *     theta_ij = w_j - sigma*C_ij,   sigma = (k+1)/eta,   w_j = s_j + gamma_j/eta,
+ * and the row log-normaliser of eq. (5) is r_i + lse_i with lse_i = LSE_j theta_ij.
  *
- * Row state.  A "row state" (M_i, S_i) represents P_ij = exp(theta_ij - M_i) / S_i.
- * A fresh evaluation sets M_i = max_j theta_ij and S_i = sum_j exp(theta_ij - M_i), so
- * P is eq. (7) written with the usual max shift (the common factor exp(-M_i) cancels).
- * Keeping M_i (an exact copy of one theta value) and S_i (an O(1..n) number) apart,
- * instead of their sum lse_i, keeps theta_ij - M_i exact for the entries that matter
- * even when sigma*C is large.
+ * Exact exponents.  w_j and theta_ij grow like sigma, but P only needs the small
+ * differences theta_ij - (row shift).  Both the column potentials w_j and the row
+ * shifts M_i are kept on a grid of spacing q (a power of two, 2^(e-50) for a bound
+ * 2^(e-1) <= |w|, |theta| < 2^e), so w_j - M_i is an exact double and
+ *     x_ij = fma(-sigma, C_ij, w_j - M_i) = theta_ij - M_i
+ * carries one rounding at the scale of x_ij itself (|x| <= ~40 for every entry that
+ * matters) instead of one at the scale of sigma.  Rounding a value v to the grid is
+ * grid(v) = q * rint(v / q) (exact operations for a power-of-two q).
  *
- * Conventions fixed where the paper is silent (each one is listed with its reason in
- * the design notes of the repository):
+ * Row state.  A pair (M_i, S_i), M_i on the grid, represents
+ *     P_ij = exp(x_ij) / S_i,   x_ij = fma(-sigma, C_ij, w_j - M_i),
+ * which is eq. (7) with the common factor exp(-M_i) cancelled.  A fresh evaluation
+ * sets M_i = grid(max_j theta_ij) and S_i = sum_j exp(x_ij).
+ *
+ * Conventions fixed where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
  *  - i* = lowest index among the maxima of a (Algorithm 1 input).
  *  - threshold test P_ij >= rho is inclusive (Algorithm 1, step 3).
  *  - norms of g in rho and in the shift are Euclidean (notation paragraph).
- *  - CG starts from 0 and stops when ||r|| <= min(0.1, ||g||)*||g|| or at cg_maxit.
- *  - Armijo decrease L(gamma+t*Delta)-L(gamma) is evaluated in difference form,
- *    see orc_trial().
+ *  - CG starts from 0 and stops when ||r|| <= max(min(0.1, ||g||), cg_rtol_min)*||g||
+ *    or at cg_maxit.
+ *  - Armijo decrease L(gamma+t*Delta)-L(gamma) is evaluated in difference form on the
+ *    grid-rounded step, see orc_trial(); only a finite decrease is accepted.
  *  - Sinkhorn warm-up re-centres gamma after every gamma-step (centering does not
  *    change P, g or the Newton iterates: L(gamma + c1) = L(gamma) since 1^T b = 1 = 1^T a).
+ *  - the inner loop also ends when the gradient gate has passed but the D_phi test has
+ *    failed stall_limit times in the same outer iteration (the test has a rounding floor).
  *  - Column sums are accumulated over 64 fixed row chunks, in chunk order, so results
  *    do not depend on the number of OpenMP threads.
  *
@@ -53,7 +63,6 @@
 #define ORC_OK 0
 #define ORC_WARN_MAXITER 1
 #define ORC_ERR_ARG (-1)
-#define ORC_ERR_CAP (-2)
 #define ORC_ERR_NUMERIC (-4)
 
 /* cost element: kind 0 = float64, kind 1 = float32 (widened exactly to double) */
@@ -64,17 +73,14 @@ static inline double cost_at(const void *C, int kind, int64_t ldc, int64_t i, in
     return ((const double *)C)[i * ldc + j];
 }
 
-static inline double theta_at(const void *C, int kind, int64_t ldc, int64_t i, int64_t j,
-                              double sigma, const double *w)
-{
-    return fma(-sigma, cost_at(C, kind, ldc, i, j), w[j]);
-}
+/* round v to the grid of spacing q (q a power of two) */
+static inline double grid(double v, double q) { return q * rint(v / q); }
 
-/* w_j = s_j + gamma_j / eta */
-static void make_w(int64_t n, const double *s, const double *gamma, double eta, double *w)
+/* x_ij = theta_ij - M_i with w_j - M_i exact */
+static inline double xval(const void *C, int kind, int64_t ldc, int64_t i, int64_t j,
+                          double sigma, const double *w, double Mi)
 {
-    for (int64_t j = 0; j < n; ++j)
-        w[j] = s[j] + gamma[j] / eta;
+    return fma(-sigma, cost_at(C, kind, ldc, i, j), w[j] - Mi);
 }
 
 static double dot(int64_t n, const double *x, const double *y)
@@ -87,34 +93,75 @@ static double dot(int64_t n, const double *x, const double *y)
 
 static double nrm2(int64_t n, const double *x) { return sqrt(dot(n, x, x)); }
 
+/* grid spacing for values bounded by B: 2^(e-50) with 2^(e-1) <= B < 2^e; values up to
+   2^(e+1) in magnitude are then multiples of q and differences of two of them are exact */
+double orc_quantum(double B)
+{
+    if (!(B >= 1.0))
+        B = 1.0;
+    return ldexp(1.0, ilogb(B) + 1 - 50);
+}
+
+double orc_cost_max(int64_t m, int64_t n, const void *C, int kind, int64_t ldc)
+{
+    double mx = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double c = fabs(cost_at(C, kind, ldc, i, j));
+            if (c > mx)
+                mx = c;
+        }
+    return mx;
+}
+
+/* quantum of an outer iteration: bound max_j |s_j + gamma_j/eta| + sigma * max|C| */
+double orc_center_quantum(int64_t n, const double *s, const double *gamma, double eta,
+                          int64_t k, double cmax)
+{
+    double mw = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double v = fabs(s[j] + gamma[j] / eta);
+        if (v > mw)
+            mw = v;
+    }
+    return orc_quantum(mw + ((double)(k + 1) / eta) * cmax);
+}
+
+/* w_j = grid(s_j + gamma_j / eta) */
+void orc_make_w(int64_t n, const double *s, const double *gamma, double eta, double q, double *w)
+{
+    for (int64_t j = 0; j < n; ++j)
+        w[j] = grid(s[j] + gamma[j] / eta, q);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Eval pass: eq. (5) (best zeta as a row LSE), eq. (6) (objective), eq. (7) (P)  */
-/* and eq. (8) (gradient g = P^T a - b).                                          */
+/* and eq. (8) (gradient g = P^T a - b), at the grid potentials w.                 */
+/* The objective uses the gamma given (gamma = eta (w - s) up to the grid).         */
 /* ------------------------------------------------------------------------- */
 int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-             const double *r, const double *s, const double *gamma, const double *a,
+             double q, const double *w, const double *r, const double *gamma, const double *a,
              const double *b, double *M, double *S, double *c, double *g, double *L,
              double *plan /* m*n (row-major) or NULL */)
 {
-    if (m < 1 || n < 1 || !(eta > 0))
+    if (m < 1 || n < 1 || !(eta > 0) || !(q > 0))
         return ORC_ERR_ARG;
     const double sigma = (double)(k + 1) / eta;
-    double *w = malloc(sizeof(double) * n);
-    make_w(n, s, gamma, eta, w);
 
-    /* row max and row sum of exp(theta - max) */
+    /* row shift (grid-rounded maximum) and row sum of exp(theta - shift) */
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
         double mx = -INFINITY;
         for (int64_t j = 0; j < n; ++j) {
-            double th = theta_at(C, kind, ldc, i, j, sigma, w);
+            double th = fma(-sigma, cost_at(C, kind, ldc, i, j), w[j]);
             if (th > mx)
                 mx = th;
         }
+        double Mi = grid(mx, q);
         double sum = 0.0;
         for (int64_t j = 0; j < n; ++j)
-            sum += exp(theta_at(C, kind, ldc, i, j, sigma, w) - mx);
-        M[i] = mx;
+            sum += exp(xval(C, kind, ldc, i, j, sigma, w, Mi));
+        M[i] = Mi;
         S[i] = sum;
     }
 
@@ -126,7 +173,7 @@ int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
         double *pc = part + (size_t)q * n;
         for (int64_t i = i0; i < i1; ++i)
             for (int64_t j = 0; j < n; ++j) {
-                double p = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]) / S[i];
+                double p = exp(xval(C, kind, ldc, i, j, sigma, w, M[i])) / S[i];
                 pc[j] += a[i] * p;
                 if (plan)
                     plan[i * n + j] = a[i] * p;
@@ -142,92 +189,103 @@ int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     free(part);
 
     /* L = -b^T gamma + eta * sum_i a_i (r_i + M_i + log S_i) */
-    if (L) {
+    if (L && r && gamma) {
         double t = 0.0;
         for (int64_t i = 0; i < m; ++i)
             t += a[i] * (r[i] + M[i] + log(S[i]));
         *L = -dot(n, b, gamma) + eta * t;
     }
-    free(w);
     return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------- */
-/* Armijo trial pass (Algorithm 2, step 9).                                        */
-/* Exact algebra for the change of the objective along gamma + t*Delta:            */
-/*   L(gamma+t Delta) - L(gamma) = -t b^T Delta + eta * sum_i a_i delta_i,         */
-/*   delta_i = log( sum_j q_ij e^{tau_j} / sum_j q_ij ),  q_ij = exp(theta_ij-M_i),  */
-/*   tau_j = t*Delta_j/eta.                                                          */
-/* delta_i = log1p(sum_j q_ij expm1(tau_j) / sum_j q_ij) keeps full relative        */
-/* precision when t*Delta is tiny (near convergence), where a difference of two      */
-/* separately rounded objective values would be pure rounding noise.                 */
-/* The trial's plan is P'_ij = q_ij e^{tau_j} / sum_l q_il e^{tau_l} (eq. (7) at the */
-/* new point, written relative to the current one); its column sums give c', g'.     */
-/* The new row state is M'_i = M_i + tau_max + log max_j(q_ij E_j),                  */
-/* S'_i = sum_j q_ij E_j / max_j(q_ij E_j), with E_j = exp(tau_j - tau_max).         */
+/* Armijo trial (Algorithm 2, step 9) from the row state M of the point w.          */
+/* The step is taken on the grid: tau_j = grid(t * Delta_j / eta), so the trial     */
+/* point is w + tau exactly.  Exact algebra for the change of the objective:        */
+/*   L(w + tau) - L(w) = -eta * b^T tau + eta * sum_i a_i delta_i,                  */
+/*   delta_i = log( sum_j q_ij e^{tau_j} / sum_j q_ij ),  q_ij = exp(x_ij).           */
+/* Small steps (max tau <= 500): delta_i = log1p(B_i / A_i) with A_i = sum_j q_ij,  */
+/* B_i = sum_j q_ij expm1(tau_j), which keeps full relative precision when tau is   */
+/* tiny; otherwise delta_i = tau_max + log(Z_i / A_i) with the shifted factors      */
+/* exp(tau_j - tau_max).  The trial plan is P'_ij = qe_ij / Z_i with                */
+/* qe_ij = q_ij e^{tau_j - shift}, Z_i = sum_j qe_ij; its column sums give c', g'.  */
+/* New row state: M'_i = grid(M_i + shift + log max_j qe_ij) and                     */
+/* S'_i = Z_i exp((M_i - M'_i) + shift), so exp(x'_ij)/S'_i = P'_ij for the fresh    */
+/* x' of the point w + tau.  A row whose factors all underflow gives delta = +inf.  */
 /* ------------------------------------------------------------------------- */
 int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-              const double *s, const double *gamma, const double *a, const double *b,
-              const double *M, const double *Delta, double t, double *dL /* out */,
+              double q, const double *w, const double *a, const double *b, const double *M,
+              const double *Delta, double t, double *dL /* out */, double *tau_out /* n or NULL */,
               double *M_new, double *S_new, double *c_new, double *g_new)
 {
-    if (m < 1 || n < 1 || !(eta > 0))
+    if (m < 1 || n < 1 || !(eta > 0) || !(q > 0))
         return ORC_ERR_ARG;
     const double sigma = (double)(k + 1) / eta;
-    double *w = malloc(sizeof(double) * n);
     double *tau = malloc(sizeof(double) * n);
-    double *E = malloc(sizeof(double) * n);
-    double *F = malloc(sizeof(double) * n);
+    double *cv = malloc(sizeof(double) * n);
     double *delta = malloc(sizeof(double) * m);
     double *Z = malloc(sizeof(double) * m);
-    double *mx = malloc(sizeof(double) * m);
-    make_w(n, s, gamma, eta, w);
     double tau_max = -INFINITY;
     for (int64_t j = 0; j < n; ++j) {
-        tau[j] = t * Delta[j] / eta;
+        tau[j] = grid(t * Delta[j] / eta, q);
         if (tau[j] > tau_max)
             tau_max = tau[j];
     }
     const int small_step = tau_max <= 500.0;
-    for (int64_t j = 0; j < n; ++j) {
-        E[j] = exp(tau[j] - tau_max);
-        F[j] = small_step ? expm1(tau[j]) : 0.0;
-    }
+    const double shift = small_step ? 0.0 : tau_max;
+    for (int64_t j = 0; j < n; ++j)
+        cv[j] = small_step ? expm1(tau[j]) : exp(tau[j] - tau_max);
 
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
         double A = 0.0, B = 0.0, Zi = 0.0, qmax = 0.0;
         for (int64_t j = 0; j < n; ++j) {
-            double q = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]);
-            A += q;
-            B += q * F[j];
-            double qe = q * E[j];
+            double qv = exp(xval(C, kind, ldc, i, j, sigma, w, M[i]));
+            A += qv;
+            double qe;
+            if (small_step) {
+                double qf = qv * cv[j];
+                B += qf;
+                qe = qv + qf;
+            } else {
+                qe = qv * cv[j];
+            }
             Zi += qe;
             if (qe > qmax)
                 qmax = qe;
         }
-        /* a step that pushes every entry of a row below the FP64 range leaves no
-           usable plan: mark the trial as not a decrease */
-        delta[i] = !(Zi > 0.0) ? INFINITY : (small_step ? log1p(B / A) : tau_max + log(Zi / A));
+        if (!(Zi > 0.0)) {
+            delta[i] = INFINITY;
+            M_new[i] = M[i];
+            S_new[i] = NAN;
+        } else {
+            delta[i] = small_step ? log1p(B / A) : shift + log(Zi / A);
+            double Mn = grid(M[i] + (shift + log(qmax)), q);
+            M_new[i] = Mn;
+            S_new[i] = Zi * exp((M[i] - Mn) + shift);
+        }
         Z[i] = Zi;
-        mx[i] = qmax;
     }
 
     double *part = calloc((size_t)ORC_NCHUNK * n, sizeof(double));
 #pragma omp parallel for schedule(static)
-    for (int q = 0; q < ORC_NCHUNK; ++q) {
-        int64_t i0 = m * q / ORC_NCHUNK, i1 = m * (q + 1) / ORC_NCHUNK;
-        double *pc = part + (size_t)q * n;
-        for (int64_t i = i0; i < i1; ++i)
+    for (int qq = 0; qq < ORC_NCHUNK; ++qq) {
+        int64_t i0 = m * qq / ORC_NCHUNK, i1 = m * (qq + 1) / ORC_NCHUNK;
+        double *pc = part + (size_t)qq * n;
+        for (int64_t i = i0; i < i1; ++i) {
+            if (!(Z[i] > 0.0))
+                continue;
             for (int64_t j = 0; j < n; ++j) {
-                double qv = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]);
-                pc[j] += a[i] * (qv * E[j] / Z[i]);
+                double qv = exp(xval(C, kind, ldc, i, j, sigma, w, M[i]));
+                double qe = small_step ? qv + qv * cv[j] : qv * cv[j];
+                pc[j] += a[i] * (qe / Z[i]);
             }
+        }
     }
     for (int64_t j = 0; j < n; ++j) {
         double acc = 0.0;
-        for (int q = 0; q < ORC_NCHUNK; ++q)
-            acc += part[(size_t)q * n + j];
+        for (int qq = 0; qq < ORC_NCHUNK; ++qq)
+            acc += part[(size_t)qq * n + j];
         c_new[j] = acc;
         g_new[j] = acc - b[j];
     }
@@ -236,17 +294,15 @@ int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_
     double sd = 0.0;
     for (int64_t i = 0; i < m; ++i)
         sd += a[i] * delta[i];
-    *dL = -t * dot(n, b, Delta) + eta * sd;
-    for (int64_t i = 0; i < m; ++i) {
-        M_new[i] = M[i] + (tau_max + log(mx[i]));
-        S_new[i] = Z[i] / mx[i];
-    }
-    free(w); free(tau); free(E); free(F); free(delta); free(Z); free(mx);
+    *dL = -eta * dot(n, b, tau) + eta * sd;
+    if (tau_out)
+        memcpy(tau_out, tau, sizeof(double) * n);
+    free(tau); free(cv); free(delta); free(Z);
     return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------- */
-/* Algorithm 1: Hessian sparsification.  P_ij = exp(theta_ij - M_i)/S_i.           */
+/* Algorithm 1: Hessian sparsification.  P_ij = exp(x_ij)/S_i.                      */
 /* For i != i*: keep P_ij >= rho and divide the kept entries by their sum.          */
 /* Row i* is copied whole.  Output CSR (row_ptr[m+1], col[nnz], val[nnz]) in row    */
 /* order, columns ascending, and d = P_rho^T a.                                     */
@@ -254,13 +310,11 @@ int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_
 /* except row_ptr).  A row whose entries all fall below rho is left empty.          */
 /* ------------------------------------------------------------------------- */
 int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
-                     double eta, const double *s, const double *gamma, const double *a,
-                     const double *M, const double *S, double rho, int64_t istar, int64_t cap,
-                     int64_t *row_ptr, int32_t *col, double *val, double *d)
+                     double eta, const double *w, const double *a, const double *M,
+                     const double *S, double rho, int64_t istar, int64_t cap, int64_t *row_ptr,
+                     int32_t *col, double *val, double *d)
 {
     const double sigma = (double)(k + 1) / eta;
-    double *w = malloc(sizeof(double) * n);
-    make_w(n, s, gamma, eta, w);
     int64_t *cnt = malloc(sizeof(int64_t) * m);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
@@ -270,7 +324,7 @@ int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
         }
         int64_t c = 0;
         for (int64_t j = 0; j < n; ++j) {
-            double p = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]) / S[i];
+            double p = exp(xval(C, kind, ldc, i, j, sigma, w, M[i])) / S[i];
             if (p >= rho)
                 ++c;
         }
@@ -281,16 +335,14 @@ int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
         row_ptr[i + 1] = row_ptr[i] + cnt[i];
     int64_t nnz = row_ptr[m];
     free(cnt);
-    if (nnz > cap) {
-        free(w);
+    if (nnz > cap)
         return -nnz - 1;
-    }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
         int64_t o = row_ptr[i];
         double kappa = 0.0;
         for (int64_t j = 0; j < n; ++j) {
-            double p = exp(theta_at(C, kind, ldc, i, j, sigma, w) - M[i]) / S[i];
+            double p = exp(xval(C, kind, ldc, i, j, sigma, w, M[i])) / S[i];
             if (i == istar || p >= rho) {
                 col[o] = (int32_t)j;
                 val[o] = p;
@@ -308,7 +360,6 @@ int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
     for (int64_t i = 0; i < m; ++i)
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
             d[col[e]] += a[i] * val[e];
-    free(w);
     return nnz;
 }
 
@@ -378,8 +429,8 @@ int orc_cg(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col, con
 /* X_ij = a_i P_ij with P from the row state.  Algorithm 3 (rounding onto Omega,    */
 /* literal: y uses the column sums of X), then                                      */
 /*   D_phi(Xhat, X) = sum Xhat log(Xhat/X) - Xhat + X          (eq. (3)),           */
-/* evaluated with log X_ij = log a_i + theta_ij - M_i - log S_i so that an X that    */
-/* underflows does not make the term infinite; 0 log 0 = 0.                          */
+/* evaluated with log X_ij = log a_i + x_ij - log S_i so that an X that underflows   */
+/* does not make the term infinite; 0 log 0 = 0.                                     */
 /* Certificate: for a dual vector v, zeta_i = min_j (C_ij - v_j) (c-transform,       */
 /* appendix C.1) makes (zeta, v) feasible for the dual LP, so a^T zeta + b^T v is a  */
 /* lower bound on the optimum; <C,Xhat> is an upper bound.  Two vectors are tried:   */
@@ -392,12 +443,10 @@ int orc_cg(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col, con
 /* out[8] = dual bound from gamma, out[9] = dual bound from psi.                      */
 /* ------------------------------------------------------------------------- */
 int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-             const double *s, const double *gamma, const double *a, const double *b,
+             const double *w, const double *gamma, const double *a, const double *b,
              const double *M, const double *S, double *out, double *xhat /* m*n or NULL */)
 {
     const double sigma = (double)(k + 1) / eta;
-    double *w = malloc(sizeof(double) * n);
-    make_w(n, s, gamma, eta, w);
     double *z = malloc(sizeof(double) * m), *er = malloc(sizeof(double) * m);
     double *colX = calloc((size_t)n, sizeof(double)), *colF = calloc((size_t)n, sizeof(double));
     double *y = malloc(sizeof(double) * n), *ec = malloc(sizeof(double) * n);
@@ -409,9 +458,9 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     for (int64_t i = 0; i < m; ++i) {
         double la = log(a[i]), ls = log(S[i]);
         for (int64_t j = 0; j < n; ++j) {
-            double th = theta_at(C, kind, ldc, i, j, sigma, w);
-            X[i * n + j] = a[i] * (exp(th - M[i]) / S[i]);
-            logX[i * n + j] = la + (th - M[i]) - ls;
+            double x = xval(C, kind, ldc, i, j, sigma, w, M[i]);
+            X[i * n + j] = a[i] * (exp(x) / S[i]);
+            logX[i * n + j] = la + x - ls;
         }
     }
     /* Algorithm 3, steps 2-4: z_i = min(a_i / sum_j X_ij, 1) */
@@ -436,11 +485,12 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
             rs += f;
             colF[j] += f;
         }
-        er[i] = a[i] - rs;
-        er1 += fabs(er[i]);
+        /* z <= 1 and y <= 1 make e_r, e_c >= 0 exactly; a negative value is rounding */
+        er[i] = fmax(a[i] - rs, 0.0);
+        er1 += er[i];
     }
     for (int64_t j = 0; j < n; ++j)
-        ec[j] = b[j] - colF[j];
+        ec[j] = fmax(b[j] - colF[j], 0.0);
 
     /* step 11 and the divergence / certificate sums */
     double dphi = 0.0, cxh = 0.0, cx = 0.0, xmin = INFINITY, xu = 0.0;
@@ -519,8 +569,7 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     out[7] = xu;
     out[8] = dual_g;
     out[9] = dual_p;
-    free(w); free(z); free(er); free(colX); free(colF); free(y); free(ec); free(X); free(logX);
-    free(zc);
+    free(z); free(er); free(colX); free(colF); free(y); free(ec); free(X); free(logX); free(zc);
     return ORC_OK;
 }
 
@@ -536,6 +585,8 @@ typedef struct {
     int max_outer, max_newton, max_backtrack, cg_maxit; /* cg_maxit <= 0 -> min(n, 1000) */
     double cg_forcing_max;            /* 0.1 */
     int rho_mode;                     /* 0 paper rule, 1 rho = 0 (no sparsification) */
+    double cg_rtol_min;               /* 1e-6: floor of the CG relative residual */
+    int stall_limit;                  /* 3 failed D_phi tests after the gate end the inner loop */
 } orc_options;
 
 typedef struct {
@@ -561,6 +612,8 @@ void orc_default_options(orc_options *o)
     o->cg_maxit = 0;
     o->cg_forcing_max = 0.1;
     o->rho_mode = 0;
+    o->cg_rtol_min = 1e-6;
+    o->stall_limit = 3;
 }
 
 static double nrm1(int64_t n, const double *x)
@@ -579,6 +632,13 @@ static void center(int64_t n, double *gamma)
     mean /= (double)n;
     for (int64_t j = 0; j < n; ++j)
         gamma[j] -= mean;
+}
+
+/* gamma = eta (w - s) */
+static void gamma_of(int64_t n, const double *w, const double *s, double eta, double *gamma)
+{
+    for (int64_t j = 0; j < n; ++j)
+        gamma[j] = eta * (w[j] - s[j]);
 }
 
 /* gamma_io: in = warm start (or NULL -> 0), out = final dual.
@@ -600,13 +660,14 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
     int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)(n < 1000 ? n : 1000);
 
     double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * n);
-    double *gamma = malloc(sizeof(double) * n);
+    double *gamma = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
     double *M = malloc(sizeof(double) * m), *S = malloc(sizeof(double) * m);
     double *c = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n);
     double *Mt = malloc(sizeof(double) * m), *St = malloc(sizeof(double) * m);
     double *ct = malloc(sizeof(double) * n), *gt = malloc(sizeof(double) * n);
     double *Delta = malloc(sizeof(double) * n), *rhs = malloc(sizeof(double) * n);
-    double *d = malloc(sizeof(double) * n);
+    double *tau = malloc(sizeof(double) * n), *d = malloc(sizeof(double) * n);
+    double *lb = malloc(sizeof(double) * n);
     int64_t *row_ptr = malloc(sizeof(int64_t) * (m + 1));
     int64_t k = 0;
     if (k_io && *k_io > 0 && r_io && s_io) {
@@ -619,8 +680,10 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         for (int64_t j = 0; j < n; ++j)
             s[j] = log(b[j]);
     }
-    for (int64_t j = 0; j < n; ++j)
+    for (int64_t j = 0; j < n; ++j) {
         gamma[j] = gamma_io ? gamma_io[j] : 0.0;
+        lb[j] = log(b[j]);
+    }
     if (k == 0)
         center(n, gamma); /* Lemma 4.1 needs 1^T gamma^{0,0} = 0; a resumed state already has it */
 
@@ -628,40 +691,51 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
     for (int64_t i = 1; i < m; ++i)
         if (a[i] > a[istar])
             istar = i;
+    const double cmax = orc_cost_max(m, n, C, kind, ldc);
 
     orc_report R;
     memset(&R, 0, sizeof(R));
     R.status = ORC_WARN_MAXITER;
     double stop_out[10] = {0};
-    double L;
     int64_t k0 = k;
     for (; k < k0 + opt.max_outer; ++k) {
         double mu = fmax(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
+        const double q = orc_center_quantum(n, s, gamma, eta, k, cmax);
+        orc_make_w(n, s, gamma, eta, q, w);
         /* Algorithm 2, step 3: Sinkhorn warm-up (semi-dual form: the zeta-step is the row
            LSE of the eval pass, the gamma-step rescales the columns to b) */
-        orc_eval(m, n, C, kind, ldc, k, eta, r, s, gamma, a, b, M, S, c, g, &L, NULL);
+        orc_eval(m, n, C, kind, ldc, k, eta, q, w, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
         for (int it = 0; it < opt.sinkhorn_maxit && nrm2(n, g) >= opt.sinkhorn_tol; ++it) {
+            /* gamma_j += eta (log b_j - log c_j), i.e. w_j += log b_j - log c_j on the grid */
             for (int64_t j = 0; j < n; ++j)
-                gamma[j] += eta * (log(b[j]) - log(c[j]));
-            center(n, gamma); /* step 4 */
-            orc_eval(m, n, C, kind, ldc, k, eta, r, s, gamma, a, b, M, S, c, g, &L, NULL);
+                w[j] += grid(lb[j] - log(c[j]), q);
+            /* step 4: centre gamma = eta (w - s) by a grid shift of w (P is unchanged) */
+            gamma_of(n, w, s, eta, gamma);
+            double mean = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                mean += gamma[j];
+            mean /= (double)n;
+            const double sh = grid(mean / eta, q);
+            for (int64_t j = 0; j < n; ++j)
+                w[j] -= sh;
+            orc_eval(m, n, C, kind, ldc, k, eta, q, w, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
             ++R.sinkhorn;
         }
-        int stopped = 0;
+        int stopped = 0, stalls = 0;
         int64_t newton_k = 0, cg_k = 0;
         for (int v = 0; v < opt.max_newton; ++v) {
             double gn = nrm2(n, g);
             double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / ((double)m * (double)n); /* step 6 */
-            int64_t nnz = orc_sparsify(m, n, C, kind, ldc, k, eta, s, gamma, a, M, S, rho, istar,
-                                       0, row_ptr, NULL, NULL, NULL);
+            int64_t nnz = orc_sparsify(m, n, C, kind, ldc, k, eta, w, a, M, S, rho, istar, 0,
+                                       row_ptr, NULL, NULL, NULL);
             nnz = -nnz - 1;
             int32_t *col = malloc(sizeof(int32_t) * (nnz > 0 ? nnz : 1));
             double *val = malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
-            orc_sparsify(m, n, C, kind, ldc, k, eta, s, gamma, a, M, S, rho, istar, nnz, row_ptr,
-                         col, val, d); /* step 7 */
+            orc_sparsify(m, n, C, kind, ldc, k, eta, w, a, M, S, rho, istar, nnz, row_ptr, col,
+                         val, d); /* step 7 */
             for (int64_t j = 0; j < n; ++j)
                 rhs[j] = -g[j];
-            double tol = fmin(opt.cg_forcing_max, gn) * gn;
+            double tol = fmax(fmin(opt.cg_forcing_max, gn), opt.cg_rtol_min) * gn;
             int it = orc_cg(m, n, row_ptr, col, val, d, a, eta, gn, rhs, tol, cg_maxit,
                             Delta); /* step 8 */
             cg_k += it;
@@ -671,8 +745,8 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             double t = 1.0, dL = 0.0;
             int bt = 0, accepted = 0;
             for (;;) { /* step 9: Armijo backtracking on a finite decrease */
-                orc_trial(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, Delta, t, &dL, Mt, St, ct,
-                          gt);
+                orc_trial(m, n, C, kind, ldc, k, eta, q, w, a, b, M, Delta, t, &dL, tau, Mt, St,
+                          ct, gt);
                 if (isfinite(dL) && dL <= opt.sigma_armijo * t * gd) {
                     accepted = 1;
                     break;
@@ -683,28 +757,31 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
                 ++bt;
             }
             R.backtracks += bt;
-            if (!accepted) /* no acceptable step: keep gamma and end the inner loop */
+            if (!accepted) /* no acceptable step: keep the iterate and end the inner loop */
                 break;
-            for (int64_t j = 0; j < n; ++j) /* step 10 */
-                gamma[j] += t * Delta[j];
+            for (int64_t j = 0; j < n; ++j) /* step 10, on the grid: exact */
+                w[j] += tau[j];
             memcpy(M, Mt, sizeof(double) * m);
             memcpy(S, St, sizeof(double) * m);
             memcpy(c, ct, sizeof(double) * n);
             memcpy(g, gt, sizeof(double) * n);
-            L += dL;
             ++newton_k;
             /* step 12 with the practical schedule: gradient gate, then D_phi test */
             if (nrm2(n, g) < mu) {
-                orc_stop(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, S, stop_out, NULL);
+                gamma_of(n, w, s, eta, gamma);
+                orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, NULL);
                 ++R.stop_tests;
                 if (stop_out[0] <= (double)(m < n ? m : n) * mu) {
                     stopped = 1;
                     break;
                 }
+                if (++stalls >= opt.stall_limit)
+                    break;
             }
         }
+        gamma_of(n, w, s, eta, gamma);
         if (!stopped) {
-            orc_stop(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, S, stop_out, NULL);
+            orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, NULL);
             ++R.stop_tests;
         }
         R.newton += newton_k;
@@ -731,12 +808,12 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         int done = (relgap <= opt.gap_tol && (opt.marg_tol <= 0 || marg <= opt.marg_tol)) ||
                    (opt.kkt_tol > 0 && stop_out[4] <= opt.kkt_tol);
         if (plan_out && (done || k + 1 == k0 + opt.max_outer))
-            orc_stop(m, n, C, kind, ldc, k, eta, s, gamma, a, b, M, S, stop_out, plan_out);
-        /* Algorithm 2, step 13: X^{k+1} = X^{k,v+1}: r = log a - lse, s = w, k = k+1 */
+            orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, plan_out);
+        /* Algorithm 2, step 13: X^{k+1} = X^{k,v+1}: r = log a - lse, s = w, k = k+1;
+           gamma^{k+1,0} = gamma^{k,v+1} */
         for (int64_t i = 0; i < m; ++i)
             r[i] = log(a[i]) - (M[i] + log(S[i]));
-        for (int64_t j = 0; j < n; ++j)
-            s[j] = s[j] + gamma[j] / eta;
+        memcpy(s, w, sizeof(double) * n);
         if (done) {
             R.status = ORC_OK;
             ++k;
@@ -754,7 +831,8 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         *k_io = k;
     if (rep)
         *rep = R;
-    free(r); free(s); free(gamma); free(M); free(S); free(c); free(g); free(Mt); free(St);
-    free(ct); free(gt); free(Delta); free(rhs); free(d); free(row_ptr);
+    free(r); free(s); free(gamma); free(w); free(M); free(S); free(c); free(g); free(Mt);
+    free(St); free(ct); free(gt); free(Delta); free(rhs); free(tau); free(d); free(lb);
+    free(row_ptr);
     return R.status;
 }

@@ -262,23 +262,36 @@ def test_p11_cg_direction_in_complement(sparse_case):
 # Armijo trial: exact algebra of the difference form
 # ---------------------------------------------------------------------------
 def test_trial_difference_form_matches_two_evals():
+    """The trial's dL is L(w + tau) - L(w) for the grid step tau = grid(t Delta / eta):
+    compare with two separate evaluations, and with the directional derivative for a
+    tiny step (where a difference of two rounded objectives would be pure noise)."""
     inst = W.gmm_points(30, 4, m=26)
     eta = 0.05
     gamma = W.random_dual(30, 6, 0.02)
     s = np.log(inst.b)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, s=s)
+    r = np.log(inst.a)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, r=r, s=s)
+    q = ev.q
     Delta = W.random_dual(30, 8, 0.01)
     for t in (1.0, 0.8, 0.3, 1e-3):
-        dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t, s=s)
-        ev2 = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma + t * Delta, s=s)
-        assert abs(dL - (ev2.L - ev.L)) <= 1e-13 * (abs(ev.L) + 1)
+        dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t,
+                                            s=s, q=q)
+        tau = q * np.rint(t * Delta / eta / q)
+        # the point whose grid potentials are exactly w + tau
+        gamma2 = eta * ((ev.w + tau) - s)
+        ev2 = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma2, r=r, s=s, q=q)
+        np.testing.assert_array_equal(ev2.w, ev.w + tau)
+        Lw = -inst.b @ (eta * (ev.w - s)) + eta * inst.a @ (r + ev.lse)
+        Lw2 = -inst.b @ (eta * (ev2.w - s)) + eta * inst.a @ (r + ev2.lse)
+        assert abs(dL - (Lw2 - Lw)) <= 1e-13 * (abs(Lw) + 1)
         np.testing.assert_allclose(cn, ev2.c, rtol=1e-12)
         np.testing.assert_allclose(Mn + np.log(Sn), ev2.lse, rtol=0, atol=1e-12)
-    # tiny step: the difference form keeps its relative precision, the directional
-    # derivative g^T Delta is recovered
-    t = 1e-9
-    dL, *_ = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t, s=s)
-    assert abs(dL / t - ev.g @ Delta) <= 1e-6 * abs(ev.g @ Delta)
+    # tiny step (second-order term ~1e-19): dL recovers g^T (eta tau)
+    t = 1e-8
+    tau = q * np.rint(t * Delta / eta / q)
+    dL, *_ = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t, s=s, q=q)
+    slope = ev.g @ (eta * tau)
+    assert abs(dL - slope) <= 1e-6 * abs(slope)
 
 
 def test_p18_newton_step_decreases_objective(sparse_case):
@@ -340,13 +353,14 @@ def test_p14_p22_constant_cost():
     b = rng.uniform(0.1, 1, n); b /= b.sum()
     C = np.full((m, n), 0.5)
     ev = orc.eval_pass(C, a, b, 0.01, np.zeros(n), want_plan=True)
-    np.testing.assert_allclose(ev.g, 0, atol=1e-15)
-    np.testing.assert_allclose(ev.plan, np.outer(a, b), rtol=1e-14)
+    # w = log b on the grid (spacing ~2^-44 here) perturbs P by ~1e-14 relative
+    np.testing.assert_allclose(ev.g, 0, atol=1e-14)
+    np.testing.assert_allclose(ev.plan, np.outer(a, b), rtol=1e-13)
     st = orc.stop_pass(C, a, b, 0.01, np.zeros(n), ev.M, ev.S)
     assert abs(st["dphi"]) <= 1e-15
     res = orc.solve(C, a, b, 0.01, want_plan=True)
     assert res["status"] == 0 and res["report"]["outer"] == 1
-    np.testing.assert_allclose(res["plan"], np.outer(a, b), rtol=1e-14)
+    np.testing.assert_allclose(res["plan"], np.outer(a, b), rtol=1e-13)
     assert abs(res["report"]["primal"] - 0.5) <= 1e-15
 
 
