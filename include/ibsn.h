@@ -26,16 +26,17 @@
  * X^0 = a b^T and X^{k+1} = diag(a) P^k(gamma) (eq. (7)) give, for every k,
  *     log X^k_ij = r_i + s_j - k C_ij / eta,
  * so the centre is held implicitly as (k, r, s): r = log a, s = log b at k = 0 and
- * r <- log a - lse, s <- s + gamma/eta, k <- k+1 at an outer update.
- * Every dense pass forms  theta_ij = fma(-sigma, C_ij, w_j)  with
- * sigma = (k+1)/eta and w_j = s_j + gamma_j/eta.
+ * r <- log a - lse, s <- s + gamma/eta, k <- k+1 at an outer update.  The plan of the
+ * subproblem at gamma is the row softmax of theta_ij = w_j - sigma C_ij with
+ * sigma = (k+1)/eta and w_j = s_j + gamma_j/eta (on the grid of ibsn_center).
  *
  * Row state
  * ---------
- * A pair of m-vectors (M, S) represents P_ij = exp(theta_ij - M_i) / S_i, the plan of
- * eq. (7) with a per-row shift.  ibsn_subproblem_eval() sets M_i = max_j theta_ij and
- * S_i = sum_j exp(theta_ij - M_i); ibsn_trial() returns the state of the trial point.
- * lse_i = M_i + log S_i is the row log-sum-exp of eq. (5).
+ * A pair of m-vectors (M, S) represents P_ij = exp(x_ij) / S_i with
+ * x_ij = fma(-sigma, C_ij, w_j - M_i) = theta_ij - M_i, the plan of eq. (7) with a
+ * per-row shift M_i on the grid.  ibsn_subproblem_eval() sets M_i to the grid-rounded
+ * max_j theta_ij and S_i = sum_j exp(x_ij); ibsn_trial() returns the state of the trial
+ * point.  lse_i = M_i + log S_i is the row log-sum-exp of eq. (5).
  */
 #ifndef IBSN_H
 #define IBSN_H
@@ -88,11 +89,23 @@ typedef struct {
     double eta;
 } ibsn_problem;
 
-/* Implicit prox centre X^k (see above): device r (m), s (n). */
+/* Implicit prox centre X^k (see above): device r (m), s (n), and the grid spacing
+   `quantum` (a power of two) of the potentials.  Every pass forms
+   w_j = grid(s_j + gamma_j/eta) with grid(v) = quantum * rint(v / quantum), keeps the row
+   shifts M_i on the same grid, and evaluates x_ij = fma(-sigma, C_ij, w_j - M_i): the
+   difference w_j - M_i is exact, so x_ij = theta_ij - M_i carries one rounding at its
+   own scale however large sigma grows.  ibsn_center_quantum() returns the spacing the
+   solver uses: 2^(e-50) for 2^(e-1) <= max_j |s_j + gamma_j/eta| + sigma max|C| < 2^e. */
 typedef struct {
     int64_t k;
     const double *r, *s;
+    double quantum;
 } ibsn_center;
+
+/* Host out: the grid spacing for (prob, ctr.k, ctr.s, gamma) (see ibsn_center).
+   Reads C once (max |C|).  Synchronises. */
+int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                        const double *gamma, double *quantum_host);
 
 /* Subproblem evaluation (eq. (5)-(8)): the row LSE pass over the m x n kernel.
    In: gamma (n).  Out: M, S (m) row state; lse (m, optional) = M + log S;
@@ -104,19 +117,19 @@ int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cen
                          const double *gamma, double *M, double *S, double *lse,
                          double *colmarg, double *grad, double *obj_host, double *plan);
 
-/* Armijo trial (Algorithm 2, step 9) at gamma + t*Delta from the row state (M) of gamma.
-   Host out dL = L^k(gamma + t Delta) - L^k(gamma), evaluated in difference form
-   (-t b^T Delta + eta sum_i a_i log(sum_j q_ij e^{tau_j} / sum_j q_ij), q = exp(theta - M),
-   tau = t Delta / eta) so that it keeps its relative precision for tiny steps.
-   Device out: M_new, S_new (m) row state of the trial point, colmarg_new, grad_new (n).
-   Synchronises the stream (dL is a host value). */
+/* Armijo trial (Algorithm 2, step 9) from the row state (M) of gamma.  The step is
+   taken on the potential grid: tau_j = grid(t Delta_j / eta), trial point w + tau.
+   Host out dL = L^k(trial) - L^k(gamma), evaluated in difference form
+   (-eta b^T tau + eta sum_i a_i log(sum_j q_ij e^{tau_j} / sum_j q_ij), q = exp(x)) so
+   that it keeps its relative precision for tiny steps.  Device out: M_new, S_new (m)
+   row state of the trial point, colmarg_new, grad_new (n).  Synchronises. */
 int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
                const double *gamma, const double *M, const double *Delta, double t,
                double *dL_host, double *M_new, double *S_new, double *colmarg_new,
                double *grad_new);
 
 /* Hessian sparsification, Algorithm 1, from the row state (M, S) at gamma:
-   P_ij = exp(theta_ij - M_i)/S_i; rows i != istar keep P_ij >= rho (inclusive) divided
+   P_ij = exp(x_ij)/S_i; rows i != istar keep P_ij >= rho (inclusive) divided
    by their kept sum; row istar is kept whole.  istar < 0 selects argmax a (lowest
    index on ties).  *out receives a library-owned handle (free with ibsn_csr_free);
    it also holds d = P_rho^T a and the transpose used by ibsn_hvp.  A row whose
@@ -168,9 +181,11 @@ typedef struct {
     double mu0, mu_floor;                /* mu_k = max(mu0/(k+1)^2, mu_floor): 1e-4, 1e-11 */
     double gap_tol, marg_tol, kkt_tol;   /* 1e-8 relative gap, 1e-9 ||X^T1-b||_1, 0 = off */
     int32_t max_outer, max_newton, max_backtrack, cg_maxit; /* 300, 1000, 60, 0 = min(n,1000) */
-    double cg_forcing_max;               /* CG stops at ||r|| <= min(0.1, ||g||) ||g|| */
-    int32_t rho_mode;                    /* 0: rho = eta ||g|| / (m n); 1: rho = 0 */
-} ibsn_options;
+    double cg_forcing_max;               /* CG stops at ||r|| <= max(min(0.1, ||g||), */
+    int32_t rho_mode;                    /*   cg_rtol_min) ||g||; rho_mode 0: rho =       */
+    double cg_rtol_min;                  /*   eta ||g|| / (m n), 1: rho = 0; 1e-6          */
+    int32_t stall_limit;                 /* 3: failed D_phi tests (gate passed) that end   */
+} ibsn_options;                          /*    the inner loop of one outer iteration       */
 
 void ibsn_default_options(ibsn_options *opt);
 

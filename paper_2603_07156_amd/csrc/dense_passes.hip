@@ -13,6 +13,12 @@
 //
 // The row after the current one is prefetched into a second register set while the
 // current one is reduced, which keeps loads in flight across the reductions.
+//
+// Exponents.  Column potentials w_j and row shifts M_i both lie on a grid of spacing
+// q (a power of two chosen per outer iteration), so w_j - M_i is exact and
+//     x_ij = fma(-sigma, C_ij, w_j - M_i)
+// is theta_ij - M_i with one rounding at the scale of x_ij, however large sigma and
+// the potentials grow.  grid(v) = q * rint(v / q).
 #include "ibsn_internal.h"
 #include "solver_kernels.h"
 
@@ -174,6 +180,8 @@ __device__ __forceinline__ void stage_lds(const double *__restrict__ src, int n,
     __syncthreads();
 }
 
+__device__ __forceinline__ double grid(double v, double q) { return q * rint(v / q); }
+
 __device__ __forceinline__ void row_range(int m, int &i0, int &i1)
 {
     const int64_t g = blockIdx.x, G = gridDim.x;
@@ -187,7 +195,8 @@ __device__ __forceinline__ void row_range(int m, int &i0, int &i1)
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int VEC, typename CT>
 __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t ldc, int m, int n,
-                                             double sigma, const double *__restrict__ w,
+                                             double sigma, double qg,
+                                             const double *__restrict__ w,
                                              const double *__restrict__ a,
                                              const double *__restrict__ r, double *__restrict__ Mo,
                                              double *__restrict__ So, double *__restrict__ lse,
@@ -219,15 +228,15 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         for (int e = 0; e < E; ++e) {
             const double th =
                 col_of<NT, VEC>(e) < n ? fma(-sigma, (double)xr[e], wr[e]) : -INFINITY;
-            x[e] = th;
             red[0] = fmax(red[0], th);
         }
         RedMax::run(red, lds, parity);
-        const double M = red[0];
+        const double M = grid(red[0], qg);
         red[0] = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const double p = exp(x[e] - M);
+            const double p =
+                col_of<NT, VEC>(e) < n ? exp(fma(-sigma, (double)xr[e], wr[e] - M)) : 0.0;
             x[e] = p;
             red[0] += p;
         }
@@ -273,7 +282,8 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int VEC, typename CT, int BIG>
 __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc, int m, int n,
-                                              double sigma, const double *__restrict__ w,
+                                              double sigma, double qg,
+                                              const double *__restrict__ w,
                                               const double *__restrict__ a,
                                               const double *__restrict__ Mb,
                                               const double *__restrict__ colv,
@@ -311,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         for (int e = 0; e < E; ++e) {
             const int j = col_of<NT, VEC>(e);
             if (j < n) {
-                const double q = exp(fma(-sigma, (double)xr[e], wr[e]) - Mi);
+                const double q = exp(fma(-sigma, (double)xr[e], wr[e] - Mi));
                 const double cv = cvl[j];
                 red[0] += q;
                 double qe;
@@ -341,8 +351,11 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
             const double delta =
                 !(Z > 0.0) ? INFINITY : (BIG ? tau_shift + log(Z / A) : log1p(B / A));
             rowacc += ai * delta;
-            Mn[i] = Mi + (tau_shift + log(mx));
-            Sn[i] = Z / mx;
+            // new shift on the grid; S' carries the exact remainder so that
+            // exp(x'_ij) / S'_i = P'_ij for the fresh x' of the point w + tau
+            const double Mnew = grid(Mi + (tau_shift + log(mx)), qg);
+            Mn[i] = Mnew;
+            Sn[i] = Z * exp((Mi - Mnew) + tau_shift);
         }
 #pragma unroll
         for (int e = 0; e < E; ++e)
@@ -405,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
         for (int e = 0; e < E; ++e) {
             const int j = col_of<NT, VEC>(e);
             const bool valid = j < n;
-            const double p = valid ? exp(fma(-sigma, (double)xr[e], wl[j]) - Mi) / Si : 0.0;
+            const double p = valid ? exp(fma(-sigma, (double)xr[e], wl[j] - Mi)) / Si : 0.0;
             const bool keep = valid && (dense || p >= rho);
             x[e] = p;
             if (keep) {
@@ -506,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
         for (int e = 0; e < E; ++e) {
             const int j = col_of<NT, VEC>(e);
             const double X =
-                j < n ? ai * (exp(fma(-sigma, (double)xr[e], wl[j]) - Mi) / Si) : 0.0;
+                j < n ? ai * (exp(fma(-sigma, (double)xr[e], wl[j] - Mi)) / Si) : 0.0;
             x[e] = X;
             red[0] += X;
         }
@@ -574,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
             const int j = col_of<NT, VEC>(e);
             if (j < n) {
                 const double c = (double)cst[e];
-                const double Xv = ai * (exp(fma(-sigma, c, wl[j]) - Mi) / Si);
+                const double Xv = ai * (exp(fma(-sigma, c, wl[j] - Mi)) / Si);
                 X[e] = Xv;
                 red[0] = fma(Xv, y[j], red[0]);
                 red[1] = fmin(red[1], c - gamma[j]);
@@ -584,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
             }
         }
         Red3::run(red, lds, parity);
-        const double eri = ai - zi * red[0];
+        const double eri = fmax(ai - zi * red[0], 0.0);   // >= 0 exactly; clamp rounding
         const double zg = red[1], zp = red[2];
         const double la = log(ai), ls = log(Si);
 #pragma unroll 2
@@ -596,7 +609,7 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
                 const double f = (zi * Xv) * y[j];
                 const double xh = er1 > 0.0 ? f + eri * ec[j] / er1 : f;
                 if (xh > 0.0) {
-                    const double lx = la + (fma(-sigma, c, wl[j]) - Mi) - ls;
+                    const double lx = la + fma(-sigma, c, wl[j] - Mi) - ls;
                     t_dphi += xh * (log(xh) - lx) - xh + Xv;
                 } else {
                     t_dphi += Xv;
@@ -715,7 +728,8 @@ hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, do
 {
 #define BODY                                                                                     \
     hipLaunchKernelGGL((k_eval<NT, Q, VEC, CT>), dim3(p.grid), dim3(NT), 0, st,                  \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, r, M, S, lse, \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, r, M, S, \
+                       lse,                                                                      \
                        plan, colpart, rowpart)
 #define X(a, b) IBSN_DISPATCH(a, b, BODY, BODY)
     IBSN_ROW_CONFIGS(X)
@@ -731,10 +745,10 @@ hipError_t launch_trial(const RowPlan &p, const DenseArgs &d, const double *M, c
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
     hipLaunchKernelGGL((k_trial<NT, Q, VEC, CT, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, colv,    \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
                        scal, M_new, S_new, colpart, rowpart);                                     \
     hipLaunchKernelGGL((k_trial<NT, Q, VEC, CT, 1>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, colv,    \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
                        scal, M_new, S_new, colpart, rowpart)
 #define X(a, b) IBSN_DISPATCH(a, b, BODY, BODY)
     IBSN_ROW_CONFIGS(X)

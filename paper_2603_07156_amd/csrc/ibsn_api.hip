@@ -46,7 +46,7 @@ struct ibsn_ctx {
     std::string err;
     // workspace
     DevBuf w, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
-    DevBuf stopout, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_partial, cg_scal, cg_counter;
+    DevBuf stopout, tauv, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_partial, cg_scal, cg_counter;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     ibsn_csr *solver_csr = nullptr;
 };
@@ -157,7 +157,19 @@ int check_center(ibsn_ctx *ctx, const ibsn_center *c)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "center (k, r, s) with device s is required");
     if (c->k < 0)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "center k=%lld < 0", (long long)c->k);
+    int e = 0;
+    if (!(c->quantum > 0.0) || !std::isfinite(c->quantum) || std::frexp(c->quantum, &e) != 0.5)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "center quantum=%g must be a power of two",
+                    c->quantum);
     return IBSN_OK;
+}
+
+// grid spacing 2^(e-50) for a bound 2^(e-1) <= B < 2^e (see ibsn_center)
+double quantum_of(double B)
+{
+    if (!(B >= 1.0))
+        B = 1.0;
+    return std::ldexp(1.0, std::ilogb(B) + 1 - 50);
 }
 
 int plan_for(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *rp)
@@ -185,12 +197,14 @@ int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
     CKI(ensure(ctx, ctx->psiv, n * 8));
     CKI(ensure(ctx, ctx->zv, m * 8));
     CKI(ensure(ctx, ctx->stopout, 16 * 8));
+    CKI(ensure(ctx, ctx->tauv, n * 8));
     return IBSN_OK;
 }
 
-DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k)
+DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k, double q)
 {
     DenseArgs d;
+    d.q = q;
     d.C = p->C;
     d.ldc = p->ldc;
     d.m = p->m;
@@ -215,12 +229,12 @@ int read_scal(ibsn_ctx *ctx, int count = SC_NSLOT)
 // ---------------------------------------------------------------------------------
 // eval at the current ctx->w (already formed); writes M, S, lse, c, g, plan; objective to
 // scal[SC_OBJ] when r != null (needs gamma for b^T gamma); norms of g to scal.
-int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, const double *r,
-             const double *gamma, double *M, double *S, double *lse, double *c, double *g,
-             double *plan)
+int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
+             const double *r, const double *gamma, double *M, double *S, double *lse, double *c,
+             double *g, double *plan)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k);
+    DenseArgs d = dense_args(ctx, p, k, q);
     CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart), P<double>(ctx->rowpart),
                     st));
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, c, p->b, g, st));
@@ -233,30 +247,33 @@ int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     return IBSN_OK;
 }
 
-// trial at gamma + t Delta: writes Mn, Sn, cn, gn; scal[SC_DL] = dL (needs scal[SC_BD]).
-int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, const double *M,
-              const double *Delta, double t, double *Mn, double *Sn, double *cn, double *gn)
+// trial at the grid point w + grid(t Delta/eta) (step kept in ctx->tauv): writes Mn, Sn,
+// cn, gn; scal[SC_DL] = dL.
+int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
+              const double *M, const double *Delta, double t, double *Mn, double *Sn, double *cn,
+              double *gn)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k);
+    DenseArgs d = dense_args(ctx, p, k, q);
     double *scal = P<double>(ctx->scal);
-    CKH(sk_trial_prep(p->n, t, p->eta, Delta, P<double>(ctx->colv), scal, st));
+    CKH(sk_trial_prep(p->n, t, p->eta, q, Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
+                      scal, st));
     CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
                      P<double>(ctx->rowpart), st));
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, cn, p->b, gn, st));
     CKH(sk_gnorms(p->n, gn, scal, st));
-    // dL = eta * sum_i a_i delta_i - t * b^T Delta
-    CKH(sk_sum_parts(rp.grid, 1, 0, P<double>(ctx->rowpart), p->eta, -t, SC_BD, SC_DL, 0, scal,
-                     st));
+    // dL = eta * sum_i a_i delta_i - eta * b^T tau
+    CKH(sk_sum_parts(rp.grid, 1, 0, P<double>(ctx->rowpart), p->eta, -p->eta, SC_TB, SC_DL, 0,
+                     scal, st));
     return IBSN_OK;
 }
 
 // stop test + certificate at the state (w, M, S); out (device, 10 doubles)
-int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
+int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
              const double *gamma, const double *M, const double *S, double *xhat)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k);
+    DenseArgs d = dense_args(ctx, p, k, q);
     double *scal = P<double>(ctx->scal);
     double *colX = P<double>(ctx->cvec);   // reuse as column sums of X
     double *colF = P<double>(ctx->colv);
@@ -310,11 +327,11 @@ void csr_release(ibsn_csr *c)
 }
 
 // sparsify into c at the state (w formed), rho; istar on device in c->istar_dev
-int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
+int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
                  const double *M, const double *S, double rho, ibsn_csr *c)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k);
+    DenseArgs d = dense_args(ctx, p, k, q);
     CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
                         P<double>(c->val), P<int32_t>(c->len), P<double>(ctx->colpart), st));
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(c->d), nullptr,
@@ -465,7 +482,8 @@ void ibsn_destroy(ibsn_ctx *ctx)
     }
     DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
-                      &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->cg_x, &ctx->cg_r, &ctx->cg_p,
+                      &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv, &ctx->cg_x, &ctx->cg_r,
+                      &ctx->cg_p,
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_partial, &ctx->cg_scal,
                       &ctx->cg_counter};
     for (DevBuf *b : bufs)
@@ -498,6 +516,28 @@ void ibsn_default_options(ibsn_options *o)
     o->cg_maxit = 0;
     o->cg_forcing_max = 0.1;
     o->rho_mode = 0;
+    o->cg_rtol_min = 1e-6;
+    o->stall_limit = 3;
+}
+
+int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                        const double *gamma, double *quantum_host)
+{
+    CKI(check_problem(ctx, prob));
+    if (!ctr || !ctr->s || ctr->k < 0 || !gamma || !quantum_host)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "center (k >= 0, s), gamma and output required");
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    double *scal = P<double>(ctx->scal);
+    CKH(sk_cost_max(prob->m, prob->n, prob->ldc, prob->cost_kind, prob->C,
+                    P<double>(ctx->rowpart2), rp.grid, scal, ctx->stream));
+    CKH(sk_wmax(prob->n, ctr->s, gamma, prob->eta, scal, ctx->stream));
+    CKI(read_scal(ctx));
+    const double sigma = (double)(ctr->k + 1) / prob->eta;
+    *quantum_host = quantum_of(ctx->host_scal[SC_WMAX] + sigma * ctx->host_scal[SC_CMAX]);
+    return IBSN_OK;
 }
 
 int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
@@ -514,8 +554,10 @@ int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cen
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    CKH(launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w), ctx->stream));
-    CKI(run_eval(ctx, prob, rp, ctr->k, obj_host ? ctr->r : nullptr, gamma, M, S, lse, colmarg,
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
+                      ctx->stream));
+    CKI(run_eval(ctx, prob, rp, ctr->k, ctr->quantum, obj_host ? ctr->r : nullptr, gamma, M, S,
+                 lse, colmarg,
                  grad, plan));
     if (obj_host) {
         CKI(read_scal(ctx));
@@ -538,9 +580,10 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, 
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    CKH(launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w), ctx->stream));
-    CKH(sk_dot_slot(prob->n, prob->b, Delta, SC_BD, P<double>(ctx->scal), ctx->stream));
-    CKI(run_trial(ctx, prob, rp, ctr->k, M, Delta, t, M_new, S_new, colmarg_new, grad_new));
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
+                      ctx->stream));
+    CKI(run_trial(ctx, prob, rp, ctr->k, ctr->quantum, M, Delta, t, M_new, S_new, colmarg_new,
+                  grad_new));
     CKI(read_scal(ctx));
     *dL_host = ctx->host_scal[SC_DL];
     return IBSN_OK;
@@ -586,12 +629,12 @@ int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ct
             rc = hipStreamSynchronize(ctx->stream) == hipSuccess ? IBSN_OK : IBSN_ERR_HIP;
     }
     if (rc == IBSN_OK) {
-        if (launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w),
+        if (launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
                           ctx->stream) != hipSuccess)
             rc = fail(ctx, IBSN_ERR_HIP, "make_w failed");
     }
     if (rc == IBSN_OK)
-        rc = run_sparsify(ctx, prob, rp, ctr->k, M, S, rho, c);
+        rc = run_sparsify(ctx, prob, rp, ctr->k, ctr->quantum, M, S, rho, c);
     if (rc < 0) {
         csr_release(c);
         delete c;
@@ -684,8 +727,9 @@ int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, c
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
     CKH(sk_dot_slot(prob->m, prob->a, nullptr, SC_SUMA, P<double>(ctx->scal), ctx->stream));
-    CKH(launch_make_w(ctr->s, gamma, 0.0, prob->eta, prob->n, P<double>(ctx->w), ctx->stream));
-    CKI(run_stop(ctx, prob, rp, ctr->k, gamma, M, S, xhat));
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
+                      ctx->stream));
+    CKI(run_stop(ctx, prob, rp, ctr->k, ctr->quantum, gamma, M, S, xhat));
     CKH(hipMemcpyAsync(out_host, ctx->stopout.p, sizeof(double) * 10, hipMemcpyDeviceToHost,
                        ctx->stream));
     CKH(hipStreamSynchronize(ctx->stream));
@@ -798,6 +842,13 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     if (!resume)
         CKSH(sk_center(n, gamma, st));
 
+    // per-problem maximum of |C| (sets the grid spacing of each outer iteration)
+    CKSH(sk_cost_max(m, n, prob->ldc, prob->cost_kind, prob->C, P<double>(ctx->rowpart2), rp.grid,
+                     scal, st));
+    CKS(read_scal(ctx));
+    const double cmax = ctx->host_scal[SC_CMAX];
+    double *w = P<double>(ctx->w);
+
     ibsn_report R;
     memset(&R, 0, sizeof(R));
     R.status = IBSN_WARN_MAXITER;
@@ -807,18 +858,22 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     const double mn = (double)m * (double)n;
     for (; k < k0 + opt.max_outer; ++k) {
         const double mu = std::max(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
-        // fresh evaluation of the new subproblem at the current gamma
+        const double sigma = (double)(k + 1) / eta;
         double ta = now_s();
-        CKSH(launch_make_w(s, gamma, 0.0, eta, n, P<double>(ctx->w), st));
-        CKS(run_eval(ctx, prob, rp, k, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
+        // grid of this outer iteration and the potentials w = grid(s + gamma/eta)
+        CKSH(sk_wmax(n, s, gamma, eta, scal, st));
+        CKS(read_scal(ctx));
+        const double q = quantum_of(ctx->host_scal[SC_WMAX] + sigma * cmax);
+        CKSH(launch_make_w(s, gamma, q, eta, n, w, st));
+        // fresh evaluation of the new subproblem
+        CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
         ++R.passes;
         CKS(read_scal(ctx));
-        // Sinkhorn warm-up (Algorithm 2, steps 3-4)
+        // Sinkhorn warm-up (Algorithm 2, steps 3-4), on the grid potentials
         for (int it = 0; it < opt.sinkhorn_maxit && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol;
              ++it) {
-            CKSH(sk_sinkhorn_step(n, eta, prob->b, c, gamma, st));
-            CKSH(launch_make_w(s, gamma, 0.0, eta, n, P<double>(ctx->w), st));
-            CKS(run_eval(ctx, prob, rp, k, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
+            CKSH(sk_sinkhorn_step(n, eta, q, prob->b, c, s, w, st));
+            CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
             ++R.passes;
             ++R.sinkhorn;
             CKS(read_scal(ctx));
@@ -830,30 +885,29 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         }
         R.t_eval += now_s() - ta;
         bool stopped = false;
+        int stalls = 0;
         for (int v = 0; v < opt.max_newton; ++v) {
             const double gn = ctx->host_scal[SC_GN];
             const double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / mn;   // step 6
             ta = now_s();
-            // w still holds s + gamma/eta of the current iterate
-            CKS(run_sparsify(ctx, prob, rp, k, M, S, rho, csr));   // step 7
+            CKS(run_sparsify(ctx, prob, rp, k, q, M, S, rho, csr));   // step 7
             ++R.passes;
             R.t_sparsify += now_s() - ta;
             ta = now_s();
             CKSH(sk_neg(n, g, Delta, st));   // rhs = -g
             int cgit = 0;
-            const double tol = std::min(opt.cg_forcing_max, gn) * gn;
+            const double tol = std::max(std::min(opt.cg_forcing_max, gn), opt.cg_rtol_min) * gn;
             CKS(run_cg(ctx, csr, prob->a, eta, gn, Delta, tol, cg_maxit, &cgit));   // step 8
             CKSH(hipMemcpyAsync(Delta, ctx->cg_x.p, n * 8, hipMemcpyDeviceToDevice, st));
             R.cg += cgit;
             R.t_cg += now_s() - ta;
             ta = now_s();
             CKSH(sk_dot_slot(n, g, Delta, SC_GD, scal, st));
-            CKSH(sk_dot_slot(n, prob->b, Delta, SC_BD, scal, st));
             double t = 1.0;
             int bt = 0;
             bool accepted = false;
             for (;;) {   // step 9: Armijo backtracking on a finite decrease
-                CKS(run_trial(ctx, prob, rp, k, M, Delta, t, Mt, St, ct, gt));
+                CKS(run_trial(ctx, prob, rp, k, q, M, Delta, t, Mt, St, ct, gt));
                 ++R.passes;
                 CKS(read_scal(ctx));
                 const double gd = ctx->host_scal[SC_GD];
@@ -869,26 +923,26 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             }
             R.backtracks += bt;
             if (!accepted) {
-                // no acceptable step: keep gamma, restore the norms of the current g and
+                // no acceptable step: keep the iterate, restore the norms of its g and
                 // end the inner loop
                 CKSH(sk_gnorms(n, g, scal, st));
                 CKS(read_scal(ctx));
                 R.t_linesearch += now_s() - ta;
                 break;
             }
-            // step 10: gamma += t Delta; the accepted trial is the new iterate
-            CKSH(sk_axpy(n, t, Delta, gamma, st));
+            // step 10 on the grid: w += tau is exact; the accepted trial is the new iterate
+            CKSH(sk_axpy(n, 1.0, P<double>(ctx->tauv), w, st));
             std::swap(M, Mt);
             std::swap(S, St);
             std::swap(c, ct);
             std::swap(g, gt);
-            CKSH(launch_make_w(s, gamma, 0.0, eta, n, P<double>(ctx->w), st));
             ++R.newton;
             R.t_linesearch += now_s() - ta;
             // step 12 with the practical schedule: gradient gate, then D_phi test
             if (ctx->host_scal[SC_GN] < mu) {
                 ta = now_s();
-                CKS(run_stop(ctx, prob, rp, k, gamma, M, S, nullptr));
+                CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
+                CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
                 R.passes += 2;
                 ++R.stop_tests;
                 CKSH(hipMemcpyAsync(stop_h, ctx->stopout.p, sizeof(stop_h), hipMemcpyDeviceToHost,
@@ -899,11 +953,14 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                     stopped = true;
                     break;
                 }
+                if (++stalls >= opt.stall_limit)
+                    break;
             }
         }
+        CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
         if (!stopped) {
             ta = now_s();
-            CKS(run_stop(ctx, prob, rp, k, gamma, M, S, nullptr));
+            CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
             R.passes += 2;
             ++R.stop_tests;
             CKSH(hipMemcpyAsync(stop_h, ctx->stopout.p, sizeof(stop_h), hipMemcpyDeviceToHost, st));
@@ -921,11 +978,11 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         const bool done = (R.rel_gap <= opt.gap_tol && (opt.marg_tol <= 0 || R.marg_l1 <= opt.marg_tol)) ||
                           (opt.kkt_tol > 0 && R.kkt <= opt.kkt_tol);
         if (plan_out && (done || k + 1 == k0 + opt.max_outer)) {
-            CKS(run_stop(ctx, prob, rp, k, gamma, M, S, plan_out));
+            CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out));
             R.passes += 2;
         }
-        // step 13: X^{k+1} = X^{k,v+1}, i.e. r = log a - lse, s = w; k = k+1
-        CKSH(sk_outer_update(m, n, prob->a, M, S, P<double>(ctx->w), r, s, st));
+        // step 13: X^{k+1} = X^{k,v+1}, i.e. r = log a - lse, s = w; k = k+1; gamma kept
+        CKSH(sk_outer_update(m, n, prob->a, M, S, w, r, s, st));
         if (done) {
             R.status = IBSN_OK;
             ++k;

@@ -25,13 +25,15 @@ struct DenseArgs {
     int64_t m, n;
     int cost_kind;
     double sigma;           // (k+1)/eta
-    const double *w;        // n: s + gamma/eta
+    double q;               // grid spacing of the potentials (power of two)
+    const double *w;        // n: grid(s + gamma/eta)
     const double *a;        // m
 };
 
 // ---- eval (fresh row LSE) ------------------------------------------------------
-// Writes M, S (and lse if non-null), plan (optional), colpart[grid][n] = column
-// partials of a_i P_ij, rowpart[grid] = sum_i a_i ((r_i + M_i) + log S_i).
+// Writes M (grid-rounded row maxima), S (and lse if non-null), plan (optional),
+// colpart[grid][n] = column partials of a_i P_ij,
+// rowpart[grid] = sum_i a_i ((r_i + M_i) + log S_i).
 hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, double *M, double *S,
                        double *lse, double *plan, double *colpart, double *rowpart,
                        hipStream_t st);
@@ -76,8 +78,9 @@ hipError_t launch_colreduce(const double *part, int G, int64_t n, double *out, c
                             double *out2, hipStream_t st);
 
 // ---- small vector / scalar kernels ----------------------------------------------
-hipError_t launch_make_w(const double *s, const double *gamma, double inv_eta_unused, double eta,
-                         int64_t n, double *w, hipStream_t st);
+// w_j = grid(s_j + gamma_j / eta) with spacing q (gamma may be null)
+hipError_t launch_make_w(const double *s, const double *gamma, double q, double eta, int64_t n,
+                         double *w, hipStream_t st);
 // out[0] = sum_i x_i (fixed order) for up to n values, single workgroup
 hipError_t launch_sum(const double *x, int64_t n, double *out, hipStream_t st);
 // out[0] = sum_i x_i * y_i (fixed order), single workgroup

@@ -14,15 +14,23 @@ enum {
     SC_BG, SC_BP, SC_ER1, SC_COLRES,        // stop test
     SC_SUMA, SC_SUMB, SC_MINA, SC_MINB, SC_BAD, SC_ISTAR,
     SC_NNZ,                                 // (as double) nnz of the last factor
+    SC_WMAX, SC_CMAX, SC_TB,                // max|s+gamma/eta|, max|C|, b^T tau
     SC_NSLOT = 32
 };
 
 hipError_t sk_gnorms(int64_t n, const double *g, double *scal, hipStream_t st);
-hipError_t sk_sinkhorn_step(int64_t n, double eta, const double *b, const double *c,
-                            double *gamma, hipStream_t st);
+hipError_t sk_sinkhorn_step(int64_t n, double eta, double q, const double *b, const double *c,
+                            const double *s, double *w, hipStream_t st);
+hipError_t sk_wmax(int64_t n, const double *s, const double *gamma, double eta, double *scal,
+                   hipStream_t st);
+// scal[SC_CMAX] = max |C| (part: G doubles of scratch)
+hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *C, double *part,
+                       int G, double *scal, hipStream_t st);
+hipError_t sk_gamma_of(int64_t n, double eta, const double *w, const double *s, double *gamma,
+                       hipStream_t st);
 hipError_t sk_center(int64_t n, double *gamma, hipStream_t st);
-hipError_t sk_trial_prep(int64_t n, double t, double eta, const double *Delta, double *colv,
-                         double *scal, hipStream_t st);
+hipError_t sk_trial_prep(int64_t n, double t, double eta, double q, const double *Delta,
+                         const double *b, double *tau, double *colv, double *scal, hipStream_t st);
 // scal[slot] = alpha * (op-reduce_g part[g*stride+off]) + beta * scal[src] (src < 0: none);
 // op 0 = sum, 1 = max, 2 = min
 hipError_t sk_sum_parts(int G, int stride, int off, const double *part, double alpha, double beta,

@@ -67,23 +67,78 @@ __global__ __launch_bounds__(NT) void k_gnorms(int n, const double *__restrict__
     }
 }
 
+__device__ __forceinline__ double grid(double v, double q) { return q * rint(v / q); }
+
 // Sinkhorn gamma-step on Z^k with zeta = zeta(gamma) (eq. (4), (5)):
-// gamma_j += eta (log b_j - log c_j), then gamma -= mean(gamma) (Algorithm 2, step 4).
-__global__ __launch_bounds__(NT) void k_sinkhorn_step(int n, double eta, const double *__restrict__ b,
+// gamma_j += eta (log b_j - log c_j), taken on the potentials w = s + gamma/eta as
+// w_j += grid(log b_j - log c_j); then gamma = eta (w - s) is centred (Algorithm 2,
+// step 4) by a grid shift of w, which leaves P unchanged.
+__global__ __launch_bounds__(NT) void k_sinkhorn_step(int n, double eta, double q,
+                                                      const double *__restrict__ b,
                                                       const double *__restrict__ c,
-                                                      double *__restrict__ gamma)
+                                                      const double *__restrict__ s,
+                                                      double *__restrict__ w)
 {
     __shared__ double lds[NW];
-    double s = 0.0;
+    double acc = 0.0;
     for (int j = threadIdx.x; j < n; j += NT) {
-        const double v = gamma[j] + eta * (log(b[j]) - log(c[j]));
-        gamma[j] = v;
-        s += v;
+        const double v = w[j] + grid(log(b[j]) - log(c[j]), q);
+        w[j] = v;
+        acc += eta * (v - s[j]);
     }
-    s = wg_red<0>(s, lds);
-    const double mean = s / (double)n;
+    acc = wg_red<0>(acc, lds);
+    const double sh = grid((acc / (double)n) / eta, q);
     for (int j = threadIdx.x; j < n; j += NT)
-        gamma[j] -= mean;
+        w[j] -= sh;
+}
+
+// scal[SC_WMAX] = max_j |s_j + gamma_j / eta|
+__global__ __launch_bounds__(NT) void k_wmax(int n, const double *__restrict__ s,
+                                             const double *__restrict__ gamma, double eta,
+                                             double *__restrict__ scal)
+{
+    __shared__ double lds[NW];
+    double mx = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT)
+        mx = fmax(mx, fabs(s[j] + gamma[j] / eta));
+    mx = wg_red<1>(mx, lds);
+    if (threadIdx.x == 0)
+        scal[SC_WMAX] = mx;
+}
+
+// per-workgroup max |C| over a block of rows -> part[g]
+__global__ __launch_bounds__(256) void k_cost_max_part(int m, int n, int64_t ldc, int kind,
+                                                       const void *__restrict__ C,
+                                                       double *__restrict__ part)
+{
+    __shared__ double lds[4];
+    const int64_t g = blockIdx.x, G = gridDim.x;
+    const int i0 = (int)((int64_t)m * g / G), i1 = (int)((int64_t)m * (g + 1) / G);
+    double mx = 0.0;
+    for (int i = i0; i < i1; ++i)
+        for (int j = threadIdx.x; j < n; j += 256) {
+            const double c = kind == 1 ? (double)((const float *)C)[(int64_t)i * ldc + j]
+                                       : ((const double *)C)[(int64_t)i * ldc + j];
+            mx = fmax(mx, fabs(c));
+        }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1)
+        mx = fmax(mx, __shfl_xor(mx, o, WAVE));
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        lds[threadIdx.x / WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[g] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+}
+
+// gamma = eta (w - s)
+__global__ __launch_bounds__(256) void k_gamma_of(int n, double eta, const double *__restrict__ w,
+                                                  const double *__restrict__ s,
+                                                  double *__restrict__ gamma)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n)
+        gamma[j] = eta * (w[j] - s[j]);
 }
 
 __global__ __launch_bounds__(NT) void k_center(int n, double *__restrict__ gamma)
@@ -98,28 +153,35 @@ __global__ __launch_bounds__(NT) void k_center(int n, double *__restrict__ gamma
         gamma[j] -= mean;
 }
 
-// Armijo column factors for step t along Delta: tau = t Delta / eta.
-// small step (max tau <= 500): colv = expm1(tau), shift 0;
-// big step: colv = exp(tau - max tau), shift = max tau.
-// Also scal[SC_BD] = b^T Delta is not touched here (computed once per direction).
-__global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta,
+// Armijo step on the grid: tau_j = grid(t Delta_j / eta), so the trial point is w + tau
+// exactly.  Column factors: small step (max tau <= 500): colv = expm1(tau), shift 0;
+// big step: colv = exp(tau - max tau), shift = max tau.  scal[SC_TB] = b^T tau.
+__global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, double q,
                                                    const double *__restrict__ Delta,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ tau,
                                                    double *__restrict__ colv,
                                                    double *__restrict__ scal)
 {
     __shared__ double lds[NW];
-    double mx = -INFINITY;
-    for (int j = threadIdx.x; j < n; j += NT)
-        mx = fmax(mx, t * Delta[j] / eta);
+    double mx = -INFINITY, bt = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double v = grid(t * Delta[j] / eta, q);
+        tau[j] = v;
+        mx = fmax(mx, v);
+        bt = fma(b[j], v, bt);
+    }
     mx = wg_red<1>(mx, lds);
+    bt = wg_red<0>(bt, lds);
     const bool big = mx > 500.0;
     for (int j = threadIdx.x; j < n; j += NT) {
-        const double tau = t * Delta[j] / eta;
-        colv[j] = big ? exp(tau - mx) : expm1(tau);
+        const double v = tau[j];
+        colv[j] = big ? exp(v - mx) : expm1(v);
     }
     if (threadIdx.x == 0) {
         scal[SC_BIG] = big ? 1.0 : 0.0;
         scal[SC_TAUSHIFT] = big ? mx : 0.0;
+        scal[SC_TB] = bt;
     }
 }
 
@@ -179,7 +241,7 @@ __global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const dou
         const double yj = fmin(bj / cx, 1.0);
         const double fj = yj * cf;
         y[j] = yj;
-        ec[j] = bj - fj;
+        ec[j] = fmax(bj - fj, 0.0);   // >= 0 exactly (y <= 1, z <= 1); clamp rounding
         syf += fj;
         cc = fma(cx - bj, cx - bj, cc);
         const double pj = (w[j] - log(bj)) / sigma;
@@ -372,16 +434,37 @@ hipError_t sk_gnorms(int64_t n, const double *g, double *scal, hipStream_t st)
 {
     L1(k_gnorms, (int)n, g, scal);
 }
-hipError_t sk_sinkhorn_step(int64_t n, double eta, const double *b, const double *c,
-                            double *gamma, hipStream_t st)
+hipError_t sk_sinkhorn_step(int64_t n, double eta, double q, const double *b, const double *c,
+                            const double *s, double *w, hipStream_t st)
 {
-    L1(k_sinkhorn_step, (int)n, eta, b, c, gamma);
+    L1(k_sinkhorn_step, (int)n, eta, q, b, c, s, w);
+}
+hipError_t sk_wmax(int64_t n, const double *s, const double *gamma, double eta, double *scal,
+                   hipStream_t st)
+{
+    L1(k_wmax, (int)n, s, gamma, eta, scal);
+}
+hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *C, double *part,
+                       int G, double *scal, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cost_max_part, dim3(G), dim3(256), 0, st, (int)m, (int)n, ldc, kind, C,
+                       part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, st, G, 1, 0, part, 1.0, 0.0, -1, SC_CMAX,
+                       1, scal);
+    return hipGetLastError();
+}
+hipError_t sk_gamma_of(int64_t n, double eta, const double *w, const double *s, double *gamma,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gamma_of, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)n, eta,
+                       w, s, gamma);
+    return hipGetLastError();
 }
 hipError_t sk_center(int64_t n, double *gamma, hipStream_t st) { L1(k_center, (int)n, gamma); }
-hipError_t sk_trial_prep(int64_t n, double t, double eta, const double *Delta, double *colv,
-                         double *scal, hipStream_t st)
+hipError_t sk_trial_prep(int64_t n, double t, double eta, double q, const double *Delta,
+                         const double *b, double *tau, double *colv, double *scal, hipStream_t st)
 {
-    L1(k_trial_prep, (int)n, t, eta, Delta, colv, scal);
+    L1(k_trial_prep, (int)n, t, eta, q, Delta, b, tau, colv, scal);
 }
 hipError_t sk_sum_parts(int G, int stride, int off, const double *part, double alpha, double beta,
                         int src, int slot, int op, double *scal, hipStream_t st)

@@ -403,13 +403,16 @@ __global__ __launch_bounds__(1024) void k_dot(int n, const double *__restrict__ 
         *out = s;
 }
 
+// w_j = grid(s_j + gamma_j / eta), grid(v) = q * rint(v / q)
 __global__ __launch_bounds__(256) void k_make_w(int n, const double *__restrict__ s,
                                                 const double *__restrict__ gamma, double eta,
-                                                double *__restrict__ w)
+                                                double q, double *__restrict__ w)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j < n)
-        w[j] = s[j] + (gamma ? gamma[j] / eta : 0.0);
+    if (j < n) {
+        const double v = s[j] + (gamma ? gamma[j] / eta : 0.0);
+        w[j] = q * rint(v / q);
+    }
 }
 
 // standard CSR from the row slots
@@ -544,11 +547,11 @@ hipError_t launch_cg_iteration(int64_t m, int64_t n, const int32_t *col, const d
     return hipGetLastError();
 }
 
-hipError_t launch_make_w(const double *s, const double *gamma, double, double eta, int64_t n,
+hipError_t launch_make_w(const double *s, const double *gamma, double q, double eta, int64_t n,
                          double *w, hipStream_t st)
 {
     hipLaunchKernelGGL(k_make_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)n, s,
-                       gamma, eta, w);
+                       gamma, eta, q, w);
     return hipGetLastError();
 }
 

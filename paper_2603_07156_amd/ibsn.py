@@ -37,7 +37,8 @@ class _Problem(ct.Structure):
 
 
 class _Center(ct.Structure):
-    _fields_ = [("k", ct.c_int64), ("r", ct.c_void_p), ("s", ct.c_void_p)]
+    _fields_ = [("k", ct.c_int64), ("r", ct.c_void_p), ("s", ct.c_void_p),
+                ("quantum", ct.c_double)]
 
 
 class Options(ct.Structure):
@@ -48,6 +49,7 @@ class Options(ct.Structure):
         ("gap_tol", ct.c_double), ("marg_tol", ct.c_double), ("kkt_tol", ct.c_double),
         ("max_outer", ct.c_int32), ("max_newton", ct.c_int32), ("max_backtrack", ct.c_int32),
         ("cg_maxit", ct.c_int32), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int32),
+        ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int32),
     ]
 
 
@@ -70,7 +72,7 @@ class Report(ct.Structure):
 
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
-           "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
+           "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve")
 
@@ -92,6 +94,7 @@ def load():
     L.ibsn_last_error.argtypes = [vp]
     L.ibsn_last_error.restype = ct.c_char_p
     L.ibsn_num_cus.argtypes = [vp]
+    L.ibsn_center_quantum.argtypes = [vp, P, C, vp, ct.POINTER(dbl)]
     L.ibsn_subproblem_eval.argtypes = [vp, P, C, vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), vp]
     L.ibsn_trial.argtypes = [vp, P, C, vp, vp, vp, dbl, ct.POINTER(dbl), vp, vp, vp, vp]
     L.ibsn_sparsify.argtypes = [vp, P, C, vp, vp, vp, dbl, i64, ct.POINTER(vp)]
@@ -201,19 +204,34 @@ class Problem:
 
 @dataclass
 class Center:
-    """Implicit prox centre log X^k = r + s - k C / eta (r may be None if unused)."""
+    """Implicit prox centre log X^k = r + s - k C / eta (r may be None if unused), with the
+    grid spacing `quantum` of the potentials (a power of two; see include/ibsn.h)."""
 
     k: int
     r: torch.Tensor | None
     s: torch.Tensor
+    quantum: float
 
     def raw(self, m, n):
-        return _Center(int(self.k), _ptr(self.r, m, name="r"), _ptr(self.s, n, name="s"))
+        return _Center(int(self.k), _ptr(self.r, m, name="r"), _ptr(self.s, n, name="s"),
+                       float(self.quantum))
 
     @staticmethod
-    def initial(prob: Problem) -> "Center":
-        """X^0 = a b^T (Algorithm 2 input)."""
-        return Center(0, torch.log(prob.a), torch.log(prob.b))
+    def initial(ctx: "Context", prob: Problem, gamma: torch.Tensor | None = None) -> "Center":
+        """X^0 = a b^T (Algorithm 2 input), with the solver's grid for gamma (0 if None)."""
+        c = Center(0, torch.log(prob.a), torch.log(prob.b), 1.0)
+        g = gamma if gamma is not None else torch.zeros_like(prob.b)
+        c.quantum = center_quantum(ctx, prob, c, g)
+        return c
+
+
+def center_quantum(ctx: "Context", prob: Problem, center: Center, gamma) -> float:
+    """ibsn_center_quantum: grid spacing for (prob, center.k, center.s, gamma)."""
+    q = ct.c_double()
+    raw = _Center(int(center.k), None, _ptr(center.s, prob.n, name="s"), 1.0)
+    ctx.check(load().ibsn_center_quantum(ctx.h, ct.byref(prob.raw()), ct.byref(raw),
+                                         _ptr(gamma, prob.n, name="gamma"), ct.byref(q)))
+    return q.value
 
 
 def _new(prob, count):
@@ -360,6 +378,7 @@ def solve(ctx: Context, prob: Problem, options: Options | None = None, gamma0=No
 
 
 # the C-ABI names
+ibsn_center_quantum = center_quantum
 ibsn_subproblem_eval = subproblem_eval
 ibsn_trial = trial
 ibsn_sparsify = sparsify

@@ -53,13 +53,20 @@ def outer_state(inst, k):
     return res["r"], res["s"], res["k"], res["gamma"] + W.random_dual(inst.n, 3, 1e-4)
 
 
+def center(ib, inst, r, s, k, gamma, C=None):
+    """Centre with the oracle's grid spacing for these inputs."""
+    q = orc.center_quantum(inst.C if C is None else C, s, gamma, inst.eta, k)
+    return ib.Center(k, dev(r), dev(s), q), q
+
+
 def check_eval(ib, ctx, inst, r, s, k, gamma, C=None, want_plan=True):
     Cc = inst.C if C is None else C
     pr = problem(ib, inst, Cc)
-    ctr = ib.Center(k, dev(r), dev(s))
+    ctr, q = center(ib, inst, r, s, k, gamma, Cc)
     gv = ib.subproblem_eval(ctx, pr, ctr, dev(gamma), want_obj=True, want_plan=want_plan)
-    ov = orc.eval_pass(Cc, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, want_plan=want_plan)
-    # row maxima: the same single fma on identical inputs -> identical bits
+    ov = orc.eval_pass(Cc, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, want_plan=want_plan,
+                       q=q)
+    # grid-rounded row maxima of identical fma values: identical bits
     np.testing.assert_array_equal(host(gv["M"]), ov.M)
     np.testing.assert_allclose(host(gv["S"]), ov.S, rtol=1e-13)
     np.testing.assert_allclose(host(gv["lse"]), ov.lse, rtol=1e-15, atol=1e-13)
@@ -114,11 +121,21 @@ def test_eval_full_size_10k(ib, ctx):
     check_eval(ib, ctx, inst, r, s, k, gamma, want_plan=False)
 
 
+def test_center_quantum_matches_oracle(ib, ctx):
+    for k in (0, 7, 300):
+        inst = W.gmm_points(257, 3, m=190)
+        gamma = W.random_dual(257, k, 0.03)
+        s = np.log(inst.b) + 0.37 * k
+        q_o = orc.center_quantum(inst.C, s, gamma, inst.eta, k)
+        q_g = ib.center_quantum(ctx, problem(ib, inst), ib.Center(k, None, dev(s), 1.0), dev(gamma))
+        assert q_g == q_o
+
+
 def test_eval_deterministic(ib, ctx):
     inst = W.uniform_points(700, 3, m=900)
     pr = problem(ib, inst)
-    ctr = ib.Center.initial(pr)
     gamma = dev(W.random_dual(700, 1, 0.01))
+    ctr = ib.Center.initial(ctx, pr, gamma)
     a = ib.subproblem_eval(ctx, pr, ctr, gamma)
     b = ib.subproblem_eval(ctx, pr, ctr, gamma)
     for key in ("M", "S", "c", "g"):
@@ -134,14 +151,16 @@ def test_eval_deterministic(ib, ctx):
 def test_trial(ib, ctx, t, k):
     inst = W.gmm_points(513, 12, m=301)
     r, s, kk, gamma = outer_state(inst, k)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk)
+    ctr, q = center(ib, inst, r, s, kk, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk, q=q)
     Delta = W.random_dual(513, 44, 0.02)
     pr = problem(ib, inst)
-    ctr = ib.Center(kk, dev(r), dev(s))
     gt = ib.trial(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(Delta), t)
     dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, Delta, t,
-                                        s=s, k=kk)
+                                        s=s, k=kk, q=q)
     assert abs(gt["dL"] - dL) <= 1e-12 * abs(dL) + 1e-17 * t
+    # new shifts are grid values computed from the same inputs
+    np.testing.assert_allclose(host(gt["M"]), Mn, rtol=0, atol=q)
     np.testing.assert_allclose(host(gt["M"]) + np.log(host(gt["S"])), Mn + np.log(Sn), rtol=1e-15,
                                atol=1e-12)
     np.testing.assert_allclose(host(gt["c"]), cn, rtol=1e-12)
@@ -154,11 +173,13 @@ def test_trial_big_step(ib, ctx):
     eta = 1e-3
     inst = W.Instance(inst.C, inst.a, inst.b, eta, "big")
     r, s, k, gamma = np.log(inst.a), np.log(inst.b), 0, np.zeros(300)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma)
+    ctr, q = center(ib, inst, r, s, 0, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, q=q)
     Delta = W.random_dual(300, 7, 0.5)
     pr = problem(ib, inst)
-    gt = ib.trial(ctx, pr, ib.Center(0, dev(r), dev(s)), dev(gamma), dev(ev.M), dev(Delta), 1.0)
-    dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, 1.0, s=s)
+    gt = ib.trial(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(Delta), 1.0)
+    dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, 1.0, s=s,
+                                        q=q)
     assert abs(gt["dL"] - dL) <= 1e-12 * abs(dL)
     np.testing.assert_allclose(host(gt["c"]), cn, rtol=1e-11, atol=1e-300)
 
@@ -191,14 +212,15 @@ def compare_patterns(gcsr, ocsr, P, rho, istar):
 def test_sparsify_and_hvp(ib, ctx, rho_rule, k):
     inst = W.gmm_points(600, 8, m=420)
     r, s, kk, gamma = outer_state(inst, k)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk, want_plan=True)
+    ctr, q = center(ib, inst, r, s, kk, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk, want_plan=True,
+                       q=q)
     P = ev.plan / inst.a[:, None]
     rho = {"zero": 0.0, "paper": inst.eta * np.linalg.norm(ev.g) / P.size,
            "1e-6": 1e-6, "1e-4": 1e-4}[rho_rule]
     pr = problem(ib, inst)
-    ctr = ib.Center(kk, dev(r), dev(s))
     gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
-    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=kk)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=kk, q=q)
     istar = int(np.argmax(inst.a))
     same, d = compare_patterns(gcsr, ocsr, P, rho, istar)
     assert same, "no entry of these inputs lies within the threshold band"
@@ -216,9 +238,9 @@ def test_hvp_determinism_and_dense_row(ib, ctx):
     """Row i* is dense (n entries); repeated products are bitwise identical."""
     inst = W.gmm_points(2000, 4, m=1500)
     r, s, k, gamma = outer_state(inst, 0)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
     pr = problem(ib, inst)
-    ctr = ib.Center(k, dev(r), dev(s))
     gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), 1e-7)
     row_ptr, col, val, d = (host(x) for x in gcsr.export())
     i = gcsr.istar
@@ -237,13 +259,13 @@ def test_hvp_determinism_and_dense_row(ib, ctx):
 def test_cg(ib, ctx):
     inst = W.gmm_points(500, 13, m=380)
     r, s, k, gamma = outer_state(inst, 3)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
     gn = np.linalg.norm(ev.g)
     rho = inst.eta * gn / (380 * 500)
     pr = problem(ib, inst)
-    ctr = ib.Center(k, dev(r), dev(s))
     gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
-    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
     shift = max(gn, 1e-2)
     tol = 1e-12 * gn
     xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
@@ -264,12 +286,12 @@ def test_cg(ib, ctx):
 def test_stop(ib, ctx, k):
     inst = W.gmm_points(333, 6, m=250)
     r, s, kk, gamma = outer_state(inst, k)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk)
+    ctr, q = center(ib, inst, r, s, kk, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk, q=q)
     pr = problem(ib, inst)
-    ctr = ib.Center(kk, dev(r), dev(s))
     gs = ib.stop(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), want_xhat=True)
     os_ = orc.stop_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, ev.S, s=s, k=kk,
-                        want_xhat=True)
+                        want_xhat=True, q=q)
     np.testing.assert_allclose(host(gs["xhat"]), os_["xhat"], rtol=1e-10, atol=1e-15)
     for key, rtol, atol in [("primal", 1e-12, 0), ("dual", 1e-12, 1e-16), ("cx", 1e-12, 0),
                             ("dual_gamma", 1e-12, 1e-16), ("dual_psi", 1e-12, 1e-16),
@@ -353,7 +375,7 @@ def test_solve_constant_cost(ib, ctx):
 def test_invalid_arguments(ib, ctx):
     inst = W.uniform_points(16, 0)
     pr = problem(ib, inst)
-    ctr = ib.Center.initial(pr)
+    ctr = ib.Center.initial(ctx, pr)
     g = torch.zeros(16, dtype=torch.float64, device="cuda")
     bad = ib.Problem(pr.C, pr.a, pr.b, -1.0)
     with pytest.raises(ib.IBSNError) as e:
@@ -368,8 +390,11 @@ def test_invalid_arguments(ib, ctx):
                                                                             dtype=torch.float64,
                                                                             device="cuda"), 0.01),
                            ib.Center(0, None, torch.zeros(20481, dtype=torch.float64,
-                                                          device="cuda")),
+                                                          device="cuda"), 1.0),
                            torch.zeros(20481, dtype=torch.float64, device="cuda"), want_obj=False)
     assert e.value.code == -5
     with pytest.raises(ValueError):   # host tensor rejected by the binding
         ib.subproblem_eval(ctx, pr, ctr, torch.zeros(16, dtype=torch.float64))
+    with pytest.raises(ib.IBSNError) as e:   # quantum not a power of two
+        ib.subproblem_eval(ctx, pr, ib.Center(0, ctr.r, ctr.s, 3e-12), g)
+    assert e.value.code == -1
