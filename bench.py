@@ -1,0 +1,157 @@
+#!/usr/bin/env python
+"""Benchmark of the IBSN hot path on one MI355X.
+
+Workload: m = n = 10^4 points uniform in [0,1]^2 on both sides (seed 1000), squared
+Euclidean cost divided by its maximum (800 MB FP64), uniform weights, eta = 1e-2.
+
+A step is one outer iteration of Algorithm 2 (every row of the hot path: outer update
+of the implicit centre, Sinkhorn warm-up when the gradient is large, sparsified
+Newton-CG with Armijo steps, the inexact stop test and the certificate).  Warm-up
+steps run from X^0 = a b^T untimed; the timed steps resume from that state.
+
+JSON line: `value` is the whole-job streaming throughput of the timed steps, i.e.
+the algorithmic bytes of every dense m x n pass the steps made divided by their wall
+time (inputs resident in HBM).  `roofline` reports the row-LSE (eval) kernel: its
+algorithmic bytes per launch over its average launch time, measured with HIP events
+recorded on the library's stream around each launch.  `cpu_baseline` times the CPU
+oracle's eval pass on the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("time to 1e-8 OT gap at n=10k (plain vs warm-start+FP32); LSE-pass HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(m: int, n: int) -> float:
+    """Algorithmic bytes of one dense pass: the FP64 cost once plus the m- and n-vectors
+    it reads or writes (w, a, M, S, partial-sum inputs: 4 m-vectors and 5 n-vectors)."""
+    return 8.0 * m * n + 8.0 * (4 * m + 5 * n)
+
+
+def cpu_baseline(inst, seconds: float):
+    """The oracle's eval pass (eqs. 5-8) on the same 10^4 workload, repeated for about
+    `seconds` of CPU time; GB/s in the same algorithmic bytes as `value`."""
+    import numpy as np
+
+    import oracle
+
+    m, n = inst.C.shape
+    gamma = np.zeros(n)
+    s = np.log(inst.b)
+    q = oracle.center_quantum(inst.C, s, gamma, inst.eta, 0)
+    t0 = time.perf_counter()
+    passes = 0
+    while True:
+        oracle.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, s=s, q=q)
+        passes += 1
+        if time.perf_counter() - t0 >= seconds or passes >= 50:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": passes * pass_bytes(m, n) / dt / 1e9, "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{passes} oracle eval passes (row LSE, P^T a, objective) at m=n={n}, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
+              "build (see the design notes for how it would shard); run with --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2603_07156_amd import ibsn, workloads
+
+    dev = torch.device("cuda", 0)
+    inst = workloads.uniform_points(args.n, args.seed)
+    m, n = inst.C.shape
+    ctx = ibsn.Context(0)
+    prob = ibsn.Problem(torch.from_numpy(inst.C).to(dev), torch.from_numpy(inst.a).to(dev),
+                        torch.from_numpy(inst.b).to(dev), inst.eta)
+    torch.cuda.synchronize()
+
+    # warm-up steps from X^0 (untimed)
+    opt = ibsn.default_options(max_outer=max(args.warmup, 1), gap_tol=0.0, marg_tol=0.0)
+    w = ibsn.solve(ctx, prob, opt)
+    state = (w["r"], w["s"], w["k"])
+    gamma = w["gamma"]
+    torch.cuda.synchronize()
+
+    # timed steps
+    opt = ibsn.default_options(max_outer=args.steps, gap_tol=0.0, marg_tol=0.0)
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ibsn.solve(ctx, prob, opt, gamma0=gamma, state=state)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.kernel_timing(False)
+    rep = res["report"]
+    steps = int(rep["outer"])
+
+    pb = pass_bytes(m, n)
+    value = rep["passes"] * pb / dt / 1e9
+    eval_ms, eval_n = kt["eval"]
+    eval_avg_ms = eval_ms / max(eval_n, 1)
+    achieved = pb / (eval_avg_ms * 1e-3) / 1e9 if eval_n else None
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / max(steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uniform points in [0,1]^2, m=n={n}, squared-Euclidean cost / max, "
+                               f"uniform weights, eta={inst.eta}, seed {args.seed}; a step is one "
+                               f"IBSN outer iteration (k = {args.warmup}..{args.warmup + steps - 1})",
+                   "m": m, "n": n, "eta": inst.eta},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "row-LSE eval pass (k_eval)", "bytes_per_launch": pb,
+                     "avg_launch_ms": eval_avg_ms, "launches": eval_n},
+        "solve": {"outer_per_s": steps / dt, "dense_passes": rep["passes"],
+                  "newton": rep["newton"], "cg": rep["cg"], "sinkhorn": rep["sinkhorn"],
+                  "backtracks": rep["backtracks"], "rel_gap_end": rep["rel_gap"],
+                  "grad_norm_end": rep["grad_norm"], "k_end": res["k"]},
+        "kernel_ms": {k: {"total": v[0], "launches": v[1],
+                          "avg": (v[0] / v[1]) if v[1] else None} for k, v in kt.items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -171,6 +171,26 @@ int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
               const double *gamma, const double *M, const double *S, double *out_host,
               double *xhat);
 
+/* Kernel timing with HIP events recorded on the context's stream around the main
+   kernel of each phase.  ibsn_kernel_timing(ctx, 1) enables it and clears the totals;
+   0 disables it.  ibsn_kernel_times_get() (host out, synchronises) returns, per phase,
+   the summed kernel time in milliseconds and the number of launches timed. */
+enum { IBSN_KT_EVAL = 0,      /* row LSE pass (eval)                                   */
+       IBSN_KT_TRIAL,         /* Armijo trial pass                                     */
+       IBSN_KT_SPARSIFY,      /* Algorithm 1 pass                                      */
+       IBSN_KT_CSC,           /* transpose of the sparsified factor                    */
+       IBSN_KT_STOP1,         /* stop test pass 1                                      */
+       IBSN_KT_STOP2,         /* stop test pass 2                                      */
+       IBSN_KT_CG,            /* one CG iteration (row gather, column gather, update)  */
+       IBSN_KT_COLRED,        /* column partial reduction                              */
+       IBSN_KT_N };
+typedef struct {
+    double ms[IBSN_KT_N];
+    int64_t count[IBSN_KT_N];
+} ibsn_kernel_times;
+int ibsn_kernel_timing(ibsn_ctx *ctx, int enable);
+int ibsn_kernel_times_get(ibsn_ctx *ctx, ibsn_kernel_times *out);
+
 /* Solver options; ibsn_default_options() fills the paper's values where it gives
    them (sigma, beta: Algorithm 2 input; Sinkhorn tolerance and mu_k schedule:
    Section 5 "Setup"; 300 outer iterations: Table 1). */

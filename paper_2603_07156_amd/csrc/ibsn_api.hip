@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 using namespace ibsn;
 
@@ -49,6 +50,18 @@ struct ibsn_ctx {
     DevBuf stopout, tauv, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_partial, cg_scal, cg_counter;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     ibsn_csr *solver_csr = nullptr;
+    // solver state (grow-only, reused across ibsn_solve calls)
+    DevBuf sv_r, sv_s, sv_g, sv_M, sv_S, sv_Mt, sv_St, sv_ct, sv_gt, sv_D, sv_c, sv_gv;
+    // kernel timing (HIP events around the main kernel of each phase)
+    bool timing = false;
+    double kt_ms[IBSN_KT_N] = {0};
+    int64_t kt_count[IBSN_KT_N] = {0};
+    std::vector<hipEvent_t> ev_free;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
 };
 
 namespace {
@@ -224,6 +237,65 @@ int read_scal(ibsn_ctx *ctx, int count = SC_NSLOT)
     return IBSN_OK;
 }
 
+// kernel timing: tic() records a start event, toc() an end event for phase `kind`
+hipEvent_t take_event(ibsn_ctx *ctx)
+{
+    if (!ctx->ev_free.empty()) {
+        hipEvent_t e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+void drain_events(ibsn_ctx *ctx)
+{
+    if (ctx->pending.empty())
+        return;
+    (void)hipEventSynchronize(ctx->pending.back().b);
+    for (auto &p : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->kt_ms[p.kind] += ms;
+            ctx->kt_count[p.kind] += 1;
+        }
+        ctx->ev_free.push_back(p.a);
+        ctx->ev_free.push_back(p.b);
+    }
+    ctx->pending.clear();
+}
+
+struct KTimer {
+    ibsn_ctx *ctx;
+    int kind;
+    hipEvent_t a = nullptr;
+    KTimer(ibsn_ctx *c, int k) : ctx(c), kind(k)
+    {
+        if (ctx->timing) {
+            a = take_event(ctx);
+            if (a)
+                (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~KTimer()
+    {
+        if (ctx->timing && a) {
+            hipEvent_t b = take_event(ctx);
+            if (b) {
+                (void)hipEventRecord(b, ctx->stream);
+                ctx->pending.push_back({kind, a, b});
+                if (ctx->pending.size() >= 512)
+                    drain_events(ctx);
+            } else {
+                ctx->ev_free.push_back(a);
+            }
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------------
 // pass-level building blocks (also used by the solver)
 // ---------------------------------------------------------------------------------
@@ -235,9 +307,15 @@ int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
 {
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q);
-    CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart), P<double>(ctx->rowpart),
-                    st));
-    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, c, p->b, g, st));
+    {
+        KTimer kt(ctx, IBSN_KT_EVAL);
+        CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart),
+                        P<double>(ctx->rowpart), st));
+    }
+    {
+        KTimer kt(ctx, IBSN_KT_COLRED);
+        CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, c, p->b, g, st));
+    }
     CKH(sk_gnorms(p->n, g, P<double>(ctx->scal), st));
     if (r && gamma) {
         CKH(sk_dot_slot(p->n, p->b, gamma, SC_BG, P<double>(ctx->scal), st));
@@ -258,9 +336,15 @@ int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k
     double *scal = P<double>(ctx->scal);
     CKH(sk_trial_prep(p->n, t, p->eta, q, Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
                       scal, st));
-    CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
-                     P<double>(ctx->rowpart), st));
-    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, cn, p->b, gn, st));
+    {
+        KTimer kt(ctx, IBSN_KT_TRIAL);
+        CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
+                         P<double>(ctx->rowpart), st));
+    }
+    {
+        KTimer kt(ctx, IBSN_KT_COLRED);
+        CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, cn, p->b, gn, st));
+    }
     CKH(sk_gnorms(p->n, gn, scal, st));
     // dL = eta * sum_i a_i delta_i - eta * b^T tau
     CKH(sk_sum_parts(rp.grid, 1, 0, P<double>(ctx->rowpart), p->eta, -p->eta, SC_TB, SC_DL, 0,
@@ -277,8 +361,11 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     double *scal = P<double>(ctx->scal);
     double *colX = P<double>(ctx->cvec);   // reuse as column sums of X
     double *colF = P<double>(ctx->colv);
-    CKH(launch_stop1(rp, d, M, S, P<double>(ctx->zv), P<double>(ctx->colpart),
-                     P<double>(ctx->colpart2), P<double>(ctx->rowpart2), st));
+    {
+        KTimer kt(ctx, IBSN_KT_STOP1);
+        CKH(launch_stop1(rp, d, M, S, P<double>(ctx->zv), P<double>(ctx->colpart),
+                         P<double>(ctx->colpart2), P<double>(ctx->rowpart2), st));
+    }
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, colX, nullptr, nullptr, st));
     CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, p->n, colF, nullptr, nullptr, st));
     CKH(sk_stop_prep(p->n, d.sigma, p->b, d.w, gamma, colX, colF, P<double>(ctx->yv),
@@ -292,7 +379,10 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     v.ec = P<double>(ctx->ecv);
     v.z = P<double>(ctx->zv);
     v.er1 = ctx->host_scal[SC_ER1];
-    CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));
+    {
+        KTimer kt(ctx, IBSN_KT_STOP2);
+        CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));
+    }
     CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), p->m, p->a, p->n, p->b,
                       P<double>(ctx->rowpart2), rp.grid, scal, P<double>(ctx->stopout), st));
     return IBSN_OK;
@@ -332,8 +422,11 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
 {
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q);
-    CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
-                        P<double>(c->val), P<int32_t>(c->len), P<double>(ctx->colpart), st));
+    {
+        KTimer kt(ctx, IBSN_KT_SPARSIFY);
+        CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
+                            P<double>(c->val), P<int32_t>(c->len), P<double>(ctx->colpart), st));
+    }
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(c->d), nullptr,
                          nullptr, st));
     CscWork cw;
@@ -343,8 +436,11 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     cw.cval = P<double>(c->cval);
     cw.blkcnt = P<int32_t>(c->blkcnt);
     cw.rb = c->rb;
-    CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), P<double>(c->val), P<int32_t>(c->len), cw,
-                         P<int64_t>(c->nnz_dev), st));
+    {
+        KTimer kt(ctx, IBSN_KT_CSC);
+        CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), P<double>(c->val),
+                             P<int32_t>(c->len), cw, P<int64_t>(c->nnz_dev), st));
+    }
     int64_t hv[2];
     CKH(hipMemcpyAsync(hv, c->nnz_dev.p, 8, hipMemcpyDeviceToHost, st));
     CKH(hipMemcpyAsync(hv + 1, c->istar_dev.p, 4, hipMemcpyDeviceToHost, st));
@@ -412,12 +508,14 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     int launched = 0, chunk = 8;
     double hs[CG_NSLOT];
     for (;;) {
-        for (int q = 0; q < chunk && launched < maxit; ++q, ++launched)
+        for (int q = 0; q < chunk && launched < maxit; ++q, ++launched) {
+            KTimer kt(ctx, IBSN_KT_CG);
             CKH(launch_cg_iteration(c->m, c->n, (const int32_t *)c->col.p, (const double *)c->val.p,
                                     (const int32_t *)c->len.p, (const int *)c->istar_dev.p,
                                     (const int64_t *)c->colptr.p, (const int32_t *)c->rowidx.p,
                                     (const double *)c->cval.p, (const double *)c->d.p, a, eta,
                                     shift, s, lr, lc, st));
+        }
         CKH(hipMemcpyAsync(hs, s.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
         CKH(hipStreamSynchronize(st));
         if (hs[CG_DONE] != 0.0 || launched >= maxit)
@@ -485,12 +583,44 @@ void ibsn_destroy(ibsn_ctx *ctx)
                       &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv, &ctx->cg_x, &ctx->cg_r,
                       &ctx->cg_p,
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_partial, &ctx->cg_scal,
-                      &ctx->cg_counter};
+                      &ctx->cg_counter, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
+                      &ctx->sv_S, &ctx->sv_Mt, &ctx->sv_St, &ctx->sv_ct, &ctx->sv_gt, &ctx->sv_D,
+                      &ctx->sv_c, &ctx->sv_gv};
     for (DevBuf *b : bufs)
         release(*b);
     if (ctx->host_scal)
         (void)hipHostFree(ctx->host_scal);
+    drain_events(ctx);
+    for (hipEvent_t e : ctx->ev_free)
+        (void)hipEventDestroy(e);
     delete ctx;
+}
+
+int ibsn_kernel_timing(ibsn_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    CKH(hipSetDevice(ctx->device));
+    drain_events(ctx);
+    ctx->timing = enable != 0;
+    for (int k = 0; k < IBSN_KT_N; ++k) {
+        ctx->kt_ms[k] = 0.0;
+        ctx->kt_count[k] = 0;
+    }
+    return IBSN_OK;
+}
+
+int ibsn_kernel_times_get(ibsn_ctx *ctx, ibsn_kernel_times *out)
+{
+    if (!ctx || !out)
+        return IBSN_ERR_INVALID_ARG;
+    CKH(hipSetDevice(ctx->device));
+    drain_events(ctx);
+    for (int k = 0; k < IBSN_KT_N; ++k) {
+        out->ms[k] = ctx->kt_ms[k];
+        out->count[k] = ctx->kt_count[k];
+    }
+    return IBSN_OK;
 }
 
 const char *ibsn_last_error(const ibsn_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -764,13 +894,11 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     CKI(ensure_ws(ctx, prob, rp));
     const int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)std::min<int64_t>(n, 1000);
 
-    // solver state buffers
-    DevBuf rB, sB, gB, MB, SB, MtB, StB, ctB, gtB, DB, cB, gvB;
-    auto cleanup = [&]() {
-        DevBuf *b[] = {&rB, &sB, &gB, &MB, &SB, &MtB, &StB, &ctB, &gtB, &DB, &cB, &gvB};
-        for (DevBuf *x : b)
-            release(*x);
-    };
+    // solver state buffers (context-owned, grow-only: no allocation once warm)
+    DevBuf &rB = ctx->sv_r, &sB = ctx->sv_s, &gB = ctx->sv_g, &MB = ctx->sv_M, &SB = ctx->sv_S,
+           &MtB = ctx->sv_Mt, &StB = ctx->sv_St, &ctB = ctx->sv_ct, &gtB = ctx->sv_gt,
+           &DB = ctx->sv_D, &cB = ctx->sv_c, &gvB = ctx->sv_gv;
+    auto cleanup = [&]() {};
     int rc = IBSN_OK;
 #define CKS(call)                  \
     do {                           \

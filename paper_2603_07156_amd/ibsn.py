@@ -70,11 +70,18 @@ class Report(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+KT_NAMES = ("eval", "trial", "sparsify", "csc", "stop1", "stop2", "cg", "colreduce")
+
+
+class _KernelTimes(ct.Structure):
+    _fields_ = [("ms", ct.c_double * len(KT_NAMES)), ("count", ct.c_int64 * len(KT_NAMES))]
+
+
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
            "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
-           "ibsn_default_options", "ibsn_solve")
+           "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get")
 
 
 def load():
@@ -109,6 +116,8 @@ def load():
     L.ibsn_default_options.restype = None
     L.ibsn_solve.argtypes = [vp, P, ct.POINTER(Options), vp, vp, vp, ct.POINTER(i64), vp,
                              ct.POINTER(Report)]
+    L.ibsn_kernel_timing.argtypes = [vp, ct.c_int]
+    L.ibsn_kernel_times_get.argtypes = [vp, ct.POINTER(_KernelTimes)]
     for name in EXPORTS:
         if not hasattr(L, name):
             raise ImportError(f"{LIB_PATH} does not export {name}")
@@ -155,6 +164,16 @@ class Context:
     @property
     def num_cus(self):
         return load().ibsn_num_cus(self.h)
+
+    def kernel_timing(self, enable: bool = True):
+        """ibsn_kernel_timing: enable (and clear) or disable HIP-event kernel timing."""
+        self.check(load().ibsn_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """ibsn_kernel_times_get: {phase: (total ms, launches)}."""
+        kt = _KernelTimes()
+        self.check(load().ibsn_kernel_times_get(self.h, ct.byref(kt)))
+        return {name: (kt.ms[i], kt.count[i]) for i, name in enumerate(KT_NAMES)}
 
     def close(self):
         if getattr(self, "h", None):
