@@ -181,7 +181,7 @@ enum { IBSN_KT_EVAL = 0,      /* row LSE pass (eval)                            
        IBSN_KT_CSC,           /* transpose of the sparsified factor                    */
        IBSN_KT_STOP1,         /* stop test pass 1                                      */
        IBSN_KT_STOP2,         /* stop test pass 2                                      */
-       IBSN_KT_CG,            /* one CG iteration (row gather, column gather, update)  */
+       IBSN_KT_CG,            /* one CG solve, host polling included (all iterations)  */
        IBSN_KT_COLRED,        /* column partial reduction                              */
        IBSN_KT_N };
 typedef struct {

@@ -37,6 +37,7 @@ struct ibsn_csr {
     int64_t istar = -1;    // host copy
     DevBuf col, val, len, colptr, colcnt, rowidx, cval, blkcnt, d, istar_dev, nnz_dev;
     int rb = 0;
+    bool abs64 = false;
 };
 
 struct ibsn_ctx {
@@ -47,7 +48,7 @@ struct ibsn_ctx {
     std::string err;
     // workspace
     DevBuf w, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
-    DevBuf stopout, tauv, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_partial, cg_scal, cg_counter;
+    DevBuf stopout, tauv, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     ibsn_csr *solver_csr = nullptr;
     // solver state (grow-only, reused across ibsn_solve calls)
@@ -393,7 +394,12 @@ int csr_alloc(ibsn_ctx *ctx, ibsn_csr *c, int64_t m, int64_t n)
     const size_t mn = (size_t)m * (size_t)n;
     c->m = m;
     c->n = n;
-    c->rb = (int)std::min<int64_t>(m, 256);
+    // row blocks of the transpose: two per CU; the fill keeps a cursor per column in LDS,
+    // as int64 positions when they fit beside the row lengths, else as int32 ranks
+    c->rb = (int)std::min<int64_t>(m, 2 * (int64_t)ctx->num_cus);
+    c->abs64 = csc_fill_lds(m, n, c->rb, true) <= ctx->max_lds;
+    if (!c->abs64 && csc_fill_lds(m, n, c->rb, false) > ctx->max_lds)
+        c->rb = (int)std::min<int64_t>(m, std::max<int64_t>(c->rb, (m + 1023) / 1024));
     CKI(ensure(ctx, c->col, mn * 4));
     CKI(ensure(ctx, c->val, mn * 8));
     CKI(ensure(ctx, c->len, (size_t)m * 4));
@@ -436,10 +442,12 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     cw.cval = P<double>(c->cval);
     cw.blkcnt = P<int32_t>(c->blkcnt);
     cw.rb = c->rb;
+    cw.abs64 = c->abs64;
     {
         KTimer kt(ctx, IBSN_KT_CSC);
         CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), P<double>(c->val),
-                             P<int32_t>(c->len), cw, P<int64_t>(c->nnz_dev), st));
+                             P<int32_t>(c->len), P<int>(c->istar_dev), cw,
+                             P<int64_t>(c->nnz_dev), st));
     }
     int64_t hv[2];
     CKH(hipMemcpyAsync(hv, c->nnz_dev.p, 8, hipMemcpyDeviceToHost, st));
@@ -450,25 +458,20 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     return IBSN_OK;
 }
 
-int lanes_for(int64_t count, int64_t groups)
+CsrView csr_view(const ibsn_csr *c)
 {
-    const double avg = groups > 0 ? (double)count / (double)groups : 0.0;
-    return avg >= 96.0 ? 64 : (avg >= 12.0 ? 16 : 4);
-}
-
-int run_hvp(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
-            const double *v, double *y, double *au)
-{
-    hipStream_t st = ctx->stream;
-    const int lr = lanes_for(c->nnz - c->n, c->m > 1 ? c->m - 1 : 1);
-    const int lc = lanes_for(c->nnz, c->n);
-    CKH(launch_row_gather(c->m, c->n, (const int32_t *)c->col.p, (const double *)c->val.p,
-                          (const int32_t *)c->len.p, (const int *)c->istar_dev.p, a, v, au, lr,
-                          st));
-    CKH(launch_col_gather(c->n, (const int64_t *)c->colptr.p, (const int32_t *)c->rowidx.p,
-                          (const double *)c->cval.p, au, (const double *)c->d.p, v, eta, shift, y,
-                          lc, st));
-    return IBSN_OK;
+    CsrView v;
+    v.m = c->m;
+    v.n = c->n;
+    v.col = (const int32_t *)c->col.p;
+    v.val = (const double *)c->val.p;
+    v.len = (const int32_t *)c->len.p;
+    v.istar = (const int *)c->istar_dev.p;
+    v.colptr = (const int64_t *)c->colptr.p;
+    v.rowidx = (const int32_t *)c->rowidx.p;
+    v.cval = (const double *)c->cval.p;
+    v.d = (const double *)c->d.p;
+    return v;
 }
 
 int ensure_cg(ibsn_ctx *ctx, int64_t m, int64_t n)
@@ -478,16 +481,26 @@ int ensure_cg(ibsn_ctx *ctx, int64_t m, int64_t n)
     CKI(ensure(ctx, ctx->cg_p, n * 8));
     CKI(ensure(ctx, ctx->cg_Ap, n * 8));
     CKI(ensure(ctx, ctx->cg_au, m * 8));
-    CKI(ensure(ctx, ctx->cg_partial, ((size_t)n * 64 / 256 + 260) * 8));
-    CKI(ensure(ctx, ctx->cg_scal, 16 * 8));
-    const bool fresh = ctx->cg_counter.p == nullptr;
-    CKI(ensure(ctx, ctx->cg_counter, 64));
-    if (fresh)
-        CKH(hipMemsetAsync(ctx->cg_counter.p, 0, 64, ctx->stream));
+    CKI(ensure(ctx, ctx->cg_star, CG_MAX_STAR * 8));
+    CKI(ensure(ctx, ctx->cg_pap, CG_MAX_COLGROUPS * 8));
+    CKI(ensure(ctx, ctx->cg_rr, CG_MAX_UPDGROUPS * 8));
+    CKI(ensure(ctx, ctx->cg_scal, (CG_NSLOT + 5) * 8));
+    return IBSN_OK;
+}
+
+int run_hvp(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
+            const double *v, double *y)
+{
+    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus);
+    CKH(launch_hvp(g, csr_view(c), a, eta, shift, v, y, P<double>(ctx->cg_au),
+                   P<double>(ctx->cg_star), ctx->stream));
     return IBSN_OK;
 }
 
 // CG for (H_rho + shift I) x = rhs from 0; result in ctx->cg_x; *iters on host.
+// Iterations are enqueued in chunks; after each chunk one small kernel records the
+// state and the host reads it.  The next chunk's length is the number of iterations the
+// residual's observed rate of decrease predicts are still needed.
 int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
            const double *rhs, double tol, int maxit, int *iters)
 {
@@ -499,30 +512,40 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     s.p = P<double>(ctx->cg_p);
     s.Ap = P<double>(ctx->cg_Ap);
     s.au = P<double>(ctx->cg_au);
-    s.partial = P<double>(ctx->cg_partial);
+    s.star_part = P<double>(ctx->cg_star);
+    s.pap_part = P<double>(ctx->cg_pap);
+    s.rr_part = P<double>(ctx->cg_rr);
     s.scal = P<double>(ctx->cg_scal);
-    s.counter = P<unsigned>(ctx->cg_counter);
+    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus);
+    const CsrView cv = csr_view(c);
+    KTimer kt(ctx, IBSN_KT_CG);
     CKH(launch_cg_init(c->n, rhs, tol, maxit, s, st));
-    const int lr = lanes_for(c->nnz - c->n, c->m > 1 ? c->m - 1 : 1);
-    const int lc = lanes_for(c->nnz, c->n);
     int launched = 0, chunk = 8;
     double hs[CG_NSLOT];
+    double last_res = -1.0;
+    int last_at = 0;
     for (;;) {
-        for (int q = 0; q < chunk && launched < maxit; ++q, ++launched) {
-            KTimer kt(ctx, IBSN_KT_CG);
-            CKH(launch_cg_iteration(c->m, c->n, (const int32_t *)c->col.p, (const double *)c->val.p,
-                                    (const int32_t *)c->len.p, (const int *)c->istar_dev.p,
-                                    (const int64_t *)c->colptr.p, (const int32_t *)c->rowidx.p,
-                                    (const double *)c->cval.p, (const double *)c->d.p, a, eta,
-                                    shift, s, lr, lc, st));
-        }
+        for (int q = 0; q < chunk && launched < maxit; ++q, ++launched)
+            CKH(launch_cg_iteration(g, cv, a, eta, shift, s, launched, st));
+        CKH(launch_cg_check(g, s, launched, st));
         CKH(hipMemcpyAsync(hs, s.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
         CKH(hipStreamSynchronize(st));
-        if (hs[CG_DONE] != 0.0 || launched >= maxit)
+        const int slot = launched & 1;
+        if (hs[CG_DONE0 + slot] != 0.0 || launched >= maxit) {
+            *iters = (int)hs[CG_IT0 + slot];
             break;
-        chunk = std::min(chunk * 2, 64);
+        }
+        const double res = std::sqrt(hs[CG_RR0 + slot]);
+        int next = 8;
+        if (last_res > 0.0 && res < last_res && res > tol && tol > 0.0) {
+            const double rate = std::log(res / last_res) / (double)(launched - last_at);
+            const double need = std::log(tol / res) / rate;
+            next = (int)std::ceil(need) + 1;
+        }
+        chunk = std::max(2, std::min(next, 64));
+        last_res = res;
+        last_at = launched;
     }
-    *iters = (int)hs[CG_IT];
     return IBSN_OK;
 }
 
@@ -582,8 +605,8 @@ void ibsn_destroy(ibsn_ctx *ctx)
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
                       &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv, &ctx->cg_x, &ctx->cg_r,
                       &ctx->cg_p,
-                      &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_partial, &ctx->cg_scal,
-                      &ctx->cg_counter, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
+                      &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_star, &ctx->cg_pap, &ctx->cg_rr,
+                      &ctx->cg_scal, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
                       &ctx->sv_S, &ctx->sv_Mt, &ctx->sv_St, &ctx->sv_ct, &ctx->sv_gt, &ctx->sv_D,
                       &ctx->sv_c, &ctx->sv_gv};
     for (DevBuf *b : bufs)
@@ -792,7 +815,8 @@ int ibsn_csr_export(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *row_ptr, int32_
         return fail(ctx, IBSN_ERR_INVALID_ARG, "all export buffers are required");
     CKH(hipSetDevice(ctx->device));
     CKH(launch_export_csr(csr->m, csr->n, (const int32_t *)csr->col.p, (const double *)csr->val.p,
-                          (const int32_t *)csr->len.p, row_ptr, col, val, ctx->stream));
+                          (const int32_t *)csr->len.p, row_ptr, col, val, csr->nnz,
+                          ctx->stream));
     CKH(hipMemcpyAsync(d, csr->d.p, sizeof(double) * csr->n, hipMemcpyDeviceToDevice,
                        ctx->stream));
     return IBSN_OK;
@@ -822,7 +846,7 @@ int ibsn_hvp(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, do
         return fail(ctx, IBSN_ERR_INVALID_ARG, "eta must be > 0 and shift finite");
     CKH(hipSetDevice(ctx->device));
     CKI(ensure_cg(ctx, csr->m, csr->n));
-    return run_hvp(ctx, csr, a, eta, shift, v, y, P<double>(ctx->cg_au));
+    return run_hvp(ctx, csr, a, eta, shift, v, y);
 }
 
 int ibsn_cg(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,

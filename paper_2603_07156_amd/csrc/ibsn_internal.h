@@ -94,39 +94,67 @@ struct CscWork {
     double *cval;        // capacity m*n
     int32_t *blkcnt;     // rb * n
     int rb;              // row blocks used for the deterministic transpose
+    bool abs64;          // fill cursor holds int64 positions (n*8 bytes of LDS)
 };
+// LDS bytes of the fill kernel (cursor array plus the block's row lengths)
+size_t csc_fill_lds(int64_t m, int64_t n, int rb, bool abs64);
+// transpose of the slotted rows without the dense row istar (device scalar)
 hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
-                            const int32_t *len, CscWork &w, int64_t *nnz_dev, hipStream_t st);
+                            const int32_t *len, const int *istar, CscWork &w, int64_t *nnz_dev,
+                            hipStream_t st);
 
-// HVP pieces: au_i = a_i * sum_{e} val * v[col]  (slotted CSR rows)
-hipError_t launch_row_gather(int64_t m, int64_t n, const int32_t *col, const double *val,
-                             const int32_t *len, const int *istar, const double *a, const double *v,
-                             double *au, int lpc, hipStream_t st);
-// y_j = (d_j v_j - sum_{CSC col j} cval * au[row]) / eta + shift * v_j
-hipError_t launch_col_gather(int64_t n, const int64_t *colptr, const int32_t *rowidx,
-                             const double *cval, const double *au, const double *d,
-                             const double *v, double eta, double shift, double *y, int lpc,
-                             hipStream_t st);
+// Device view of a sparsified factor: slotted rows plus the CSC of the rows != istar.
+struct CsrView {
+    int64_t m, n;
+    const int32_t *col;
+    const double *val;
+    const int32_t *len;
+    const int *istar;         // device scalar
+    const int64_t *colptr;
+    const int32_t *rowidx;
+    const double *cval;
+    const double *d;          // column sums d_j of the sparsified plan
+};
 
-// CG on device: see cg.hip
+// Launch shape of the two gathers of an HVP (and of the CG vector kernels).
+enum { CG_MAX_STAR = 64, CG_MAX_COLGROUPS = 2048, CG_MAX_UPDGROUPS = 128 };
+struct GatherPlan {
+    int lpc_row, lpc_col;     // lanes per row / per column
+    int row_blocks;           // workgroups of the sparse rows
+    int nstar, star_chunk;    // dense-row chunks (extra workgroups) and their width
+    int col_blocks;           // column-gather workgroups (grid-stride)
+    int upd_blocks;           // CG update workgroups
+};
+GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus);
+
+// y = (H_rho + shift I) v; au (m) and star_part (CG_MAX_STAR) are scratch
+hipError_t launch_hvp(const GatherPlan &g, const CsrView &c, const double *a, double eta,
+                      double shift, const double *v, double *y, double *au, double *star_part,
+                      hipStream_t st);
+
+// CG on the device.  Scalars (CG_* slots) are double-buffered by iteration parity.
 struct CgState {
     double *x, *r, *p, *Ap, *au;   // n, n, n, n, m
-    double *partial;               // >= number of workgroups of the vector kernels
-    double *scal;                  // device scalars (see CG_* slots)
-    unsigned *counter;             // 2 counters, zero-initialised
+    double *star_part;             // CG_MAX_STAR
+    double *pap_part;              // CG_MAX_COLGROUPS
+    double *rr_part;               // CG_MAX_UPDGROUPS
+    double *scal;                  // CG_NSLOT
 };
-enum { CG_RR = 0, CG_PAP, CG_ALPHA, CG_BETA, CG_TOL, CG_DONE, CG_IT, CG_MAXIT, CG_NSLOT };
+enum {
+    CG_TOL = 0, CG_MAXIT, CG_BRK, CG_RR0, CG_RR1, CG_BETA0, CG_BETA1, CG_DONE0, CG_DONE1,
+    CG_IT0, CG_IT1, CG_NSLOT
+};
 hipError_t launch_cg_init(int64_t n, const double *rhs, double tol, int maxit, CgState &s,
                           hipStream_t st);
-hipError_t launch_cg_iteration(int64_t m, int64_t n, const int32_t *col, const double *val,
-                               const int32_t *len, const int *istar, const int64_t *colptr,
-                               const int32_t *rowidx, const double *cval, const double *d,
-                               const double *a, double eta, double shift, CgState &s, int lpc_row,
-                               int lpc_col, hipStream_t st);
+// iteration `it` (0-based): three kernels; a no-op once CG has finished
+hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const double *a, double eta,
+                               double shift, CgState &s, int it, hipStream_t st);
+// writes the state after `it` iterations to slot it&1 (rr, done, iteration count)
+hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, hipStream_t st);
 
 // export slotted CSR to standard CSR
 hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const double *val,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,
-                             hipStream_t st);
+                             int64_t cap, hipStream_t st);
 
 }  // namespace ibsn

@@ -10,13 +10,14 @@
 //
 // CG runs entirely on the device: alpha, beta, the residual norm and a done flag live
 // in device memory, so the host enqueues iterations without reading anything back.
-// Grid-wide sums use a "last workgroup finishes" pattern: each workgroup writes a
-// partial, the last to arrive (atomic ticket, device-scope fences) adds the partials in
-// index order.
+// A grid-wide sum is a per-workgroup partial written by one kernel and added, in index
+// order, by every workgroup of the next kernel that needs it (no atomics, no fences).
 #include "ibsn_internal.h"
 #include "solver_kernels.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace ibsn {
 namespace {
@@ -49,39 +50,45 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return r;
 }
 
-// Last-workgroup-done: returns true in the workgroup that arrives last (all threads).
-__device__ __forceinline__ bool last_block(unsigned *counter, int *flag_lds)
+// ---------------------------------------------------------------------------------
+// deterministic transpose of the slotted rows (the dense row istar is not included:
+// the column gather reads it directly from its row slot, where it is stored whole in
+// column order)
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void block_rows(int m, int rb, int b, int &i0, int &i1)
 {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(counter, 1u);
-        *flag_lds = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    if (last)
-        __threadfence();
-    return last;
+    i0 = (int)((int64_t)m * b / rb);
+    i1 = (int)((int64_t)m * (b + 1) / rb);
 }
 
-// ---------------------------------------------------------------------------------
-// deterministic transpose of the slotted rows
-// ---------------------------------------------------------------------------------
-// cnt[b][j] = number of entries of column j in row block b
+// cnt[b][j] = number of entries of column j in row block b.  Histogram in LDS (n ints);
+// the four waves take rows round robin (LDS atomics: counts do not depend on order).
 __global__ __launch_bounds__(256) void k_csc_count(int m, int n, int rb, const int32_t *__restrict__ col,
                                                    const int32_t *__restrict__ len,
+                                                   const int *__restrict__ istar_p,
                                                    int32_t *__restrict__ cnt)
 {
+    extern __shared__ int32_t hist[];
     const int b = blockIdx.x;
-    const int i0 = (int)((int64_t)m * b / rb), i1 = (int)((int64_t)m * (b + 1) / rb);
-    int32_t *cb = cnt + (int64_t)b * n;
-    for (int i = i0; i < i1; ++i) {
+    int i0, i1;
+    block_rows(m, rb, b, i0, i1);
+    for (int j = threadIdx.x; j < n; j += 256)
+        hist[j] = 0;
+    __syncthreads();
+    const int istar = *istar_p;
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    for (int i = i0 + wv; i < i1; i += 256 / WAVE) {
+        if (i == istar)
+            continue;
         const int L = len[i];
         const int32_t *cr = col + (int64_t)i * n;
-        for (int e = threadIdx.x; e < L; e += blockDim.x)
-            atomicAdd(&cb[cr[e]], 1);
+        for (int e = lane; e < L; e += WAVE)
+            atomicAdd(&hist[cr[e]], 1);
     }
+    __syncthreads();
+    int32_t *cb = cnt + (int64_t)b * n;
+    for (int j = threadIdx.x; j < n; j += 256)
+        cb[j] = hist[j];
 }
 
 // per column: exclusive scan of cnt over row blocks (in place); colcnt_j = total
@@ -91,8 +98,21 @@ __global__ __launch_bounds__(256) void k_csc_blockscan(int n, int rb, int32_t *_
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n)
         return;
+    constexpr int U = 16;
     int32_t run = 0;
-    for (int b = 0; b < rb; ++b) {
+    int b = 0;
+    for (; b + U <= rb; b += U) {
+        int32_t t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            t[u] = cnt[(int64_t)(b + u) * n + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cnt[(int64_t)(b + u) * n + j] = run;
+            run += t[u];
+        }
+    }
+    for (; b < rb; ++b) {
         const int32_t t = cnt[(int64_t)b * n + j];
         cnt[(int64_t)b * n + j] = run;
         run += t;
@@ -101,9 +121,12 @@ __global__ __launch_bounds__(256) void k_csc_blockscan(int n, int rb, int32_t *_
 }
 
 // exclusive scan of n counts into ptr[0..n], single workgroup of 1024 threads;
-// ptr[n] = total, also copied to *total.
+// ptr[n] = total.  *total = ptr[n] plus the length of the dense row istar (held in the
+// row slots only), i.e. the number of stored entries of the factor.
 __global__ __launch_bounds__(1024) void k_scan(int n, const int64_t *__restrict__ cnt,
-                                               int64_t *__restrict__ ptr, int64_t *__restrict__ total)
+                                               int64_t *__restrict__ ptr, int64_t *__restrict__ total,
+                                               const int32_t *__restrict__ len,
+                                               const int *__restrict__ istar_p)
 {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
@@ -122,8 +145,10 @@ __global__ __launch_bounds__(1024) void k_scan(int n, const int64_t *__restrict_
             run += v;
         }
         ptr[n] = run;
-        if (total)
-            *total = run;
+        if (total) {
+            const int istar = istar_p ? *istar_p : -1;
+            *total = run + (istar >= 0 ? (int64_t)len[istar] : 0);
+        }
     }
     __syncthreads();
     int64_t run = part[t];
@@ -163,40 +188,159 @@ __global__ __launch_bounds__(1024) void k_scan32(int n, const int32_t *__restric
     }
 }
 
-// fill: row block b walks its rows in order; within a row every column occurs once, so
-// the per-(block, column) cursor needs no atomics; rows are separated by barriers.
+// fill: row block b walks its rows in order with a per-column cursor in LDS (within a
+// row every column occurs once, so a barrier between rows is all the ordering needed).
+// ABS64: the cursor holds the absolute CSC position (int64, n*8 bytes of LDS);
+// otherwise the rank within the column (int32) and the column start is read per entry.
+// Work items are chunks of CSC_FK*256 entries of one row; the next item's indices and
+// values are loaded before the current one is scattered.
+constexpr int CSC_FK = 4;
+
+template <bool ABS64>
 __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, int rb, const int32_t *__restrict__ col,
                                                   const double *__restrict__ val,
                                                   const int32_t *__restrict__ len,
+                                                  const int *__restrict__ istar_p,
                                                   const int64_t *__restrict__ colptr,
-                                                  int32_t *__restrict__ cur,
+                                                  const int32_t *__restrict__ blkoff,
                                                   int32_t *__restrict__ rowidx,
                                                   double *__restrict__ cval)
 {
+    extern __shared__ int64_t smem64[];
+    int64_t *cur64 = smem64;
+    int32_t *cur32 = reinterpret_cast<int32_t *>(smem64);
     const int b = blockIdx.x;
-    const int i0 = (int)((int64_t)m * b / rb), i1 = (int)((int64_t)m * (b + 1) / rb);
-    int32_t *cb = cur + (int64_t)b * n;
-    for (int i = i0; i < i1; ++i) {
-        const int L = len[i];
-        const int32_t *cr = col + (int64_t)i * n;
-        const double *vr = val + (int64_t)i * n;
-        for (int e = threadIdx.x; e < L; e += blockDim.x) {
-            const int j = cr[e];
-            const int32_t k = cb[j];
-            cb[j] = k + 1;
-            const int64_t pos = colptr[j] + k;
-            rowidx[pos] = i;
-            cval[pos] = vr[e];
+    int i0, i1;
+    block_rows(m, rb, b, i0, i1);
+    const int R = i1 - i0;
+    int32_t *lens = reinterpret_cast<int32_t *>(
+        reinterpret_cast<unsigned char *>(smem64) + (ABS64 ? 8 : 4) * (size_t)((n + 1) & ~1));
+    const int istar = *istar_p;
+    const int32_t *bo = blkoff + (int64_t)b * n;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        if (ABS64)
+            cur64[j] = colptr[j] + bo[j];
+        else
+            cur32[j] = bo[j];
+    }
+    for (int r = threadIdx.x; r < R; r += 256)
+        lens[r] = (i0 + r == istar) ? 0 : len[i0 + r];
+    __syncthreads();
+
+    int jj[CSC_FK], nj[CSC_FK];
+    double vv[CSC_FK], nv[CSC_FK];
+    auto fetch = [&](int r, int e0, int *J, double *V) {
+        const int L = lens[r];
+        const int32_t *cr = col + (int64_t)(i0 + r) * n;
+        const double *vr = val + (int64_t)(i0 + r) * n;
+#pragma unroll
+        for (int k = 0; k < CSC_FK; ++k) {
+            const int e = e0 + k * 256 + threadIdx.x;
+            J[k] = e < L ? cr[e] : 0;
+            V[k] = e < L ? vr[e] : 0.0;
+        }
+    };
+    int r = 0, e0 = 0;
+    if (R > 0)
+        fetch(0, 0, jj, vv);
+    while (r < R) {
+        const int L = lens[r];
+        int nr = r, ne = e0 + CSC_FK * 256;
+        if (ne >= L) {
+            nr = r + 1;
+            ne = 0;
+        }
+        if (nr < R)
+            fetch(nr, ne, nj, nv);
+#pragma unroll
+        for (int k = 0; k < CSC_FK; ++k) {
+            const int e = e0 + k * 256 + threadIdx.x;
+            if (e < L) {
+                const int j = jj[k];
+                int64_t pos;
+                if (ABS64) {
+                    pos = cur64[j];
+                    cur64[j] = pos + 1;
+                } else {
+                    const int32_t c = cur32[j];
+                    cur32[j] = c + 1;
+                    pos = colptr[j] + c;
+                }
+                rowidx[pos] = i0 + r;
+                cval[pos] = vv[k];
+            }
         }
         __syncthreads();
+        r = nr;
+        e0 = ne;
+#pragma unroll
+        for (int k = 0; k < CSC_FK; ++k) {
+            jj[k] = nj[k];
+            vv[k] = nv[k];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------------
-// HVP gathers
+// HVP gathers and device-driven CG
 // ---------------------------------------------------------------------------------
-// au_i = a_i * sum_e val * v[col]; LPC lanes per row; the dense row istar is done by the
-// extra last workgroup with all its threads.
+// CG scalars are double-buffered by iteration parity: the kernels of iteration `it`
+// read slot it&1 (or (it-1)&1) and only workgroup 0 of the row gather writes slot it&1,
+// before any later kernel reads it.  Grid-wide sums are not finished by one workgroup:
+// every consumer workgroup adds the producer's per-workgroup partials itself, in index
+// order, so all of them hold the same value and no device-scope fence is needed.
+//
+// cg_begin (all threads of a 256-thread workgroup) returns true when CG has finished
+// before iteration `it`; otherwise beta for p = r + beta p.
+__device__ __forceinline__ bool cg_begin(int it, double *__restrict__ scal,
+                                         const double *__restrict__ rr_part, int nrr, double *lds,
+                                         double *beta_out)
+{
+    if (it == 0) {
+        *beta_out = 0.0;
+        return scal[CG_DONE0] != 0.0;
+    }
+    const int ps = (it - 1) & 1, cs = it & 1;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (scal[CG_DONE0 + ps] != 0.0) {
+        if (lead) {
+            scal[CG_RR0 + cs] = scal[CG_RR0 + ps];
+            scal[CG_BETA0 + cs] = 0.0;
+            scal[CG_IT0 + cs] = scal[CG_IT0 + ps];
+            scal[CG_DONE0 + cs] = 1.0;
+        }
+        return true;
+    }
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nrr; k += 256)
+        t += rr_part[k];
+    const double rr = block_sum<256>(t, lds);
+    const double beta = rr / scal[CG_RR0 + ps];
+    const bool brk = scal[CG_BRK] != 0.0;   // p.Ap <= 0 in iteration it-1: no step taken
+    const bool done = brk || !(sqrt(rr) > scal[CG_TOL]) || (double)it >= scal[CG_MAXIT];
+    if (lead) {
+        scal[CG_RR0 + cs] = rr;
+        scal[CG_BETA0 + cs] = beta;
+        scal[CG_IT0 + cs] = (double)(brk ? it - 1 : it);
+        scal[CG_DONE0 + cs] = done ? 1.0 : 0.0;
+    }
+    *beta_out = beta;
+    return done;
+}
+
+// State after `it` iterations into slot it&1 (one workgroup; the host reads it).
+__global__ __launch_bounds__(256) void k_cg_check(int it, double *__restrict__ scal,
+                                                  const double *__restrict__ rr_part, int nrr)
+{
+    __shared__ double lds[4];
+    double beta;
+    (void)cg_begin(it, scal, rr_part, nrr, lds, &beta);
+}
+
+// au_i = a_i * sum_e val * v[col] for rows i != istar, LPC lanes per row.  The dense
+// row istar (every column, in order) is split into chunks of `star_chunk` columns, one
+// per extra workgroup: star_part[c] = sum over the chunk of val * v.
+// CG mode (scal != null): the vector is p = r + beta p_old, formed on the fly.
 template <int LPC>
 __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t *__restrict__ col,
                                                     const double *__restrict__ val,
@@ -205,31 +349,32 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
                                                     const double *__restrict__ a,
                                                     const double *__restrict__ v,
                                                     double *__restrict__ au,
-                                                    const double *__restrict__ scal, int p_mode,
+                                                    double *__restrict__ star_part, int row_blocks,
+                                                    int star_chunk, int it,
+                                                    double *__restrict__ scal,
+                                                    const double *__restrict__ rr_part, int nrr,
                                                     const double *__restrict__ r_vec)
 {
-    // p_mode = 1 (inside CG): the vector gathered is p_new = r + beta * p_old, formed on the
-    // fly (scal[CG_BETA]); v = p_old, r_vec = r.  Skipped when CG is done.
-    if (p_mode && scal[CG_DONE] != 0.0)
+    __shared__ double lds[4];
+    const bool cgm = scal != nullptr;
+    double beta = 0.0;
+    if (cgm && cg_begin(it, scal, rr_part, nrr, lds, &beta))
         return;
-    const double beta = p_mode ? scal[CG_BETA] : 0.0;
     const int istar = *istar_p;
-    if (blockIdx.x == gridDim.x - 1) {
-        __shared__ double lds[4];
-        if (istar < 0)
-            return;
-        const int L = len[istar];
-        const int32_t *cr = col + (int64_t)istar * n;
-        const double *vr = val + (int64_t)istar * n;
+    if ((int)blockIdx.x >= row_blocks) {
+        const int c = blockIdx.x - row_blocks;
         double s = 0.0;
-        for (int e = threadIdx.x; e < L; e += blockDim.x) {
-            const int j = cr[e];
-            const double vj = p_mode ? fma(beta, v[j], r_vec[j]) : v[j];
-            s = fma(vr[e], vj, s);
+        if (istar >= 0) {
+            const int j0 = c * star_chunk, j1 = min(n, j0 + star_chunk);
+            const double *vr = val + (int64_t)istar * n;
+            for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+                const double vj = cgm ? fma(beta, v[j], r_vec[j]) : v[j];
+                s = fma(vr[j], vj, s);
+            }
         }
         s = block_sum<256>(s, lds);
         if (threadIdx.x == 0)
-            au[istar] = a[istar] * s;
+            star_part[c] = s;
         return;
     }
     const int g = (blockIdx.x * 256 + threadIdx.x) / LPC;
@@ -242,7 +387,7 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
     double s = 0.0;
     for (int e = l; e < L; e += LPC) {
         const int j = cr[e];
-        const double vj = p_mode ? fma(beta, v[j], r_vec[j]) : v[j];
+        const double vj = cgm ? fma(beta, v[j], r_vec[j]) : v[j];
         s = fma(vr[e], vj, s);
     }
 #pragma unroll
@@ -252,115 +397,116 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
         au[g] = a[g] * s;
 }
 
-// y_j = (d_j v_j - sum_{col j} cval * au[row]) / eta + shift * v_j.
-// p_mode = 1 (CG): v_j = r_j + beta p_old_j is formed here and written back to p;
-// y = Ap; per-workgroup partial of p.Ap; the last workgroup computes pAp and alpha.
+// y_j = (d_j v_j - sum_{i != istar} P_ij au_i - P_istar,j au_istar) / eta + shift * v_j,
+// au_istar = a_istar * (sum of the dense-row chunk partials, in order).  Columns are
+// taken grid-stride, LPC lanes each.
+// CG mode: v_j = r_j + beta p_old_j is formed here and written back to p; y = Ap and a
+// per-workgroup partial of p.Ap goes to pap_part.
 template <int LPC>
 __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__restrict__ colptr,
                                                     const int32_t *__restrict__ rowidx,
                                                     const double *__restrict__ cval,
                                                     const double *__restrict__ au,
                                                     const double *__restrict__ d,
-                                                    double *__restrict__ v, double eta,
-                                                    double shift, double *__restrict__ y,
-                                                    double *__restrict__ scal, int p_mode,
+                                                    const double *__restrict__ val,
+                                                    const int *__restrict__ istar_p,
+                                                    const double *__restrict__ a,
+                                                    const double *__restrict__ star_part,
+                                                    int nstar, double *__restrict__ v, double eta,
+                                                    double shift, double *__restrict__ y, int it,
+                                                    const double *__restrict__ scal,
                                                     const double *__restrict__ r_vec,
-                                                    double *__restrict__ partial,
-                                                    unsigned *__restrict__ counter)
+                                                    double *__restrict__ pap_part)
 {
-    if (p_mode && scal[CG_DONE] != 0.0)
-        return;
     __shared__ double lds[4];
-    __shared__ int flag;
-    const int j = (blockIdx.x * 256 + threadIdx.x) / LPC;
+    const bool cgm = scal != nullptr;
+    double beta = 0.0;
+    if (cgm) {
+        const int cs = it & 1;
+        if (scal[CG_DONE0 + cs] != 0.0)
+            return;
+        beta = scal[CG_BETA0 + cs];
+    }
+    const int istar = *istar_p;
+    double aus = 0.0;
+    const double *prow = nullptr;
+    if (istar >= 0) {
+        double t = 0.0;
+        for (int k = threadIdx.x; k < nstar; k += 256)
+            t += star_part[k];
+        aus = a[istar] * block_sum<256>(t, lds);
+        prow = val + (int64_t)istar * n;
+    }
+    constexpr int CPB = 256 / LPC;
     const int l = threadIdx.x % LPC;
-    double s = 0.0;
-    if (j < n) {
+    double pap = 0.0;
+    for (int j = blockIdx.x * CPB + threadIdx.x / LPC; j < n; j += gridDim.x * CPB) {
         const int64_t e0 = colptr[j], e1 = colptr[j + 1];
+        double s = 0.0;
         for (int64_t e = e0 + l; e < e1; e += LPC)
             s = fma(cval[e], au[rowidx[e]], s);
-    }
 #pragma unroll
-    for (int o = LPC / 2; o > 0; o >>= 1)
-        s += __shfl_xor(s, o, LPC);
-    double pap = 0.0;
-    if (j < n && l == 0) {
-        double vj = v[j];
-        if (p_mode) {
-            vj = fma(scal[CG_BETA], vj, r_vec[j]);
-            v[j] = vj;
+        for (int o = LPC / 2; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, LPC);
+        if (l == 0) {
+            double vj = v[j];
+            if (cgm) {
+                vj = fma(beta, vj, r_vec[j]);
+                v[j] = vj;
+            }
+            if (prow)
+                s = fma(prow[j], aus, s);
+            const double yj = (d[j] * vj - s) / eta + shift * vj;
+            y[j] = yj;
+            pap = fma(vj, yj, pap);
         }
-        const double yj = (d[j] * vj - s) / eta + shift * vj;
-        y[j] = yj;
-        pap = vj * yj;
     }
-    if (!p_mode)
+    if (!cgm)
         return;
     pap = block_sum<256>(pap, lds);
     if (threadIdx.x == 0)
-        partial[blockIdx.x] = pap;
-    if (last_block(counter, &flag)) {
-        double t = 0.0;
-        for (int k = threadIdx.x; k < (int)gridDim.x; k += 256)
-            t += partial[k];
-        // fixed order: strided partial sums then the workgroup reduction
-        t = block_sum<256>(t, lds);
-        if (threadIdx.x == 0) {
-            scal[CG_PAP] = t;
-            if (!(t > 0.0)) {
-                scal[CG_DONE] = 1.0;
-                scal[CG_ALPHA] = 0.0;
-            } else {
-                scal[CG_ALPHA] = scal[CG_RR] / t;
-            }
-            *counter = 0u;
-        }
-    }
+        pap_part[blockIdx.x] = pap;
 }
 
-// x += alpha p; r -= alpha Ap; rr_new; beta = rr_new/rr; done test.
-__global__ __launch_bounds__(256) void k_cg_update(int n, double *__restrict__ x,
+// alpha = rr / p.Ap (p.Ap from the column-gather partials, in order); x += alpha p;
+// r -= alpha Ap; per-workgroup partial of r.r.  p.Ap <= 0 (or not a number): no step,
+// flag it for the next iteration's start.
+__global__ __launch_bounds__(256) void k_cg_update(int n, int it, double *__restrict__ x,
                                                    double *__restrict__ r,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ Ap,
                                                    double *__restrict__ scal,
-                                                   double *__restrict__ partial,
-                                                   unsigned *__restrict__ counter)
+                                                   const double *__restrict__ pap_part, int npap,
+                                                   double *__restrict__ rr_part)
 {
-    if (scal[CG_DONE] != 0.0)
-        return;
     __shared__ double lds[4];
-    __shared__ int flag;
-    const double alpha = scal[CG_ALPHA];
+    const int cs = it & 1;
+    if (scal[CG_DONE0 + cs] != 0.0)
+        return;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < npap; k += 256)
+        t += pap_part[k];
+    t = block_sum<256>(t, lds);
+    const bool ok = t > 0.0;
+    if (!ok && blockIdx.x == 0 && threadIdx.x == 0)
+        scal[CG_BRK] = 1.0;
+    const double alpha = ok ? scal[CG_RR0 + cs] / t : 0.0;
     double s = 0.0;
     for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
-        x[j] = fma(alpha, p[j], x[j]);
-        const double rj = fma(-alpha, Ap[j], r[j]);
-        r[j] = rj;
+        double rj = r[j];
+        if (ok) {
+            x[j] = fma(alpha, p[j], x[j]);
+            rj = fma(-alpha, Ap[j], rj);
+            r[j] = rj;
+        }
         s = fma(rj, rj, s);
     }
     s = block_sum<256>(s, lds);
     if (threadIdx.x == 0)
-        partial[blockIdx.x] = s;
-    if (last_block(counter, &flag)) {
-        double t = 0.0;
-        for (int k = threadIdx.x; k < (int)gridDim.x; k += 256)
-            t += partial[k];
-        t = block_sum<256>(t, lds);
-        if (threadIdx.x == 0) {
-            const double rr = scal[CG_RR];
-            scal[CG_BETA] = t / rr;
-            scal[CG_RR] = t;
-            const double it = scal[CG_IT] + 1.0;
-            scal[CG_IT] = it;
-            if (sqrt(t) <= scal[CG_TOL] || it >= scal[CG_MAXIT])
-                scal[CG_DONE] = 1.0;
-            *counter = 0u;
-        }
-    }
+        rr_part[blockIdx.x] = s;
 }
 
-// CG start: x = 0, r = rhs, p = rhs (the first iteration forms p = r + 0*p), rr = r.r
+// CG start: x = 0, r = rhs, p = 0 (the first iteration forms p = r + 0*p), rr = r.r
 __global__ __launch_bounds__(1024) void k_cg_init(int n, const double *__restrict__ rhs, double tol,
                                                   int maxit, double *__restrict__ x,
                                                   double *__restrict__ r, double *__restrict__ p,
@@ -377,14 +523,17 @@ __global__ __launch_bounds__(1024) void k_cg_init(int n, const double *__restric
     }
     s = block_sum<1024>(s, lds);
     if (threadIdx.x == 0) {
-        scal[CG_RR] = s;
-        scal[CG_PAP] = 0.0;
-        scal[CG_ALPHA] = 0.0;
-        scal[CG_BETA] = 0.0;
         scal[CG_TOL] = tol;
-        scal[CG_IT] = 0.0;
         scal[CG_MAXIT] = (double)maxit;
-        scal[CG_DONE] = (sqrt(s) <= tol || maxit <= 0) ? 1.0 : 0.0;
+        scal[CG_BRK] = 0.0;
+        scal[CG_RR0] = s;
+        scal[CG_BETA0] = 0.0;
+        scal[CG_IT0] = 0.0;
+        scal[CG_DONE0] = (!(sqrt(s) > tol) || maxit <= 0) ? 1.0 : 0.0;
+        scal[CG_RR1] = 0.0;
+        scal[CG_BETA1] = 0.0;
+        scal[CG_IT1] = 0.0;
+        scal[CG_DONE1] = 0.0;
     }
 }
 
@@ -415,18 +564,18 @@ __global__ __launch_bounds__(256) void k_make_w(int n, const double *__restrict_
     }
 }
 
-// standard CSR from the row slots
+// standard CSR from the row slots; writes stay below cap (the caller's buffer length)
 __global__ __launch_bounds__(256) void k_export_csr(int m, int n, const int32_t *__restrict__ col,
                                                     const double *__restrict__ val,
                                                     const int64_t *__restrict__ row_ptr,
                                                     int32_t *__restrict__ ocol,
-                                                    double *__restrict__ oval)
+                                                    double *__restrict__ oval, int64_t cap)
 {
     const int i = blockIdx.x;
     if (i >= m)
         return;
     const int64_t o = row_ptr[i];
-    const int L = (int)(row_ptr[i + 1] - o);
+    const int L = (int)min(row_ptr[i + 1] - o, cap - o);
     for (int e = threadIdx.x; e < L; e += 256) {
         ocol[o + e] = col[(int64_t)i * n + e];
         oval[o + e] = val[(int64_t)i * n + e];
@@ -438,58 +587,112 @@ __global__ __launch_bounds__(256) void k_export_csr(int m, int n, const int32_t 
 // ---------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------
-hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
-                            const int32_t *len, CscWork &w, int64_t *nnz_dev, hipStream_t st)
+GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus)
 {
-    hipError_t e = sk_zero_i32((int64_t)w.rb * n, w.blkcnt, st);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_csc_count, dim3(w.rb), dim3(256), 0, st, (int)m, (int)n, w.rb, col, len,
-                       w.blkcnt);
+    GatherPlan g;
+    const int64_t dense = istar >= 0 ? n : 0;
+    const int64_t rows = istar >= 0 ? m - 1 : m;
+    const double avg_row = rows > 0 ? (double)(nnz - dense) / (double)rows : 0.0;
+    const double avg_col = n > 0 ? (double)(nnz - dense) / (double)n : 0.0;
+    auto lanes = [](double avg) { return avg >= 96.0 ? 64 : (avg >= 12.0 ? 16 : 4); };
+    g.lpc_row = lanes(avg_row);
+    g.lpc_col = lanes(avg_col);
+    g.row_blocks = (int)((m * g.lpc_row + 255) / 256);
+    g.star_chunk = 1024;
+    g.nstar = (int)((n + g.star_chunk - 1) / g.star_chunk);
+    if (g.nstar > CG_MAX_STAR) {
+        g.nstar = CG_MAX_STAR;
+        g.star_chunk = (int)((n + CG_MAX_STAR - 1) / CG_MAX_STAR);
+    }
+    const int64_t need = (n * g.lpc_col + 255) / 256;
+    g.col_blocks = (int)std::min<int64_t>(need, std::min<int64_t>(CG_MAX_COLGROUPS, 4 * num_cus));
+    if (g.col_blocks < 1)
+        g.col_blocks = 1;
+    g.upd_blocks = (int)std::min<int64_t>((n + 255) / 256, CG_MAX_UPDGROUPS);
+    if (g.upd_blocks < 1)
+        g.upd_blocks = 1;
+    return g;
+}
+
+size_t csc_fill_lds(int64_t m, int64_t n, int rb, bool abs64)
+{
+    const int64_t rows = (m + rb - 1) / rb;
+    return (size_t)(abs64 ? 8 : 4) * (size_t)((n + 1) & ~1) + (size_t)rows * 4;
+}
+
+hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
+                            const int32_t *len, const int *istar, CscWork &w, int64_t *nnz_dev,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_csc_count, dim3(w.rb), dim3(256), (size_t)n * 4, st, (int)m, (int)n, w.rb,
+                       col, len, istar, w.blkcnt);
     hipLaunchKernelGGL(k_csc_blockscan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        (int)n, w.rb, w.blkcnt, w.colcnt);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (int)n, w.colcnt, w.colptr, nnz_dev);
-    hipLaunchKernelGGL(k_csc_fill, dim3(w.rb), dim3(256), 0, st, (int)m, (int)n, w.rb, col, val,
-                       len, w.colptr, w.blkcnt, w.rowidx, w.cval);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (int)n, w.colcnt, w.colptr, nnz_dev, len,
+                       istar);
+    const size_t lds = csc_fill_lds(m, n, w.rb, w.abs64);
+    if (w.abs64)
+        hipLaunchKernelGGL((k_csc_fill<true>), dim3(w.rb), dim3(256), lds, st, (int)m, (int)n, w.rb,
+                           col, val, len, istar, w.colptr, w.blkcnt, w.rowidx, w.cval);
+    else
+        hipLaunchKernelGGL((k_csc_fill<false>), dim3(w.rb), dim3(256), lds, st, (int)m, (int)n,
+                           w.rb, col, val, len, istar, w.colptr, w.blkcnt, w.rowidx, w.cval);
     return hipGetLastError();
 }
 
-hipError_t launch_row_gather(int64_t m, int64_t n, const int32_t *col, const double *val,
-                             const int32_t *len, const int *istar, const double *a, const double *v,
-                             double *au, int lpc, hipStream_t st)
+namespace {
+template <int L>
+void row_gather_l(const GatherPlan &g, const CsrView &c, const double *a, const double *v,
+                  double *au, double *star_part, int it, double *scal, const double *rr_part,
+                  int nrr, const double *r_vec, hipStream_t st)
 {
-    const int blocks = (int)((m * lpc + 255) / 256) + 1;
-#define G(L)                                                                                   \
-    hipLaunchKernelGGL((k_row_gather<L>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col, \
-                       val, len, istar, a, v, au, (const double *)nullptr, 0,                   \
-                       (const double *)nullptr)
-    if (lpc >= 64)
-        G(64);
-    else if (lpc >= 16)
-        G(16);
-    else
-        G(4);
-#undef G
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_row_gather<L>), dim3(g.row_blocks + g.nstar), dim3(256), 0, st, (int)c.m,
+                       (int)c.n, c.col, c.val, c.len, c.istar, a, v, au, star_part, g.row_blocks,
+                       g.star_chunk, it, scal, rr_part, nrr, r_vec);
 }
 
-hipError_t launch_col_gather(int64_t n, const int64_t *colptr, const int32_t *rowidx,
-                             const double *cval, const double *au, const double *d,
-                             const double *v, double eta, double shift, double *y, int lpc,
-                             hipStream_t st)
+void row_gather(const GatherPlan &g, const CsrView &c, const double *a, const double *v,
+                double *au, double *star_part, int it, double *scal, const double *rr_part, int nrr,
+                const double *r_vec, hipStream_t st)
 {
-    const int blocks = (int)((n * lpc + 255) / 256);
-#define G(L)                                                                                       \
-    hipLaunchKernelGGL((k_col_gather<L>), dim3(blocks), dim3(256), 0, st, (int)n, colptr, rowidx, \
-                       cval, au, d, const_cast<double *>(v), eta, shift, y, (double *)nullptr, 0,  \
-                       (const double *)nullptr, (double *)nullptr, (unsigned *)nullptr)
-    if (lpc >= 64)
-        G(64);
-    else if (lpc >= 16)
-        G(16);
+    if (g.lpc_row >= 64)
+        row_gather_l<64>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
+    else if (g.lpc_row >= 16)
+        row_gather_l<16>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
     else
-        G(4);
-#undef G
+        row_gather_l<4>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
+}
+
+template <int L>
+void col_gather_l(const GatherPlan &g, const CsrView &c, const double *a, const double *au,
+                  const double *star_part, double *v, double eta, double shift, double *y, int it,
+                  const double *scal, const double *r_vec, double *pap_part, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_col_gather<L>), dim3(g.col_blocks), dim3(256), 0, st, (int)c.n, c.colptr,
+                       c.rowidx, c.cval, au, c.d, c.val, c.istar, a, star_part, g.nstar, v, eta,
+                       shift, y, it, scal, r_vec, pap_part);
+}
+
+void col_gather(const GatherPlan &g, const CsrView &c, const double *a, const double *au,
+                const double *star_part, double *v, double eta, double shift, double *y, int it,
+                const double *scal, const double *r_vec, double *pap_part, hipStream_t st)
+{
+    if (g.lpc_col >= 64)
+        col_gather_l<64>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec, pap_part, st);
+    else if (g.lpc_col >= 16)
+        col_gather_l<16>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec, pap_part, st);
+    else
+        col_gather_l<4>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec, pap_part, st);
+}
+}  // namespace
+
+hipError_t launch_hvp(const GatherPlan &g, const CsrView &c, const double *a, double eta,
+                      double shift, const double *v, double *y, double *au, double *star_part,
+                      hipStream_t st)
+{
+    row_gather(g, c, a, v, au, star_part, 0, nullptr, nullptr, 0, nullptr, st);
+    col_gather(g, c, a, au, star_part, const_cast<double *>(v), eta, shift, y, 0, nullptr,
+               nullptr, nullptr, st);
     return hipGetLastError();
 }
 
@@ -501,49 +704,23 @@ hipError_t launch_cg_init(int64_t n, const double *rhs, double tol, int maxit, C
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(int64_t m, int64_t n, const int32_t *col, const double *val,
-                               const int32_t *len, const int *istar, const int64_t *colptr,
-                               const int32_t *rowidx, const double *cval, const double *d,
-                               const double *a, double eta, double shift, CgState &s, int lpc_row,
-                               int lpc_col, hipStream_t st)
+hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const double *a, double eta,
+                               double shift, CgState &s, int it, hipStream_t st)
 {
-    // 1) au = a . (P_rho p_new), p_new = r + beta p formed on the fly
-    {
-        const int blocks = (int)((m * lpc_row + 255) / 256) + 1;
-#define G(L)                                                                                      \
-    hipLaunchKernelGGL((k_row_gather<L>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col, val, \
-                       len, istar, a, s.p, s.au, s.scal, 1, s.r)
-        if (lpc_row >= 64)
-            G(64);
-        else if (lpc_row >= 16)
-            G(16);
-        else
-            G(4);
-#undef G
-    }
-    // 2) p = p_new; Ap; pAp; alpha
-    {
-        const int blocks = (int)((n * lpc_col + 255) / 256);
-#define G(L)                                                                                       \
-    hipLaunchKernelGGL((k_col_gather<L>), dim3(blocks), dim3(256), 0, st, (int)n, colptr, rowidx, \
-                       cval, s.au, d, s.p, eta, shift, s.Ap, s.scal, 1, s.r, s.partial,            \
-                       s.counter)
-        if (lpc_col >= 64)
-            G(64);
-        else if (lpc_col >= 16)
-            G(16);
-        else
-            G(4);
-#undef G
-    }
-    // 3) x, r, rr, beta, done
-    {
-        int blocks = (int)((n + 255) / 256);
-        if (blocks > 256)
-            blocks = 256;
-        hipLaunchKernelGGL(k_cg_update, dim3(blocks), dim3(256), 0, st, (int)n, s.x, s.r, s.p,
-                           s.Ap, s.scal, s.partial, s.counter + 1);
-    }
+    // 1) p_new = r + beta p (beta, rr, done from the update partials); au = a.(P p_new)
+    row_gather(g, c, a, s.p, s.au, s.star_part, it, s.scal, s.rr_part, g.upd_blocks, s.r, st);
+    // 2) p = p_new; Ap; partials of p.Ap
+    col_gather(g, c, a, s.au, s.star_part, s.p, eta, shift, s.Ap, it, s.scal, s.r, s.pap_part,
+               st);
+    // 3) alpha; x, r; partials of r.r
+    hipLaunchKernelGGL(k_cg_update, dim3(g.upd_blocks), dim3(256), 0, st, (int)c.n, it, s.x, s.r,
+                       s.p, s.Ap, s.scal, s.pap_part, g.col_blocks, s.rr_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(256), 0, st, it, s.scal, s.rr_part, g.upd_blocks);
     return hipGetLastError();
 }
 
@@ -569,11 +746,11 @@ hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, 
 
 hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const double *val,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,
-                             hipStream_t st)
+                             int64_t cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scan32, dim3(1), dim3(1024), 0, st, (int)m, len, row_ptr);
     hipLaunchKernelGGL(k_export_csr, dim3((unsigned)m), dim3(256), 0, st, (int)m, (int)n, col, val,
-                       row_ptr, ocol, oval);
+                       row_ptr, ocol, oval, cap);
     return hipGetLastError();
 }
 

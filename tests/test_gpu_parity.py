@@ -190,6 +190,8 @@ def test_trial_big_step(ib, ctx):
 def compare_patterns(gcsr, ocsr, P, rho, istar):
     row_ptr, col, val, d = (host(x) for x in gcsr.export())
     assert gcsr.istar == ocsr.istar == istar
+    # the reported nnz counts every stored entry, the dense row included
+    assert int(row_ptr[-1]) == gcsr.nnz == len(col)
     m = len(row_ptr) - 1
     same = True
     for i in range(m):
