@@ -57,9 +57,10 @@ enum {
     IBSN_ERR_UNSUPPORTED = -5     /* shape outside the compiled kernel range               */
 };
 
-/* Largest n the dense row kernels hold in registers (FP64 cost: 20480; FP32: 40960). */
-#define IBSN_MAX_N_F64 20480
-#define IBSN_MAX_N_F32 40960
+/* Largest n of the dense row kernels: a workgroup holds one row of C in registers and
+   an n-vector of potentials in LDS (FP64 cost: 10240 columns; FP32 cost: 20000). */
+#define IBSN_MAX_N_F64 10240
+#define IBSN_MAX_N_F32 20000
 
 typedef struct ibsn_ctx ibsn_ctx;
 typedef struct ibsn_csr ibsn_csr;

@@ -159,9 +159,10 @@ int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
     const size_t es = p->cost_kind == IBSN_COST_F64 ? 8 : 4;
     if (((uintptr_t)p->C % es) != 0)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "C must be aligned to its element size");
-    if ((size_t)p->n * sizeof(double) > ctx->max_lds)
+    // the row passes stage an n-vector in LDS beside up to 2 KB of their own
+    if ((size_t)p->n * sizeof(double) + 2048 > ctx->max_lds)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld needs %zu bytes of LDS (device max %zu)",
-                    (long long)p->n, (size_t)p->n * 8, ctx->max_lds);
+                    (long long)p->n, (size_t)p->n * 8 + 2048, ctx->max_lds);
     return IBSN_OK;
 }
 
@@ -688,6 +689,8 @@ int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cent
                     P<double>(ctx->rowpart2), rp.grid, scal, ctx->stream));
     CKH(sk_wmax(prob->n, ctr->s, gamma, prob->eta, scal, ctx->stream));
     CKI(read_scal(ctx));
+    if (!std::isfinite(ctx->host_scal[SC_CMAX]))
+        return fail(ctx, IBSN_ERR_NUMERIC, "C has a NaN or infinite entry");
     const double sigma = (double)(ctr->k + 1) / prob->eta;
     *quantum_host = quantum_of(ctx->host_scal[SC_WMAX] + sigma * ctx->host_scal[SC_CMAX]);
     return IBSN_OK;
@@ -999,6 +1002,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                      scal, st));
     CKS(read_scal(ctx));
     const double cmax = ctx->host_scal[SC_CMAX];
+    if (!std::isfinite(cmax))
+        CKS(fail(ctx, IBSN_ERR_NUMERIC, "C has a NaN or infinite entry"));
     double *w = P<double>(ctx->w);
 
     ibsn_report R;

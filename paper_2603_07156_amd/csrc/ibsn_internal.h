@@ -10,10 +10,12 @@ namespace ibsn {
 // Work split of the dense row passes: `grid` workgroups, workgroup g owns rows
 // [m*g/grid, m*(g+1)/grid), and writes one n-long column partial row.
 struct RowPlan {
-    int nt;        // threads per workgroup
-    int q;         // vector slots per thread (row held as q*vec values per thread)
-    int vec;       // elements per vector load (2 for FP64 cost, 4 for FP32)
-    int grid;      // number of workgroups
+    int nt;              // threads per workgroup (eval, stop pass 1)
+    int q;               // vector slots per thread (row held as q*vec values per thread)
+    int qf;              // leading slabs that lie inside the row for every thread
+    int nt_h, q_h, qf_h; // the same for trial, sparsify and stop pass 2
+    int vec;             // elements per vector load (2 for FP64 cost, 4 for FP32)
+    int grid;            // number of workgroups (all passes)
 };
 
 // Choose the register tile for a row of n entries; returns false if n is too large.

@@ -119,7 +119,8 @@ __global__ __launch_bounds__(256) void k_cost_max_part(int m, int n, int64_t ldc
         for (int j = threadIdx.x; j < n; j += 256) {
             const double c = kind == 1 ? (double)((const float *)C)[(int64_t)i * ldc + j]
                                        : ((const double *)C)[(int64_t)i * ldc + j];
-            mx = fmax(mx, fabs(c));
+            // a NaN or infinite entry makes the maximum +inf (fmax would drop a NaN)
+            mx = fabs(c) <= 1.7976931348623157e308 ? fmax(mx, fabs(c)) : INFINITY;
         }
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1)

@@ -21,7 +21,7 @@ IBSN_OK = 0
 IBSN_WARN_MAXITER = 1
 IBSN_COST_F64 = 0
 IBSN_COST_F32 = 1
-MAX_N_F64 = 20480
+MAX_N_F64 = 10240
 
 
 class IBSNError(RuntimeError):
