@@ -38,6 +38,26 @@ def pass_bytes(m: int, n: int) -> float:
     return 8.0 * m * n + 8.0 * (4 * m + 5 * n)
 
 
+def cg_roofline(m: int, n: int, rep: dict, kt: dict):
+    """The CG iterations' sparse gathers: per iteration the row gather reads each stored
+    entry of the sparsified factor (int32 column + FP64 value) and the column gather its
+    transpose (int32 row + FP64 value), i.e. 24 bytes per stored entry outside the dense
+    row, 8 bytes per dense-row entry read twice, plus the n- and m-vectors they read and
+    write (8 (6n + 2m) bytes).  Time per iteration from the CG solves' HIP events (host
+    polling between chunks of iterations included)."""
+    iters = rep["cg"]
+    if not iters or not kt.get("cg", (0, 0))[1]:
+        return None
+    nnz = rep["nnz_mean"]
+    per_iter = 24.0 * max(nnz - n, 0.0) + 16.0 * n + 8.0 * (6 * n + 2 * m)
+    ms_per_iter = kt["cg"][0] / iters
+    achieved = per_iter / (ms_per_iter * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "CG iteration (row gather + column gather + update)",
+            "bytes_per_iteration": per_iter, "ms_per_iteration": ms_per_iter}
+
+
 def cpu_baseline(inst, seconds: float):
     """The oracle's eval pass (eqs. 5-8) on the same 10^4 workload, repeated for about
     `seconds` of CPU time; GB/s in the same algorithmic bytes as `value`."""
@@ -143,7 +163,10 @@ def main() -> int:
         "solve": {"outer_per_s": steps / dt, "dense_passes": rep["passes"],
                   "newton": rep["newton"], "cg": rep["cg"], "sinkhorn": rep["sinkhorn"],
                   "backtracks": rep["backtracks"], "rel_gap_end": rep["rel_gap"],
-                  "grad_norm_end": rep["grad_norm"], "k_end": res["k"]},
+                  "grad_norm_end": rep["grad_norm"], "k_end": res["k"],
+                  "nnz_mean": rep["nnz_mean"], "nnz_last": rep["nnz_last"],
+                  "density_mean": rep["nnz_mean"] / (m * n)},
+        "roofline_cg": cg_roofline(m, n, rep, kt),
         "kernel_ms": {k: {"total": v[0], "launches": v[1],
                           "avg": (v[0] / v[1]) if v[1] else None} for k, v in kt.items()},
     }

@@ -214,6 +214,7 @@ typedef struct {
     int64_t outer, newton, cg, sinkhorn, backtracks, stop_tests, passes;
     double grad_norm, primal, dual, rel_gap, kkt, dphi, marg_l1;
     double t_eval, t_sparsify, t_cg, t_linesearch, t_stop, t_total;  /* seconds */
+    double nnz_mean, nnz_last;  /* stored entries of the sparsified factors (mean, last) */
     int32_t status;
 } ibsn_report;
 

@@ -282,39 +282,53 @@ constexpr int ROWCH = 64;
 // the current row.  stage(i) runs before rows i .. i+ROWCH-1 are touched (it fills the
 // LDS row scalars; it begins and ends with a barrier); body(i, slot, x) processes row i
 // held in x, with slot = its index in the staged chunk.
-template <int NT, int Q, int QF, int VEC, bool VECOK, typename CT, typename Stage,
-          typename Body>
+template <int NT, int Q, int QF, int VEC, bool VECOK, bool PREFETCH, typename CT,
+          typename Stage, typename Body>
 __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc, int n, int i0,
                                            int i1, Stage &stage, Body &body)
 {
-    CT xr[Q * VEC], xn[Q * VEC];
-    if (i0 < i1)
-        load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i0 * ldc, n, xr);
-    for (int i = i0; i < i1; ++i) {
-        const int slot = (i - i0) & (ROWCH - 1);
-        if (slot == 0)
-            stage(i);
-        if (i + 1 < i1)
-            load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)(i + 1) * ldc, n, xn);
-        body(i, slot, xr);
+    CT xr[Q * VEC];
+    if constexpr (PREFETCH) {
+        CT xn[Q * VEC];
+        if (i0 < i1)
+            load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i0 * ldc, n, xr);
+        for (int i = i0; i < i1; ++i) {
+            const int slot = (i - i0) & (ROWCH - 1);
+            if (slot == 0)
+                stage(i);
+            if (i + 1 < i1)
+                load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)(i + 1) * ldc, n, xn);
+            body(i, slot, xr);
 #pragma unroll
-        for (int e = 0; e < Q * VEC; ++e)
-            xr[e] = xn[e];
+            for (int e = 0; e < Q * VEC; ++e)
+                xr[e] = xn[e];
+        }
+    } else {
+        for (int i = i0; i < i1; ++i) {
+            const int slot = (i - i0) & (ROWCH - 1);
+            if (slot == 0)
+                stage(i);
+            load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i * ldc, n, xr);
+            body(i, slot, xr);
+        }
     }
 }
 
 // 16-byte vector loads when the matrix start and the row pitch are 16-byte aligned and n
 // is a multiple of VEC (the same for every row); scalar loads otherwise.
-template <int NT, int Q, int QF, int VEC, typename CT, typename Stage, typename Body>
+// PREFETCH = false (passes whose per-entry state leaves no registers for a second row):
+// each row is loaded when it is reached.
+template <int NT, int Q, int QF, int VEC, bool PREFETCH = true, typename CT, typename Stage,
+          typename Body>
 __device__ __forceinline__ void row_loop(const CT *__restrict__ C, int64_t ldc, int n, int i0,
                                          int i1, Stage &&stage, Body &&body)
 {
     const bool vec_ok = (reinterpret_cast<uintptr_t>(C) & 15u) == 0 &&
                         ((uint64_t)ldc * sizeof(CT)) % 16 == 0 && n % VEC == 0;
     if (vec_ok)
-        row_loop_v<NT, Q, QF, VEC, true>(C, ldc, n, i0, i1, stage, body);
+        row_loop_v<NT, Q, QF, VEC, true, PREFETCH>(C, ldc, n, i0, i1, stage, body);
     else
-        row_loop_v<NT, Q, QF, VEC, false>(C, ldc, n, i0, i1, stage, body);
+        row_loop_v<NT, Q, QF, VEC, false, PREFETCH>(C, ldc, n, i0, i1, stage, body);
 }
 
 // Copy rows [i, min(i + ROWCH, i1)) of up to four m-vectors into LDS (null: skipped).
@@ -733,7 +747,7 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
            t_cf = 0.0;
     double azg = 0.0, azp = 0.0;
     const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
-    row_loop<NT, Q, QF, VEC>(
+    row_loop<NT, Q, QF, VEC, false>(
         C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA, z, rZ); },
         [&](int i, int slot, const CT *cst) {
         const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];

@@ -492,7 +492,7 @@ int ensure_cg(ibsn_ctx *ctx, int64_t m, int64_t n)
 int run_hvp(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
             const double *v, double *y)
 {
-    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus);
+    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->max_lds);
     CKH(launch_hvp(g, csr_view(c), a, eta, shift, v, y, P<double>(ctx->cg_au),
                    P<double>(ctx->cg_star), ctx->stream));
     return IBSN_OK;
@@ -517,7 +517,7 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     s.pap_part = P<double>(ctx->cg_pap);
     s.rr_part = P<double>(ctx->cg_rr);
     s.scal = P<double>(ctx->cg_scal);
-    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus);
+    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->max_lds);
     const CsrView cv = csr_view(c);
     KTimer kt(ctx, IBSN_KT_CG);
     CKH(launch_cg_init(c->n, rhs, tol, maxit, s, st));
@@ -1009,6 +1009,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     ibsn_report R;
     memset(&R, 0, sizeof(R));
     R.status = IBSN_WARN_MAXITER;
+    double nnz_sum = 0.0;
+    int64_t nnz_calls = 0;
     const double t0 = now_s();
     double stop_h[10] = {0};
     const int64_t k0 = k;
@@ -1049,6 +1051,9 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             ta = now_s();
             CKS(run_sparsify(ctx, prob, rp, k, q, M, S, rho, csr));   // step 7
             ++R.passes;
+            R.nnz_last = (double)csr->nnz;
+            nnz_sum += (double)csr->nnz;
+            ++nnz_calls;
             R.t_sparsify += now_s() - ta;
             ta = now_s();
             CKSH(sk_neg(n, g, Delta, st));   // rhs = -g
@@ -1149,6 +1154,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     R.outer = k - k0;
     CKSH(hipStreamSynchronize(st));
     R.t_total = now_s() - t0;
+    R.nnz_mean = nnz_calls > 0 ? nnz_sum / (double)nnz_calls : 0.0;
     if (gamma_io)
         CKSH(hipMemcpyAsync(gamma_io, gamma, n * 8, hipMemcpyDeviceToDevice, st));
     if (r_io)

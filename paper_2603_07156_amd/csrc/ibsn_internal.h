@@ -121,13 +121,15 @@ struct CsrView {
 // Launch shape of the two gathers of an HVP (and of the CG vector kernels).
 enum { CG_MAX_STAR = 64, CG_MAX_COLGROUPS = 2048, CG_MAX_UPDGROUPS = 128 };
 struct GatherPlan {
+    bool lds;                 // gathered vectors staged in LDS (persistent 1024-thread grid)
     int lpc_row, lpc_col;     // lanes per row / per column
     int row_blocks;           // workgroups of the sparse rows
     int nstar, star_chunk;    // dense-row chunks (extra workgroups) and their width
     int col_blocks;           // column-gather workgroups (grid-stride)
     int upd_blocks;           // CG update workgroups
 };
-GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus);
+GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus,
+                       size_t max_lds);
 
 // y = (H_rho + shift I) v; au (m) and star_part (CG_MAX_STAR) are scratch
 hipError_t launch_hvp(const GatherPlan &g, const CsrView &c, const double *a, double eta,

@@ -290,8 +290,9 @@ __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, int rb, const in
 // every consumer workgroup adds the producer's per-workgroup partials itself, in index
 // order, so all of them hold the same value and no device-scope fence is needed.
 //
-// cg_begin (all threads of a 256-thread workgroup) returns true when CG has finished
+// cg_begin (all threads of an NT-thread workgroup) returns true when CG has finished
 // before iteration `it`; otherwise beta for p = r + beta p.
+template <int NT>
 __device__ __forceinline__ bool cg_begin(int it, double *__restrict__ scal,
                                          const double *__restrict__ rr_part, int nrr, double *lds,
                                          double *beta_out)
@@ -312,9 +313,9 @@ __device__ __forceinline__ bool cg_begin(int it, double *__restrict__ scal,
         return true;
     }
     double t = 0.0;
-    for (int k = threadIdx.x; k < nrr; k += 256)
+    for (int k = threadIdx.x; k < nrr; k += NT)
         t += rr_part[k];
-    const double rr = block_sum<256>(t, lds);
+    const double rr = block_sum<NT>(t, lds);
     const double beta = rr / scal[CG_RR0 + ps];
     const bool brk = scal[CG_BRK] != 0.0;   // p.Ap <= 0 in iteration it-1: no step taken
     const bool done = brk || !(sqrt(rr) > scal[CG_TOL]) || (double)it >= scal[CG_MAXIT];
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(256) void k_cg_check(int it, double *__restrict__ s
 {
     __shared__ double lds[4];
     double beta;
-    (void)cg_begin(it, scal, rr_part, nrr, lds, &beta);
+    (void)cg_begin<256>(it, scal, rr_part, nrr, lds, &beta);
 }
 
 // au_i = a_i * sum_e val * v[col] for rows i != istar, LPC lanes per row.  The dense
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
     __shared__ double lds[4];
     const bool cgm = scal != nullptr;
     double beta = 0.0;
-    if (cgm && cg_begin(it, scal, rr_part, nrr, lds, &beta))
+    if (cgm && cg_begin<256>(it, scal, rr_part, nrr, lds, &beta))
         return;
     const int istar = *istar_p;
     if ((int)blockIdx.x >= row_blocks) {
@@ -464,6 +465,159 @@ __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__rest
     if (!cgm)
         return;
     pap = block_sum<256>(pap, lds);
+    if (threadIdx.x == 0)
+        pap_part[blockIdx.x] = pap;
+}
+
+// The same two gathers with the gathered vector staged in LDS by every workgroup
+// (n, respectively m, doubles), on a persistent grid of 1024-thread workgroups: the
+// sparse entries are then read as coalesced (index, value) streams and the vector from
+// LDS.  Summation order per row / column is the same as in the kernels above.
+template <int LPC>
+__global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val,
+                                                         const int32_t *__restrict__ len,
+                                                         const int *__restrict__ istar_p,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ v,
+                                                         double *__restrict__ au,
+                                                         double *__restrict__ star_part,
+                                                         int nstar, int star_chunk, int it,
+                                                         double *__restrict__ scal,
+                                                         const double *__restrict__ rr_part,
+                                                         int nrr,
+                                                         const double *__restrict__ r_vec)
+{
+    extern __shared__ double vs[];   // the gathered vector, n doubles
+    __shared__ double lds[16];
+    const bool cgm = scal != nullptr;
+    double beta = 0.0;
+    if (cgm && cg_begin<1024>(it, scal, rr_part, nrr, lds, &beta))
+        return;
+    for (int j = threadIdx.x; j < n; j += 1024)
+        vs[j] = cgm ? fma(beta, v[j], r_vec[j]) : v[j];
+    __syncthreads();
+    const int istar = *istar_p;
+    for (int c = blockIdx.x; c < nstar; c += gridDim.x) {
+        double t = 0.0;
+        if (istar >= 0) {
+            const int j0 = c * star_chunk, j1 = min(n, j0 + star_chunk);
+            const double *vr = val + (int64_t)istar * n;
+            for (int j = j0 + threadIdx.x; j < j1; j += 1024)
+                t = fma(vr[j], vs[j], t);
+        }
+        t = block_sum<1024>(t, lds);
+        if (threadIdx.x == 0)
+            star_part[c] = t;
+    }
+    constexpr int GPB = 1024 / LPC;
+    const int l = threadIdx.x % LPC;
+    for (int g = blockIdx.x * GPB + threadIdx.x / LPC; g < m; g += gridDim.x * GPB) {
+        if (g == istar)
+            continue;
+        const int L = len[g];
+        const int32_t *cr = col + (int64_t)g * n;
+        const double *vr = val + (int64_t)g * n;
+        double s = 0.0;
+        int e = l;
+        for (; e + 3 * LPC < L; e += 4 * LPC) {
+            const int j0 = cr[e], j1 = cr[e + LPC], j2 = cr[e + 2 * LPC], j3 = cr[e + 3 * LPC];
+            const double v0 = vr[e], v1 = vr[e + LPC], v2 = vr[e + 2 * LPC], v3 = vr[e + 3 * LPC];
+            s = fma(v0, vs[j0], s);
+            s = fma(v1, vs[j1], s);
+            s = fma(v2, vs[j2], s);
+            s = fma(v3, vs[j3], s);
+        }
+        for (; e < L; e += LPC)
+            s = fma(vr[e], vs[cr[e]], s);
+#pragma unroll
+        for (int o = LPC / 2; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, LPC);
+        if (l == 0)
+            au[g] = a[g] * s;
+    }
+}
+
+template <int LPC>
+__global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
+                                                         const int64_t *__restrict__ colptr,
+                                                         const int32_t *__restrict__ rowidx,
+                                                         const double *__restrict__ cval,
+                                                         const double *__restrict__ au,
+                                                         const double *__restrict__ d,
+                                                         const double *__restrict__ val,
+                                                         const int *__restrict__ istar_p,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ star_part,
+                                                         int nstar, double *__restrict__ v,
+                                                         double eta, double shift,
+                                                         double *__restrict__ y, int it,
+                                                         const double *__restrict__ scal,
+                                                         const double *__restrict__ r_vec,
+                                                         double *__restrict__ pap_part)
+{
+    extern __shared__ double us[];   // a_i (P p)_i, m doubles (entry istar unused)
+    __shared__ double lds[16];
+    const bool cgm = scal != nullptr;
+    double beta = 0.0;
+    if (cgm) {
+        const int cs = it & 1;
+        if (scal[CG_DONE0 + cs] != 0.0)
+            return;
+        beta = scal[CG_BETA0 + cs];
+    }
+    for (int i = threadIdx.x; i < m; i += 1024)
+        us[i] = au[i];
+    const int istar = *istar_p;
+    double aus = 0.0;
+    const double *prow = nullptr;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nstar; k += 1024)
+        t += star_part[k];
+    t = block_sum<1024>(t, lds);   // its barriers also publish us[]
+    if (istar >= 0) {
+        aus = a[istar] * t;
+        prow = val + (int64_t)istar * n;
+    }
+    constexpr int CPB = 1024 / LPC;
+    const int l = threadIdx.x % LPC;
+    double pap = 0.0;
+    for (int j = blockIdx.x * CPB + threadIdx.x / LPC; j < n; j += gridDim.x * CPB) {
+        const int64_t e0 = colptr[j], e1 = colptr[j + 1];
+        double s = 0.0;
+        int64_t e = e0 + l;
+        for (; e + 3 * LPC < e1; e += 4 * LPC) {
+            const int i0 = rowidx[e], i1 = rowidx[e + LPC], i2 = rowidx[e + 2 * LPC],
+                      i3 = rowidx[e + 3 * LPC];
+            const double c0 = cval[e], c1 = cval[e + LPC], c2 = cval[e + 2 * LPC],
+                         c3 = cval[e + 3 * LPC];
+            s = fma(c0, us[i0], s);
+            s = fma(c1, us[i1], s);
+            s = fma(c2, us[i2], s);
+            s = fma(c3, us[i3], s);
+        }
+        for (; e < e1; e += LPC)
+            s = fma(cval[e], us[rowidx[e]], s);
+#pragma unroll
+        for (int o = LPC / 2; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, LPC);
+        if (l == 0) {
+            double vj = v[j];
+            if (cgm) {
+                vj = fma(beta, vj, r_vec[j]);
+                v[j] = vj;
+            }
+            if (prow)
+                s = fma(prow[j], aus, s);
+            const double yj = (d[j] * vj - s) / eta + shift * vj;
+            y[j] = yj;
+            pap = fma(vj, yj, pap);
+        }
+    }
+    if (!cgm)
+        return;
+    pap = block_sum<1024>(pap, lds);
     if (threadIdx.x == 0)
         pap_part[blockIdx.x] = pap;
 }
@@ -587,9 +741,12 @@ __global__ __launch_bounds__(256) void k_export_csr(int m, int n, const int32_t 
 // ---------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------
-GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus)
+GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus,
+                       size_t max_lds)
 {
     GatherPlan g;
+    // the LDS-staged gathers hold an n-vector (rows) or an m-vector (columns) per workgroup
+    g.lds = (size_t)n * 8 + 256 <= max_lds && (size_t)m * 8 + 256 <= max_lds;
     const int64_t dense = istar >= 0 ? n : 0;
     const int64_t rows = istar >= 0 ? m - 1 : m;
     const double avg_row = rows > 0 ? (double)(nnz - dense) / (double)rows : 0.0;
@@ -608,6 +765,10 @@ GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num
     g.col_blocks = (int)std::min<int64_t>(need, std::min<int64_t>(CG_MAX_COLGROUPS, 4 * num_cus));
     if (g.col_blocks < 1)
         g.col_blocks = 1;
+    if (g.lds) {
+        g.row_blocks = num_cus;   // persistent: one 1024-thread workgroup per CU
+        g.col_blocks = (int)std::min<int64_t>(num_cus, CG_MAX_COLGROUPS);
+    }
     g.upd_blocks = (int)std::min<int64_t>((n + 255) / 256, CG_MAX_UPDGROUPS);
     if (g.upd_blocks < 1)
         g.upd_blocks = 1;
@@ -646,9 +807,15 @@ void row_gather_l(const GatherPlan &g, const CsrView &c, const double *a, const 
                   double *au, double *star_part, int it, double *scal, const double *rr_part,
                   int nrr, const double *r_vec, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_row_gather<L>), dim3(g.row_blocks + g.nstar), dim3(256), 0, st, (int)c.m,
-                       (int)c.n, c.col, c.val, c.len, c.istar, a, v, au, star_part, g.row_blocks,
-                       g.star_chunk, it, scal, rr_part, nrr, r_vec);
+    if (g.lds)
+        hipLaunchKernelGGL((k_row_gather_lds<L>), dim3(g.row_blocks), dim3(1024),
+                           (size_t)c.n * sizeof(double), st, (int)c.m, (int)c.n, c.col, c.val,
+                           c.len, c.istar, a, v, au, star_part, g.nstar, g.star_chunk, it, scal,
+                           rr_part, nrr, r_vec);
+    else
+        hipLaunchKernelGGL((k_row_gather<L>), dim3(g.row_blocks + g.nstar), dim3(256), 0, st,
+                           (int)c.m, (int)c.n, c.col, c.val, c.len, c.istar, a, v, au, star_part,
+                           g.row_blocks, g.star_chunk, it, scal, rr_part, nrr, r_vec);
 }
 
 void row_gather(const GatherPlan &g, const CsrView &c, const double *a, const double *v,
@@ -668,9 +835,15 @@ void col_gather_l(const GatherPlan &g, const CsrView &c, const double *a, const 
                   const double *star_part, double *v, double eta, double shift, double *y, int it,
                   const double *scal, const double *r_vec, double *pap_part, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_col_gather<L>), dim3(g.col_blocks), dim3(256), 0, st, (int)c.n, c.colptr,
-                       c.rowidx, c.cval, au, c.d, c.val, c.istar, a, star_part, g.nstar, v, eta,
-                       shift, y, it, scal, r_vec, pap_part);
+    if (g.lds)
+        hipLaunchKernelGGL((k_col_gather_lds<L>), dim3(g.col_blocks), dim3(1024),
+                           (size_t)c.m * sizeof(double), st, (int)c.m, (int)c.n, c.colptr,
+                           c.rowidx, c.cval, au, c.d, c.val, c.istar, a, star_part, g.nstar, v,
+                           eta, shift, y, it, scal, r_vec, pap_part);
+    else
+        hipLaunchKernelGGL((k_col_gather<L>), dim3(g.col_blocks), dim3(256), 0, st, (int)c.n,
+                           c.colptr, c.rowidx, c.cval, au, c.d, c.val, c.istar, a, star_part,
+                           g.nstar, v, eta, shift, y, it, scal, r_vec, pap_part);
 }
 
 void col_gather(const GatherPlan &g, const CsrView &c, const double *a, const double *au,

@@ -63,6 +63,7 @@ class Report(ct.Structure):
         ("marg_l1", ct.c_double),
         ("t_eval", ct.c_double), ("t_sparsify", ct.c_double), ("t_cg", ct.c_double),
         ("t_linesearch", ct.c_double), ("t_stop", ct.c_double), ("t_total", ct.c_double),
+        ("nnz_mean", ct.c_double), ("nnz_last", ct.c_double),
         ("status", ct.c_int32),
     ]
 
