@@ -35,9 +35,7 @@ struct ibsn_csr {
     int64_t m = 0, n = 0;
     int64_t nnz = 0;       // host copy (valid after sparsify)
     int64_t istar = -1;    // host copy
-    DevBuf col, val, len, colptr, colcnt, rowidx, cval, blkcnt, d, istar_dev, nnz_dev;
-    int rb = 0;
-    bool abs64 = false;
+    DevBuf col, val, len, colptr, colcnt, rowidx, cval, mask, off, d, istar_dev, nnz_dev;
 };
 
 struct ibsn_ctx {
@@ -395,12 +393,6 @@ int csr_alloc(ibsn_ctx *ctx, ibsn_csr *c, int64_t m, int64_t n)
     const size_t mn = (size_t)m * (size_t)n;
     c->m = m;
     c->n = n;
-    // row blocks of the transpose: two per CU; the fill keeps a cursor per column in LDS,
-    // as int64 positions when they fit beside the row lengths, else as int32 ranks
-    c->rb = (int)std::min<int64_t>(m, 2 * (int64_t)ctx->num_cus);
-    c->abs64 = csc_fill_lds(m, n, c->rb, true) <= ctx->max_lds;
-    if (!c->abs64 && csc_fill_lds(m, n, c->rb, false) > ctx->max_lds)
-        c->rb = (int)std::min<int64_t>(m, std::max<int64_t>(c->rb, (m + 1023) / 1024));
     CKI(ensure(ctx, c->col, mn * 4));
     CKI(ensure(ctx, c->val, mn * 8));
     CKI(ensure(ctx, c->len, (size_t)m * 4));
@@ -408,7 +400,8 @@ int csr_alloc(ibsn_ctx *ctx, ibsn_csr *c, int64_t m, int64_t n)
     CKI(ensure(ctx, c->colcnt, (size_t)n * 8));
     CKI(ensure(ctx, c->rowidx, mn * 4));
     CKI(ensure(ctx, c->cval, mn * 8));
-    CKI(ensure(ctx, c->blkcnt, (size_t)c->rb * n * 4));
+    CKI(ensure(ctx, c->mask, (size_t)csc_row_blocks(m) * n * 4));
+    CKI(ensure(ctx, c->off, (size_t)csc_row_blocks(m) * n * 4));
     CKI(ensure(ctx, c->d, (size_t)n * 8));
     CKI(ensure(ctx, c->istar_dev, 16));
     CKI(ensure(ctx, c->nnz_dev, 16));
@@ -418,7 +411,7 @@ int csr_alloc(ibsn_ctx *ctx, ibsn_csr *c, int64_t m, int64_t n)
 void csr_release(ibsn_csr *c)
 {
     DevBuf *bufs[] = {&c->col, &c->val, &c->len, &c->colptr, &c->colcnt, &c->rowidx,
-                      &c->cval, &c->blkcnt, &c->d, &c->istar_dev, &c->nnz_dev};
+                      &c->cval, &c->mask, &c->off, &c->d, &c->istar_dev, &c->nnz_dev};
     for (DevBuf *b : bufs)
         release(*b);
 }
@@ -441,9 +434,10 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     cw.colcnt = P<int64_t>(c->colcnt);
     cw.rowidx = P<int32_t>(c->rowidx);
     cw.cval = P<double>(c->cval);
-    cw.blkcnt = P<int32_t>(c->blkcnt);
-    cw.rb = c->rb;
-    cw.abs64 = c->abs64;
+    cw.mask = P<uint32_t>(c->mask);
+    cw.off = P<int32_t>(c->off);
+    // lanes per row of the fill from the previous factor's mean row length (64 at first)
+    cw.lpc = (c->nnz > 0 && (double)c->nnz / (double)c->m < 96.0) ? 16 : 64;
     {
         KTimer kt(ctx, IBSN_KT_CSC);
         CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), P<double>(c->val),
@@ -604,7 +598,8 @@ void ibsn_destroy(ibsn_ctx *ctx)
     }
     DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
-                      &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv, &ctx->cg_x, &ctx->cg_r,
+                      &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv,
+                      &ctx->cg_x, &ctx->cg_r,
                       &ctx->cg_p,
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_star, &ctx->cg_pap, &ctx->cg_rr,
                       &ctx->cg_scal, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,

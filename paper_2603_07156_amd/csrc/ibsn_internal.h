@@ -94,12 +94,12 @@ struct CscWork {
     int64_t *colcnt;     // n
     int32_t *rowidx;     // capacity m*n
     double *cval;        // capacity m*n
-    int32_t *blkcnt;     // rb * n
-    int rb;              // row blocks used for the deterministic transpose
-    bool abs64;          // fill cursor holds int64 positions (n*8 bytes of LDS)
+    uint32_t *mask;      // csc_row_blocks(m) * n: rows of a 32-row block keeping column j
+    int32_t *off;        // csc_row_blocks(m) * n: exclusive scan of the mask popcounts
+    int lpc;             // lanes per row of the fill (16 or 64)
 };
-// LDS bytes of the fill kernel (cursor array plus the block's row lengths)
-size_t csc_fill_lds(int64_t m, int64_t n, int rb, bool abs64);
+// number of 32-row blocks of the transpose
+int csc_row_blocks(int64_t m);
 // transpose of the slotted rows without the dense row istar (device scalar)
 hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
                             const int32_t *len, const int *istar, CscWork &w, int64_t *nnz_dev,

@@ -54,26 +54,28 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
 // deterministic transpose of the slotted rows (the dense row istar is not included:
 // the column gather reads it directly from its row slot, where it is stored whole in
 // column order)
+//
+// Rows are grouped in blocks of CSC_RB = 32.  For block b and column j, bit r of
+// mask[b][j] says that row 32 b + r keeps column j.  The position of entry (i, j) in
+// column j is then
+//     colptr[j] + off[b][j] + popcount(mask[b][j] & ((1 << r) - 1)),
+// with off the exclusive scan over blocks of the mask popcounts, which lists every
+// column's rows in ascending order; the fill needs no ordering between threads.
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ void block_rows(int m, int rb, int b, int &i0, int &i1)
-{
-    i0 = (int)((int64_t)m * b / rb);
-    i1 = (int)((int64_t)m * (b + 1) / rb);
-}
+constexpr int CSC_RB = 32;
 
-// cnt[b][j] = number of entries of column j in row block b.  Histogram in LDS (n ints);
-// the four waves take rows round robin (LDS atomics: counts do not depend on order).
-__global__ __launch_bounds__(256) void k_csc_count(int m, int n, int rb, const int32_t *__restrict__ col,
-                                                   const int32_t *__restrict__ len,
-                                                   const int *__restrict__ istar_p,
-                                                   int32_t *__restrict__ cnt)
+// mask[b][j]: one workgroup per row block, masks built in LDS (n words) with atomic ORs
+// (order-free), then written out.
+__global__ __launch_bounds__(256) void k_csc_mask(int m, int n, const int32_t *__restrict__ col,
+                                                  const int32_t *__restrict__ len,
+                                                  const int *__restrict__ istar_p,
+                                                  uint32_t *__restrict__ mask)
 {
-    extern __shared__ int32_t hist[];
+    extern __shared__ uint32_t mk[];
     const int b = blockIdx.x;
-    int i0, i1;
-    block_rows(m, rb, b, i0, i1);
+    const int i0 = b * CSC_RB, i1 = min(m, i0 + CSC_RB);
     for (int j = threadIdx.x; j < n; j += 256)
-        hist[j] = 0;
+        mk[j] = 0u;
     __syncthreads();
     const int istar = *istar_p;
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
@@ -82,17 +84,21 @@ __global__ __launch_bounds__(256) void k_csc_count(int m, int n, int rb, const i
             continue;
         const int L = len[i];
         const int32_t *cr = col + (int64_t)i * n;
+        const uint32_t bit = 1u << (i - i0);
         for (int e = lane; e < L; e += WAVE)
-            atomicAdd(&hist[cr[e]], 1);
+            atomicOr(&mk[cr[e]], bit);
     }
     __syncthreads();
-    int32_t *cb = cnt + (int64_t)b * n;
+    uint32_t *mb = mask + (int64_t)b * n;
     for (int j = threadIdx.x; j < n; j += 256)
-        cb[j] = hist[j];
+        mb[j] = mk[j];
 }
 
-// per column: exclusive scan of cnt over row blocks (in place); colcnt_j = total
-__global__ __launch_bounds__(256) void k_csc_blockscan(int n, int rb, int32_t *__restrict__ cnt,
+// per column: off[b][j] = number of kept rows of column j in blocks before b;
+// colcnt_j = total.
+__global__ __launch_bounds__(256) void k_csc_blockscan(int n, int rb,
+                                                       const uint32_t *__restrict__ mask,
+                                                       int32_t *__restrict__ off,
                                                        int64_t *__restrict__ colcnt)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -102,20 +108,20 @@ __global__ __launch_bounds__(256) void k_csc_blockscan(int n, int rb, int32_t *_
     int32_t run = 0;
     int b = 0;
     for (; b + U <= rb; b += U) {
-        int32_t t[U];
+        uint32_t t[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            t[u] = cnt[(int64_t)(b + u) * n + j];
+            t[u] = mask[(int64_t)(b + u) * n + j];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            cnt[(int64_t)(b + u) * n + j] = run;
-            run += t[u];
+            off[(int64_t)(b + u) * n + j] = run;
+            run += __popc(t[u]);
         }
     }
     for (; b < rb; ++b) {
-        const int32_t t = cnt[(int64_t)b * n + j];
-        cnt[(int64_t)b * n + j] = run;
-        run += t;
+        const uint32_t t = mask[(int64_t)b * n + j];
+        off[(int64_t)b * n + j] = run;
+        run += __popc(t);
     }
     colcnt[j] = run;
 }
@@ -188,96 +194,34 @@ __global__ __launch_bounds__(1024) void k_scan32(int n, const int32_t *__restric
     }
 }
 
-// fill: row block b walks its rows in order with a per-column cursor in LDS (within a
-// row every column occurs once, so a barrier between rows is all the ordering needed).
-// ABS64: the cursor holds the absolute CSC position (int64, n*8 bytes of LDS);
-// otherwise the rank within the column (int32) and the column start is read per entry.
-// Work items are chunks of CSC_FK*256 entries of one row; the next item's indices and
-// values are loaded before the current one is scattered.
-constexpr int CSC_FK = 4;
-
-template <bool ABS64>
-__global__ __launch_bounds__(256) void k_csc_fill(int m, int n, int rb, const int32_t *__restrict__ col,
+// fill: LPC lanes per row, every entry independently (see the position formula above)
+template <int LPC>
+__global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *__restrict__ col,
                                                   const double *__restrict__ val,
                                                   const int32_t *__restrict__ len,
                                                   const int *__restrict__ istar_p,
                                                   const int64_t *__restrict__ colptr,
-                                                  const int32_t *__restrict__ blkoff,
+                                                  const uint32_t *__restrict__ mask,
+                                                  const int32_t *__restrict__ off,
                                                   int32_t *__restrict__ rowidx,
                                                   double *__restrict__ cval)
 {
-    extern __shared__ int64_t smem64[];
-    int64_t *cur64 = smem64;
-    int32_t *cur32 = reinterpret_cast<int32_t *>(smem64);
-    const int b = blockIdx.x;
-    int i0, i1;
-    block_rows(m, rb, b, i0, i1);
-    const int R = i1 - i0;
-    int32_t *lens = reinterpret_cast<int32_t *>(
-        reinterpret_cast<unsigned char *>(smem64) + (ABS64 ? 8 : 4) * (size_t)((n + 1) & ~1));
-    const int istar = *istar_p;
-    const int32_t *bo = blkoff + (int64_t)b * n;
-    for (int j = threadIdx.x; j < n; j += 256) {
-        if (ABS64)
-            cur64[j] = colptr[j] + bo[j];
-        else
-            cur32[j] = bo[j];
-    }
-    for (int r = threadIdx.x; r < R; r += 256)
-        lens[r] = (i0 + r == istar) ? 0 : len[i0 + r];
-    __syncthreads();
-
-    int jj[CSC_FK], nj[CSC_FK];
-    double vv[CSC_FK], nv[CSC_FK];
-    auto fetch = [&](int r, int e0, int *J, double *V) {
-        const int L = lens[r];
-        const int32_t *cr = col + (int64_t)(i0 + r) * n;
-        const double *vr = val + (int64_t)(i0 + r) * n;
-#pragma unroll
-        for (int k = 0; k < CSC_FK; ++k) {
-            const int e = e0 + k * 256 + threadIdx.x;
-            J[k] = e < L ? cr[e] : 0;
-            V[k] = e < L ? vr[e] : 0.0;
-        }
-    };
-    int r = 0, e0 = 0;
-    if (R > 0)
-        fetch(0, 0, jj, vv);
-    while (r < R) {
-        const int L = lens[r];
-        int nr = r, ne = e0 + CSC_FK * 256;
-        if (ne >= L) {
-            nr = r + 1;
-            ne = 0;
-        }
-        if (nr < R)
-            fetch(nr, ne, nj, nv);
-#pragma unroll
-        for (int k = 0; k < CSC_FK; ++k) {
-            const int e = e0 + k * 256 + threadIdx.x;
-            if (e < L) {
-                const int j = jj[k];
-                int64_t pos;
-                if (ABS64) {
-                    pos = cur64[j];
-                    cur64[j] = pos + 1;
-                } else {
-                    const int32_t c = cur32[j];
-                    cur32[j] = c + 1;
-                    pos = colptr[j] + c;
-                }
-                rowidx[pos] = i0 + r;
-                cval[pos] = vv[k];
-            }
-        }
-        __syncthreads();
-        r = nr;
-        e0 = ne;
-#pragma unroll
-        for (int k = 0; k < CSC_FK; ++k) {
-            jj[k] = nj[k];
-            vv[k] = nv[k];
-        }
+    const int i = (blockIdx.x * 256 + threadIdx.x) / LPC;
+    const int l = threadIdx.x % LPC;
+    if (i >= m || i == *istar_p)
+        return;
+    const int L = len[i];
+    const int32_t *cr = col + (int64_t)i * n;
+    const double *vr = val + (int64_t)i * n;
+    const int b = i / CSC_RB;
+    const uint32_t below = (1u << (i - b * CSC_RB)) - 1u;
+    const uint32_t *mb = mask + (int64_t)b * n;
+    const int32_t *ob = off + (int64_t)b * n;
+    for (int e = l; e < L; e += LPC) {
+        const int j = cr[e];
+        const int64_t pos = colptr[j] + ob[j] + __popc(mb[j] & below);
+        rowidx[pos] = i;
+        cval[pos] = vr[e];
     }
 }
 
@@ -469,6 +413,31 @@ __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__rest
         pap_part[blockIdx.x] = pap;
 }
 
+constexpr int GUNR = 8;   // loads in flight per lane in the LDS-staged gathers
+
+// dst[j] = beta * v[j] + r[j] (r null: dst[j] = v[j]) for j < len, 1024 threads, with
+// eight independent loads in flight per thread (a plain strided loop waits on each load)
+__device__ __forceinline__ void stage_vec(double *dst, const double *__restrict__ v,
+                                          const double *__restrict__ r, double beta, int len)
+{
+    constexpr int U = 8;
+    for (int j0 = threadIdx.x; j0 < len; j0 += U * 1024) {
+        double a[U], b[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j = j0 + k * 1024;
+            a[k] = j < len ? v[j] : 0.0;
+            b[k] = (r && j < len) ? r[j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j = j0 + k * 1024;
+            if (j < len)
+                dst[j] = r ? fma(beta, a[k], b[k]) : a[k];
+        }
+    }
+}
+
 // The same two gathers with the gathered vector staged in LDS by every workgroup
 // (n, respectively m, doubles), on a persistent grid of 1024-thread workgroups: the
 // sparse entries are then read as coalesced (index, value) streams and the vector from
@@ -495,8 +464,7 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
     double beta = 0.0;
     if (cgm && cg_begin<1024>(it, scal, rr_part, nrr, lds, &beta))
         return;
-    for (int j = threadIdx.x; j < n; j += 1024)
-        vs[j] = cgm ? fma(beta, v[j], r_vec[j]) : v[j];
+    stage_vec(vs, v, cgm ? r_vec : nullptr, beta, n);
     __syncthreads();
     const int istar = *istar_p;
     for (int c = blockIdx.x; c < nstar; c += gridDim.x) {
@@ -511,26 +479,31 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
         if (threadIdx.x == 0)
             star_part[c] = t;
     }
+    // rows interleaved over the workgroups (row g in workgroup g mod grid), so that every
+    // workgroup gets an equal share even when m < grid * groups per workgroup
     constexpr int GPB = 1024 / LPC;
     const int l = threadIdx.x % LPC;
-    for (int g = blockIdx.x * GPB + threadIdx.x / LPC; g < m; g += gridDim.x * GPB) {
+    for (int g = blockIdx.x + gridDim.x * (threadIdx.x / LPC); g < m; g += gridDim.x * GPB) {
         if (g == istar)
             continue;
         const int L = len[g];
         const int32_t *cr = col + (int64_t)g * n;
         const double *vr = val + (int64_t)g * n;
         double s = 0.0;
-        int e = l;
-        for (; e + 3 * LPC < L; e += 4 * LPC) {
-            const int j0 = cr[e], j1 = cr[e + LPC], j2 = cr[e + 2 * LPC], j3 = cr[e + 3 * LPC];
-            const double v0 = vr[e], v1 = vr[e + LPC], v2 = vr[e + 2 * LPC], v3 = vr[e + 3 * LPC];
-            s = fma(v0, vs[j0], s);
-            s = fma(v1, vs[j1], s);
-            s = fma(v2, vs[j2], s);
-            s = fma(v3, vs[j3], s);
+        // each lane issues GUNR (index, value) loads before using any of them
+        for (int base = l; base < L; base += GUNR * LPC) {
+            int jj[GUNR];
+            double vv[GUNR];
+#pragma unroll
+            for (int k = 0; k < GUNR; ++k) {
+                const int e = base + k * LPC;
+                jj[k] = e < L ? cr[e] : 0;
+                vv[k] = e < L ? vr[e] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < GUNR; ++k)
+                s = fma(vv[k], vs[jj[k]], s);
         }
-        for (; e < L; e += LPC)
-            s = fma(vr[e], vs[cr[e]], s);
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
             s += __shfl_xor(s, o, LPC);
@@ -567,8 +540,7 @@ __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
             return;
         beta = scal[CG_BETA0 + cs];
     }
-    for (int i = threadIdx.x; i < m; i += 1024)
-        us[i] = au[i];
+    stage_vec(us, au, nullptr, 0.0, m);
     const int istar = *istar_p;
     double aus = 0.0;
     const double *prow = nullptr;
@@ -583,22 +555,22 @@ __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
     constexpr int CPB = 1024 / LPC;
     const int l = threadIdx.x % LPC;
     double pap = 0.0;
-    for (int j = blockIdx.x * CPB + threadIdx.x / LPC; j < n; j += gridDim.x * CPB) {
+    for (int j = blockIdx.x + gridDim.x * (threadIdx.x / LPC); j < n; j += gridDim.x * CPB) {
         const int64_t e0 = colptr[j], e1 = colptr[j + 1];
         double s = 0.0;
-        int64_t e = e0 + l;
-        for (; e + 3 * LPC < e1; e += 4 * LPC) {
-            const int i0 = rowidx[e], i1 = rowidx[e + LPC], i2 = rowidx[e + 2 * LPC],
-                      i3 = rowidx[e + 3 * LPC];
-            const double c0 = cval[e], c1 = cval[e + LPC], c2 = cval[e + 2 * LPC],
-                         c3 = cval[e + 3 * LPC];
-            s = fma(c0, us[i0], s);
-            s = fma(c1, us[i1], s);
-            s = fma(c2, us[i2], s);
-            s = fma(c3, us[i3], s);
+        for (int64_t base = e0 + l; base < e1; base += GUNR * LPC) {
+            int ii[GUNR];
+            double cc[GUNR];
+#pragma unroll
+            for (int k = 0; k < GUNR; ++k) {
+                const int64_t e = base + k * LPC;
+                ii[k] = e < e1 ? rowidx[e] : 0;
+                cc[k] = e < e1 ? cval[e] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < GUNR; ++k)
+                s = fma(cc[k], us[ii[k]], s);
         }
-        for (; e < e1; e += LPC)
-            s = fma(cval[e], us[rowidx[e]], s);
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
             s += __shfl_xor(s, o, LPC);
@@ -754,6 +726,12 @@ GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num
     auto lanes = [](double avg) { return avg >= 96.0 ? 64 : (avg >= 12.0 ? 16 : 4); };
     g.lpc_row = lanes(avg_row);
     g.lpc_col = lanes(avg_col);
+    if (g.lds) {
+        // with the vector in LDS and GUNR loads in flight per lane, several rows per wave
+        // beat one long row per wave
+        g.lpc_row = avg_row >= 12.0 ? 16 : 4;
+        g.lpc_col = avg_col >= 12.0 ? 16 : 4;
+    }
     g.row_blocks = (int)((m * g.lpc_row + 255) / 256);
     g.star_chunk = 1024;
     g.nstar = (int)((n + g.star_chunk - 1) / g.star_chunk);
@@ -775,29 +753,27 @@ GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num
     return g;
 }
 
-size_t csc_fill_lds(int64_t m, int64_t n, int rb, bool abs64)
-{
-    const int64_t rows = (m + rb - 1) / rb;
-    return (size_t)(abs64 ? 8 : 4) * (size_t)((n + 1) & ~1) + (size_t)rows * 4;
-}
+int csc_row_blocks(int64_t m) { return (int)((m + CSC_RB - 1) / CSC_RB); }
 
 hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
                             const int32_t *len, const int *istar, CscWork &w, int64_t *nnz_dev,
                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_csc_count, dim3(w.rb), dim3(256), (size_t)n * 4, st, (int)m, (int)n, w.rb,
-                       col, len, istar, w.blkcnt);
+    const int rb = csc_row_blocks(m);
+    hipLaunchKernelGGL(k_csc_mask, dim3(rb), dim3(256), (size_t)n * 4, st, (int)m, (int)n, col, len,
+                       istar, w.mask);
     hipLaunchKernelGGL(k_csc_blockscan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       (int)n, w.rb, w.blkcnt, w.colcnt);
+                       (int)n, rb, w.mask, w.off, w.colcnt);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (int)n, w.colcnt, w.colptr, nnz_dev, len,
                        istar);
-    const size_t lds = csc_fill_lds(m, n, w.rb, w.abs64);
-    if (w.abs64)
-        hipLaunchKernelGGL((k_csc_fill<true>), dim3(w.rb), dim3(256), lds, st, (int)m, (int)n, w.rb,
-                           col, val, len, istar, w.colptr, w.blkcnt, w.rowidx, w.cval);
+    const int lpc = w.lpc;
+    const unsigned blocks = (unsigned)((m * lpc + 255) / 256);
+    if (lpc >= 64)
+        hipLaunchKernelGGL((k_csc_fill<64>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col,
+                           val, len, istar, w.colptr, w.mask, w.off, w.rowidx, w.cval);
     else
-        hipLaunchKernelGGL((k_csc_fill<false>), dim3(w.rb), dim3(256), lds, st, (int)m, (int)n,
-                           w.rb, col, val, len, istar, w.colptr, w.blkcnt, w.rowidx, w.cval);
+        hipLaunchKernelGGL((k_csc_fill<16>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col,
+                           val, len, istar, w.colptr, w.mask, w.off, w.rowidx, w.cval);
     return hipGetLastError();
 }
 
@@ -824,6 +800,8 @@ void row_gather(const GatherPlan &g, const CsrView &c, const double *a, const do
 {
     if (g.lpc_row >= 64)
         row_gather_l<64>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
+    else if (g.lpc_row >= 32)
+        row_gather_l<32>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
     else if (g.lpc_row >= 16)
         row_gather_l<16>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
     else
@@ -852,6 +830,8 @@ void col_gather(const GatherPlan &g, const CsrView &c, const double *a, const do
 {
     if (g.lpc_col >= 64)
         col_gather_l<64>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec, pap_part, st);
+    else if (g.lpc_col >= 32)
+        col_gather_l<32>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec, pap_part, st);
     else if (g.lpc_col >= 16)
         col_gather_l<16>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec, pap_part, st);
     else

@@ -149,6 +149,7 @@ class Context:
 
     def __init__(self, device: int | torch.device = 0, stream: torch.cuda.Stream | None = None):
         L = load()
+        self._lib = L   # handles are released through the library that made them
         self.device = torch.device("cuda", device) if isinstance(device, int) else device
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ct.c_void_p()
@@ -178,7 +179,7 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            load().ibsn_destroy(self.h)
+            self._lib.ibsn_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -306,7 +307,7 @@ class Csr:
 
     def free(self):
         if self.h:
-            load().ibsn_csr_free(self.h)
+            self.ctx._lib.ibsn_csr_free(self.h)
             self.h = None
 
     def __del__(self):
