@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# HBM counters of the LSE pass (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy of known
+# size); used only while they describe the dense-pass source that is built
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_uniform10000_hbm_counters.md")
 METRIC = ("time to 1e-8 OT gap at n=10k (plain vs warm-start+FP32); LSE-pass HBM GB/s")
 HBM_PEAK_GBS = 8000.0
 
@@ -103,7 +106,7 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_2603_07156_amd import ibsn, workloads
+    from paper_2603_07156_amd import ibsn, probe, workloads
 
     dev = torch.device("cuda", 0)
     inst = workloads.uniform_points(args.n, args.seed)
@@ -157,7 +160,8 @@ def main() -> int:
                                f"IBSN outer iteration (k = {args.warmup}..{args.warmup + steps - 1})",
                    "m": m, "n": n, "eta": inst.eta},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": probe.read_traffic(TRAFFIC_MD) if args.n == 10000 else None,
                      "kernel": "row-LSE eval pass (k_eval)", "bytes_per_launch": pb,
                      "avg_launch_ms": eval_avg_ms, "launches": eval_n},
         "solve": {"outer_per_s": steps / dt, "dense_passes": rep["passes"],
