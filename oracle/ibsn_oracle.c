@@ -587,6 +587,8 @@ typedef struct {
     int rho_mode;                     /* 0 paper rule, 1 rho = 0 (no sparsification) */
     double cg_rtol_min;               /* 1e-6: floor of the CG relative residual */
     int stall_limit;                  /* 3 failed D_phi tests after the gate end the inner loop */
+    int eot;                          /* 1: (E)IBSN of appendix C.4: centre 1 1^T, one subproblem */
+    double eot_tol;                   /* (E)IBSN stops at ||g|| < eot_tol (1e-9, appendix C.4) */
 } orc_options;
 
 typedef struct {
@@ -614,6 +616,8 @@ void orc_default_options(orc_options *o)
     o->rho_mode = 0;
     o->cg_rtol_min = 1e-6;
     o->stall_limit = 3;
+    o->eot = 0;
+    o->eot_tol = 1e-9;
 }
 
 static double nrm1(int64_t n, const double *x)
@@ -674,6 +678,12 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         k = *k_io;
         memcpy(r, r_io, sizeof(double) * m);
         memcpy(s, s_io, sizeof(double) * n);
+    } else if (opt.eot) {
+        /* (E)IBSN: X^0 = 1 1^T (appendix C.4), so the subproblem is entropic OT with cost C */
+        for (int64_t i = 0; i < m; ++i)
+            r[i] = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            s[j] = 0.0;
     } else {
         for (int64_t i = 0; i < m; ++i)
             r[i] = log(a[i]);
@@ -725,6 +735,10 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         int64_t newton_k = 0, cg_k = 0;
         for (int v = 0; v < opt.max_newton; ++v) {
             double gn = nrm2(n, g);
+            if (opt.eot && gn < opt.eot_tol) { /* (E)IBSN: the single subproblem is solved */
+                stopped = 1;
+                break;
+            }
             double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / ((double)m * (double)n); /* step 6 */
             int64_t nnz = orc_sparsify(m, n, C, kind, ldc, k, eta, w, a, M, S, rho, istar, 0,
                                        row_ptr, NULL, NULL, NULL);
@@ -767,7 +781,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             memcpy(g, gt, sizeof(double) * n);
             ++newton_k;
             /* step 12 with the practical schedule: gradient gate, then D_phi test */
-            if (nrm2(n, g) < mu) {
+            if (!opt.eot && nrm2(n, g) < mu) {
                 gamma_of(n, w, s, eta, gamma);
                 orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, NULL);
                 ++R.stop_tests;
@@ -780,7 +794,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             }
         }
         gamma_of(n, w, s, eta, gamma);
-        if (!stopped) {
+        if (!stopped || opt.eot) {
             orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, NULL);
             ++R.stop_tests;
         }
@@ -807,6 +821,14 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         R.marg_l1 = marg;
         int done = (relgap <= opt.gap_tol && (opt.marg_tol <= 0 || marg <= opt.marg_tol)) ||
                    (opt.kkt_tol > 0 && stop_out[4] <= opt.kkt_tol);
+        if (opt.eot) {
+            /* (E)IBSN: one subproblem, no outer update; done when its gradient is small */
+            if (plan_out)
+                orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, plan_out);
+            R.status = R.grad_norm < opt.eot_tol ? ORC_OK : ORC_WARN_MAXITER;
+            ++k; /* one subproblem solved; the centre (r, s) = (0, 0) is left as it was */
+            break;
+        }
         if (plan_out && (done || k + 1 == k0 + opt.max_outer))
             orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, plan_out);
         /* Algorithm 2, step 13: X^{k+1} = X^{k,v+1}: r = log a - lse, s = w, k = k+1;

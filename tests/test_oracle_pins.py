@@ -420,3 +420,23 @@ def test_resume_matches_uninterrupted():
     assert rest["k"] == full["k"] == 12
     np.testing.assert_array_equal(rest["gamma"], full["gamma"])
     np.testing.assert_array_equal(rest["s"], full["s"])
+
+
+def test_p16_eibsn_single_subproblem_is_entropic_ot():
+    # (E)IBSN (appendix C.4): prox centre 1 1^T and one subproblem solved to a small gradient;
+    # its plan diag(a) P(gamma) is the entropic OT plan at epsilon = eta, here computed
+    # independently by log-domain Sinkhorn
+    inst = W.gmm_points(12, 41, m=9)
+    eta = 0.15
+    opt = orc.default_options(eot=1, eot_tol=1e-13, max_newton=200)
+    res = orc.solve(inst.C, inst.a, inst.b, eta, options=opt)
+    rep = res["report"]
+    assert res["status"] == 0 and rep["outer"] == 1 and rep["grad_norm"] < 1e-13
+    m, n = inst.C.shape
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, res["gamma"], r=np.zeros(m), s=np.zeros(n),
+                       k=0, want_plan=True)
+    Xe = log_sinkhorn(inst.C, inst.a, inst.b, eta)
+    np.testing.assert_allclose(ev.plan, Xe, rtol=0, atol=1e-12)
+    # rows are exact by construction; columns to the gradient tolerance
+    np.testing.assert_allclose(ev.plan.sum(1), inst.a, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ev.plan.sum(0), inst.b, rtol=0, atol=1e-13)
