@@ -206,7 +206,10 @@ typedef struct {
     int32_t rho_mode;                    /*   cg_rtol_min) ||g||; rho_mode 0: rho =       */
     double cg_rtol_min;                  /*   eta ||g|| / (m n), 1: rho = 0; 1e-6          */
     int32_t stall_limit;                 /* 3: failed D_phi tests (gate passed) that end   */
-} ibsn_options;                          /*    the inner loop of one outer iteration       */
+                                         /*    the inner loop of one outer iteration       */
+    int32_t eot;                         /* 1: (E)IBSN of appendix C.4: prox centre 1 1^T,  */
+    double eot_tol;                      /*    one subproblem until ||g|| < eot_tol (1e-9) */
+} ibsn_options;
 
 void ibsn_default_options(ibsn_options *opt);
 

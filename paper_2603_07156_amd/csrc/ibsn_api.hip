@@ -667,6 +667,8 @@ void ibsn_default_options(ibsn_options *o)
     o->rho_mode = 0;
     o->cg_rtol_min = 1e-6;
     o->stall_limit = 3;
+    o->eot = 0;
+    o->eot_tol = 1e-9;
 }
 
 int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
@@ -902,7 +904,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     else
         ibsn_default_options(&opt);
     if (opt.max_outer < 1 || opt.max_newton < 1 || opt.max_backtrack < 0 ||
-        !(opt.beta > 0 && opt.beta < 1) || !(opt.sigma_armijo > 0 && opt.sigma_armijo < 1))
+        !(opt.beta > 0 && opt.beta < 1) || !(opt.sigma_armijo > 0 && opt.sigma_armijo < 1) ||
+        (opt.eot != 0 && opt.eot != 1) || (opt.eot && !(opt.eot_tol > 0)))
         return fail(ctx, IBSN_ERR_INVALID_ARG, "invalid options");
     const bool resume = k_io && *k_io > 0;
     if (resume && (!r_io || !s_io))
@@ -982,6 +985,10 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         k = *k_io;
         CKSH(hipMemcpyAsync(r, r_io, m * 8, hipMemcpyDeviceToDevice, st));
         CKSH(hipMemcpyAsync(s, s_io, n * 8, hipMemcpyDeviceToDevice, st));
+    } else if (opt.eot) {
+        // (E)IBSN: X^0 = 1 1^T (appendix C.4): the subproblem is entropic OT with cost C
+        CKSH(hipMemsetAsync(r, 0, m * 8, st));
+        CKSH(hipMemsetAsync(s, 0, n * 8, st));
     } else {
         CKSH(sk_init_center(m, n, prob->a, prob->b, r, s, st));
     }
@@ -1042,6 +1049,10 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         int stalls = 0;
         for (int v = 0; v < opt.max_newton; ++v) {
             const double gn = ctx->host_scal[SC_GN];
+            if (opt.eot && gn < opt.eot_tol) {   // (E)IBSN: the single subproblem is solved
+                stopped = true;
+                break;
+            }
             const double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / mn;   // step 6
             ta = now_s();
             CKS(run_sparsify(ctx, prob, rp, k, q, M, S, rho, csr));   // step 7
@@ -1096,7 +1107,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             ++R.newton;
             R.t_linesearch += now_s() - ta;
             // step 12 with the practical schedule: gradient gate, then D_phi test
-            if (ctx->host_scal[SC_GN] < mu) {
+            if (!opt.eot && ctx->host_scal[SC_GN] < mu) {
                 ta = now_s();
                 CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
                 CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
@@ -1115,7 +1126,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             }
         }
         CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
-        if (!stopped) {
+        if (!stopped || opt.eot) {
             ta = now_s();
             CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
             R.passes += 2;
@@ -1134,6 +1145,16 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         R.marg_l1 = ctx->host_scal[SC_G1];
         const bool done = (R.rel_gap <= opt.gap_tol && (opt.marg_tol <= 0 || R.marg_l1 <= opt.marg_tol)) ||
                           (opt.kkt_tol > 0 && R.kkt <= opt.kkt_tol);
+        if (opt.eot) {
+            // (E)IBSN: one subproblem and no outer update; the centre stays (0, 0)
+            if (plan_out) {
+                CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out));
+                R.passes += 2;
+            }
+            R.status = R.grad_norm < opt.eot_tol ? IBSN_OK : IBSN_WARN_MAXITER;
+            ++k;
+            break;
+        }
         if (plan_out && (done || k + 1 == k0 + opt.max_outer)) {
             CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out));
             R.passes += 2;

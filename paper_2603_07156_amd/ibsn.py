@@ -50,6 +50,7 @@ class Options(ct.Structure):
         ("max_outer", ct.c_int32), ("max_newton", ct.c_int32), ("max_backtrack", ct.c_int32),
         ("cg_maxit", ct.c_int32), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int32),
         ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int32),
+        ("eot", ct.c_int32), ("eot_tol", ct.c_double),
     ]
 
 

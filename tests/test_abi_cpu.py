@@ -43,3 +43,34 @@ def test_no_oracle_import_in_product():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "ibsn_oracle" not in text, f
+
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and field offsets of the option and report structs, compiled from the header
+    with the host C compiler, equal those of the ctypes binding."""
+    import shutil
+    import subprocess
+    from paper_2603_07156_amd import ibsn
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    fields_o = [f for f, _ in ibsn.Options._fields_]
+    fields_r = [f for f, _ in ibsn.Report._fields_]
+    nl = "\\n"
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "ibsn.h"', "int main(void) {",
+           f'printf("%zu %zu{nl}", sizeof(ibsn_options), sizeof(ibsn_report));']
+    src += [f'printf("%zu{nl}", offsetof(ibsn_options, {f}));' for f in fields_o]
+    src += [f'printf("%zu{nl}", offsetof(ibsn_report, {f}));' for f in fields_r]
+    src += ["return 0; }"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    so, sr = int(out[0]), int(out[1])
+    offs = [int(x) for x in out[2:]]
+    assert so == ctypes.sizeof(ibsn.Options) and sr == ctypes.sizeof(ibsn.Report)
+    assert offs[:len(fields_o)] == [getattr(ibsn.Options, f).offset for f in fields_o]
+    assert offs[len(fields_o):] == [getattr(ibsn.Report, f).offset for f in fields_r]

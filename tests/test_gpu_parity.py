@@ -360,6 +360,29 @@ def test_solve_resume_matches(ib, ctx):
     assert torch.equal(rest["s"], full["s"])
 
 
+def test_solve_eibsn_matches_oracle(ib, ctx):
+    # (E)IBSN (appendix C.4): centre 1 1^T, one subproblem to a small gradient.  The GPU and
+    # the oracle reach the same entropic OT plan.
+    inst = W.gmm_points(96, 52, m=80)
+    inst = W.Instance(inst.C, inst.a, inst.b, 0.05, "eot")
+    gopt = ib.default_options(eot=1, eot_tol=1e-12, max_newton=300)
+    res = ib.solve(ctx, problem(ib, inst), gopt)
+    rep = res["report"]
+    assert res["status"] == 0 and rep["outer"] == 1 and rep["grad_norm"] < 1e-12, rep
+    o = orc.solve(inst.C, inst.a, inst.b, inst.eta,
+                  options=orc.default_options(eot=1, eot_tol=1e-12, max_newton=300))
+    assert o["status"] == 0 and o["report"]["outer"] == 1
+    m, n = inst.C.shape
+    z_m, z_n = np.zeros(m), np.zeros(n)
+    pg = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, host(res["gamma"]), r=z_m, s=z_n, k=0,
+                       want_plan=True).plan
+    po = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, o["gamma"], r=z_m, s=z_n, k=0,
+                       want_plan=True).plan
+    np.testing.assert_allclose(pg, po, rtol=0, atol=1e-12)
+    # the returned centre is the (E)IBSN one
+    assert res["k"] == 1 and float(host(res["r"]).max()) == 0.0 and float(host(res["s"]).max()) == 0.0
+
+
 def test_solve_constant_cost(ib, ctx):
     m, n = 9, 11
     rng = np.random.default_rng(0)
