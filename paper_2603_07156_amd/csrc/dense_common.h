@@ -1,0 +1,399 @@
+// dense_common.h -- shared device helpers and tile tables of the m x n streaming passes of the
+// IBSN hot path on gfx950 (dense_eval.hip, dense_trial.hip, dense_sparsify.hip, dense_stop.hip).
+//
+// Every pass reads the cost matrix once, row by row.  A workgroup owns a contiguous
+// block of rows and holds one whole row in registers: thread t of NT owns the
+// columns j = (q*NT + t)*VEC + v (q < Q, v < VEC), loaded as 16-byte vectors, so a
+// row is Q coalesced sweeps of NT*16 bytes.  Because the row stays on chip, each
+// pass needs one exp per entry: the row maximum / normaliser come from workgroup
+// reductions (wave butterflies, then LDS across the waves) and the entries are
+// then reused from registers.  Column sums (P^T a, d = P_rho^T a, the rounding sums)
+// are accumulated per thread in registers over the workgroup's rows and written
+// once as a partial row; a second kernel adds the partials in a fixed order, so no
+// floating point atomics are used and results are run-to-run reproducible.
+//
+// The row after the current one is prefetched into a second register set while the
+// current one is reduced, which keeps loads in flight across the reductions.
+//
+// Exponents.  Column potentials w_j and row shifts M_i both lie on a grid of spacing
+// q (a power of two chosen per outer iteration), so w_j - M_i is exact and
+//     x_ij = fma(-sigma, C_ij, w_j - M_i)
+// is theta_ij - M_i with one rounding at the scale of x_ij, however large sigma and
+// the potentials grow.  grid(v) = q * rint(v / q).
+#pragma once
+
+#include "ibsn_internal.h"
+#include "solver_kernels.h"
+
+#include <math.h>
+
+namespace ibsn {
+namespace {
+
+
+constexpr int WAVE = 64;
+enum { OP_SUM = 0, OP_MAX = 1, OP_MIN = 2 };
+
+template <int OP>
+__device__ __forceinline__ double comb(double x, double y)
+{
+    if constexpr (OP == OP_SUM)
+        return x + y;
+    else if constexpr (OP == OP_MAX)
+        return fmax(x, y);
+    else
+        return fmin(x, y);
+}
+
+// Move a double across lanes with a DPP control (all 64 lanes active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Wave reduction without LDS: within each row of 16 lanes, DPP lane ^ 1 and lane ^ 2
+// (quad permutes), then rotations by 4 and 8; lane 16 r then holds row r's result, and
+// the four rows are combined in a fixed order.  Every lane returns the same value.
+// Call with all 64 lanes active.
+template <int OP>
+__device__ __forceinline__ double wave_red(double v)
+{
+    v = comb<OP>(v, dpp_mov<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = comb<OP>(v, dpp_mov<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = comb<OP>(v, dpp_mov<0x124>(v));   // row_ror:4
+    v = comb<OP>(v, dpp_mov<0x128>(v));   // row_ror:8
+    return comb<OP>(comb<OP>(readlane_d(v, 0), readlane_d(v, 16)),
+                    comb<OP>(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+// Workgroup reduction of K values with per-slot operators.  `lds` holds two buffers of
+// K*(NT/64) doubles used alternately, so one barrier per reduction suffices: a buffer
+// is rewritten only after every wave has passed the barrier of the next reduction.
+template <int NT, int... OPS>
+struct BlockRed {
+    static constexpr int K = sizeof...(OPS);
+    static constexpr int NW = NT / WAVE;
+    static constexpr int LDS = 2 * K * NW;
+
+    template <int I, int OP, int... REST>
+    __device__ __forceinline__ static void wave_all(double *v)
+    {
+        v[I] = wave_red<OP>(v[I]);
+        if constexpr (sizeof...(REST) > 0)
+            wave_all<I + 1, REST...>(v);
+    }
+    template <int I, int OP, int... REST>
+    __device__ __forceinline__ static void fold_all(double *v, const double *buf)
+    {
+        double r = buf[I * NW];
+#pragma unroll
+        for (int k = 1; k < NW; ++k)
+            r = comb<OP>(r, buf[I * NW + k]);
+        v[I] = r;
+        if constexpr (sizeof...(REST) > 0)
+            fold_all<I + 1, REST...>(v, buf);
+    }
+    __device__ __forceinline__ static void run(double *v, double *lds, int &parity)
+    {
+        double *buf = lds + parity * K * NW;
+        parity ^= 1;
+        wave_all<0, OPS...>(v);
+        const int w = threadIdx.x / WAVE;
+        if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                buf[k * NW + w] = v[k];
+        }
+        __syncthreads();
+        fold_all<0, OPS...>(v, buf);
+    }
+};
+
+template <typename CT, int VEC>
+struct VecLoad;
+template <>
+struct VecLoad<double, 2> {
+    __device__ __forceinline__ static void get(const double *p, double *x)
+    {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        x[0] = v.x;
+        x[1] = v.y;
+    }
+};
+template <>
+struct VecLoad<float, 4> {
+    __device__ __forceinline__ static void get(const float *p, float *x)
+    {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        x[0] = v.x;
+        x[1] = v.y;
+        x[2] = v.z;
+        x[3] = v.w;
+    }
+};
+
+template <int NT, int VEC>
+__device__ __forceinline__ int col_of(int e)
+{
+    return ((e / VEC) * NT + (int)threadIdx.x) * VEC + (e % VEC);
+}
+
+// Load row `row` (n entries) into x[Q*VEC] (cost type) without branches per slot.
+// When the row starts on a 16-byte boundary and n is a multiple of VEC, every slot is a
+// 16-byte vector load whose start is clamped to the last full vector of the row;
+// otherwise scalar loads with each column clamped to n - 1.  Either way every address is
+// inside the row, and slots past n hold copies of in-row values: every caller masks
+// those slots (col_of(e) >= n) before their values are used.
+template <int NT, int Q, int QF, int VEC, bool VECOK, typename CT>
+__device__ __forceinline__ void load_row(const CT *__restrict__ row, int n, CT *x)
+{
+    if constexpr (VECOK) {
+        // every row starts on a 16-byte boundary and n % VEC == 0 (checked per launch),
+        // so each slot start, a multiple of VEC, is 16-byte aligned
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j0 = (q * NT + (int)threadIdx.x) * VEC;
+            const CT *p = static_cast<const CT *>(
+                __builtin_assume_aligned(row + (q < QF ? j0 : min(j0, n - VEC)), 16));
+            VecLoad<CT, VEC>::get(p, x + q * VEC);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j0 = (q * NT + (int)threadIdx.x) * VEC;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                x[q * VEC + v] = row[q < QF ? j0 + v : min(j0 + v, n - 1)];
+        }
+    }
+}
+
+template <int NT, int Q, int VEC>
+__device__ __forceinline__ void store_cols(double *__restrict__ dst, int n, const double *x)
+{
+#pragma unroll
+    for (int e = 0; e < Q * VEC; ++e) {
+        const int j = col_of<NT, VEC>(e);
+        if (j < n)
+            dst[j] = x[e];
+    }
+}
+
+// Copy an n-vector into this workgroup's dynamic LDS (one value per column).
+__device__ __forceinline__ void stage_lds(const double *__restrict__ src, int n, double *lds)
+{
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        lds[j] = src[j];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double grid(double v, double q) { return q * rint(v / q); }
+
+// exp(x) for finite x <= 709, by table-driven argument reduction (P. T. P. Tang,
+// "Table-driven implementation of the exponential function in IEEE floating-point
+// arithmetic", ACM TOMS 15(2), 1989): x = (128 e + j) ln2/128 + r with |r| <= ln2/256, so
+// exp(x) = 2^e 2^(j/128) exp(r), and exp(r) - 1 is its Taylor polynomial of degree 5
+// (the next term is below 6e-19 relative).
+//  - k = round(x 128/ln2) comes from one fused multiply-add with 1.5*2^52, whose unit in
+//    the last place is 1: the sum holds k in the low word of its bit pattern.
+//  - ln2/128 is split into a double and its remainder; with fused multiply-adds the
+//    reduced argument is exact to the last bit of r.
+//  - x <= -746 gives 0 (clamped; the result underflows); NaN also gives 0, so the
+//    callers require finite costs and potentials.
+// etab[j] = 2^(j/128), see exp_table_init.  The passes never produce x > 709: x is
+// theta - M_i with M_i the grid-rounded row maximum.
+constexpr int EXP_TAB = 128;
+constexpr double EXP_SHIFT = 0x1.8p52;               // 1.5 * 2^52
+constexpr double EXP_INV_L = 0x1.71547652b82fep+7;   // 128 / ln 2
+constexpr double EXP_L_HI = 0x1.62e42fefa39efp-8;    // ln 2 / 128, rounded
+constexpr double EXP_L_LO = 0x1.abc9e3b39803fp-63;   // ln 2 / 128 - EXP_L_HI
+
+__device__ __forceinline__ double exp_tab(double x, const double *__restrict__ etab)
+{
+    x = fmax(x, -746.0);
+    const double t = fma(x, EXP_INV_L, EXP_SHIFT);
+    const int k = __double2loint(t);
+    const double kd = t - EXP_SHIFT;
+    double r = fma(-kd, EXP_L_HI, x);
+    r = fma(-kd, EXP_L_LO, r);
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p *= r;                                   // exp(r) - 1
+    const double tj = etab[k & (EXP_TAB - 1)];
+    return ldexp(fma(tj, p, tj), k >> 7);
+}
+
+// 2^(j/128), j < 128, into LDS (one barrier)
+__device__ __forceinline__ void exp_table_init(double *etab)
+{
+    for (int j = threadIdx.x; j < EXP_TAB; j += blockDim.x)
+        etab[j] = exp2((double)j * (1.0 / EXP_TAB));
+    __syncthreads();
+}
+
+// Slot e of a thread holds column col_of(e).  The tiles are chosen so that the first QF
+// slabs (slots e < QF*VEC) lie inside the row for every thread; only later slabs can
+// reach past n and need a mask.
+template <int QF, int NT, int VEC>
+__device__ __forceinline__ bool slot_valid(int e, int n)
+{
+    return e / VEC < QF || col_of<NT, VEC>(e) < n;
+}
+
+// column of slot e, clamped into [0, n) in the slabs that may reach past n
+template <int QF, int NT, int VEC>
+__device__ __forceinline__ int slot_col(int e, int n)
+{
+    const int j = col_of<NT, VEC>(e);
+    return e / VEC < QF ? j : min(j, n - 1);
+}
+
+// w at the owned columns; padding slots get -inf so that exp of their argument is 0
+template <int NT, int Q, int VEC>
+__device__ __forceinline__ void load_w(const double *__restrict__ w, int n, double *x)
+{
+#pragma unroll
+    for (int e = 0; e < Q * VEC; ++e) {
+        const int j = col_of<NT, VEC>(e);
+        x[e] = j < n ? w[j] : -INFINITY;
+    }
+}
+
+__device__ __forceinline__ void row_range(int m, int &i0, int &i1)
+{
+    const int64_t g = blockIdx.x, G = gridDim.x;
+    i0 = (int)((int64_t)m * g / G);
+    i1 = (int)((int64_t)m * (g + 1) / G);
+}
+
+// Per-row scalars (shifts, normalisers, weights) are staged in LDS ROWCH rows at a time,
+// so that the row loop reads them from LDS instead of waiting on memory every row.
+constexpr int ROWCH = 64;
+
+// Row loop of a workgroup over its rows [i0, i1).  Row i+1 is loaded into a second
+// register set while row i is processed, so its loads are in flight across the whole of
+// the current row.  stage(i) runs before rows i .. i+ROWCH-1 are touched (it fills the
+// LDS row scalars; it begins and ends with a barrier); body(i, slot, x) processes row i
+// held in x, with slot = its index in the staged chunk.
+template <int NT, int Q, int QF, int VEC, bool VECOK, bool PREFETCH, typename CT,
+          typename Stage, typename Body>
+__device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc, int n, int i0,
+                                           int i1, Stage &stage, Body &body)
+{
+    CT xr[Q * VEC];
+    if constexpr (PREFETCH) {
+        CT xn[Q * VEC];
+        if (i0 < i1)
+            load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i0 * ldc, n, xr);
+        for (int i = i0; i < i1; ++i) {
+            const int slot = (i - i0) & (ROWCH - 1);
+            if (slot == 0)
+                stage(i);
+            if (i + 1 < i1)
+                load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)(i + 1) * ldc, n, xn);
+            body(i, slot, xr);
+#pragma unroll
+            for (int e = 0; e < Q * VEC; ++e)
+                xr[e] = xn[e];
+        }
+    } else {
+        for (int i = i0; i < i1; ++i) {
+            const int slot = (i - i0) & (ROWCH - 1);
+            if (slot == 0)
+                stage(i);
+            load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i * ldc, n, xr);
+            body(i, slot, xr);
+        }
+    }
+}
+
+// 16-byte vector loads when the matrix start and the row pitch are 16-byte aligned and n
+// is a multiple of VEC (the same for every row); scalar loads otherwise.
+// PREFETCH = false (passes whose per-entry state leaves no registers for a second row):
+// each row is loaded when it is reached.
+template <int NT, int Q, int QF, int VEC, bool PREFETCH = true, typename CT, typename Stage,
+          typename Body>
+__device__ __forceinline__ void row_loop(const CT *__restrict__ C, int64_t ldc, int n, int i0,
+                                         int i1, Stage &&stage, Body &&body)
+{
+    const bool vec_ok = (reinterpret_cast<uintptr_t>(C) & 15u) == 0 &&
+                        ((uint64_t)ldc * sizeof(CT)) % 16 == 0 && n % VEC == 0;
+    if (vec_ok)
+        row_loop_v<NT, Q, QF, VEC, true, PREFETCH>(C, ldc, n, i0, i1, stage, body);
+    else
+        row_loop_v<NT, Q, QF, VEC, false, PREFETCH>(C, ldc, n, i0, i1, stage, body);
+}
+
+// Copy rows [i, min(i + ROWCH, i1)) of up to four m-vectors into LDS (null: skipped).
+__device__ __forceinline__ void stage_rows(int i, int i1, const double *__restrict__ s0,
+                                           double *d0, const double *__restrict__ s1, double *d1,
+                                           const double *__restrict__ s2, double *d2,
+                                           const double *__restrict__ s3 = nullptr,
+                                           double *d3 = nullptr)
+{
+    __syncthreads();   // the previous chunk may still be read
+    const int cnt = min(ROWCH, i1 - i);
+    for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+        if (s0)
+            d0[r] = s0[i + r];
+        if (s1)
+            d1[r] = s1[i + r];
+        if (s2)
+            d2[r] = s2[i + r];
+        if (s3)
+            d3[r] = s3[i + r];
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+#define IBSN_LIGHT_TILES(X) \
+    X(256, 1, 0)            \
+    X(256, 2, 1)            \
+    X(256, 3, 2)            \
+    X(256, 4, 3)            \
+    X(512, 3, 2)            \
+    X(512, 4, 3)            \
+    X(1024, 3, 2)           \
+    X(1024, 4, 3)           \
+    X(1024, 5, 4)           \
+    X(512, 10, 8)
+#define IBSN_HEAVY_TILES(X) \
+    X(256, 1, 0)            \
+    X(256, 2, 1)            \
+    X(256, 3, 2)            \
+    X(256, 4, 3)            \
+    X(512, 3, 2)            \
+    X(512, 4, 3)            \
+    X(512, 6, 4)            \
+    X(512, 8, 6)            \
+    X(512, 10, 8)
+
+#define IBSN_DISPATCH(NT_, Q_, QF_, BODY)                                         \
+    if (p.nt == NT_ && p.q == Q_ && p.qf == QF_) {                               \
+        constexpr int NT = NT_, Q = Q_, QF = QF_;                                \
+        if (d.cost_kind == 0) {                                                  \
+            constexpr int VEC = 2;                                               \
+            using CT = double;                                                   \
+            BODY;                                                                \
+        } else {                                                                 \
+            constexpr int VEC = 4;                                               \
+            using CT = float;                                                    \
+            BODY;                                                                \
+        }                                                                        \
+        return hipGetLastError();                                                \
+    }
+
+}  // namespace ibsn

@@ -1,0 +1,122 @@
+// dense_eval.hip -- the subproblem eval (row LSE) pass on gfx950; helpers in dense_common.h.
+#include "dense_common.h"
+
+namespace ibsn {
+namespace {
+
+// ---------------------------------------------------------------------------------
+// eval: M_i = max_j theta_ij, S_i = sum_j exp(theta_ij - M_i), column partials of
+// a_i P_ij, objective row terms a_i ((r_i + M_i) + log S_i).
+// ---------------------------------------------------------------------------------
+template <int NT, int Q, int QF, int VEC, typename CT>
+__global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t ldc, int m, int n,
+                                             double sigma, double qg,
+                                             const double *__restrict__ w,
+                                             const double *__restrict__ a,
+                                             const double *__restrict__ r, double *__restrict__ Mo,
+                                             double *__restrict__ So, double *__restrict__ lse,
+                                             double *__restrict__ plan,
+                                             double *__restrict__ colpart,
+                                             double *__restrict__ rowpart)
+{
+    constexpr int E = Q * VEC;
+    constexpr int NW = NT / WAVE;
+    // per row: each wave takes its own shift m_w = grid(wave max of theta) and sums
+    // exp(theta - m_w); one barrier publishes the (m_w, s_w) pairs; every wave then forms
+    // M = max_w m_w = grid(max theta) (grid rounding is monotone) and
+    // S = sum_w s_w exp(m_w - M), and scales its entries by exp(m_w - M).  All shifts
+    // lie on the grid, so m_w - M is exact.  The pair buffer alternates between rows.
+    __shared__ double pairs[2][2 * NW];
+    __shared__ double etab[EXP_TAB];
+    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    int parity = 0;
+    int i0, i1;
+    row_range(m, i0, i1);
+    exp_table_init(etab);
+    stage_lds(w, n, wl);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    __shared__ double rA[ROWCH], rR[ROWCH];
+    double acc[E], x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        acc[e] = 0.0;
+    double rowacc = 0.0;
+    row_loop<NT, Q, QF, VEC>(
+        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, a, rA, r, rR, nullptr, nullptr); },
+        [&](int i, int slot, const CT *xr) {
+        // padding slots: theta = -inf, so they drop out of the max and p = 0; a wave
+        // with no column in the row gets m_w = -inf, s_w = 0 and factor 0
+        double mt = -INFINITY;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double th = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)]);
+            mt = fmax(mt, slot_valid<QF, NT, VEC>(e, n) ? th : -INFINITY);
+        }
+        const double mw = grid(wave_red<OP_MAX>(mt), qg);
+        double st = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double xa = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - mw);
+            const double p = exp_tab(slot_valid<QF, NT, VEC>(e, n) ? xa : -INFINITY, etab);
+            x[e] = p;
+            st += p;
+        }
+        const double sw = wave_red<OP_SUM>(st);
+        double *pr = pairs[parity];
+        parity ^= 1;
+        if (lane == 0) {
+            pr[wv] = mw;
+            pr[NW + wv] = sw;
+        }
+        __syncthreads();
+        const double mk = lane < NW ? pr[lane] : -INFINITY;
+        const double M = wave_red<OP_MAX>(mk);
+        const double term = lane < NW ? pr[NW + lane] * exp_tab(mk - M, etab) : 0.0;
+        const double S = wave_red<OP_SUM>(term);
+        const double ai = rA[slot];
+        const double sc = ai / S * exp_tab(mw - M, etab);   // a_i exp(m_w - M) / S
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            acc[e] = fma(sc, x[e], acc[e]);
+        if (plan) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int j = col_of<NT, VEC>(e);
+                if (j < n)
+                    plan[(int64_t)i * n + j] = sc * x[e];
+            }
+        }
+        if (threadIdx.x == 0) {
+            const double ls = log(S);
+            Mo[i] = M;
+            So[i] = S;
+            if (lse)
+                lse[i] = M + ls;
+            if (r)
+                rowacc += ai * ((rR[slot] + M) + ls);
+        }
+        });
+    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
+    if (threadIdx.x == 0)
+        rowpart[blockIdx.x] = rowacc;
+}
+
+}  // namespace
+
+hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, double *M, double *S,
+                       double *lse, double *plan, double *colpart, double *rowpart, hipStream_t st)
+{
+#define BODY                                                                                     \
+    hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT),                         \
+                       (size_t)d.n * sizeof(double), st,                                         \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, r, M, S, \
+                       lse,                                                                      \
+                       plan, colpart, rowpart)
+#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+    IBSN_LIGHT_TILES(X)
+#undef X
+#undef BODY
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ibsn

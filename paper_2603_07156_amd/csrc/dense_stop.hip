@@ -1,0 +1,301 @@
+// dense_stop.hip -- the stop-test passes (Algorithm 3, certificate), the fixed-order column
+// reduction and the choice of row tiles, on gfx950; helpers in dense_common.h.
+#include "dense_common.h"
+
+namespace ibsn {
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Stop test pass 1 (Algorithm 3, steps 2-8): X = a_i P; z_i; column sums of X and z X.
+// ---------------------------------------------------------------------------------
+template <int NT, int Q, int QF, int VEC, typename CT>
+__global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t ldc, int m, int n,
+                                              double sigma, const double *__restrict__ w,
+                                              const double *__restrict__ a,
+                                              const double *__restrict__ M,
+                                              const double *__restrict__ S,
+                                              double *__restrict__ z, double *__restrict__ colpart,
+                                              double *__restrict__ colpart2,
+                                              double *__restrict__ rowpart)
+{
+    constexpr int E = Q * VEC;
+    using RedSum = BlockRed<NT, OP_SUM>;
+    __shared__ double lds[RedSum::LDS];
+    __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH];
+    int parity = 0;
+    int i0, i1;
+    row_range(m, i0, i1);
+    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    __shared__ double etab[EXP_TAB];
+    double ax[E], az[E], x[E];
+    exp_table_init(etab);
+    stage_lds(w, n, wl);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        ax[e] = 0.0;
+        az[e] = 0.0;
+    }
+    double rowacc = 0.0;
+    row_loop<NT, Q, QF, VEC>(
+        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA); },
+        [&](int i, int slot, const CT *xr) {
+            const double Mi = rM[slot], ai = rA[slot], aS = ai / rS[slot];
+            double red[1] = {0.0};
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const bool valid = slot_valid<QF, NT, VEC>(e, n);
+                const double xa =
+                    fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - Mi);
+                const double X = exp_tab(valid ? xa : -INFINITY, etab) * aS;
+                x[e] = X;
+                red[0] += X;
+            }
+            RedSum::run(red, lds, parity);
+            const double rs = red[0];
+            const double zi = fmin(ai / rs, 1.0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                ax[e] += x[e];
+                az[e] = fma(zi, x[e], az[e]);
+            }
+            if (threadIdx.x == 0) {
+                z[i] = zi;
+                rowacc += (rs - ai) * (rs - ai);
+            }
+        });
+    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, ax);
+    store_cols<NT, Q, VEC>(colpart2 + (int64_t)blockIdx.x * n, n, az);
+    if (threadIdx.x == 0)
+        rowpart[blockIdx.x] = rowacc;
+}
+
+// ---------------------------------------------------------------------------------
+// Stop test pass 2: e_r (row-local), Xhat = z X y + e_r e_c^T / ||e_r||_1 (Algorithm 3,
+// steps 9-11), D_phi(Xhat, X) in the log domain, <C,Xhat>, <C,X>, c-transforms of
+// gamma and psi, <X, U(gamma, zeta^c)>, norms for Delta_kkt.
+// ---------------------------------------------------------------------------------
+template <int NT, int Q, int QF, int VEC, typename CT>
+__global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t ldc, int m, int n,
+                                              double sigma, const double *__restrict__ w,
+                                              const double *__restrict__ a,
+                                              const double *__restrict__ M,
+                                              const double *__restrict__ S,
+                                              const double *__restrict__ gamma,
+                                              const double *__restrict__ psi,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ ec,
+                                              const double *__restrict__ z, double er1,
+                                              double *__restrict__ xhat,
+                                              double *__restrict__ rowpart)
+{
+    constexpr int E = Q * VEC;
+    using Red3 = BlockRed<NT, OP_SUM, OP_MIN, OP_MIN>;
+    using RedEnd = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_SUM, OP_MIN, OP_SUM, OP_SUM>;
+    __shared__ double lds[Red3::LDS + RedEnd::LDS];
+    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    int parity = 0;
+    int i0, i1;
+    row_range(m, i0, i1);
+    __shared__ double etab[EXP_TAB];
+    exp_table_init(etab);
+    stage_lds(w, n, wl);
+    __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH], rZ[ROWCH];
+    double X[E];
+    double t_dphi = 0.0, t_cxh = 0.0, t_cx = 0.0, t_xu = 0.0, t_xhmin = INFINITY, t_xf = 0.0,
+           t_cf = 0.0;
+    double azg = 0.0, azp = 0.0;
+    const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
+    row_loop<NT, Q, QF, VEC, false>(
+        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA, z, rZ); },
+        [&](int i, int slot, const CT *cst) {
+        const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];
+        double red[3] = {0.0, INFINITY, INFINITY};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const bool valid = slot_valid<QF, NT, VEC>(e, n);
+            const int j = slot_col<QF, NT, VEC>(e, n);
+            const double c = valid ? (double)cst[e] : 0.0;
+            const double Xv = exp_tab(valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY, etab) * aS;
+            X[e] = Xv;
+            red[0] = fma(Xv, y[j], red[0]);
+            red[1] = fmin(red[1], valid ? c - gamma[j] : INFINITY);
+            red[2] = fmin(red[2], valid ? c - psi[j] : INFINITY);
+        }
+        Red3::run(red, lds, parity);
+        const double eri = fmax(ai - zi * red[0], 0.0);   // >= 0 exactly; clamp rounding
+        const double zg = red[1], zp = red[2];
+        const double lr = log(ai) - log(rS[slot]);   // log X_ij = lr + (theta_ij - M_i)
+        const double es = eri * inv_er1;         // rank-one factor e_r,i / ||e_r||_1
+#pragma unroll 2
+        for (int e = 0; e < E; ++e) {
+            const bool valid = slot_valid<QF, NT, VEC>(e, n);
+            const int j = slot_col<QF, NT, VEC>(e, n);
+            const double c = valid ? (double)cst[e] : 0.0;
+            const double Xv = X[e];
+            const double f = (zi * Xv) * y[j];
+            const double xh = valid ? fma(es, ec[j], f) : 0.0;
+            const double lx = lr + fma(-sigma, c, wl[j] - Mi);
+            const bool pos = xh > 0.0;
+            const double lxh = log(pos ? xh : 1.0);
+            t_dphi += pos ? (xh * (lxh - lx) - xh) + Xv : Xv;
+            t_cxh = fma(c, xh, t_cxh);
+            t_cx = fma(c, Xv, t_cx);
+            t_xhmin = fmin(t_xhmin, valid ? xh : INFINITY);
+            t_xu = fma(Xv, (c - gamma[j]) - zg, t_xu);
+            t_xf = fma(Xv, Xv, t_xf);
+            t_cf = fma(c, c, t_cf);
+            if (xhat && valid)
+                xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xh;
+        }
+        if (threadIdx.x == 0) {
+            azg += ai * zg;
+            azp += ai * zp;
+        }
+        });
+    double fin[7] = {t_dphi, t_cxh, t_cx, t_xu, t_xhmin, t_xf, t_cf};
+    int p2 = 0;
+    RedEnd::run(fin, lds + Red3::LDS, p2);
+    if (threadIdx.x == 0) {
+        double *o = rowpart + (int64_t)blockIdx.x * STOP2_NSLOT;
+        o[STOP2_DPHI] = fin[0];
+        o[STOP2_CXH] = fin[1];
+        o[STOP2_AZG] = azg;
+        o[STOP2_AZP] = azp;
+        o[STOP2_CX] = fin[2];
+        o[STOP2_XU] = fin[3];
+        o[STOP2_XHMIN] = fin[4];
+        o[STOP2_XF] = fin[5];
+        o[STOP2_CF] = fin[6];
+        o[STOP2_NEG] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// column reduction: out_j = sum_g part[g][j], g ascending within each of NW strided
+// subsets, subsets added in order.  64 columns per workgroup.
+// ---------------------------------------------------------------------------------
+template <int NW>
+__global__ __launch_bounds__(NW *WAVE) void k_colreduce(const double *__restrict__ part, int G, int n,
+                                                        double *__restrict__ out,
+                                                        const double *__restrict__ sub,
+                                                        double *__restrict__ out2)
+{
+    __shared__ double s[NW][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int j = blockIdx.x * WAVE + lane;
+    double acc = 0.0;
+    if (j < n)
+        for (int g = wv; g < G; g += NW)
+            acc += part[(int64_t)g * n + j];
+    s[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && j < n) {
+        double t = s[0][lane];
+        for (int k = 1; k < NW; ++k)
+            t += s[k][lane];
+        out[j] = t;
+        if (sub)
+            out2[j] = t - sub[j];
+    }
+}
+
+}  // namespace
+
+// Tiles (NT threads, Q vector slots per thread, QF slabs always inside the row).  Each
+// tile serves n in (previous capacity, NT*Q*VEC], so the first QF slabs are full for
+// every n it is chosen for.  Light tiles serve eval and stop pass 1; the heavy tile of the
+// same row serves trial, sparsify and stop pass 2, which keep more values live per
+// entry; both run on the same grid.  1024-thread tiles keep 10 entries per thread at
+// n <= 10240 (FP64), which leaves room for four waves per SIMD.
+struct TileRow {
+    int cap;                  // largest n served
+    int nt, q, qf;            // light tile
+    int nt_h, q_h, qf_h;      // heavy tile
+    int per_cu;               // workgroups per CU
+};
+const TileRow TILES64[] = {
+    {512, 256, 1, 0, 256, 1, 0, 4},      {1024, 256, 2, 1, 256, 2, 1, 4},
+    {1536, 256, 3, 2, 256, 3, 2, 4},     {2048, 256, 4, 3, 256, 4, 3, 4},
+    {3072, 512, 3, 2, 512, 3, 2, 2},     {4096, 512, 4, 3, 512, 4, 3, 2},
+    {6144, 1024, 3, 2, 512, 6, 4, 1},    {8192, 1024, 4, 3, 512, 8, 6, 1},
+    {10240, 1024, 5, 4, 512, 10, 8, 1},
+};
+const TileRow TILES32[] = {
+    {1024, 256, 1, 0, 256, 1, 0, 4},     {2048, 256, 2, 1, 256, 2, 1, 4},
+    {3072, 256, 3, 2, 256, 3, 2, 4},     {4096, 256, 4, 3, 256, 4, 3, 4},
+    {6144, 512, 3, 2, 512, 3, 2, 2},     {8192, 512, 4, 3, 512, 4, 3, 2},
+    {12288, 1024, 3, 2, 512, 6, 4, 1},   {16384, 1024, 4, 3, 512, 8, 6, 1},
+    {20480, 512, 10, 8, 512, 10, 8, 1},
+};
+bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *p)
+{
+    const TileRow *t = cost_kind == 1 ? TILES32 : TILES64;
+    const int nt = (int)(sizeof(TILES64) / sizeof(TILES64[0]));
+    for (int k = 0; k < nt; ++k) {
+        if (n <= t[k].cap) {
+            p->nt = t[k].nt;
+            p->q = t[k].q;
+            p->qf = t[k].qf;
+            p->nt_h = t[k].nt_h;
+            p->q_h = t[k].q_h;
+            p->qf_h = t[k].qf_h;
+            p->vec = cost_kind == 1 ? 4 : 2;
+            const int64_t g = (int64_t)num_cus * t[k].per_cu;
+            p->grid = (int)(g < m ? g : m);
+            return true;
+        }
+    }
+    return false;
+}
+
+RowPlan heavy_plan(const RowPlan &p)
+{
+    RowPlan h = p;
+    h.nt = p.nt_h;
+    h.q = p.q_h;
+    h.qf = p.qf_h;
+    return h;
+}
+
+hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
+                        double *z, double *colpart, double *colpart2, double *rowpart,
+                        hipStream_t st)
+{
+    const size_t lds_bytes = (size_t)d.n * sizeof(double);
+#define BODY                                                                                     \
+    hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, z,   \
+                       colpart, colpart2, rowpart)
+#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+    IBSN_LIGHT_TILES(X)
+#undef X
+#undef BODY
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stop2(const RowPlan &p_in, const DenseArgs &d, const double *M, const double *S,
+                        const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st)
+{
+    const RowPlan p = heavy_plan(p_in);
+    const size_t lds_bytes = (size_t)d.n * sizeof(double);
+#define BODY                                                                                      \
+    hipLaunchKernelGGL((k_stop2<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                  \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
+                       v.gamma, v.psi, v.y, v.ec, v.z, v.er1, xhat, rowpart)
+#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+    IBSN_HEAVY_TILES(X)
+#undef X
+#undef BODY
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_colreduce(const double *part, int G, int64_t n, double *out, const double *sub,
+                            double *out2, hipStream_t st)
+{
+    const int blocks = (int)((n + WAVE - 1) / WAVE);
+    hipLaunchKernelGGL((k_colreduce<16>), dim3(blocks), dim3(16 * WAVE), 0, st, part, G, (int)n,
+                       out, sub, out2);
+    return hipGetLastError();
+}
+
+}  // namespace ibsn

@@ -1,0 +1,115 @@
+// dense_trial.hip -- the Armijo trial pass on gfx950; helpers in dense_common.h.
+#include "dense_common.h"
+
+namespace ibsn {
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Armijo trial from the row state M of the base point, tau = t*Delta/eta:
+//   q = exp(theta - M_i), A = sum q, small step (BIG=0, cv = expm1(tau)):
+//   B = sum q*cv, qe = q + q*cv = q e^tau, delta = log1p(B/A);
+//   big step (BIG=1, cv = exp(tau - tau_shift)): qe = q*cv, delta = tau_shift + log(Z/A).
+//   Z = sum qe, P'_ij = qe / Z, new state M' = M + tau_shift + log(max qe), S' = Z / max qe.
+// ---------------------------------------------------------------------------------
+template <int NT, int Q, int QF, int VEC, typename CT, int BIG>
+__global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc, int m, int n,
+                                              double sigma, double qg,
+                                              const double *__restrict__ w,
+                                              const double *__restrict__ a,
+                                              const double *__restrict__ Mb,
+                                              const double *__restrict__ colv,
+                                              const double *__restrict__ scal,
+                                              double *__restrict__ Mn, double *__restrict__ Sn,
+                                              double *__restrict__ colpart,
+                                              double *__restrict__ rowpart)
+{
+    constexpr int E = Q * VEC;
+    using Red = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_MAX>;
+    __shared__ double lds[Red::LDS];
+    int parity = 0;
+    int i0, i1;
+    row_range(m, i0, i1);
+    if ((scal[SC_BIG] != 0.0) != (BIG != 0))
+        return;   // the other form of the trial handles this step
+    const double tau_shift = scal[SC_TAUSHIFT];
+    extern __shared__ double cvl[];   // colv staged in LDS (n doubles)
+    __shared__ double etab[EXP_TAB];
+    __shared__ double rM[ROWCH], rA[ROWCH];
+    double wr[E], acc[E], x[E];
+    exp_table_init(etab);
+    load_w<NT, Q, VEC>(w, n, wr);   // padding slots: -inf, so q = 0 there
+    stage_lds(colv, n, cvl);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        acc[e] = 0.0;
+    double rowacc = 0.0;
+    row_loop<NT, Q, QF, VEC>(
+        C, ldc, n, i0, i1,
+        [&](int i) { stage_rows(i, i1, Mb, rM, a, rA, nullptr, nullptr); },
+        [&](int i, int slot, const CT *xr) {
+        const double Mi = rM[slot];
+        double red[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double q = exp_tab(fma(-sigma, (double)xr[e], wr[e] - Mi), etab);
+            const double cv = cvl[slot_col<QF, NT, VEC>(e, n)];   // finite, and q = 0 on padding
+            red[0] += q;
+            double qe;
+            if constexpr (BIG) {
+                qe = q * cv;
+            } else {
+                const double qf = q * cv;
+                red[1] += qf;
+                qe = q + qf;
+            }
+            red[2] += qe;
+            red[3] = fmax(red[3], qe);
+            x[e] = qe;
+        }
+        Red::run(red, lds, parity);
+        const double A = red[0], B = red[1], Z = red[2], mx = red[3];
+        const double ai = rA[slot];
+        const double sc = ai / Z;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            acc[e] = fma(sc, x[e], acc[e]);
+        if (threadIdx.x == 0) {
+            // a step that pushes a whole row below the FP64 range is not a decrease
+            const double delta =
+                !(Z > 0.0) ? INFINITY : (BIG ? tau_shift + log(Z / A) : log1p(B / A));
+            rowacc += ai * delta;
+            // new shift on the grid; S' carries the exact remainder so that
+            // exp(x'_ij) / S'_i = P'_ij for the fresh x' of the point w + tau
+            const double Mnew = grid(Mi + (tau_shift + log(mx)), qg);
+            Mn[i] = Mnew;
+            Sn[i] = Z * exp((Mi - Mnew) + tau_shift);
+        }
+        });
+    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
+    if (threadIdx.x == 0)
+        rowpart[blockIdx.x] = rowacc;
+}
+
+}  // namespace
+
+hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M, const double *colv,
+                        const double *scal, double *M_new, double *S_new, double *colpart,
+                        double *rowpart, hipStream_t st)
+{
+    const RowPlan p = heavy_plan(p_in);
+    const size_t lds_bytes = (size_t)d.n * sizeof(double);
+#define BODY                                                                                      \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
+                       scal, M_new, S_new, colpart, rowpart);                                     \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, 1>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
+                       scal, M_new, S_new, colpart, rowpart)
+#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+    IBSN_HEAVY_TILES(X)
+#undef X
+#undef BODY
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ibsn

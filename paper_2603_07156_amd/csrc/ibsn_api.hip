@@ -4,7 +4,7 @@
 //
 // The host only sequences kernels and reads back the scalars a decision needs
 // (||g||, the Armijo decrease, D_phi and the certificate, the CG done flag).  All
-// arithmetic on problem data runs in the kernels of dense_passes.hip, sparse_ops.hip
+// arithmetic on problem data runs in the kernels of dense_*.hip, sparse_ops.hip
 // and solver_kernels.hip.
 #include "../../include/ibsn.h"
 #include "ibsn_internal.h"

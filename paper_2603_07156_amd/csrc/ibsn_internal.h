@@ -20,6 +20,8 @@ struct RowPlan {
 
 // Choose the register tile for a row of n entries; returns false if n is too large.
 bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *plan);
+// the same plan with the heavy tile (trial, sparsify, stop pass 2) as the tile
+RowPlan heavy_plan(const RowPlan &p);
 
 struct DenseArgs {
     const void *C;

@@ -16,7 +16,7 @@ The probe runs the eval kernel five times on the m = n = 10^4 uniform-points wor
 (the benchmark's) and five plain device-to-device copies of 800 MB, whose bytes are known:
 the counters of the copies give the factor that turns FETCH_SIZE / WRITE_SIZE (KiB per
 dispatch) into bytes, and that factor is applied to the eval kernel's counters.  The
-summary records a hash of the dense-pass source, so that a reader (bench.py) can tell
+summary records a hash of the LSE-pass source, so that a reader (bench.py) can tell
 whether the counters still describe the kernel that is built.
 """
 from __future__ import annotations
@@ -28,15 +28,19 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DENSE_SRC = os.path.join(HERE, "csrc", "dense_passes.hip")
+# the LSE-pass kernel is built from these two files
+DENSE_SRC = [os.path.join(HERE, "csrc", f) for f in ("dense_common.h", "dense_eval.hip")]
 COPY_BYTES = 800_000_000
 N = 10000
 SEED = 1000
 
 
 def source_hash() -> str:
-    with open(DENSE_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in DENSE_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def algorithmic_bytes(m: int, n: int) -> float:
@@ -118,7 +122,7 @@ def summarize(fetch_csv: str, write_csv: str) -> str:
         f"| eval: algorithmic bytes per launch | {alg:.4g} |",
         "",
         f"traffic_bytes_per_launch: {fetch_b + write_b:.6e}",
-        f"dense_passes.hip sha256: {source_hash()}",
+        f"LSE-pass source sha256: {source_hash()}",
         "",
     ]
     return "\n".join(lines)
@@ -126,7 +130,7 @@ def summarize(fetch_csv: str, write_csv: str) -> str:
 
 def read_traffic(md_path: str):
     """Traffic per launch from a summary written by --summarize, or None if the file is
-    missing or was made for a different dense-pass source."""
+    missing or was made for a different LSE-pass source."""
     if not os.path.exists(md_path):
         return None
     traffic, h = None, None
@@ -134,7 +138,7 @@ def read_traffic(md_path: str):
         for line in f:
             if line.startswith("traffic_bytes_per_launch:"):
                 traffic = float(line.split(":", 1)[1])
-            elif line.startswith("dense_passes.hip sha256:"):
+            elif line.startswith("LSE-pass source sha256:"):
                 h = line.split(":", 1)[1].strip()
     if traffic is None or h != source_hash():
         return None
