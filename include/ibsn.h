@@ -76,6 +76,17 @@ int ibsn_num_cus(const ibsn_ctx *ctx);
 
 typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1 } ibsn_cost_kind;
 
+/* Arithmetic of the m x n passes.  IBSN_PREC_F64: everything in FP64.
+   IBSN_PREC_MIXED (the precision form; the paper fixes no precision): the eval, trial and
+   sparsify passes take exp(theta_ij - M_i) in FP32 (argument formed in FP64, relative
+   error of each exponential about 2^-22) and the sparsified factor stores FP32 values,
+   which the HVP widens to FP64; shifts, row sums, column sums, CG dot products and norms,
+   the stop test with its rounding and certificate, and the objective stay FP64.  Results
+   of the pass-level calls then carry relative errors of a few 1e-7 (S, c, g, plan, the
+   factor's values); ibsn_solve switches back to FP64 passes near convergence (see
+   ibsn_options.mixed_switch), so its final iterate is held to FP64 accuracy. */
+typedef enum { IBSN_PREC_F64 = 0, IBSN_PREC_MIXED = 1 } ibsn_precision;
+
 /* OT problem, eq. (1).  C is row-major with leading dimension ldc >= n (elements);
    an FP32 cost is widened exactly to FP64 before use.  No rescaling of C is done:
    normalising max C to 1 (Section 5, "Setup") is the caller's job.
@@ -84,6 +95,7 @@ typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1 } ibsn_cost_kind;
 typedef struct {
     int64_t m, n;
     int32_t cost_kind;        /* ibsn_cost_kind */
+    int32_t precision;        /* ibsn_precision (0 = FP64) */
     const void *C;
     int64_t ldc;
     const double *a, *b;      /* device, m and n */
@@ -134,7 +146,13 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
    by their kept sum; row istar is kept whole.  istar < 0 selects argmax a (lowest
    index on ties).  *out receives a library-owned handle (free with ibsn_csr_free);
    it also holds d = P_rho^T a and the transpose used by ibsn_hvp.  A row whose
-   entries all fall below rho is left empty.  Needs 24*m*n bytes of workspace. */
+   entries all fall below rho is left empty.  ibsn_destroy releases the device memory of
+   the handles of its context that are still open; such a handle is then valid only for
+   ibsn_csr_free (which frees what remains), and the calls that take it with a context
+   return IBSN_ERR_INVALID_ARG for it, as for a handle of another context.
+   IBSN_PREC_MIXED: the values are stored as FP32 (P~) and d = P~^T (a o P~ 1), so that
+   H_rho 1 = 0 and H_rho is positive semidefinite for the stored factor (Theorem 3.2);
+   P~ 1 = 1 up to FP32 rounding of the values.  Needs 24*m*n bytes of workspace. */
 int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
                   const double *gamma, const double *M, const double *S, double rho,
                   int64_t istar, ibsn_csr **out);
@@ -209,6 +227,10 @@ typedef struct {
                                          /*    the inner loop of one outer iteration       */
     int32_t eot;                         /* 1: (E)IBSN of appendix C.4: prox centre 1 1^T,  */
     double eot_tol;                      /*    one subproblem until ||g|| < eot_tol (1e-9) */
+    double mixed_switch;                 /* IBSN_PREC_MIXED: Newton steps use the FP32    */
+                                         /*   passes while ||g||_2 >= mixed_switch *      */
+                                         /*   FLT_EPSILON * ||b||_2 (64), and FP64 after   */
+                                         /*   that or after an FP32 line search fails     */
 } ibsn_options;
 
 void ibsn_default_options(ibsn_options *opt);
@@ -218,6 +240,7 @@ typedef struct {
     double grad_norm, primal, dual, rel_gap, kkt, dphi, marg_l1;
     double t_eval, t_sparsify, t_cg, t_linesearch, t_stop, t_total;  /* seconds */
     double nnz_mean, nnz_last;  /* stored entries of the sparsified factors (mean, last) */
+    int64_t mixed_passes;       /* m x n passes run in the FP32 form (IBSN_PREC_MIXED) */
     int32_t status;
 } ibsn_report;
 

@@ -27,6 +27,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace ibsn {
 namespace {
 
@@ -234,6 +236,33 @@ __device__ __forceinline__ double exp_tab(double x, const double *__restrict__ e
     return ldexp(fma(tj, p, tj), k >> 7);
 }
 
+// exp(x) in FP32 for the mixed-precision passes (eval, trial, sparsify).  The FP64
+// argument x (as above, <= 709) is split as x/ln2 = kk + f with kk = rint(x/ln2), |f| <= 1/2;
+// f is rounded to FP32 (absolute error <= 2^-25), 2^f comes from the hardware base-2
+// exponential (v_exp_f32) and 2^kk is applied exactly with ldexp.  The relative error is
+// a few FP32 units in the last place whatever |x| is; results below the FP32 range
+// (x < about -103) are flushed to 0, and NaN gives 0 as in exp_tab.
+constexpr double MX_LOG2E = 0x1.71547652b82fep+0;   // 1 / ln 2
+__device__ __forceinline__ float exp_mx(double x)
+{
+    const double t = fmax(x * MX_LOG2E, -160.0);
+    const double kk = rint(t);
+    return ldexpf(__builtin_amdgcn_exp2f((float)(t - kk)), (int)kk);
+}
+
+// register type of the per-entry values of a pass: FP32 in the mixed-precision form
+template <bool MX>
+using xval_t = typename std::conditional<MX, float, double>::type;
+
+template <bool MX>
+__device__ __forceinline__ double exp_pass(double x, const double *__restrict__ etab)
+{
+    if constexpr (MX)
+        return (double)exp_mx(x);
+    else
+        return exp_tab(x, etab);
+}
+
 // 2^(j/128), j < 128, into LDS (one barrier)
 __device__ __forceinline__ void exp_table_init(double *etab)
 {
@@ -380,6 +409,34 @@ __device__ __forceinline__ void stage_rows(int i, int i1, const double *__restri
     X(512, 6, 4)            \
     X(512, 8, 6)            \
     X(512, 10, 8)
+
+// the same with the precision form as a second compile-time choice (constexpr bool MX)
+#define IBSN_DISPATCH_MX(NT_, Q_, QF_, BODY)                                      \
+    if (p.nt == NT_ && p.q == Q_ && p.qf == QF_) {                               \
+        constexpr int NT = NT_, Q = Q_, QF = QF_;                                \
+        if (d.cost_kind == 0) {                                                  \
+            constexpr int VEC = 2;                                               \
+            using CT = double;                                                   \
+            if (d.mixed) {                                                       \
+                constexpr bool MX = true;                                        \
+                BODY;                                                            \
+            } else {                                                             \
+                constexpr bool MX = false;                                       \
+                BODY;                                                            \
+            }                                                                    \
+        } else {                                                                 \
+            constexpr int VEC = 4;                                               \
+            using CT = float;                                                    \
+            if (d.mixed) {                                                       \
+                constexpr bool MX = true;                                        \
+                BODY;                                                            \
+            } else {                                                             \
+                constexpr bool MX = false;                                       \
+                BODY;                                                            \
+            }                                                                    \
+        }                                                                        \
+        return hipGetLastError();                                                \
+    }
 
 #define IBSN_DISPATCH(NT_, Q_, QF_, BODY)                                         \
     if (p.nt == NT_ && p.q == Q_ && p.qf == QF_) {                               \

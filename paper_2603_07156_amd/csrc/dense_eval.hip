@@ -7,8 +7,10 @@ namespace {
 // ---------------------------------------------------------------------------------
 // eval: M_i = max_j theta_ij, S_i = sum_j exp(theta_ij - M_i), column partials of
 // a_i P_ij, objective row terms a_i ((r_i + M_i) + log S_i).
+// MX (mixed precision): exp(theta_ij - m_w) in FP32 and held as FP32; the argument, the
+// shifts, S_i, the column partials and the objective stay FP64.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT>
+template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
 __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t ldc, int m, int n,
                                              double sigma, double qg,
                                              const double *__restrict__ w,
@@ -36,7 +38,8 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
     stage_lds(w, n, wl);
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     __shared__ double rA[ROWCH], rR[ROWCH];
-    double acc[E], x[E];
+    double acc[E];
+    xval_t<MX> x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e)
         acc[e] = 0.0;
@@ -57,8 +60,9 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const double xa = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - mw);
-            const double p = exp_tab(slot_valid<QF, NT, VEC>(e, n) ? xa : -INFINITY, etab);
-            x[e] = p;
+            const double p =
+                exp_pass<MX>(slot_valid<QF, NT, VEC>(e, n) ? xa : -INFINITY, etab);
+            x[e] = (xval_t<MX>)p;   // exact: in the mixed form p is already an FP32 value
             st += p;
         }
         const double sw = wave_red<OP_SUM>(st);
@@ -77,13 +81,13 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         const double sc = ai / S * exp_tab(mw - M, etab);   // a_i exp(m_w - M) / S
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            acc[e] = fma(sc, x[e], acc[e]);
+            acc[e] = fma(sc, (double)x[e], acc[e]);
         if (plan) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int j = col_of<NT, VEC>(e);
                 if (j < n)
-                    plan[(int64_t)i * n + j] = sc * x[e];
+                    plan[(int64_t)i * n + j] = sc * (double)x[e];
             }
         }
         if (threadIdx.x == 0) {
@@ -107,12 +111,12 @@ hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, do
                        double *lse, double *plan, double *colpart, double *rowpart, hipStream_t st)
 {
 #define BODY                                                                                     \
-    hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT),                         \
+    hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT),                     \
                        (size_t)d.n * sizeof(double), st,                                         \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, r, M, S, \
                        lse,                                                                      \
                        plan, colpart, rowpart)
-#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+#define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)
 #undef X
 #undef BODY

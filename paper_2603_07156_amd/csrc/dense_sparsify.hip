@@ -10,8 +10,11 @@ namespace {
 // per vector lane gives the wave's kept count and each lane's rank; the counts of all
 // (q, wave) segments, in column order, give each segment's base.  Entries go to the
 // row's slot [i*n, i*n + len_i) in ascending column order.
+// MX (mixed precision): p from the FP32 exponential (the threshold test is taken on that
+// value, widened), kept values stored as FP32; sums stay FP64, and d = P~^T (a o P~ 1) for
+// the stored factor P~.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT>
+template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
 __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64_t ldc, int m, int n,
                                                  double sigma, const double *__restrict__ w,
                                                  const double *__restrict__ a,
@@ -19,7 +22,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
                                                  const double *__restrict__ S, double rho,
                                                  const int *__restrict__ istar_p,
                                                  int32_t *__restrict__ col,
-                                                 double *__restrict__ val,
+                                                 xval_t<MX> *__restrict__ val,
                                                  int32_t *__restrict__ len,
                                                  double *__restrict__ colpart)
 {
@@ -36,7 +39,8 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
     extern __shared__ double wl[];   // w staged in LDS (n doubles)
     __shared__ double etab[EXP_TAB];
     __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH];
-    double acc[E], x[E];
+    double acc[E];
+    xval_t<MX> x[E];
     const int istar = *istar_p;
     exp_table_init(etab);
     stage_lds(w, n, wl);
@@ -57,9 +61,9 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
             const int j = col_of<NT, VEC>(e);
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
             const double xa = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - Mi);
-            const double p = exp_tab(valid ? xa : -INFINITY, etab) * iS;
+            const double p = exp_pass<MX>(valid ? xa : -INFINITY, etab) * iS;
             const bool keep = valid && (dense || p >= rho);
-            x[e] = p;
+            x[e] = (xval_t<MX>)p;
             if (keep) {
                 keepbits |= 1ull << e;
                 red[0] += p;
@@ -88,8 +92,9 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
             }
         }
         const double ai = rA[slot];
+        double rs = 0.0;   // MX: sum of the row's stored values
         int32_t *crow = col + (int64_t)i * n;
-        double *vrow = val + (int64_t)i * n;
+        xval_t<MX> *vrow = val + (int64_t)i * n;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             int before = 0;
@@ -100,14 +105,34 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
             for (int v = 0; v < VEC; ++v) {
                 const int e = q * VEC + v;
                 if (keepbits & (1ull << e)) {
-                    const double pv = dense ? x[e] : x[e] * ik;
+                    // d = P_rho^T a from the values as stored, so that H_rho 1 = 0 holds
+                    // for the factor the HVP reads
+                    const xval_t<MX> pv =
+                        (xval_t<MX>)(dense ? (double)x[e] : (double)x[e] * ik);
                     const int pos = base[q] + before;
                     crow[pos] = col_of<NT, VEC>(e);
                     vrow[pos] = pv;
-                    acc[e] = fma(ai, pv, acc[e]);
+                    if constexpr (MX) {
+                        x[e] = pv;
+                        rs += (double)pv;
+                    } else {
+                        acc[e] = fma(ai, (double)pv, acc[e]);
+                    }
                     ++before;
                 }
             }
+        }
+        if constexpr (MX) {
+            // FP32 values make the stored row sum 1 + O(2^-24) rather than 1; with
+            // d = P~^T (a o P~ 1) the stored factor P~ still gives H_rho 1 = 0 and a
+            // positive semidefinite H_rho (Theorem 3.2)
+            double t[1] = {rs};
+            RedSum::run(t, lds, parity);
+            const double sc = ai * t[0];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (keepbits & (1ull << e))
+                    acc[e] = fma(sc, (double)x[e], acc[e]);
         }
         if (threadIdx.x == 0)
             len[i] = running;
@@ -118,16 +143,16 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
 }  // namespace
 
 hipError_t launch_sparsify(const RowPlan &p_in, const DenseArgs &d, const double *M, const double *S,
-                           double rho, const int *istar, int32_t *col, double *val, int32_t *len,
+                           double rho, const int *istar, int32_t *col, void *val, int32_t *len,
                            double *colpart, hipStream_t st)
 {
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                     \
-    hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,              \
+    hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT), lds_bytes, st, \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, rho, \
-                       istar, col, val, len, colpart)
-#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+                       istar, col, (xval_t<MX> *)val, len, colpart)
+#define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)
 #undef X
 #undef BODY

@@ -10,8 +10,10 @@ namespace {
 //   B = sum q*cv, qe = q + q*cv = q e^tau, delta = log1p(B/A);
 //   big step (BIG=1, cv = exp(tau - tau_shift)): qe = q*cv, delta = tau_shift + log(Z/A).
 //   Z = sum qe, P'_ij = qe / Z, new state M' = M + tau_shift + log(max qe), S' = Z / max qe.
+// MX (mixed precision): q from the FP32 exponential and qe held as FP32; cv, the sums
+// A, B, Z, the decrease and the new row state stay FP64.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT, int BIG>
+template <int NT, int Q, int QF, int VEC, typename CT, bool MX, int BIG>
 __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc, int m, int n,
                                               double sigma, double qg,
                                               const double *__restrict__ w,
@@ -35,7 +37,8 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
     extern __shared__ double cvl[];   // colv staged in LDS (n doubles)
     __shared__ double etab[EXP_TAB];
     __shared__ double rM[ROWCH], rA[ROWCH];
-    double wr[E], acc[E], x[E];
+    double wr[E], acc[E];
+    xval_t<MX> x[E];
     exp_table_init(etab);
     load_w<NT, Q, VEC>(w, n, wr);   // padding slots: -inf, so q = 0 there
     stage_lds(colv, n, cvl);
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         double red[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const double q = exp_tab(fma(-sigma, (double)xr[e], wr[e] - Mi), etab);
+            const double q = exp_pass<MX>(fma(-sigma, (double)xr[e], wr[e] - Mi), etab);
             const double cv = cvl[slot_col<QF, NT, VEC>(e, n)];   // finite, and q = 0 on padding
             red[0] += q;
             double qe;
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
             }
             red[2] += qe;
             red[3] = fmax(red[3], qe);
-            x[e] = qe;
+            x[e] = (xval_t<MX>)qe;
         }
         Red::run(red, lds, parity);
         const double A = red[0], B = red[1], Z = red[2], mx = red[3];
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         const double sc = ai / Z;
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            acc[e] = fma(sc, x[e], acc[e]);
+            acc[e] = fma(sc, (double)x[e], acc[e]);
         if (threadIdx.x == 0) {
             // a step that pushes a whole row below the FP64 range is not a decrease
             const double delta =
@@ -99,13 +102,13 @@ hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
-    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
                        scal, M_new, S_new, colpart, rowpart);                                     \
-    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, 1>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 1>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
                        scal, M_new, S_new, colpart, rowpart)
-#define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
+#define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)
 #undef X
 #undef BODY

@@ -11,6 +11,7 @@
 #include "solver_kernels.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -35,6 +36,7 @@ struct ibsn_csr {
     int64_t m = 0, n = 0;
     int64_t nnz = 0;       // host copy (valid after sparsify)
     int64_t istar = -1;    // host copy
+    int f32 = 0;           // values stored as FP32 (mixed-precision sparsify)
     DevBuf col, val, len, colptr, colcnt, rowidx, cval, mask, off, d, istar_dev, nnz_dev;
 };
 
@@ -49,6 +51,7 @@ struct ibsn_ctx {
     DevBuf stopout, tauv, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     ibsn_csr *solver_csr = nullptr;
+    std::vector<ibsn_csr *> csrs;  // handles returned by ibsn_sparsify and not yet freed
     // solver state (grow-only, reused across ibsn_solve calls)
     DevBuf sv_r, sv_s, sv_g, sv_M, sv_S, sv_Mt, sv_St, sv_ct, sv_gt, sv_D, sv_c, sv_gv;
     // kernel timing (HIP events around the main kernel of each phase)
@@ -145,6 +148,8 @@ int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "eta=%g must be finite and > 0", p->eta);
     if (p->cost_kind != IBSN_COST_F64 && p->cost_kind != IBSN_COST_F32)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "cost_kind=%d unknown", p->cost_kind);
+    if (p->precision != IBSN_PREC_F64 && p->precision != IBSN_PREC_MIXED)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "precision=%d unknown", p->precision);
     if (!p->C || !p->a || !p->b)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "C, a and b must be device pointers");
     if (p->ldc < p->n)
@@ -214,9 +219,10 @@ int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
     return IBSN_OK;
 }
 
-DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k, double q)
+DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k, double q, int mixed = 0)
 {
     DenseArgs d;
+    d.mixed = mixed;
     d.q = q;
     d.C = p->C;
     d.ldc = p->ldc;
@@ -303,10 +309,10 @@ struct KTimer {
 // scal[SC_OBJ] when r != null (needs gamma for b^T gamma); norms of g to scal.
 int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
              const double *r, const double *gamma, double *M, double *S, double *lse, double *c,
-             double *g, double *plan)
+             double *g, double *plan, int mixed)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k, q);
+    DenseArgs d = dense_args(ctx, p, k, q, mixed);
     {
         KTimer kt(ctx, IBSN_KT_EVAL);
         CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart),
@@ -329,10 +335,10 @@ int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
 // cn, gn; scal[SC_DL] = dL.
 int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
               const double *M, const double *Delta, double t, double *Mn, double *Sn, double *cn,
-              double *gn)
+              double *gn, int mixed)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k, q);
+    DenseArgs d = dense_args(ctx, p, k, q, mixed);
     double *scal = P<double>(ctx->scal);
     CKH(sk_trial_prep(p->n, t, p->eta, q, Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
                       scal, st));
@@ -418,14 +424,15 @@ void csr_release(ibsn_csr *c)
 
 // sparsify into c at the state (w formed), rho; istar on device in c->istar_dev
 int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
-                 const double *M, const double *S, double rho, ibsn_csr *c)
+                 const double *M, const double *S, double rho, ibsn_csr *c, int mixed)
 {
     hipStream_t st = ctx->stream;
-    DenseArgs d = dense_args(ctx, p, k, q);
+    DenseArgs d = dense_args(ctx, p, k, q, mixed);
+    c->f32 = mixed;
     {
         KTimer kt(ctx, IBSN_KT_SPARSIFY);
         CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
-                            P<double>(c->val), P<int32_t>(c->len), P<double>(ctx->colpart), st));
+                            c->val.p, P<int32_t>(c->len), P<double>(ctx->colpart), st));
     }
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(c->d), nullptr,
                          nullptr, st));
@@ -433,14 +440,14 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     cw.colptr = P<int64_t>(c->colptr);
     cw.colcnt = P<int64_t>(c->colcnt);
     cw.rowidx = P<int32_t>(c->rowidx);
-    cw.cval = P<double>(c->cval);
+    cw.cval = c->cval.p;
     cw.mask = P<uint32_t>(c->mask);
     cw.off = P<int32_t>(c->off);
     // lanes per row of the fill from the previous factor's mean row length (64 at first)
     cw.lpc = (c->nnz > 0 && (double)c->nnz / (double)c->m < 96.0) ? 16 : 64;
     {
         KTimer kt(ctx, IBSN_KT_CSC);
-        CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), P<double>(c->val),
+        CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), c->val.p, c->f32,
                              P<int32_t>(c->len), P<int>(c->istar_dev), cw,
                              P<int64_t>(c->nnz_dev), st));
     }
@@ -459,12 +466,13 @@ CsrView csr_view(const ibsn_csr *c)
     v.m = c->m;
     v.n = c->n;
     v.col = (const int32_t *)c->col.p;
-    v.val = (const double *)c->val.p;
+    v.val = c->val.p;
+    v.f32 = c->f32;
     v.len = (const int32_t *)c->len.p;
     v.istar = (const int *)c->istar_dev.p;
     v.colptr = (const int64_t *)c->colptr.p;
     v.rowidx = (const int32_t *)c->rowidx.p;
-    v.cval = (const double *)c->cval.p;
+    v.cval = c->cval.p;
     v.d = (const double *)c->d.p;
     return v;
 }
@@ -596,6 +604,12 @@ void ibsn_destroy(ibsn_ctx *ctx)
         csr_release(ctx->solver_csr);
         delete ctx->solver_csr;
     }
+    // handles still open lose their device memory now; ibsn_csr_free later frees the rest
+    for (ibsn_csr *c : ctx->csrs) {
+        csr_release(c);
+        c->ctx = nullptr;
+    }
+    ctx->csrs.clear();
     DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
                       &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv,
@@ -669,6 +683,7 @@ void ibsn_default_options(ibsn_options *o)
     o->stall_limit = 3;
     o->eot = 0;
     o->eot_tol = 1e-9;
+    o->mixed_switch = 64.0;
 }
 
 int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
@@ -711,7 +726,7 @@ int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cen
                       ctx->stream));
     CKI(run_eval(ctx, prob, rp, ctr->k, ctr->quantum, obj_host ? ctr->r : nullptr, gamma, M, S,
                  lse, colmarg,
-                 grad, plan));
+                 grad, plan, prob->precision));
     if (obj_host) {
         CKI(read_scal(ctx));
         *obj_host = ctx->host_scal[SC_OBJ];
@@ -736,7 +751,7 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, 
     CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
                       ctx->stream));
     CKI(run_trial(ctx, prob, rp, ctr->k, ctr->quantum, M, Delta, t, M_new, S_new, colmarg_new,
-                  grad_new));
+                  grad_new, prob->precision));
     CKI(read_scal(ctx));
     *dL_host = ctx->host_scal[SC_DL];
     return IBSN_OK;
@@ -787,12 +802,13 @@ int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ct
             rc = fail(ctx, IBSN_ERR_HIP, "make_w failed");
     }
     if (rc == IBSN_OK)
-        rc = run_sparsify(ctx, prob, rp, ctr->k, ctr->quantum, M, S, rho, c);
+        rc = run_sparsify(ctx, prob, rp, ctr->k, ctr->quantum, M, S, rho, c, prob->precision);
     if (rc < 0) {
         csr_release(c);
         delete c;
         return rc;
     }
+    ctx->csrs.push_back(c);
     *out = c;
     return IBSN_OK;
 }
@@ -801,6 +817,8 @@ int ibsn_csr_info(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *nnz, int64_t *ist
 {
     if (!ctx || !csr)
         return IBSN_ERR_INVALID_ARG;
+    if (csr->ctx != ctx)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "the factor belongs to another context");
     if (nnz)
         *nnz = csr->nnz;
     if (istar)
@@ -813,8 +831,10 @@ int ibsn_csr_export(ibsn_ctx *ctx, const ibsn_csr *csr, int64_t *row_ptr, int32_
 {
     if (!ctx || !csr || !row_ptr || !col || !val || !d)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "all export buffers are required");
+    if (csr->ctx != ctx)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "the factor belongs to another context");
     CKH(hipSetDevice(ctx->device));
-    CKH(launch_export_csr(csr->m, csr->n, (const int32_t *)csr->col.p, (const double *)csr->val.p,
+    CKH(launch_export_csr(csr->m, csr->n, (const int32_t *)csr->col.p, csr->val.p, csr->f32,
                           (const int32_t *)csr->len.p, row_ptr, col, val, csr->nnz,
                           ctx->stream));
     CKH(hipMemcpyAsync(d, csr->d.p, sizeof(double) * csr->n, hipMemcpyDeviceToDevice,
@@ -826,12 +846,15 @@ void ibsn_csr_free(ibsn_csr *csr)
 {
     if (!csr)
         return;
-    if (csr->ctx) {
-        (void)hipSetDevice(csr->ctx->device);
-        if (csr->ctx->stream)
-            (void)hipStreamSynchronize(csr->ctx->stream);
+    if (ibsn_ctx *ctx = csr->ctx) {
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream)
+            (void)hipStreamSynchronize(ctx->stream);
+        auto it = std::find(ctx->csrs.begin(), ctx->csrs.end(), csr);
+        if (it != ctx->csrs.end())
+            ctx->csrs.erase(it);
+        csr_release(csr);
     }
-    csr_release(csr);
     delete csr;
 }
 
@@ -842,6 +865,8 @@ int ibsn_hvp(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, do
         return IBSN_ERR_INVALID_ARG;
     if (!csr || !a || !v || !y)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "csr, a, v and y are required");
+    if (csr->ctx != ctx)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "the factor belongs to another context");
     if (!(eta > 0.0) || !std::isfinite(shift))
         return fail(ctx, IBSN_ERR_INVALID_ARG, "eta must be > 0 and shift finite");
     CKH(hipSetDevice(ctx->device));
@@ -856,6 +881,8 @@ int ibsn_cg(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, dou
         return IBSN_ERR_INVALID_ARG;
     if (!csr || !a || !rhs || !x)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "csr, a, rhs and x are required");
+    if (csr->ctx != ctx)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "the factor belongs to another context");
     if (!(eta > 0.0) || !(shift >= 0.0) || !(tol >= 0.0) || maxit < 0)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "need eta > 0, shift >= 0, tol >= 0, maxit >= 0");
     CKH(hipSetDevice(ctx->device));
@@ -905,7 +932,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         ibsn_default_options(&opt);
     if (opt.max_outer < 1 || opt.max_newton < 1 || opt.max_backtrack < 0 ||
         !(opt.beta > 0 && opt.beta < 1) || !(opt.sigma_armijo > 0 && opt.sigma_armijo < 1) ||
-        (opt.eot != 0 && opt.eot != 1) || (opt.eot && !(opt.eot_tol > 0)))
+        (opt.eot != 0 && opt.eot != 1) || (opt.eot && !(opt.eot_tol > 0)) ||
+        !(opt.mixed_switch >= 0))
         return fail(ctx, IBSN_ERR_INVALID_ARG, "invalid options");
     const bool resume = k_io && *k_io > 0;
     if (resume && (!r_io || !s_io))
@@ -1007,6 +1035,17 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     if (!std::isfinite(cmax))
         CKS(fail(ctx, IBSN_ERR_NUMERIC, "C has a NaN or infinite entry"));
     double *w = P<double>(ctx->w);
+    // Mixed precision: Newton steps run their passes (sparsify, trial) in the FP32 form
+    // while ||g||_2 >= mixed_switch * eps32 * ||b||_2; below that, after a mixed-form line
+    // search fails, and always for the Sinkhorn steps, the stop test and the outer update,
+    // the state comes from FP64 passes (an FP64 eval refreshes a state left by a mixed pass).
+    const bool mx_on = prob->precision == IBSN_PREC_MIXED;
+    double mx_thr = INFINITY;
+    if (mx_on) {
+        CKSH(sk_dot_slot(n, prob->b, prob->b, SC_BB, scal, st));
+        CKS(read_scal(ctx));
+        mx_thr = opt.mixed_switch * (double)FLT_EPSILON * std::sqrt(ctx->host_scal[SC_BB]);
+    }
 
     ibsn_report R;
     memset(&R, 0, sizeof(R));
@@ -1026,15 +1065,30 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         CKS(read_scal(ctx));
         const double q = quantum_of(ctx->host_scal[SC_WMAX] + sigma * cmax);
         CKSH(launch_make_w(s, gamma, q, eta, n, w, st));
+        bool state_mx = false;   // (M, S, c, g) come from a mixed-precision pass
+        bool fp64_lock = false;  // FP64 passes for the rest of this subproblem
+        auto refresh = [&]() -> int {   // FP64 eval at the current point
+            CKI(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr, 0));
+            ++R.passes;
+            state_mx = false;
+            return read_scal(ctx);
+        };
         // fresh evaluation of the new subproblem
-        CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
+        CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr,
+                     mx_on ? 1 : 0));
         ++R.passes;
+        if (mx_on)
+            ++R.mixed_passes;
+        state_mx = mx_on;
         CKS(read_scal(ctx));
+        if (state_mx && (ctx->host_scal[SC_GN] < mx_thr ||
+                         (opt.sinkhorn_maxit > 0 && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol)))
+            CKS(refresh());
         // Sinkhorn warm-up (Algorithm 2, steps 3-4), on the grid potentials
         for (int it = 0; it < opt.sinkhorn_maxit && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol;
              ++it) {
             CKSH(sk_sinkhorn_step(n, eta, q, prob->b, c, s, w, st));
-            CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr));
+            CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr, 0));
             ++R.passes;
             ++R.sinkhorn;
             CKS(read_scal(ctx));
@@ -1048,15 +1102,19 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         bool stopped = false;
         int stalls = 0;
         for (int v = 0; v < opt.max_newton; ++v) {
+            if (state_mx && (fp64_lock || ctx->host_scal[SC_GN] < mx_thr))
+                CKS(refresh());
             const double gn = ctx->host_scal[SC_GN];
+            const int mxs = (mx_on && !fp64_lock && gn >= mx_thr) ? 1 : 0;
             if (opt.eot && gn < opt.eot_tol) {   // (E)IBSN: the single subproblem is solved
                 stopped = true;
                 break;
             }
             const double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / mn;   // step 6
             ta = now_s();
-            CKS(run_sparsify(ctx, prob, rp, k, q, M, S, rho, csr));   // step 7
+            CKS(run_sparsify(ctx, prob, rp, k, q, M, S, rho, csr, mxs));   // step 7
             ++R.passes;
+            R.mixed_passes += mxs;
             R.nnz_last = (double)csr->nnz;
             nnz_sum += (double)csr->nnz;
             ++nnz_calls;
@@ -1075,8 +1133,9 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             int bt = 0;
             bool accepted = false;
             for (;;) {   // step 9: Armijo backtracking on a finite decrease
-                CKS(run_trial(ctx, prob, rp, k, q, M, Delta, t, Mt, St, ct, gt));
+                CKS(run_trial(ctx, prob, rp, k, q, M, Delta, t, Mt, St, ct, gt, mxs));
                 ++R.passes;
+                R.mixed_passes += mxs;
                 CKS(read_scal(ctx));
                 const double gd = ctx->host_scal[SC_GD];
                 const double dL = ctx->host_scal[SC_DL];
@@ -1090,6 +1149,12 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                 ++bt;
             }
             R.backtracks += bt;
+            if (!accepted && mxs) {
+                // the FP32 form could not certify a decrease: continue in FP64
+                fp64_lock = true;
+                R.t_linesearch += now_s() - ta;
+                continue;
+            }
             if (!accepted) {
                 // no acceptable step: keep the iterate, restore the norms of its g and
                 // end the inner loop
@@ -1104,9 +1169,13 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             std::swap(S, St);
             std::swap(c, ct);
             std::swap(g, gt);
+            state_mx = mxs != 0;
             ++R.newton;
             R.t_linesearch += now_s() - ta;
-            // step 12 with the practical schedule: gradient gate, then D_phi test
+            // step 12 with the practical schedule: gradient gate, then D_phi test (on an
+            // FP64 state)
+            if (!opt.eot && state_mx && ctx->host_scal[SC_GN] < mu)
+                CKS(refresh());
             if (!opt.eot && ctx->host_scal[SC_GN] < mu) {
                 ta = now_s();
                 CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
@@ -1125,6 +1194,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                     break;
             }
         }
+        if (state_mx)
+            CKS(refresh());
         CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
         if (!stopped || opt.eot) {
             ta = now_s();

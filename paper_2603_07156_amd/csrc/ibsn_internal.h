@@ -32,6 +32,8 @@ struct DenseArgs {
     double q;               // grid spacing of the potentials (power of two)
     const double *w;        // n: grid(s + gamma/eta)
     const double *a;        // m
+    int mixed;              // 1: FP32 exponentials and FP32 sparse values (eval, trial,
+                            // sparsify); sums, shifts and row state stay FP64
 };
 
 // ---- eval (fresh row LSE) ------------------------------------------------------
@@ -55,7 +57,7 @@ hipError_t launch_trial(const RowPlan &p, const DenseArgs &d, const double *M, c
 // Slotted CSR: row i's kept entries at [i*n, i*n + len_i), columns ascending.
 // colpart = column partials of a_i [P_rho]_ij (for d = P_rho^T a).
 hipError_t launch_sparsify(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
-                           double rho, const int *istar, int32_t *col, double *val, int32_t *len,
+                           double rho, const int *istar, int32_t *col, void *val, int32_t *len,
                            double *colpart, hipStream_t st);
 
 // ---- stop test, pass 1 (Algorithm 3 rows/columns) -------------------------------
@@ -95,7 +97,7 @@ struct CscWork {
     int64_t *colptr;     // n+1
     int64_t *colcnt;     // n
     int32_t *rowidx;     // capacity m*n
-    double *cval;        // capacity m*n
+    void *cval;          // capacity m*n values (FP64, or FP32 for a mixed-precision factor)
     uint32_t *mask;      // csc_row_blocks(m) * n: rows of a 32-row block keeping column j
     int32_t *off;        // csc_row_blocks(m) * n: exclusive scan of the mask popcounts
     int lpc;             // lanes per row of the fill (16 or 64)
@@ -103,7 +105,7 @@ struct CscWork {
 // number of 32-row blocks of the transpose
 int csc_row_blocks(int64_t m);
 // transpose of the slotted rows without the dense row istar (device scalar)
-hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
+hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                             const int32_t *len, const int *istar, CscWork &w, int64_t *nnz_dev,
                             hipStream_t st);
 
@@ -111,13 +113,14 @@ hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const doub
 struct CsrView {
     int64_t m, n;
     const int32_t *col;
-    const double *val;
+    const void *val;          // FP64, or FP32 when f32
     const int32_t *len;
     const int *istar;         // device scalar
     const int64_t *colptr;
     const int32_t *rowidx;
-    const double *cval;
-    const double *d;          // column sums d_j of the sparsified plan
+    const void *cval;         // same type as val
+    const double *d;          // column sums d_j of the sparsified plan (FP64)
+    int f32;
 };
 
 // Launch shape of the two gathers of an HVP (and of the CG vector kernels).
@@ -159,7 +162,7 @@ hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const doub
 hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, hipStream_t st);
 
 // export slotted CSR to standard CSR
-hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const double *val,
+hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,
                              int64_t cap, hipStream_t st);
 

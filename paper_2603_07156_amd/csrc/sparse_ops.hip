@@ -195,16 +195,16 @@ __global__ __launch_bounds__(1024) void k_scan32(int n, const int32_t *__restric
 }
 
 // fill: LPC lanes per row, every entry independently (see the position formula above)
-template <int LPC>
+template <int LPC, typename VT>
 __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *__restrict__ col,
-                                                  const double *__restrict__ val,
+                                                  const VT *__restrict__ val,
                                                   const int32_t *__restrict__ len,
                                                   const int *__restrict__ istar_p,
                                                   const int64_t *__restrict__ colptr,
                                                   const uint32_t *__restrict__ mask,
                                                   const int32_t *__restrict__ off,
                                                   int32_t *__restrict__ rowidx,
-                                                  double *__restrict__ cval)
+                                                  VT *__restrict__ cval)
 {
     const int i = (blockIdx.x * 256 + threadIdx.x) / LPC;
     const int l = threadIdx.x % LPC;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *_
         return;
     const int L = len[i];
     const int32_t *cr = col + (int64_t)i * n;
-    const double *vr = val + (int64_t)i * n;
+    const VT *vr = val + (int64_t)i * n;
     const int b = i / CSC_RB;
     const uint32_t below = (1u << (i - b * CSC_RB)) - 1u;
     const uint32_t *mb = mask + (int64_t)b * n;
@@ -286,9 +286,9 @@ __global__ __launch_bounds__(256) void k_cg_check(int it, double *__restrict__ s
 // row istar (every column, in order) is split into chunks of `star_chunk` columns, one
 // per extra workgroup: star_part[c] = sum over the chunk of val * v.
 // CG mode (scal != null): the vector is p = r + beta p_old, formed on the fly.
-template <int LPC>
+template <int LPC, typename VT>
 __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t *__restrict__ col,
-                                                    const double *__restrict__ val,
+                                                    const VT *__restrict__ val,
                                                     const int32_t *__restrict__ len,
                                                     const int *__restrict__ istar_p,
                                                     const double *__restrict__ a,
@@ -311,10 +311,10 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
         double s = 0.0;
         if (istar >= 0) {
             const int j0 = c * star_chunk, j1 = min(n, j0 + star_chunk);
-            const double *vr = val + (int64_t)istar * n;
+            const VT *vr = val + (int64_t)istar * n;
             for (int j = j0 + threadIdx.x; j < j1; j += 256) {
                 const double vj = cgm ? fma(beta, v[j], r_vec[j]) : v[j];
-                s = fma(vr[j], vj, s);
+                s = fma((double)vr[j], vj, s);
             }
         }
         s = block_sum<256>(s, lds);
@@ -328,12 +328,12 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
         return;
     const int L = len[g];
     const int32_t *cr = col + (int64_t)g * n;
-    const double *vr = val + (int64_t)g * n;
+    const VT *vr = val + (int64_t)g * n;
     double s = 0.0;
     for (int e = l; e < L; e += LPC) {
         const int j = cr[e];
         const double vj = cgm ? fma(beta, v[j], r_vec[j]) : v[j];
-        s = fma(vr[e], vj, s);
+        s = fma((double)vr[e], vj, s);
     }
 #pragma unroll
     for (int o = LPC / 2; o > 0; o >>= 1)
@@ -347,13 +347,13 @@ __global__ __launch_bounds__(256) void k_row_gather(int m, int n, const int32_t 
 // taken grid-stride, LPC lanes each.
 // CG mode: v_j = r_j + beta p_old_j is formed here and written back to p; y = Ap and a
 // per-workgroup partial of p.Ap goes to pap_part.
-template <int LPC>
+template <int LPC, typename VT>
 __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__restrict__ colptr,
                                                     const int32_t *__restrict__ rowidx,
-                                                    const double *__restrict__ cval,
+                                                    const VT *__restrict__ cval,
                                                     const double *__restrict__ au,
                                                     const double *__restrict__ d,
-                                                    const double *__restrict__ val,
+                                                    const VT *__restrict__ val,
                                                     const int *__restrict__ istar_p,
                                                     const double *__restrict__ a,
                                                     const double *__restrict__ star_part,
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__rest
     }
     const int istar = *istar_p;
     double aus = 0.0;
-    const double *prow = nullptr;
+    const VT *prow = nullptr;
     if (istar >= 0) {
         double t = 0.0;
         for (int k = threadIdx.x; k < nstar; k += 256)
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__rest
         const int64_t e0 = colptr[j], e1 = colptr[j + 1];
         double s = 0.0;
         for (int64_t e = e0 + l; e < e1; e += LPC)
-            s = fma(cval[e], au[rowidx[e]], s);
+            s = fma((double)cval[e], au[rowidx[e]], s);
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
             s += __shfl_xor(s, o, LPC);
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__rest
                 v[j] = vj;
             }
             if (prow)
-                s = fma(prow[j], aus, s);
+                s = fma((double)prow[j], aus, s);
             const double yj = (d[j] * vj - s) / eta + shift * vj;
             y[j] = yj;
             pap = fma(vj, yj, pap);
@@ -442,10 +442,10 @@ __device__ __forceinline__ void stage_vec(double *dst, const double *__restrict_
 // (n, respectively m, doubles), on a persistent grid of 1024-thread workgroups: the
 // sparse entries are then read as coalesced (index, value) streams and the vector from
 // LDS.  Summation order per row / column is the same as in the kernels above.
-template <int LPC>
+template <int LPC, typename VT>
 __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
                                                          const int32_t *__restrict__ col,
-                                                         const double *__restrict__ val,
+                                                         const VT *__restrict__ val,
                                                          const int32_t *__restrict__ len,
                                                          const int *__restrict__ istar_p,
                                                          const double *__restrict__ a,
@@ -471,9 +471,9 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
         double t = 0.0;
         if (istar >= 0) {
             const int j0 = c * star_chunk, j1 = min(n, j0 + star_chunk);
-            const double *vr = val + (int64_t)istar * n;
+            const VT *vr = val + (int64_t)istar * n;
             for (int j = j0 + threadIdx.x; j < j1; j += 1024)
-                t = fma(vr[j], vs[j], t);
+                t = fma((double)vr[j], vs[j], t);
         }
         t = block_sum<1024>(t, lds);
         if (threadIdx.x == 0)
@@ -488,21 +488,21 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
             continue;
         const int L = len[g];
         const int32_t *cr = col + (int64_t)g * n;
-        const double *vr = val + (int64_t)g * n;
+        const VT *vr = val + (int64_t)g * n;
         double s = 0.0;
         // each lane issues GUNR (index, value) loads before using any of them
         for (int base = l; base < L; base += GUNR * LPC) {
             int jj[GUNR];
-            double vv[GUNR];
+            VT vv[GUNR];
 #pragma unroll
             for (int k = 0; k < GUNR; ++k) {
                 const int e = base + k * LPC;
                 jj[k] = e < L ? cr[e] : 0;
-                vv[k] = e < L ? vr[e] : 0.0;
+                vv[k] = e < L ? vr[e] : (VT)0;
             }
 #pragma unroll
             for (int k = 0; k < GUNR; ++k)
-                s = fma(vv[k], vs[jj[k]], s);
+                s = fma((double)vv[k], vs[jj[k]], s);
         }
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
@@ -512,14 +512,14 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
     }
 }
 
-template <int LPC>
+template <int LPC, typename VT>
 __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
                                                          const int64_t *__restrict__ colptr,
                                                          const int32_t *__restrict__ rowidx,
-                                                         const double *__restrict__ cval,
+                                                         const VT *__restrict__ cval,
                                                          const double *__restrict__ au,
                                                          const double *__restrict__ d,
-                                                         const double *__restrict__ val,
+                                                         const VT *__restrict__ val,
                                                          const int *__restrict__ istar_p,
                                                          const double *__restrict__ a,
                                                          const double *__restrict__ star_part,
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
     stage_vec(us, au, nullptr, 0.0, m);
     const int istar = *istar_p;
     double aus = 0.0;
-    const double *prow = nullptr;
+    const VT *prow = nullptr;
     double t = 0.0;
     for (int k = threadIdx.x; k < nstar; k += 1024)
         t += star_part[k];
@@ -560,16 +560,16 @@ __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
         double s = 0.0;
         for (int64_t base = e0 + l; base < e1; base += GUNR * LPC) {
             int ii[GUNR];
-            double cc[GUNR];
+            VT cc[GUNR];
 #pragma unroll
             for (int k = 0; k < GUNR; ++k) {
                 const int64_t e = base + k * LPC;
                 ii[k] = e < e1 ? rowidx[e] : 0;
-                cc[k] = e < e1 ? cval[e] : 0.0;
+                cc[k] = e < e1 ? cval[e] : (VT)0;
             }
 #pragma unroll
             for (int k = 0; k < GUNR; ++k)
-                s = fma(cc[k], us[ii[k]], s);
+                s = fma((double)cc[k], us[ii[k]], s);
         }
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
                 v[j] = vj;
             }
             if (prow)
-                s = fma(prow[j], aus, s);
+                s = fma((double)prow[j], aus, s);
             const double yj = (d[j] * vj - s) / eta + shift * vj;
             y[j] = yj;
             pap = fma(vj, yj, pap);
@@ -690,9 +690,11 @@ __global__ __launch_bounds__(256) void k_make_w(int n, const double *__restrict_
     }
 }
 
-// standard CSR from the row slots; writes stay below cap (the caller's buffer length)
+// standard CSR from the row slots (values widened to FP64); writes stay below cap (the
+// caller's buffer length)
+template <typename VT>
 __global__ __launch_bounds__(256) void k_export_csr(int m, int n, const int32_t *__restrict__ col,
-                                                    const double *__restrict__ val,
+                                                    const VT *__restrict__ val,
                                                     const int64_t *__restrict__ row_ptr,
                                                     int32_t *__restrict__ ocol,
                                                     double *__restrict__ oval, int64_t cap)
@@ -704,7 +706,7 @@ __global__ __launch_bounds__(256) void k_export_csr(int m, int n, const int32_t 
     const int L = (int)min(row_ptr[i + 1] - o, cap - o);
     for (int e = threadIdx.x; e < L; e += 256) {
         ocol[o + e] = col[(int64_t)i * n + e];
-        oval[o + e] = val[(int64_t)i * n + e];
+        oval[o + e] = (double)val[(int64_t)i * n + e];
     }
 }
 
@@ -755,7 +757,7 @@ GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num
 
 int csc_row_blocks(int64_t m) { return (int)((m + CSC_RB - 1) / CSC_RB); }
 
-hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const double *val,
+hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                             const int32_t *len, const int *istar, CscWork &w, int64_t *nnz_dev,
                             hipStream_t st)
 {
@@ -768,30 +770,52 @@ hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const doub
                        istar);
     const int lpc = w.lpc;
     const unsigned blocks = (unsigned)((m * lpc + 255) / 256);
-    if (lpc >= 64)
-        hipLaunchKernelGGL((k_csc_fill<64>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col,
-                           val, len, istar, w.colptr, w.mask, w.off, w.rowidx, w.cval);
-    else
-        hipLaunchKernelGGL((k_csc_fill<16>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col,
-                           val, len, istar, w.colptr, w.mask, w.off, w.rowidx, w.cval);
+#define FILL(L_, VT_)                                                                          \
+    hipLaunchKernelGGL((k_csc_fill<L_, VT_>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col, \
+                       (const VT_ *)val, len, istar, w.colptr, w.mask, w.off, w.rowidx,           \
+                       (VT_ *)w.cval)
+    if (f32) {
+        if (lpc >= 64)
+            FILL(64, float);
+        else
+            FILL(16, float);
+    } else {
+        if (lpc >= 64)
+            FILL(64, double);
+        else
+            FILL(16, double);
+    }
+#undef FILL
     return hipGetLastError();
 }
 
 namespace {
+template <int L, typename VT>
+void row_gather_lt(const GatherPlan &g, const CsrView &c, const double *a, const double *v,
+                   double *au, double *star_part, int it, double *scal, const double *rr_part,
+                   int nrr, const double *r_vec, hipStream_t st)
+{
+    const VT *val = (const VT *)c.val;
+    if (g.lds)
+        hipLaunchKernelGGL((k_row_gather_lds<L, VT>), dim3(g.row_blocks), dim3(1024),
+                           (size_t)c.n * sizeof(double), st, (int)c.m, (int)c.n, c.col, val,
+                           c.len, c.istar, a, v, au, star_part, g.nstar, g.star_chunk, it, scal,
+                           rr_part, nrr, r_vec);
+    else
+        hipLaunchKernelGGL((k_row_gather<L, VT>), dim3(g.row_blocks + g.nstar), dim3(256), 0, st,
+                           (int)c.m, (int)c.n, c.col, val, c.len, c.istar, a, v, au, star_part,
+                           g.row_blocks, g.star_chunk, it, scal, rr_part, nrr, r_vec);
+}
+
 template <int L>
 void row_gather_l(const GatherPlan &g, const CsrView &c, const double *a, const double *v,
                   double *au, double *star_part, int it, double *scal, const double *rr_part,
                   int nrr, const double *r_vec, hipStream_t st)
 {
-    if (g.lds)
-        hipLaunchKernelGGL((k_row_gather_lds<L>), dim3(g.row_blocks), dim3(1024),
-                           (size_t)c.n * sizeof(double), st, (int)c.m, (int)c.n, c.col, c.val,
-                           c.len, c.istar, a, v, au, star_part, g.nstar, g.star_chunk, it, scal,
-                           rr_part, nrr, r_vec);
+    if (c.f32)
+        row_gather_lt<L, float>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
     else
-        hipLaunchKernelGGL((k_row_gather<L>), dim3(g.row_blocks + g.nstar), dim3(256), 0, st,
-                           (int)c.m, (int)c.n, c.col, c.val, c.len, c.istar, a, v, au, star_part,
-                           g.row_blocks, g.star_chunk, it, scal, rr_part, nrr, r_vec);
+        row_gather_lt<L, double>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
 }
 
 void row_gather(const GatherPlan &g, const CsrView &c, const double *a, const double *v,
@@ -808,20 +832,34 @@ void row_gather(const GatherPlan &g, const CsrView &c, const double *a, const do
         row_gather_l<4>(g, c, a, v, au, star_part, it, scal, rr_part, nrr, r_vec, st);
 }
 
+template <int L, typename VT>
+void col_gather_lt(const GatherPlan &g, const CsrView &c, const double *a, const double *au,
+                   const double *star_part, double *v, double eta, double shift, double *y, int it,
+                   const double *scal, const double *r_vec, double *pap_part, hipStream_t st)
+{
+    const VT *val = (const VT *)c.val, *cval = (const VT *)c.cval;
+    if (g.lds)
+        hipLaunchKernelGGL((k_col_gather_lds<L, VT>), dim3(g.col_blocks), dim3(1024),
+                           (size_t)c.m * sizeof(double), st, (int)c.m, (int)c.n, c.colptr,
+                           c.rowidx, cval, au, c.d, val, c.istar, a, star_part, g.nstar, v,
+                           eta, shift, y, it, scal, r_vec, pap_part);
+    else
+        hipLaunchKernelGGL((k_col_gather<L, VT>), dim3(g.col_blocks), dim3(256), 0, st, (int)c.n,
+                           c.colptr, c.rowidx, cval, au, c.d, val, c.istar, a, star_part,
+                           g.nstar, v, eta, shift, y, it, scal, r_vec, pap_part);
+}
+
 template <int L>
 void col_gather_l(const GatherPlan &g, const CsrView &c, const double *a, const double *au,
                   const double *star_part, double *v, double eta, double shift, double *y, int it,
                   const double *scal, const double *r_vec, double *pap_part, hipStream_t st)
 {
-    if (g.lds)
-        hipLaunchKernelGGL((k_col_gather_lds<L>), dim3(g.col_blocks), dim3(1024),
-                           (size_t)c.m * sizeof(double), st, (int)c.m, (int)c.n, c.colptr,
-                           c.rowidx, c.cval, au, c.d, c.val, c.istar, a, star_part, g.nstar, v,
-                           eta, shift, y, it, scal, r_vec, pap_part);
+    if (c.f32)
+        col_gather_lt<L, float>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec,
+                                pap_part, st);
     else
-        hipLaunchKernelGGL((k_col_gather<L>), dim3(g.col_blocks), dim3(256), 0, st, (int)c.n,
-                           c.colptr, c.rowidx, c.cval, au, c.d, c.val, c.istar, a, star_part,
-                           g.nstar, v, eta, shift, y, it, scal, r_vec, pap_part);
+        col_gather_lt<L, double>(g, c, a, au, star_part, v, eta, shift, y, it, scal, r_vec,
+                                 pap_part, st);
 }
 
 void col_gather(const GatherPlan &g, const CsrView &c, const double *a, const double *au,
@@ -897,13 +935,17 @@ hipError_t launch_dot(const double *x, const double *y, int64_t n, double *out, 
     return hipGetLastError();
 }
 
-hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const double *val,
+hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,
                              int64_t cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scan32, dim3(1), dim3(1024), 0, st, (int)m, len, row_ptr);
-    hipLaunchKernelGGL(k_export_csr, dim3((unsigned)m), dim3(256), 0, st, (int)m, (int)n, col, val,
-                       row_ptr, ocol, oval, cap);
+    if (f32)
+        hipLaunchKernelGGL((k_export_csr<float>), dim3((unsigned)m), dim3(256), 0, st, (int)m,
+                           (int)n, col, (const float *)val, row_ptr, ocol, oval, cap);
+    else
+        hipLaunchKernelGGL((k_export_csr<double>), dim3((unsigned)m), dim3(256), 0, st, (int)m,
+                           (int)n, col, (const double *)val, row_ptr, ocol, oval, cap);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ IBSN_OK = 0
 IBSN_WARN_MAXITER = 1
 IBSN_COST_F64 = 0
 IBSN_COST_F32 = 1
+PREC_F64 = 0    # ibsn_precision
+PREC_MIXED = 1
 MAX_N_F64 = 10240
 
 
@@ -32,7 +34,7 @@ class IBSNError(RuntimeError):
 
 class _Problem(ct.Structure):
     _fields_ = [("m", ct.c_int64), ("n", ct.c_int64), ("cost_kind", ct.c_int32),
-                ("C", ct.c_void_p), ("ldc", ct.c_int64), ("a", ct.c_void_p), ("b", ct.c_void_p),
+                ("precision", ct.c_int32), ("C", ct.c_void_p), ("ldc", ct.c_int64), ("a", ct.c_void_p), ("b", ct.c_void_p),
                 ("eta", ct.c_double)]
 
 
@@ -50,7 +52,7 @@ class Options(ct.Structure):
         ("max_outer", ct.c_int32), ("max_newton", ct.c_int32), ("max_backtrack", ct.c_int32),
         ("cg_maxit", ct.c_int32), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int32),
         ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int32),
-        ("eot", ct.c_int32), ("eot_tol", ct.c_double),
+        ("eot", ct.c_int32), ("eot_tol", ct.c_double), ("mixed_switch", ct.c_double),
     ]
 
 
@@ -65,6 +67,7 @@ class Report(ct.Structure):
         ("t_eval", ct.c_double), ("t_sparsify", ct.c_double), ("t_cg", ct.c_double),
         ("t_linesearch", ct.c_double), ("t_stop", ct.c_double), ("t_total", ct.c_double),
         ("nnz_mean", ct.c_double), ("nnz_last", ct.c_double),
+        ("mixed_passes", ct.c_int64),
         ("status", ct.c_int32),
     ]
 
@@ -192,12 +195,14 @@ class Context:
 
 @dataclass
 class Problem:
-    """eq. (1) data on the device: C (m x n, float64 or float32, row-major), a, b, eta."""
+    """eq. (1) data on the device: C (m x n, float64 or float32, row-major), a, b, eta;
+    precision: PREC_F64 or PREC_MIXED (FP32 exponentials and sparse values, FP64 sums)."""
 
     C: torch.Tensor
     a: torch.Tensor
     b: torch.Tensor
     eta: float
+    precision: int = 0
 
     @property
     def m(self):
@@ -219,7 +224,10 @@ class Problem:
         if not self.C.is_cuda:
             raise ValueError("C must be a device tensor")
         dev = self.C.device
-        return _Problem(self.m, self.n, kind, ct.c_void_p(self.C.data_ptr()), self.C.stride(0),
+        if self.precision not in (PREC_F64, PREC_MIXED):
+            raise ValueError("precision must be PREC_F64 or PREC_MIXED")
+        return _Problem(self.m, self.n, kind, int(self.precision), ct.c_void_p(self.C.data_ptr()),
+                        self.C.stride(0),
                         _ptr(self.a, self.m, name="a", device=dev),
                         _ptr(self.b, self.n, name="b", device=dev), float(self.eta))
 

@@ -12,7 +12,7 @@ LIB = os.path.join(ROOT, "paper_2603_07156_amd", "libibsn.so")
 
 
 def declared():
-    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)   # comments out
     return sorted(set(re.findall(r"\b(ibsn_[a-z_]+)\s*\(", text)))
 
 

@@ -423,3 +423,23 @@ def test_invalid_arguments(ib, ctx):
     with pytest.raises(ib.IBSNError) as e:   # quantum not a power of two
         ib.subproblem_eval(ctx, pr, ib.Center(0, ctr.r, ctr.s, 3e-12), g)
     assert e.value.code == -1
+
+
+def test_csr_handle_lifetime(ib, ctx):
+    """A factor is tied to its context: another context rejects it, and destroying its
+    context first leaves ibsn_csr_free valid (it frees only what remains)."""
+    inst = W.gmm_points(200, 3, m=150)
+    r, s, k, gamma = outer_state(inst, 0)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    c2 = ib.Context(0)
+    pr = problem(ib, inst)
+    gcsr = ib.sparsify(c2, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), 1e-6)
+    v = dev(W.random_dual(200, 5, 1.0))
+    with pytest.raises(ib.IBSNError):
+        ib.hvp(ctx, gcsr, pr.a, inst.eta, 0.0, v)
+    y = ib.hvp(c2, gcsr, pr.a, inst.eta, 0.0, v)
+    assert torch.isfinite(y).all()
+    c2.close()
+    gcsr.free()
+    assert gcsr.h is None
