@@ -9,6 +9,11 @@ of the implicit centre, Sinkhorn warm-up when the gradient is large, sparsified
 Newton-CG with Armijo steps, the inexact stop test and the certificate).  Warm-up
 steps run from X^0 = a b^T untimed; the timed steps resume from that state.
 
+`time_to_gap` compares the two precision forms on the same instance from X^0: plain FP64
+runs `--gap-outer` outer iterations and reaches a certified relative gap G; the
+mixed-precision form (FP32 exponentials and sparse values, FP64 sums, FP64 near
+convergence) then runs until its certified gap is <= G.  Both wall times are reported.
+
 JSON line: `value` is the whole-job streaming throughput of the timed steps, i.e.
 the algorithmic bytes of every dense m x n pass the steps made divided by their wall
 time (inputs resident in HBM).  `roofline` reports the row-LSE (eval) kernel: its
@@ -87,6 +92,32 @@ def cpu_baseline(inst, seconds: float):
                       f"{dt:.1f} s"}
 
 
+def time_to_gap(ibsn, ctx, prob, outer: int):
+    """Plain FP64 for `outer` outer iterations from X^0 sets the gap target G; the mixed
+    form runs from X^0 until its certified relative gap is <= G."""
+    import torch
+
+    def run(precision, **kw):
+        pr = ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=precision)
+        opt = ibsn.default_options(marg_tol=0.0, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ibsn.solve(ctx, pr, opt)
+        torch.cuda.synchronize()
+        rep = res["report"]
+        return {"seconds": time.perf_counter() - t0, "rel_gap": rep["rel_gap"],
+                "outer": rep["outer"], "newton": rep["newton"], "cg": rep["cg"],
+                "dense_passes": rep["passes"], "mixed_passes": rep["mixed_passes"],
+                "status": res["status"]}
+
+    plain = run(ibsn.PREC_F64, max_outer=outer, gap_tol=0.0)
+    target = plain["rel_gap"]
+    mixed = run(ibsn.PREC_MIXED, max_outer=2 * outer, gap_tol=target)
+    return {"target_rel_gap": target, "start": "X^0 = a b^T, gamma = 0",
+            "plain_f64": plain, "mixed": mixed,
+            "mixed_over_plain_time": mixed["seconds"] / plain["seconds"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +127,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--gap-outer", type=int, default=100,
+                    help="outer iterations of the plain run that sets the common gap target")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
@@ -174,6 +207,8 @@ def main() -> int:
         "kernel_ms": {k: {"total": v[0], "launches": v[1],
                           "avg": (v[0] / v[1]) if v[1] else None} for k, v in kt.items()},
     }
+    if args.gap_outer > 0:
+        out["time_to_gap"] = time_to_gap(ibsn, ctx, prob, args.gap_outer)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out))

@@ -492,9 +492,11 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     for (int64_t j = 0; j < n; ++j)
         ec[j] = fmax(b[j] - colF[j], 0.0);
 
-    /* step 11 and the divergence / certificate sums */
+    /* step 11 and the divergence / certificate sums (each row summed on its own, then the
+       row totals: a single running sum over m*n terms loses accuracy at large m*n) */
     double dphi = 0.0, cxh = 0.0, cx = 0.0, xmin = INFINITY, xu = 0.0;
     for (int64_t i = 0; i < m; ++i) {
+        double r_dphi = 0.0, r_cxh = 0.0, r_cx = 0.0, r_xu = 0.0;
         double zmin = INFINITY;
         for (int64_t j = 0; j < n; ++j) {
             double u = cost_at(C, kind, ldc, i, j) - gamma[j];
@@ -510,15 +512,19 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
             if (xhat)
                 xhat[i * n + j] = xh;
             if (xh > 0.0)
-                dphi += xh * (log(xh) - logX[i * n + j]) - xh + x;
+                r_dphi += xh * (log(xh) - logX[i * n + j]) - xh + x;
             else
-                dphi += x;
-            cxh += cij * xh;
-            cx += cij * x;
+                r_dphi += x;
+            r_cxh += cij * xh;
+            r_cx += cij * x;
             if (xh < xmin)
                 xmin = xh;
-            xu += x * ((cij - gamma[j]) - zmin);
+            r_xu += x * ((cij - gamma[j]) - zmin);
         }
+        dphi += r_dphi;
+        cxh += r_cxh;
+        cx += r_cx;
+        xu += r_xu;
     }
     double dual_g = dot(m, a, zc) + dot(n, b, gamma);
     double *psi = malloc(sizeof(double) * n);
@@ -541,16 +547,19 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     /* Delta_kkt (appendix C.1) for (X, gamma, zeta^c); U >= 0 by construction */
     double rr = 0.0, cc = 0.0, xf = 0.0, cf = 0.0, neg = 0.0;
     for (int64_t i = 0; i < m; ++i) {
-        double rs = 0.0;
+        double rs = 0.0, r_xf = 0.0, r_neg = 0.0, r_cf = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             double x = X[i * n + j];
             rs += x;
-            xf += x * x;
+            r_xf += x * x;
             if (x < 0.0)
-                neg += x * x;
+                r_neg += x * x;
             double cij = cost_at(C, kind, ldc, i, j);
-            cf += cij * cij;
+            r_cf += cij * cij;
         }
+        xf += r_xf;
+        neg += r_neg;
+        cf += r_cf;
         rr += (rs - a[i]) * (rs - a[i]);
     }
     for (int64_t j = 0; j < n; ++j)

@@ -315,7 +315,7 @@ constexpr int ROWCH = 64;
 // the current row.  stage(i) runs before rows i .. i+ROWCH-1 are touched (it fills the
 // LDS row scalars; it begins and ends with a barrier); body(i, slot, x) processes row i
 // held in x, with slot = its index in the staged chunk.
-template <int NT, int Q, int QF, int VEC, bool VECOK, bool PREFETCH, typename CT,
+template <int NT, int Q, int QF, int VEC, bool VECOK, bool PREFETCH, int RC, typename CT,
           typename Stage, typename Body>
 __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc, int n, int i0,
                                            int i1, Stage &stage, Body &body)
@@ -326,7 +326,7 @@ __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc
         if (i0 < i1)
             load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i0 * ldc, n, xr);
         for (int i = i0; i < i1; ++i) {
-            const int slot = (i - i0) & (ROWCH - 1);
+            const int slot = (i - i0) & (RC - 1);
             if (slot == 0)
                 stage(i);
             if (i + 1 < i1)
@@ -338,7 +338,7 @@ __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc
         }
     } else {
         for (int i = i0; i < i1; ++i) {
-            const int slot = (i - i0) & (ROWCH - 1);
+            const int slot = (i - i0) & (RC - 1);
             if (slot == 0)
                 stage(i);
             load_row<NT, Q, QF, VEC, VECOK>(C + (int64_t)i * ldc, n, xr);
@@ -351,20 +351,22 @@ __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc
 // is a multiple of VEC (the same for every row); scalar loads otherwise.
 // PREFETCH = false (passes whose per-entry state leaves no registers for a second row):
 // each row is loaded when it is reached.
-template <int NT, int Q, int QF, int VEC, bool PREFETCH = true, typename CT, typename Stage,
-          typename Body>
+// RC: rows per staged chunk (a power of two; the kernel's stage_rows<RC> fills them).
+template <int NT, int Q, int QF, int VEC, bool PREFETCH = true, int RC = ROWCH, typename CT,
+          typename Stage, typename Body>
 __device__ __forceinline__ void row_loop(const CT *__restrict__ C, int64_t ldc, int n, int i0,
                                          int i1, Stage &&stage, Body &&body)
 {
     const bool vec_ok = (reinterpret_cast<uintptr_t>(C) & 15u) == 0 &&
                         ((uint64_t)ldc * sizeof(CT)) % 16 == 0 && n % VEC == 0;
     if (vec_ok)
-        row_loop_v<NT, Q, QF, VEC, true, PREFETCH>(C, ldc, n, i0, i1, stage, body);
+        row_loop_v<NT, Q, QF, VEC, true, PREFETCH, RC>(C, ldc, n, i0, i1, stage, body);
     else
-        row_loop_v<NT, Q, QF, VEC, false, PREFETCH>(C, ldc, n, i0, i1, stage, body);
+        row_loop_v<NT, Q, QF, VEC, false, PREFETCH, RC>(C, ldc, n, i0, i1, stage, body);
 }
 
-// Copy rows [i, min(i + ROWCH, i1)) of up to four m-vectors into LDS (null: skipped).
+// Copy rows [i, min(i + RC, i1)) of up to four m-vectors into LDS (null: skipped).
+template <int RC = ROWCH>
 __device__ __forceinline__ void stage_rows(int i, int i1, const double *__restrict__ s0,
                                            double *d0, const double *__restrict__ s1, double *d1,
                                            const double *__restrict__ s2, double *d2,
@@ -372,7 +374,7 @@ __device__ __forceinline__ void stage_rows(int i, int i1, const double *__restri
                                            double *d3 = nullptr)
 {
     __syncthreads();   // the previous chunk may still be read
-    const int cnt = min(ROWCH, i1 - i);
+    const int cnt = min(RC, i1 - i);
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
         if (s0)
             d0[r] = s0[i + r];
@@ -384,6 +386,31 @@ __device__ __forceinline__ void stage_rows(int i, int i1, const double *__restri
             d3[r] = s3[i + r];
     }
     __syncthreads();
+}
+
+// Host side: a launch of `fn` with `dyn` bytes of dynamic LDS fits the device's LDS per
+// workgroup (its static LDS included).  hipErrorInvalidConfiguration otherwise, so that an
+// oversized request fails as an error instead of reaching the hardware.
+inline hipError_t lds_check(const void *fn, size_t dyn)
+{
+    static int max_lds[64] = {0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= 64)
+        return hipErrorInvalidDevice;
+    if (max_lds[dev] == 0) {
+        e = hipDeviceGetAttribute(&max_lds[dev], hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipFuncAttributes fa;
+    e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess)
+        return e;
+    return fa.sharedSizeBytes + dyn <= (size_t)max_lds[dev] ? hipSuccess
+                                                             : hipErrorInvalidConfiguration;
 }
 
 }  // namespace

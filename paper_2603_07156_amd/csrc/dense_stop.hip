@@ -99,14 +99,17 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
     __shared__ double etab[EXP_TAB];
     exp_table_init(etab);
     stage_lds(w, n, wl);
-    __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH], rZ[ROWCH];
+    // 32 rows per staged chunk: with an n-vector of 20000 doubles the static LDS must stay
+    // below 3.8 KB
+    constexpr int RC = 32;
+    __shared__ double rM[RC], rS[RC], rA[RC], rZ[RC];
     double X[E];
     double t_dphi = 0.0, t_cxh = 0.0, t_cx = 0.0, t_xu = 0.0, t_xhmin = INFINITY, t_xf = 0.0,
            t_cf = 0.0;
     double azg = 0.0, azp = 0.0;
     const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
-    row_loop<NT, Q, QF, VEC, false>(
-        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA, z, rZ); },
+    row_loop<NT, Q, QF, VEC, false, RC>(
+        C, ldc, n, i0, i1, [&](int i) { stage_rows<RC>(i, i1, M, rM, S, rS, a, rA, z, rZ); },
         [&](int i, int slot, const CT *cst) {
         const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];
         double red[3] = {0.0, INFINITY, INFINITY};
@@ -263,6 +266,8 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
 {
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                     \
+    if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT>, lds_bytes); e_ != hipSuccess) \
+        return e_; \
     hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, z,   \
                        colpart, colpart2, rowpart)
@@ -279,6 +284,8 @@ hipError_t launch_stop2(const RowPlan &p_in, const DenseArgs &d, const double *M
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
+    if (hipError_t e_ = lds_check((const void *)k_stop2<NT, Q, QF, VEC, CT>, lds_bytes); e_ != hipSuccess) \
+        return e_; \
     hipLaunchKernelGGL((k_stop2<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                  \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
                        v.gamma, v.psi, v.y, v.ec, v.z, v.er1, xhat, rowpart)

@@ -162,10 +162,11 @@ int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
     const size_t es = p->cost_kind == IBSN_COST_F64 ? 8 : 4;
     if (((uintptr_t)p->C % es) != 0)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "C must be aligned to its element size");
-    // the row passes stage an n-vector in LDS beside up to 2 KB of their own
-    if ((size_t)p->n * sizeof(double) + 2048 > ctx->max_lds)
+    // the row passes stage an n-vector in LDS beside at most 3.5 KB of their own (each
+    // launch also checks its exact total against the device limit)
+    if ((size_t)p->n * sizeof(double) + 3584 > ctx->max_lds)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld needs %zu bytes of LDS (device max %zu)",
-                    (long long)p->n, (size_t)p->n * 8 + 2048, ctx->max_lds);
+                    (long long)p->n, (size_t)p->n * 8 + 3584, ctx->max_lds);
     return IBSN_OK;
 }
 

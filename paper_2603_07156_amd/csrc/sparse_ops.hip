@@ -415,6 +415,56 @@ __global__ __launch_bounds__(256) void k_col_gather(int n, const int64_t *__rest
 
 constexpr int GUNR = 8;   // loads in flight per lane in the LDS-staged gathers
 
+template <typename VT> struct Pair2;
+template <> struct Pair2<double> { using T = double2; };
+template <> struct Pair2<float> { using T = float2; };
+
+// sum_{e < L} val[e] * vec[idx[e]] over the LPC lanes of a group (lane l), entries taken in
+// aligned pairs: one 8-byte index load and one 2-value load per pair, GUNR pairs in
+// flight per lane.  `odd` = the global offset of entry 0 is odd: entry 0 is then taken
+// alone (by lane 0) and the pairs start at entry 1; an unpaired last entry is taken alone
+// by lane 0 too.  Returns the lane's partial sum (fixed order for fixed inputs).
+template <int LPC, typename VT>
+__device__ __forceinline__ double pair_dot(const int32_t *__restrict__ idx,
+                                           const VT *__restrict__ val, int64_t L, bool odd,
+                                           int l, const double *__restrict__ vec)
+{
+    using V2 = typename Pair2<VT>::T;
+    double s = 0.0;
+    const int64_t h = (odd && L > 0) ? 1 : 0;
+    const int64_t npair = (L - h) >> 1;
+    if (l == 0) {
+        if (h)
+            s = fma((double)val[0], vec[idx[0]], s);
+        if (((L - h) & 1) != 0)
+            s = fma((double)val[L - 1], vec[idx[L - 1]], s);
+    }
+    const int2 *ip = reinterpret_cast<const int2 *>(idx + h);
+    const V2 *vp = reinterpret_cast<const V2 *>(val + h);
+    for (int64_t base = l; base < npair; base += GUNR * LPC) {
+        int2 jj[GUNR];
+        V2 vv[GUNR];
+#pragma unroll
+        for (int k = 0; k < GUNR; ++k) {
+            const int64_t p = base + k * LPC;
+            if (p < npair) {
+                jj[k] = ip[p];
+                vv[k] = vp[p];
+            } else {
+                jj[k] = make_int2(0, 0);
+                vv[k].x = 0;
+                vv[k].y = 0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < GUNR; ++k) {
+            s = fma((double)vv[k].x, vec[jj[k].x], s);
+            s = fma((double)vv[k].y, vec[jj[k].y], s);
+        }
+    }
+    return s;
+}
+
 // dst[j] = beta * v[j] + r[j] (r null: dst[j] = v[j]) for j < len, 1024 threads, with
 // eight independent loads in flight per thread (a plain strided loop waits on each load)
 __device__ __forceinline__ void stage_vec(double *dst, const double *__restrict__ v,
@@ -440,8 +490,9 @@ __device__ __forceinline__ void stage_vec(double *dst, const double *__restrict_
 
 // The same two gathers with the gathered vector staged in LDS by every workgroup
 // (n, respectively m, doubles), on a persistent grid of 1024-thread workgroups: the
-// sparse entries are then read as coalesced (index, value) streams and the vector from
-// LDS.  Summation order per row / column is the same as in the kernels above.
+// sparse entries are then read as coalesced streams of (index, value) pairs (pair_dot)
+// and the vector from LDS.  Each sum has its own fixed order, so results are
+// run-to-run reproducible (the order differs from the kernels above).
 template <int LPC, typename VT>
 __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
                                                          const int32_t *__restrict__ col,
@@ -487,23 +538,8 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
         if (g == istar)
             continue;
         const int L = len[g];
-        const int32_t *cr = col + (int64_t)g * n;
-        const VT *vr = val + (int64_t)g * n;
-        double s = 0.0;
-        // each lane issues GUNR (index, value) loads before using any of them
-        for (int base = l; base < L; base += GUNR * LPC) {
-            int jj[GUNR];
-            VT vv[GUNR];
-#pragma unroll
-            for (int k = 0; k < GUNR; ++k) {
-                const int e = base + k * LPC;
-                jj[k] = e < L ? cr[e] : 0;
-                vv[k] = e < L ? vr[e] : (VT)0;
-            }
-#pragma unroll
-            for (int k = 0; k < GUNR; ++k)
-                s = fma((double)vv[k], vs[jj[k]], s);
-        }
+        const int64_t off = (int64_t)g * n;
+        double s = pair_dot<LPC, VT>(col + off, val + off, L, (off & 1) != 0, l, vs);
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
             s += __shfl_xor(s, o, LPC);
@@ -557,20 +593,7 @@ __global__ __launch_bounds__(1024) void k_col_gather_lds(int m, int n,
     double pap = 0.0;
     for (int j = blockIdx.x + gridDim.x * (threadIdx.x / LPC); j < n; j += gridDim.x * CPB) {
         const int64_t e0 = colptr[j], e1 = colptr[j + 1];
-        double s = 0.0;
-        for (int64_t base = e0 + l; base < e1; base += GUNR * LPC) {
-            int ii[GUNR];
-            VT cc[GUNR];
-#pragma unroll
-            for (int k = 0; k < GUNR; ++k) {
-                const int64_t e = base + k * LPC;
-                ii[k] = e < e1 ? rowidx[e] : 0;
-                cc[k] = e < e1 ? cval[e] : (VT)0;
-            }
-#pragma unroll
-            for (int k = 0; k < GUNR; ++k)
-                s = fma((double)cc[k], us[ii[k]], s);
-        }
+        double s = pair_dot<LPC, VT>(rowidx + e0, cval + e0, e1 - e0, (e0 & 1) != 0, l, us);
 #pragma unroll
         for (int o = LPC / 2; o > 0; o >>= 1)
             s += __shfl_xor(s, o, LPC);

@@ -276,3 +276,21 @@ def test_mixed_switch_zero_runs_mixed_to_the_end(ib, ctx):
     rep = res["report"]
     assert rep["mixed_passes"] > 0
     assert rep["primal"] >= rep["dual"] - 1e-14
+
+
+def test_cfg3_full_size_fp32_cost(ib, ctx):
+    """20000 x 20000, 3-D unit-cube points vs an 8-component mixture, cost stored FP32
+    (1.6 GB): the mixed eval against the oracle on the same (widened) cost, and the FP64
+    stop pass, whose staged n-vector plus static LDS is the largest request of the dense
+    passes (it must fit the 160 KB per workgroup)."""
+    inst = W.cube_vs_gmm(20000, 200, cost_dtype=np.float32)
+    r, s, k, gamma = np.log(inst.a), np.log(inst.b), 0, W.random_dual(20000, 4, 0.01)
+    gv, ov = check_eval_mixed(ib, ctx, inst, r, s, k, gamma, want_plan=False)
+    pr = ib.Problem(dev(inst.C), dev(inst.a), dev(inst.b), inst.eta)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    gs = ib.stop(ctx, pr, ctr, dev(gamma), dev(ov.M), dev(ov.S))
+    os_ = orc.stop_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ov.M, ov.S, s=s, k=k, q=q)
+    # 4e8 terms: both sides sum per row (GPU: per thread) before the totals; each is within
+    # a few 1e-15 of an exactly rounded sum
+    for key in ("primal", "cx"):
+        assert abs(gs[key] - os_[key]) <= 1e-12 * abs(os_[key]), (key, gs[key], os_[key])

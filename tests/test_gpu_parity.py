@@ -305,6 +305,24 @@ def test_stop(ib, ctx, k):
     np.testing.assert_allclose(Xh.sum(0), inst.b, atol=1e-15 * 333, rtol=0)
 
 
+@pytest.mark.parametrize("m,n", [(250, 333), (64, 2049), (40, 4099)])
+def test_stop_fp32_cost(ib, ctx, m, n):
+    """FP32-stored cost (16-byte vectors of four floats, ragged tails) in both stop passes."""
+    inst = W.gmm_points(n, 6, m=m)
+    C32 = inst.C.astype(np.float32)
+    r, s, k, gamma = outer_state(inst, 0)
+    ctr, q = center(ib, inst, r, s, k, gamma, C32)
+    ev = orc.eval_pass(C32, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    pr = problem(ib, inst, C32)
+    gs = ib.stop(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), want_xhat=True)
+    os_ = orc.stop_pass(C32, inst.a, inst.b, inst.eta, gamma, ev.M, ev.S, s=s, k=k,
+                        want_xhat=True, q=q)
+    np.testing.assert_allclose(host(gs["xhat"]), os_["xhat"], rtol=1e-10, atol=1e-15)
+    for key, rtol, atol in [("primal", 1e-12, 0), ("dual", 1e-12, 1e-16), ("cx", 1e-12, 0),
+                            ("dphi", 1e-9, 1e-15), ("kkt", 1e-9, 1e-16)]:
+        assert abs(gs[key] - os_[key]) <= rtol * abs(os_[key]) + atol, (key, gs[key], os_[key])
+
+
 # ---------------------------------------------------------------------------
 # full solve (Algorithm 2) against exact optima and the oracle
 # ---------------------------------------------------------------------------
