@@ -100,12 +100,19 @@ def time_to_gap(ibsn, ctx, prob, outer: int):
     def run(precision, **kw):
         pr = ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=precision)
         opt = ibsn.default_options(marg_tol=0.0, **kw)
+        ctx.kernel_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = ibsn.solve(ctx, pr, opt)
         torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = ctx.kernel_times()
+        ctx.kernel_timing(False)
         rep = res["report"]
-        return {"seconds": time.perf_counter() - t0, "rel_gap": rep["rel_gap"],
+        return {"seconds": dt, "rel_gap": rep["rel_gap"],
+                "kernel_ms": {k: {"total": v[0], "launches": v[1],
+                                  "avg": (v[0] / v[1]) if v[1] else None}
+                              for k, v in kt.items() if v[1]},
                 "outer": rep["outer"], "newton": rep["newton"], "cg": rep["cg"],
                 "dense_passes": rep["passes"], "mixed_passes": rep["mixed_passes"],
                 "status": res["status"]}
@@ -208,7 +215,17 @@ def main() -> int:
                           "avg": (v[0] / v[1]) if v[1] else None} for k, v in kt.items()},
     }
     if args.gap_outer > 0:
-        out["time_to_gap"] = time_to_gap(ibsn, ctx, prob, args.gap_outer)
+        ttg = time_to_gap(ibsn, ctx, prob, args.gap_outer)
+        out["time_to_gap"] = ttg
+        # the LSE pass of the mixed form (FP32 exponentials, FP64 sums): same bytes
+        mk = ttg["mixed"]["kernel_ms"].get("eval_mixed")
+        if mk:
+            ach = pb / (mk["avg"] * 1e-3) / 1e9
+            out["roofline_mixed_eval"] = {
+                "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "row-LSE eval pass, mixed-precision form (k_eval<..., MX>)",
+                "bytes_per_launch": pb, "avg_launch_ms": mk["avg"], "launches": mk["launches"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out))

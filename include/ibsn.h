@@ -202,6 +202,9 @@ enum { IBSN_KT_EVAL = 0,      /* row LSE pass (eval)                            
        IBSN_KT_STOP2,         /* stop test pass 2                                      */
        IBSN_KT_CG,            /* one CG solve, host polling included (all iterations)  */
        IBSN_KT_COLRED,        /* column partial reduction                              */
+       IBSN_KT_EVAL_MIXED,    /* eval pass in the mixed-precision form                 */
+       IBSN_KT_TRIAL_MIXED,   /* Armijo trial pass in the mixed-precision form         */
+       IBSN_KT_SPARSIFY_MIXED,/* Algorithm 1 pass in the mixed-precision form          */
        IBSN_KT_N };
 typedef struct {
     double ms[IBSN_KT_N];

@@ -27,6 +27,7 @@
 
 #include <math.h>
 
+#include <atomic>
 #include <type_traits>
 
 namespace ibsn {
@@ -390,27 +391,37 @@ __device__ __forceinline__ void stage_rows(int i, int i1, const double *__restri
 
 // Host side: a launch of `fn` with `dyn` bytes of dynamic LDS fits the device's LDS per
 // workgroup (its static LDS included).  hipErrorInvalidConfiguration otherwise, so that an
-// oversized request fails as an error instead of reaching the hardware.
-inline hipError_t lds_check(const void *fn, size_t dyn)
+// oversized request fails as an error instead of reaching the hardware.  `cache` (one per
+// launch site) keeps the kernel's static LDS size after the first query.
+struct LdsCache {
+    std::atomic<long> static_bytes{-1};
+};
+inline hipError_t lds_check(const void *fn, size_t dyn, LdsCache &cache)
 {
-    static int max_lds[64] = {0};
+    static std::atomic<int> max_lds[64];
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return e;
     if (dev < 0 || dev >= 64)
         return hipErrorInvalidDevice;
-    if (max_lds[dev] == 0) {
-        e = hipDeviceGetAttribute(&max_lds[dev], hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    int lim = max_lds[dev].load(std::memory_order_relaxed);
+    if (lim <= 0) {
+        e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e != hipSuccess)
             return e;
+        max_lds[dev].store(lim, std::memory_order_relaxed);
     }
-    hipFuncAttributes fa;
-    e = hipFuncGetAttributes(&fa, fn);
-    if (e != hipSuccess)
-        return e;
-    return fa.sharedSizeBytes + dyn <= (size_t)max_lds[dev] ? hipSuccess
-                                                             : hipErrorInvalidConfiguration;
+    long st = cache.static_bytes.load(std::memory_order_relaxed);
+    if (st < 0) {
+        hipFuncAttributes fa;
+        e = hipFuncGetAttributes(&fa, fn);
+        if (e != hipSuccess)
+            return e;
+        st = (long)fa.sharedSizeBytes;
+        cache.static_bytes.store(st, std::memory_order_relaxed);
+    }
+    return (size_t)st + dyn <= (size_t)lim ? hipSuccess : hipErrorInvalidConfiguration;
 }
 
 }  // namespace

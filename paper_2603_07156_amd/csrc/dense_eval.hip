@@ -111,7 +111,8 @@ hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, do
                        double *lse, double *plan, double *colpart, double *rowpart, hipStream_t st)
 {
 #define BODY                                                                                     \
-    if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX>, (size_t)d.n * sizeof(double)); e_ != hipSuccess) \
+    static LdsCache lc_; \
+    if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX>, (size_t)d.n * sizeof(double), lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT),                     \
                        (size_t)d.n * sizeof(double), st,                                         \

@@ -149,7 +149,8 @@ hipError_t launch_sparsify(const RowPlan &p_in, const DenseArgs &d, const double
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                     \
-    if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX>, lds_bytes); e_ != hipSuccess) \
+    static LdsCache lc_; \
+    if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT), lds_bytes, st, \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, rho, \

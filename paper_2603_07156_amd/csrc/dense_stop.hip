@@ -266,7 +266,8 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
 {
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                     \
-    if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT>, lds_bytes); e_ != hipSuccess) \
+    static LdsCache lc_; \
+    if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, z,   \
@@ -284,7 +285,8 @@ hipError_t launch_stop2(const RowPlan &p_in, const DenseArgs &d, const double *M
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
-    if (hipError_t e_ = lds_check((const void *)k_stop2<NT, Q, QF, VEC, CT>, lds_bytes); e_ != hipSuccess) \
+    static LdsCache lc_; \
+    if (hipError_t e_ = lds_check((const void *)k_stop2<NT, Q, QF, VEC, CT>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_stop2<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                  \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \

@@ -102,7 +102,8 @@ hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
-    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MX, 0>, lds_bytes); e_ != hipSuccess) \
+    static LdsCache lc_; \
+    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MX, 0>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \

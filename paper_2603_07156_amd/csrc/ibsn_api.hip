@@ -315,7 +315,7 @@ int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q, mixed);
     {
-        KTimer kt(ctx, IBSN_KT_EVAL);
+        KTimer kt(ctx, mixed ? IBSN_KT_EVAL_MIXED : IBSN_KT_EVAL);
         CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart),
                         P<double>(ctx->rowpart), st));
     }
@@ -344,7 +344,7 @@ int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k
     CKH(sk_trial_prep(p->n, t, p->eta, q, Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
                       scal, st));
     {
-        KTimer kt(ctx, IBSN_KT_TRIAL);
+        KTimer kt(ctx, mixed ? IBSN_KT_TRIAL_MIXED : IBSN_KT_TRIAL);
         CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
                          P<double>(ctx->rowpart), st));
     }
@@ -431,7 +431,7 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     DenseArgs d = dense_args(ctx, p, k, q, mixed);
     c->f32 = mixed;
     {
-        KTimer kt(ctx, IBSN_KT_SPARSIFY);
+        KTimer kt(ctx, mixed ? IBSN_KT_SPARSIFY_MIXED : IBSN_KT_SPARSIFY);
         CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
                             c->val.p, P<int32_t>(c->len), P<double>(ctx->colpart), st));
     }

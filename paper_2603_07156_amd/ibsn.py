@@ -75,7 +75,8 @@ class Report(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-KT_NAMES = ("eval", "trial", "sparsify", "csc", "stop1", "stop2", "cg", "colreduce")
+KT_NAMES = ("eval", "trial", "sparsify", "csc", "stop1", "stop2", "cg", "colreduce",
+            "eval_mixed", "trial_mixed", "sparsify_mixed")
 
 
 class _KernelTimes(ct.Structure):
