@@ -740,6 +740,12 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             orc_eval(m, n, C, kind, ldc, k, eta, q, w, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
             ++R.sinkhorn;
         }
+        /* a column whose kernel entries all lie below the FP64 range gives c_j = 0 and a
+           non-finite gradient: no step can follow, report it (as the GPU solver does) */
+        if (!isfinite(nrm2(n, g))) {
+            R.status = ORC_ERR_NUMERIC;
+            break;
+        }
         int stopped = 0, stalls = 0;
         int64_t newton_k = 0, cg_k = 0;
         for (int v = 0; v < opt.max_newton; ++v) {

@@ -461,3 +461,15 @@ def test_csr_handle_lifetime(ib, ctx):
     c2.close()
     gcsr.free()
     assert gcsr.h is None
+
+
+def test_solve_tiny_eta_numeric_error(ib, ctx):
+    """eta = 1e-6: columns of the first kernel underflow, c_j = 0; the solve returns
+    IBSN_ERR_NUMERIC as the oracle does, instead of iterating on NaN."""
+    inst = W.uniform_points(64, 0)
+    pr = ib.Problem(dev(inst.C), dev(inst.a), dev(inst.b), 1e-6)
+    with pytest.raises(ib.IBSNError) as ei:
+        ib.solve(ctx, pr, ib.default_options(max_outer=50))
+    assert ei.value.code == -4
+    o = orc.solve(inst.C, inst.a, inst.b, 1e-6, options=orc.default_options(max_outer=50))
+    assert o["status"] == -4

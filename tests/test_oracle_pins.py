@@ -440,3 +440,13 @@ def test_p16_eibsn_single_subproblem_is_entropic_ot():
     # rows are exact by construction; columns to the gradient tolerance
     np.testing.assert_allclose(ev.plan.sum(1), inst.a, rtol=0, atol=1e-15)
     np.testing.assert_allclose(ev.plan.sum(0), inst.b, rtol=0, atol=1e-13)
+
+
+def test_tiny_eta_reports_numeric_error():
+    """At eta = 1e-6 (sigma = 1e6 on a cost normalised to max 1) whole columns of the first
+    subproblem's kernel fall below the FP64 range, so c_j = 0 and the Sinkhorn step cannot
+    be taken: the solve reports a numeric error instead of iterating on NaN."""
+    inst = W.uniform_points(64, 0)
+    res = orc.solve(inst.C, inst.a, inst.b, 1e-6, options=orc.default_options(max_outer=50))
+    assert res["status"] == -4
+    assert res["report"]["outer"] == 0
