@@ -48,7 +48,7 @@ struct ibsn_ctx {
     std::string err;
     // workspace
     DevBuf w, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
-    DevBuf stopout, tauv, cg_x, cg_r, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
+    DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     ibsn_csr *solver_csr = nullptr;
     std::vector<ibsn_csr *> csrs;  // handles returned by ibsn_sparsify and not yet freed
@@ -482,6 +482,7 @@ int ensure_cg(ibsn_ctx *ctx, int64_t m, int64_t n)
 {
     CKI(ensure(ctx, ctx->cg_x, n * 8));
     CKI(ensure(ctx, ctx->cg_r, n * 8));
+    CKI(ensure(ctx, ctx->cg_r2, n * 8));
     CKI(ensure(ctx, ctx->cg_p, n * 8));
     CKI(ensure(ctx, ctx->cg_Ap, n * 8));
     CKI(ensure(ctx, ctx->cg_au, m * 8));
@@ -513,6 +514,7 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     CgState s;
     s.x = P<double>(ctx->cg_x);
     s.r = P<double>(ctx->cg_r);
+    s.r2 = P<double>(ctx->cg_r2);
     s.p = P<double>(ctx->cg_p);
     s.Ap = P<double>(ctx->cg_Ap);
     s.au = P<double>(ctx->cg_au);
@@ -531,7 +533,7 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     for (;;) {
         for (int q = 0; q < chunk && launched < maxit; ++q, ++launched)
             CKH(launch_cg_iteration(g, cv, a, eta, shift, s, launched, st));
-        CKH(launch_cg_check(g, s, launched, st));
+        CKH(launch_cg_check(g, s, launched, c->n, st));
         CKH(hipMemcpyAsync(hs, s.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
         CKH(hipStreamSynchronize(st));
         const int slot = launched & 1;
@@ -614,7 +616,7 @@ void ibsn_destroy(ibsn_ctx *ctx)
     DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
                       &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv,
-                      &ctx->cg_x, &ctx->cg_r,
+                      &ctx->cg_x, &ctx->cg_r, &ctx->cg_r2,
                       &ctx->cg_p,
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_star, &ctx->cg_pap, &ctx->cg_rr,
                       &ctx->cg_scal, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,

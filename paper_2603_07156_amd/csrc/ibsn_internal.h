@@ -132,7 +132,10 @@ struct GatherPlan {
     int nstar, star_chunk;    // dense-row chunks (extra workgroups) and their width
     int col_blocks;           // column-gather workgroups (grid-stride)
     int upd_blocks;           // CG update workgroups
+    bool fused;               // two-kernel CG iterations (LDS path, n <= CG_FUSED_MAX_N)
 };
+// largest n for which the CG vector update is folded into the next row gather
+constexpr int64_t CG_FUSED_MAX_N = 4096;
 GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus,
                        size_t max_lds);
 
@@ -144,6 +147,7 @@ hipError_t launch_hvp(const GatherPlan &g, const CsrView &c, const double *a, do
 // CG on the device.  Scalars (CG_* slots) are double-buffered by iteration parity.
 struct CgState {
     double *x, *r, *p, *Ap, *au;   // n, n, n, n, m
+    double *r2;                    // n: second residual buffer (two-kernel CG, by parity)
     double *star_part;             // CG_MAX_STAR
     double *pap_part;              // CG_MAX_COLGROUPS
     double *rr_part;               // CG_MAX_UPDGROUPS
@@ -159,7 +163,7 @@ hipError_t launch_cg_init(int64_t n, const double *rhs, double tol, int maxit, C
 hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const double *a, double eta,
                                double shift, CgState &s, int it, hipStream_t st);
 // writes the state after `it` iterations to slot it&1 (rr, done, iteration count)
-hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, hipStream_t st);
+hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, int64_t n, hipStream_t st);
 
 // export slotted CSR to standard CSR
 hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,

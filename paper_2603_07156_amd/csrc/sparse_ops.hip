@@ -488,6 +488,47 @@ __device__ __forceinline__ void stage_vec(double *dst, const double *__restrict_
     }
 }
 
+// Star-row chunks and rows of the LDS-staged row gather, with the gathered vector already in
+// vs (n doubles, visible to the whole workgroup).
+template <int LPC, typename VT>
+__device__ __forceinline__ void row_gather_tail(int m, int n, const int32_t *__restrict__ col,
+                                                const VT *__restrict__ val,
+                                                const int32_t *__restrict__ len, int istar,
+                                                const double *__restrict__ a, const double *vs,
+                                                double *__restrict__ au,
+                                                double *__restrict__ star_part, int nstar,
+                                                int star_chunk, double *lds)
+{
+    for (int c = blockIdx.x; c < nstar; c += gridDim.x) {
+        double t = 0.0;
+        if (istar >= 0) {
+            const int j0 = c * star_chunk, j1 = min(n, j0 + star_chunk);
+            const VT *vr = val + (int64_t)istar * n;
+            for (int j = j0 + threadIdx.x; j < j1; j += 1024)
+                t = fma((double)vr[j], vs[j], t);
+        }
+        t = block_sum<1024>(t, lds);
+        if (threadIdx.x == 0)
+            star_part[c] = t;
+    }
+    // rows interleaved over the workgroups (row g in workgroup g mod grid), so that every
+    // workgroup gets an equal share even when m < grid * groups per workgroup
+    constexpr int GPB = 1024 / LPC;
+    const int l = threadIdx.x % LPC;
+    for (int g = blockIdx.x + gridDim.x * (threadIdx.x / LPC); g < m; g += gridDim.x * GPB) {
+        if (g == istar)
+            continue;
+        const int L = len[g];
+        const int64_t off = (int64_t)g * n;
+        double s = pair_dot<LPC, VT>(col + off, val + off, L, (off & 1) != 0, l, vs);
+#pragma unroll
+        for (int o = LPC / 2; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, LPC);
+        if (l == 0)
+            au[g] = a[g] * s;
+    }
+}
+
 // The same two gathers with the gathered vector staged in LDS by every workgroup
 // (n, respectively m, doubles), on a persistent grid of 1024-thread workgroups: the
 // sparse entries are then read as coalesced streams of (index, value) pairs (pair_dot)
@@ -517,35 +558,138 @@ __global__ __launch_bounds__(1024) void k_row_gather_lds(int m, int n,
         return;
     stage_vec(vs, v, cgm ? r_vec : nullptr, beta, n);
     __syncthreads();
-    const int istar = *istar_p;
-    for (int c = blockIdx.x; c < nstar; c += gridDim.x) {
-        double t = 0.0;
-        if (istar >= 0) {
-            const int j0 = c * star_chunk, j1 = min(n, j0 + star_chunk);
-            const VT *vr = val + (int64_t)istar * n;
-            for (int j = j0 + threadIdx.x; j < j1; j += 1024)
-                t = fma((double)vr[j], vs[j], t);
+    row_gather_tail<LPC, VT>(m, n, col, val, len, *istar_p, a, vs, au, star_part, nstar,
+                             star_chunk, lds);
+}
+
+// Two-kernel CG iteration for small n, where each kernel's work is a few microseconds
+// and a third launch per iteration is a large share of the time.  Iteration `it` >= 1 of
+// the row gather first finishes iteration it-1 (the vector update of the three-kernel form):
+//   alpha = rr_{it-1} / p.Ap (p.Ap from the column gather's partials, added in order),
+//   r_it = r_{it-1} - alpha Ap over all n in every workgroup, so that each forms the same
+//   ||r_it||^2 (same order, same operations); x += alpha p and r_it are written only for
+//   the workgroup's own slice of columns.  r is double-buffered by iteration parity (r_it in
+//   rbuf[it & 1]), so no workgroup reads an entry another one writes.  p.Ap <= 0 (or not a
+//   number): no step, and CG ends with the previous iterate, as in the three-kernel form.
+// Then beta, the done test, and workgroup 0 writes slot it & 1 of the scalars.
+// vs (LDS, n doubles) receives r_it.  When write_if_done_only (the single-workgroup state
+// kernel), nothing is written unless CG has finished; it then writes x and r for all n.
+template <int NT>
+__device__ __forceinline__ bool cg_fused_update(int it, int n, double *__restrict__ scal,
+                                                const double *__restrict__ pap_part, int npap,
+                                                double *__restrict__ x,
+                                                const double *__restrict__ rprev,
+                                                double *__restrict__ rcur,
+                                                const double *__restrict__ p,
+                                                const double *__restrict__ Ap, double *vs,
+                                                int lo, int hi, bool write_if_done_only,
+                                                double *lds, double *beta_out)
+{
+    const int ps = (it - 1) & 1, cs = it & 1;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (scal[CG_DONE0 + ps] != 0.0) {
+        if (lead) {
+            scal[CG_RR0 + cs] = scal[CG_RR0 + ps];
+            scal[CG_BETA0 + cs] = 0.0;
+            scal[CG_IT0 + cs] = scal[CG_IT0 + ps];
+            scal[CG_DONE0 + cs] = 1.0;
         }
-        t = block_sum<1024>(t, lds);
-        if (threadIdx.x == 0)
-            star_part[c] = t;
+        return true;
     }
-    // rows interleaved over the workgroups (row g in workgroup g mod grid), so that every
-    // workgroup gets an equal share even when m < grid * groups per workgroup
-    constexpr int GPB = 1024 / LPC;
-    const int l = threadIdx.x % LPC;
-    for (int g = blockIdx.x + gridDim.x * (threadIdx.x / LPC); g < m; g += gridDim.x * GPB) {
-        if (g == istar)
-            continue;
-        const int L = len[g];
-        const int64_t off = (int64_t)g * n;
-        double s = pair_dot<LPC, VT>(col + off, val + off, L, (off & 1) != 0, l, vs);
-#pragma unroll
-        for (int o = LPC / 2; o > 0; o >>= 1)
-            s += __shfl_xor(s, o, LPC);
-        if (l == 0)
-            au[g] = a[g] * s;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < npap; k += NT)
+        t += pap_part[k];
+    const double pap = block_sum<NT>(t, lds);
+    const bool ok = pap > 0.0;
+    const double rr_old = scal[CG_RR0 + ps];
+    const double alpha = ok ? rr_old / pap : 0.0;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const double rn = ok ? fma(-alpha, Ap[j], rprev[j]) : rprev[j];
+        if (vs)
+            vs[j] = rn;
+        acc = fma(rn, rn, acc);
     }
+    const double rr = block_sum<NT>(acc, lds);   // its barriers also publish vs
+    const bool done = !ok || !(sqrt(rr) > scal[CG_TOL]) || (double)it >= scal[CG_MAXIT];
+    if (!write_if_done_only || done) {
+        for (int j = lo + (int)threadIdx.x; j < hi; j += NT) {
+            if (ok)
+                x[j] = fma(alpha, p[j], x[j]);
+            rcur[j] = vs ? vs[j] : (ok ? fma(-alpha, Ap[j], rprev[j]) : rprev[j]);
+        }
+    }
+    const double beta = rr / rr_old;
+    if (lead) {
+        scal[CG_RR0 + cs] = rr;
+        scal[CG_BETA0 + cs] = beta;
+        scal[CG_IT0 + cs] = (double)(ok ? it : it - 1);
+        scal[CG_DONE0 + cs] = done ? 1.0 : 0.0;
+    }
+    *beta_out = beta;
+    return done;
+}
+
+template <int LPC, typename VT>
+__global__ __launch_bounds__(1024) void k_row_gather_cg(int m, int n,
+                                                        const int32_t *__restrict__ col,
+                                                        const VT *__restrict__ val,
+                                                        const int32_t *__restrict__ len,
+                                                        const int *__restrict__ istar_p,
+                                                        const double *__restrict__ a,
+                                                        double *__restrict__ au,
+                                                        double *__restrict__ star_part,
+                                                        int nstar, int star_chunk, int it,
+                                                        double *__restrict__ scal,
+                                                        const double *__restrict__ pap_part,
+                                                        int npap, double *__restrict__ x,
+                                                        double *__restrict__ r0,
+                                                        double *__restrict__ r1,
+                                                        const double *__restrict__ p,
+                                                        const double *__restrict__ Ap)
+{
+    extern __shared__ double vs[];   // r_it, then p_it = r_it + beta p_{it-1}
+    __shared__ double lds[16];
+    double beta = 0.0;
+    if (it == 0) {
+        if (scal[CG_DONE0] != 0.0)
+            return;
+        for (int j = threadIdx.x; j < n; j += 1024)
+            vs[j] = r0[j];   // p_0 = r_0
+    } else {
+        const int chunk = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int lo = min(n, (int)blockIdx.x * chunk), hi = min(n, lo + chunk);
+        double *rprev = (it & 1) ? r0 : r1, *rcur = (it & 1) ? r1 : r0;
+        if (cg_fused_update<1024>(it, n, scal, pap_part, npap, x, rprev, rcur, p, Ap, vs, lo,
+                                  hi, false, lds, &beta))
+            return;
+        __syncthreads();   // the slice writes above read r_it from vs: finish them first
+        for (int j = threadIdx.x; j < n; j += 1024)
+            vs[j] = fma(beta, p[j], vs[j]);
+    }
+    __syncthreads();
+    row_gather_tail<LPC, VT>(m, n, col, val, len, *istar_p, a, vs, au, star_part, nstar,
+                             star_chunk, lds);
+}
+
+// State after `it` iterations of the two-kernel CG into slot it & 1 (one workgroup; the host
+// reads it).  Writes x and r only if CG has then finished (otherwise the next row gather
+// performs the same update).
+__global__ __launch_bounds__(1024) void k_cg_state(int it, int n, double *__restrict__ scal,
+                                                   const double *__restrict__ pap_part, int npap,
+                                                   double *__restrict__ x,
+                                                   double *__restrict__ r0,
+                                                   double *__restrict__ r1,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ Ap)
+{
+    __shared__ double lds[16];
+    if (it == 0)
+        return;   // k_cg_init wrote slot 0
+    double beta;
+    double *rprev = (it & 1) ? r0 : r1, *rcur = (it & 1) ? r1 : r0;
+    (void)cg_fused_update<1024>(it, n, scal, pap_part, npap, x, rprev, rcur, p, Ap, nullptr, 0,
+                                n, true, lds, &beta);
 }
 
 template <int LPC, typename VT>
@@ -773,6 +917,9 @@ GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num
         g.col_blocks = (int)std::min<int64_t>(num_cus, CG_MAX_COLGROUPS);
     }
     g.upd_blocks = (int)std::min<int64_t>((n + 255) / 256, CG_MAX_UPDGROUPS);
+    // two kernels per CG iteration while the vector update repeated in every workgroup
+    // (4 n-vectors read from L2) costs less than a third launch
+    g.fused = g.lds && n <= CG_FUSED_MAX_N;
     if (g.upd_blocks < 1)
         g.upd_blocks = 1;
     return g;
@@ -856,6 +1003,31 @@ void row_gather(const GatherPlan &g, const CsrView &c, const double *a, const do
 }
 
 template <int L, typename VT>
+void row_gather_cg_lt(const GatherPlan &g, const CsrView &c, const double *a, CgState &s, int it,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL((k_row_gather_cg<L, VT>), dim3(g.row_blocks), dim3(1024),
+                       (size_t)c.n * sizeof(double), st, (int)c.m, (int)c.n, c.col,
+                       (const VT *)c.val, c.len, c.istar, a, s.au, s.star_part, g.nstar,
+                       g.star_chunk, it, s.scal, s.pap_part, g.col_blocks, s.x, s.r, s.r2, s.p,
+                       s.Ap);
+}
+
+template <typename VT>
+void row_gather_cg_t(const GatherPlan &g, const CsrView &c, const double *a, CgState &s, int it,
+                     hipStream_t st)
+{
+    if (g.lpc_row >= 64)
+        row_gather_cg_lt<64, VT>(g, c, a, s, it, st);
+    else if (g.lpc_row >= 32)
+        row_gather_cg_lt<32, VT>(g, c, a, s, it, st);
+    else if (g.lpc_row >= 16)
+        row_gather_cg_lt<16, VT>(g, c, a, s, it, st);
+    else
+        row_gather_cg_lt<4, VT>(g, c, a, s, it, st);
+}
+
+template <int L, typename VT>
 void col_gather_lt(const GatherPlan &g, const CsrView &c, const double *a, const double *au,
                    const double *star_part, double *v, double eta, double shift, double *y, int it,
                    const double *scal, const double *r_vec, double *pap_part, hipStream_t st)
@@ -921,6 +1093,16 @@ hipError_t launch_cg_init(int64_t n, const double *rhs, double tol, int maxit, C
 hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const double *a, double eta,
                                double shift, CgState &s, int it, hipStream_t st)
 {
+    if (g.fused) {
+        // two kernels: the row gather also finishes iteration it-1's vector update
+        if (c.f32)
+            row_gather_cg_t<float>(g, c, a, s, it, st);
+        else
+            row_gather_cg_t<double>(g, c, a, s, it, st);
+        col_gather(g, c, a, s.au, s.star_part, s.p, eta, shift, s.Ap, it, s.scal,
+                   (it & 1) ? s.r2 : s.r, s.pap_part, st);
+        return hipGetLastError();
+    }
     // 1) p_new = r + beta p (beta, rr, done from the update partials); au = a.(P p_new)
     row_gather(g, c, a, s.p, s.au, s.star_part, it, s.scal, s.rr_part, g.upd_blocks, s.r, st);
     // 2) p = p_new; Ap; partials of p.Ap
@@ -932,8 +1114,13 @@ hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, hipStream_t st)
+hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, int64_t n, hipStream_t st)
 {
+    if (g.fused) {
+        hipLaunchKernelGGL(k_cg_state, dim3(1), dim3(1024), 0, st, it, (int)n, s.scal,
+                           s.pap_part, g.col_blocks, s.x, s.r, s.r2, s.p, s.Ap);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(256), 0, st, it, s.scal, s.rr_part, g.upd_blocks);
     return hipGetLastError();
 }
