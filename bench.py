@@ -125,6 +125,35 @@ def time_to_gap(ibsn, ctx, prob, outer: int):
             "mixed_over_plain_time": mixed["seconds"] / plain["seconds"]}
 
 
+def time_to_1e8(ibsn, ctx, n: int, eta: float):
+    """Wall time to a certified relative gap of 1e-8 from X^0, plain FP64 and the mixed
+    form, on uniform points at size n (seed 0) with the given eta: a size and eta at which
+    the target is reachable in seconds (at n = 10^4 and eta = 1e-2 it needs ~10^7 outer
+    iterations)."""
+    import torch
+
+    from paper_2603_07156_amd import workloads
+    inst = workloads.uniform_points(n, 0, eta=eta)
+    dev = torch.device("cuda", 0)
+    C = torch.from_numpy(inst.C).to(dev)
+    a = torch.from_numpy(inst.a).to(dev)
+    b = torch.from_numpy(inst.b).to(dev)
+    out = {"workload": f"uniform points in [0,1]^2, m=n={n}, eta={eta:g}, seed 0, from X^0",
+           "target_rel_gap": 1e-8}
+    for name, prec in (("plain_f64", ibsn.PREC_F64), ("mixed", ibsn.PREC_MIXED)):
+        pr = ibsn.Problem(C, a, b, eta, precision=prec)
+        opt = ibsn.default_options(max_outer=5000, gap_tol=1e-8, marg_tol=0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ibsn.solve(ctx, pr, opt)
+        torch.cuda.synchronize()
+        rep = res["report"]
+        out[name] = {"seconds": time.perf_counter() - t0, "status": res["status"],
+                     "rel_gap": rep["rel_gap"], "outer": rep["outer"], "newton": rep["newton"],
+                     "cg": rep["cg"], "t_cg": rep["t_cg"]}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +165,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--gap-outer", type=int, default=100,
                     help="outer iterations of the plain run that sets the common gap target")
+    ap.add_argument("--ttg-n", type=int, default=1024,
+                    help="size of the time-to-1e-8-gap runs (0 = skip); eta set by --ttg-eta")
+    ap.add_argument("--ttg-eta", type=float, default=1e-5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
@@ -226,6 +258,8 @@ def main() -> int:
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "kernel": "row-LSE eval pass, mixed-precision form (k_eval<..., MX>)",
                 "bytes_per_launch": pb, "avg_launch_ms": mk["avg"], "launches": mk["launches"]}
+    if args.ttg_n > 0:
+        out["time_to_1e-8_gap"] = time_to_1e8(ibsn, ctx, args.ttg_n, args.ttg_eta)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out))

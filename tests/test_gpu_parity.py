@@ -281,6 +281,53 @@ def test_cg(ib, ctx):
     gcsr.free()
 
 
+def test_cg_three_kernel_path(ib, ctx):
+    """n > 4096 runs CG as three kernels per iteration (row gather, column gather, update);
+    smaller n folds the update into the row gather.  Both against the oracle's CG."""
+    m, n = 300, 5000
+    inst = W.gmm_points(n, 23, m=m)
+    r, s, k, gamma = outer_state(inst, 0)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    gn = np.linalg.norm(ev.g)
+    rho = inst.eta * gn / (m * n)
+    pr = problem(ib, inst)
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
+    shift = max(gn, 1e-2)
+    tol = 1e-12 * gn
+    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
+    xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
+    assert itg < 500 and ito < 500
+    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    # a cap of a few iterations stops both at the same iterate
+    x3, it3 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 3)
+    xo3, ito3 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 3)
+    assert it3 == ito3 == 3
+    np.testing.assert_allclose(host(x3), xo3, rtol=0, atol=1e-9 * np.abs(xo3).max())
+    gcsr.free()
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 5, 9])
+def test_cg_two_kernel_iterates(ib, ctx, maxit):
+    """The folded update (n <= 4096) gives the same iterate as the oracle's CG after each
+    number of iterations, across the host's chunk boundaries."""
+    inst = W.gmm_points(600, 8, m=420)
+    r, s, k, gamma = outer_state(inst, 0)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    pr = problem(ib, inst)
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), 1e-6)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, 1e-6, s=s, k=k, q=q)
+    shift = 1e-2
+    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, maxit)
+    xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, maxit)
+    assert itg == ito == maxit
+    # rounding of different summation orders, amplified by CG up to ~cond = 5000 here
+    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    gcsr.free()
+
+
 # ---------------------------------------------------------------------------
 # stop test and certificate (rows a7, a10)
 # ---------------------------------------------------------------------------
