@@ -70,28 +70,29 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
 }
 
 // ---------------------------------------------------------------------------------
-// Stop test pass 2: e_r (row-local), Xhat = z X y + e_r e_c^T / ||e_r||_1 (Algorithm 3,
-// steps 9-11), D_phi(Xhat, X) in the log domain, <C,Xhat>, <C,X>, c-transforms of
-// gamma and psi, <X, U(gamma, zeta^c)>, norms for Delta_kkt.
+// Stop test pass 2, in two streaming passes over C (Algorithm 3, steps 9-11, and the
+// certificate of appendix C.1).
+// Pass 2a, per row: e_r,i = max(a_i - z_i sum_j X_ij y_j, 0) (exactly >= 0; the clamp
+// removes rounding), and the c-transforms zg_i = min_j (C_ij - gamma_j),
+// zp_i = min_j (C_ij - psi_j); per workgroup sum_i a_i zg_i and sum_i a_i zp_i.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT>
-__global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t ldc, int m, int n,
-                                              double sigma, const double *__restrict__ w,
-                                              const double *__restrict__ a,
-                                              const double *__restrict__ M,
-                                              const double *__restrict__ S,
-                                              const double *__restrict__ gamma,
-                                              const double *__restrict__ psi,
-                                              const double *__restrict__ y,
-                                              const double *__restrict__ ec,
-                                              const double *__restrict__ z, double er1,
-                                              double *__restrict__ xhat,
-                                              double *__restrict__ rowpart)
+__global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t ldc, int m, int n,
+                                               double sigma, const double *__restrict__ w,
+                                               const double *__restrict__ a,
+                                               const double *__restrict__ M,
+                                               const double *__restrict__ S,
+                                               const double *__restrict__ gamma,
+                                               const double *__restrict__ psi,
+                                               const double *__restrict__ y,
+                                               const double *__restrict__ z,
+                                               double *__restrict__ er_row,
+                                               double *__restrict__ zg_row,
+                                               double *__restrict__ rowpart)
 {
     constexpr int E = Q * VEC;
     using Red3 = BlockRed<NT, OP_SUM, OP_MIN, OP_MIN>;
-    using RedEnd = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_SUM, OP_MIN, OP_SUM, OP_SUM>;
-    __shared__ double lds[Red3::LDS + RedEnd::LDS];
+    __shared__ double lds[Red3::LDS];
     extern __shared__ double wl[];   // w staged in LDS (n doubles)
     int parity = 0;
     int i0, i1;
@@ -99,45 +100,94 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
     __shared__ double etab[EXP_TAB];
     exp_table_init(etab);
     stage_lds(w, n, wl);
-    // 32 rows per staged chunk: with an n-vector of 20000 doubles the static LDS must stay
-    // below 3.8 KB
-    constexpr int RC = 32;
-    __shared__ double rM[RC], rS[RC], rA[RC], rZ[RC];
-    double X[E];
-    double t_dphi = 0.0, t_cxh = 0.0, t_cx = 0.0, t_xu = 0.0, t_xhmin = INFINITY, t_xf = 0.0,
-           t_cf = 0.0;
+    constexpr int RCA = 32;   // rows per staged chunk (static LDS within 3.5 KB)
+    __shared__ double rM[RCA], rS[RCA], rA[RCA], rZ[RCA];
     double azg = 0.0, azp = 0.0;
-    const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
-    row_loop<NT, Q, QF, VEC, false, RC>(
-        C, ldc, n, i0, i1, [&](int i) { stage_rows<RC>(i, i1, M, rM, S, rS, a, rA, z, rZ); },
+    row_loop<NT, Q, QF, VEC, true, RCA>(
+        C, ldc, n, i0, i1, [&](int i) { stage_rows<RCA>(i, i1, M, rM, S, rS, a, rA, z, rZ); },
         [&](int i, int slot, const CT *cst) {
-        const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];
+        const double Mi = rM[slot], ai = rA[slot], aS = ai / rS[slot];
         double red[3] = {0.0, INFINITY, INFINITY};
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool valid = slot_valid<QF, NT, VEC>(e, n);
-            const int j = slot_col<QF, NT, VEC>(e, n);
-            const double c = valid ? (double)cst[e] : 0.0;
-            const double Xv = exp_tab(valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY, etab) * aS;
-            X[e] = Xv;
-            red[0] = fma(Xv, y[j], red[0]);
-            red[1] = fmin(red[1], valid ? c - gamma[j] : INFINITY);
-            red[2] = fmin(red[2], valid ? c - psi[j] : INFINITY);
-        }
-        Red3::run(red, lds, parity);
-        const double eri = fmax(ai - zi * red[0], 0.0);   // >= 0 exactly; clamp rounding
-        const double zg = red[1], zp = red[2];
-        const double lr = log(ai) - log(rS[slot]);   // log X_ij = lr + (theta_ij - M_i)
-        const double es = eri * inv_er1;         // rank-one factor e_r,i / ||e_r||_1
 #pragma unroll 2
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
             const int j = slot_col<QF, NT, VEC>(e, n);
             const double c = valid ? (double)cst[e] : 0.0;
-            const double Xv = X[e];
+            const double Xv = exp_tab(valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY, etab) * aS;
+            red[0] = fma(Xv, y[j], red[0]);
+            red[1] = fmin(red[1], valid ? c - gamma[j] : INFINITY);
+            red[2] = fmin(red[2], valid ? c - psi[j] : INFINITY);
+        }
+        Red3::run(red, lds, parity);
+        if (threadIdx.x == 0) {
+            er_row[i] = fmax(ai - rZ[slot] * red[0], 0.0);
+            zg_row[i] = red[1];
+            azg += ai * red[1];
+            azp += ai * red[2];
+        }
+        });
+    if (threadIdx.x == 0) {
+        double *o = rowpart + (int64_t)blockIdx.x * STOP2_NSLOT;
+        o[STOP2_AZG] = azg;
+        o[STOP2_AZP] = azp;
+    }
+}
+
+// Pass 2b, streaming: Xhat = z X y + e_r e_c^T / ||e_r||_1, D_phi(Xhat, X) in the log
+// domain (log X_ij = log a_i - log S_i + (theta_ij - M_i)), <C,Xhat>, <C,X>, min Xhat,
+// <X, U> with U_ij = C_ij - gamma_j - zg_i, and ||X||_F^2, ||C||_F^2 for Delta_kkt.
+template <int NT, int Q, int QF, int VEC, typename CT>
+__global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t ldc, int m, int n,
+                                               double sigma, const double *__restrict__ w,
+                                               const double *__restrict__ a,
+                                               const double *__restrict__ M,
+                                               const double *__restrict__ S,
+                                               const double *__restrict__ gamma,
+                                               const double *__restrict__ y,
+                                               const double *__restrict__ ec,
+                                               const double *__restrict__ z,
+                                               const double *__restrict__ er_row,
+                                               const double *__restrict__ zg_row, double er1,
+                                               double *__restrict__ xhat,
+                                               double *__restrict__ rowpart)
+{
+    constexpr int E = Q * VEC;
+    using RedEnd = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_SUM, OP_MIN, OP_SUM, OP_SUM>;
+    __shared__ double lds[RedEnd::LDS];
+    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    int i0, i1;
+    row_range(m, i0, i1);
+    __shared__ double etab[EXP_TAB];
+    exp_table_init(etab);
+    stage_lds(w, n, wl);
+    // 16 rows per staged chunk: with an n-vector of 20000 doubles the static LDS must stay
+    // within 3.5 KB
+    constexpr int RC = 16;
+    __shared__ double rM[RC], rS[RC], rA[RC], rZ[RC], rE[RC], rG[RC];
+    double t_dphi = 0.0, t_cxh = 0.0, t_cx = 0.0, t_xu = 0.0, t_xhmin = INFINITY, t_xf = 0.0,
+           t_cf = 0.0;
+    const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
+    row_loop<NT, Q, QF, VEC, false, RC>(
+        C, ldc, n, i0, i1,
+        [&](int i) {
+            stage_rows<RC>(i, i1, M, rM, S, rS, a, rA, z, rZ);
+            stage_rows<RC>(i, i1, er_row, rE, zg_row, rG, nullptr, nullptr);
+        },
+        [&](int i, int slot, const CT *cst) {
+        const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];
+        const double es = rE[slot] * inv_er1;   // rank-one factor e_r,i / ||e_r||_1
+        const double zg = rG[slot];
+        const double lr = log(ai) - log(rS[slot]);
+#pragma unroll 2
+        for (int e = 0; e < E; ++e) {
+            const bool valid = slot_valid<QF, NT, VEC>(e, n);
+            const int j = slot_col<QF, NT, VEC>(e, n);
+            const double c = valid ? (double)cst[e] : 0.0;
+            const double xa = valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY;
+            const double Xv = exp_tab(xa, etab) * aS;
             const double f = (zi * Xv) * y[j];
             const double xh = valid ? fma(es, ec[j], f) : 0.0;
-            const double lx = lr + fma(-sigma, c, wl[j] - Mi);
+            const double lx = lr + xa;
             const bool pos = xh > 0.0;
             const double lxh = log(pos ? xh : 1.0);
             t_dphi += pos ? (xh * (lxh - lx) - xh) + Xv : Xv;
@@ -150,20 +200,14 @@ __global__ __launch_bounds__(NT) void k_stop2(const CT *__restrict__ C, int64_t 
             if (xhat && valid)
                 xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xh;
         }
-        if (threadIdx.x == 0) {
-            azg += ai * zg;
-            azp += ai * zp;
-        }
         });
     double fin[7] = {t_dphi, t_cxh, t_cx, t_xu, t_xhmin, t_xf, t_cf};
     int p2 = 0;
-    RedEnd::run(fin, lds + Red3::LDS, p2);
+    RedEnd::run(fin, lds, p2);
     if (threadIdx.x == 0) {
         double *o = rowpart + (int64_t)blockIdx.x * STOP2_NSLOT;
         o[STOP2_DPHI] = fin[0];
         o[STOP2_CXH] = fin[1];
-        o[STOP2_AZG] = azg;
-        o[STOP2_AZP] = azp;
         o[STOP2_CX] = fin[2];
         o[STOP2_XU] = fin[3];
         o[STOP2_XHMIN] = fin[4];
@@ -279,20 +323,26 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stop2(const RowPlan &p_in, const DenseArgs &d, const double *M, const double *S,
+hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
                         const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st)
 {
-    const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
-    static LdsCache lc_; \
-    if (hipError_t e_ = lds_check((const void *)k_stop2<NT, Q, QF, VEC, CT>, lds_bytes, lc_); e_ != hipSuccess) \
-        return e_; \
-    hipLaunchKernelGGL((k_stop2<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                  \
+    static LdsCache lca_, lcb_;                                                                   \
+    if (hipError_t e_ = lds_check((const void *)k_stop2a<NT, Q, QF, VEC, CT>, lds_bytes, lca_);   \
+        e_ != hipSuccess)                                                                         \
+        return e_;                                                                                \
+    if (hipError_t e_ = lds_check((const void *)k_stop2b<NT, Q, QF, VEC, CT>, lds_bytes, lcb_);   \
+        e_ != hipSuccess)                                                                         \
+        return e_;                                                                                \
+    hipLaunchKernelGGL((k_stop2a<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
                        (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
-                       v.gamma, v.psi, v.y, v.ec, v.z, v.er1, xhat, rowpart)
+                       v.gamma, v.psi, v.y, v.z, v.er_row, v.zg_row, rowpart);                    \
+    hipLaunchKernelGGL((k_stop2b<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
+                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
+                       v.gamma, v.y, v.ec, v.z, v.er_row, v.zg_row, v.er1, xhat, rowpart)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
-    IBSN_HEAVY_TILES(X)
+    IBSN_LIGHT_TILES(X)
 #undef X
 #undef BODY
     return hipErrorInvalidValue;

@@ -48,6 +48,7 @@ struct ibsn_ctx {
     std::string err;
     // workspace
     DevBuf w, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
+    DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     ibsn_csr *solver_csr = nullptr;
@@ -215,6 +216,8 @@ int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
     CKI(ensure(ctx, ctx->ecv, n * 8));
     CKI(ensure(ctx, ctx->psiv, n * 8));
     CKI(ensure(ctx, ctx->zv, m * 8));
+    CKI(ensure(ctx, ctx->erv, m * 8));
+    CKI(ensure(ctx, ctx->zgv, m * 8));
     CKI(ensure(ctx, ctx->stopout, 16 * 8));
     CKI(ensure(ctx, ctx->tauv, n * 8));
     return IBSN_OK;
@@ -385,6 +388,8 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     v.y = P<double>(ctx->yv);
     v.ec = P<double>(ctx->ecv);
     v.z = P<double>(ctx->zv);
+    v.er_row = P<double>(ctx->erv);
+    v.zg_row = P<double>(ctx->zgv);
     v.er1 = ctx->host_scal[SC_ER1];
     {
         KTimer kt(ctx, IBSN_KT_STOP2);
@@ -615,7 +620,7 @@ void ibsn_destroy(ibsn_ctx *ctx)
     ctx->csrs.clear();
     DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
-                      &ctx->psiv, &ctx->zv, &ctx->stopout, &ctx->tauv,
+                      &ctx->psiv, &ctx->zv, &ctx->erv, &ctx->zgv, &ctx->stopout, &ctx->tauv,
                       &ctx->cg_x, &ctx->cg_r, &ctx->cg_r2,
                       &ctx->cg_p,
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_star, &ctx->cg_pap, &ctx->cg_rr,

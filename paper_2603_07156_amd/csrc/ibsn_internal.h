@@ -70,6 +70,7 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
 // ---- stop test, pass 2 (rounded plan, D_phi, certificate) -----------------------
 struct Stop2Vec {
     const double *gamma, *psi, *y, *ec, *z;   // n, n, n, n, m
+    double *er_row, *zg_row;                  // m, m: e_r,i and min_j (C_ij - gamma_j)
     double er1;                               // ||e_r||_1
 };
 // rowpart[grid * 10]: per-workgroup sums (see STOP2_* slots).
