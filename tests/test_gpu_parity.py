@@ -520,3 +520,56 @@ def test_solve_tiny_eta_numeric_error(ib, ctx):
     assert ei.value.code == -4
     o = orc.solve(inst.C, inst.a, inst.b, 1e-6, options=orc.default_options(max_outer=50))
     assert o["status"] == -4
+
+
+def test_full_size_10k_passes(ib, ctx):
+    """m = n = 10^4 (800 MB FP64 cost) in the benchmark's launch configuration: trial,
+    sparsify (pattern and values), HVP, CG and the stop pass against the oracle, at the
+    prox centre of outer iteration 60 (sigma = 6100, a factor as sparse as in the benchmark)."""
+    n = 10000
+    inst = W.uniform_points(n, 1000)
+    k = 60
+    r, s = np.log(inst.a), np.log(inst.b)
+    gamma = W.random_dual(n, 2, 1e-4)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    pr = problem(ib, inst)
+    g_gamma = dev(gamma)
+    # Armijo trial
+    Delta = W.random_dual(n, 44, 1e-4)
+    gt = ib.trial(ctx, pr, ctr, g_gamma, dev(ev.M), dev(Delta), 1.0)
+    dL, Mn, Sn, cn, gn_ = orc.trial_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, Delta, 1.0,
+                                         s=s, k=k, q=q)
+    assert abs(gt["dL"] - dL) <= 1e-12 * abs(dL) + 1e-17
+    np.testing.assert_allclose(host(gt["M"]) + np.log(host(gt["S"])), Mn + np.log(Sn), rtol=1e-15,
+                               atol=1e-12)
+    np.testing.assert_allclose(host(gt["c"]), cn, rtol=1e-12, atol=1e-300)
+    # sparsify with the paper's rho
+    gnorm = np.linalg.norm(ev.g)
+    rho = inst.eta * gnorm / (n * n)
+    gcsr = ib.sparsify(ctx, pr, ctr, g_gamma, dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
+    row_ptr, col, val, d = (host(x) for x in gcsr.export())
+    assert gcsr.nnz == ocsr.nnz and np.array_equal(row_ptr, ocsr.row_ptr)
+    assert np.array_equal(col, ocsr.col), "no entry of these inputs lies in the threshold band"
+    np.testing.assert_allclose(val, ocsr.val, rtol=1e-12)
+    np.testing.assert_allclose(d, ocsr.d, rtol=1e-12)
+    assert 1e5 < gcsr.nnz < 2e7
+    # HVP and CG on the same factor
+    v = W.random_dual(n, 21, 1.0)
+    shift = gnorm
+    yg = host(ib.hvp(ctx, gcsr, pr.a, inst.eta, shift, dev(v)))
+    yo = orc.hvp(ocsr, inst.a, inst.eta, shift, v)
+    np.testing.assert_allclose(yg, yo, rtol=1e-12, atol=1e-12 * np.abs(yo).max())
+    tol = 1e-8 * gnorm
+    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 400)
+    xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 400)
+    assert itg < 400 and ito < 400
+    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-7 * np.abs(xo).max())
+    gcsr.free()
+    # stop test and certificate
+    gs = ib.stop(ctx, pr, ctr, g_gamma, dev(ev.M), dev(ev.S))
+    os_ = orc.stop_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, ev.S, s=s, k=k, q=q)
+    for key, rtol, atol in [("primal", 1e-12, 0), ("dual", 1e-12, 1e-16), ("cx", 1e-12, 0),
+                            ("dphi", 1e-9, 1e-15), ("kkt", 1e-9, 1e-16)]:
+        assert abs(gs[key] - os_[key]) <= rtol * abs(os_[key]) + atol, (key, gs[key], os_[key])
