@@ -154,6 +154,35 @@ def time_to_1e8(ibsn, ctx, n: int, eta: float):
     return out
 
 
+def batch_solves(ibsn, count: int, outer: int = 20):
+    """The batched workload (grid histograms, sizes m, n in [64, 2048], seed 300, eta 1e-2):
+    `outer` outer iterations per problem, with one context and with four contexts on their
+    own streams (ibsn_solve_batch)."""
+    import torch
+
+    from paper_2603_07156_amd import workloads
+    batch = workloads.grid_histogram_batch(count, 300)
+    dev = torch.device("cuda", 0)
+    probs = [ibsn.Problem(torch.from_numpy(b.C).to(dev), torch.from_numpy(b.a).to(dev),
+                          torch.from_numpy(b.b).to(dev), b.eta) for b in batch]
+    opt = ibsn.default_options(max_outer=outer, gap_tol=0.0, marg_tol=0.0)
+    res = {"workload": f"{count} grid-histogram problems, m,n in [64, 2048], sum m n = "
+                       f"{sum(b.C.size for b in batch):.3g}, eta 1e-2, {outer} outer iterations each"}
+    for workers in (1, 4):
+        ctxs = [ibsn.Context(0, stream=torch.cuda.Stream()) for _ in range(workers)]
+        ibsn.solve_batch(ctxs, probs[:workers], opt)   # warm the workspaces
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = ibsn.solve_batch(ctxs, probs, opt)
+        dt = time.perf_counter() - t0
+        res[f"contexts_{workers}"] = {"seconds": dt, "problems_per_s": count / dt,
+                                      "failed": sum(1 for o in outs if o["status"] < 0)}
+        for c in ctxs:
+            c.close()
+    res["speedup_4_over_1"] = res["contexts_1"]["seconds"] / res["contexts_4"]["seconds"]
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +197,8 @@ def main() -> int:
     ap.add_argument("--ttg-n", type=int, default=1024,
                     help="size of the time-to-1e-8-gap runs (0 = skip); eta set by --ttg-eta")
     ap.add_argument("--ttg-eta", type=float, default=1e-5)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="problems of the batched grid-histogram workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
@@ -260,6 +291,8 @@ def main() -> int:
                 "bytes_per_launch": pb, "avg_launch_ms": mk["avg"], "launches": mk["launches"]}
     if args.ttg_n > 0:
         out["time_to_1e-8_gap"] = time_to_1e8(ibsn, ctx, args.ttg_n, args.ttg_eta)
+    if args.batch > 0:
+        out["batch"] = batch_solves(ibsn, args.batch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out))

@@ -259,6 +259,20 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt,
                double *gamma_io, double *r_io, double *s_io, int64_t *k_io, double *plan_out,
                ibsn_report *rep);
 
+/* Many independent problems (the batched form; the paper solves one problem at a time).
+   nctx contexts, each used by one host worker thread of this call, on its own stream:
+   the small, launch-latency-bound passes of different problems then overlap on the GPU.
+   Problems are taken largest m n first from a shared counter.  For problem i:
+   gamma_io[i] (n_i, device; gamma_io or gamma_io[i] may be NULL) is the warm start in and
+   the final dual out, reps[i] (optional) its report, status[i] its ibsn_solve return code.
+   opt (NULL = defaults) applies to all.  Results do not depend on nctx or on which context
+   solved a problem.  Returns IBSN_OK once every problem has been attempted, or
+   IBSN_ERR_INVALID_ARG (no problem attempted) for bad arguments, including a context
+   passed twice.  The contexts must not be used by other threads during the call. */
+int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_problem *probs,
+                     const ibsn_options *opt, double *const *gamma_io, ibsn_report *reps,
+                     int32_t *status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,9 @@
 #include "solver_kernels.h"
 
 #include <algorithm>
+#include <atomic>
+#include <numeric>
+#include <thread>
 #include <cfloat>
 #include <chrono>
 #include <cmath>
@@ -1265,6 +1268,47 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     return R.status;
 #undef CKS
 #undef CKSH
+}
+
+int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_problem *probs,
+                     const ibsn_options *opt, double *const *gamma_io, ibsn_report *reps,
+                     int32_t *status)
+{
+    if (!ctxs || nctx < 1 || nprob < 0 || (nprob > 0 && (!probs || !status)))
+        return IBSN_ERR_INVALID_ARG;
+    for (int w = 0; w < nctx; ++w) {
+        if (!ctxs[w])
+            return IBSN_ERR_INVALID_ARG;
+        for (int v = 0; v < w; ++v)
+            if (ctxs[v] == ctxs[w])
+                return fail(ctxs[w], IBSN_ERR_INVALID_ARG, "each worker needs its own context");
+    }
+    // longest (largest m n) first, then a shared counter: each worker takes the next problem
+    std::vector<int64_t> order((size_t)nprob);
+    std::iota(order.begin(), order.end(), (int64_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return probs[x].m * probs[x].n > probs[y].m * probs[y].n;
+    });
+    std::atomic<int64_t> next{0};
+    auto worker = [&](int w) {
+        for (;;) {
+            const int64_t t = next.fetch_add(1);
+            if (t >= nprob)
+                break;
+            const int64_t i = order[(size_t)t];
+            ibsn_report r;
+            status[i] = ibsn_solve(ctxs[w], &probs[i], opt, gamma_io ? gamma_io[i] : nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, reps ? &reps[i] : &r);
+        }
+    };
+    std::vector<std::thread> pool;
+    pool.reserve((size_t)nctx);
+    for (int w = 1; w < nctx; ++w)
+        pool.emplace_back(worker, w);
+    worker(0);
+    for (std::thread &t : pool)
+        t.join();
+    return IBSN_OK;
 }
 
 }  // extern "C"

@@ -87,7 +87,8 @@ _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
            "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
-           "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get")
+           "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
+           "ibsn_solve_batch")
 
 
 def load():
@@ -122,6 +123,8 @@ def load():
     L.ibsn_default_options.restype = None
     L.ibsn_solve.argtypes = [vp, P, ct.POINTER(Options), vp, vp, vp, ct.POINTER(i64), vp,
                              ct.POINTER(Report)]
+    L.ibsn_solve_batch.argtypes = [ct.POINTER(vp), ct.c_int, i64, P, ct.POINTER(Options),
+                                   ct.POINTER(vp), ct.POINTER(Report), ct.POINTER(ct.c_int32)]
     L.ibsn_kernel_timing.argtypes = [vp, ct.c_int]
     L.ibsn_kernel_times_get.argtypes = [vp, ct.POINTER(_KernelTimes)]
     for name in EXPORTS:
@@ -408,6 +411,38 @@ def solve(ctx: Context, prob: Problem, options: Options | None = None, gamma0=No
     return dict(status=rc, gamma=gamma, r=r, s=s, k=k.value, plan=plan, report=rep.as_dict())
 
 
+def solve_batch(ctxs, probs, options: Options | None = None, gamma0=None):
+    """ibsn_solve_batch: solve independent problems with one host worker per context (each
+    context on its own stream).  gamma0: optional list of warm starts.  Returns a list of
+    dict(status, gamma, report), in the order of `probs`."""
+    ctxs = list(ctxs)
+    if not ctxs:
+        raise ValueError("at least one context")
+    L = load()
+    raws = (_Problem * max(len(probs), 1))(*[p.raw() for p in probs])
+    gammas = []
+    for i, p in enumerate(probs):
+        g = _new(p, p.n)
+        if gamma0 is not None and gamma0[i] is not None:
+            g.copy_(gamma0[i])
+        else:
+            g.zero_()
+        gammas.append(g)
+    gptr = (ct.c_void_p * max(len(probs), 1))(*[ct.c_void_p(g.data_ptr()) for g in gammas])
+    reps = (Report * max(len(probs), 1))()
+    status = (ct.c_int32 * max(len(probs), 1))()
+    handles = (ct.c_void_p * len(ctxs))(*[c.h for c in ctxs])
+    opt = options if options is not None else default_options()
+    for p in probs:
+        if p.C.device != probs[0].C.device:
+            raise ValueError("all problems must live on one device")
+    torch.cuda.synchronize()   # inputs written on torch's stream are visible to every worker
+    ctxs[0].check(L.ibsn_solve_batch(handles, len(ctxs), len(probs), raws, ct.byref(opt), gptr,
+                                     reps, status))
+    return [dict(status=int(status[i]), gamma=gammas[i], report=reps[i].as_dict())
+            for i in range(len(probs))]
+
+
 # the C-ABI names
 ibsn_center_quantum = center_quantum
 ibsn_subproblem_eval = subproblem_eval
@@ -417,3 +452,4 @@ ibsn_hvp = hvp
 ibsn_cg = cg
 ibsn_stop = stop
 ibsn_solve = solve
+ibsn_solve_batch = solve_batch

@@ -142,3 +142,36 @@ def random_dual(n: int, seed: int, scale: float = 1e-2) -> np.ndarray:
     rng = np.random.default_rng(seed)
     g = scale * rng.standard_normal(n)
     return g - g.mean()
+
+
+def _grid_histogram(rng: np.random.Generator, size: int):
+    """A histogram on a side x side grid (side = round(sqrt(size))) over [0,1]^2: a sum of
+    1-5 Gaussian blobs (centres U[0,1]^2, std U(0.05, 0.2), weights U(0,1)) plus a 1e-6
+    floor, normalised; returns (coordinates (side^2, 2), weights)."""
+    side = max(2, int(round(np.sqrt(size))))
+    u = np.arange(side, dtype=np.float64) / (side - 1)
+    pts = np.stack(np.meshgrid(u, u, indexing="ij"), -1).reshape(-1, 2)
+    K = int(rng.integers(1, 6))
+    centres = rng.random((K, 2))
+    stds = rng.uniform(0.05, 0.2, K)
+    wts = rng.random(K)
+    h = np.full(len(pts), 1e-6)
+    for c, s_, w_ in zip(centres, stds, wts):
+        h += w_ * np.exp(-((pts - c) ** 2).sum(-1) / (2.0 * s_ * s_))
+    return pts, _normalise(h)
+
+
+def grid_histogram_batch(count: int, seed: int, eta: float = 1e-2, lo: int = 64,
+                         hi: int = 2048) -> list:
+    """The batched workload: `count` problems whose sizes m, n are drawn uniformly in
+    [lo, hi] and rounded to square grids; each side a grid histogram, cost the squared
+    coordinate distance divided by its maximum."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(count):
+        m_req, n_req = (int(v) for v in rng.integers(lo, hi + 1, 2))
+        xs, a = _grid_histogram(rng, m_req)
+        ys, b = _grid_histogram(rng, n_req)
+        C = sqdist_cost(xs, ys)
+        out.append(Instance(C, a, b, eta, f"grid_batch_{t}_s{seed}", xs, ys))
+    return out

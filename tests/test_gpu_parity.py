@@ -573,3 +573,36 @@ def test_full_size_10k_passes(ib, ctx):
     for key, rtol, atol in [("primal", 1e-12, 0), ("dual", 1e-12, 1e-16), ("cx", 1e-12, 0),
                             ("dphi", 1e-9, 1e-15), ("kkt", 1e-9, 1e-16)]:
         assert abs(gs[key] - os_[key]) <= rtol * abs(os_[key]) + atol, (key, gs[key], os_[key])
+
+
+def test_solve_batch_matches_sequential(ib, ctx):
+    """The batched form (three worker contexts on their own streams) returns, for every
+    problem, bitwise the result of solving it alone: each solve is deterministic and the
+    workers share nothing.  One problem is also checked against the oracle's solve."""
+    batch = W.grid_histogram_batch(7, 301, lo=64, hi=600)
+    probs = [problem(ib, inst) for inst in batch]
+    opt = ib.default_options(max_outer=25, gap_tol=0.0, marg_tol=0.0)
+    ctxs = [ib.Context(0, stream=torch.cuda.Stream()) for _ in range(3)]
+    out = ib.solve_batch(ctxs, probs, opt)
+    for inst, pr, o in zip(batch, probs, out):
+        ref = ib.solve(ctx, pr, opt)
+        assert o["status"] == ref["status"]
+        assert torch.equal(o["gamma"], ref["gamma"]), inst.name
+        for key in ("outer", "newton", "cg", "primal", "dual", "rel_gap"):
+            assert o["report"][key] == ref["report"][key], (inst.name, key)
+    # the smallest problem against the oracle's solve with the same options: after a fixed
+    # number of inexact outer iterations the two trajectories differ, but each certificate
+    # brackets the same OT value (dual <= OT <= primal), so the primal values differ by at
+    # most the larger certified gap, and each dual stays below the other's primal
+    i = int(np.argmin([inst.C.size for inst in batch]))
+    inst = batch[i]
+    o = orc.solve(inst.C, inst.a, inst.b, inst.eta, options=orc.default_options(
+        max_outer=25, gap_tol=0.0, marg_tol=0.0))["report"]
+    g = out[i]["report"]
+    assert abs(g["primal"] - o["primal"]) <= max(g["primal"] - g["dual"], o["primal"] - o["dual"])
+    assert g["dual"] <= o["primal"] * (1 + 1e-13) and o["dual"] <= g["primal"] * (1 + 1e-13)
+    # the same context twice is rejected before any problem is attempted
+    with pytest.raises(ib.IBSNError):
+        ib.solve_batch([ctxs[0], ctxs[0]], probs[:2], opt)
+    for c in ctxs:
+        c.close()
