@@ -58,7 +58,7 @@ enum {
 };
 
 /* Largest n of the dense row kernels: a workgroup holds one row of C in registers and
-   an n-vector of potentials in LDS (FP64 cost: 10240 columns; FP32 cost: 20000). */
+   an n-vector of potentials in LDS (FP64 cost and points: 10240 columns; FP32 cost: 20000). */
 #define IBSN_MAX_N_F64 10240
 #define IBSN_MAX_N_F32 20000
 
@@ -74,7 +74,7 @@ const char *ibsn_last_error(const ibsn_ctx *ctx);
 /* Number of compute units of the context's device (host value). */
 int ibsn_num_cus(const ibsn_ctx *ctx);
 
-typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1 } ibsn_cost_kind;
+typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1, IBSN_COST_POINTS = 2 } ibsn_cost_kind;
 
 /* Arithmetic of the m x n passes.  IBSN_PREC_F64: everything in FP64.
    IBSN_PREC_MIXED (the precision form; the paper fixes no precision): the eval, trial and
@@ -100,6 +100,13 @@ typedef struct {
     int64_t ldc;
     const double *a, *b;      /* device, m and n */
     double eta;
+    /* IBSN_COST_POINTS: the cost is not stored but formed from points in every pass:
+       C points to x (m x dim, row-major FP64), ldc = dim (2 or 3), y (n x dim) and
+       C_ij = cost_scale * ((x_i1 - y_j1)^2 + (x_i2 - y_j2)^2 [+ (x_i3 - y_j3)^2]), each
+       square and sum rounded separately, in that order (no fused multiply-add), so that a
+       caller can form the same matrix exactly.  Unused for the stored cost kinds. */
+    const double *y;
+    double cost_scale;
 } ibsn_problem;
 
 /* Implicit prox centre X^k (see above): device r (m), s (n), and the grid spacing

@@ -348,6 +348,67 @@ __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc
     }
 }
 
+// Cost formed from points (no stored matrix): the kernels' cost type is the tag PtsCost<DIM>,
+// their C argument points to x (m x DIM) and py / pscale give y (n x DIM) and the scale.
+// C_ij = pscale * ((x_i1 - y_j1)^2 + (x_i2 - y_j2)^2 [+ (x_i3 - y_j3)^2]), every product
+// and sum rounded separately in that order.
+template <int DIM>
+struct PtsCost {};
+template <typename CT>
+struct IsPts : std::false_type {};
+template <int DIM>
+struct IsPts<PtsCost<DIM>> : std::true_type {
+    static constexpr int dim = DIM;
+};
+
+template <int DIM>
+__device__ __forceinline__ double pts_cost(const double *xi, const double *yj, double scale)
+{
+#pragma clang fp contract(off)
+    const double t0 = xi[0] - yj[0];
+    double s = t0 * t0;
+    const double t1 = xi[1] - yj[1];
+    s = s + t1 * t1;
+    if constexpr (DIM == 3) {
+        const double t2 = xi[2] - yj[2];
+        s = s + t2 * t2;
+    }
+    return s * scale;
+}
+
+// Row loop over a points cost: each thread keeps y of its own columns in registers (slots
+// past n use column n - 1, as load_row does) and forms every row from x_i, so the pass
+// reads no m x n array.
+template <int NT, int Q, int QF, int DIM, int RC, typename Stage, typename Body>
+__device__ __forceinline__ void row_loop_pts(const double *__restrict__ x,
+                                             const double *__restrict__ y, double scale, int n,
+                                             int i0, int i1, Stage &stage, Body &body)
+{
+    constexpr int E = Q * 2;
+    double yr[E * DIM];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = min(col_of<NT, 2>(e), n - 1);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+            yr[e * DIM + k] = y[(int64_t)j * DIM + k];
+    }
+    double xr[E];
+    for (int i = i0; i < i1; ++i) {
+        const int slot = (i - i0) & (RC - 1);
+        if (slot == 0)
+            stage(i);
+        double xi[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+            xi[k] = x[(int64_t)i * DIM + k];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            xr[e] = pts_cost<DIM>(xi, yr + e * DIM, scale);
+        body(i, slot, xr);
+    }
+}
+
 // 16-byte vector loads when the matrix start and the row pitch are 16-byte aligned and n
 // is a multiple of VEC (the same for every row); scalar loads otherwise.
 // PREFETCH = false (passes whose per-entry state leaves no registers for a second row):
@@ -355,15 +416,22 @@ __device__ __forceinline__ void row_loop_v(const CT *__restrict__ C, int64_t ldc
 // RC: rows per staged chunk (a power of two; the kernel's stage_rows<RC> fills them).
 template <int NT, int Q, int QF, int VEC, bool PREFETCH = true, int RC = ROWCH, typename CT,
           typename Stage, typename Body>
-__device__ __forceinline__ void row_loop(const CT *__restrict__ C, int64_t ldc, int n, int i0,
-                                         int i1, Stage &&stage, Body &&body)
+__device__ __forceinline__ void row_loop(const CT *__restrict__ C, int64_t ldc,
+                                         const double *__restrict__ py, double pscale, int n,
+                                         int i0, int i1, Stage &&stage, Body &&body)
 {
+    if constexpr (IsPts<CT>::value) {
+        row_loop_pts<NT, Q, QF, IsPts<CT>::dim, RC>(reinterpret_cast<const double *>(C), py,
+                                                    pscale, n, i0, i1, stage, body);
+        return;
+    } else {
     const bool vec_ok = (reinterpret_cast<uintptr_t>(C) & 15u) == 0 &&
                         ((uint64_t)ldc * sizeof(CT)) % 16 == 0 && n % VEC == 0;
     if (vec_ok)
         row_loop_v<NT, Q, QF, VEC, true, PREFETCH, RC>(C, ldc, n, i0, i1, stage, body);
     else
         row_loop_v<NT, Q, QF, VEC, false, PREFETCH, RC>(C, ldc, n, i0, i1, stage, body);
+    }
 }
 
 // Copy rows [i, min(i + RC, i1)) of up to four m-vectors into LDS (null: skipped).
@@ -462,9 +530,29 @@ inline hipError_t lds_check(const void *fn, size_t dyn, LdsCache &cache)
                 constexpr bool MX = false;                                       \
                 BODY;                                                            \
             }                                                                    \
-        } else {                                                                 \
+        } else if (d.cost_kind == 1) {                                           \
             constexpr int VEC = 4;                                               \
             using CT = float;                                                    \
+            if (d.mixed) {                                                       \
+                constexpr bool MX = true;                                        \
+                BODY;                                                            \
+            } else {                                                             \
+                constexpr bool MX = false;                                       \
+                BODY;                                                            \
+            }                                                                    \
+        } else if (d.pdim == 2) {                                                \
+            constexpr int VEC = 2;                                               \
+            using CT = PtsCost<2>;                                               \
+            if (d.mixed) {                                                       \
+                constexpr bool MX = true;                                        \
+                BODY;                                                            \
+            } else {                                                             \
+                constexpr bool MX = false;                                       \
+                BODY;                                                            \
+            }                                                                    \
+        } else {                                                                 \
+            constexpr int VEC = 2;                                               \
+            using CT = PtsCost<3>;                                               \
             if (d.mixed) {                                                       \
                 constexpr bool MX = true;                                        \
                 BODY;                                                            \
@@ -483,9 +571,17 @@ inline hipError_t lds_check(const void *fn, size_t dyn, LdsCache &cache)
             constexpr int VEC = 2;                                               \
             using CT = double;                                                   \
             BODY;                                                                \
-        } else {                                                                 \
+        } else if (d.cost_kind == 1) {                                           \
             constexpr int VEC = 4;                                               \
             using CT = float;                                                    \
+            BODY;                                                                \
+        } else if (d.pdim == 2) {                                                \
+            constexpr int VEC = 2;                                               \
+            using CT = PtsCost<2>;                                               \
+            BODY;                                                                \
+        } else {                                                                 \
+            constexpr int VEC = 2;                                               \
+            using CT = PtsCost<3>;                                               \
             BODY;                                                                \
         }                                                                        \
         return hipGetLastError();                                                \

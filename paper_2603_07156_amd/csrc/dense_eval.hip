@@ -11,7 +11,8 @@ namespace {
 // shifts, S_i, the column partials and the objective stay FP64.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
-__global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t ldc, int m, int n,
+__global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t ldc,
+                                              const double *__restrict__ py, double pscale, int m, int n,
                                              double sigma, double qg,
                                              const double *__restrict__ w,
                                              const double *__restrict__ a,
@@ -45,8 +46,8 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         acc[e] = 0.0;
     double rowacc = 0.0;
     row_loop<NT, Q, QF, VEC>(
-        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, a, rA, r, rR, nullptr, nullptr); },
-        [&](int i, int slot, const CT *xr) {
+        C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows(i, i1, a, rA, r, rR, nullptr, nullptr); },
+        [&](int i, int slot, const auto *xr) {
         // padding slots: theta = -inf, so they drop out of the max and p = 0; a wave
         // with no column in the row gets m_w = -inf, s_w = 0 and factor 0
         double mt = -INFINITY;
@@ -116,7 +117,7 @@ hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, do
         return e_; \
     hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT),                     \
                        (size_t)d.n * sizeof(double), st,                                         \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, r, M, S, \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, r, M, S, \
                        lse,                                                                      \
                        plan, colpart, rowpart)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)

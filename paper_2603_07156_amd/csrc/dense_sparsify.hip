@@ -15,7 +15,8 @@ namespace {
 // the stored factor P~.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
-__global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64_t ldc, int m, int n,
+__global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64_t ldc,
+                                              const double *__restrict__ py, double pscale, int m, int n,
                                                  double sigma, const double *__restrict__ w,
                                                  const double *__restrict__ a,
                                                  const double *__restrict__ M,
@@ -48,8 +49,8 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
     for (int e = 0; e < E; ++e)
         acc[e] = 0.0;
     row_loop<NT, Q, QF, VEC>(
-        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA); },
-        [&](int i, int slot, const CT *xr) {
+        C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA); },
+        [&](int i, int slot, const auto *xr) {
         const double Mi = rM[slot], iS = 1.0 / rS[slot];
         const bool dense = (i == istar);
         int *cn = cnt[i & 1];
@@ -153,7 +154,7 @@ hipError_t launch_sparsify(const RowPlan &p_in, const DenseArgs &d, const double
     if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT), lds_bytes, st, \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, rho, \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, rho, \
                        istar, col, (xval_t<MX> *)val, len, colpart)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)

@@ -9,7 +9,8 @@ namespace {
 // Stop test pass 1 (Algorithm 3, steps 2-8): X = a_i P; z_i; column sums of X and z X.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT>
-__global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t ldc, int m, int n,
+__global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t ldc,
+                                              const double *__restrict__ py, double pscale, int m, int n,
                                               double sigma, const double *__restrict__ w,
                                               const double *__restrict__ a,
                                               const double *__restrict__ M,
@@ -37,8 +38,8 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
     }
     double rowacc = 0.0;
     row_loop<NT, Q, QF, VEC>(
-        C, ldc, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA); },
-        [&](int i, int slot, const CT *xr) {
+        C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA); },
+        [&](int i, int slot, const auto *xr) {
             const double Mi = rM[slot], ai = rA[slot], aS = ai / rS[slot];
             double red[1] = {0.0};
 #pragma unroll
@@ -77,7 +78,8 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
 // zp_i = min_j (C_ij - psi_j); per workgroup sum_i a_i zg_i and sum_i a_i zp_i.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT>
-__global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t ldc, int m, int n,
+__global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t ldc,
+                                              const double *__restrict__ py, double pscale, int m, int n,
                                                double sigma, const double *__restrict__ w,
                                                const double *__restrict__ a,
                                                const double *__restrict__ M,
@@ -104,8 +106,8 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
     __shared__ double rM[RCA], rS[RCA], rA[RCA], rZ[RCA];
     double azg = 0.0, azp = 0.0;
     row_loop<NT, Q, QF, VEC, true, RCA>(
-        C, ldc, n, i0, i1, [&](int i) { stage_rows<RCA>(i, i1, M, rM, S, rS, a, rA, z, rZ); },
-        [&](int i, int slot, const CT *cst) {
+        C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows<RCA>(i, i1, M, rM, S, rS, a, rA, z, rZ); },
+        [&](int i, int slot, const auto *cst) {
         const double Mi = rM[slot], ai = rA[slot], aS = ai / rS[slot];
         double red[3] = {0.0, INFINITY, INFINITY};
 #pragma unroll 2
@@ -137,7 +139,8 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
 // domain (log X_ij = log a_i - log S_i + (theta_ij - M_i)), <C,Xhat>, <C,X>, min Xhat,
 // <X, U> with U_ij = C_ij - gamma_j - zg_i, and ||X||_F^2, ||C||_F^2 for Delta_kkt.
 template <int NT, int Q, int QF, int VEC, typename CT>
-__global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t ldc, int m, int n,
+__global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t ldc,
+                                              const double *__restrict__ py, double pscale, int m, int n,
                                                double sigma, const double *__restrict__ w,
                                                const double *__restrict__ a,
                                                const double *__restrict__ M,
@@ -168,12 +171,12 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
            t_cf = 0.0;
     const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
     row_loop<NT, Q, QF, VEC, false, RC>(
-        C, ldc, n, i0, i1,
+        C, ldc, py, pscale, n, i0, i1,
         [&](int i) {
             stage_rows<RC>(i, i1, M, rM, S, rS, a, rA, z, rZ);
             stage_rows<RC>(i, i1, er_row, rE, zg_row, rG, nullptr, nullptr);
         },
-        [&](int i, int slot, const CT *cst) {
+        [&](int i, int slot, const auto *cst) {
         const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];
         const double es = rE[slot] * inv_er1;   // rank-one factor e_r,i / ||e_r||_1
         const double zg = rG[slot];
@@ -314,7 +317,7 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
     if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, z,   \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, z,   \
                        colpart, colpart2, rowpart)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)
@@ -336,10 +339,10 @@ hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, c
         e_ != hipSuccess)                                                                         \
         return e_;                                                                                \
     hipLaunchKernelGGL((k_stop2a<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
                        v.gamma, v.psi, v.y, v.z, v.er_row, v.zg_row, rowpart);                    \
     hipLaunchKernelGGL((k_stop2b<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
                        v.gamma, v.y, v.ec, v.z, v.er_row, v.zg_row, v.er1, xhat, rowpart)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)

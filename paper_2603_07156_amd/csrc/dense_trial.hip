@@ -14,7 +14,8 @@ namespace {
 // A, B, Z, the decrease and the new row state stay FP64.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT, bool MX, int BIG>
-__global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc, int m, int n,
+__global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc,
+                                              const double *__restrict__ py, double pscale, int m, int n,
                                               double sigma, double qg,
                                               const double *__restrict__ w,
                                               const double *__restrict__ a,
@@ -47,9 +48,9 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         acc[e] = 0.0;
     double rowacc = 0.0;
     row_loop<NT, Q, QF, VEC>(
-        C, ldc, n, i0, i1,
+        C, ldc, py, pscale, n, i0, i1,
         [&](int i) { stage_rows(i, i1, Mb, rM, a, rA, nullptr, nullptr); },
-        [&](int i, int slot, const CT *xr) {
+        [&](int i, int slot, const auto *xr) {
         const double Mi = rM[slot];
         double red[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -106,10 +107,10 @@ hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M
     if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MX, 0>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
                        scal, M_new, S_new, colpart, rowpart);                                     \
     hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 1>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
-                       (const CT *)d.C, d.ldc, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
                        scal, M_new, S_new, colpart, rowpart)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)

@@ -150,10 +150,30 @@ int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "m*n too large");
     if (!(p->eta > 0.0) || !std::isfinite(p->eta))
         return fail(ctx, IBSN_ERR_INVALID_ARG, "eta=%g must be finite and > 0", p->eta);
-    if (p->cost_kind != IBSN_COST_F64 && p->cost_kind != IBSN_COST_F32)
+    if (p->cost_kind != IBSN_COST_F64 && p->cost_kind != IBSN_COST_F32 &&
+        p->cost_kind != IBSN_COST_POINTS)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "cost_kind=%d unknown", p->cost_kind);
     if (p->precision != IBSN_PREC_F64 && p->precision != IBSN_PREC_MIXED)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "precision=%d unknown", p->precision);
+    if (p->cost_kind == IBSN_COST_POINTS) {
+        if (!p->C || !p->y || !p->a || !p->b)
+            return fail(ctx, IBSN_ERR_INVALID_ARG, "points cost needs device x (C), y, a and b");
+        if (p->ldc != 2 && p->ldc != 3)
+            return fail(ctx, IBSN_ERR_UNSUPPORTED, "points of dimension %lld (2 or 3 supported)",
+                        (long long)p->ldc);
+        if (!(p->cost_scale > 0.0) || !std::isfinite(p->cost_scale))
+            return fail(ctx, IBSN_ERR_INVALID_ARG, "cost_scale=%g must be finite and > 0",
+                        p->cost_scale);
+        if (((uintptr_t)p->C % 8) != 0 || ((uintptr_t)p->y % 8) != 0)
+            return fail(ctx, IBSN_ERR_INVALID_ARG, "x and y must be 8-byte aligned");
+        if (p->n > IBSN_MAX_N_F64)
+            return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld exceeds the register-tiled row kernels "
+                        "(max %d for points)", (long long)p->n, IBSN_MAX_N_F64);
+        if ((size_t)p->n * sizeof(double) + 3584 > ctx->max_lds)
+            return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld needs %zu bytes of LDS (device max %zu)",
+                        (long long)p->n, (size_t)p->n * 8 + 3584, ctx->max_lds);
+        return IBSN_OK;
+    }
     if (!p->C || !p->a || !p->b)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "C, a and b must be device pointers");
     if (p->ldc < p->n)
@@ -236,6 +256,9 @@ DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k, double q, 
     d.m = p->m;
     d.n = p->n;
     d.cost_kind = p->cost_kind;
+    d.py = p->cost_kind == IBSN_COST_POINTS ? p->y : nullptr;
+    d.pscale = p->cost_kind == IBSN_COST_POINTS ? p->cost_scale : 0.0;
+    d.pdim = p->cost_kind == IBSN_COST_POINTS ? (int)p->ldc : 0;
     d.sigma = (double)(k + 1) / p->eta;
     d.w = P<double>(ctx->w);
     d.a = p->a;
@@ -708,7 +731,7 @@ int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cent
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
     double *scal = P<double>(ctx->scal);
-    CKH(sk_cost_max(prob->m, prob->n, prob->ldc, prob->cost_kind, prob->C,
+    CKH(sk_cost_max(prob->m, prob->n, prob->ldc, prob->cost_kind, prob->C, prob->y, prob->cost_scale,
                     P<double>(ctx->rowpart2), rp.grid, scal, ctx->stream));
     CKH(sk_wmax(prob->n, ctr->s, gamma, prob->eta, scal, ctx->stream));
     CKI(read_scal(ctx));
@@ -1039,7 +1062,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         CKSH(sk_center(n, gamma, st));
 
     // per-problem maximum of |C| (sets the grid spacing of each outer iteration)
-    CKSH(sk_cost_max(m, n, prob->ldc, prob->cost_kind, prob->C, P<double>(ctx->rowpart2), rp.grid,
+    CKSH(sk_cost_max(m, n, prob->ldc, prob->cost_kind, prob->C, prob->y, prob->cost_scale,
+                     P<double>(ctx->rowpart2), rp.grid,
                      scal, st));
     CKS(read_scal(ctx));
     const double cmax = ctx->host_scal[SC_CMAX];

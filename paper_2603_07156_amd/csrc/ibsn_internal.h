@@ -24,8 +24,11 @@ bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *plan);
 RowPlan heavy_plan(const RowPlan &p);
 
 struct DenseArgs {
-    const void *C;
+    const void *C;            // the cost, or x (m x pdim) for points
     int64_t ldc;
+    const double *py;         // points: y (n x pdim)
+    double pscale;            // points: cost scale
+    int pdim;                 // points: 2 or 3
     int64_t m, n;
     int cost_kind;
     double sigma;           // (k+1)/eta

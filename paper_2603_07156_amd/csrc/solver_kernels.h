@@ -25,8 +25,9 @@ hipError_t sk_sinkhorn_step(int64_t n, double eta, double q, const double *b, co
 hipError_t sk_wmax(int64_t n, const double *s, const double *gamma, double eta, double *scal,
                    hipStream_t st);
 // scal[SC_CMAX] = max |C| (part: G doubles of scratch)
-hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *C, double *part,
-                       int G, double *scal, hipStream_t st);
+hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *C,
+                       const double *py, double pscale, double *part, int G, double *scal,
+                       hipStream_t st);
 hipError_t sk_gamma_of(int64_t n, double eta, const double *w, const double *s, double *gamma,
                        hipStream_t st);
 hipError_t sk_center(int64_t n, double *gamma, hipStream_t st);

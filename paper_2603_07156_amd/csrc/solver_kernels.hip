@@ -107,8 +107,24 @@ __global__ __launch_bounds__(NT) void k_wmax(int n, const double *__restrict__ s
 }
 
 // per-workgroup max |C| over a block of rows -> part[g]
+__device__ __forceinline__ double cost_from_points(const double *__restrict__ x,
+                                                   const double *__restrict__ y, int dim,
+                                                   double scale, int64_t i, int64_t j)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        const double t = x[i * dim + k] - y[j * dim + k];
+        s = k == 0 ? t * t : s + t * t;
+    }
+    return s * scale;
+}
+
+// kind 2 (points): C is x (m x ldc), y and scale give the cost
 __global__ __launch_bounds__(256) void k_cost_max_part(int m, int n, int64_t ldc, int kind,
                                                        const void *__restrict__ C,
+                                                       const double *__restrict__ py,
+                                                       double pscale,
                                                        double *__restrict__ part)
 {
     __shared__ double lds[4];
@@ -117,8 +133,10 @@ __global__ __launch_bounds__(256) void k_cost_max_part(int m, int n, int64_t ldc
     double mx = 0.0;
     for (int i = i0; i < i1; ++i)
         for (int j = threadIdx.x; j < n; j += 256) {
-            const double c = kind == 1 ? (double)((const float *)C)[(int64_t)i * ldc + j]
-                                       : ((const double *)C)[(int64_t)i * ldc + j];
+            const double c =
+                kind == 2   ? cost_from_points((const double *)C, py, (int)ldc, pscale, i, j)
+                : kind == 1 ? (double)((const float *)C)[(int64_t)i * ldc + j]
+                            : ((const double *)C)[(int64_t)i * ldc + j];
             // a NaN or infinite entry makes the maximum +inf (fmax would drop a NaN)
             mx = fabs(c) <= 1.7976931348623157e308 ? fmax(mx, fabs(c)) : INFINITY;
         }
@@ -445,11 +463,12 @@ hipError_t sk_wmax(int64_t n, const double *s, const double *gamma, double eta, 
 {
     L1(k_wmax, (int)n, s, gamma, eta, scal);
 }
-hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *C, double *part,
-                       int G, double *scal, hipStream_t st)
+hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *C,
+                       const double *py, double pscale, double *part, int G, double *scal,
+                       hipStream_t st)
 {
     hipLaunchKernelGGL(k_cost_max_part, dim3(G), dim3(256), 0, st, (int)m, (int)n, ldc, kind, C,
-                       part);
+                       py, pscale, part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, st, G, 1, 0, part, 1.0, 0.0, -1, SC_CMAX,
                        1, scal);
     return hipGetLastError();

@@ -21,6 +21,7 @@ IBSN_OK = 0
 IBSN_WARN_MAXITER = 1
 IBSN_COST_F64 = 0
 IBSN_COST_F32 = 1
+IBSN_COST_POINTS = 2
 PREC_F64 = 0    # ibsn_precision
 PREC_MIXED = 1
 MAX_N_F64 = 10240
@@ -34,8 +35,9 @@ class IBSNError(RuntimeError):
 
 class _Problem(ct.Structure):
     _fields_ = [("m", ct.c_int64), ("n", ct.c_int64), ("cost_kind", ct.c_int32),
-                ("precision", ct.c_int32), ("C", ct.c_void_p), ("ldc", ct.c_int64), ("a", ct.c_void_p), ("b", ct.c_void_p),
-                ("eta", ct.c_double)]
+                ("precision", ct.c_int32), ("C", ct.c_void_p), ("ldc", ct.c_int64),
+                ("a", ct.c_void_p), ("b", ct.c_void_p), ("eta", ct.c_double),
+                ("y", ct.c_void_p), ("cost_scale", ct.c_double)]
 
 
 class _Center(ct.Structure):
@@ -200,13 +202,21 @@ class Context:
 @dataclass
 class Problem:
     """eq. (1) data on the device: C (m x n, float64 or float32, row-major), a, b, eta;
-    precision: PREC_F64 or PREC_MIXED (FP32 exponentials and sparse values, FP64 sums)."""
+    precision: PREC_F64 or PREC_MIXED (FP32 exponentials and sparse values, FP64 sums).
+    Points cost (no stored matrix): C = x (m x dim, float64), y (n x dim) and cost_scale,
+    C_ij = cost_scale * sum_d (x_id - y_jd)^2 (see Problem.from_points)."""
 
     C: torch.Tensor
     a: torch.Tensor
     b: torch.Tensor
     eta: float
     precision: int = 0
+    y: torch.Tensor | None = None
+    cost_scale: float = 0.0
+
+    @classmethod
+    def from_points(cls, x, y, a, b, eta, cost_scale, precision=0):
+        return cls(x, a, b, eta, precision, y, float(cost_scale))
 
     @property
     def m(self):
@@ -214,11 +224,24 @@ class Problem:
 
     @property
     def n(self):
-        return self.C.shape[1]
+        return self.C.shape[1] if self.y is None else self.y.shape[0]
 
     def raw(self):
         if self.C.dim() != 2 or self.C.stride(1) != 1:
             raise ValueError("C must be a row-major 2-D tensor")
+        if self.precision not in (PREC_F64, PREC_MIXED):
+            raise ValueError("precision must be PREC_F64 or PREC_MIXED")
+        if self.y is not None:
+            x, y = self.C, self.y
+            if (x.dtype != torch.float64 or y.dtype != torch.float64 or not x.is_contiguous()
+                    or not y.is_contiguous() or y.dim() != 2 or y.shape[1] != x.shape[1]):
+                raise ValueError("points: x (m x d) and y (n x d), contiguous float64")
+            dev = x.device
+            return _Problem(self.m, self.n, IBSN_COST_POINTS, int(self.precision),
+                            ct.c_void_p(x.data_ptr()), x.shape[1],
+                            _ptr(self.a, self.m, name="a", device=dev),
+                            _ptr(self.b, self.n, name="b", device=dev), float(self.eta),
+                            ct.c_void_p(y.data_ptr()), float(self.cost_scale))
         if self.C.dtype == torch.float64:
             kind = IBSN_COST_F64
         elif self.C.dtype == torch.float32:
@@ -228,8 +251,6 @@ class Problem:
         if not self.C.is_cuda:
             raise ValueError("C must be a device tensor")
         dev = self.C.device
-        if self.precision not in (PREC_F64, PREC_MIXED):
-            raise ValueError("precision must be PREC_F64 or PREC_MIXED")
         return _Problem(self.m, self.n, kind, int(self.precision), ct.c_void_p(self.C.data_ptr()),
                         self.C.stride(0),
                         _ptr(self.a, self.m, name="a", device=dev),

@@ -175,3 +175,27 @@ def grid_histogram_batch(count: int, seed: int, eta: float = 1e-2, lo: int = 64,
         C = sqdist_cost(xs, ys)
         out.append(Instance(C, a, b, eta, f"grid_batch_{t}_s{seed}", xs, ys))
     return out
+
+
+def points_cost(x: np.ndarray, y: np.ndarray, scale: float, block: int = 2048) -> np.ndarray:
+    """C_ij = scale * ((x_i1 - y_j1)^2 + (x_i2 - y_j2)^2 [+ (x_i3 - y_j3)^2]): the points cost
+    in the library's order of operations (differences, squares, sums left to right, then one
+    product with the scale; numpy fuses none of them), so that the oracle sees exactly the
+    matrix the kernels form."""
+    m = x.shape[0]
+    C = np.empty((m, y.shape[0]), dtype=np.float64)
+    for i0 in range(0, m, block):
+        i1 = min(m, i0 + block)
+        d = x[i0:i1, None, :] - y[None, :, :]
+        C[i0:i1] = (d * d).sum(-1)
+    C *= scale
+    return C
+
+
+def points_scale(x: np.ndarray, y: np.ndarray, block: int = 2048) -> float:
+    """1 / max_ij sum_d (x_id - y_jd)^2 (so that the points cost has maximum 1 up to rounding)."""
+    mx = 0.0
+    for i0 in range(0, x.shape[0], block):
+        d = x[i0:i0 + block, None, :] - y[None, :, :]
+        mx = max(mx, float((d * d).sum(-1).max()))
+    return 1.0 / mx
