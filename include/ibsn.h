@@ -110,7 +110,7 @@ typedef struct {
 } ibsn_problem;
 
 /* Implicit prox centre X^k (see above): device r (m), s (n), and the grid spacing
-   `quantum` (a power of two) of the potentials.  Every pass forms
+   `quantum` (a power of two, at least DBL_MIN) of the potentials.  Every pass forms
    w_j = grid(s_j + gamma_j/eta) with grid(v) = quantum * rint(v / quantum), keeps the row
    shifts M_i on the same grid, and evaluates x_ij = fma(-sigma, C_ij, w_j - M_i): the
    difference w_j - M_i is exact, so x_ij = theta_ij - M_i carries one rounding at its

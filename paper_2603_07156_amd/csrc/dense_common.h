@@ -48,13 +48,31 @@ __device__ __forceinline__ double comb(double x, double y)
         return fmin(x, y);
 }
 
-// Move a double across lanes with a DPP control (all 64 lanes active).
+// Move a double across lanes with a DPP control whose every lane has a source lane
+// (quad permutes, row rotations, mirrors; all 64 lanes active): no old value is kept.
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
+}
+
+// DPP row broadcast into the rows of ROWMASK; lanes of the other rows receive `id`.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_bcast(double v, double id)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(id), __double2loint(v), CTRL,
+                                               ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(id), __double2hiint(v), CTRL,
+                                               ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int OP>
+__device__ __forceinline__ constexpr double op_identity()
+{
+    return OP == OP_SUM ? 0.0 : (OP == OP_MAX ? -__builtin_huge_val() : __builtin_huge_val());
 }
 
 __device__ __forceinline__ double readlane_d(double v, int lane)
@@ -63,19 +81,37 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
                             __builtin_amdgcn_readlane(__double2loint(v), lane));
 }
 
-// Wave reduction without LDS: within each row of 16 lanes, DPP lane ^ 1 and lane ^ 2
-// (quad permutes), then rotations by 4 and 8; lane 16 r then holds row r's result, and
-// the four rows are combined in a fixed order.  Every lane returns the same value.
-// Call with all 64 lanes active.
+// Reduction within each row of 16 lanes: DPP lane ^ 1 and lane ^ 2 (quad permutes), then
+// rotations by 4 and 8; every lane of row r then holds row r's result.
 template <int OP>
-__device__ __forceinline__ double wave_red(double v)
+__device__ __forceinline__ double row_red(double v)
 {
     v = comb<OP>(v, dpp_mov<0xB1>(v));    // quad_perm [1,0,3,2]
     v = comb<OP>(v, dpp_mov<0x4E>(v));    // quad_perm [2,3,0,1]
     v = comb<OP>(v, dpp_mov<0x124>(v));   // row_ror:4
-    v = comb<OP>(v, dpp_mov<0x128>(v));   // row_ror:8
-    return comb<OP>(comb<OP>(readlane_d(v, 0), readlane_d(v, 16)),
-                    comb<OP>(readlane_d(v, 32), readlane_d(v, 48)));
+    return comb<OP>(v, dpp_mov<0x128>(v));   // row_ror:8
+}
+
+// Wave reduction without LDS: row_red, then row r += row r-1 for rows 1 and 3 (broadcast of
+// lane 15 of each row) and rows 2, 3 += lane 31; lane 63 then holds
+// (row2 + row3) + (row0 + row1).  Every lane returns that value.  Call with all 64 lanes
+// active.
+template <int OP>
+__device__ __forceinline__ double wave_red(double v)
+{
+    constexpr double id = op_identity<OP>();
+    v = row_red<OP>(v);
+    v = comb<OP>(v, dpp_bcast<0x142, 0xA>(v, id));   // row_bcast:15 into rows 1, 3
+    v = comb<OP>(v, dpp_bcast<0x143, 0xC>(v, id));   // row_bcast:31 into rows 2, 3
+    return readlane_d(v, 63);
+}
+
+// Reduction of the values of lanes 0..15 (the other lanes' values are ignored): row 0's
+// row_red, read from lane 0.  Used where at most 16 values (one per wave) are combined.
+template <int OP>
+__device__ __forceinline__ double row0_red(double v)
+{
+    return readlane_d(row_red<OP>(v), 0);
 }
 
 // Workgroup reduction of K values with per-slot operators.  `lds` holds two buffers of
@@ -199,7 +235,10 @@ __device__ __forceinline__ void stage_lds(const double *__restrict__ src, int n,
     __syncthreads();
 }
 
-__device__ __forceinline__ double grid(double v, double q) { return q * rint(v / q); }
+// grid(v) = q rint(v / q).  q is a power of two no smaller than the least normal double
+// (the API checks this), so 1/q is exact and v (1/q) is v / q rounded once, the same
+// value; the compiler hoists 1/q out of the row loops.
+__device__ __forceinline__ double grid(double v, double q) { return q * rint(v * (1.0 / q)); }
 
 // exp(x) for finite x <= 709, by table-driven argument reduction (P. T. P. Tang,
 // "Table-driven implementation of the exponential function in IEEE floating-point

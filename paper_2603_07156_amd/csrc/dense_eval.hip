@@ -74,10 +74,11 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
             pr[NW + wv] = sw;
         }
         __syncthreads();
+        static_assert(NW <= 16, "the wave pairs are combined within one row of lanes");
         const double mk = lane < NW ? pr[lane] : -INFINITY;
-        const double M = wave_red<OP_MAX>(mk);
+        const double M = row0_red<OP_MAX>(mk);
         const double term = lane < NW ? pr[NW + lane] * exp_tab(mk - M, etab) : 0.0;
-        const double S = wave_red<OP_SUM>(term);
+        const double S = row0_red<OP_SUM>(term);
         const double ai = rA[slot];
         const double sc = ai / S * exp_tab(mw - M, etab);   // a_i exp(m_w - M) / S
 #pragma unroll

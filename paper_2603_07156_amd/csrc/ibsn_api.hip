@@ -201,9 +201,10 @@ int check_center(ibsn_ctx *ctx, const ibsn_center *c)
     if (c->k < 0)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "center k=%lld < 0", (long long)c->k);
     int e = 0;
-    if (!(c->quantum > 0.0) || !std::isfinite(c->quantum) || std::frexp(c->quantum, &e) != 0.5)
-        return fail(ctx, IBSN_ERR_INVALID_ARG, "center quantum=%g must be a power of two",
-                    c->quantum);
+    if (!(c->quantum >= DBL_MIN) || !std::isfinite(c->quantum) ||
+        std::frexp(c->quantum, &e) != 0.5)
+        return fail(ctx, IBSN_ERR_INVALID_ARG,
+                    "center quantum=%g must be a normal power of two", c->quantum);
     return IBSN_OK;
 }
 
