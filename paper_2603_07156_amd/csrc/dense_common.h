@@ -141,6 +141,13 @@ struct BlockRed {
         if constexpr (sizeof...(REST) > 0)
             fold_all<I + 1, REST...>(v, buf);
     }
+    // a single reduction (at a kernel's end) uses only the first buffer: K*NW doubles
+    static constexpr int LDS1 = K * NW;
+    __device__ __forceinline__ static void run_once(double *v, double *lds)
+    {
+        int parity = 0;
+        run(v, lds, parity);
+    }
     __device__ __forceinline__ static void run(double *v, double *lds, int &parity)
     {
         double *buf = lds + parity * K * NW;
@@ -309,6 +316,52 @@ __device__ __forceinline__ void exp_table_init(double *etab)
     for (int j = threadIdx.x; j < EXP_TAB; j += blockDim.x)
         etab[j] = exp2((double)j * (1.0 / EXP_TAB));
     __syncthreads();
+}
+
+// log(x) for finite x > 0, table-driven after P. T. P. Tang, "Table-driven implementation
+// of the logarithm function in IEEE floating-point arithmetic", ACM TOMS 16(4), 1990, in
+// the variant with a tabulated reciprocal: x = 2^e f with f in [1/2, 1); the top six
+// fraction bits of f pick interval j, whose centre c_j has the stored reciprocal
+// v_j = RN(1/c_j) and the stored L_j = -log(v_j) (computed for the stored v_j, so the
+// rounding of 1/c_j costs nothing).  Then f v_j = 1 + r with r = fma(f, v_j, -1),
+// |r| <= 2^-7 (+ one rounding, relative 2^-53), and
+//   log x = e ln2 + L_j + log1p(r),
+// log1p(r) by its Taylor polynomial of degree 8 (remainder below r^9/9 < 2^-66).
+// Absolute error about one unit in the last place of max(|log x|, 1/2); subnormal x are
+// handled by the hardware frexp.  ltab[2j] = v_j, ltab[2j+1] = L_j, see log_table_init.
+constexpr int LOG_TAB = 64;
+constexpr double LOG_LN2_HI = 0x1.62e42fefa39efp-1;    // ln 2, rounded
+constexpr double LOG_LN2_LO = 0x1.abc9e3b39803fp-56;   // ln 2 - LOG_LN2_HI
+
+__device__ __forceinline__ double log_tab(double x, const double *__restrict__ ltab)
+{
+    const double f = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const int j = (__double2hiint(f) >> 14) & (LOG_TAB - 1);
+    const double2 t = reinterpret_cast<const double2 *>(ltab)[j];
+    const double r = fma(f, t.x, -1.0);
+    double q = fma(r, -1.0 / 8.0, 1.0 / 7.0);
+    q = fma(q, r, -1.0 / 6.0);
+    q = fma(q, r, 1.0 / 5.0);
+    q = fma(q, r, -1.0 / 4.0);
+    q = fma(q, r, 1.0 / 3.0);
+    q = fma(q, r, -0.5);
+    const double p = fma(r * r, q, r);                   // log1p(r)
+    const double ed = (double)e;
+    return fma(ed, LOG_LN2_HI, t.y) + fma(ed, LOG_LN2_LO, p);
+}
+
+// (v_j, L_j) for j < 64 into LDS (2 * LOG_TAB doubles, 16-byte aligned); the caller's
+// next barrier publishes it.  c_j = (1 + (j + 1/2)/64) / 2 is the centre of the j-th of the
+// 64 equal parts of [1/2, 1).
+__device__ __forceinline__ void log_table_init(double *ltab)
+{
+    for (int j = threadIdx.x; j < LOG_TAB; j += blockDim.x) {
+        const double c = 0.5 * (1.0 + ((double)j + 0.5) * (1.0 / LOG_TAB));
+        const double v = 1.0 / c;
+        ltab[2 * j] = v;
+        ltab[2 * j + 1] = -log(v);
+    }
 }
 
 // Slot e of a thread holds column col_of(e).  The tiles are chosen so that the first QF

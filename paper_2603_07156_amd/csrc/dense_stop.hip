@@ -110,15 +110,27 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
         [&](int i, int slot, const auto *cst) {
         const double Mi = rM[slot], ai = rA[slot], aS = ai / rS[slot];
         double red[3] = {0.0, INFINITY, INFINITY};
+        // column loads kept in the row loop and one entry ahead, as in pass 2b
+        const double *yv = y, *gv = gamma, *pv = psi;
+        asm volatile("" : "+s"(yv), "+s"(gv), "+s"(pv));
+        int jn = slot_col<QF, NT, VEC>(0, n);
+        double ny = yv[jn], ng = gv[jn], np = pv[jn];
 #pragma unroll 2
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
-            const int j = slot_col<QF, NT, VEC>(e, n);
+            const int j = jn;
+            const double yj = ny, gj = ng, pj = np;
+            if (e + 1 < E) {
+                jn = slot_col<QF, NT, VEC>(e + 1, n);
+                ny = yv[jn];
+                ng = gv[jn];
+                np = pv[jn];
+            }
             const double c = valid ? (double)cst[e] : 0.0;
             const double Xv = exp_tab(valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY, etab) * aS;
-            red[0] = fma(Xv, y[j], red[0]);
-            red[1] = fmin(red[1], valid ? c - gamma[j] : INFINITY);
-            red[2] = fmin(red[2], valid ? c - psi[j] : INFINITY);
+            red[0] = fma(Xv, yj, red[0]);
+            red[1] = fmin(red[1], valid ? c - gj : INFINITY);
+            red[2] = fmin(red[2], valid ? c - pj : INFINITY);
         }
         Red3::run(red, lds, parity);
         if (threadIdx.x == 0) {
@@ -156,16 +168,18 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
 {
     constexpr int E = Q * VEC;
     using RedEnd = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_SUM, OP_MIN, OP_SUM, OP_SUM>;
-    __shared__ double lds[RedEnd::LDS];
+    __shared__ double lds[RedEnd::LDS1];
     extern __shared__ double wl[];   // w staged in LDS (n doubles)
     int i0, i1;
     row_range(m, i0, i1);
     __shared__ double etab[EXP_TAB];
-    exp_table_init(etab);
+    __shared__ __align__(16) double ltab[2 * LOG_TAB];
+    log_table_init(ltab);
+    exp_table_init(etab);   // its barrier also publishes ltab
     stage_lds(w, n, wl);
-    // 16 rows per staged chunk: with an n-vector of 20000 doubles the static LDS must stay
-    // within 3.5 KB
-    constexpr int RC = 16;
+    // 8 rows per staged chunk: with an n-vector of 20000 doubles the static LDS (exp and log
+    // tables, reduction buffer, row scalars: 3328 bytes) must stay within 3.5 KB
+    constexpr int RC = 8;
     __shared__ double rM[RC], rS[RC], rA[RC], rZ[RC], rE[RC], rG[RC];
     double t_dphi = 0.0, t_cxh = 0.0, t_cx = 0.0, t_xu = 0.0, t_xhmin = INFINITY, t_xf = 0.0,
            t_cf = 0.0;
@@ -181,23 +195,38 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
         const double es = rE[slot] * inv_er1;   // rank-one factor e_r,i / ||e_r||_1
         const double zg = rG[slot];
         const double lr = log(ai) - log(rS[slot]);
+        // A thread's columns are the same in every row, so the compiler would hoist all
+        // of their y, e_c, gamma loads out of the row loop and spill them at this register
+        // budget.  The pointers are made opaque per row to keep the loads in the loop, and
+        // the values of entry e + 1 are loaded while entry e is computed.
+        const double *yv = y, *ecv = ec, *gv = gamma;
+        asm volatile("" : "+s"(yv), "+s"(ecv), "+s"(gv));
+        int jn = slot_col<QF, NT, VEC>(0, n);
+        double ny = yv[jn], nec = ecv[jn], ng = gv[jn];
 #pragma unroll 2
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
-            const int j = slot_col<QF, NT, VEC>(e, n);
+            const int j = jn;
+            const double yj = ny, ecj = nec, gj = ng;
+            if (e + 1 < E) {
+                jn = slot_col<QF, NT, VEC>(e + 1, n);
+                ny = yv[jn];
+                nec = ecv[jn];
+                ng = gv[jn];
+            }
             const double c = valid ? (double)cst[e] : 0.0;
             const double xa = valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY;
             const double Xv = exp_tab(xa, etab) * aS;
-            const double f = (zi * Xv) * y[j];
-            const double xh = valid ? fma(es, ec[j], f) : 0.0;
+            const double f = (zi * Xv) * yj;
+            const double xh = valid ? fma(es, ecj, f) : 0.0;
             const double lx = lr + xa;
             const bool pos = xh > 0.0;
-            const double lxh = log(pos ? xh : 1.0);
+            const double lxh = log_tab(pos ? xh : 1.0, ltab);
             t_dphi += pos ? (xh * (lxh - lx) - xh) + Xv : Xv;
             t_cxh = fma(c, xh, t_cxh);
             t_cx = fma(c, Xv, t_cx);
             t_xhmin = fmin(t_xhmin, valid ? xh : INFINITY);
-            t_xu = fma(Xv, (c - gamma[j]) - zg, t_xu);
+            t_xu = fma(Xv, (c - gj) - zg, t_xu);
             t_xf = fma(Xv, Xv, t_xf);
             t_cf = fma(c, c, t_cf);
             if (xhat && valid)
@@ -205,8 +234,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
         }
         });
     double fin[7] = {t_dphi, t_cxh, t_cx, t_xu, t_xhmin, t_xf, t_cf};
-    int p2 = 0;
-    RedEnd::run(fin, lds, p2);
+    RedEnd::run_once(fin, lds);
     if (threadIdx.x == 0) {
         double *o = rowpart + (int64_t)blockIdx.x * STOP2_NSLOT;
         o[STOP2_DPHI] = fin[0];
