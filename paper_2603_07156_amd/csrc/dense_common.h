@@ -106,6 +106,20 @@ __device__ __forceinline__ double wave_red(double v)
     return readlane_d(v, 63);
 }
 
+// Inclusive prefix sum over the 64 lanes (lane order): Hillis-Steele shifts by 1, 2, 4, 8
+// inside each row of 16 lanes (lanes without a source add 0), then row 1 and row 3 add
+// lane 15 of the row below (row broadcast), and rows 2, 3 add lane 31.  Integer, so exact.
+__device__ __forceinline__ int wave_scan_incl(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
 // Reduction of the values of lanes 0..15 (the other lanes' values are ignored): row 0's
 // row_red, read from lane 0.  Used where at most 16 values (one per wave) are combined.
 template <int OP>
@@ -140,6 +154,39 @@ struct BlockRed {
         v[I] = r;
         if constexpr (sizeof...(REST) > 0)
             fold_all<I + 1, REST...>(v, buf);
+    }
+    template <int NALL, int I, int OP, int... REST>
+    __device__ __forceinline__ static void fold_first(double *v, const double *buf)
+    {
+        if constexpr (I < NALL) {
+            double r = buf[I * NW];
+#pragma unroll
+            for (int k = 1; k < NW; ++k)
+                r = comb<OP>(r, buf[I * NW + k]);
+            v[I] = r;
+            if constexpr (sizeof...(REST) > 0)
+                fold_first<NALL, I + 1, REST...>(v, buf);
+        }
+    }
+    // As run, but only slots 0..NALL-1 are folded in every wave; the other slots are
+    // folded in wave 0 only (for thread 0) and are unspecified in the other waves.
+    template <int NALL>
+    __device__ __forceinline__ static void run_part(double *v, double *lds, int &parity)
+    {
+        double *buf = lds + parity * K * NW;
+        parity ^= 1;
+        wave_all<0, OPS...>(v);
+        const int w = threadIdx.x / WAVE;
+        if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                buf[k * NW + w] = v[k];
+        }
+        __syncthreads();
+        if (w == 0)
+            fold_all<0, OPS...>(v, buf);
+        else if constexpr (NALL > 0)
+            fold_first<NALL, 0, OPS...>(v, buf);
     }
     // a single reduction (at a kernel's end) uses only the first buffer: K*NW doubles
     static constexpr int LDS1 = K * NW;

@@ -7,9 +7,9 @@ namespace {
 // ---------------------------------------------------------------------------------
 // Algorithm 1.  p = exp(theta - M_i)/S_i; rows i != istar keep p >= rho and divide
 // by the kept sum; row istar is kept whole.  Compaction: per (slab q, wave) a ballot
-// per vector lane gives the wave's kept count and each lane's rank; the counts of all
-// (q, wave) segments, in column order, give each segment's base.  Entries go to the
-// row's slot [i*n, i*n + len_i) in ascending column order.
+// per vector lane gives the wave's kept count and each lane's rank; an exclusive scan of
+// the counts of all (q, wave) segments, in column order, gives each segment's base.
+// Entries go to the row's slot [i*n, i*n + len_i) in ascending column order.
 // MX (mixed precision): p from the FP32 exponential (the threshold test is taken on that
 // value, widened), kept values stored as FP32; sums stay FP64, and d = P~^T (a o P~ 1) for
 // the stored factor P~.
@@ -36,7 +36,6 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
     int i0, i1;
     row_range(m, i0, i1);
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const unsigned long long lt = (1ull << lane) - 1ull;
     extern __shared__ double wl[];   // w staged in LDS (n doubles)
     __shared__ double etab[EXP_TAB];
     __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH];
@@ -56,10 +55,16 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
         int *cn = cnt[i & 1];
         double red[1] = {0.0};
         unsigned long long keepbits = 0;
-        unsigned long long bal[E];
+        // per slab: this lane's rank among the wave's kept entries (lanes below, all
+        // vector slots) and the wave's kept count
+        int rank[Q], wcnt[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            rank[q] = 0;
+            wcnt[q] = 0;
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int j = col_of<NT, VEC>(e);
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
             const double xa = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - Mi);
             const double p = exp_pass<MX>(valid ? xa : -INFINITY, etab) * iS;
@@ -69,28 +74,35 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
                 keepbits |= 1ull << e;
                 red[0] += p;
             }
-            bal[e] = __ballot(keep);
+            const unsigned long long bal = __ballot(keep);
+            rank[e / VEC] += __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            wcnt[e / VEC] += __popcll(bal);
         }
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                int c = 0;
-#pragma unroll
-                for (int v = 0; v < VEC; ++v)
-                    c += __popcll(bal[q * VEC + v]);
-                cn[q * NW + wv] = c;
-            }
+            for (int q = 0; q < Q; ++q)
+                cn[q * NW + wv] = wcnt[q];
         }
         RedSum::run(red, lds, parity);   // its barrier also publishes cn[]
         const double ik = 1.0 / red[0];   // 1 / kept row sum
+        // exclusive scan of the Q*NW segment counts (column order), 64 per wave scan
+        constexpr int NSEG = Q * NW, NCH = (NSEG + WAVE - 1) / WAVE;
         int running = 0, base[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            for (int k = 0; k < NW; ++k) {
-                if (k == wv)
-                    base[q] = running;
-                running += cn[q * NW + k];
+        for (int c = 0; c < NCH; ++c) {
+            const int f = c * WAVE + lane;
+            const int v = f < NSEG ? cn[f] : 0;
+            const int inc = wave_scan_incl(v) + running;
+            const int exc = inc - v;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int fq = q * NW + wv;   // the same in all lanes of the wave
+                const int b = __builtin_amdgcn_ds_bpermute((fq & (WAVE - 1)) * 4, exc);
+                if (fq / WAVE == c)
+                    base[q] = b;
             }
+            running = __builtin_amdgcn_ds_bpermute((WAVE - 1) * 4, inc);
         }
         const double ai = rA[slot];
         double rs = 0.0;   // MX: sum of the row's stored values
@@ -98,10 +110,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
         xval_t<MX> *vrow = val + (int64_t)i * n;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            int before = 0;
-#pragma unroll
-            for (int v = 0; v < VEC; ++v)
-                before += __popcll(bal[q * VEC + v] & lt);
+            int before = rank[q];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
                 const int e = q * VEC + v;

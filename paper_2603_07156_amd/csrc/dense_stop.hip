@@ -132,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
             red[1] = fmin(red[1], valid ? c - gj : INFINITY);
             red[2] = fmin(red[2], valid ? c - pj : INFINITY);
         }
-        Red3::run(red, lds, parity);
+        Red3::template run_part<0>(red, lds, parity);   // used by thread 0 only
         if (threadIdx.x == 0) {
             er_row[i] = fmax(ai - rZ[slot] * red[0], 0.0);
             zg_row[i] = red[1];

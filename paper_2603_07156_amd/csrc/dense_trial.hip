@@ -52,26 +52,27 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         [&](int i) { stage_rows(i, i1, Mb, rM, a, rA, nullptr, nullptr); },
         [&](int i, int slot, const auto *xr) {
         const double Mi = rM[slot];
+        // slot 0 (Z) is needed by every thread, the others by thread 0 only
         double red[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const double q = exp_pass<MX>(fma(-sigma, (double)xr[e], wr[e] - Mi), etab);
             const double cv = cvl[slot_col<QF, NT, VEC>(e, n)];   // finite, and q = 0 on padding
-            red[0] += q;
+            red[1] += q;
             double qe;
             if constexpr (BIG) {
                 qe = q * cv;
             } else {
                 const double qf = q * cv;
-                red[1] += qf;
+                red[2] += qf;
                 qe = q + qf;
             }
-            red[2] += qe;
+            red[0] += qe;
             red[3] = fmax(red[3], qe);
             x[e] = (xval_t<MX>)qe;
         }
-        Red::run(red, lds, parity);
-        const double A = red[0], B = red[1], Z = red[2], mx = red[3];
+        Red::template run_part<1>(red, lds, parity);
+        const double Z = red[0], A = red[1], B = red[2], mx = red[3];
         const double ai = rA[slot];
         const double sc = ai / Z;
 #pragma unroll

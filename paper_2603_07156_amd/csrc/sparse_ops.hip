@@ -466,11 +466,12 @@ __device__ __forceinline__ double pair_dot(const int32_t *__restrict__ idx,
 }
 
 // dst[j] = beta * v[j] + r[j] (r null: dst[j] = v[j]) for j < len, 1024 threads, with
-// eight independent loads in flight per thread (a plain strided loop waits on each load)
+// sixteen independent loads in flight per thread (a plain strided loop waits on each
+// load): one round of loads for len <= 16384
 __device__ __forceinline__ void stage_vec(double *dst, const double *__restrict__ v,
                                           const double *__restrict__ r, double beta, int len)
 {
-    constexpr int U = 8;
+    constexpr int U = 16;
     for (int j0 = threadIdx.x; j0 < len; j0 += U * 1024) {
         double a[U], b[U];
 #pragma unroll

@@ -236,6 +236,27 @@ def test_sparsify_and_hvp(ib, ctx, rho_rule, k):
     gcsr.free()
 
 
+@pytest.mark.parametrize("n", [2000, 7000, 9500, 10240])
+def test_sparsify_compaction_tiles(ib, ctx, n):
+    """Kept-entry compaction on the wider tiles: the (slab, wave) segment bases come from
+    one (n <= 8192) or two (n > 8192: 80 segments) 64-lane scans; pattern, values and d
+    against the oracle."""
+    inst = W.gmm_points(n, 6, m=29)
+    r, s, kk, gamma = outer_state(inst, 3)
+    ctr, q = center(ib, inst, r, s, kk, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=kk, want_plan=True,
+                       q=q)
+    P = ev.plan / inst.a[:, None]
+    rho = 1e-5
+    pr = problem(ib, inst)
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=kk, q=q)
+    same, d = compare_patterns(gcsr, ocsr, P, rho, int(np.argmax(inst.a)))
+    assert same and gcsr.nnz == ocsr.nnz
+    np.testing.assert_allclose(d, ocsr.d, rtol=1e-12)
+    gcsr.free()
+
+
 def test_hvp_determinism_and_dense_row(ib, ctx):
     """Row i* is dense (n entries); repeated products are bitwise identical."""
     inst = W.gmm_points(2000, 4, m=1500)
