@@ -54,6 +54,8 @@ struct ibsn_ctx {
     DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
+    double *cg_host = nullptr;     // pinned, 2 * CG_NSLOT: CG state records, double-buffered
+    hipEvent_t cg_ev[2] = {nullptr, nullptr};
     ibsn_csr *solver_csr = nullptr;
     std::vector<ibsn_csr *> csrs;  // handles returned by ibsn_sparsify and not yet freed
     // solver state (grow-only, reused across ibsn_solve calls)
@@ -536,8 +538,12 @@ int run_hvp(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, doubl
 
 // CG for (H_rho + shift I) x = rhs from 0; result in ctx->cg_x; *iters on host.
 // Iterations are enqueued in chunks; after each chunk one small kernel records the
-// state and the host reads it.  The next chunk's length is the number of iterations the
-// residual's observed rate of decrease predicts are still needed.
+// state, which is copied to pinned host memory behind an event.  The next chunk is
+// enqueued before the host waits for the previous record, so the device does not idle
+// while the host reads it: the chunk's length is what the residual's observed rate of
+// decrease predicts is still needed beyond the iterations already queued.  Iterations
+// enqueued after CG has finished are no-ops on the device (they see the done flag and
+// carry the final state forward), so overshoot costs only their launches.
 int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double shift,
            const double *rhs, double tol, int maxit, int *iters)
 {
@@ -558,31 +564,53 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     const CsrView cv = csr_view(c);
     KTimer kt(ctx, IBSN_KT_CG);
     CKH(launch_cg_init(c->n, rhs, tol, maxit, s, st));
-    int launched = 0, chunk = 8;
-    double hs[CG_NSLOT];
-    double last_res = -1.0;
-    int last_at = 0;
-    for (;;) {
+    int launched = 0;
+    // outstanding state records, oldest first: host buffer index and iteration count
+    int pend_buf[2], pend_at[2], npend = 0, nextbuf = 0;
+    auto enqueue = [&](int chunk) -> int {
         for (int q = 0; q < chunk && launched < maxit; ++q, ++launched)
             CKH(launch_cg_iteration(g, cv, a, eta, shift, s, launched, st));
         CKH(launch_cg_check(g, s, launched, c->n, st));
-        CKH(hipMemcpyAsync(hs, s.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
-        CKH(hipStreamSynchronize(st));
-        const int slot = launched & 1;
-        if (hs[CG_DONE0 + slot] != 0.0 || launched >= maxit) {
+        double *h = ctx->cg_host + nextbuf * CG_NSLOT;
+        CKH(hipMemcpyAsync(h, s.scal, sizeof(double) * CG_NSLOT, hipMemcpyDeviceToHost, st));
+        CKH(hipEventRecord(ctx->cg_ev[nextbuf], st));
+        pend_buf[npend] = nextbuf;
+        pend_at[npend] = launched;
+        ++npend;
+        nextbuf ^= 1;
+        return IBSN_OK;
+    };
+    CKI(enqueue(8));
+    if (launched < maxit)
+        CKI(enqueue(8));
+    double last_res = -1.0;
+    int last_at = 0;
+    for (;;) {
+        const int b = pend_buf[0], at = pend_at[0];
+        pend_buf[0] = pend_buf[1];
+        pend_at[0] = pend_at[1];
+        --npend;
+        CKH(hipEventSynchronize(ctx->cg_ev[b]));
+        const double *hs = ctx->cg_host + b * CG_NSLOT;
+        const int slot = at & 1;
+        if (hs[CG_DONE0 + slot] != 0.0 || at >= maxit) {
             *iters = (int)hs[CG_IT0 + slot];
-            break;
+            break;   // a chunk still queued runs as no-ops
         }
         const double res = std::sqrt(hs[CG_RR0 + slot]);
-        int next = 8;
+        int need = 16;   // iterations still needed after `at` (no rate known yet: 16)
         if (last_res > 0.0 && res < last_res && res > tol && tol > 0.0) {
-            const double rate = std::log(res / last_res) / (double)(launched - last_at);
-            const double need = std::log(tol / res) / rate;
-            next = (int)std::ceil(need) + 1;
+            const double rate = std::log(res / last_res) / (double)(at - last_at);
+            need = (int)std::ceil(std::log(tol / res) / rate) + 1;
         }
-        chunk = std::max(2, std::min(next, 64));
         last_res = res;
-        last_at = launched;
+        last_at = at;
+        const int queued = (npend > 0 ? pend_at[npend - 1] : at) - at;
+        int more = need - queued;
+        if (npend == 0)
+            more = std::max(more, 2);   // nothing queued: keep going
+        if (more > 0 && launched < maxit)
+            CKI(enqueue(std::max(2, std::min(more, 64))));
     }
     return IBSN_OK;
 }
@@ -622,6 +650,12 @@ int ibsn_create(ibsn_ctx **out, int device, void *hip_stream)
         delete ctx;
         return IBSN_ERR_HIP;
     }
+    if (hipHostMalloc((void **)&ctx->cg_host, sizeof(double) * 2 * CG_NSLOT) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->cg_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->cg_ev[1], hipEventDisableTiming) != hipSuccess) {
+        ibsn_destroy(ctx);
+        return IBSN_ERR_HIP;
+    }
     *out = ctx;
     return IBSN_OK;
 }
@@ -658,6 +692,11 @@ void ibsn_destroy(ibsn_ctx *ctx)
         release(*b);
     if (ctx->host_scal)
         (void)hipHostFree(ctx->host_scal);
+    if (ctx->cg_host)
+        (void)hipHostFree(ctx->cg_host);
+    for (hipEvent_t e : ctx->cg_ev)
+        if (e)
+            (void)hipEventDestroy(e);
     drain_events(ctx);
     for (hipEvent_t e : ctx->ev_free)
         (void)hipEventDestroy(e);
