@@ -582,7 +582,7 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     };
     CKI(enqueue(8));
     if (launched < maxit)
-        CKI(enqueue(8));
+        CKI(enqueue(4));
     double last_res = -1.0;
     int last_at = 0;
     for (;;) {
@@ -598,7 +598,7 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
             break;   // a chunk still queued runs as no-ops
         }
         const double res = std::sqrt(hs[CG_RR0 + slot]);
-        int need = 16;   // iterations still needed after `at` (no rate known yet: 16)
+        int need = 8;   // iterations still needed after `at` (no rate known yet: 8)
         if (last_res > 0.0 && res < last_res && res > tol && tol > 0.0) {
             const double rate = std::log(res / last_res) / (double)(at - last_at);
             need = (int)std::ceil(std::log(tol / res) / rate) + 1;

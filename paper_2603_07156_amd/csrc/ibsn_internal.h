@@ -157,9 +157,11 @@ struct CgState {
     double *rr_part;               // CG_MAX_UPDGROUPS
     double *scal;                  // CG_NSLOT
 };
+// CG_FIN: the iteration at which the single-workgroup state kernel (two-kernel form)
+// finished CG and applied the last update itself; -1 otherwise.
 enum {
     CG_TOL = 0, CG_MAXIT, CG_BRK, CG_RR0, CG_RR1, CG_BETA0, CG_BETA1, CG_DONE0, CG_DONE1,
-    CG_IT0, CG_IT1, CG_NSLOT
+    CG_IT0, CG_IT1, CG_FIN, CG_NSLOT
 };
 hipError_t launch_cg_init(int64_t n, const double *rhs, double tol, int maxit, CgState &s,
                           hipStream_t st);

@@ -597,6 +597,12 @@ __device__ __forceinline__ bool cg_fused_update(int it, int n, double *__restric
         }
         return true;
     }
+    // The state kernel already finished iteration `it` (CG ended exactly where the host
+    // polled) and wrote x, r and slot cs; a row gather queued after that poll must not
+    // apply x += alpha p a second time.  The marker is written only by the state kernel,
+    // never by a workgroup of the kernel that reads it.
+    if (!write_if_done_only && scal[CG_FIN] == (double)it)
+        return true;
     double t = 0.0;
     for (int k = threadIdx.x; k < npap; k += NT)
         t += pap_part[k];
@@ -626,6 +632,8 @@ __device__ __forceinline__ bool cg_fused_update(int it, int n, double *__restric
         scal[CG_BETA0 + cs] = beta;
         scal[CG_IT0 + cs] = (double)(ok ? it : it - 1);
         scal[CG_DONE0 + cs] = done ? 1.0 : 0.0;
+        if (write_if_done_only && done)
+            scal[CG_FIN] = (double)it;
     }
     *beta_out = beta;
     return done;
@@ -824,6 +832,12 @@ __global__ __launch_bounds__(1024) void k_cg_init(int n, const double *__restric
         scal[CG_BETA0] = 0.0;
         scal[CG_IT0] = 0.0;
         scal[CG_DONE0] = (!(sqrt(s) > tol) || maxit <= 0) ? 1.0 : 0.0;
+        // slot 1 may hold the end of a previous solve
+        scal[CG_RR1] = s;
+        scal[CG_BETA1] = 0.0;
+        scal[CG_IT1] = 0.0;
+        scal[CG_DONE1] = 0.0;
+        scal[CG_FIN] = -1.0;
         scal[CG_RR1] = 0.0;
         scal[CG_BETA1] = 0.0;
         scal[CG_IT1] = 0.0;

@@ -326,13 +326,22 @@ def test_cg_three_kernel_path(ib, ctx):
     xo3, ito3 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 3)
     assert it3 == ito3 == 3
     np.testing.assert_allclose(host(x3), xo3, rtol=0, atol=1e-9 * np.abs(xo3).max())
+    # A cap inside the third queued chunk.  Unconverged iterates this far in are sensitive
+    # to rounding: with only the column order of this problem permuted, the oracle's own
+    # 17th iterate moves by 5e-7 of max|x|.  One iteration more or less moves it by about
+    # 4%, so a bound of 1e-5 tells a wrong iteration count from rounding.
+    x17, it17 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 17)
+    xo17, ito17 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 17)
+    assert it17 == ito17 == 17
+    np.testing.assert_allclose(host(x17), xo17, rtol=0, atol=1e-5 * np.abs(xo17).max())
     gcsr.free()
 
 
-@pytest.mark.parametrize("maxit", [1, 2, 5, 9])
+@pytest.mark.parametrize("maxit", [1, 2, 5, 9, 13])
 def test_cg_two_kernel_iterates(ib, ctx, maxit):
     """The folded update (n <= 4096) gives the same iterate as the oracle's CG after each
-    number of iterations, across the host's chunk boundaries."""
+    number of iterations, across the host's chunk boundaries (chunks of 8 and 4 are queued
+    before the first state record is read)."""
     inst = W.gmm_points(600, 8, m=420)
     r, s, k, gamma = outer_state(inst, 0)
     ctr, q = center(ib, inst, r, s, k, gamma)
@@ -344,8 +353,49 @@ def test_cg_two_kernel_iterates(ib, ctx, maxit):
     xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, maxit)
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, maxit)
     assert itg == ito == maxit
-    # rounding of different summation orders, amplified by CG up to ~cond = 5000 here
-    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    # Rounding of different summation orders, amplified by CG (cond ~5000 here).  With only
+    # the column order permuted, the oracle's own iterate moves by < 1e-11 of max|x| up to
+    # 9 iterations and by 3e-9 at 13.  One iteration more or less moves the 13th iterate by
+    # about 9%.
+    rel = 1e-9 if maxit <= 9 else 1e-6
+    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=rel * np.abs(xo).max())
+    gcsr.free()
+
+
+@pytest.mark.parametrize("n,stop_at", [(600, 8), (600, 12), (5000, 8), (5000, 12)])
+def test_cg_converges_at_chunk_end(ib, ctx, n, stop_at):
+    """CG that reaches its tolerance exactly where the host polls (after the first chunk of
+    8 or the second of 4, with more iterations already queued behind the poll): the
+    iterations queued after convergence must leave x alone.  The shift (1.0: condition
+    number ~10) makes the residual fall by 0.3-0.6 per iteration, and the tolerance is set
+    at the geometric mean of the oracle's residual norms after stop_at - 1 and stop_at
+    iterations.  n = 600 runs the two-kernel iteration, n = 5000 the three-kernel one."""
+    m = 420 if n == 600 else 300
+    inst = W.gmm_points(n, 8 if n == 600 else 23, m=m)
+    r, s, k, gamma = outer_state(inst, 0)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    pr = problem(ib, inst)
+    rho = 1e-6 if n == 600 else inst.eta * np.linalg.norm(ev.g) / (m * n)
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
+    shift = 1.0
+    rhs = -ev.g
+
+    def resid(x):
+        return np.linalg.norm(rhs - orc.hvp(ocsr, inst.a, inst.eta, shift, x))
+
+    xa, _ = orc.cg(ocsr, inst.a, inst.eta, shift, rhs, 0.0, stop_at - 1)
+    xb, _ = orc.cg(ocsr, inst.a, inst.eta, shift, rhs, 0.0, stop_at)
+    ra, rb = resid(xa), resid(xb)
+    assert rb < 0.7 * ra, (ra, rb)
+    tol = np.sqrt(ra * rb)
+    xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, rhs, tol, 100)
+    assert ito == stop_at
+    for _ in range(2):   # the second solve starts from a context whose CG just ended
+        xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(rhs), tol, 100)
+        assert itg == stop_at
+        np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
     gcsr.free()
 
 
