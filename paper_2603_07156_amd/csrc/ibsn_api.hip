@@ -982,6 +982,8 @@ int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, c
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
     CKH(sk_dot_slot(prob->m, prob->a, nullptr, SC_SUMA, P<double>(ctx->scal), ctx->stream));
+    CKH(sk_dot_slot(prob->m, prob->a, prob->a, SC_AA, P<double>(ctx->scal), ctx->stream));
+    CKH(sk_dot_slot(prob->n, prob->b, prob->b, SC_BB, P<double>(ctx->scal), ctx->stream));
     CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
                       ctx->stream));
     CKI(run_stop(ctx, prob, rp, ctr->k, ctr->quantum, gamma, M, S, xhat));
@@ -1067,8 +1069,10 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     double *ct = P<double>(ctB), *gt = P<double>(gtB), *Delta = P<double>(DB);
     double *scal = P<double>(ctx->scal);
 
-    // problem checks and per-problem scalars (istar, sums)
+    // problem checks and per-problem scalars (istar, sums, a^T a and b^T b)
     CKSH(sk_problem_scalars(m, n, prob->a, prob->b, scal, P<int>(csr->istar_dev), st));
+    CKSH(sk_dot_slot(m, prob->a, prob->a, SC_AA, scal, st));
+    CKSH(sk_dot_slot(n, prob->b, prob->b, SC_BB, scal, st));
     CKS(read_scal(ctx));
     {
         const double *h = ctx->host_scal;
@@ -1116,11 +1120,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     // the state comes from FP64 passes (an FP64 eval refreshes a state left by a mixed pass).
     const bool mx_on = prob->precision == IBSN_PREC_MIXED;
     double mx_thr = INFINITY;
-    if (mx_on) {
-        CKSH(sk_dot_slot(n, prob->b, prob->b, SC_BB, scal, st));
-        CKS(read_scal(ctx));
+    if (mx_on)
         mx_thr = opt.mixed_switch * (double)FLT_EPSILON * std::sqrt(ctx->host_scal[SC_BB]);
-    }
 
     ibsn_report R;
     memset(&R, 0, sizeof(R));

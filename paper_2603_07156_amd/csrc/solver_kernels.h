@@ -15,7 +15,8 @@ enum {
     SC_SUMA, SC_SUMB, SC_MINA, SC_MINB, SC_BAD, SC_ISTAR,
     SC_NNZ,                                 // (as double) nnz of the last factor
     SC_WMAX, SC_CMAX, SC_TB,                // max|s+gamma/eta|, max|C|, b^T tau
-    SC_BB,                                  // b^T b (mixed-precision switch)
+    SC_BB,                                  // b^T b (mixed-precision switch, Delta_kkt)
+    SC_AA,                                  // a^T a (Delta_kkt)
     SC_NSLOT = 32
 };
 

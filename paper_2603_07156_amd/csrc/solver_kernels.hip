@@ -280,7 +280,10 @@ __global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const dou
     }
 }
 
-// Certificate and KKT finalisation into out[10] (see ibsn_stop in ibsn.h).
+// Certificate and KKT finalisation into out[10] (see ibsn_stop in ibsn.h).  ||a||^2 and
+// ||b||^2 come from scal[SC_AA], scal[SC_BB].  All the sums are reduced together: one
+// shuffle reduction per value in each wave, one exchange through LDS, then thread 0 adds
+// the waves' values in wave order.
 __global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restrict__ part, int m,
                                                    const double *__restrict__ a, int n,
                                                    const double *__restrict__ b,
@@ -288,10 +291,11 @@ __global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restri
                                                    double *__restrict__ scal,
                                                    double *__restrict__ out)
 {
-    __shared__ double lds[NW];
-    double v[STOP2_NSLOT];
+    constexpr int K = STOP2_NSLOT + 1;   // the stop-pass slots, then the row residual
+    __shared__ double lds[K * NW];
+    double v[K];
 #pragma unroll
-    for (int k = 0; k < STOP2_NSLOT; ++k)
+    for (int k = 0; k < K; ++k)
         v[k] = (k == STOP2_XHMIN) ? INFINITY : 0.0;
     for (int g = threadIdx.x; g < G; g += NT) {
         const double *p = part + (int64_t)g * STOP2_NSLOT;
@@ -299,21 +303,33 @@ __global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restri
         for (int k = 0; k < STOP2_NSLOT; ++k)
             v[k] = (k == STOP2_XHMIN) ? fmin(v[k], p[k]) : v[k] + p[k];
     }
-#pragma unroll
-    for (int k = 0; k < STOP2_NSLOT; ++k)
-        v[k] = (k == STOP2_XHMIN) ? wg_red<2>(v[k], lds) : wg_red<0>(v[k], lds);
-    double rr = 0.0;
     for (int g = threadIdx.x; g < G1; g += NT)
-        rr += rowres_part[g];
-    rr = wg_red<0>(rr, lds);
-    double na = 0.0, nb = 0.0;
-    for (int i = threadIdx.x; i < m; i += NT)
-        na = fma(a[i], a[i], na);
-    for (int j = threadIdx.x; j < n; j += NT)
-        nb = fma(b[j], b[j], nb);
-    na = wg_red<0>(na, lds);
-    nb = wg_red<0>(nb, lds);
+        v[STOP2_NSLOT] += rowres_part[g];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const double t = __shfl_xor(v[k], o, WAVE);
+            v[k] = (k == STOP2_XHMIN) ? fmin(v[k], t) : v[k] + t;
+        }
+    }
+    const int wv = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            lds[k * NW + wv] = v[k];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double r = lds[k * NW];
+            for (int w = 1; w < NW; ++w)
+                r = (k == STOP2_XHMIN) ? fmin(r, lds[k * NW + w]) : r + lds[k * NW + w];
+            v[k] = r;
+        }
+        const double rr = v[STOP2_NSLOT];
+        const double na = scal[SC_AA], nb = scal[SC_BB];
         const double dual_g = v[STOP2_AZG] + scal[SC_BG];
         const double dual_p = v[STOP2_AZP] + scal[SC_BP];
         double dp = fmax(sqrt(rr) / (1.0 + sqrt(na)), sqrt(scal[SC_COLRES]) / (1.0 + sqrt(nb)));
