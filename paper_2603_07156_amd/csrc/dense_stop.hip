@@ -162,7 +162,8 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
                                                const double *__restrict__ ec,
                                                const double *__restrict__ z,
                                                const double *__restrict__ er_row,
-                                               const double *__restrict__ zg_row, double er1,
+                                               const double *__restrict__ zg_row,
+                                               const double *__restrict__ er1p,
                                                double *__restrict__ xhat,
                                                double *__restrict__ rowpart)
 {
@@ -183,6 +184,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
     __shared__ double rM[RC], rS[RC], rA[RC], rZ[RC], rE[RC], rG[RC];
     double t_dphi = 0.0, t_cxh = 0.0, t_cx = 0.0, t_xu = 0.0, t_xhmin = INFINITY, t_xf = 0.0,
            t_cf = 0.0;
+    const double er1 = *er1p;   // written by the stop preparation kernel before this one
     const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
     row_loop<NT, Q, QF, VEC, false, RC>(
         C, ldc, py, pscale, n, i0, i1,

@@ -409,8 +409,6 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, p->n, colF, nullptr, nullptr, st));
     CKH(sk_stop_prep(p->n, d.sigma, p->b, d.w, gamma, colX, colF, P<double>(ctx->yv),
                      P<double>(ctx->ecv), P<double>(ctx->psiv), scal, st));
-    // er1 is needed as a kernel argument: read it back
-    CKI(read_scal(ctx));
     Stop2Vec v;
     v.gamma = gamma;
     v.psi = P<double>(ctx->psiv);
@@ -419,7 +417,7 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     v.z = P<double>(ctx->zv);
     v.er_row = P<double>(ctx->erv);
     v.zg_row = P<double>(ctx->zgv);
-    v.er1 = ctx->host_scal[SC_ER1];
+    v.er1 = scal + SC_ER1;   // read on the device: no host round trip
     {
         KTimer kt(ctx, IBSN_KT_STOP2);
         CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));

@@ -74,7 +74,7 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
 struct Stop2Vec {
     const double *gamma, *psi, *y, *ec, *z;   // n, n, n, n, m
     double *er_row, *zg_row;                  // m, m: e_r,i and min_j (C_ij - gamma_j)
-    double er1;                               // ||e_r||_1
+    const double *er1;                        // ||e_r||_1 (device scalar)
 };
 // rowpart[grid * 10]: per-workgroup sums (see STOP2_* slots).
 enum { STOP2_DPHI = 0, STOP2_CXH, STOP2_AZG, STOP2_AZP, STOP2_CX, STOP2_XU, STOP2_XHMIN,
