@@ -126,6 +126,38 @@ __global__ __launch_bounds__(256) void k_csc_blockscan(int n, int rb,
     colcnt[j] = run;
 }
 
+// Exclusive prefix sum of one value per thread over a 1024-thread workgroup: shuffle scan
+// inside each wave, then wave 0 scans the 16 wave totals.  *total receives the sum.
+// Integer, so the result does not depend on the order.
+__device__ __forceinline__ int64_t block_excl_scan_1024(int64_t v, int64_t *wtot, int64_t *total)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, WAVE);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == WAVE - 1)
+        wtot[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int64_t t = lane < 16 ? wtot[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int64_t y = __shfl_up(t, o, WAVE);
+            if (lane >= o)
+                t += y;
+        }
+        if (lane < 16)
+            wtot[lane] = t;   // inclusive totals of waves 0..lane
+    }
+    __syncthreads();
+    *total = wtot[15];
+    return (w > 0 ? wtot[w - 1] : 0) + x - v;
+}
+
 // exclusive scan of n counts into ptr[0..n], single workgroup of 1024 threads;
 // ptr[n] = total.  *total = ptr[n] plus the length of the dense row istar (held in the
 // row slots only), i.e. the number of stored entries of the factor.
@@ -134,30 +166,22 @@ __global__ __launch_bounds__(1024) void k_scan(int n, const int64_t *__restrict_
                                                const int32_t *__restrict__ len,
                                                const int *__restrict__ istar_p)
 {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t wtot[16];
     const int t = threadIdx.x;
     const int per = (n + 1023) / 1024;
     const int j0 = t * per, j1 = min(n, j0 + per);
     int64_t s = 0;
     for (int j = j0; j < j1; ++j)
         s += cnt[j];
-    part[t] = s;
-    __syncthreads();
+    int64_t all;
+    int64_t run = block_excl_scan_1024(s, wtot, &all);
     if (t == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int64_t v = part[k];
-            part[k] = run;
-            run += v;
-        }
-        ptr[n] = run;
+        ptr[n] = all;
         if (total) {
             const int istar = istar_p ? *istar_p : -1;
-            *total = run + (istar >= 0 ? (int64_t)len[istar] : 0);
+            *total = all + (istar >= 0 ? (int64_t)len[istar] : 0);
         }
     }
-    __syncthreads();
-    int64_t run = part[t];
     for (int j = j0; j < j1; ++j) {
         ptr[j] = run;
         run += cnt[j];
@@ -168,26 +192,17 @@ __global__ __launch_bounds__(1024) void k_scan(int n, const int64_t *__restrict_
 __global__ __launch_bounds__(1024) void k_scan32(int n, const int32_t *__restrict__ cnt,
                                                  int64_t *__restrict__ ptr)
 {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t wtot[16];
     const int t = threadIdx.x;
     const int per = (n + 1023) / 1024;
     const int j0 = t * per, j1 = min(n, j0 + per);
     int64_t s = 0;
     for (int j = j0; j < j1; ++j)
         s += cnt[j];
-    part[t] = s;
-    __syncthreads();
-    if (t == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int64_t v = part[k];
-            part[k] = run;
-            run += v;
-        }
-        ptr[n] = run;
-    }
-    __syncthreads();
-    int64_t run = part[t];
+    int64_t all;
+    int64_t run = block_excl_scan_1024(s, wtot, &all);
+    if (t == 0)
+        ptr[n] = all;
     for (int j = j0; j < j1; ++j) {
         ptr[j] = run;
         run += cnt[j];
