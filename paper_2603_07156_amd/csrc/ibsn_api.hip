@@ -422,8 +422,8 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
         KTimer kt(ctx, IBSN_KT_STOP2);
         CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));
     }
-    CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), p->m, p->a, p->n, p->b,
-                      P<double>(ctx->rowpart2), rp.grid, scal, P<double>(ctx->stopout), st));
+    CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), P<double>(ctx->rowpart2), rp.grid, scal,
+                      P<double>(ctx->stopout), st));
     return IBSN_OK;
 }
 

@@ -43,9 +43,9 @@ hipError_t sk_dot_slot(int64_t n, const double *x, const double *y, int slot, do
 hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *w,
                         const double *gamma, const double *colX, const double *colF, double *y,
                         double *ec, double *psi, double *scal, hipStream_t st);
-hipError_t sk_stop_final(int G, const double *part, int64_t m, const double *a, int64_t n,
-                         const double *b, const double *rowres_part, int G1, double *scal,
-                         double *out, hipStream_t st);
+// certificate and Delta_kkt from the stop passes' partials; needs scal[SC_AA], scal[SC_BB]
+hipError_t sk_stop_final(int G, const double *part, const double *rowres_part, int G1,
+                         double *scal, double *out, hipStream_t st);
 hipError_t sk_problem_scalars(int64_t m, int64_t n, const double *a, const double *b,
                               double *scal, int *istar, hipStream_t st);
 hipError_t sk_outer_update(int64_t m, int64_t n, const double *a, const double *M, const double *S,

@@ -284,9 +284,7 @@ __global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const dou
 // ||b||^2 come from scal[SC_AA], scal[SC_BB].  All the sums are reduced together: one
 // shuffle reduction per value in each wave, one exchange through LDS, then thread 0 adds
 // the waves' values in wave order.
-__global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restrict__ part, int m,
-                                                   const double *__restrict__ a, int n,
-                                                   const double *__restrict__ b,
+__global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restrict__ part,
                                                    const double *__restrict__ rowres_part, int G1,
                                                    double *__restrict__ scal,
                                                    double *__restrict__ out)
@@ -518,11 +516,10 @@ hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *
 {
     L1(k_stop_prep, (int)n, sigma, b, w, gamma, colX, colF, y, ec, psi, scal);
 }
-hipError_t sk_stop_final(int G, const double *part, int64_t m, const double *a, int64_t n,
-                         const double *b, const double *rowres_part, int G1, double *scal,
-                         double *out, hipStream_t st)
+hipError_t sk_stop_final(int G, const double *part, const double *rowres_part, int G1,
+                         double *scal, double *out, hipStream_t st)
 {
-    L1(k_stop_final, G, part, (int)m, a, (int)n, b, rowres_part, G1, scal, out);
+    L1(k_stop_final, G, part, rowres_part, G1, scal, out);
 }
 hipError_t sk_problem_scalars(int64_t m, int64_t n, const double *a, const double *b,
                               double *scal, int *istar, hipStream_t st)
