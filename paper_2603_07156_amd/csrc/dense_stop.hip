@@ -264,9 +264,11 @@ __global__ __launch_bounds__(NW *WAVE) void k_colreduce(const double *__restrict
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int j = blockIdx.x * WAVE + lane;
     double acc = 0.0;
-    if (j < n)
+    if (j < n) {
+#pragma unroll 8   // independent loads in flight; the additions keep their order
         for (int g = wv; g < G; g += NW)
             acc += part[(int64_t)g * n + j];
+    }
     s[wv][lane] = acc;
     __syncthreads();
     if (wv == 0 && j < n) {

@@ -184,6 +184,7 @@ __global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, 
 {
     __shared__ double lds[NW];
     double mx = -INFINITY, bt = 0.0;
+#pragma unroll 4   // one workgroup: keep several loads in flight per thread
     for (int j = threadIdx.x; j < n; j += NT) {
         const double v = grid(t * Delta[j] / eta, q);
         tau[j] = v;
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, 
     mx = wg_red<1>(mx, lds);
     bt = wg_red<0>(bt, lds);
     const bool big = mx > 500.0;
+#pragma unroll 4
     for (int j = threadIdx.x; j < n; j += NT) {
         const double v = tau[j];
         colv[j] = big ? exp(v - mx) : expm1(v);
@@ -255,6 +257,7 @@ __global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const dou
 {
     __shared__ double lds[NW];
     double syf = 0.0, cc = 0.0, bg = 0.0, bp = 0.0;
+#pragma unroll 4   // one workgroup: keep several loads in flight per thread
     for (int j = threadIdx.x; j < n; j += NT) {
         const double bj = b[j], cx = colX[j], cf = colF[j];
         const double yj = fmin(bj / cx, 1.0);
