@@ -51,6 +51,10 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
         C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows(i, i1, M, rM, S, rS, a, rA); },
         [&](int i, int slot, const auto *xr) {
         const double Mi = rM[slot], iS = 1.0 / rS[slot];
+        // an index offset the compiler cannot see through keeps the row-invariant LDS reads
+        // of w in the row loop (hoisted, they spill at this register budget)
+        int zo = 0;
+        asm volatile("" : "+v"(zo));
         const bool dense = (i == istar);
         int *cn = cnt[i & 1];
         double red[1] = {0.0};
@@ -66,7 +70,8 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
-            const double xa = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - Mi);
+            const double xa =
+                fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n) + zo] - Mi);
             const double p = exp_pass<MX>(valid ? xa : -INFINITY, etab) * iS;
             const bool keep = valid && (dense || p >= rho);
             x[e] = (xval_t<MX>)p;

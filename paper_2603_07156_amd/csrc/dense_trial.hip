@@ -52,12 +52,17 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         [&](int i) { stage_rows(i, i1, Mb, rM, a, rA, nullptr, nullptr); },
         [&](int i, int slot, const auto *xr) {
         const double Mi = rM[slot];
+        // The staged column values are the same for every row; an index offset the compiler
+        // cannot see through keeps their LDS reads in the row loop instead of hoisting them
+        // into registers (which spills at this register budget).
+        int zo = 0;
+        asm volatile("" : "+v"(zo));
         // slot 0 (Z) is needed by every thread, the others by thread 0 only
         double red[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const double q = exp_pass<MX>(fma(-sigma, (double)xr[e], wr[e] - Mi), etab);
-            const double cv = cvl[slot_col<QF, NT, VEC>(e, n)];   // finite, and q = 0 on padding
+            const double cv = cvl[slot_col<QF, NT, VEC>(e, n) + zo];   // finite; q = 0 on padding
             red[1] += q;
             double qe;
             if constexpr (BIG) {
