@@ -31,11 +31,15 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
     // lie on the grid, so m_w - M is exact.  The pair buffer alternates between rows.
     __shared__ double pairs[2][2 * NW];
     __shared__ double etab[EXP_TAB];
+    // log S_i for the row outputs, by thread 0: the table log keeps wave 0 from falling
+    // ~75 instructions (the library log) behind the other waves at every row's barrier
+    __shared__ __align__(16) double ltab[2 * LOG_TAB];
     extern __shared__ double wl[];   // w staged in LDS (n doubles)
     int parity = 0;
     int i0, i1;
     row_range(m, i0, i1);
-    exp_table_init(etab);
+    log_table_init(ltab);
+    exp_table_init(etab);   // its barrier also publishes ltab
     stage_lds(w, n, wl);
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     __shared__ double rA[ROWCH], rR[ROWCH];
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
             }
         }
         if (threadIdx.x == 0) {
-            const double ls = log(S);
+            const double ls = log_tab(S, ltab);
             Mo[i] = M;
             So[i] = S;
             if (lse)
