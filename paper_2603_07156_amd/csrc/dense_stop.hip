@@ -196,7 +196,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
         const double Mi = rM[slot], ai = rA[slot], zi = rZ[slot], aS = ai / rS[slot];
         const double es = rE[slot] * inv_er1;   // rank-one factor e_r,i / ||e_r||_1
         const double zg = rG[slot];
-        const double lr = log(ai) - log(rS[slot]);
+        const double lr = log_tab(ai, ltab) - log_tab(rS[slot], ltab);   // per row, all threads
         // A thread's columns are the same in every row, so the compiler would hoist all
         // of their y, e_c, gamma loads out of the row loop and spill them at this register
         // budget.  The pointers are made opaque per row to keep the loads in the loop, and
