@@ -104,6 +104,17 @@ def _declare(L):
                            _dp]
     L.orc_default_options.restype = None
     L.orc_default_options.argtypes = [ct.POINTER(Options)]
+    L.orc_plain_eval.restype = ct.c_int
+    L.orc_plain_eval.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, _dp, _dp,
+                                 _dp, _dp, _dp, _dp]
+    L.orc_plain_sparsify.restype = ct.c_int64
+    L.orc_plain_sparsify.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, dbl, i64,
+                                     i64, _i64p, _i32p, _dp, _dp]
+    L.orc_plain_stop.restype = ct.c_int
+    L.orc_plain_stop.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, _dp, _dp,
+                                 _dp, _dp, _dp, _dp]
+    L.orc_round.restype = None
+    L.orc_round.argtypes = [i64, i64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_solve.restype = ct.c_int
     L.orc_solve.argtypes = [i64, i64, vp, i32, i64, _dp, _dp, dbl, ct.POINTER(Options), _dp, _dp,
                             _dp, _i64p, _dp, ct.POINTER(Report), _dp, i64]
@@ -335,3 +346,85 @@ def solve(C, a, b, eta, gamma0=None, options: Options | None = None, want_plan=F
     if trace is not None:
         out["trace"] = trace[: min(trace_cap, rep.outer)]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Plain reference passes: the definitions with no potential grid (w = s + gamma/eta,
+# theta = fma(-sigma, C, w), M = max theta, S = sum exp(theta - M), P = exp(theta - M)/S).
+# ---------------------------------------------------------------------------
+@dataclass
+class PlainEval:
+    lse: np.ndarray
+    c: np.ndarray
+    g: np.ndarray
+    L: float | None
+    plan: np.ndarray | None
+
+
+def plain_eval(C, a, b, eta, gamma, r=None, s=None, k=0, want_plan=False) -> PlainEval:
+    """Eqs. (5)-(8) at (k, s, gamma) with the implicit centre; r = log a, s = log b default."""
+    C, kind = _cost(C)
+    m, n = C.shape
+    a, b, gamma = _f64(a), _f64(b), _f64(gamma)
+    r = np.log(a) if r is None else _f64(r)
+    s = np.log(b) if s is None else _f64(s)
+    lse, c, g = np.empty(m), np.empty(n), np.empty(n)
+    L = ct.c_double()
+    plan = np.empty((m, n)) if want_plan else None
+    rc = lib().orc_plain_eval(m, n, C.ctypes.data, kind, n, int(k), float(eta), _p(r), _p(s),
+                              _p(gamma), _p(a), _p(b), _p(lse), _p(c), _p(g), ct.byref(L),
+                              _p(plan))
+    assert rc == 0, rc
+    return PlainEval(lse, c, g, L.value, plan)
+
+
+def plain_sparsify(C, a, eta, gamma, rho, s, k=0, istar=None) -> CSR:
+    """Algorithm 1 on the plain P at (k, s, gamma)."""
+    C, kind = _cost(C)
+    m, n = C.shape
+    a, s, gamma = _f64(a), _f64(s), _f64(gamma)
+    istar = istar_of(a) if istar is None else int(istar)
+    row_ptr = np.empty(m + 1, dtype=np.int64)
+    need = lib().orc_plain_sparsify(m, n, C.ctypes.data, kind, n, int(k), float(eta), _p(s),
+                                    _p(gamma), _p(a), float(rho), istar, 0, _p(row_ptr), None,
+                                    None, None)
+    nnz = -need - 1
+    col = np.empty(max(nnz, 1), dtype=np.int32)
+    val = np.empty(max(nnz, 1))
+    d = np.empty(n)
+    got = lib().orc_plain_sparsify(m, n, C.ctypes.data, kind, n, int(k), float(eta), _p(s),
+                                   _p(gamma), _p(a), float(rho), istar, nnz, _p(row_ptr),
+                                   _p(col), _p(val), _p(d))
+    assert got == nnz
+    return CSR(m, n, row_ptr, col[:nnz], val[:nnz], d, istar)
+
+
+def plain_stop(C, a, b, eta, gamma, s, k=0, want_xhat=False, want_steps=False):
+    """Algorithm 3, D_phi and the certificate for the plain plan at (k, s, gamma).
+    want_steps: also return Algorithm 3's z, y, e_r, e_c."""
+    C, kind = _cost(C)
+    m, n = C.shape
+    a, b, gamma, s = map(_f64, (a, b, gamma, s))
+    out = np.empty(10)
+    xhat = np.empty((m, n)) if want_xhat else None
+    z, er = (np.empty(m), np.empty(m)) if want_steps else (None, None)
+    y, ec = (np.empty(n), np.empty(n)) if want_steps else (None, None)
+    rc = lib().orc_plain_stop(m, n, C.ctypes.data, kind, n, int(k), float(eta), _p(s),
+                              _p(gamma), _p(a), _p(b), _p(out), _p(xhat), _p(z), _p(y), _p(er),
+                              _p(ec))
+    assert rc == 0
+    res = dict(zip(STOP_FIELDS, out.tolist()))
+    if want_xhat:
+        res["xhat"] = xhat
+    if want_steps:
+        res.update(z=z, y=y, er=er, ec=ec)
+    return res
+
+
+def round_plan(X, a, b):
+    """Algorithm 3 on a nonnegative matrix X: returns (xhat, z, y, e_r, e_c)."""
+    X, a, b = map(_f64, (X, a, b))
+    m, n = X.shape
+    xhat, z, y, er, ec = np.empty((m, n)), np.empty(m), np.empty(n), np.empty(m), np.empty(n)
+    lib().orc_round(m, n, _p(X), _p(a), _p(b), _p(xhat), _p(z), _p(y), _p(er), _p(ec))
+    return xhat, z, y, er, ec

@@ -29,6 +29,13 @@
  * matters) instead of one at the scale of sigma.  Rounding a value v to the grid is
  * grid(v) = q * rint(v / q) (exact operations for a power-of-two q).
  *
+ * Two sets of passes.  The grid passes (orc_eval, orc_trial, orc_sparsify, orc_stop) follow
+ * the solver's exact-exponent scheme described here and drive orc_solve.  The plain passes
+ * at the end of the file (orc_plain_eval, orc_plain_sparsify, orc_plain_stop) take the same
+ * quantities straight from their definitions, with no grid; they are the reference that the
+ * grid scheme (here and in any other implementation) is held to, within the bound that the
+ * grid's rounding of w sets.
+ *
  * Row state.  A pair (M_i, S_i), M_i on the grid, represents
  *     P_ij = exp(x_ij) / S_i,   x_ij = fma(-sigma, C_ij, w_j - M_i),
  * which is eq. (7) with the common factor exp(-M_i) cancelled.  A fresh evaluation
@@ -442,41 +449,28 @@ int orc_cg(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col, con
 /* out[4] = Delta_kkt, out[5] = min Xhat, out[6] = ||e_r||_1, out[7] = <X,U>,        */
 /* out[8] = dual bound from gamma, out[9] = dual bound from psi.                      */
 /* ------------------------------------------------------------------------- */
-int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-             const double *w, const double *gamma, const double *a, const double *b,
-             const double *M, const double *S, double *out, double *xhat /* m*n or NULL */)
+/* Algorithm 3, steps 2-10, for a nonnegative X (m*n): z_i = min(a_i / sum_j X_ij, 1),
+   y_j = min(b_j / sum_i X_ij, 1) (the column sums of X itself, as the algorithm states),
+   F = diag(z) X diag(y), e_r = a - F 1, e_c = b - F^T 1.  colX (n) receives X^T 1.
+   Returns ||e_r||_1. */
+static double alg3_factors(int64_t m, int64_t n, const double *X, const double *a,
+                           const double *b, double *z, double *y, double *er, double *ec,
+                           double *colX)
 {
-    const double sigma = (double)(k + 1) / eta;
-    double *z = malloc(sizeof(double) * m), *er = malloc(sizeof(double) * m);
-    double *colX = calloc((size_t)n, sizeof(double)), *colF = calloc((size_t)n, sizeof(double));
-    double *y = malloc(sizeof(double) * n), *ec = malloc(sizeof(double) * n);
-    double *X = malloc(sizeof(double) * (size_t)m * n);
-    double *logX = malloc(sizeof(double) * (size_t)m * n);
-    double *zc = malloc(sizeof(double) * m);
-
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < m; ++i) {
-        double la = log(a[i]), ls = log(S[i]);
-        for (int64_t j = 0; j < n; ++j) {
-            double x = xval(C, kind, ldc, i, j, sigma, w, M[i]);
-            X[i * n + j] = a[i] * (exp(x) / S[i]);
-            logX[i * n + j] = la + x - ls;
-        }
-    }
-    /* Algorithm 3, steps 2-4: z_i = min(a_i / sum_j X_ij, 1) */
+    double *colF = calloc((size_t)n, sizeof(double));
     for (int64_t i = 0; i < m; ++i) {
         double rs = 0.0;
         for (int64_t j = 0; j < n; ++j)
             rs += X[i * n + j];
         z[i] = fmin(a[i] / rs, 1.0);
     }
-    /* steps 6-8: y_j = min(b_j / sum_i X_ij, 1) */
+    for (int64_t j = 0; j < n; ++j)
+        colX[j] = 0.0;
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < n; ++j)
             colX[j] += X[i * n + j];
     for (int64_t j = 0; j < n; ++j)
         y[j] = fmin(b[j] / colX[j], 1.0);
-    /* steps 5, 9: F = diag(z) X diag(y); step 10: e_r = a - F1, e_c = b - F^T 1 */
     double er1 = 0.0;
     for (int64_t i = 0; i < m; ++i) {
         double rs = 0.0;
@@ -491,6 +485,50 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     }
     for (int64_t j = 0; j < n; ++j)
         ec[j] = fmax(b[j] - colF[j], 0.0);
+    free(colF);
+    return er1;
+}
+
+/* Algorithm 3 on a nonnegative X (m*n): the feasible plan xhat = F + e_r e_c^T / ||e_r||_1
+   (F when ||e_r||_1 = 0).  z, y, er, ec (optional) receive the algorithm's vectors. */
+void orc_round(int64_t m, int64_t n, const double *X, const double *a, const double *b,
+               double *xhat, double *z_out, double *y_out, double *er_out, double *ec_out)
+{
+    double *z = malloc(sizeof(double) * m), *er = malloc(sizeof(double) * m);
+    double *y = malloc(sizeof(double) * n), *ec = malloc(sizeof(double) * n);
+    double *colX = malloc(sizeof(double) * n);
+    const double er1 = alg3_factors(m, n, X, a, b, z, y, er, ec, colX);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            const double f = z[i] * X[i * n + j] * y[j];
+            xhat[i * n + j] = er1 > 0.0 ? f + er[i] * ec[j] / er1 : f;
+        }
+    if (z_out)
+        memcpy(z_out, z, sizeof(double) * m);
+    if (y_out)
+        memcpy(y_out, y, sizeof(double) * n);
+    if (er_out)
+        memcpy(er_out, er, sizeof(double) * m);
+    if (ec_out)
+        memcpy(ec_out, ec, sizeof(double) * n);
+    free(z); free(er); free(y); free(ec); free(colX);
+}
+
+/* Algorithm 3 and the certificate for a plan given entry by entry: X (m*n) and its
+   logarithm logX (m*n, finite where X underflows), the dual vectors gamma and psi (n).
+   Optional outputs: xhat (m*n), and Algorithm 3's z (m), y (n), e_r (m), e_c (n). */
+static void stop_from_plan(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
+                           const double *X, const double *logX, const double *gamma,
+                           const double *psi, const double *a, const double *b, double *out,
+                           double *xhat, double *z_out, double *y_out, double *er_out,
+                           double *ec_out)
+{
+    double *z = malloc(sizeof(double) * m), *er = malloc(sizeof(double) * m);
+    double *colX = malloc(sizeof(double) * n);
+    double *y = malloc(sizeof(double) * n), *ec = malloc(sizeof(double) * n);
+    double *zc = malloc(sizeof(double) * m);
+    /* Algorithm 3, steps 2-10 */
+    const double er1 = alg3_factors(m, n, X, a, b, z, y, er, ec, colX);
 
     /* step 11 and the divergence / certificate sums (each row summed on its own, then the
        row totals: a single running sum over m*n terms loses accuracy at large m*n) */
@@ -527,9 +565,6 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
         xu += r_xu;
     }
     double dual_g = dot(m, a, zc) + dot(n, b, gamma);
-    double *psi = malloc(sizeof(double) * n);
-    for (int64_t j = 0; j < n; ++j)
-        psi[j] = (w[j] - log(b[j])) / sigma;
     double dual_p = 0.0;
     for (int64_t i = 0; i < m; ++i) {
         double zmin = INFINITY;
@@ -541,7 +576,6 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
         dual_p += a[i] * zmin;
     }
     dual_p += dot(n, b, psi);
-    free(psi);
     double dual = fmax(dual_g, dual_p);
 
     /* Delta_kkt (appendix C.1) for (X, gamma, zeta^c); U >= 0 by construction */
@@ -578,7 +612,40 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     out[7] = xu;
     out[8] = dual_g;
     out[9] = dual_p;
-    free(z); free(er); free(colX); free(colF); free(y); free(ec); free(X); free(logX); free(zc);
+    if (z_out)
+        memcpy(z_out, z, sizeof(double) * m);
+    if (y_out)
+        memcpy(y_out, y, sizeof(double) * n);
+    if (er_out)
+        memcpy(er_out, er, sizeof(double) * m);
+    if (ec_out)
+        memcpy(ec_out, ec, sizeof(double) * n);
+    free(z); free(er); free(colX); free(y); free(ec); free(zc);
+}
+
+int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
+             const double *w, const double *gamma, const double *a, const double *b,
+             const double *M, const double *S, double *out, double *xhat /* m*n or NULL */)
+{
+    const double sigma = (double)(k + 1) / eta;
+    double *X = malloc(sizeof(double) * (size_t)m * n);
+    double *logX = malloc(sizeof(double) * (size_t)m * n);
+    double *psi = malloc(sizeof(double) * n);
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double la = log(a[i]), ls = log(S[i]);
+        for (int64_t j = 0; j < n; ++j) {
+            double x = xval(C, kind, ldc, i, j, sigma, w, M[i]);
+            X[i * n + j] = a[i] * (exp(x) / S[i]);
+            logX[i * n + j] = la + x - ls;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        psi[j] = (w[j] - log(b[j])) / sigma;
+    stop_from_plan(m, n, C, kind, ldc, X, logX, gamma, psi, a, b, out, xhat, NULL, NULL, NULL,
+                   NULL);
+    free(X); free(logX); free(psi);
     return ORC_OK;
 }
 
@@ -872,4 +939,183 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
     free(St); free(ct); free(gt); free(Delta); free(rhs); free(tau); free(d); free(lb);
     free(row_ptr);
     return R.status;
+}
+
+/* ========================================================================= */
+/* Plain reference passes.  The same quantities as orc_eval, orc_sparsify and      */
+/* orc_stop, taken straight from their definitions with no potential grid:          */
+/*   w_j = s_j + gamma_j/eta,  theta_ij = fma(-sigma, C_ij, w_j),  sigma = (k+1)/eta  */
+/* (eq. (7) with the implicit centre log X^k_ij = r_i + s_j - k C_ij/eta: the row     */
+/* term r_i cancels in P), M_i = max_j theta_ij, S_i = sum_j exp(theta_ij - M_i),     */
+/* lse_i = M_i + log S_i (eq. (5) up to the row constant), and                        */
+/*   P_ij = exp(theta_ij - lse_i), evaluated as exp(theta_ij - M_i) / S_i,            */
+/* which is the same number in exact arithmetic and does not round lse_i at the       */
+/* scale of sigma.  These functions are the definition the HIP passes are held to;   */
+/* the grid functions above are the solver's own scheme and are held to these too.   */
+/* ========================================================================= */
+
+/* theta of row i at the plain potentials w; returns M_i and S_i */
+static void plain_row(const void *C, int kind, int64_t ldc, int64_t i, int64_t n, double sigma,
+                      const double *w, double *theta, double *Mi, double *Si)
+{
+    double mx = -INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+        theta[j] = fma(-sigma, cost_at(C, kind, ldc, i, j), w[j]);
+        if (theta[j] > mx)
+            mx = theta[j];
+    }
+    double sum = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        sum += exp(theta[j] - mx);
+    *Mi = mx;
+    *Si = sum;
+}
+
+static void plain_w(int64_t n, const double *s, const double *gamma, double eta, double *w)
+{
+    for (int64_t j = 0; j < n; ++j)
+        w[j] = s[j] + gamma[j] / eta;
+}
+
+/* Eval (eqs. (5)-(8)): lse (m), c = P^T a, g = c - b (n), L (eq. (6)), plan = diag(a) P.
+   r may be NULL (then L is not formed); lse and plan may be NULL. */
+int orc_plain_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
+                   double eta, const double *r, const double *s, const double *gamma,
+                   const double *a, const double *b, double *lse, double *c, double *g, double *L,
+                   double *plan)
+{
+    if (m < 1 || n < 1 || !(eta > 0))
+        return ORC_ERR_ARG;
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n);
+    double *Mv = malloc(sizeof(double) * m), *Sv = malloc(sizeof(double) * m);
+    plain_w(n, s, gamma, eta, w);
+    double *part = calloc((size_t)ORC_NCHUNK * n, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int qq = 0; qq < ORC_NCHUNK; ++qq) {
+        int64_t i0 = m * qq / ORC_NCHUNK, i1 = m * (qq + 1) / ORC_NCHUNK;
+        double *pc = part + (size_t)qq * n;
+        double *theta = malloc(sizeof(double) * n);
+        for (int64_t i = i0; i < i1; ++i) {
+            plain_row(C, kind, ldc, i, n, sigma, w, theta, &Mv[i], &Sv[i]);
+            for (int64_t j = 0; j < n; ++j) {
+                double p = exp(theta[j] - Mv[i]) / Sv[i];
+                pc[j] += a[i] * p;
+                if (plan)
+                    plan[i * n + j] = a[i] * p;
+            }
+        }
+        free(theta);
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int qq = 0; qq < ORC_NCHUNK; ++qq)
+            acc += part[(size_t)qq * n + j];
+        c[j] = acc;
+        g[j] = acc - b[j];
+    }
+    free(part);
+    if (lse)
+        for (int64_t i = 0; i < m; ++i)
+            lse[i] = Mv[i] + log(Sv[i]);
+    if (L && r) {
+        double t = 0.0;
+        for (int64_t i = 0; i < m; ++i)
+            t += a[i] * (r[i] + (Mv[i] + log(Sv[i])));
+        *L = -dot(n, b, gamma) + eta * t;
+    }
+    free(w); free(Mv); free(Sv);
+    return ORC_OK;
+}
+
+/* Algorithm 1 on the plain P at (k, s, gamma): rows i != istar keep P_ij >= rho and are
+   divided by their kept sum; row istar is kept whole.  CSR in row order, columns
+   ascending, d = P_rho^T a.  Returns nnz, or -(needed nnz) - 1 when cap is too small
+   (then only row_ptr is written). */
+int64_t orc_plain_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
+                           double eta, const double *s, const double *gamma, const double *a,
+                           double rho, int64_t istar, int64_t cap, int64_t *row_ptr, int32_t *col,
+                           double *val, double *d)
+{
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n);
+    plain_w(n, s, gamma, eta, w);
+    double *P = malloc(sizeof(double) * (size_t)m * n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double Mi, Si;
+        double *theta = P + (size_t)i * n;
+        plain_row(C, kind, ldc, i, n, sigma, w, theta, &Mi, &Si);
+        for (int64_t j = 0; j < n; ++j)
+            theta[j] = exp(theta[j] - Mi) / Si;
+    }
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (i == istar || P[(size_t)i * n + j] >= rho)
+                ++cnt;
+        row_ptr[i + 1] = row_ptr[i] + cnt;
+    }
+    int64_t nnz = row_ptr[m];
+    if (nnz > cap) {
+        free(w); free(P);
+        return -nnz - 1;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t o = row_ptr[i];
+        double kappa = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double p = P[(size_t)i * n + j];
+            if (i == istar || p >= rho) {
+                col[o] = (int32_t)j;
+                val[o] = p;
+                kappa += p;
+                ++o;
+            }
+        }
+        if (i != istar && kappa > 0.0)
+            for (int64_t e = row_ptr[i]; e < o; ++e)
+                val[e] = val[e] / kappa;
+    }
+    for (int64_t j = 0; j < n; ++j)
+        d[j] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            d[col[e]] += a[i] * val[e];
+    free(w); free(P);
+    return nnz;
+}
+
+/* Algorithm 3, D_phi(Xhat, X) (eq. (3), log domain) and the certificate of orc_stop for the
+   plain plan X = diag(a) P at (k, s, gamma); log X_ij = log a_i + (theta_ij - M_i) - log S_i;
+   psi_j = (w_j - log b_j)/sigma with the plain w.  Optional outputs: xhat (m*n), z, e_r (m),
+   y, e_c (n) of Algorithm 3. */
+int orc_plain_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
+                   double eta, const double *s, const double *gamma, const double *a,
+                   const double *b, double *out, double *xhat, double *z, double *y, double *er,
+                   double *ec)
+{
+    const double sigma = (double)(k + 1) / eta;
+    double *w = malloc(sizeof(double) * n), *psi = malloc(sizeof(double) * n);
+    double *X = malloc(sizeof(double) * (size_t)m * n);
+    double *logX = malloc(sizeof(double) * (size_t)m * n);
+    plain_w(n, s, gamma, eta, w);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double Mi, Si;
+        double *theta = X + (size_t)i * n;
+        plain_row(C, kind, ldc, i, n, sigma, w, theta, &Mi, &Si);
+        const double la = log(a[i]), ls = log(Si);
+        for (int64_t j = 0; j < n; ++j) {
+            const double x = theta[j] - Mi;
+            logX[(size_t)i * n + j] = la + x - ls;
+            theta[j] = a[i] * (exp(x) / Si);
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        psi[j] = (w[j] - log(b[j])) / sigma;
+    stop_from_plan(m, n, C, kind, ldc, X, logX, gamma, psi, a, b, out, xhat, z, y, er, ec);
+    free(w); free(psi); free(X); free(logX);
+    return ORC_OK;
 }
