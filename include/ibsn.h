@@ -83,7 +83,9 @@ typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1, IBSN_COST_POINTS = 2 } ibsn
    which the HVP widens to FP64; shifts, row sums, column sums, CG dot products and norms,
    the stop test with its rounding and certificate, and the objective stay FP64.  Results
    of the pass-level calls then carry relative errors of a few 1e-7 (S, c, g, plan, the
-   factor's values); ibsn_solve switches back to FP64 passes near convergence (see
+   factor's values).  An Armijo trial whose largest potential step t Delta_j / eta exceeds
+   80 runs in FP64 (its unshifted factors q e^tau could exceed the FP32 range).
+   ibsn_solve switches back to FP64 passes near convergence (see
    ibsn_options.mixed_switch), so its final iterate is held to FP64 accuracy. */
 typedef enum { IBSN_PREC_F64 = 0, IBSN_PREC_MIXED = 1 } ibsn_precision;
 

@@ -285,8 +285,10 @@ __global__ __launch_bounds__(NW *WAVE) void k_colreduce(const double *__restrict
 
 // Tiles (NT threads, Q vector slots per thread, QF slabs always inside the row).  Each
 // tile serves n in (previous capacity, NT*Q*VEC], so the first QF slabs are full for
-// every n it is chosen for.  Light tiles serve eval and stop pass 1; the heavy tile of the
-// same row serves trial, sparsify and stop pass 2, which keep more values live per
+// every n it is chosen for.  Light tiles serve eval and both stop passes (stop pass 2 is
+// split into 2a and 2b so that neither holds a row's values across a reduction; its
+// static LDS, with 8- and 32-row chunks of row scalars, is sized for the light tile); the
+// heavy tile of the same row serves trial and sparsify, which keep more values live per
 // entry; both run on the same grid.  1024-thread tiles keep 10 entries per thread at
 // n <= 10240 (FP64), which leaves room for four waves per SIMD.
 struct TileRow {

@@ -11,7 +11,10 @@ namespace {
 //   big step (BIG=1, cv = exp(tau - tau_shift)): qe = q*cv, delta = tau_shift + log(Z/A).
 //   Z = sum qe, P'_ij = qe / Z, new state M' = M + tau_shift + log(max qe), S' = Z / max qe.
 // MX (mixed precision): q from the FP32 exponential and qe held as FP32; cv, the sums
-// A, B, Z, the decrease and the new row state stay FP64.
+// A, B, Z, the decrease and the new row state stay FP64.  The mixed form only takes steps
+// with max tau <= 80 (q e^tau <= e^80 < FLT_MAX); larger steps go to the FP64 pass.
+// `flags` selects the steps a launch handles: bit f for scal[SC_BIG] == f (0: max tau <=
+// 80, 2: 80 < max tau <= 500, 1: larger, the shifted form).
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT, bool MX, int BIG>
 __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc,
@@ -24,7 +27,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
                                               const double *__restrict__ scal,
                                               double *__restrict__ Mn, double *__restrict__ Sn,
                                               double *__restrict__ colpart,
-                                              double *__restrict__ rowpart)
+                                              double *__restrict__ rowpart, int flags)
 {
     constexpr int E = Q * VEC;
     using Red = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_MAX>;
@@ -32,8 +35,8 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
     int parity = 0;
     int i0, i1;
     row_range(m, i0, i1);
-    if ((scal[SC_BIG] != 0.0) != (BIG != 0))
-        return;   // the other form of the trial handles this step
+    if (!((flags >> (int)scal[SC_BIG]) & 1))
+        return;   // another launch of the trial handles this step
     const double tau_shift = scal[SC_TAUSHIFT];
     extern __shared__ double cvl[];   // colv staged in LDS (n doubles)
     __shared__ double etab[EXP_TAB];
@@ -108,20 +111,27 @@ hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M
 {
     const RowPlan p = heavy_plan(p_in);
     const size_t lds_bytes = (size_t)d.n * sizeof(double);
+#define LAUNCH_TRIAL(MXV, BIGV, FLAGS, LC)                                                        \
+    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>, lds_bytes, LC); \
+        e_ != hipSuccess)                                                                         \
+        return e_;                                                                                \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, \
+                       d.a, M, colv, scal, M_new, S_new, colpart, rowpart, FLAGS)
+    // FP64: the small form for flags 0 and 2, the shifted form for flag 1.  Mixed: the FP32
+    // small form for flag 0 only; flags 2 and 1 run the FP64 forms.
 #define BODY                                                                                      \
-    static LdsCache lc_; \
-    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MX, 0>, lds_bytes, lc_); e_ != hipSuccess) \
-        return e_; \
-    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 0>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
-                       scal, M_new, S_new, colpart, rowpart);                                     \
-    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MX, 1>), dim3(p.grid), dim3(NT), lds_bytes, st,       \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, M, colv, \
-                       scal, M_new, S_new, colpart, rowpart)
+    static LdsCache lc0_, lc1_, lc2_;                                                             \
+    if constexpr (MX) {                                                                           \
+        LAUNCH_TRIAL(true, 0, 1, lc2_);                                                           \
+    }                                                                                             \
+    LAUNCH_TRIAL(false, 0, MX ? 4 : 5, lc0_);                                                     \
+    LAUNCH_TRIAL(false, 1, 2, lc1_)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)
 #undef X
 #undef BODY
+#undef LAUNCH_TRIAL
     return hipErrorInvalidValue;
 }
 

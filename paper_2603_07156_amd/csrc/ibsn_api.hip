@@ -1213,7 +1213,9 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                 CKS(read_scal(ctx));
                 const double gd = ctx->host_scal[SC_GD];
                 const double dL = ctx->host_scal[SC_DL];
-                if (std::isfinite(dL) && dL <= opt.sigma_armijo * t * gd) {
+                // a trial whose gradient is not finite is never accepted
+                if (std::isfinite(dL) && std::isfinite(ctx->host_scal[SC_GN]) &&
+                    dL <= opt.sigma_armijo * t * gd) {
                     accepted = true;
                     break;
                 }
@@ -1224,8 +1226,14 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             }
             R.backtracks += bt;
             if (!accepted && mxs) {
-                // the FP32 form could not certify a decrease: continue in FP64
+                // the FP32 form could not certify a decrease: continue in FP64.  The trials
+                // overwrote the norms of g; a mixed state is refreshed by an FP64 eval at the
+                // top of the loop, an FP64 state gets its own norms back here.
                 fp64_lock = true;
+                if (!state_mx) {
+                    CKSH(sk_gnorms(n, g, scal, st));
+                    CKS(read_scal(ctx));
+                }
                 R.t_linesearch += now_s() - ta;
                 continue;
             }

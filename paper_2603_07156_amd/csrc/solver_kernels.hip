@@ -175,6 +175,8 @@ __global__ __launch_bounds__(NT) void k_center(int n, double *__restrict__ gamma
 // Armijo step on the grid: tau_j = grid(t Delta_j / eta), so the trial point is w + tau
 // exactly.  Column factors: small step (max tau <= 500): colv = expm1(tau), shift 0;
 // big step: colv = exp(tau - max tau), shift = max tau.  scal[SC_TB] = b^T tau.
+// scal[SC_BIG] = 0 (max tau <= 80), 2 (80 < max tau <= 500: small form, but q e^tau can
+// exceed FLT_MAX, so the mixed form hands such a step to the FP64 pass) or 1 (big step).
 __global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, double q,
                                                    const double *__restrict__ Delta,
                                                    const double *__restrict__ b,
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, 
         colv[j] = big ? exp(v - mx) : expm1(v);
     }
     if (threadIdx.x == 0) {
-        scal[SC_BIG] = big ? 1.0 : 0.0;
+        scal[SC_BIG] = big ? 1.0 : (mx > 80.0 ? 2.0 : 0.0);
         scal[SC_TAUSHIFT] = big ? mx : 0.0;
         scal[SC_TB] = bt;
     }

@@ -154,6 +154,38 @@ def test_trial_mixed(ib, ctx, t):
     np.testing.assert_allclose(host(gt["g"]), gn, rtol=0, atol=6 * U * np.abs(cn).max())
 
 
+@pytest.mark.parametrize("scale", [0.04, 0.1])
+def test_trial_mixed_large_step(ib, ctx, scale):
+    """Steps with max tau = t Delta / eta in (89, 500]: the small form keeps q e^tau unshifted
+    there, which would overflow an FP32 value (e^89 > FLT_MAX), so the mixed trial hands
+    steps with max tau > 80 to the FP64 pass.  All outputs finite and within the error model
+    against the FP64 oracle."""
+    inst = W.gmm_points(300, 2, m=200)
+    inst = W.Instance(inst.C, inst.a, inst.b, 1e-3, "large_step")
+    r, s, k, gamma = np.log(inst.a), np.log(inst.b), 0, np.zeros(300)
+    ctr, q = center(ib, inst, r, s, 0, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, q=q)
+    Delta = W.random_dual(300, 7, scale)
+    tau_max = np.abs(Delta).max() / inst.eta
+    assert 89 < Delta.max() / inst.eta <= 500, Delta.max() / inst.eta
+    pr = mproblem(ib, inst)
+    gt = ib.trial(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(Delta), 1.0)
+    dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, inst.eta, gamma, ev.M, Delta, 1.0,
+                                        s=s, q=q)
+    for key in ("M", "S", "c", "g"):
+        assert torch.isfinite(gt[key]).all(), key
+    assert np.isfinite(gt["dL"])
+    bound = 4 * U * min(inst.eta, tau_max * inst.eta)
+    assert abs(gt["dL"] - dL) <= bound + 1e-12 * abs(dL), (gt["dL"], dL, bound)
+    np.testing.assert_allclose(host(gt["M"]) + np.log(host(gt["S"])), Mn + np.log(Sn), rtol=0,
+                               atol=4 * U)
+    # The small form's q e^tau = q + q expm1(tau) cancels for tau << 0 (both sides): columns
+    # whose steps are very negative carry an absolute error at the level of the unstepped
+    # column sum, far below max c.
+    np.testing.assert_allclose(host(gt["c"]), cn, rtol=6 * U, atol=1e-14 * np.abs(cn).max())
+    np.testing.assert_allclose(host(gt["g"]), gn, rtol=0, atol=6 * U * np.abs(cn).max())
+
+
 def exported_csr(gcsr, m, n):
     row_ptr, col, val, d = (host(x) for x in gcsr.export())
     return orc.CSR(m, n, row_ptr.astype(np.int64), col.astype(np.int32), val, d, gcsr.istar)

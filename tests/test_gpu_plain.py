@@ -1,0 +1,286 @@
+"""HIP passes against the oracle's plain passes (no potential grid), at k = 0, 60 and 2000.
+
+The plain passes take every quantity straight from its definition: w = s + gamma/eta,
+theta = fma(-sigma, C, w), M = max theta, S = sum exp(theta - M), P = exp(theta - M)/S
+(eq. (7)), the gradient and objective of eqs. (6) and (8), Algorithm 1 and Algorithm 3.
+The HIP passes keep w and the row shifts on a grid of spacing q (a power of two), so the
+two differ by the grid's rounding of w (at most q/2 per column) plus FP64 rounding at the
+scale of sigma on the plain side.  `dev_bound` states that deviation; every tolerance
+below is the larger of the parity bar (1e-9 absolute per plan entry, 1e-10 relative
+objective, identical pattern except within 1e-12 rho of the threshold) and that bound.
+With inputs whose w lies on the grid ("on-grid" cases) only the plain side's own rounding
+remains; it grows like sigma, and the bar itself holds at k = 0.
+
+States.  The potentials of a late outer iteration are concentrated: w_j = sigma psi_j with
+psi a c-concave column potential (two c-transforms), plus O(1) noise, so each row of P
+has a handful of entries above 1e-12 as in a converging solve.  k = 60 is also run from
+the oracle's own solver state.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2603_07156_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_2603_07156_amd import ibsn
+    return ibsn
+
+
+@pytest.fixture(scope="module")
+def ctx(ib):
+    return ib.Context(0)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def c_concave(C, rounds=2):
+    """Column potential psi after `rounds` pairs of c-transforms from psi = 0 (blocked)."""
+    m, n = C.shape
+    psi = np.zeros(n)
+    for _ in range(rounds):
+        zeta = np.empty(m)
+        for i0 in range(0, m, 1024):
+            zeta[i0:i0 + 1024] = (C[i0:i0 + 1024] - psi[None, :]).min(1)
+        psi = np.full(n, np.inf)
+        for i0 in range(0, m, 1024):
+            psi = np.minimum(psi, (C[i0:i0 + 1024] - zeta[i0:i0 + 1024, None]).min(0))
+    return psi
+
+
+def late_state(inst, k, seed, on_grid=False):
+    """(r, s, k, gamma) of a concentrated late state; on_grid: gamma = 0 and s on the grid
+    the solver uses for it, so that both sides see the same w."""
+    sigma = (k + 1) / inst.eta
+    rng = np.random.default_rng(seed)
+    w = sigma * c_concave(inst.C) + rng.standard_normal(inst.n)
+    r = np.log(inst.a)
+    if on_grid:
+        g0 = np.zeros(inst.n)
+        q = orc.center_quantum(inst.C, w, g0, inst.eta, k)
+        s = q * np.rint(w / q)
+        assert orc.center_quantum(inst.C, s, g0, inst.eta, k) == q
+        return r, s, k, g0
+    gamma = W.random_dual(inst.n, seed + 1, 0.02)
+    return r, w - gamma / inst.eta, k, gamma
+
+
+def oracle_state(inst, k):
+    opt = orc.default_options(max_outer=k, gap_tol=0.0, marg_tol=0.0)
+    res = orc.solve(inst.C, inst.a, inst.b, inst.eta, options=opt)
+    return res["r"], res["s"], res["k"], res["gamma"] + W.random_dual(inst.n, 3, 1e-4)
+
+
+def dev_bound(C, s, gamma, eta, k, q, on_grid):
+    """Bound on |x_gpu - x_plain| for one entry, x = theta - (row shift), where P matters
+    (|x| <= 1024).  B bounds |theta|.  The plain side rounds sigma (u sigma max C), theta
+    (u B) and theta - M (u |x|), and, off the grid, gamma/eta and s + gamma/eta (u each
+    at their size).  The grid side rounds s + gamma/eta the same way, then to the grid
+    (q/2), and x once (u |x|).  With w on the grid (gamma = 0, s a grid value) only the
+    plain side's sigma, theta and x roundings remain.  The row normaliser carries the same
+    error again, so P's relative deviation is below 2 dx + 1e-13 (exp and sums)."""
+    sigma = (k + 1) / eta
+    w = s + gamma / eta
+    B = sigma * np.abs(C).max() + np.abs(w).max()
+    dx = U * (sigma * np.abs(C).max() + B + 2 * 1024)
+    if not on_grid:
+        dx += 2 * U * (np.abs(w).max() + np.abs(gamma / eta).max()) + q / 2
+    return dx
+
+
+def problem(ib, inst):
+    return ib.Problem(dev(inst.C), dev(inst.a), dev(inst.b), inst.eta)
+
+
+def run_pair(ib, ctx, inst, state, on_grid, want_plan=True):
+    r, s, k, gamma = state
+    q = orc.center_quantum(inst.C, s, gamma, inst.eta, k)
+    ctr = ib.Center(k, dev(r), dev(s), q)
+    pr = problem(ib, inst)
+    gv = ib.subproblem_eval(ctx, pr, ctr, dev(gamma), want_obj=True, want_plan=want_plan)
+    pv = orc.plain_eval(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k,
+                        want_plan=want_plan)
+    dx = dev_bound(inst.C, s, gamma, inst.eta, k, q, on_grid)
+    return pr, ctr, gv, pv, dx, q
+
+
+def check_eval(ib, gv, pv, inst, state, dx, want_plan=True):
+    r, s, k, gamma = state
+    relP = 2 * dx + 1e-13
+    np.testing.assert_allclose(host(gv["lse"]), pv.lse, rtol=0,
+                               atol=dx + 4 * U * np.abs(pv.lse).max())
+    np.testing.assert_allclose(host(gv["c"]), pv.c, rtol=relP, atol=1e-300)
+    np.testing.assert_allclose(host(gv["g"]), pv.g, rtol=0, atol=relP * np.abs(pv.c).max())
+    scale = abs(inst.b @ gamma) + inst.eta * np.abs(inst.a * (r + pv.lse)).sum()
+    dL = abs(gv["L"] - pv.L)
+    assert dL <= 1e-10 * scale, (dL, scale)
+    assert dL <= inst.eta * (dx + 4 * U * np.abs(pv.lse).max()) + 1e-14 * scale, (dL, dx)
+    if want_plan:
+        Xg = host(gv["plan"])
+        assert np.abs(Xg - pv.plan).max() <= 1e-9
+        np.testing.assert_allclose(Xg, pv.plan, rtol=relP, atol=1e-300)
+
+
+KS = [0, 60, 2000]
+
+
+@pytest.mark.parametrize("on_grid", [False, True])
+@pytest.mark.parametrize("k", KS)
+def test_eval_vs_plain(ib, ctx, k, on_grid):
+    inst = W.gmm_points(600, 31, m=419)
+    state = late_state(inst, k, 7 + k, on_grid)
+    _, _, gv, pv, dx, q = run_pair(ib, ctx, inst, state, on_grid)
+    if on_grid and k == 0:
+        # at sigma = 100 the plain side's own rounding is inside the bar's relative 1e-12;
+        # it grows like sigma (4e-12 at k = 60, 1e-10 at k = 2000)
+        assert 2 * dx + 1e-13 <= 1e-12
+    check_eval(ib, gv, pv, inst, state, dx)
+
+
+def test_eval_vs_plain_oracle_state_k60(ib, ctx):
+    """k = 60 from the oracle solver's own outer state (not synthetic)."""
+    inst = W.uniform_points(200, 4, m=170)
+    state = oracle_state(inst, 60)
+    _, _, gv, pv, dx, q = run_pair(ib, ctx, inst, state, False)
+    check_eval(ib, gv, pv, inst, state, dx)
+
+
+_BIG = {}
+
+
+def big_instance():
+    if "inst" not in _BIG:
+        _BIG["inst"] = W.uniform_points(10000, 1000)
+    return _BIG["inst"]
+
+
+@pytest.mark.parametrize("k", [0, 60, 2000])
+def test_eval_vs_plain_10k(ib, ctx, k):
+    """10^4 x 10^4 in the benchmark's launch configuration (full outputs, no plan)."""
+    inst = big_instance()
+    state = late_state(inst, k, 11, on_grid=False)
+    _, _, gv, pv, dx, q = run_pair(ib, ctx, inst, state, False, want_plan=False)
+    check_eval(ib, gv, pv, inst, state, dx, want_plan=False)
+
+
+def compare_to_plain(gcsr, pcsr, Pplain, rho, relP):
+    """Pattern identical except within max(1e-12, relP) * rho of the threshold; values of
+    rows with the same pattern to 2 relP.  Returns the number of rows that differ."""
+    row_ptr, col, val, d = (host(x) for x in gcsr.export())
+    band = max(1e-12, relP) * rho
+    differ = 0
+    for i in range(len(row_ptr) - 1):
+        gc = col[row_ptr[i]:row_ptr[i + 1]]
+        pc = pcsr.col[pcsr.row_ptr[i]:pcsr.row_ptr[i + 1]]
+        if not np.array_equal(gc, pc):
+            differ += 1
+            diff = np.setxor1d(gc, pc)
+            assert np.all(np.abs(Pplain[i, diff] - rho) <= band), (i, diff)
+        else:
+            np.testing.assert_allclose(val[row_ptr[i]:row_ptr[i + 1]],
+                                       pcsr.val[pcsr.row_ptr[i]:pcsr.row_ptr[i + 1]],
+                                       rtol=2 * relP + 1e-14, atol=1e-300)
+    return differ, d
+
+
+@pytest.mark.parametrize("on_grid", [False, True])
+@pytest.mark.parametrize("k", KS)
+def test_sparsify_vs_plain(ib, ctx, k, on_grid):
+    inst = W.gmm_points(600, 31, m=419)
+    state = late_state(inst, k, 7 + k, on_grid)
+    r, s, kk, gamma = state
+    pr, ctr, gv, pv, dx, q = run_pair(ib, ctx, inst, state, on_grid)
+    relP = 2 * dx + 1e-13
+    Pplain = pv.plan / inst.a[:, None]
+    for rho in (inst.eta * np.linalg.norm(pv.g) / Pplain.size, 1e-9, 1e-5):
+        gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), gv["M"], gv["S"], rho)
+        pcsr = orc.plain_sparsify(inst.C, inst.a, inst.eta, gamma, rho, s, k=kk)
+        differ, d = compare_to_plain(gcsr, pcsr, Pplain, rho, relP)
+        # a row whose pattern differs moves d by at most its band entries' weight
+        atol = 4 * differ * (rho + relP) * inst.a.max() + 1e-300
+        np.testing.assert_allclose(d, pcsr.d, rtol=2 * relP + 1e-13, atol=atol)
+        gcsr.free()
+
+
+def test_sparsify_entries_exactly_at_rho(ib, ctx):
+    """Inclusive threshold (Algorithm 1): rows whose kept entries equal rho exactly.
+
+    C_ij is 0 or 10 and gamma = 0, so x_ij is 0 or -1000: exp gives exactly 1 or 0 and
+    P_ij = 1/n0_i or 0 on both sides, bit for bit, where n0_i is the row's count of zero
+    costs.  With rho = 1/N (as rounded), rows with n0 = N sit exactly at the threshold and
+    must be kept; rows with n0 > N fall below it and are emptied; rows with n0 < N are kept.
+    """
+    m, n, N = 40, 97, 8
+    rng = np.random.default_rng(5)
+    counts = np.concatenate([np.full(14, N), rng.integers(1, N, 13), rng.integers(N + 1, 30, 13)])
+    C = np.full((m, n), 10.0)
+    for i, c0 in enumerate(counts):
+        C[i, rng.choice(n, c0, replace=False)] = 0.0
+    a = np.full(m, 1.0 / m)
+    b = np.full(n, 1.0 / n)
+    a[3] *= 1.5   # i* = 3 is kept whole
+    a /= a.sum()
+    inst = W.Instance(C, a, b, 1e-2, "at_rho")
+    state = (np.log(a), np.zeros(n), 0, np.zeros(n))
+    pr, ctr, gv, pv, dx, q = run_pair(ib, ctx, inst, state, True)
+    np.testing.assert_array_equal(host(gv["S"]), counts.astype(float))
+    rho = 1.0 / N
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(np.zeros(n)), gv["M"], gv["S"], rho)
+    pcsr = orc.plain_sparsify(C, a, 1e-2, np.zeros(n), rho, np.zeros(n), k=0)
+    row_ptr, col, val, d = (host(x) for x in gcsr.export())
+    np.testing.assert_array_equal(row_ptr, pcsr.row_ptr)
+    np.testing.assert_array_equal(col, pcsr.col)
+    # the kept values are P / kappa: a product with 1/kappa on the GPU, a quotient here
+    np.testing.assert_allclose(val, pcsr.val, rtol=4 * U, atol=0)
+    lens = np.diff(row_ptr)
+    for i, c0 in enumerate(counts):
+        if i == 3:
+            assert lens[i] == n
+        elif c0 <= N:
+            assert lens[i] == c0, (i, c0, lens[i])
+        else:
+            assert lens[i] == 0, (i, c0, lens[i])
+    gcsr.free()
+
+
+@pytest.mark.parametrize("on_grid", [False, True])
+@pytest.mark.parametrize("k", KS)
+def test_stop_vs_plain(ib, ctx, k, on_grid):
+    inst = W.gmm_points(333, 6, m=250)
+    state = late_state(inst, k, 3 + k, on_grid)
+    r, s, kk, gamma = state
+    pr, ctr, gv, pv, dx, q = run_pair(ib, ctx, inst, state, on_grid, want_plan=False)
+    relP = 2 * dx + 1e-13
+    gs = ib.stop(ctx, pr, ctr, dev(gamma), gv["M"], gv["S"], want_xhat=True)
+    ps = orc.plain_stop(inst.C, inst.a, inst.b, inst.eta, gamma, s, k=kk, want_xhat=True)
+    Xg, Xp = host(gs["xhat"]), ps["xhat"]
+    assert np.abs(Xg - Xp).max() <= min(1e-9, 8 * relP * Xp.max() + 1e-18)
+    assert Xg.min() >= 0
+    np.testing.assert_allclose(Xg.sum(1), inst.a, atol=1e-15 * 333, rtol=0)
+    np.testing.assert_allclose(Xg.sum(0), inst.b, atol=1e-15 * 333, rtol=0)
+    tol_obj = max(4 * relP, 1e-13)
+    if k <= 60:
+        assert tol_obj <= 1e-10   # the parity bar for objectives
+    for key in ("primal", "cx"):
+        assert abs(gs[key] - ps[key]) <= tol_obj * abs(ps[key]), (key, gs[key], ps[key])
+    # the gamma bound reads gamma and C only; the psi bound moves with w by dx / sigma
+    sigma = (kk + 1) / inst.eta
+    assert abs(gs["dual_gamma"] - ps["dual_gamma"]) <= 1e-13 * abs(ps["dual_gamma"]) + 1e-16
+    assert abs(gs["dual_psi"] - ps["dual_psi"]) <= 2 * dx / sigma + 1e-13 * abs(ps["dual_psi"])
+    # D_phi, Delta_kkt and ||e_r||_1 are sums of small terms; each entry's term moves by at
+    # most a few relP times Xhat_ij, and sum Xhat = 1
+    for key in ("dphi", "er1", "kkt"):
+        assert abs(gs[key] - ps[key]) <= 1e-9 * abs(ps[key]) + 8 * relP, (key, gs[key], ps[key])
