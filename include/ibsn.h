@@ -124,6 +124,10 @@ typedef struct {
     double quantum;
 } ibsn_center;
 
+/* Initial prox centre X^0 = a b^T (Algorithm 2 input): r = log a (m), s = log b (n),
+   device outputs the caller owns; k = 0.  Asynchronous on the context's stream. */
+int ibsn_center_init(ibsn_ctx *ctx, const ibsn_problem *prob, double *r, double *s);
+
 /* Host out: the grid spacing for (prob, ctr.k, ctr.s, gamma) (see ibsn_center).
    Reads C once (max |C|).  Synchronises. */
 int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
@@ -222,6 +226,20 @@ typedef struct {
 int ibsn_kernel_timing(ibsn_ctx *ctx, int enable);
 int ibsn_kernel_times_get(ibsn_ctx *ctx, ibsn_kernel_times *out);
 
+/* One record per outer iteration of ibsn_solve (the per-iteration log): counts and times
+   are those of this outer iteration alone; the certificate fields are those of its final
+   stop pass.  Summed over the records of a solve, the counts and times equal the report's
+   totals (t_total aside, which also covers set-up). */
+typedef struct {
+    int64_t k;                                 /* index of the subproblem (prox centre X^k) */
+    int64_t newton, cg, sinkhorn, backtracks, stop_tests, passes, mixed_passes;
+    double grad_norm, primal, dual, rel_gap, kkt, dphi, marg_l1;
+    double nnz_mean;                           /* mean stored entries of its factors (0: none) */
+    double t_eval, t_sparsify, t_cg, t_linesearch, t_stop, t_total;   /* seconds */
+    int32_t inner_stopped;                     /* 1: the D_phi test (or (E)IBSN's ||g||) passed */
+    int32_t reserved;
+} ibsn_iter_record;
+
 /* Solver options; ibsn_default_options() fills the paper's values where it gives
    them (sigma, beta: Algorithm 2 input; Sinkhorn tolerance and mu_k schedule:
    Section 5 "Setup"; 300 outer iterations: Table 1). */
@@ -243,6 +261,9 @@ typedef struct {
                                          /*   passes while ||g||_2 >= mixed_switch *      */
                                          /*   FLT_EPSILON * ||b||_2 (64), and FP64 after   */
                                          /*   that or after an FP32 line search fails     */
+    ibsn_iter_record *trace;             /* host, optional (NULL): the first trace_cap outer */
+    int64_t trace_cap;                   /*   iterations' records; ibsn_report.trace_len     */
+                                         /*   says how many were written                     */
 } ibsn_options;
 
 void ibsn_default_options(ibsn_options *opt);
@@ -253,6 +274,7 @@ typedef struct {
     double t_eval, t_sparsify, t_cg, t_linesearch, t_stop, t_total;  /* seconds */
     double nnz_mean, nnz_last;  /* stored entries of the sparsified factors (mean, last) */
     int64_t mixed_passes;       /* m x n passes run in the FP32 form (IBSN_PREC_MIXED) */
+    int64_t trace_len;          /* records written to ibsn_options.trace */
     int32_t status;
 } ibsn_report;
 

@@ -756,6 +756,18 @@ void ibsn_default_options(ibsn_options *o)
     o->eot = 0;
     o->eot_tol = 1e-9;
     o->mixed_switch = 64.0;
+    o->trace = nullptr;
+    o->trace_cap = 0;
+}
+
+int ibsn_center_init(ibsn_ctx *ctx, const ibsn_problem *prob, double *r, double *s)
+{
+    CKI(check_problem(ctx, prob));
+    if (!r || !s)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "r and s are required");
+    CKH(hipSetDevice(ctx->device));
+    CKH(sk_init_center(prob->m, prob->n, prob->a, prob->b, r, s, ctx->stream));
+    return IBSN_OK;
 }
 
 int ibsn_center_quantum(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
@@ -1007,7 +1019,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     if (opt.max_outer < 1 || opt.max_newton < 1 || opt.max_backtrack < 0 ||
         !(opt.beta > 0 && opt.beta < 1) || !(opt.sigma_armijo > 0 && opt.sigma_armijo < 1) ||
         (opt.eot != 0 && opt.eot != 1) || (opt.eot && !(opt.eot_tol > 0)) ||
-        !(opt.mixed_switch >= 0))
+        !(opt.mixed_switch >= 0) || opt.trace_cap < 0 || (opt.trace_cap > 0 && !opt.trace))
         return fail(ctx, IBSN_ERR_INVALID_ARG, "invalid options");
     const bool resume = k_io && *k_io > 0;
     if (resume && (!r_io || !s_io))
@@ -1130,7 +1142,49 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     double stop_h[10] = {0};
     const int64_t k0 = k;
     const double mn = (double)m * (double)n;
+    // per-outer-iteration record: the report's counters at the start of the iteration
+    ibsn_report Rb;
+    double nnz_sum_b = 0.0;
+    int64_t nnz_calls_b = 0;
+    double t_iter = 0.0;
+    auto record = [&](bool inner_stopped) {
+        const int64_t idx = k - k0;
+        if (idx >= opt.trace_cap)
+            return;
+        ibsn_iter_record &T = opt.trace[idx];
+        memset(&T, 0, sizeof(T));
+        T.k = k;
+        T.newton = R.newton - Rb.newton;
+        T.cg = R.cg - Rb.cg;
+        T.sinkhorn = R.sinkhorn - Rb.sinkhorn;
+        T.backtracks = R.backtracks - Rb.backtracks;
+        T.stop_tests = R.stop_tests - Rb.stop_tests;
+        T.passes = R.passes - Rb.passes;
+        T.mixed_passes = R.mixed_passes - Rb.mixed_passes;
+        T.grad_norm = R.grad_norm;
+        T.primal = R.primal;
+        T.dual = R.dual;
+        T.rel_gap = R.rel_gap;
+        T.kkt = R.kkt;
+        T.dphi = R.dphi;
+        T.marg_l1 = R.marg_l1;
+        T.nnz_mean = nnz_calls > nnz_calls_b
+                         ? (nnz_sum - nnz_sum_b) / (double)(nnz_calls - nnz_calls_b)
+                         : 0.0;
+        T.t_eval = R.t_eval - Rb.t_eval;
+        T.t_sparsify = R.t_sparsify - Rb.t_sparsify;
+        T.t_cg = R.t_cg - Rb.t_cg;
+        T.t_linesearch = R.t_linesearch - Rb.t_linesearch;
+        T.t_stop = R.t_stop - Rb.t_stop;
+        T.t_total = now_s() - t_iter;
+        T.inner_stopped = inner_stopped ? 1 : 0;
+        R.trace_len = idx + 1;
+    };
     for (; k < k0 + opt.max_outer; ++k) {
+        Rb = R;
+        nnz_sum_b = nnz_sum;
+        nnz_calls_b = nnz_calls;
+        t_iter = now_s();
         const double mu = std::max(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
         const double sigma = (double)(k + 1) / eta;
         double ta = now_s();
@@ -1305,6 +1359,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                 R.passes += 2;
             }
             R.status = R.grad_norm < opt.eot_tol ? IBSN_OK : IBSN_WARN_MAXITER;
+            record(stopped);
             ++k;
             break;
         }
@@ -1314,6 +1369,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         }
         // step 13: X^{k+1} = X^{k,v+1}, i.e. r = log a - lse, s = w; k = k+1; gamma kept
         CKSH(sk_outer_update(m, n, prob->a, M, S, w, r, s, st));
+        record(stopped);
         if (done) {
             R.status = IBSN_OK;
             ++k;

@@ -55,7 +55,26 @@ class Options(ct.Structure):
         ("cg_maxit", ct.c_int32), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int32),
         ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int32),
         ("eot", ct.c_int32), ("eot_tol", ct.c_double), ("mixed_switch", ct.c_double),
+        ("trace", ct.c_void_p), ("trace_cap", ct.c_int64),
     ]
+
+
+class IterRecord(ct.Structure):
+    """ibsn_iter_record: one outer iteration of ibsn_solve."""
+    _fields_ = [
+        ("k", ct.c_int64), ("newton", ct.c_int64), ("cg", ct.c_int64), ("sinkhorn", ct.c_int64),
+        ("backtracks", ct.c_int64), ("stop_tests", ct.c_int64), ("passes", ct.c_int64),
+        ("mixed_passes", ct.c_int64),
+        ("grad_norm", ct.c_double), ("primal", ct.c_double), ("dual", ct.c_double),
+        ("rel_gap", ct.c_double), ("kkt", ct.c_double), ("dphi", ct.c_double),
+        ("marg_l1", ct.c_double), ("nnz_mean", ct.c_double),
+        ("t_eval", ct.c_double), ("t_sparsify", ct.c_double), ("t_cg", ct.c_double),
+        ("t_linesearch", ct.c_double), ("t_stop", ct.c_double), ("t_total", ct.c_double),
+        ("inner_stopped", ct.c_int32), ("reserved", ct.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class Report(ct.Structure):
@@ -69,7 +88,7 @@ class Report(ct.Structure):
         ("t_eval", ct.c_double), ("t_sparsify", ct.c_double), ("t_cg", ct.c_double),
         ("t_linesearch", ct.c_double), ("t_stop", ct.c_double), ("t_total", ct.c_double),
         ("nnz_mean", ct.c_double), ("nnz_last", ct.c_double),
-        ("mixed_passes", ct.c_int64),
+        ("mixed_passes", ct.c_int64), ("trace_len", ct.c_int64),
         ("status", ct.c_int32),
     ]
 
@@ -87,7 +106,7 @@ class _KernelTimes(ct.Structure):
 
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
-           "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
+           "ibsn_center_init", "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
            "ibsn_solve_batch")
@@ -110,6 +129,7 @@ def load():
     L.ibsn_last_error.argtypes = [vp]
     L.ibsn_last_error.restype = ct.c_char_p
     L.ibsn_num_cus.argtypes = [vp]
+    L.ibsn_center_init.argtypes = [vp, P, vp, vp]
     L.ibsn_center_quantum.argtypes = [vp, P, C, vp, ct.POINTER(dbl)]
     L.ibsn_subproblem_eval.argtypes = [vp, P, C, vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), vp]
     L.ibsn_trial.argtypes = [vp, P, C, vp, vp, vp, dbl, ct.POINTER(dbl), vp, vp, vp, vp]
@@ -273,11 +293,21 @@ class Center:
 
     @staticmethod
     def initial(ctx: "Context", prob: Problem, gamma: torch.Tensor | None = None) -> "Center":
-        """X^0 = a b^T (Algorithm 2 input), with the solver's grid for gamma (0 if None)."""
-        c = Center(0, torch.log(prob.a), torch.log(prob.b), 1.0)
+        """X^0 = a b^T (Algorithm 2 input; r = log a, s = log b from ibsn_center_init), with
+        the solver's grid for gamma (0 if None)."""
+        r, s = _new(prob, prob.m), _new(prob, prob.n)
+        center_init(ctx, prob, r, s)
+        c = Center(0, r, s, 1.0)
         g = gamma if gamma is not None else torch.zeros_like(prob.b)
         c.quantum = center_quantum(ctx, prob, c, g)
         return c
+
+
+def center_init(ctx: "Context", prob: Problem, r, s):
+    """ibsn_center_init: r = log a, s = log b (the centre X^0 = a b^T) into r (m), s (n)."""
+    ctx.check(load().ibsn_center_init(ctx.h, ct.byref(prob.raw()), _ptr(r, prob.m, name="r"),
+                                      _ptr(s, prob.n, name="s")))
+    return r, s
 
 
 def center_quantum(ctx: "Context", prob: Problem, center: Center, gamma) -> float:
@@ -409,9 +439,10 @@ def default_options(**kw) -> Options:
 
 
 def solve(ctx: Context, prob: Problem, options: Options | None = None, gamma0=None, state=None,
-          want_plan: bool = False):
-    """ibsn_solve (Algorithm 2).  state = (r, s, k) resumes an outer state.
-    Returns dict(status, gamma, r, s, k, plan, report)."""
+          want_plan: bool = False, trace_cap: int = 0):
+    """ibsn_solve (Algorithm 2).  state = (r, s, k) resumes an outer state.  trace_cap > 0
+    returns the first trace_cap per-outer-iteration records (ibsn_iter_record) as dicts.
+    Returns dict(status, gamma, r, s, k, plan, report, trace)."""
     m, n = prob.m, prob.n
     gamma = _new(prob, n)
     if gamma0 is not None:
@@ -426,10 +457,16 @@ def solve(ctx: Context, prob: Problem, options: Options | None = None, gamma0=No
         k.value = int(state[2])
     plan = torch.empty((m, n), dtype=torch.float64, device=prob.C.device) if want_plan else None
     rep = Report()
-    opt = options if options is not None else default_options()
+    opt = Options()
+    ct.pointer(opt)[0] = options if options is not None else default_options()
+    recs = (IterRecord * max(int(trace_cap), 1))()
+    opt.trace = ct.cast(recs, ct.c_void_p) if trace_cap > 0 else None
+    opt.trace_cap = int(trace_cap)
     rc = ctx.check(load().ibsn_solve(ctx.h, ct.byref(prob.raw()), ct.byref(opt), _ptr(gamma),
                                      _ptr(r), _ptr(s), ct.byref(k), _ptr(plan), ct.byref(rep)))
-    return dict(status=rc, gamma=gamma, r=r, s=s, k=k.value, plan=plan, report=rep.as_dict())
+    trace = [recs[i].as_dict() for i in range(rep.trace_len)] if trace_cap > 0 else None
+    return dict(status=rc, gamma=gamma, r=r, s=s, k=k.value, plan=plan, report=rep.as_dict(),
+                trace=trace)
 
 
 def solve_batch(ctxs, probs, options: Options | None = None, gamma0=None):
@@ -465,6 +502,7 @@ def solve_batch(ctxs, probs, options: Options | None = None, gamma0=None):
 
 
 # the C-ABI names
+ibsn_center_init = center_init
 ibsn_center_quantum = center_quantum
 ibsn_subproblem_eval = subproblem_eval
 ibsn_trial = trial

@@ -58,19 +58,25 @@ def test_struct_layouts_match_header(tmp_path):
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     fields_o = [f for f, _ in ibsn.Options._fields_]
     fields_r = [f for f, _ in ibsn.Report._fields_]
+    fields_t = [f for f, _ in ibsn.IterRecord._fields_]
     nl = "\\n"
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "ibsn.h"', "int main(void) {",
-           f'printf("%zu %zu{nl}", sizeof(ibsn_options), sizeof(ibsn_report));']
+           f'printf("%zu %zu %zu{nl}", sizeof(ibsn_options), sizeof(ibsn_report), '
+           'sizeof(ibsn_iter_record));']
     src += [f'printf("%zu{nl}", offsetof(ibsn_options, {f}));' for f in fields_o]
     src += [f'printf("%zu{nl}", offsetof(ibsn_report, {f}));' for f in fields_r]
+    src += [f'printf("%zu{nl}", offsetof(ibsn_iter_record, {f}));' for f in fields_t]
     src += ["return 0; }"]
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src) + "\n")
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", inc, str(c), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    so, sr = int(out[0]), int(out[1])
-    offs = [int(x) for x in out[2:]]
+    so, sr, stt = int(out[0]), int(out[1]), int(out[2])
+    offs = [int(x) for x in out[3:]]
     assert so == ctypes.sizeof(ibsn.Options) and sr == ctypes.sizeof(ibsn.Report)
-    assert offs[:len(fields_o)] == [getattr(ibsn.Options, f).offset for f in fields_o]
-    assert offs[len(fields_o):] == [getattr(ibsn.Report, f).offset for f in fields_r]
+    assert stt == ctypes.sizeof(ibsn.IterRecord)
+    no, nr = len(fields_o), len(fields_r)
+    assert offs[:no] == [getattr(ibsn.Options, f).offset for f in fields_o]
+    assert offs[no:no + nr] == [getattr(ibsn.Report, f).offset for f in fields_r]
+    assert offs[no + nr:] == [getattr(ibsn.IterRecord, f).offset for f in fields_t]
