@@ -186,6 +186,19 @@ void ibsn_csr_free(ibsn_csr *csr);
 int ibsn_hvp(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,
              const double *v, double *y);
 
+/* ibsn_hvp for callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid allocation): the same product and kernels,
+   but no allocation of any kind.  The intermediate u = a o (P_rho v) (m doubles) and the
+   dense row's partial sums go to one fixed device array of the library, about 8 MiB per
+   device, located by ibsn_create and held until the process ends.  Requires m <=
+   IBSN_NOALLOC_MAX_M (else IBSN_ERR_INVALID_ARG, nothing launched).  Every call on one
+   device uses that device's array: calls that overlap on one device (other streams, other
+   threads, other contexts) race and must be serialised by the caller.  The array needs no
+   clearing: each call writes every entry it reads before reading it. */
+#define IBSN_NOALLOC_MAX_M 1048576
+int ibsn_hvp_noalloc(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta,
+                     double shift, const double *v, double *y);
+
 /* Conjugate gradients (Algorithm 2, step 8) for (H_rho + shift I) x = rhs from x = 0,
    stopping at ||r||_2 <= tol or after maxit iterations.  Host out: iterations. */
 int ibsn_cg(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,

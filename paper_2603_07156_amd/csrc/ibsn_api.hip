@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <atomic>
 #include <numeric>
+#include <mutex>
 #include <thread>
 #include <cfloat>
 #include <chrono>
@@ -43,9 +44,18 @@ struct ibsn_csr {
     DevBuf col, val, len, colptr, colcnt, rowidx, cval, mask, off, d, istar_dev, nnz_dev;
 };
 
+// Device memory of ibsn_hvp_noalloc, for callers that cannot allocate: u = a o (P_rho v)
+// (up to IBSN_NOALLOC_MAX_M rows) followed by the dense row's CG_MAX_STAR chunk partials.
+// Each device holds its own copy until the process ends.  Host code never uses the array's
+// name as an address: ibsn_create looks up each device's copy once (scratch_dev).
+static __device__ __align__(256) double scratch[IBSN_NOALLOC_MAX_M + CG_MAX_STAR];
+static double *scratch_dev[64];
+static std::mutex scratch_mu;
+
 struct ibsn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    double *scratch = nullptr;   // this device's copy of `scratch` (device address)
     int num_cus = 256;
     size_t max_lds = 65536;
     std::string err;
@@ -636,9 +646,24 @@ int ibsn_create(ibsn_ctx **out, int device, void *hip_stream)
         return IBSN_ERR_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess)
         return IBSN_ERR_HIP;
+    if (device >= 64)
+        return IBSN_ERR_UNSUPPORTED;
+    double *scr = nullptr;
+    {
+        // once per device, with the device current: the address of its copy of `scratch`
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        if (!scratch_dev[device]) {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+                return IBSN_ERR_HIP;
+            scratch_dev[device] = (double *)ptr;
+        }
+        scr = scratch_dev[device];
+    }
     ibsn_ctx *ctx = new ibsn_ctx();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    ctx->scratch = scr;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         ctx->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -956,6 +981,35 @@ int ibsn_hvp(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, do
     CKH(hipSetDevice(ctx->device));
     CKI(ensure_cg(ctx, csr->m, csr->n));
     return run_hvp(ctx, csr, a, eta, shift, v, y);
+}
+
+int ibsn_hvp_noalloc(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta,
+                     double shift, const double *v, double *y)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (!csr || !a || !v || !y)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "csr, a, v and y are required");
+    if (csr->ctx != ctx)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "the factor belongs to another context");
+    if (!(eta > 0.0) || !std::isfinite(shift))
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "eta must be > 0 and shift finite");
+    if (csr->m > IBSN_NOALLOC_MAX_M)
+        return fail(ctx, IBSN_ERR_INVALID_ARG,
+                    "ibsn_hvp_noalloc: m = %lld exceeds its fixed buffer (m <= %d)",
+                    (long long)csr->m, (int)IBSN_NOALLOC_MAX_M);
+    if (!ctx->scratch)
+        return fail(ctx, IBSN_ERR_HIP, "ibsn_hvp_noalloc: no device buffer for this context");
+    const GatherPlan g = gather_plan(csr->m, csr->n, csr->nnz, csr->istar, ctx->num_cus,
+                                     ctx->max_lds);
+    if (g.nstar > CG_MAX_STAR)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "dense row split into too many chunks");
+    CKH(hipSetDevice(ctx->device));
+    // u = a o (P_rho v) and the dense row's partials go to the fixed array; every entry the
+    // column gather reads is written by the row gather of this call first
+    CKH(launch_hvp(g, csr_view(csr), a, eta, shift, v, y, ctx->scratch,
+                   ctx->scratch + IBSN_NOALLOC_MAX_M, ctx->stream));
+    return IBSN_OK;
 }
 
 int ibsn_cg(ibsn_ctx *ctx, const ibsn_csr *csr, const double *a, double eta, double shift,

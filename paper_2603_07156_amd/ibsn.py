@@ -109,7 +109,7 @@ EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
            "ibsn_center_init", "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
-           "ibsn_solve_batch")
+           "ibsn_solve_batch", "ibsn_hvp_noalloc")
 
 
 def load():
@@ -139,6 +139,7 @@ def load():
     L.ibsn_csr_free.argtypes = [vp]
     L.ibsn_csr_free.restype = None
     L.ibsn_hvp.argtypes = [vp, vp, vp, dbl, dbl, vp, vp]
+    L.ibsn_hvp_noalloc.argtypes = [vp, vp, vp, dbl, dbl, vp, vp]
     L.ibsn_cg.argtypes = [vp, vp, vp, dbl, dbl, vp, dbl, ct.c_int, vp, ct.POINTER(ct.c_int)]
     L.ibsn_stop.argtypes = [vp, P, C, vp, vp, vp, ct.POINTER(dbl), vp]
     L.ibsn_default_options.argtypes = [ct.POINTER(Options)]
@@ -400,6 +401,18 @@ def hvp(ctx: Context, csr: Csr, a, eta: float, shift: float, v):
     return y
 
 
+NOALLOC_MAX_M = 1048576
+
+
+def hvp_noalloc(ctx: Context, csr: Csr, a, eta: float, shift: float, v, y):
+    """ibsn_hvp_noalloc: y = (H_rho + shift I) v into the caller's y; the library allocates
+    nothing (its intermediate lives in a fixed per-device array; m <= NOALLOC_MAX_M)."""
+    ctx.check(load().ibsn_hvp_noalloc(ctx.h, csr.h, _ptr(a, csr.m, name="a"), float(eta),
+                                      float(shift), _ptr(v, csr.n, name="v"),
+                                      _ptr(y, csr.n, name="y")))
+    return y
+
+
 def cg(ctx: Context, csr: Csr, a, eta: float, shift: float, rhs, tol: float, maxit: int):
     """ibsn_cg: returns (x, iterations)."""
     x = torch.empty(csr.n, dtype=torch.float64, device=csr.device)
@@ -508,6 +521,7 @@ ibsn_subproblem_eval = subproblem_eval
 ibsn_trial = trial
 ibsn_sparsify = sparsify
 ibsn_hvp = hvp
+ibsn_hvp_noalloc = hvp_noalloc
 ibsn_cg = cg
 ibsn_stop = stop
 ibsn_solve = solve
