@@ -113,11 +113,14 @@ typedef struct {
 
 /* Implicit prox centre X^k (see above): device r (m), s (n), and the grid spacing
    `quantum` (a power of two, at least DBL_MIN) of the potentials.  Every pass forms
-   w_j = grid(s_j + gamma_j/eta) with grid(v) = quantum * rint(v / quantum), keeps the row
-   shifts M_i on the same grid, and evaluates x_ij = fma(-sigma, C_ij, w_j - M_i): the
-   difference w_j - M_i is exact, so x_ij = theta_ij - M_i carries one rounding at its
-   own scale however large sigma grows.  ibsn_center_quantum() returns the spacing the
-   solver uses: 2^(e-50) for 2^(e-1) <= max_j |s_j + gamma_j/eta| + sigma max|C| < 2^e. */
+   w_j = s_j + gamma_j/eta as two parts, wh_j = grid(s_j + gamma_j/eta) with
+   grid(v) = quantum * rint(v / quantum) and the remainder wl_j (exact up to the rounding
+   of gamma_j/eta), keeps the row shifts M_i on the same grid, and evaluates
+   x_ij = fma(-sigma, C_ij, wh_j - M_i) + wl_j: the difference wh_j - M_i is exact, so
+   x_ij = theta_ij - M_i carries two roundings at its own scale however large sigma
+   grows.  (FP32 costs with n > 12288 keep the potentials on the grid: wl_j = 0, w_j =
+   grid(s_j + gamma_j/eta).)  ibsn_center_quantum() returns the spacing the solver uses:
+   2^(e-50) for 2^(e-1) <= max_j |s_j + gamma_j/eta| + sigma max|C| < 2^e. */
 typedef struct {
     int64_t k;
     const double *r, *s;
@@ -144,7 +147,8 @@ int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cen
                          double *colmarg, double *grad, double *obj_host, double *plan);
 
 /* Armijo trial (Algorithm 2, step 9) from the row state (M) of gamma.  The step is
-   taken on the potential grid: tau_j = grid(t Delta_j / eta), trial point w + tau.
+   tau_j = t Delta_j / eta (on the potential grid, grid(t Delta_j / eta), where the
+   potentials are kept on it), trial point w + tau.
    Host out dL = L^k(trial) - L^k(gamma), evaluated in difference form
    (-eta b^T tau + eta sum_i a_i log(sum_j q_ij e^{tau_j} / sum_j q_ij), q = exp(x)) so
    that it keeps its relative precision for tiny steps.  Device out: M_new, S_new (m)

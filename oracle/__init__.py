@@ -85,23 +85,23 @@ def _declare(L):
     L.orc_center_quantum.restype = dbl
     L.orc_center_quantum.argtypes = [i64, _dp, _dp, dbl, i64, dbl]
     L.orc_make_w.restype = None
-    L.orc_make_w.argtypes = [i64, _dp, _dp, dbl, dbl, _dp]
+    L.orc_make_w.argtypes = [i64, _dp, _dp, dbl, dbl, _dp, _dp]
     L.orc_eval.restype = ct.c_int
     L.orc_eval.argtypes = [i64, i64, vp, i32, i64, i64, dbl, dbl, _dp, _dp, _dp, _dp, _dp, _dp,
-                           _dp, _dp, _dp, _dp, _dp]
+                           _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_trial.restype = ct.c_int
-    L.orc_trial.argtypes = [i64, i64, vp, i32, i64, i64, dbl, dbl, _dp, _dp, _dp, _dp, _dp, dbl,
-                            _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_trial.argtypes = [i64, i64, vp, i32, i64, i64, dbl, dbl, _dp, _dp, _dp, _dp, _dp, _dp,
+                            dbl, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_sparsify.restype = ct.c_int64
-    L.orc_sparsify.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, dbl, i64,
-                               i64, _i64p, _i32p, _dp, _dp]
+    L.orc_sparsify.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, _dp, dbl,
+                               i64, i64, _i64p, _i32p, _dp, _dp]
     L.orc_hvp.restype = None
     L.orc_hvp.argtypes = [i64, i64, _i64p, _i32p, _dp, _dp, _dp, dbl, dbl, _dp, _dp]
     L.orc_cg.restype = ct.c_int
     L.orc_cg.argtypes = [i64, i64, _i64p, _i32p, _dp, _dp, _dp, dbl, dbl, _dp, dbl, i32, _dp]
     L.orc_stop.restype = ct.c_int
     L.orc_stop.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                           _dp]
+                           _dp, _dp]
     L.orc_default_options.restype = None
     L.orc_default_options.argtypes = [ct.POINTER(Options)]
     L.orc_plain_eval.restype = ct.c_int
@@ -156,6 +156,7 @@ class EvalResult:
     plan: np.ndarray | None
     q: float
     w: np.ndarray
+    wl: np.ndarray | None = None
 
     @property
     def lse(self):
@@ -178,47 +179,54 @@ def center_quantum(C, s, gamma, eta, k):
     return lib().orc_center_quantum(len(s), _p(s), _p(gamma), float(eta), int(k), cost_max(C))
 
 
-def make_w(s, gamma, eta, q):
+def make_w(s, gamma, eta, q, split=True):
+    """Two-level potentials (w, wl) with w + wl = s + gamma/eta, w on the grid of spacing q
+    (split=False: w = grid(s + gamma/eta) and wl = None)."""
     s, gamma = _f64(s), _f64(gamma)
     w = np.empty(len(s))
-    lib().orc_make_w(len(s), _p(s), _p(gamma), float(eta), float(q), _p(w))
-    return w
+    wl = np.empty(len(s)) if split else None
+    lib().orc_make_w(len(s), _p(s), _p(gamma), float(eta), float(q), _p(w), _p(wl))
+    return w, wl
 
 
-def _wq(C, b, eta, gamma, s, k, q):
+def _wq(C, b, eta, gamma, s, k, q, split):
     s = np.log(_f64(b)) if s is None else _f64(s)
     gamma = _f64(gamma)
     if q is None:
         q = center_quantum(C, s, gamma, eta, k)
-    return s, make_w(s, gamma, eta, q), q
+    w, wl = make_w(s, gamma, eta, q, split)
+    return s, w, wl, q
 
 
-def eval_pass(C, a, b, eta, gamma, r=None, s=None, k=0, want_plan=False, q=None) -> EvalResult:
+def eval_pass(C, a, b, eta, gamma, r=None, s=None, k=0, want_plan=False, q=None,
+              split=True) -> EvalResult:
+    """Eval at w = s + gamma/eta held as two-level potentials (split=False: on the grid)."""
     C, kind = _cost(C)
     m, n = C.shape
     a, b, gamma = _f64(a), _f64(b), _f64(gamma)
     r = np.log(a) if r is None else _f64(r)
-    s, w, q = _wq(C, b, eta, gamma, s, k, q)
+    s, w, wl, q = _wq(C, b, eta, gamma, s, k, q, split)
     M, S, c, g = np.empty(m), np.empty(m), np.empty(n), np.empty(n)
     L = ct.c_double()
     plan = np.empty((m, n)) if want_plan else None
-    rc = lib().orc_eval(m, n, C.ctypes.data, kind, n, k, eta, q, _p(w), _p(r), _p(gamma), _p(a),
-                        _p(b), _p(M), _p(S), _p(c), _p(g), ct.byref(L), _p(plan))
+    rc = lib().orc_eval(m, n, C.ctypes.data, kind, n, k, eta, q, _p(w), _p(wl), _p(r), _p(gamma),
+                        _p(a), _p(b), _p(M), _p(S), _p(c), _p(g), ct.byref(L), _p(plan))
     assert rc == 0, rc
-    return EvalResult(M, S, c, g, L.value, plan, q, w)
+    return EvalResult(M, S, c, g, L.value, plan, q, w, wl)
 
 
-def trial_pass(C, a, b, eta, gamma, M, Delta, t, s=None, k=0, q=None):
-    """Armijo trial at the grid point w + grid(t*Delta/eta) from the row state M of w.
-    Returns (dL, M_new, S_new, c_new, g_new)."""
+def trial_pass(C, a, b, eta, gamma, M, Delta, t, s=None, k=0, q=None, split=True):
+    """Armijo trial at w + t*Delta/eta (split=False: the step on the grid) from the row state
+    M of w.  Returns (dL, M_new, S_new, c_new, g_new)."""
     C, kind = _cost(C)
     m, n = C.shape
     a, b, M, Delta = map(_f64, (a, b, M, Delta))
-    s, w, q = _wq(C, b, eta, gamma, s, k, q)
+    s, w, wl, q = _wq(C, b, eta, gamma, s, k, q, split)
     Mn, Sn, cn, gn = np.empty(m), np.empty(m), np.empty(n), np.empty(n)
     dL = ct.c_double()
-    rc = lib().orc_trial(m, n, C.ctypes.data, kind, n, k, eta, q, _p(w), _p(a), _p(b), _p(M),
-                         _p(Delta), float(t), ct.byref(dL), None, _p(Mn), _p(Sn), _p(cn), _p(gn))
+    rc = lib().orc_trial(m, n, C.ctypes.data, kind, n, k, eta, q, _p(w), _p(wl), _p(a), _p(b),
+                         _p(M), _p(Delta), float(t), ct.byref(dL), None, _p(Mn), _p(Sn), _p(cn),
+                         _p(gn))
     assert rc == 0, rc
     return dL.value, Mn, Sn, cn, gn
 
@@ -250,7 +258,7 @@ def istar_of(a):
     return int(np.argmax(np.asarray(a)))
 
 
-def sparsify(C, a, eta, gamma, M, S, rho, s, k=0, istar=None, q=None) -> CSR:
+def sparsify(C, a, eta, gamma, M, S, rho, s, k=0, istar=None, q=None, split=True) -> CSR:
     """Algorithm 1 from the row state (M, S) at (s, gamma, k)."""
     C, kind = _cost(C)
     m, n = C.shape
@@ -259,17 +267,17 @@ def sparsify(C, a, eta, gamma, M, S, rho, s, k=0, istar=None, q=None) -> CSR:
     gamma = _f64(gamma)
     if q is None:
         q = center_quantum(C, s, gamma, eta, k)
-    w = make_w(s, gamma, eta, q)
+    w, wl = make_w(s, gamma, eta, q, split)
     istar = istar_of(a) if istar is None else int(istar)
     row_ptr = np.empty(m + 1, dtype=np.int64)
-    need = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(a), _p(M), _p(S),
-                              float(rho), istar, 0, _p(row_ptr), None, None, None)
+    need = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(wl), _p(a), _p(M),
+                              _p(S), float(rho), istar, 0, _p(row_ptr), None, None, None)
     nnz = -need - 1
     col = np.empty(max(nnz, 1), dtype=np.int32)
     val = np.empty(max(nnz, 1))
     d = np.empty(n)
-    got = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(a), _p(M), _p(S),
-                             float(rho), istar, nnz, _p(row_ptr), _p(col), _p(val), _p(d))
+    got = lib().orc_sparsify(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(wl), _p(a), _p(M),
+                             _p(S), float(rho), istar, nnz, _p(row_ptr), _p(col), _p(val), _p(d))
     assert got == nnz
     return CSR(m, n, row_ptr, col[:nnz], val[:nnz], d, istar)
 
@@ -295,17 +303,17 @@ STOP_FIELDS = ("dphi", "primal", "dual", "cx", "kkt", "xhat_min", "er1", "xu", "
                "dual_psi")
 
 
-def stop_pass(C, a, b, eta, gamma, M, S, s=None, k=0, want_xhat=False, q=None):
+def stop_pass(C, a, b, eta, gamma, M, S, s=None, k=0, want_xhat=False, q=None, split=True):
     """Rounding, D_phi and certificate for the plan of the row state (M, S) at w.
     The certificate's dual is gamma as given."""
     C, kind = _cost(C)
     m, n = C.shape
     a, b, gamma, M, S = map(_f64, (a, b, gamma, M, S))
-    s, w, q = _wq(C, b, eta, gamma, s, k, q)
+    s, w, wl, q = _wq(C, b, eta, gamma, s, k, q, split)
     out = np.empty(10)
     xhat = np.empty((m, n)) if want_xhat else None
-    rc = lib().orc_stop(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(gamma), _p(a), _p(b),
-                        _p(M), _p(S), _p(out), _p(xhat))
+    rc = lib().orc_stop(m, n, C.ctypes.data, kind, n, k, eta, _p(w), _p(wl), _p(gamma), _p(a),
+                        _p(b), _p(M), _p(S), _p(out), _p(xhat))
     assert rc == 0
     res = dict(zip(STOP_FIELDS, out.tolist()))
     if want_xhat:

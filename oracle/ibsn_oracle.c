@@ -83,11 +83,34 @@ static inline double cost_at(const void *C, int kind, int64_t ldc, int64_t i, in
 /* round v to the grid of spacing q (q a power of two) */
 static inline double grid(double v, double q) { return q * rint(v / q); }
 
-/* x_ij = theta_ij - M_i with w_j - M_i exact */
+/* x_ij = theta_ij - M_i for the potential w_j + wl_j (wl may be NULL: 0), with w_j - M_i
+   exact (both on the grid) */
 static inline double xval(const void *C, int kind, int64_t ldc, int64_t i, int64_t j,
-                          double sigma, const double *w, double Mi)
+                          double sigma, const double *w, const double *wl, double Mi)
 {
-    return fma(-sigma, cost_at(C, kind, ldc, i, j), w[j] - Mi);
+    double x = fma(-sigma, cost_at(C, kind, ldc, i, j), w[j] - Mi);
+    return wl ? x + wl[j] : x;
+}
+
+/* Knuth's two-sum: hi + lo = a + b exactly, hi = fl(a + b) */
+static inline void two_sum(double a, double b, double *hi, double *lo)
+{
+    double h = a + b;
+    double bv = h - a;
+    double av = h - bv;
+    *hi = h;
+    *lo = (a - av) + (b - bv);
+}
+
+/* (w, wl) += d with w kept on the grid of spacing q: the exact sum wl + d is split into
+   its grid part (added to w, exactly) and the remainder */
+static inline void pot_add(double *w, double *wl, double d, double q)
+{
+    double u, e;
+    two_sum(*wl, d, &u, &e);
+    double gpart = grid(u, q);
+    *w += gpart;
+    *wl = (u - gpart) + e;
 }
 
 static double dot(int64_t n, const double *x, const double *y)
@@ -134,11 +157,23 @@ double orc_center_quantum(int64_t n, const double *s, const double *gamma, doubl
     return orc_quantum(mw + ((double)(k + 1) / eta) * cmax);
 }
 
-/* w_j = grid(s_j + gamma_j / eta) */
-void orc_make_w(int64_t n, const double *s, const double *gamma, double eta, double q, double *w)
+/* Two-level potentials w_j + wl_j = s_j + gamma_j / eta: w_j = grid(s_j + gamma_j / eta)
+   and wl_j the remainder, carried exactly up to one rounding at its own size (the rounding
+   of s_j + d_j from a two-sum, that of d_j = gamma_j / eta from its fma residual).
+   wl == NULL: the potentials are kept on the grid (w_j only). */
+void orc_make_w(int64_t n, const double *s, const double *gamma, double eta, double q, double *w,
+                double *wl)
 {
-    for (int64_t j = 0; j < n; ++j)
-        w[j] = grid(s[j] + gamma[j] / eta, q);
+    for (int64_t j = 0; j < n; ++j) {
+        double d = gamma[j] / eta;
+        double t, e;
+        two_sum(s[j], d, &t, &e);
+        w[j] = grid(t, q);
+        if (wl) {
+            double rd = fma(-d, eta, gamma[j]); /* gamma_j - d eta, exactly */
+            wl[j] = ((t - w[j]) + e) + rd / eta;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -147,7 +182,8 @@ void orc_make_w(int64_t n, const double *s, const double *gamma, double eta, dou
 /* The objective uses the gamma given (gamma = eta (w - s) up to the grid).         */
 /* ------------------------------------------------------------------------- */
 int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-             double q, const double *w, const double *r, const double *gamma, const double *a,
+             double q, const double *w, const double *wl, const double *r, const double *gamma,
+             const double *a,
              const double *b, double *M, double *S, double *c, double *g, double *L,
              double *plan /* m*n (row-major) or NULL */)
 {
@@ -167,7 +203,7 @@ int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
         double Mi = grid(mx, q);
         double sum = 0.0;
         for (int64_t j = 0; j < n; ++j)
-            sum += exp(xval(C, kind, ldc, i, j, sigma, w, Mi));
+            sum += exp(xval(C, kind, ldc, i, j, sigma, w, wl, Mi));
         M[i] = Mi;
         S[i] = sum;
     }
@@ -180,7 +216,7 @@ int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
         double *pc = part + (size_t)q * n;
         for (int64_t i = i0; i < i1; ++i)
             for (int64_t j = 0; j < n; ++j) {
-                double p = exp(xval(C, kind, ldc, i, j, sigma, w, M[i])) / S[i];
+                double p = exp(xval(C, kind, ldc, i, j, sigma, w, wl, M[i])) / S[i];
                 pc[j] += a[i] * p;
                 if (plan)
                     plan[i * n + j] = a[i] * p;
@@ -207,8 +243,8 @@ int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
 
 /* ------------------------------------------------------------------------- */
 /* Armijo trial (Algorithm 2, step 9) from the row state M of the point w.          */
-/* The step is taken on the grid: tau_j = grid(t * Delta_j / eta), so the trial     */
-/* point is w + tau exactly.  Exact algebra for the change of the objective:        */
+/* The step is tau_j = t * Delta_j / eta (rounded to the grid when the potentials    */
+/* are kept on it); the trial point is w + tau.  Exact algebra for the change:      */
 /*   L(w + tau) - L(w) = -eta * b^T tau + eta * sum_i a_i delta_i,                  */
 /*   delta_i = log( sum_j q_ij e^{tau_j} / sum_j q_ij ),  q_ij = exp(x_ij).           */
 /* Small steps (max tau <= 500): delta_i = log1p(B_i / A_i) with A_i = sum_j q_ij,  */
@@ -221,7 +257,8 @@ int orc_eval(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
 /* x' of the point w + tau.  A row whose factors all underflow gives delta = +inf.  */
 /* ------------------------------------------------------------------------- */
 int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-              double q, const double *w, const double *a, const double *b, const double *M,
+              double q, const double *w, const double *wl, const double *a, const double *b,
+              const double *M,
               const double *Delta, double t, double *dL /* out */, double *tau_out /* n or NULL */,
               double *M_new, double *S_new, double *c_new, double *g_new)
 {
@@ -234,7 +271,8 @@ int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_
     double *Z = malloc(sizeof(double) * m);
     double tau_max = -INFINITY;
     for (int64_t j = 0; j < n; ++j) {
-        tau[j] = grid(t * Delta[j] / eta, q);
+        /* with two-level potentials the step is taken as it is; on the grid otherwise */
+        tau[j] = wl ? t * Delta[j] / eta : grid(t * Delta[j] / eta, q);
         if (tau[j] > tau_max)
             tau_max = tau[j];
     }
@@ -247,7 +285,7 @@ int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_
     for (int64_t i = 0; i < m; ++i) {
         double A = 0.0, B = 0.0, Zi = 0.0, qmax = 0.0;
         for (int64_t j = 0; j < n; ++j) {
-            double qv = exp(xval(C, kind, ldc, i, j, sigma, w, M[i]));
+            double qv = exp(xval(C, kind, ldc, i, j, sigma, w, wl, M[i]));
             A += qv;
             double qe;
             if (small_step) {
@@ -283,7 +321,7 @@ int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_
             if (!(Z[i] > 0.0))
                 continue;
             for (int64_t j = 0; j < n; ++j) {
-                double qv = exp(xval(C, kind, ldc, i, j, sigma, w, M[i]));
+                double qv = exp(xval(C, kind, ldc, i, j, sigma, w, wl, M[i]));
                 double qe = small_step ? qv + qv * cv[j] : qv * cv[j];
                 pc[j] += a[i] * (qe / Z[i]);
             }
@@ -317,7 +355,7 @@ int orc_trial(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_
 /* except row_ptr).  A row whose entries all fall below rho is left empty.          */
 /* ------------------------------------------------------------------------- */
 int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
-                     double eta, const double *w, const double *a, const double *M,
+                     double eta, const double *w, const double *wl, const double *a, const double *M,
                      const double *S, double rho, int64_t istar, int64_t cap, int64_t *row_ptr,
                      int32_t *col, double *val, double *d)
 {
@@ -331,7 +369,7 @@ int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
         }
         int64_t c = 0;
         for (int64_t j = 0; j < n; ++j) {
-            double p = exp(xval(C, kind, ldc, i, j, sigma, w, M[i])) / S[i];
+            double p = exp(xval(C, kind, ldc, i, j, sigma, w, wl, M[i])) / S[i];
             if (p >= rho)
                 ++c;
         }
@@ -349,7 +387,7 @@ int64_t orc_sparsify(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
         int64_t o = row_ptr[i];
         double kappa = 0.0;
         for (int64_t j = 0; j < n; ++j) {
-            double p = exp(xval(C, kind, ldc, i, j, sigma, w, M[i])) / S[i];
+            double p = exp(xval(C, kind, ldc, i, j, sigma, w, wl, M[i])) / S[i];
             if (i == istar || p >= rho) {
                 col[o] = (int32_t)j;
                 val[o] = p;
@@ -624,7 +662,7 @@ static void stop_from_plan(int64_t m, int64_t n, const void *C, int kind, int64_
 }
 
 int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k, double eta,
-             const double *w, const double *gamma, const double *a, const double *b,
+             const double *w, const double *wl, const double *gamma, const double *a, const double *b,
              const double *M, const double *S, double *out, double *xhat /* m*n or NULL */)
 {
     const double sigma = (double)(k + 1) / eta;
@@ -636,13 +674,13 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
     for (int64_t i = 0; i < m; ++i) {
         double la = log(a[i]), ls = log(S[i]);
         for (int64_t j = 0; j < n; ++j) {
-            double x = xval(C, kind, ldc, i, j, sigma, w, M[i]);
+            double x = xval(C, kind, ldc, i, j, sigma, w, wl, M[i]);
             X[i * n + j] = a[i] * (exp(x) / S[i]);
             logX[i * n + j] = la + x - ls;
         }
     }
     for (int64_t j = 0; j < n; ++j)
-        psi[j] = (w[j] - log(b[j])) / sigma;
+        psi[j] = ((wl ? w[j] + wl[j] : w[j]) - log(b[j])) / sigma;
     stop_from_plan(m, n, C, kind, ldc, X, logX, gamma, psi, a, b, out, xhat, NULL, NULL, NULL,
                    NULL);
     free(X); free(logX); free(psi);
@@ -714,11 +752,12 @@ static void center(int64_t n, double *gamma)
         gamma[j] -= mean;
 }
 
-/* gamma = eta (w - s) */
-static void gamma_of(int64_t n, const double *w, const double *s, double eta, double *gamma)
+/* gamma = eta (w + wl - s) */
+static void gamma_of(int64_t n, const double *w, const double *wl, const double *s, double eta,
+                     double *gamma)
 {
     for (int64_t j = 0; j < n; ++j)
-        gamma[j] = eta * (w[j] - s[j]);
+        gamma[j] = eta * ((w[j] - s[j]) + wl[j]);
 }
 
 /* gamma_io: in = warm start (or NULL -> 0), out = final dual.
@@ -741,6 +780,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
 
     double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * n);
     double *gamma = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
+    double *wl = malloc(sizeof(double) * n);
     double *M = malloc(sizeof(double) * m), *S = malloc(sizeof(double) * m);
     double *c = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n);
     double *Mt = malloc(sizeof(double) * m), *St = malloc(sizeof(double) * m);
@@ -787,24 +827,24 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
     for (; k < k0 + opt.max_outer; ++k) {
         double mu = fmax(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
         const double q = orc_center_quantum(n, s, gamma, eta, k, cmax);
-        orc_make_w(n, s, gamma, eta, q, w);
+        orc_make_w(n, s, gamma, eta, q, w, wl);
         /* Algorithm 2, step 3: Sinkhorn warm-up (semi-dual form: the zeta-step is the row
            LSE of the eval pass, the gamma-step rescales the columns to b) */
-        orc_eval(m, n, C, kind, ldc, k, eta, q, w, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
+        orc_eval(m, n, C, kind, ldc, k, eta, q, w, wl, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
         for (int it = 0; it < opt.sinkhorn_maxit && nrm2(n, g) >= opt.sinkhorn_tol; ++it) {
-            /* gamma_j += eta (log b_j - log c_j), i.e. w_j += log b_j - log c_j on the grid */
+            /* gamma_j += eta (log b_j - log c_j), i.e. w_j += log b_j - log c_j */
             for (int64_t j = 0; j < n; ++j)
-                w[j] += grid(lb[j] - log(c[j]), q);
-            /* step 4: centre gamma = eta (w - s) by a grid shift of w (P is unchanged) */
-            gamma_of(n, w, s, eta, gamma);
+                pot_add(&w[j], &wl[j], lb[j] - log(c[j]), q);
+            /* step 4: centre gamma = eta (w - s) by a common shift of w (P is unchanged) */
+            gamma_of(n, w, wl, s, eta, gamma);
             double mean = 0.0;
             for (int64_t j = 0; j < n; ++j)
                 mean += gamma[j];
             mean /= (double)n;
-            const double sh = grid(mean / eta, q);
             for (int64_t j = 0; j < n; ++j)
-                w[j] -= sh;
-            orc_eval(m, n, C, kind, ldc, k, eta, q, w, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
+                pot_add(&w[j], &wl[j], -(mean / eta), q);
+            orc_eval(m, n, C, kind, ldc, k, eta, q, w, wl, NULL, NULL, a, b, M, S, c, g, NULL,
+                     NULL);
             ++R.sinkhorn;
         }
         /* a column whose kernel entries all lie below the FP64 range gives c_j = 0 and a
@@ -822,13 +862,13 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
                 break;
             }
             double rho = opt.rho_mode == 1 ? 0.0 : eta * gn / ((double)m * (double)n); /* step 6 */
-            int64_t nnz = orc_sparsify(m, n, C, kind, ldc, k, eta, w, a, M, S, rho, istar, 0,
+            int64_t nnz = orc_sparsify(m, n, C, kind, ldc, k, eta, w, wl, a, M, S, rho, istar, 0,
                                        row_ptr, NULL, NULL, NULL);
             nnz = -nnz - 1;
             int32_t *col = malloc(sizeof(int32_t) * (nnz > 0 ? nnz : 1));
             double *val = malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
-            orc_sparsify(m, n, C, kind, ldc, k, eta, w, a, M, S, rho, istar, nnz, row_ptr, col,
-                         val, d); /* step 7 */
+            orc_sparsify(m, n, C, kind, ldc, k, eta, w, wl, a, M, S, rho, istar, nnz, row_ptr,
+                         col, val, d); /* step 7 */
             for (int64_t j = 0; j < n; ++j)
                 rhs[j] = -g[j];
             double tol = fmax(fmin(opt.cg_forcing_max, gn), opt.cg_rtol_min) * gn;
@@ -841,8 +881,8 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             double t = 1.0, dL = 0.0;
             int bt = 0, accepted = 0;
             for (;;) { /* step 9: Armijo backtracking on a finite decrease */
-                orc_trial(m, n, C, kind, ldc, k, eta, q, w, a, b, M, Delta, t, &dL, tau, Mt, St,
-                          ct, gt);
+                orc_trial(m, n, C, kind, ldc, k, eta, q, w, wl, a, b, M, Delta, t, &dL, tau, Mt,
+                          St, ct, gt);
                 if (isfinite(dL) && dL <= opt.sigma_armijo * t * gd) {
                     accepted = 1;
                     break;
@@ -855,8 +895,8 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             R.backtracks += bt;
             if (!accepted) /* no acceptable step: keep the iterate and end the inner loop */
                 break;
-            for (int64_t j = 0; j < n; ++j) /* step 10, on the grid: exact */
-                w[j] += tau[j];
+            for (int64_t j = 0; j < n; ++j) /* step 10: w += tau, exactly */
+                pot_add(&w[j], &wl[j], tau[j], q);
             memcpy(M, Mt, sizeof(double) * m);
             memcpy(S, St, sizeof(double) * m);
             memcpy(c, ct, sizeof(double) * n);
@@ -864,8 +904,8 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             ++newton_k;
             /* step 12 with the practical schedule: gradient gate, then D_phi test */
             if (!opt.eot && nrm2(n, g) < mu) {
-                gamma_of(n, w, s, eta, gamma);
-                orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, NULL);
+                gamma_of(n, w, wl, s, eta, gamma);
+                orc_stop(m, n, C, kind, ldc, k, eta, w, wl, gamma, a, b, M, S, stop_out, NULL);
                 ++R.stop_tests;
                 if (stop_out[0] <= (double)(m < n ? m : n) * mu) {
                     stopped = 1;
@@ -875,9 +915,9 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
                     break;
             }
         }
-        gamma_of(n, w, s, eta, gamma);
+        gamma_of(n, w, wl, s, eta, gamma);
         if (!stopped || opt.eot) {
-            orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, NULL);
+            orc_stop(m, n, C, kind, ldc, k, eta, w, wl, gamma, a, b, M, S, stop_out, NULL);
             ++R.stop_tests;
         }
         R.newton += newton_k;
@@ -906,18 +946,21 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         if (opt.eot) {
             /* (E)IBSN: one subproblem, no outer update; done when its gradient is small */
             if (plan_out)
-                orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, plan_out);
+                orc_stop(m, n, C, kind, ldc, k, eta, w, wl, gamma, a, b, M, S, stop_out, plan_out);
             R.status = R.grad_norm < opt.eot_tol ? ORC_OK : ORC_WARN_MAXITER;
             ++k; /* one subproblem solved; the centre (r, s) = (0, 0) is left as it was */
             break;
         }
         if (plan_out && (done || k + 1 == k0 + opt.max_outer))
-            orc_stop(m, n, C, kind, ldc, k, eta, w, gamma, a, b, M, S, stop_out, plan_out);
+            orc_stop(m, n, C, kind, ldc, k, eta, w, wl, gamma, a, b, M, S, stop_out, plan_out);
         /* Algorithm 2, step 13: X^{k+1} = X^{k,v+1}: r = log a - lse, s = w, k = k+1;
            gamma^{k+1,0} = gamma^{k,v+1} */
         for (int64_t i = 0; i < m; ++i)
             r[i] = log(a[i]) - (M[i] + log(S[i]));
-        memcpy(s, w, sizeof(double) * n);
+        /* s = w rounded to one double: a column rescaling of X^{k+1} by 1 + O(2^-53), which
+           the next subproblem's dual absorbs (its optimal plan is unchanged) */
+        for (int64_t j = 0; j < n; ++j)
+            s[j] = w[j] + wl[j];
         if (done) {
             R.status = ORC_OK;
             ++k;
@@ -935,7 +978,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         *k_io = k;
     if (rep)
         *rep = R;
-    free(r); free(s); free(gamma); free(w); free(M); free(S); free(c); free(g); free(Mt);
+    free(r); free(s); free(gamma); free(w); free(wl); free(M); free(S); free(c); free(g); free(Mt);
     free(St); free(ct); free(gt); free(Delta); free(rhs); free(tau); free(d); free(lb);
     free(row_ptr);
     return R.status;

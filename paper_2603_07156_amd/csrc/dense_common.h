@@ -15,11 +15,13 @@
 // The row after the current one is prefetched into a second register set while the
 // current one is reduced, which keeps loads in flight across the reductions.
 //
-// Exponents.  Column potentials w_j and row shifts M_i both lie on a grid of spacing
-// q (a power of two chosen per outer iteration), so w_j - M_i is exact and
-//     x_ij = fma(-sigma, C_ij, w_j - M_i)
-// is theta_ij - M_i with one rounding at the scale of x_ij, however large sigma and
-// the potentials grow.  grid(v) = q * rint(v / q).
+// Exponents.  Column potentials are held in two parts, w_j = wh_j + wl_j: wh_j and the
+// row shifts M_i lie on a grid of spacing q (a power of two chosen per outer iteration),
+// so wh_j - M_i is exact, and wl_j is the small remainder (|wl_j| <= q/2).  Then
+//     x_ij = fma(-sigma, C_ij, wh_j - M_i) + wl_j
+// is theta_ij - M_i with two roundings at the scale of x_ij, however large sigma and the
+// potentials grow, and the potentials themselves are not limited to the grid.
+// grid(v) = q * rint(v / q).
 #pragma once
 
 #include "ibsn_internal.h"
@@ -287,6 +289,37 @@ __device__ __forceinline__ void stage_lds(const double *__restrict__ src, int n,
     for (int j = threadIdx.x; j < n; j += blockDim.x)
         lds[j] = src[j];
     __syncthreads();
+}
+
+// Stage the high parts (n doubles) and, for tiles with room (LO), the low parts as FP32
+// right after them in the dynamic LDS; one barrier.
+template <bool LO>
+__device__ __forceinline__ void stage_w2(const double *__restrict__ hi,
+                                         const double *__restrict__ lo, int n, double *lds)
+{
+    float *lf = reinterpret_cast<float *>(lds + n);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        lds[j] = hi[j];
+        if constexpr (LO)
+            lf[j] = (float)lo[j];
+    }
+    __syncthreads();
+}
+
+// x + wl_j with wl_j from the FP32 copy staged by stage_w2 (after n doubles at `base`)
+template <bool LO>
+__device__ __forceinline__ double add_lo(double x, const double *base, int n, int j)
+{
+    if constexpr (LO)
+        return x + (double)reinterpret_cast<const float *>(base + n)[j];
+    else
+        return x;
+}
+
+// dynamic LDS of a pass that stages one n-vector of doubles, plus the low parts if LO
+__host__ __device__ constexpr size_t lds_w2(int64_t n, bool lo)
+{
+    return (size_t)n * sizeof(double) + (lo ? (size_t)n * sizeof(float) : 0);
 }
 
 // grid(v) = q rint(v / q).  q is a power of two no smaller than the least normal double

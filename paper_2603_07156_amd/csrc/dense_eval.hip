@@ -15,6 +15,7 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
                                               const double *__restrict__ py, double pscale, int m, int n,
                                              double sigma, double qg,
                                              const double *__restrict__ w,
+                                             const double *__restrict__ wlo,
                                              const double *__restrict__ a,
                                              const double *__restrict__ r, double *__restrict__ Mo,
                                              double *__restrict__ So, double *__restrict__ lse,
@@ -24,6 +25,7 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
 {
     constexpr int E = Q * VEC;
     constexpr int NW = NT / WAVE;
+    constexpr bool LO = lo_tile(NT, Q, VEC);
     // per row: each wave takes its own shift m_w = grid(wave max of theta) and sums
     // exp(theta - m_w); one barrier publishes the (m_w, s_w) pairs; every wave then forms
     // M = max_w m_w = grid(max theta) (grid rounding is monotone) and
@@ -34,13 +36,13 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
     // log S_i for the row outputs, by thread 0: the table log keeps wave 0 from falling
     // ~75 instructions (the library log) behind the other waves at every row's barrier
     __shared__ __align__(16) double ltab[2 * LOG_TAB];
-    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    extern __shared__ double wl[];   // w staged in LDS (n doubles, then the FP32 low parts)
     int parity = 0;
     int i0, i1;
     row_range(m, i0, i1);
     log_table_init(ltab);
     exp_table_init(etab);   // its barrier also publishes ltab
-    stage_lds(w, n, wl);
+    stage_w2<LO>(w, wlo, n, wl);
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     __shared__ double rA[ROWCH], rR[ROWCH];
     double acc[E];
@@ -53,7 +55,8 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows(i, i1, a, rA, r, rR, nullptr, nullptr); },
         [&](int i, int slot, const auto *xr) {
         // padding slots: theta = -inf, so they drop out of the max and p = 0; a wave
-        // with no column in the row gets m_w = -inf, s_w = 0 and factor 0
+        // with no column in the row gets m_w = -inf, s_w = 0 and factor 0.  The shift is
+        // taken from the high parts alone (any value near the maximum serves).
         double mt = -INFINITY;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -64,7 +67,8 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         double st = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const double xa = fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - mw);
+            const int j = slot_col<QF, NT, VEC>(e, n);
+            const double xa = add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - mw), wl, n, j);
             const double p =
                 exp_pass<MX>(slot_valid<QF, NT, VEC>(e, n) ? xa : -INFINITY, etab);
             x[e] = (xval_t<MX>)p;   // exact: in the mixed form p is already an FP32 value
@@ -118,11 +122,12 @@ hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, do
 {
 #define BODY                                                                                     \
     static LdsCache lc_; \
-    if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX>, (size_t)d.n * sizeof(double), lc_); e_ != hipSuccess) \
+    const size_t lds_ = lds_w2(d.n, lo_tile(NT, Q, VEC)); \
+    if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX>, lds_, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT),                     \
-                       (size_t)d.n * sizeof(double), st,                                         \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.a, r, M, S, \
+                       lds_, st,                                         \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.wlo, d.a, r, M, S, \
                        lse,                                                                      \
                        plan, colpart, rowpart)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)

@@ -18,6 +18,7 @@ template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
 __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                                  double sigma, const double *__restrict__ w,
+                                                 const double *__restrict__ wlo,
                                                  const double *__restrict__ a,
                                                  const double *__restrict__ M,
                                                  const double *__restrict__ S, double rho,
@@ -29,6 +30,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
 {
     constexpr int E = Q * VEC;
     constexpr int NW = NT / WAVE;
+    constexpr bool LO = lo_tile(NT, Q, VEC);
     using RedSum = BlockRed<NT, OP_SUM>;
     __shared__ double lds[RedSum::LDS];
     __shared__ int cnt[2][Q * NW];
@@ -36,14 +38,14 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
     int i0, i1;
     row_range(m, i0, i1);
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    extern __shared__ double wl[];   // w staged in LDS (n doubles, then the FP32 low parts)
     __shared__ double etab[EXP_TAB];
     __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH];
     double acc[E];
     xval_t<MX> x[E];
     const int istar = *istar_p;
     exp_table_init(etab);
-    stage_lds(w, n, wl);
+    stage_w2<LO>(w, wlo, n, wl);
 #pragma unroll
     for (int e = 0; e < E; ++e)
         acc[e] = 0.0;
@@ -70,8 +72,8 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
-            const double xa =
-                fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n) + zo] - Mi);
+            const int j = slot_col<QF, NT, VEC>(e, n) + zo;
+            const double xa = add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - Mi), wl, n, j);
             const double p = exp_pass<MX>(valid ? xa : -INFINITY, etab) * iS;
             const bool keep = valid && (dense || p >= rho);
             x[e] = (xval_t<MX>)p;
@@ -162,13 +164,13 @@ hipError_t launch_sparsify(const RowPlan &p_in, const DenseArgs &d, const double
                            double *colpart, hipStream_t st)
 {
     const RowPlan p = heavy_plan(p_in);
-    const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                     \
     static LdsCache lc_; \
+    const size_t lds_bytes = lds_w2(d.n, lo_tile(NT, Q, VEC)); \
     if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT), lds_bytes, st, \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, rho, \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, rho, \
                        istar, col, (xval_t<MX> *)val, len, colpart)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)

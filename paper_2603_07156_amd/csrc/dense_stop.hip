@@ -12,6 +12,7 @@ template <int NT, int Q, int QF, int VEC, typename CT>
 __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                               double sigma, const double *__restrict__ w,
+                                              const double *__restrict__ wlo,
                                               const double *__restrict__ a,
                                               const double *__restrict__ M,
                                               const double *__restrict__ S,
@@ -20,17 +21,18 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
                                               double *__restrict__ rowpart)
 {
     constexpr int E = Q * VEC;
+    constexpr bool LO = lo_tile(NT, Q, VEC);
     using RedSum = BlockRed<NT, OP_SUM>;
     __shared__ double lds[RedSum::LDS];
     __shared__ double rM[ROWCH], rS[ROWCH], rA[ROWCH];
     int parity = 0;
     int i0, i1;
     row_range(m, i0, i1);
-    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    extern __shared__ double wl[];   // w staged in LDS (n doubles, then the FP32 low parts)
     __shared__ double etab[EXP_TAB];
     double ax[E], az[E], x[E];
     exp_table_init(etab);
-    stage_lds(w, n, wl);
+    stage_w2<LO>(w, wlo, n, wl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         ax[e] = 0.0;
@@ -45,8 +47,8 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const bool valid = slot_valid<QF, NT, VEC>(e, n);
-                const double xa =
-                    fma(-sigma, (double)xr[e], wl[slot_col<QF, NT, VEC>(e, n)] - Mi);
+                const int j = slot_col<QF, NT, VEC>(e, n);
+                const double xa = add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - Mi), wl, n, j);
                 const double X = exp_tab(valid ? xa : -INFINITY, etab) * aS;
                 x[e] = X;
                 red[0] += X;
@@ -81,6 +83,7 @@ template <int NT, int Q, int QF, int VEC, typename CT>
 __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                                double sigma, const double *__restrict__ w,
+                                               const double *__restrict__ wlo,
                                                const double *__restrict__ a,
                                                const double *__restrict__ M,
                                                const double *__restrict__ S,
@@ -93,15 +96,16 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
                                                double *__restrict__ rowpart)
 {
     constexpr int E = Q * VEC;
+    constexpr bool LO = lo_tile(NT, Q, VEC);
     using Red3 = BlockRed<NT, OP_SUM, OP_MIN, OP_MIN>;
     __shared__ double lds[Red3::LDS];
-    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    extern __shared__ double wl[];   // w staged in LDS (n doubles, then the FP32 low parts)
     int parity = 0;
     int i0, i1;
     row_range(m, i0, i1);
     __shared__ double etab[EXP_TAB];
     exp_table_init(etab);
-    stage_lds(w, n, wl);
+    stage_w2<LO>(w, wlo, n, wl);
     constexpr int RCA = 32;   // rows per staged chunk (static LDS within 3.5 KB)
     __shared__ double rM[RCA], rS[RCA], rA[RCA], rZ[RCA];
     double azg = 0.0, azp = 0.0;
@@ -127,7 +131,9 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
                 np = pv[jn];
             }
             const double c = valid ? (double)cst[e] : 0.0;
-            const double Xv = exp_tab(valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY, etab) * aS;
+            const double Xv =
+                exp_tab(valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY,
+                        etab) * aS;
             red[0] = fma(Xv, yj, red[0]);
             red[1] = fmin(red[1], valid ? c - gj : INFINITY);
             red[2] = fmin(red[2], valid ? c - pj : INFINITY);
@@ -154,6 +160,7 @@ template <int NT, int Q, int QF, int VEC, typename CT>
 __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                                double sigma, const double *__restrict__ w,
+                                               const double *__restrict__ wlo,
                                                const double *__restrict__ a,
                                                const double *__restrict__ M,
                                                const double *__restrict__ S,
@@ -168,16 +175,17 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
                                                double *__restrict__ rowpart)
 {
     constexpr int E = Q * VEC;
+    constexpr bool LO = lo_tile(NT, Q, VEC);
     using RedEnd = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_SUM, OP_MIN, OP_SUM, OP_SUM>;
     __shared__ double lds[RedEnd::LDS1];
-    extern __shared__ double wl[];   // w staged in LDS (n doubles)
+    extern __shared__ double wl[];   // w staged in LDS (n doubles, then the FP32 low parts)
     int i0, i1;
     row_range(m, i0, i1);
     __shared__ double etab[EXP_TAB];
     __shared__ __align__(16) double ltab[2 * LOG_TAB];
     log_table_init(ltab);
     exp_table_init(etab);   // its barrier also publishes ltab
-    stage_lds(w, n, wl);
+    stage_w2<LO>(w, wlo, n, wl);
     // 8 rows per staged chunk: with an n-vector of 20000 doubles the static LDS (exp and log
     // tables, reduction buffer, row scalars: 3328 bytes) must stay within 3.5 KB
     constexpr int RC = 8;
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
                 ng = gv[jn];
             }
             const double c = valid ? (double)cst[e] : 0.0;
-            const double xa = valid ? fma(-sigma, c, wl[j] - Mi) : -INFINITY;
+            const double xa = valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY;
             const double Xv = exp_tab(xa, etab) * aS;
             const double f = (zi * Xv) * yj;
             const double xh = valid ? fma(es, ecj, f) : 0.0;
@@ -345,13 +353,13 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
                         double *z, double *colpart, double *colpart2, double *rowpart,
                         hipStream_t st)
 {
-    const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                     \
     static LdsCache lc_; \
+    const size_t lds_bytes = lds_w2(d.n, lo_tile(NT, Q, VEC)); \
     if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
     hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S, z,   \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, z,   \
                        colpart, colpart2, rowpart)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)
@@ -363,9 +371,9 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
 hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
                         const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st)
 {
-    const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define BODY                                                                                      \
     static LdsCache lca_, lcb_;                                                                   \
+    const size_t lds_bytes = lds_w2(d.n, lo_tile(NT, Q, VEC));                                    \
     if (hipError_t e_ = lds_check((const void *)k_stop2a<NT, Q, QF, VEC, CT>, lds_bytes, lca_);   \
         e_ != hipSuccess)                                                                         \
         return e_;                                                                                \
@@ -373,10 +381,10 @@ hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, c
         e_ != hipSuccess)                                                                         \
         return e_;                                                                                \
     hipLaunchKernelGGL((k_stop2a<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, \
                        v.gamma, v.psi, v.y, v.z, v.er_row, v.zg_row, rowpart);                    \
     hipLaunchKernelGGL((k_stop2b<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.a, M, S,       \
+                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, \
                        v.gamma, v.y, v.ec, v.z, v.er_row, v.zg_row, v.er1, xhat, rowpart)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)

@@ -21,6 +21,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
                                               const double *__restrict__ py, double pscale, int m, int n,
                                               double sigma, double qg,
                                               const double *__restrict__ w,
+                                              const double *__restrict__ wlo,
                                               const double *__restrict__ a,
                                               const double *__restrict__ Mb,
                                               const double *__restrict__ colv,
@@ -30,6 +31,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
                                               double *__restrict__ rowpart, int flags)
 {
     constexpr int E = Q * VEC;
+    constexpr bool LO = lo_tile(NT, Q, VEC);
     using Red = BlockRed<NT, OP_SUM, OP_SUM, OP_SUM, OP_MAX>;
     __shared__ double lds[Red::LDS];
     int parity = 0;
@@ -38,14 +40,14 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
     if (!((flags >> (int)scal[SC_BIG]) & 1))
         return;   // another launch of the trial handles this step
     const double tau_shift = scal[SC_TAUSHIFT];
-    extern __shared__ double cvl[];   // colv staged in LDS (n doubles)
+    extern __shared__ double cvl[];   // colv staged in LDS (n doubles, then the low parts of w)
     __shared__ double etab[EXP_TAB];
     __shared__ double rM[ROWCH], rA[ROWCH];
     double wr[E], acc[E];
     xval_t<MX> x[E];
     exp_table_init(etab);
     load_w<NT, Q, VEC>(w, n, wr);   // padding slots: -inf, so q = 0 there
-    stage_lds(colv, n, cvl);
+    stage_w2<LO>(colv, wlo, n, cvl);
 #pragma unroll
     for (int e = 0; e < E; ++e)
         acc[e] = 0.0;
@@ -64,8 +66,10 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         double red[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const double q = exp_pass<MX>(fma(-sigma, (double)xr[e], wr[e] - Mi), etab);
-            const double cv = cvl[slot_col<QF, NT, VEC>(e, n) + zo];   // finite; q = 0 on padding
+            const int j = slot_col<QF, NT, VEC>(e, n) + zo;
+            const double q =
+                exp_pass<MX>(add_lo<LO>(fma(-sigma, (double)xr[e], wr[e] - Mi), cvl, n, j), etab);
+            const double cv = cvl[j];   // finite; q = 0 on padding
             red[1] += q;
             double qe;
             if constexpr (BIG) {
@@ -110,14 +114,15 @@ hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M
                         double *rowpart, hipStream_t st)
 {
     const RowPlan p = heavy_plan(p_in);
-    const size_t lds_bytes = (size_t)d.n * sizeof(double);
 #define LAUNCH_TRIAL(MXV, BIGV, FLAGS, LC)                                                        \
-    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>, lds_bytes, LC); \
+    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>,          \
+                                  lds_w2(d.n, lo_tile(NT, Q, VEC)), LC);                          \
         e_ != hipSuccess)                                                                         \
         return e_;                                                                                \
-    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>), dim3(p.grid), dim3(NT),         \
+                       lds_w2(d.n, lo_tile(NT, Q, VEC)), st,                                      \
                        (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, \
-                       d.a, M, colv, scal, M_new, S_new, colpart, rowpart, FLAGS)
+                       d.wlo, d.a, M, colv, scal, M_new, S_new, colpart, rowpart, FLAGS)
     // FP64: the small form for flags 0 and 2, the shifted form for flag 1.  Mixed: the FP32
     // small form for flag 0 only; flags 2 and 1 run the FP64 forms.
 #define BODY                                                                                      \

@@ -60,7 +60,7 @@ struct ibsn_ctx {
     size_t max_lds = 65536;
     std::string err;
     // workspace
-    DevBuf w, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
+    DevBuf w, wlo, lcv, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
     DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
@@ -240,6 +240,8 @@ int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
 {
     const size_t n = (size_t)p->n, m = (size_t)p->m, G = (size_t)rp.grid;
     CKI(ensure(ctx, ctx->w, n * 8));
+    CKI(ensure(ctx, ctx->wlo, n * 8));
+    CKI(ensure(ctx, ctx->lcv, n * 8));
     CKI(ensure(ctx, ctx->colpart, G * n * 8));
     CKI(ensure(ctx, ctx->colpart2, G * n * 8));
     CKI(ensure(ctx, ctx->rowpart, G * STOP2_NSLOT * 8));
@@ -274,8 +276,16 @@ DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k, double q, 
     d.pdim = p->cost_kind == IBSN_COST_POINTS ? (int)p->ldc : 0;
     d.sigma = (double)(k + 1) / p->eta;
     d.w = P<double>(ctx->w);
+    d.wlo = P<double>(ctx->wlo);
     d.a = p->a;
     return d;
+}
+
+// whether the dense passes of this problem carry the low parts of the potentials: every
+// tile except the FP32-cost ones wider than LO_MAX_COLS columns
+int lo_split(const ibsn_problem *p)
+{
+    return (p->cost_kind != IBSN_COST_F32 || p->n <= LO_MAX_COLS) ? 1 : 0;
 }
 
 int read_scal(ibsn_ctx *ctx, int count = SC_NSLOT)
@@ -383,7 +393,7 @@ int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q, mixed);
     double *scal = P<double>(ctx->scal);
-    CKH(sk_trial_prep(p->n, t, p->eta, q, Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
+    CKH(sk_trial_prep(p->n, t, p->eta, q, lo_split(p), Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
                       scal, st));
     {
         KTimer kt(ctx, mixed ? IBSN_KT_TRIAL_MIXED : IBSN_KT_TRIAL);
@@ -417,7 +427,7 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     }
     CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, colX, nullptr, nullptr, st));
     CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, p->n, colF, nullptr, nullptr, st));
-    CKH(sk_stop_prep(p->n, d.sigma, p->b, d.w, gamma, colX, colF, P<double>(ctx->yv),
+    CKH(sk_stop_prep(p->n, d.sigma, p->b, d.w, d.wlo, gamma, colX, colF, P<double>(ctx->yv),
                      P<double>(ctx->ecv), P<double>(ctx->psiv), scal, st));
     Stop2Vec v;
     v.gamma = gamma;
@@ -702,7 +712,7 @@ void ibsn_destroy(ibsn_ctx *ctx)
         c->ctx = nullptr;
     }
     ctx->csrs.clear();
-    DevBuf *bufs[] = {&ctx->w, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
+    DevBuf *bufs[] = {&ctx->w, &ctx->wlo, &ctx->lcv, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
                       &ctx->psiv, &ctx->zv, &ctx->erv, &ctx->zgv, &ctx->stopout, &ctx->tauv,
                       &ctx->cg_x, &ctx->cg_r, &ctx->cg_r2,
@@ -831,8 +841,8 @@ int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cen
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
-                      ctx->stream));
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+                      P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream));
     CKI(run_eval(ctx, prob, rp, ctr->k, ctr->quantum, obj_host ? ctr->r : nullptr, gamma, M, S,
                  lse, colmarg,
                  grad, plan, prob->precision));
@@ -857,8 +867,8 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, 
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
-                      ctx->stream));
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+                      P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream));
     CKI(run_trial(ctx, prob, rp, ctr->k, ctr->quantum, M, Delta, t, M_new, S_new, colmarg_new,
                   grad_new, prob->precision));
     CKI(read_scal(ctx));
@@ -906,8 +916,8 @@ int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ct
             rc = hipStreamSynchronize(ctx->stream) == hipSuccess ? IBSN_OK : IBSN_ERR_HIP;
     }
     if (rc == IBSN_OK) {
-        if (launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
-                          ctx->stream) != hipSuccess)
+        if (launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+                          P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream) != hipSuccess)
             rc = fail(ctx, IBSN_ERR_HIP, "make_w failed");
     }
     if (rc == IBSN_OK)
@@ -1048,8 +1058,8 @@ int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, c
     CKH(sk_dot_slot(prob->m, prob->a, nullptr, SC_SUMA, P<double>(ctx->scal), ctx->stream));
     CKH(sk_dot_slot(prob->m, prob->a, prob->a, SC_AA, P<double>(ctx->scal), ctx->stream));
     CKH(sk_dot_slot(prob->n, prob->b, prob->b, SC_BB, P<double>(ctx->scal), ctx->stream));
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, P<double>(ctx->w),
-                      ctx->stream));
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+                      P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream));
     CKI(run_stop(ctx, prob, rp, ctr->k, ctr->quantum, gamma, M, S, xhat));
     CKH(hipMemcpyAsync(out_host, ctx->stopout.p, sizeof(double) * 10, hipMemcpyDeviceToHost,
                        ctx->stream));
@@ -1177,7 +1187,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     const double cmax = ctx->host_scal[SC_CMAX];
     if (!std::isfinite(cmax))
         CKS(fail(ctx, IBSN_ERR_NUMERIC, "C has a NaN or infinite entry"));
-    double *w = P<double>(ctx->w);
+    double *w = P<double>(ctx->w), *wlo = P<double>(ctx->wlo), *lc = P<double>(ctx->lcv);
+    const int split = lo_split(prob);
     // Mixed precision: Newton steps run their passes (sparsify, trial) in the FP32 form
     // while ||g||_2 >= mixed_switch * eps32 * ||b||_2; below that, after a mixed-form line
     // search fails, and always for the Sinkhorn steps, the stop test and the outer update,
@@ -1246,7 +1257,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         CKSH(sk_wmax(n, s, gamma, eta, scal, st));
         CKS(read_scal(ctx));
         const double q = quantum_of(ctx->host_scal[SC_WMAX] + sigma * cmax);
-        CKSH(launch_make_w(s, gamma, q, eta, n, w, st));
+        CKSH(launch_make_w(s, gamma, q, eta, n, split, w, wlo, st));
         bool state_mx = false;   // (M, S, c, g) come from a mixed-precision pass
         bool fp64_lock = false;  // FP64 passes for the rest of this subproblem
         auto refresh = [&]() -> int {   // FP64 eval at the current point
@@ -1269,7 +1280,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         // Sinkhorn warm-up (Algorithm 2, steps 3-4), on the grid potentials
         for (int it = 0; it < opt.sinkhorn_maxit && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol;
              ++it) {
-            CKSH(sk_sinkhorn_step(n, eta, q, prob->b, c, s, w, st));
+            CKSH(sk_log(n, c, lc, st));
+            CKSH(sk_sinkhorn_step(n, eta, q, split, prob->b, lc, s, w, wlo, st));
             CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr, 0));
             ++R.passes;
             ++R.sinkhorn;
@@ -1353,8 +1365,9 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                 R.t_linesearch += now_s() - ta;
                 break;
             }
-            // step 10 on the grid: w += tau is exact; the accepted trial is the new iterate
-            CKSH(sk_axpy(n, 1.0, P<double>(ctx->tauv), w, st));
+            // step 10: w += tau, exactly in the two-level potential (on the grid when the
+            // potentials are kept there); the accepted trial is the new iterate
+            CKSH(sk_dd_axpy(n, q, P<double>(ctx->tauv), w, wlo, st));
             std::swap(M, Mt);
             std::swap(S, St);
             std::swap(c, ct);
@@ -1368,7 +1381,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                 CKS(refresh());
             if (!opt.eot && ctx->host_scal[SC_GN] < mu) {
                 ta = now_s();
-                CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
+                CKSH(sk_gamma_of(n, eta, w, wlo, s, gamma, st));
                 CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
                 R.passes += 2;
                 ++R.stop_tests;
@@ -1386,7 +1399,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         }
         if (state_mx)
             CKS(refresh());
-        CKSH(sk_gamma_of(n, eta, w, s, gamma, st));
+        CKSH(sk_gamma_of(n, eta, w, wlo, s, gamma, st));
         if (!stopped || opt.eot) {
             ta = now_s();
             CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
@@ -1422,7 +1435,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             R.passes += 2;
         }
         // step 13: X^{k+1} = X^{k,v+1}, i.e. r = log a - lse, s = w; k = k+1; gamma kept
-        CKSH(sk_outer_update(m, n, prob->a, M, S, w, r, s, st));
+        CKSH(sk_outer_update(m, n, prob->a, M, S, w, wlo, r, s, st));
         record(stopped);
         if (done) {
             R.status = IBSN_OK;

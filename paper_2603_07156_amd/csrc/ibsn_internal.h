@@ -23,6 +23,14 @@ bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *plan);
 // the same plan with the heavy tile (trial, sparsify, stop pass 2) as the tile
 RowPlan heavy_plan(const RowPlan &p);
 
+// Two-level potentials: w_j = wh_j + wl_j with wh on the grid of spacing q and wl the
+// remainder (|wl| <= q/2 plus rounding).  The dense passes stage wl as FP32 after the n
+// doubles they stage; a tile spanning more than LO_MAX_COLS columns (FP32 cost beyond
+// that many columns) has no LDS left for it, and there the host keeps wl = 0 (potentials
+// and steps rounded to the grid).
+constexpr int LO_MAX_COLS = 12288;
+__host__ __device__ constexpr bool lo_tile(int nt, int q, int vec) { return nt * q * vec <= LO_MAX_COLS; }
+
 struct DenseArgs {
     const void *C;            // the cost, or x (m x pdim) for points
     int64_t ldc;
@@ -33,7 +41,8 @@ struct DenseArgs {
     int cost_kind;
     double sigma;           // (k+1)/eta
     double q;               // grid spacing of the potentials (power of two)
-    const double *w;        // n: grid(s + gamma/eta)
+    const double *w;        // n: high part of the potentials, on the grid
+    const double *wlo;      // n: low part (zero where the tile has no room for it)
     const double *a;        // m
     int mixed;              // 1: FP32 exponentials and FP32 sparse values (eval, trial,
                             // sparsify); sums, shifts and row state stay FP64
@@ -88,9 +97,10 @@ hipError_t launch_colreduce(const double *part, int G, int64_t n, double *out, c
                             double *out2, hipStream_t st);
 
 // ---- small vector / scalar kernels ----------------------------------------------
-// w_j = grid(s_j + gamma_j / eta) with spacing q (gamma may be null)
+// w = s + gamma/eta as a two-level potential (w on the grid of spacing q, wlo the rest);
+// split = 0: w = grid(s + gamma/eta), wlo = 0.  gamma may be null.
 hipError_t launch_make_w(const double *s, const double *gamma, double q, double eta, int64_t n,
-                         double *w, hipStream_t st);
+                         int split, double *w, double *wlo, hipStream_t st);
 // out[0] = sum_i x_i (fixed order) for up to n values, single workgroup
 hipError_t launch_sum(const double *x, int64_t n, double *out, hipStream_t st);
 // out[0] = sum_i x_i * y_i (fixed order), single workgroup

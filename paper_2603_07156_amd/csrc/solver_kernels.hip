@@ -69,27 +69,72 @@ __global__ __launch_bounds__(NT) void k_gnorms(int n, const double *__restrict__
 
 __device__ __forceinline__ double grid(double v, double q) { return q * rint(v / q); }
 
+// Add d to the two-level potential (wh, wl): u = wl + d with its rounding error e (two-sum),
+// wh += grid(u) (exact: both on the grid), wl = (u - grid(u)) + e.  With wl = 0 and d on the
+// grid (potentials kept on the grid) this is wh += d, wl = 0.
+__device__ __forceinline__ void dd_add(double &wh, double &wl, double d, double q)
+{
+    const double u = wl + d;
+    const double bb = u - wl;
+    const double e = (wl - (u - bb)) + (d - bb);
+    const double g = grid(u, q);
+    wh += g;
+    wl = (u - g) + e;
+}
+
 // Sinkhorn gamma-step on Z^k with zeta = zeta(gamma) (eq. (4), (5)):
 // gamma_j += eta (log b_j - log c_j), taken on the potentials w = s + gamma/eta as
-// w_j += grid(log b_j - log c_j); then gamma = eta (w - s) is centred (Algorithm 2,
-// step 4) by a grid shift of w, which leaves P unchanged.
-__global__ __launch_bounds__(NT) void k_sinkhorn_step(int n, double eta, double q,
+// w_j += log b_j - lc_j with lc_j = log c_j (split = 0: the step rounded to the grid); then
+// gamma = eta (w - s) is centred (Algorithm 2, step 4) by a common shift of w, which leaves
+// P unchanged.
+__global__ __launch_bounds__(NT) void k_sinkhorn_step(int n, double eta, double q, int split,
                                                       const double *__restrict__ b,
-                                                      const double *__restrict__ c,
+                                                      const double *__restrict__ lc,
                                                       const double *__restrict__ s,
-                                                      double *__restrict__ w)
+                                                      double *__restrict__ w,
+                                                      double *__restrict__ wlo)
 {
     __shared__ double lds[NW];
     double acc = 0.0;
     for (int j = threadIdx.x; j < n; j += NT) {
-        const double v = w[j] + grid(log(b[j]) - log(c[j]), q);
-        w[j] = v;
-        acc += eta * (v - s[j]);
+        const double d0 = log(b[j]) - lc[j];
+        double wh = w[j], wl = wlo[j];
+        dd_add(wh, wl, split ? d0 : grid(d0, q), q);
+        w[j] = wh;
+        wlo[j] = wl;
+        acc += eta * ((wh - s[j]) + wl);
     }
     acc = wg_red<0>(acc, lds);
-    const double sh = grid((acc / (double)n) / eta, q);
-    for (int j = threadIdx.x; j < n; j += NT)
-        w[j] -= sh;
+    const double sh0 = (acc / (double)n) / eta;
+    const double sh = split ? -sh0 : -grid(sh0, q);
+    for (int j = threadIdx.x; j < n; j += NT) {
+        double wh = w[j], wl = wlo[j];
+        dd_add(wh, wl, sh, q);
+        w[j] = wh;
+        wlo[j] = wl;
+    }
+}
+
+// (wh, wl) += d over n columns (the accepted Newton step)
+__global__ __launch_bounds__(256) void k_dd_axpy(int n, double q, const double *__restrict__ d,
+                                                 double *__restrict__ w, double *__restrict__ wlo)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) {
+        double wh = w[j], wl = wlo[j];
+        dd_add(wh, wl, d[j], q);
+        w[j] = wh;
+        wlo[j] = wl;
+    }
+}
+
+// log c_j from the eval's column sums (the Sinkhorn step's lc)
+__global__ __launch_bounds__(256) void k_log(int n, const double *__restrict__ c,
+                                             double *__restrict__ lc)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n)
+        lc[j] = log(c[j]);
 }
 
 // scal[SC_WMAX] = max_j |s_j + gamma_j / eta|
@@ -150,14 +195,16 @@ __global__ __launch_bounds__(256) void k_cost_max_part(int m, int n, int64_t ldc
         part[g] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
 }
 
-// gamma = eta (w - s)
+// gamma = eta (w - s) with w = wh + wl (wh - s is exact: both are grid values of the
+// outer iteration or earlier ones, and their difference is small)
 __global__ __launch_bounds__(256) void k_gamma_of(int n, double eta, const double *__restrict__ w,
+                                                  const double *__restrict__ wlo,
                                                   const double *__restrict__ s,
                                                   double *__restrict__ gamma)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j < n)
-        gamma[j] = eta * (w[j] - s[j]);
+        gamma[j] = eta * ((w[j] - s[j]) + wlo[j]);
 }
 
 __global__ __launch_bounds__(NT) void k_center(int n, double *__restrict__ gamma)
@@ -172,12 +219,13 @@ __global__ __launch_bounds__(NT) void k_center(int n, double *__restrict__ gamma
         gamma[j] -= mean;
 }
 
-// Armijo step on the grid: tau_j = grid(t Delta_j / eta), so the trial point is w + tau
-// exactly.  Column factors: small step (max tau <= 500): colv = expm1(tau), shift 0;
+// Armijo step tau_j = t Delta_j / eta (split = 0: rounded to the grid, tau_j =
+// grid(t Delta_j / eta)); the trial point is w + tau, which the accepted step forms exactly
+// as a two-level potential.  Column factors: small step (max tau <= 500): colv = expm1(tau), shift 0;
 // big step: colv = exp(tau - max tau), shift = max tau.  scal[SC_TB] = b^T tau.
 // scal[SC_BIG] = 0 (max tau <= 80), 2 (80 < max tau <= 500: small form, but q e^tau can
 // exceed FLT_MAX, so the mixed form hands such a step to the FP64 pass) or 1 (big step).
-__global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, double q,
+__global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, double q, int split,
                                                    const double *__restrict__ Delta,
                                                    const double *__restrict__ b,
                                                    double *__restrict__ tau,
@@ -188,7 +236,8 @@ __global__ __launch_bounds__(NT) void k_trial_prep(int n, double t, double eta, 
     double mx = -INFINITY, bt = 0.0;
 #pragma unroll 4   // one workgroup: keep several loads in flight per thread
     for (int j = threadIdx.x; j < n; j += NT) {
-        const double v = grid(t * Delta[j] / eta, q);
+        const double v0 = t * Delta[j] / eta;
+        const double v = split ? v0 : grid(v0, q);
         tau[j] = v;
         mx = fmax(mx, v);
         bt = fma(b[j], v, bt);
@@ -246,10 +295,11 @@ __global__ __launch_bounds__(NT) void k_dot_slot(int n, const double *__restrict
 }
 
 // Algorithm 3 vectors after pass 1: y_j = min(b_j / colX_j, 1), e_c = b - y.colF,
-// ||e_r||_1 = sum a - sum_j y_j colF_j (sum of the rows of F), psi_j = (w_j - log b_j)/sigma,
-// column residual sum_j (colX_j - b_j)^2, b^T gamma, b^T psi.
+// ||e_r||_1 = sum a - sum_j y_j colF_j (sum of the rows of F), psi_j = (w_j - log b_j)/sigma
+// with w = wh + wl, column residual sum_j (colX_j - b_j)^2, b^T gamma, b^T psi.
 __global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const double *__restrict__ b,
                                                   const double *__restrict__ w,
+                                                  const double *__restrict__ wlo,
                                                   const double *__restrict__ gamma,
                                                   const double *__restrict__ colX,
                                                   const double *__restrict__ colF,
@@ -268,7 +318,7 @@ __global__ __launch_bounds__(NT) void k_stop_prep(int n, double sigma, const dou
         ec[j] = fmax(bj - fj, 0.0);   // >= 0 exactly (y <= 1, z <= 1); clamp rounding
         syf += fj;
         cc = fma(cx - bj, cx - bj, cc);
-        const double pj = (w[j] - log(bj)) / sigma;
+        const double pj = ((w[j] + wlo[j]) - log(bj)) / sigma;
         psi[j] = pj;
         bg = fma(bj, gamma[j], bg);
         bp = fma(bj, pj, bp);
@@ -352,11 +402,14 @@ __global__ __launch_bounds__(NT) void k_stop_final(int G, const double *__restri
 }
 
 // outer update of the implicit centre (Algorithm 2, step 13 with eq. (7)):
-// r_i = log a_i - (M_i + log S_i); s_j = w_j (= s_j + gamma_j / eta)
+// r_i = log a_i - (M_i + log S_i); s_j = w_j (= s_j + gamma_j / eta), rounded to one
+// double.  The rounding rescales the columns of the new centre X^{k+1} by factors
+// 1 + O(2^-53), which the next subproblem's dual absorbs: its optimal plan does not change.
 __global__ __launch_bounds__(256) void k_outer_update(int m, int n, const double *__restrict__ a,
                                                       const double *__restrict__ M,
                                                       const double *__restrict__ S,
                                                       const double *__restrict__ w,
+                                                      const double *__restrict__ wlo,
                                                       double *__restrict__ r,
                                                       double *__restrict__ s)
 {
@@ -364,7 +417,7 @@ __global__ __launch_bounds__(256) void k_outer_update(int m, int n, const double
     if (t < m)
         r[t] = log(a[t]) - (M[t] + log(S[t]));
     if (t < n)
-        s[t] = w[t];
+        s[t] = w[t] + wlo[t];
 }
 
 // r = log a, s = log b (X^0 = a b^T)
@@ -472,10 +525,21 @@ hipError_t sk_gnorms(int64_t n, const double *g, double *scal, hipStream_t st)
 {
     L1(k_gnorms, (int)n, g, scal);
 }
-hipError_t sk_sinkhorn_step(int64_t n, double eta, double q, const double *b, const double *c,
-                            const double *s, double *w, hipStream_t st)
+hipError_t sk_sinkhorn_step(int64_t n, double eta, double q, int split, const double *b,
+                            const double *lc, const double *s, double *w, double *wlo,
+                            hipStream_t st)
 {
-    L1(k_sinkhorn_step, (int)n, eta, q, b, c, s, w);
+    L1(k_sinkhorn_step, (int)n, eta, q, split, b, lc, s, w, wlo);
+}
+hipError_t sk_dd_axpy(int64_t n, double q, const double *d, double *w, double *wlo, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dd_axpy, dim3(nblk(n)), dim3(256), 0, st, (int)n, q, d, w, wlo);
+    return hipGetLastError();
+}
+hipError_t sk_log(int64_t n, const double *c, double *lc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_log, dim3(nblk(n)), dim3(256), 0, st, (int)n, c, lc);
+    return hipGetLastError();
 }
 hipError_t sk_wmax(int64_t n, const double *s, const double *gamma, double eta, double *scal,
                    hipStream_t st)
@@ -492,18 +556,18 @@ hipError_t sk_cost_max(int64_t m, int64_t n, int64_t ldc, int kind, const void *
                        1, scal);
     return hipGetLastError();
 }
-hipError_t sk_gamma_of(int64_t n, double eta, const double *w, const double *s, double *gamma,
-                       hipStream_t st)
+hipError_t sk_gamma_of(int64_t n, double eta, const double *w, const double *wlo, const double *s,
+                       double *gamma, hipStream_t st)
 {
     hipLaunchKernelGGL(k_gamma_of, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)n, eta,
-                       w, s, gamma);
+                       w, wlo, s, gamma);
     return hipGetLastError();
 }
 hipError_t sk_center(int64_t n, double *gamma, hipStream_t st) { L1(k_center, (int)n, gamma); }
-hipError_t sk_trial_prep(int64_t n, double t, double eta, double q, const double *Delta,
+hipError_t sk_trial_prep(int64_t n, double t, double eta, double q, int split, const double *Delta,
                          const double *b, double *tau, double *colv, double *scal, hipStream_t st)
 {
-    L1(k_trial_prep, (int)n, t, eta, q, Delta, b, tau, colv, scal);
+    L1(k_trial_prep, (int)n, t, eta, q, split, Delta, b, tau, colv, scal);
 }
 hipError_t sk_sum_parts(int G, int stride, int off, const double *part, double alpha, double beta,
                         int src, int slot, int op, double *scal, hipStream_t st)
@@ -516,10 +580,11 @@ hipError_t sk_dot_slot(int64_t n, const double *x, const double *y, int slot, do
     L1(k_dot_slot, (int)n, x, y, slot, scal);
 }
 hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *w,
-                        const double *gamma, const double *colX, const double *colF, double *y,
-                        double *ec, double *psi, double *scal, hipStream_t st)
+                        const double *wlo, const double *gamma, const double *colX,
+                        const double *colF, double *y, double *ec, double *psi, double *scal,
+                        hipStream_t st)
 {
-    L1(k_stop_prep, (int)n, sigma, b, w, gamma, colX, colF, y, ec, psi, scal);
+    L1(k_stop_prep, (int)n, sigma, b, w, wlo, gamma, colX, colF, y, ec, psi, scal);
 }
 hipError_t sk_stop_final(int G, const double *part, const double *rowres_part, int G1,
                          double *scal, double *out, hipStream_t st)
@@ -532,10 +597,10 @@ hipError_t sk_problem_scalars(int64_t m, int64_t n, const double *a, const doubl
     L1(k_problem_scalars, (int)m, (int)n, a, b, scal, istar);
 }
 hipError_t sk_outer_update(int64_t m, int64_t n, const double *a, const double *M, const double *S,
-                           const double *w, double *r, double *s, hipStream_t st)
+                           const double *w, const double *wlo, double *r, double *s, hipStream_t st)
 {
     hipLaunchKernelGGL(k_outer_update, dim3(nblk(m > n ? m : n)), dim3(256), 0, st, (int)m, (int)n,
-                       a, M, S, w, r, s);
+                       a, M, S, w, wlo, r, s);
     return hipGetLastError();
 }
 hipError_t sk_init_center(int64_t m, int64_t n, const double *a, const double *b, double *r,

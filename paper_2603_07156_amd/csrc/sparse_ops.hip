@@ -876,14 +876,30 @@ __global__ __launch_bounds__(1024) void k_dot(int n, const double *__restrict__ 
 }
 
 // w_j = grid(s_j + gamma_j / eta), grid(v) = q * rint(v / q)
+// w = s + gamma/eta as a two-level potential: wh = grid(s + d) with d = gamma/eta rounded,
+// wl = the rest, exactly up to one rounding at the size of wl: (s + d) - wh is exact, the
+// error of s + d comes from a two-sum and that of d from an fma residual.  split = 0: wh =
+// grid(s + gamma/eta), wl = 0 (potentials on the grid).
 __global__ __launch_bounds__(256) void k_make_w(int n, const double *__restrict__ s,
                                                 const double *__restrict__ gamma, double eta,
-                                                double q, double *__restrict__ w)
+                                                double q, int split, double *__restrict__ w,
+                                                double *__restrict__ wlo)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j < n) {
-        const double v = s[j] + (gamma ? gamma[j] / eta : 0.0);
-        w[j] = q * rint(v / q);
+        const double sj = s[j], gj = gamma ? gamma[j] : 0.0;
+        const double d = gj / eta;
+        const double t = sj + d;
+        const double wh = q * rint(t / q);
+        w[j] = wh;
+        if (split) {
+            const double rd = fma(-d, eta, gj);   // gamma - d eta, exactly
+            const double bb = t - sj;
+            const double e = (sj - (t - bb)) + (d - bb);
+            wlo[j] = ((t - wh) + e) + rd / eta;
+        } else {
+            wlo[j] = 0.0;
+        }
     }
 }
 
@@ -1156,10 +1172,10 @@ hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, int64_t n, h
 }
 
 hipError_t launch_make_w(const double *s, const double *gamma, double q, double eta, int64_t n,
-                         double *w, hipStream_t st)
+                         int split, double *w, double *wlo, hipStream_t st)
 {
     hipLaunchKernelGGL(k_make_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)n, s,
-                       gamma, eta, q, w);
+                       gamma, eta, q, split, w, wlo);
     return hipGetLastError();
 }
 

@@ -88,16 +88,16 @@ def dev_bound(C, s, gamma, eta, k, q, on_grid):
     """Bound on |x_gpu - x_plain| for one entry, x = theta - (row shift), where P matters
     (|x| <= 1024).  B bounds |theta|.  The plain side rounds sigma (u sigma max C), theta
     (u B) and theta - M (u |x|), and, off the grid, gamma/eta and s + gamma/eta (u each
-    at their size).  The grid side rounds s + gamma/eta the same way, then to the grid
-    (q/2), and x once (u |x|).  With w on the grid (gamma = 0, s a grid value) only the
-    plain side's sigma, theta and x roundings remain.  The row normaliser carries the same
-    error again, so P's relative deviation is below 2 dx + 1e-13 (exp and sums)."""
+    at their size).  The HIP side holds w = s + gamma/eta as a grid part plus a remainder
+    (exact up to the rounding of gamma/eta), stages the remainder as FP32 (q 2^-25) and
+    rounds x twice at |x|.  The row normaliser carries the same error again, so P's
+    relative deviation is below 2 dx + 1e-13 (exp and sums)."""
     sigma = (k + 1) / eta
     w = s + gamma / eta
     B = sigma * np.abs(C).max() + np.abs(w).max()
-    dx = U * (sigma * np.abs(C).max() + B + 2 * 1024)
+    dx = U * (sigma * np.abs(C).max() + B + 3 * 1024) + q * 2.0 ** -25
     if not on_grid:
-        dx += 2 * U * (np.abs(w).max() + np.abs(gamma / eta).max()) + q / 2
+        dx += U * (np.abs(w).max() + 2 * np.abs(gamma / eta).max())
     return dx
 
 

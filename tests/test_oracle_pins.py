@@ -261,35 +261,44 @@ def test_p11_cg_direction_in_complement(sparse_case):
 # ---------------------------------------------------------------------------
 # Armijo trial: exact algebra of the difference form
 # ---------------------------------------------------------------------------
-def test_trial_difference_form_matches_two_evals():
-    """The trial's dL is L(w + tau) - L(w) for the grid step tau = grid(t Delta / eta):
-    compare with two separate evaluations, and with the directional derivative for a
-    tiny step (where a difference of two rounded objectives would be pure noise)."""
+@pytest.mark.parametrize("split", [True, False])
+def test_trial_difference_form_matches_two_evals(split):
+    """The trial's dL is L(w + tau) - L(w) for the step tau = t Delta / eta (two-level
+    potentials; split=False: the grid step tau = grid(t Delta / eta)): compare with two
+    separate evaluations, and with the directional derivative for a tiny step (where a
+    difference of two rounded objectives would be pure noise)."""
     inst = W.gmm_points(30, 4, m=26)
     eta = 0.05
     gamma = W.random_dual(30, 6, 0.02)
     s = np.log(inst.b)
     r = np.log(inst.a)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, r=r, s=s)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, r=r, s=s, split=split)
     q = ev.q
+
+    def step(t):
+        return t * Delta / eta if split else q * np.rint(t * Delta / eta / q)
+
     Delta = W.random_dual(30, 8, 0.01)
     for t in (1.0, 0.8, 0.3, 1e-3):
         dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t,
-                                            s=s, q=q)
-        tau = q * np.rint(t * Delta / eta / q)
-        # the point whose grid potentials are exactly w + tau
-        gamma2 = eta * ((ev.w + tau) - s)
-        ev2 = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma2, r=r, s=s, q=q)
-        np.testing.assert_array_equal(ev2.w, ev.w + tau)
-        Lw = -inst.b @ (eta * (ev.w - s)) + eta * inst.a @ (r + ev.lse)
-        Lw2 = -inst.b @ (eta * (ev2.w - s)) + eta * inst.a @ (r + ev2.lse)
+                                            s=s, q=q, split=split)
+        tau = step(t)
+        # the point with potentials w + tau: gamma + eta tau (exact in split form up to the
+        # rounding of gamma + eta tau; exactly on the grid otherwise)
+        gamma2 = gamma + eta * tau if split else eta * ((ev.w + tau) - s)
+        ev2 = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma2, r=r, s=s, q=q, split=split)
+        if not split:
+            np.testing.assert_array_equal(ev2.w, ev.w + tau)
+        Lw = -inst.b @ gamma + eta * inst.a @ (r + ev.lse)
+        Lw2 = -inst.b @ gamma2 + eta * inst.a @ (r + ev2.lse)
         assert abs(dL - (Lw2 - Lw)) <= 1e-13 * (abs(Lw) + 1)
         np.testing.assert_allclose(cn, ev2.c, rtol=1e-12)
         np.testing.assert_allclose(Mn + np.log(Sn), ev2.lse, rtol=0, atol=1e-12)
     # tiny step (second-order term ~1e-19): dL recovers g^T (eta tau)
     t = 1e-8
-    tau = q * np.rint(t * Delta / eta / q)
-    dL, *_ = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t, s=s, q=q)
+    tau = step(t)
+    dL, *_ = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t, s=s, q=q,
+                            split=split)
     slope = ev.g @ (eta * tau)
     assert abs(dL - slope) <= 1e-6 * abs(slope)
 

@@ -286,27 +286,30 @@ def lse_ld(C, w, sigma):
     return M + np.log(np.exp(th - M[:, None]).sum(1))
 
 
+@pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("t,scale", [(1.0, 0.01), (1.0, 30.0), (0.5, 80.0)])
-def test_trial_branches_against_long_double(t, scale):
-    """orc_trial's dL = L(w + tau) - L(w) on the grid point, in its small-step form
-    (max tau <= 500, expm1/log1p) and its shifted form (max tau > 500), against two
-    evaluations of the objective in long double.  The row state it returns gives the
+def test_trial_branches_against_long_double(t, scale, split):
+    """orc_trial's dL = L(w + tau) - L(w), in its small-step form (max tau <= 500,
+    expm1/log1p) and its shifted form (max tau > 500), against two evaluations of the
+    objective in long double.  Two-level potentials (split): w + wl carried in long double,
+    tau = t Delta / eta; grid form: tau on the grid.  The row state it returns gives the
     trial point's normalisers."""
     inst = W.gmm_points(30, 4, m=26)
     eta = 0.05
     gamma = W.random_dual(30, 6, 0.02)
     s, r = np.log(inst.b), np.log(inst.a)
-    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, r=r, s=s)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, r=r, s=s, split=split)
     q = ev.q
     Delta = W.random_dual(30, 8, 1.0) * scale
     dL, Mn, Sn, cn, gn = orc.trial_pass(inst.C, inst.a, inst.b, eta, gamma, ev.M, Delta, t,
-                                        s=s, q=q)
-    tau = q * np.rint(t * Delta / eta / q)
+                                        s=s, q=q, split=split)
+    tau = t * Delta / eta if split else q * np.rint(t * Delta / eta / q)
     big = tau.max() > 500
     assert big == (scale > 10)
     sigma = 1.0 / eta
-    l0 = lse_ld(inst.C, ev.w, sigma)
-    l1 = lse_ld(inst.C, ev.w + tau, sigma)     # w + tau is exact on the grid
+    w0 = ev.w.astype(LD) + (ev.wl.astype(LD) if split else LD(0))
+    l0 = lse_ld(inst.C, w0, sigma)
+    l1 = lse_ld(inst.C, w0 + tau.astype(LD), sigma)
     dL_ld = -LD(eta) * (inst.b.astype(LD) * tau.astype(LD)).sum() \
         + LD(eta) * (inst.a.astype(LD) * (l1 - l0)).sum()
     scale_L = eta * (np.abs(inst.b @ tau) + np.abs(inst.a @ np.asarray(l1 - l0, np.float64)))
