@@ -158,6 +158,25 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
                double *dL_host, double *M_new, double *S_new, double *colmarg_new,
                double *grad_new);
 
+/* Sinkhorn gamma-step of the warm-up (Algorithm 2, steps 3-4), from the eval's row state
+   (M, S) and column sums colmarg = P^T a at gamma: gamma_out = gamma + eta (log b - log c),
+   then centred (sum_j gamma_out_j = 0; P is unchanged by the shift).  log c_j is formed in
+   the log domain, by a column log-sum-exp pass over C, when some c_j < 1e-290, so that a
+   column whose kernel entries all underflow still moves.  gamma_out (n) may alias gamma.
+   Synchronises (one scalar read). */
+int ibsn_sinkhorn_step(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                       const double *gamma, const double *M, const double *S,
+                       const double *colmarg, double *gamma_out);
+
+/* Outer update (Algorithm 2, step 13 with eq. (7)): the next centre X^{k+1} = diag(a) P at
+   gamma, from the row state (M, S) at gamma: r_out = log a - (M + log S) (m) and
+   s_out = s + gamma/eta (n, the two-level potential rounded to one double: a column
+   rescaling of X^{k+1} by 1 + O(2^-53), absorbed by the next subproblem's dual).  The
+   caller advances k.  r_out and s_out may alias ctr->r and ctr->s. */
+int ibsn_outer_update(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                      const double *gamma, const double *M, const double *S, double *r_out,
+                      double *s_out);
+
 /* Hessian sparsification, Algorithm 1, from the row state (M, S) at gamma:
    P_ij = exp(x_ij)/S_i; rows i != istar keep P_ij >= rho (inclusive) divided
    by their kept sum; row istar is kept whole.  istar < 0 selects argmax a (lowest

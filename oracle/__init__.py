@@ -102,6 +102,11 @@ def _declare(L):
     L.orc_stop.restype = ct.c_int
     L.orc_stop.argtypes = [i64, i64, vp, i32, i64, i64, dbl, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                            _dp, _dp]
+    L.orc_sinkhorn_step.restype = ct.c_int
+    L.orc_sinkhorn_step.argtypes = [i64, i64, vp, i32, i64, i64, dbl, dbl, _dp, _dp, _dp, _dp,
+                                    _dp, _dp, _dp, _dp]
+    L.orc_outer_update.restype = None
+    L.orc_outer_update.argtypes = [i64, i64, dbl, dbl, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_default_options.restype = None
     L.orc_default_options.argtypes = [ct.POINTER(Options)]
     L.orc_plain_eval.restype = ct.c_int
@@ -229,6 +234,31 @@ def trial_pass(C, a, b, eta, gamma, M, Delta, t, s=None, k=0, q=None, split=True
                          _p(gn))
     assert rc == 0, rc
     return dL.value, Mn, Sn, cn, gn
+
+
+def sinkhorn_step(C, a, b, eta, gamma, M, S, c, s, k=0, q=None):
+    """One Sinkhorn gamma-step (Algorithm 2, steps 3-4) from the eval (M, S, c) at gamma,
+    centred; log c in the log domain where a column sum underflows."""
+    C, kind = _cost(C)
+    m, n = C.shape
+    a, b, gamma, M, S, c, s = map(_f64, (a, b, gamma, M, S, c, s))
+    if q is None:
+        q = center_quantum(C, s, gamma, eta, k)
+    out = np.empty(n)
+    rc = lib().orc_sinkhorn_step(m, n, C.ctypes.data, kind, n, int(k), float(eta), float(q),
+                                 _p(s), _p(gamma), _p(a), _p(b), _p(M), _p(S), _p(c), _p(out))
+    assert rc == 0
+    return out
+
+
+def outer_update(a, eta, gamma, M, S, s, q):
+    """The next centre (r, s) from the row state (M, S) at gamma (Algorithm 2, step 13)."""
+    a, gamma, M, S, s = map(_f64, (a, gamma, M, S, s))
+    m, n = len(a), len(s)
+    r_out, s_out = np.empty(m), np.empty(n)
+    lib().orc_outer_update(m, n, float(eta), float(q), _p(a), _p(M), _p(S), _p(s), _p(gamma),
+                           _p(r_out), _p(s_out))
+    return r_out, s_out
 
 
 @dataclass

@@ -688,6 +688,99 @@ int orc_stop(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t
 }
 
 /* ------------------------------------------------------------------------- */
+/* Sinkhorn gamma-step (Algorithm 2, steps 3-4; eqs. (4)-(5) in semi-dual form):       */
+/*   gamma_j += eta (log b_j - log c_j),  c_j = sum_i a_i P_ij,                         */
+/* then gamma is centred.  On the potentials: w_j += log b_j - log c_j and a common     */
+/* shift (which leaves P unchanged).  When some c_j is at or below the bottom of the    */
+/* FP64 range (every entry of column j underflows), log c_j is taken in the log domain: */
+/*   log c_j = max_i v_ij + log sum_i exp(v_ij - max_i v_ij),  v_ij = x_ij + log a_i - log S_i. */
+/* ------------------------------------------------------------------------- */
+static void log_colsums(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, double sigma,
+                        const double *w, const double *wl, const double *a, const double *M,
+                        const double *S, const double *c, double *lc)
+{
+    double cmin = INFINITY;
+    for (int64_t j = 0; j < n; ++j)
+        if (c[j] < cmin)
+            cmin = c[j];
+    if (!(cmin < 1e-290)) {
+        for (int64_t j = 0; j < n; ++j)
+            lc[j] = log(c[j]);
+        return;
+    }
+    double *rho = malloc(sizeof(double) * m);
+    for (int64_t i = 0; i < m; ++i)
+        rho[i] = log(a[i]) - log(S[i]);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        double mx = -INFINITY;
+        for (int64_t i = 0; i < m; ++i) {
+            double v = xval(C, kind, ldc, i, j, sigma, w, wl, M[i]) + rho[i];
+            if (v > mx)
+                mx = v;
+        }
+        double sum = 0.0;
+        for (int64_t i = 0; i < m; ++i)
+            sum += exp((xval(C, kind, ldc, i, j, sigma, w, wl, M[i]) + rho[i]) - mx);
+        lc[j] = mx + log(sum);
+    }
+    free(rho);
+}
+
+/* one gamma-step on the two-level potentials (w, wl) from the eval's row state (M, S) and
+   column sums c at (w, wl); s is the centre's column potential (gamma = eta (w + wl - s)) */
+static void sinkhorn_update(int64_t m, int64_t n, const void *C, int kind, int64_t ldc,
+                            int64_t k, double eta, double q, double *w, double *wl,
+                            const double *s, const double *a, const double *b, const double *M,
+                            const double *S, const double *c)
+{
+    const double sigma = (double)(k + 1) / eta;
+    double *lc = malloc(sizeof(double) * n);
+    log_colsums(m, n, C, kind, ldc, sigma, w, wl, a, M, S, c, lc);
+    for (int64_t j = 0; j < n; ++j)
+        pot_add(&w[j], &wl[j], log(b[j]) - lc[j], q);
+    /* step 4: centre gamma by a common shift of w */
+    double mean = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        mean += eta * ((w[j] - s[j]) + wl[j]);
+    mean /= (double)n;
+    for (int64_t j = 0; j < n; ++j)
+        pot_add(&w[j], &wl[j], -(mean / eta), q);
+    free(lc);
+}
+
+/* Exported step: gamma_out = the Sinkhorn step from gamma at the centre (k, s) on the grid q,
+   given the eval's row state (M, S) and column sums c at gamma. */
+int orc_sinkhorn_step(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, int64_t k,
+                      double eta, double q, const double *s, const double *gamma, const double *a,
+                      const double *b, const double *M, const double *S, const double *c,
+                      double *gamma_out)
+{
+    double *w = malloc(sizeof(double) * n), *wl = malloc(sizeof(double) * n);
+    orc_make_w(n, s, gamma, eta, q, w, wl);
+    sinkhorn_update(m, n, C, kind, ldc, k, eta, q, w, wl, s, a, b, M, S, c);
+    for (int64_t j = 0; j < n; ++j)
+        gamma_out[j] = eta * ((w[j] - s[j]) + wl[j]);
+    free(w); free(wl);
+    return ORC_OK;
+}
+
+/* Outer update (Algorithm 2, step 13 with eq. (7)): X^{k+1} = diag(a) P(gamma), i.e.
+   r_i = log a_i - (M_i + log S_i) and s_j = s_j + gamma_j / eta (one double), k + 1. */
+void orc_outer_update(int64_t m, int64_t n, double eta, double q, const double *a,
+                      const double *M, const double *S, const double *s, const double *gamma,
+                      double *r_out, double *s_out)
+{
+    double *w = malloc(sizeof(double) * n), *wl = malloc(sizeof(double) * n);
+    orc_make_w(n, s, gamma, eta, q, w, wl);
+    for (int64_t i = 0; i < m; ++i)
+        r_out[i] = log(a[i]) - (M[i] + log(S[i]));
+    for (int64_t j = 0; j < n; ++j)
+        s_out[j] = w[j] + wl[j];
+    free(w); free(wl);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Full IBSN (Algorithm 2) with the practical schedule of Section 5 "Setup".        */
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -832,17 +925,8 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
            LSE of the eval pass, the gamma-step rescales the columns to b) */
         orc_eval(m, n, C, kind, ldc, k, eta, q, w, wl, NULL, NULL, a, b, M, S, c, g, NULL, NULL);
         for (int it = 0; it < opt.sinkhorn_maxit && nrm2(n, g) >= opt.sinkhorn_tol; ++it) {
-            /* gamma_j += eta (log b_j - log c_j), i.e. w_j += log b_j - log c_j */
-            for (int64_t j = 0; j < n; ++j)
-                pot_add(&w[j], &wl[j], lb[j] - log(c[j]), q);
-            /* step 4: centre gamma = eta (w - s) by a common shift of w (P is unchanged) */
-            gamma_of(n, w, wl, s, eta, gamma);
-            double mean = 0.0;
-            for (int64_t j = 0; j < n; ++j)
-                mean += gamma[j];
-            mean /= (double)n;
-            for (int64_t j = 0; j < n; ++j)
-                pot_add(&w[j], &wl[j], -(mean / eta), q);
+            /* gamma_j += eta (log b_j - log c_j), then centred (steps 3-4) */
+            sinkhorn_update(m, n, C, kind, ldc, k, eta, q, w, wl, s, a, b, M, S, c);
             orc_eval(m, n, C, kind, ldc, k, eta, q, w, wl, NULL, NULL, a, b, M, S, c, g, NULL,
                      NULL);
             ++R.sinkhorn;

@@ -60,7 +60,7 @@ struct ibsn_ctx {
     size_t max_lds = 65536;
     std::string err;
     // workspace
-    DevBuf w, wlo, lcv, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
+    DevBuf w, wlo, lcv, clpart, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
     DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
@@ -242,6 +242,7 @@ int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
     CKI(ensure(ctx, ctx->w, n * 8));
     CKI(ensure(ctx, ctx->wlo, n * 8));
     CKI(ensure(ctx, ctx->lcv, n * 8));
+    CKI(ensure(ctx, ctx->clpart, 2 * (size_t)COLLSE_MAX_RB * n * 8));
     CKI(ensure(ctx, ctx->colpart, G * n * 8));
     CKI(ensure(ctx, ctx->colpart2, G * n * 8));
     CKI(ensure(ctx, ctx->rowpart, G * STOP2_NSLOT * 8));
@@ -712,7 +713,7 @@ void ibsn_destroy(ibsn_ctx *ctx)
         c->ctx = nullptr;
     }
     ctx->csrs.clear();
-    DevBuf *bufs[] = {&ctx->w, &ctx->wlo, &ctx->lcv, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
+    DevBuf *bufs[] = {&ctx->w, &ctx->wlo, &ctx->lcv, &ctx->clpart, &ctx->colpart, &ctx->colpart2, &ctx->rowpart, &ctx->rowpart2,
                       &ctx->scal, &ctx->colv, &ctx->cvec, &ctx->gvec, &ctx->yv, &ctx->ecv,
                       &ctx->psiv, &ctx->zv, &ctx->erv, &ctx->zgv, &ctx->stopout, &ctx->tauv,
                       &ctx->cg_x, &ctx->cg_r, &ctx->cg_r2,
@@ -873,6 +874,58 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, 
                   grad_new, prob->precision));
     CKI(read_scal(ctx));
     *dL_host = ctx->host_scal[SC_DL];
+    return IBSN_OK;
+}
+
+int ibsn_sinkhorn_step(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                       const double *gamma, const double *M, const double *S,
+                       const double *colmarg, double *gamma_out)
+{
+    CKI(check_problem(ctx, prob));
+    CKI(check_center(ctx, ctr));
+    if (!gamma || !M || !S || !colmarg || !gamma_out)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "gamma, M, S, colmarg and gamma_out are required");
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    hipStream_t st = ctx->stream;
+    const int64_t m = prob->m, n = prob->n;
+    const int split = lo_split(prob);
+    double *w = P<double>(ctx->w), *wlo = P<double>(ctx->wlo), *lc = P<double>(ctx->lcv);
+    double *scal = P<double>(ctx->scal);
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, n, split, w, wlo, st));
+    CKH(sk_sum_parts((int)n, 1, 0, colmarg, 1.0, 0.0, -1, SC_CMIN, 2, scal, st));
+    CKI(read_scal(ctx));
+    if (ctx->host_scal[SC_CMIN] < 1e-290) {
+        const int RB = collse_row_blocks(m, n, COLLSE_MAX_RB);
+        double *pm = P<double>(ctx->clpart);
+        CKH(launch_collse(dense_args(ctx, prob, ctr->k, ctr->quantum), split, M, S, RB, pm,
+                          pm + (size_t)RB * n, lc, st));
+    } else {
+        CKH(sk_log(n, colmarg, lc, st));
+    }
+    CKH(sk_sinkhorn_step(n, prob->eta, ctr->quantum, split, prob->b, lc, ctr->s, w, wlo, st));
+    CKH(sk_gamma_of(n, prob->eta, w, wlo, ctr->s, gamma_out, st));
+    return IBSN_OK;
+}
+
+int ibsn_outer_update(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr,
+                      const double *gamma, const double *M, const double *S, double *r_out,
+                      double *s_out)
+{
+    CKI(check_problem(ctx, prob));
+    CKI(check_center(ctx, ctr));
+    if (!gamma || !M || !S || !r_out || !s_out)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "gamma, M, S, r_out and s_out are required");
+    CKH(hipSetDevice(ctx->device));
+    RowPlan rp;
+    CKI(plan_for(ctx, prob, &rp));
+    CKI(ensure_ws(ctx, prob, rp));
+    double *w = P<double>(ctx->w), *wlo = P<double>(ctx->wlo);
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob), w, wlo,
+                      ctx->stream));
+    CKH(sk_outer_update(prob->m, prob->n, prob->a, M, S, w, wlo, r_out, s_out, ctx->stream));
     return IBSN_OK;
 }
 
@@ -1273,18 +1326,34 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         if (mx_on)
             ++R.mixed_passes;
         state_mx = mx_on;
+        if (!mx_on)
+            CKSH(sk_sum_parts((int)n, 1, 0, c, 1.0, 0.0, -1, SC_CMIN, 2, scal, st));
         CKS(read_scal(ctx));
         if (state_mx && (ctx->host_scal[SC_GN] < mx_thr ||
-                         (opt.sinkhorn_maxit > 0 && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol)))
+                         (opt.sinkhorn_maxit > 0 && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol))) {
             CKS(refresh());
+            CKSH(sk_sum_parts((int)n, 1, 0, c, 1.0, 0.0, -1, SC_CMIN, 2, scal, st));
+            CKS(read_scal(ctx));
+        }
         // Sinkhorn warm-up (Algorithm 2, steps 3-4), on the grid potentials
         for (int it = 0; it < opt.sinkhorn_maxit && ctx->host_scal[SC_GN] >= opt.sinkhorn_tol;
              ++it) {
-            CKSH(sk_log(n, c, lc, st));
+            // lc = log c; in the log domain (column LSE pass) when a column sum is near or
+            // below the bottom of the FP64 range
+            if (ctx->host_scal[SC_CMIN] < 1e-290) {
+                const int RB = collse_row_blocks(m, n, COLLSE_MAX_RB);
+                double *pm = P<double>(ctx->clpart);
+                CKSH(launch_collse(dense_args(ctx, prob, k, q), split, M, S, RB, pm,
+                                   pm + (size_t)RB * n, lc, st));
+                ++R.passes;
+            } else {
+                CKSH(sk_log(n, c, lc, st));
+            }
             CKSH(sk_sinkhorn_step(n, eta, q, split, prob->b, lc, s, w, wlo, st));
             CKS(run_eval(ctx, prob, rp, k, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr, 0));
             ++R.passes;
             ++R.sinkhorn;
+            CKSH(sk_sum_parts((int)n, 1, 0, c, 1.0, 0.0, -1, SC_CMIN, 2, scal, st));
             CKS(read_scal(ctx));
         }
         if (!std::isfinite(ctx->host_scal[SC_GN])) {

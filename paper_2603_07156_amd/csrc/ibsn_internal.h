@@ -56,6 +56,14 @@ hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, do
                        double *lse, double *plan, double *colpart, double *rowpart,
                        hipStream_t st);
 
+// ---- column log-sum-exp (Sinkhorn step in the log domain) -----------------------
+// lc_j = log sum_i a_i exp(x_ij) / S_i from the row state (M, S) at w (lo: with the low
+// parts); RB row blocks (collse_row_blocks), pmax and psum RB*n doubles each.
+constexpr int COLLSE_MAX_RB = 64;
+int collse_row_blocks(int64_t m, int64_t n, int max_rb);
+hipError_t launch_collse(const DenseArgs &d, int lo, const double *M, const double *S, int RB,
+                         double *pmax, double *psum, double *lc, hipStream_t st);
+
 // ---- Armijo trial --------------------------------------------------------------
 // big = 0: colv = expm1(tau) (small-step form); big = 1: colv = exp(tau - tau_max).
 // Writes M_new, S_new, colpart (a_i P'_ij), rowpart = sum a_i delta_i.

@@ -17,6 +17,7 @@ enum {
     SC_WMAX, SC_CMAX, SC_TB,                // max|s+gamma/eta|, max|C|, b^T tau
     SC_BB,                                  // b^T b (mixed-precision switch, Delta_kkt)
     SC_AA,                                  // a^T a (Delta_kkt)
+    SC_CMIN,                                // min_j c_j (Sinkhorn: log-domain step below ~1e-290)
     SC_NSLOT = 32
 };
 

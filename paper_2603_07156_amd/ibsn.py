@@ -106,7 +106,7 @@ class _KernelTimes(ct.Structure):
 
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
-           "ibsn_center_init", "ibsn_center_quantum", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
+           "ibsn_center_init", "ibsn_center_quantum", "ibsn_sinkhorn_step", "ibsn_outer_update", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
            "ibsn_solve_batch", "ibsn_hvp_noalloc")
@@ -134,6 +134,8 @@ def load():
     L.ibsn_subproblem_eval.argtypes = [vp, P, C, vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), vp]
     L.ibsn_trial.argtypes = [vp, P, C, vp, vp, vp, dbl, ct.POINTER(dbl), vp, vp, vp, vp]
     L.ibsn_sparsify.argtypes = [vp, P, C, vp, vp, vp, dbl, i64, ct.POINTER(vp)]
+    L.ibsn_sinkhorn_step.argtypes = [vp, P, C, vp, vp, vp, vp, vp]
+    L.ibsn_outer_update.argtypes = [vp, P, C, vp, vp, vp, vp, vp]
     L.ibsn_csr_info.argtypes = [vp, vp, ct.POINTER(i64), ct.POINTER(i64)]
     L.ibsn_csr_export.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ibsn_csr_free.argtypes = [vp]
@@ -351,6 +353,26 @@ def trial(ctx: Context, prob: Problem, center: Center, gamma, M, Delta, t: float
     return dict(dL=dL.value, M=Mn, S=Sn, c=cn, g=gn)
 
 
+def sinkhorn_step(ctx: Context, prob: Problem, center: Center, gamma, M, S, c):
+    """ibsn_sinkhorn_step: gamma + eta (log b - log c), centred, from the eval at gamma."""
+    m, n = prob.m, prob.n
+    out = _new(prob, n)
+    ctx.check(load().ibsn_sinkhorn_step(ctx.h, ct.byref(prob.raw()), ct.byref(center.raw(m, n)),
+                                        _ptr(gamma, n, name="gamma"), _ptr(M, m, name="M"),
+                                        _ptr(S, m, name="S"), _ptr(c, n, name="c"), _ptr(out)))
+    return out
+
+
+def outer_update(ctx: Context, prob: Problem, center: Center, gamma, M, S):
+    """ibsn_outer_update: the next centre's (r, s) from the row state (M, S) at gamma."""
+    m, n = prob.m, prob.n
+    r, s = _new(prob, m), _new(prob, n)
+    ctx.check(load().ibsn_outer_update(ctx.h, ct.byref(prob.raw()), ct.byref(center.raw(m, n)),
+                                       _ptr(gamma, n, name="gamma"), _ptr(M, m, name="M"),
+                                       _ptr(S, m, name="S"), _ptr(r), _ptr(s)))
+    return r, s
+
+
 class Csr:
     """Library-owned sparsified factor P_rho (Algorithm 1)."""
 
@@ -519,6 +541,8 @@ ibsn_center_init = center_init
 ibsn_center_quantum = center_quantum
 ibsn_subproblem_eval = subproblem_eval
 ibsn_trial = trial
+ibsn_sinkhorn_step = sinkhorn_step
+ibsn_outer_update = outer_update
 ibsn_sparsify = sparsify
 ibsn_hvp = hvp
 ibsn_hvp_noalloc = hvp_noalloc

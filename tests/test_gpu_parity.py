@@ -581,16 +581,44 @@ def test_csr_handle_lifetime(ib, ctx):
     assert gcsr.h is None
 
 
-def test_solve_tiny_eta_numeric_error(ib, ctx):
-    """eta = 1e-6: columns of the first kernel underflow, c_j = 0; the solve returns
-    IBSN_ERR_NUMERIC as the oracle does, instead of iterating on NaN."""
+def test_solve_tiny_eta_reaches_optimum(ib, ctx):
+    """eta = 1e-6: columns of the first kernel underflow (c_j = 0); the Sinkhorn step takes
+    log c_j in the log domain and the solve reaches the exact assignment optimum, as the
+    oracle does."""
+    from scipy.optimize import linear_sum_assignment
     inst = W.uniform_points(64, 0)
+    rr, cc = linear_sum_assignment(inst.C)
+    fstar = inst.C[rr, cc].sum() / 64
     pr = ib.Problem(dev(inst.C), dev(inst.a), dev(inst.b), 1e-6)
-    with pytest.raises(ib.IBSNError) as ei:
-        ib.solve(ctx, pr, ib.default_options(max_outer=50))
-    assert ei.value.code == -4
-    o = orc.solve(inst.C, inst.a, inst.b, 1e-6, options=orc.default_options(max_outer=50))
-    assert o["status"] == -4
+    opt = ib.default_options(max_outer=50, gap_tol=1e-10, marg_tol=0.0, sinkhorn_maxit=200)
+    res = ib.solve(ctx, pr, opt)
+    rep = res["report"]
+    assert res["status"] == 0, rep
+    assert rep["dual"] <= fstar * (1 + 1e-13) and abs(rep["primal"] - fstar) <= 1e-10 * fstar
+
+
+def test_sinkhorn_step_and_outer_update(ib, ctx):
+    """One Sinkhorn gamma-step (the ordinary and the log-domain form) and one outer update,
+    element by element against the oracle on the same eval state."""
+    for eta, m, n in ((1e-2, 300, 257), (1e-6, 35, 40), (1e-6, 300, 4099)):
+        inst = W.uniform_points(n, 3, m=m)
+        inst = W.Instance(inst.C, inst.a, inst.b, eta, "step")
+        r, s, k, gamma = np.log(inst.a), np.log(inst.b), 0, W.random_dual(n, 5, 1e-3 * eta)
+        ctr, q = center(ib, inst, r, s, k, gamma)
+        ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, r=r, s=s, k=k, q=q)
+        if eta < 1e-4:
+            assert ev.c.min() < 1e-290   # the log-domain form runs
+        pr = problem(ib, inst)
+        gs = host(ib.sinkhorn_step(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), dev(ev.c)))
+        os_ = orc.sinkhorn_step(inst.C, inst.a, inst.b, eta, gamma, ev.M, ev.S, ev.c, s, q=q)
+        # gamma = eta (w - s): the step's own size sets the rounding scale
+        np.testing.assert_allclose(gs, os_, rtol=0, atol=1e-13 * np.abs(os_).max())
+        assert abs(gs.sum()) <= 1e-12 * np.abs(gs).max()
+        gr, gsx = (host(x) for x in ib.outer_update(ctx, pr, ctr, dev(gamma), dev(ev.M),
+                                                    dev(ev.S)))
+        o_r, o_s = orc.outer_update(inst.a, eta, gamma, ev.M, ev.S, s, q)
+        np.testing.assert_allclose(gr, o_r, rtol=1e-15, atol=1e-13)
+        np.testing.assert_array_equal(gsx, o_s)
 
 
 def test_full_size_10k_passes(ib, ctx):

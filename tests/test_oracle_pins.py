@@ -451,11 +451,41 @@ def test_p16_eibsn_single_subproblem_is_entropic_ot():
     np.testing.assert_allclose(ev.plan.sum(0), inst.b, rtol=0, atol=1e-13)
 
 
-def test_tiny_eta_reports_numeric_error():
+def test_tiny_eta_log_domain_sinkhorn_reaches_optimum():
     """At eta = 1e-6 (sigma = 1e6 on a cost normalised to max 1) whole columns of the first
-    subproblem's kernel fall below the FP64 range, so c_j = 0 and the Sinkhorn step cannot
-    be taken: the solve reports a numeric error instead of iterating on NaN."""
+    subproblem's kernel fall below the FP64 range, so c_j = 0 and log c_j = -inf: the
+    Sinkhorn step takes log c_j in the log domain instead, and the solve reaches the exact
+    assignment optimum (Birkhoff: f* = min over permutations / n)."""
+    from scipy.optimize import linear_sum_assignment
     inst = W.uniform_points(64, 0)
-    res = orc.solve(inst.C, inst.a, inst.b, 1e-6, options=orc.default_options(max_outer=50))
-    assert res["status"] == -4
-    assert res["report"]["outer"] == 0
+    rr, cc = linear_sum_assignment(inst.C)
+    fstar = inst.C[rr, cc].sum() / 64
+    opt = orc.default_options(max_outer=50, gap_tol=1e-10, marg_tol=0.0, sinkhorn_maxit=200)
+    res = orc.solve(inst.C, inst.a, inst.b, 1e-6, options=opt)
+    rep = res["report"]
+    assert res["status"] == 0, rep
+    assert rep["dual"] <= fstar * (1 + 1e-13) and abs(rep["primal"] - fstar) <= 1e-10 * fstar
+
+
+def test_log_domain_column_sums_against_long_double():
+    """The Sinkhorn step's log c_j (log_colsums in the oracle): where every entry of a column
+    underflows, log c_j = LSE_i (log a_i + theta_ij - lse_i) evaluated in long double from the
+    explicit kernel; the step is gamma + eta (log b - log c), centred."""
+    inst = W.uniform_points(40, 3, m=35)
+    eta = 1e-6
+    gamma = np.zeros(40)
+    s = np.log(inst.b)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, eta, gamma, s=s)
+    assert ev.c.min() == 0.0   # columns underflow in FP64
+    out = orc.sinkhorn_step(inst.C, inst.a, inst.b, eta, gamma, ev.M, ev.S, ev.c, s, q=ev.q)
+    LD = np.longdouble
+    th = (ev.w.astype(LD) + ev.wl.astype(LD))[None, :] - LD(1 / eta) * inst.C.astype(LD)
+    lse = th.max(1) + np.log(np.exp(th - th.max(1)[:, None]).sum(1))
+    v = np.log(inst.a.astype(LD))[:, None] + th - lse[:, None]
+    lc = v.max(0) + np.log(np.exp(v - v.max(0)[None, :]).sum(0))
+    step = eta * (np.log(inst.b.astype(LD)) - lc)
+    expect = gamma.astype(LD) + step
+    expect -= expect.mean()
+    np.testing.assert_allclose(out, np.asarray(expect, np.float64), rtol=0,
+                               atol=1e-9 * float(np.abs(expect).max()))
+    assert abs(out.sum()) <= 1e-12 * np.abs(out).max()
