@@ -1,25 +1,29 @@
 #!/usr/bin/env python
 """Benchmark of the IBSN hot path on one MI355X.
 
-Workload: m = n = 10^4 points uniform in [0,1]^2 on both sides (seed 1000), squared
-Euclidean cost divided by its maximum (800 MB FP64), uniform weights, eta = 1e-2.
+Workload (the metric's instance): m = n = 10^4 points uniform in [0,1]^2 on both sides
+(seed 1000), squared Euclidean cost divided by its maximum (800 MB FP64), uniform weights,
+eta = 3e-6.  At this eta plain FP64 IBSN reaches a certified relative gap of 1e-8 in about a
+thousand outer iterations, seconds on one GPU (at eta = 1e-2 the same gap needs ~10^7
+outer iterations).
 
-A step is one outer iteration of Algorithm 2 (every row of the hot path: outer update
-of the implicit centre, Sinkhorn warm-up when the gradient is large, sparsified
-Newton-CG with Armijo steps, the inexact stop test and the certificate).  Warm-up
-steps run from X^0 = a b^T untimed; the timed steps resume from that state.
+A step is one outer iteration of Algorithm 2 (every row of the hot path: the implicit
+centre and its outer update, the Sinkhorn warm-up when the gradient is large, the eval
+(row LSE) pass, sparsification, Newton-CG, the Armijo trial passes, the inexact stop test
+with Algorithm 3's rounding, and the certificate).  W warm-up steps run from X^0 = a b^T
+untimed; the K timed steps resume from that state.
 
-`time_to_gap` compares the two precision forms on the same instance from X^0: plain FP64
-runs `--gap-outer` outer iterations and reaches a certified relative gap G; the
-mixed-precision form (FP32 exponentials and sparse values, FP64 sums, FP64 near
-convergence) then runs until its certified gap is <= G.  Both wall times are reported.
-
-JSON line: `value` is the whole-job streaming throughput of the timed steps, i.e.
-the algorithmic bytes of every dense m x n pass the steps made divided by their wall
-time (inputs resident in HBM).  `roofline` reports the row-LSE (eval) kernel: its
-algorithmic bytes per launch over its average launch time, measured with HIP events
-recorded on the library's stream around each launch.  `cpu_baseline` times the CPU
-oracle's eval pass on the same workload.
+JSON line:
+  value          LSE-pass throughput of the timed steps: algorithmic bytes of the eval
+                 kernel per launch over its mean launch time (HIP events recorded on the
+                 library's stream around each launch), in GB/s.  `roofline` is the same
+                 kernel against the 8 TB/s peak.
+  time_to_1e-8_gap  the metric's time half at m = n = 10^4: wall time from X^0 to a
+                 certified relative gap <= 1e-8, plain FP64 and the precision form (FP32
+                 exponentials and sparse values with FP64 sums), each from zero
+                 initialisation; counts and the gap reached.
+  cpu_baseline   the oracle's eval pass on the same instance, on the host's cores, for a
+                 bounded time, in the unit of `value`.
 """
 from __future__ import annotations
 
@@ -38,12 +42,14 @@ if ROOT not in sys.path:
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_uniform10000_hbm_counters.md")
 METRIC = ("time to 1e-8 OT gap at n=10k (plain vs warm-start+FP32); LSE-pass HBM GB/s")
 HBM_PEAK_GBS = 8000.0
+ETA = 3e-6
 
 
 def pass_bytes(m: int, n: int) -> float:
     """Algorithmic bytes of one dense pass: the FP64 cost once plus the m- and n-vectors
-    it reads or writes (w, a, M, S, partial-sum inputs: 4 m-vectors and 5 n-vectors)."""
-    return 8.0 * m * n + 8.0 * (4 * m + 5 * n)
+    it reads or writes (w and its low parts, a, M, S, partial sums: 4 m-vectors and 5.5
+    n-vectors; the low parts are read as FP64 and staged as FP32)."""
+    return 8.0 * m * n + 8.0 * (4 * m + 5 * n) + 8.0 * n
 
 
 def cg_roofline(m: int, n: int, rep: dict, kt: dict):
@@ -63,7 +69,8 @@ def cg_roofline(m: int, n: int, rep: dict, kt: dict):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "CG iteration (row gather + column gather + update)",
-            "bytes_per_iteration": per_iter, "ms_per_iteration": ms_per_iter}
+            "bytes_per_iteration": per_iter, "ms_per_iteration": ms_per_iter,
+            "nnz_mean": nnz}
 
 
 def cpu_baseline(inst, seconds: float):
@@ -89,69 +96,37 @@ def cpu_baseline(inst, seconds: float):
     return {"value": passes * pass_bytes(m, n) / dt / 1e9, "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{passes} oracle eval passes (row LSE, P^T a, objective) at m=n={n}, "
-                      f"{dt:.1f} s"}
+                      f"eta={inst.eta:g}, {dt:.1f} s"}
 
 
-def time_to_gap(ibsn, ctx, prob, outer: int):
-    """Plain FP64 for `outer` outer iterations from X^0 sets the gap target G; the mixed
-    form runs from X^0 until its certified relative gap is <= G."""
+def kt_dict(kt):
+    return {k: {"total": v[0], "launches": v[1], "avg": (v[0] / v[1]) if v[1] else None}
+            for k, v in kt.items() if v[1]}
+
+
+def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0=None):
+    """Wall time from X^0 (gamma0 or zero) to a certified relative gap <= `gap`."""
     import torch
 
-    def run(precision, **kw):
-        pr = ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=precision)
-        opt = ibsn.default_options(marg_tol=0.0, **kw)
-        ctx.kernel_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ibsn.solve(ctx, pr, opt)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        kt = ctx.kernel_times()
-        ctx.kernel_timing(False)
-        rep = res["report"]
-        return {"seconds": dt, "rel_gap": rep["rel_gap"],
-                "kernel_ms": {k: {"total": v[0], "launches": v[1],
-                                  "avg": (v[0] / v[1]) if v[1] else None}
-                              for k, v in kt.items() if v[1]},
-                "outer": rep["outer"], "newton": rep["newton"], "cg": rep["cg"],
-                "dense_passes": rep["passes"], "mixed_passes": rep["mixed_passes"],
-                "status": res["status"]}
-
-    plain = run(ibsn.PREC_F64, max_outer=outer, gap_tol=0.0)
-    target = plain["rel_gap"]
-    mixed = run(ibsn.PREC_MIXED, max_outer=2 * outer, gap_tol=target)
-    return {"target_rel_gap": target, "start": "X^0 = a b^T, gamma = 0",
-            "plain_f64": plain, "mixed": mixed,
-            "mixed_over_plain_time": mixed["seconds"] / plain["seconds"]}
-
-
-def time_to_1e8(ibsn, ctx, n: int, eta: float):
-    """Wall time to a certified relative gap of 1e-8 from X^0, plain FP64 and the mixed
-    form, on uniform points at size n (seed 0) with the given eta: a size and eta at which
-    the target is reachable in seconds (at n = 10^4 and eta = 1e-2 it needs ~10^7 outer
-    iterations)."""
-    import torch
-
-    from paper_2603_07156_amd import workloads
-    inst = workloads.uniform_points(n, 0, eta=eta)
-    dev = torch.device("cuda", 0)
-    C = torch.from_numpy(inst.C).to(dev)
-    a = torch.from_numpy(inst.a).to(dev)
-    b = torch.from_numpy(inst.b).to(dev)
-    out = {"workload": f"uniform points in [0,1]^2, m=n={n}, eta={eta:g}, seed 0, from X^0",
-           "target_rel_gap": 1e-8}
-    for name, prec in (("plain_f64", ibsn.PREC_F64), ("mixed", ibsn.PREC_MIXED)):
-        pr = ibsn.Problem(C, a, b, eta, precision=prec)
-        opt = ibsn.default_options(max_outer=5000, gap_tol=1e-8, marg_tol=0.0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ibsn.solve(ctx, pr, opt)
-        torch.cuda.synchronize()
-        rep = res["report"]
-        out[name] = {"seconds": time.perf_counter() - t0, "status": res["status"],
-                     "rel_gap": rep["rel_gap"], "outer": rep["outer"], "newton": rep["newton"],
-                     "cg": rep["cg"], "t_cg": rep["t_cg"]}
-    return out
+    pr = ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=precision)
+    opt = ibsn.default_options(max_outer=max_outer, gap_tol=gap, marg_tol=0.0)
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ibsn.solve(ctx, pr, opt, gamma0=gamma0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.kernel_timing(False)
+    rep = res["report"]
+    return {"seconds": dt, "status": res["status"], "rel_gap": rep["rel_gap"],
+            "primal": rep["primal"], "dual": rep["dual"], "outer": rep["outer"],
+            "newton": rep["newton"], "cg": rep["cg"], "sinkhorn": rep["sinkhorn"],
+            "backtracks": rep["backtracks"], "dense_passes": rep["passes"],
+            "mixed_passes": rep["mixed_passes"],
+            "t_eval": rep["t_eval"], "t_sparsify": rep["t_sparsify"], "t_cg": rep["t_cg"],
+            "t_linesearch": rep["t_linesearch"], "t_stop": rep["t_stop"],
+            "kernel_ms": kt_dict(kt)}
 
 
 def batch_solves(ibsn, count: int, outer: int = 20):
@@ -186,18 +161,15 @@ def batch_solves(ibsn, count: int, outer: int = 20):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--eta", type=float, default=ETA)
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--gap-outer", type=int, default=100,
-                    help="outer iterations of the plain run that sets the common gap target")
-    ap.add_argument("--ttg-n", type=int, default=1024,
-                    help="size of the time-to-1e-8-gap runs (0 = skip); eta set by --ttg-eta")
-    ap.add_argument("--ttg-eta", type=float, default=1e-5)
-    ap.add_argument("--batch", type=int, default=64,
+    ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-1e-8-gap runs")
+    ap.add_argument("--batch", type=int, default=32,
                     help="problems of the batched grid-histogram workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -206,18 +178,20 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
-    from paper_2603_07156_amd import ibsn, probe, workloads
+    import probe
+    from paper_2603_07156_amd import ibsn, workloads
 
     dev = torch.device("cuda", 0)
-    inst = workloads.uniform_points(args.n, args.seed)
+    inst = workloads.uniform_points(args.n, args.seed, eta=args.eta)
     m, n = inst.C.shape
     ctx = ibsn.Context(0)
     prob = ibsn.Problem(torch.from_numpy(inst.C).to(dev), torch.from_numpy(inst.a).to(dev),
                         torch.from_numpy(inst.b).to(dev), inst.eta)
     torch.cuda.synchronize()
+    workload = (f"uniform points in [0,1]^2, m=n={n}, squared-Euclidean cost / max (FP64), "
+                f"uniform weights, eta={inst.eta:g}, seed {args.seed}")
 
     # warm-up steps from X^0 (untimed)
     opt = ibsn.default_options(max_outer=max(args.warmup, 1), gap_tol=0.0, marg_tol=0.0)
@@ -240,14 +214,14 @@ def main() -> int:
     steps = int(rep["outer"])
 
     pb = pass_bytes(m, n)
-    value = rep["passes"] * pb / dt / 1e9
     eval_ms, eval_n = kt["eval"]
     eval_avg_ms = eval_ms / max(eval_n, 1)
     achieved = pb / (eval_avg_ms * 1e-3) / 1e9 if eval_n else None
+    k0 = max(args.warmup, 1)
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": achieved,
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": steps,
@@ -258,9 +232,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"uniform points in [0,1]^2, m=n={n}, squared-Euclidean cost / max, "
-                               f"uniform weights, eta={inst.eta}, seed {args.seed}; a step is one "
-                               f"IBSN outer iteration (k = {args.warmup}..{args.warmup + steps - 1})",
+        "config": {"workload": workload + f"; a step is one IBSN outer iteration "
+                               f"(k = {k0}..{k0 + steps - 1}); value is the LSE (eval) pass's "
+                               f"HBM throughput over the timed steps",
                    "m": m, "n": n, "eta": inst.eta},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
@@ -274,14 +248,15 @@ def main() -> int:
                   "nnz_mean": rep["nnz_mean"], "nnz_last": rep["nnz_last"],
                   "density_mean": rep["nnz_mean"] / (m * n)},
         "roofline_cg": cg_roofline(m, n, rep, kt),
-        "kernel_ms": {k: {"total": v[0], "launches": v[1],
-                          "avg": (v[0] / v[1]) if v[1] else None} for k, v in kt.items()},
+        "kernel_ms": kt_dict(kt),
     }
-    if args.gap_outer > 0:
-        ttg = time_to_gap(ibsn, ctx, prob, args.gap_outer)
-        out["time_to_gap"] = ttg
-        # the LSE pass of the mixed form (FP32 exponentials, FP64 sums): same bytes
-        mk = ttg["mixed"]["kernel_ms"].get("eval_mixed")
+    if not args.no_ttg:
+        ttg = {"workload": workload + ", from X^0 (gamma = 0)", "target_rel_gap": 1e-8}
+        ttg["plain_f64"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_F64)
+        ttg["mixed_fp32"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_MIXED)
+        ttg["mixed_over_plain_time"] = ttg["mixed_fp32"]["seconds"] / ttg["plain_f64"]["seconds"]
+        out["time_to_1e-8_gap"] = ttg
+        mk = ttg["mixed_fp32"]["kernel_ms"].get("eval_mixed")
         if mk:
             ach = pb / (mk["avg"] * 1e-3) / 1e9
             out["roofline_mixed_eval"] = {
@@ -289,8 +264,6 @@ def main() -> int:
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "kernel": "row-LSE eval pass, mixed-precision form (k_eval<..., MX>)",
                 "bytes_per_launch": pb, "avg_launch_ms": mk["avg"], "launches": mk["launches"]}
-    if args.ttg_n > 0:
-        out["time_to_1e-8_gap"] = time_to_1e8(ibsn, ctx, args.ttg_n, args.ttg_eta)
     if args.batch > 0:
         out["batch"] = batch_solves(ibsn, args.batch)
     if not args.no_cpu:

@@ -2,14 +2,12 @@
 
 Two counter runs, each on its own (rocprofv3 collects one counter group per run):
 
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- \
-        python3 -m paper_2603_07156_amd.probe
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- \
-        python3 -m paper_2603_07156_amd.probe
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- python3 probe.py
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- python3 probe.py
 
 then
 
-    python3 -m paper_2603_07156_amd.probe --summarize <dir>/fetch_counter_collection.csv \
+    python3 probe.py --summarize <dir>/fetch_counter_collection.csv \
         <dir>/write_counter_collection.csv > profiles/<name>.md
 
 The probe runs the eval kernel five times on the m = n = 10^4 uniform-points workload
@@ -28,8 +26,11 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
 # the LSE-pass kernel is built from these two files
-DENSE_SRC = [os.path.join(HERE, "csrc", f) for f in ("dense_common.h", "dense_eval.hip")]
+DENSE_SRC = [os.path.join(HERE, "paper_2603_07156_amd", "csrc", f)
+             for f in ("dense_common.h", "dense_eval.hip")]
 COPY_BYTES = 800_000_000
 N = 10000
 SEED = 1000
@@ -50,7 +51,7 @@ def algorithmic_bytes(m: int, n: int) -> float:
 def run_probe() -> None:
     import torch
 
-    from . import ibsn, workloads
+    from paper_2603_07156_amd import ibsn, workloads
 
     dev = torch.device("cuda", 0)
     inst = workloads.uniform_points(N, SEED)
@@ -101,10 +102,10 @@ def summarize(fetch_csv: str, write_csv: str) -> str:
         "",
         "```",
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-        "python3 -m paper_2603_07156_amd.probe",
+        "python3 probe.py",
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-        "python3 -m paper_2603_07156_amd.probe",
-        "python3 -m paper_2603_07156_amd.probe --summarize "
+        "python3 probe.py",
+        "python3 probe.py --summarize "
         "gpurun_out/pmc_fetch/fetch_counter_collection.csv "
         "gpurun_out/pmc_write/write_counter_collection.csv",
         "```",
