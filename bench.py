@@ -113,13 +113,24 @@ def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0=N
     ctx.kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = ibsn.solve(ctx, pr, opt, gamma0=gamma0)
+    res = ibsn.solve(ctx, pr, opt, gamma0=gamma0, trace_cap=max_outer)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kt = ctx.kernel_times()
     ctx.kernel_timing(False)
     rep = res["report"]
+    # where the time goes: cumulative seconds and gap after the first outer iterations
+    tr = res["trace"] or []
+    cum, acc = {}, 0.0
+    marks = {1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 2000, 5000}
+    for t in tr:
+        acc += t["t_total"]
+        if t["k"] + 1 in marks or t is tr[-1]:
+            cum[str(t["k"] + 1)] = {"seconds": acc, "rel_gap": t["rel_gap"],
+                                    "newton": t["newton"], "backtracks": t["backtracks"],
+                                    "sinkhorn": t["sinkhorn"]}
     return {"seconds": dt, "status": res["status"], "rel_gap": rep["rel_gap"],
+            "by_outer": cum,
             "primal": rep["primal"], "dual": rep["dual"], "outer": rep["outer"],
             "newton": rep["newton"], "cg": rep["cg"], "sinkhorn": rep["sinkhorn"],
             "backtracks": rep["backtracks"], "dense_passes": rep["passes"],
