@@ -300,6 +300,11 @@ typedef struct {
     ibsn_iter_record *trace;             /* host, optional (NULL): the first trace_cap outer */
     int64_t trace_cap;                   /*   iterations' records; ibsn_report.trace_len     */
                                          /*   says how many were written                     */
+    int32_t armijo_warm;                 /* 1: each line search starts at                      */
+                                         /*   min(1, t_prev / beta), t_prev the step the      */
+                                         /*   previous line search accepted; 0: at t = 1. The */
+                                         /*   paper leaves the first trial step open; the     */
+                                         /*   Armijo condition itself is the same             */
 } ibsn_options;
 
 void ibsn_default_options(ibsn_options *opt);

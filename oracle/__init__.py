@@ -59,7 +59,7 @@ class Options(ct.Structure):
         ("max_outer", ct.c_int), ("max_newton", ct.c_int), ("max_backtrack", ct.c_int),
         ("cg_maxit", ct.c_int), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int),
         ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int),
-        ("eot", ct.c_int), ("eot_tol", ct.c_double),
+        ("eot", ct.c_int), ("eot_tol", ct.c_double), ("armijo_warm", ct.c_int),
     ]
 
 

@@ -796,6 +796,8 @@ typedef struct {
     int stall_limit;                  /* 3 failed D_phi tests after the gate end the inner loop */
     int eot;                          /* 1: (E)IBSN of appendix C.4: centre 1 1^T, one subproblem */
     double eot_tol;                   /* (E)IBSN stops at ||g|| < eot_tol (1e-9, appendix C.4) */
+    int armijo_warm;                  /* 1: each line search starts at min(1, t_prev / beta),
+                                         t_prev the last accepted step; 0: at t = 1 */
 } orc_options;
 
 typedef struct {
@@ -825,6 +827,7 @@ void orc_default_options(orc_options *o)
     o->stall_limit = 3;
     o->eot = 0;
     o->eot_tol = 1e-9;
+    o->armijo_warm = 1;
 }
 
 static double nrm1(int64_t n, const double *x)
@@ -917,6 +920,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
     R.status = ORC_WARN_MAXITER;
     double stop_out[10] = {0};
     int64_t k0 = k;
+    double t_prev = 1.0; /* step of the last accepted line search (armijo_warm) */
     for (; k < k0 + opt.max_outer; ++k) {
         double mu = fmax(opt.mu0 / ((double)(k + 1) * (double)(k + 1)), opt.mu_floor);
         const double q = orc_center_quantum(n, s, gamma, eta, k, cmax);
@@ -962,7 +966,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             free(col);
             free(val);
             double gd = dot(n, g, Delta);
-            double t = 1.0, dL = 0.0;
+            double t = opt.armijo_warm ? fmin(1.0, t_prev / opt.beta) : 1.0, dL = 0.0;
             int bt = 0, accepted = 0;
             for (;;) { /* step 9: Armijo backtracking on a finite decrease */
                 orc_trial(m, n, C, kind, ldc, k, eta, q, w, wl, a, b, M, Delta, t, &dL, tau, Mt,
@@ -979,6 +983,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
             R.backtracks += bt;
             if (!accepted) /* no acceptable step: keep the iterate and end the inner loop */
                 break;
+            t_prev = t;
             for (int64_t j = 0; j < n; ++j) /* step 10: w += tau, exactly */
                 pot_add(&w[j], &wl[j], tau[j], q);
             memcpy(M, Mt, sizeof(double) * m);

@@ -390,6 +390,23 @@ __device__ __forceinline__ double exp_pass(double x, const double *__restrict__ 
         return exp_tab(x, etab);
 }
 
+// The same values, with the arithmetic skipped where the result is 0 anyway: x <= -746 in
+// FP64 (exp underflows past the least subnormal), x <= -110 in the FP32 form; -inf and NaN
+// give 0 as before.  A wave whose lanes all fall below skips the exponential (at large
+// sigma almost every entry of a row does), so the results are unchanged bit for bit.
+template <bool MX>
+__device__ __forceinline__ double exp_pass_z(double x, const double *__restrict__ etab)
+{
+    double r = 0.0;
+    if (x > (MX ? -110.0 : -746.0))
+        r = exp_pass<MX>(x, etab);
+    return r;
+}
+__device__ __forceinline__ double exp_tab_z(double x, const double *__restrict__ etab)
+{
+    return exp_pass_z<false>(x, etab);
+}
+
 // 2^(j/128), j < 128, into LDS (one barrier)
 __device__ __forceinline__ void exp_table_init(double *etab)
 {

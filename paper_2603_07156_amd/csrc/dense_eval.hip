@@ -65,12 +65,17 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         }
         const double mw = grid(wave_red<OP_MAX>(mt), qg);
         double st = 0.0;
+        // the low parts are the same in every row: an index offset the compiler cannot
+        // see through keeps their LDS reads in the row loop (hoisted, they spill)
+        int zo = 0;
+        asm volatile("" : "+v"(zo));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = slot_col<QF, NT, VEC>(e, n);
-            const double xa = add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - mw), wl, n, j);
+            const double xa =
+                add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - mw), wl, n, j + zo);
             const double p =
-                exp_pass<MX>(slot_valid<QF, NT, VEC>(e, n) ? xa : -INFINITY, etab);
+                exp_pass_z<MX>(slot_valid<QF, NT, VEC>(e, n) ? xa : -INFINITY, etab);
             x[e] = (xval_t<MX>)p;   // exact: in the mixed form p is already an FP32 value
             st += p;
         }

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
             const int j = slot_col<QF, NT, VEC>(e, n) + zo;
             const double xa = add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - Mi), wl, n, j);
-            const double p = exp_pass<MX>(valid ? xa : -INFINITY, etab) * iS;
+            const double p = exp_pass_z<MX>(valid ? xa : -INFINITY, etab) * iS;
             const bool keep = valid && (dense || p >= rho);
             x[e] = (xval_t<MX>)p;
             if (keep) {

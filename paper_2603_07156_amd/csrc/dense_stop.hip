@@ -49,7 +49,7 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
                 const bool valid = slot_valid<QF, NT, VEC>(e, n);
                 const int j = slot_col<QF, NT, VEC>(e, n);
                 const double xa = add_lo<LO>(fma(-sigma, (double)xr[e], wl[j] - Mi), wl, n, j);
-                const double X = exp_tab(valid ? xa : -INFINITY, etab) * aS;
+                const double X = exp_tab_z(valid ? xa : -INFINITY, etab) * aS;
                 x[e] = X;
                 red[0] += X;
             }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
             }
             const double c = valid ? (double)cst[e] : 0.0;
             const double Xv =
-                exp_tab(valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY,
+                exp_tab_z(valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY,
                         etab) * aS;
             red[0] = fma(Xv, yj, red[0]);
             red[1] = fmin(red[1], valid ? c - gj : INFINITY);
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
             }
             const double c = valid ? (double)cst[e] : 0.0;
             const double xa = valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY;
-            const double Xv = exp_tab(xa, etab) * aS;
+            const double Xv = exp_tab_z(xa, etab) * aS;
             const double f = (zi * Xv) * yj;
             const double xh = valid ? fma(es, ecj, f) : 0.0;
             const double lx = lr + xa;

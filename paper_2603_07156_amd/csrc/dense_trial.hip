@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         for (int e = 0; e < E; ++e) {
             const int j = slot_col<QF, NT, VEC>(e, n) + zo;
             const double q =
-                exp_pass<MX>(add_lo<LO>(fma(-sigma, (double)xr[e], wr[e] - Mi), cvl, n, j), etab);
+                exp_pass_z<MX>(add_lo<LO>(fma(-sigma, (double)xr[e], wr[e] - Mi), cvl, n, j), etab);
             const double cv = cvl[j];   // finite; q = 0 on padding
             red[1] += q;
             double qe;

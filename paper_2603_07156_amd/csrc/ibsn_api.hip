@@ -794,6 +794,7 @@ void ibsn_default_options(ibsn_options *o)
     o->mixed_switch = 64.0;
     o->trace = nullptr;
     o->trace_cap = 0;
+    o->armijo_warm = 1;
 }
 
 int ibsn_center_init(ibsn_ctx *ctx, const ibsn_problem *prob, double *r, double *s)
@@ -1136,7 +1137,8 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     if (opt.max_outer < 1 || opt.max_newton < 1 || opt.max_backtrack < 0 ||
         !(opt.beta > 0 && opt.beta < 1) || !(opt.sigma_armijo > 0 && opt.sigma_armijo < 1) ||
         (opt.eot != 0 && opt.eot != 1) || (opt.eot && !(opt.eot_tol > 0)) ||
-        !(opt.mixed_switch >= 0) || opt.trace_cap < 0 || (opt.trace_cap > 0 && !opt.trace))
+        !(opt.mixed_switch >= 0) || opt.trace_cap < 0 || (opt.trace_cap > 0 && !opt.trace) ||
+        (opt.armijo_warm != 0 && opt.armijo_warm != 1))
         return fail(ctx, IBSN_ERR_INVALID_ARG, "invalid options");
     const bool resume = k_io && *k_io > 0;
     if (resume && (!r_io || !s_io))
@@ -1260,6 +1262,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     double stop_h[10] = {0};
     const int64_t k0 = k;
     const double mn = (double)m * (double)n;
+    double t_prev = 1.0;   // step of the last accepted line search (armijo_warm)
     // per-outer-iteration record: the report's counters at the start of the iteration
     ibsn_report Rb;
     double nnz_sum_b = 0.0;
@@ -1392,7 +1395,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             R.t_cg += now_s() - ta;
             ta = now_s();
             CKSH(sk_dot_slot(n, g, Delta, SC_GD, scal, st));
-            double t = 1.0;
+            double t = opt.armijo_warm ? std::min(1.0, t_prev / opt.beta) : 1.0;
             int bt = 0;
             bool accepted = false;
             for (;;) {   // step 9: Armijo backtracking on a finite decrease
@@ -1434,6 +1437,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                 R.t_linesearch += now_s() - ta;
                 break;
             }
+            t_prev = t;
             // step 10: w += tau, exactly in the two-level potential (on the grid when the
             // potentials are kept there); the accepted trial is the new iterate
             CKSH(sk_dd_axpy(n, q, P<double>(ctx->tauv), w, wlo, st));

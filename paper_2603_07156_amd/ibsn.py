@@ -55,7 +55,7 @@ class Options(ct.Structure):
         ("cg_maxit", ct.c_int32), ("cg_forcing_max", ct.c_double), ("rho_mode", ct.c_int32),
         ("cg_rtol_min", ct.c_double), ("stall_limit", ct.c_int32),
         ("eot", ct.c_int32), ("eot_tol", ct.c_double), ("mixed_switch", ct.c_double),
-        ("trace", ct.c_void_p), ("trace_cap", ct.c_int64),
+        ("trace", ct.c_void_p), ("trace_cap", ct.c_int64), ("armijo_warm", ct.c_int32),
     ]
 
 
