@@ -1,0 +1,126 @@
+"""Reference of the learned warm start's network (test infrastructure only).
+
+A plain NumPy (FP64) forward and backward pass of the point-set network that the library
+evaluates with BF16 MFMA kernels: per-point encoder (3 layers of width 256, ReLU between),
+mean pooling of the sources and of the targets, per-target head (3 layers), output centred
+per instance.  With ``bf16=True`` every operand of a matrix product is rounded to BF16
+(round to nearest even) where it enters the product, as the library does; the products
+themselves, biases, activations, pooling and the loss are exact FP64 here (the library
+accumulates in FP32).  ``bf16=False`` is the plain FP64 network, checked against finite
+differences in the tests.  Parameter order and shapes follow ``ibsn_ws_param_count``:
+W1 (4 x 256), b1, W2 (256 x 256), b2, W3, b3, Wf (4 x 256), Wc (512 x 256), bf, Wg, bg,
+wo (256 x 1), bo.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+WID, NF = 256, 4
+SHAPES = [("W1", NF, WID), ("b1", 1, WID), ("W2", WID, WID), ("b2", 1, WID), ("W3", WID, WID),
+          ("b3", 1, WID), ("Wf", NF, WID), ("Wc", 2 * WID, WID), ("bf", 1, WID),
+          ("Wg", WID, WID), ("bg", 1, WID), ("wo", WID, 1), ("bo", 1, 1)]
+
+
+def param_count() -> int:
+    return sum(r * c for _, r, c in SHAPES)
+
+
+def unpack(flat: np.ndarray) -> dict:
+    out, off = {}, 0
+    for name, r, c in SHAPES:
+        out[name] = np.asarray(flat[off:off + r * c], dtype=np.float64).reshape(r, c)
+        off += r * c
+    return out
+
+
+def pack(d: dict) -> np.ndarray:
+    return np.concatenate([d[name].reshape(-1) for name, _, _ in SHAPES])
+
+
+def bf16_round(x) -> np.ndarray:
+    """x rounded to FP32, then to BF16 (round to nearest, ties to even), as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    r = np.where(np.isnan(f), u, r).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _mm(a, b, rnd):
+    if rnd:
+        return bf16_round(a) @ bf16_round(b)
+    return a @ b
+
+
+def forward(flat, fs, fte, fth, B, m, n, bf16=True):
+    """Outputs o (B n) and the values the backward pass needs.  fs (B m x 4), fte, fth
+    (B n x 4) stacked by instance."""
+    p = unpack(flat)
+    X = np.concatenate([np.asarray(fs, np.float64), np.asarray(fte, np.float64)])
+    H1 = np.maximum(_mm(X, p["W1"], bf16) + p["b1"], 0.0)
+    H2 = np.maximum(_mm(H1, p["W2"], bf16) + p["b2"], 0.0)
+    E = _mm(H2, p["W3"], bf16) + p["b3"]
+    hs = E[:B * m].reshape(B, m, WID).mean(1)
+    ht = E[B * m:].reshape(B, n, WID).mean(1)
+    CTX = np.concatenate([hs, ht], axis=1)
+    CB = _mm(CTX, p["Wc"], bf16) + p["bf"]
+    XH = np.asarray(fth, np.float64)
+    Z1 = np.maximum(_mm(XH, p["Wf"], bf16) + np.repeat(CB, n, axis=0), 0.0)
+    Z2 = np.maximum(_mm(Z1, p["Wg"], bf16) + p["bg"], 0.0)
+    O = (_mm(Z2, p["wo"], bf16) + p["bo"]).reshape(-1)
+    cache = dict(p=p, X=X, H1=H1, H2=H2, E=E, CTX=CTX, XH=XH, Z1=Z1, Z2=Z2)
+    return O, cache
+
+
+def loss(O, target, B, n):
+    """Mean over instances and targets of ((o_j - mean o) - t_j)^2."""
+    o = O.reshape(B, n)
+    oc = o - o.mean(1, keepdims=True)
+    return float(((oc - np.asarray(target, np.float64).reshape(B, n)) ** 2).mean())
+
+
+def loss_and_grad(flat, fs, fte, fth, target, B, m, n, bf16=True):
+    """The loss and its gradient with respect to the flat parameters (backpropagation)."""
+    O, c = forward(flat, fs, fte, fth, B, m, n, bf16)
+    p = c["p"]
+    o = O.reshape(B, n)
+    d = (o - o.mean(1, keepdims=True)) - np.asarray(target, np.float64).reshape(B, n)
+    L = float((d ** 2).mean())
+    dO = (2.0 / (B * n)) * (d - d.mean(1, keepdims=True))
+    dO = dO.reshape(-1, 1)
+    g = {}
+    g["wo"] = _mm(c["Z2"].T, dO, bf16)
+    g["bo"] = dO.sum(0, keepdims=True)
+    dZ2 = _mm(dO, p["wo"].T, bf16) * (c["Z2"] > 0)
+    g["Wg"] = _mm(c["Z1"].T, dZ2, bf16)
+    g["bg"] = dZ2.sum(0, keepdims=True)
+    dZ1 = _mm(dZ2, p["Wg"].T, bf16) * (c["Z1"] > 0)
+    g["Wf"] = _mm(c["XH"].T, dZ1, bf16)
+    dCB = dZ1.reshape(B, n, WID).sum(1)
+    g["bf"] = dCB.sum(0, keepdims=True)
+    g["Wc"] = _mm(c["CTX"].T, dCB, bf16)
+    dCTX = _mm(dCB, p["Wc"].T, bf16)
+    dE = np.concatenate([np.repeat(dCTX[:, :WID] / m, m, axis=0),
+                         np.repeat(dCTX[:, WID:] / n, n, axis=0)])
+    g["W3"] = _mm(c["H2"].T, dE, bf16)
+    g["b3"] = dE.sum(0, keepdims=True)
+    dH2 = _mm(dE, p["W3"].T, bf16) * (c["H2"] > 0)
+    g["W2"] = _mm(c["H1"].T, dH2, bf16)
+    g["b2"] = dH2.sum(0, keepdims=True)
+    dH1 = _mm(dH2, p["W2"].T, bf16) * (c["H1"] > 0)
+    g["W1"] = _mm(c["X"].T, dH1, bf16)
+    g["b1"] = dH1.sum(0, keepdims=True)
+    return L, pack(g), O
+
+
+def features(x, y, a, b, C):
+    """Feature rows of one instance (FP64): fs (m x 4), fte, fth (n x 4), and the scale
+    mean_j min_i C_ij, as defined for ibsn_ws_features."""
+    m, n = len(a), len(b)
+    cmin = np.asarray(C, np.float64).min(0)
+    scale = cmin.mean()
+    fs = np.column_stack([x[:, 0], x[:, 1], m * np.asarray(a), np.ones(m)])
+    fte = np.column_stack([y[:, 0], y[:, 1], n * np.asarray(b), -np.ones(n)])
+    fth = np.column_stack([y[:, 0], y[:, 1], n * np.asarray(b), cmin / scale])
+    return fs, fte, fth, scale

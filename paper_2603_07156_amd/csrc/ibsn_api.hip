@@ -645,6 +645,12 @@ double now_s()
 // =================================================================================
 // exported API
 // =================================================================================
+namespace ibsn {
+hipStream_t ctx_stream(const ibsn_ctx *ctx) { return ctx->stream; }
+int ctx_device(const ibsn_ctx *ctx) { return ctx->device; }
+int ctx_fail(ibsn_ctx *ctx, int code, const char *msg) { return fail(ctx, code, "%s", msg); }
+}  // namespace ibsn
+
 extern "C" {
 
 int ibsn_create(ibsn_ctx **out, int device, void *hip_stream)

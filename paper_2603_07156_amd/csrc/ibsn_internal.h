@@ -194,4 +194,13 @@ hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const voi
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,
                              int64_t cap, hipStream_t st);
 
+// ---- context access for the other translation units of the C ABI -----------------
+// (ibsn_ctx is defined in ibsn_api.hip)
+}  // namespace ibsn
+struct ibsn_ctx;
+namespace ibsn {
+hipStream_t ctx_stream(const ibsn_ctx *ctx);
+int ctx_device(const ibsn_ctx *ctx);
+// record the message on ctx and return code (as every entry point does on error)
+int ctx_fail(ibsn_ctx *ctx, int code, const char *msg);
 }  // namespace ibsn

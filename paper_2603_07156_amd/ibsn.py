@@ -109,7 +109,9 @@ EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
            "ibsn_center_init", "ibsn_center_quantum", "ibsn_sinkhorn_step", "ibsn_outer_update", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
-           "ibsn_solve_batch", "ibsn_hvp_noalloc")
+           "ibsn_solve_batch", "ibsn_hvp_noalloc", "ibsn_ws_param_count", "ibsn_ws_create",
+           "ibsn_ws_free", "ibsn_ws_get_params", "ibsn_ws_set_params", "ibsn_ws_features",
+           "ibsn_ws_forward", "ibsn_ws_predict", "ibsn_ws_train_step")
 
 
 def load():
@@ -150,6 +152,19 @@ def load():
                              ct.POINTER(Report)]
     L.ibsn_solve_batch.argtypes = [ct.POINTER(vp), ct.c_int, i64, P, ct.POINTER(Options),
                                    ct.POINTER(vp), ct.POINTER(Report), ct.POINTER(ct.c_int32)]
+    fp = ct.POINTER(ct.c_float)
+    L.ibsn_ws_param_count.argtypes = []
+    L.ibsn_ws_param_count.restype = i64
+    L.ibsn_ws_create.argtypes = [vp, ct.c_uint64, ct.POINTER(vp)]
+    L.ibsn_ws_free.argtypes = [vp]
+    L.ibsn_ws_free.restype = None
+    L.ibsn_ws_get_params.argtypes = [vp, vp, fp, i64]
+    L.ibsn_ws_set_params.argtypes = [vp, vp, fp, i64]
+    L.ibsn_ws_features.argtypes = [vp, P, vp, vp, vp, vp, vp, ct.POINTER(dbl)]
+    L.ibsn_ws_forward.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, vp]
+    L.ibsn_ws_predict.argtypes = [vp, vp, i64, i64, vp, vp, vp, dbl, vp]
+    L.ibsn_ws_train_step.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, vp, ct.c_float,
+                                     ct.POINTER(ct.c_float), fp]
     L.ibsn_kernel_timing.argtypes = [vp, ct.c_int]
     L.ibsn_kernel_times_get.argtypes = [vp, ct.POINTER(_KernelTimes)]
     for name in EXPORTS:
@@ -461,6 +476,90 @@ def stop(ctx: Context, prob: Problem, center: Center, gamma, M, S, want_xhat: bo
     if want_xhat:
         res["xhat"] = xhat
     return res
+
+
+class WarmStart:
+    """The learned warm start (ibsn_ws_*): a point-set network predicting the first
+    subproblem's dual, with BF16 MFMA kernels.  Features and outputs are device tensors."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        L = load()
+        self.ctx, self._lib = ctx, L
+        h = ct.c_void_p()
+        ctx.check(L.ibsn_ws_create(ctx.h, ct.c_uint64(seed), ct.byref(h)))
+        self.h = h
+        self.count = int(L.ibsn_ws_param_count())
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.count, dtype=np.float32)
+        self.ctx.check(load().ibsn_ws_get_params(
+            self.ctx.h, self.h, out.ctypes.data_as(ct.POINTER(ct.c_float)), self.count))
+        return out
+
+    def set_params(self, flat):
+        import numpy as np
+        arr = np.ascontiguousarray(flat, dtype=np.float32)
+        if arr.size != self.count:
+            raise ValueError(f"expected {self.count} parameters, got {arr.size}")
+        self.ctx.check(load().ibsn_ws_set_params(
+            self.ctx.h, self.h, arr.ctypes.data_as(ct.POINTER(ct.c_float)), self.count))
+
+    def features(self, prob: "Problem", x, y):
+        """ibsn_ws_features: (fs, fte, fth, scale) of one problem with 2-D points x, y."""
+        m, n = prob.m, prob.n
+        dev = prob.a.device
+        fs = torch.empty((m, 4), dtype=torch.float32, device=dev)
+        fte = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        fth = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        sc = ct.c_double()
+        self.ctx.check(load().ibsn_ws_features(
+            self.ctx.h, ct.byref(prob.raw()), _ptr(x, 2 * m, name="x"), _ptr(y, 2 * n, name="y"),
+            _ptr(fs, dtype=torch.float32), _ptr(fte, dtype=torch.float32),
+            _ptr(fth, dtype=torch.float32), ct.byref(sc)))
+        return fs, fte, fth, sc.value
+
+    def forward(self, B, m, n, fs, fte, fth):
+        """ibsn_ws_forward: raw outputs (B n) for stacked instances."""
+        out = torch.empty(B * n, dtype=torch.float32, device=fs.device)
+        f32 = torch.float32
+        self.ctx.check(load().ibsn_ws_forward(
+            self.ctx.h, self.h, B, m, n, _ptr(fs, B * m * 4, f32, "fs"),
+            _ptr(fte, B * n * 4, f32, "fte"), _ptr(fth, B * n * 4, f32, "fth"), _ptr(out, dtype=f32)))
+        return out
+
+    def predict(self, m, n, fs, fte, fth, scale):
+        """ibsn_ws_predict: the warm-start dual (n, float64) of one instance."""
+        g = torch.empty(n, dtype=torch.float64, device=fs.device)
+        f32 = torch.float32
+        self.ctx.check(load().ibsn_ws_predict(
+            self.ctx.h, self.h, m, n, _ptr(fs, m * 4, f32, "fs"), _ptr(fte, n * 4, f32, "fte"),
+            _ptr(fth, n * 4, f32, "fth"), float(scale), _ptr(g)))
+        return g
+
+    def train_step(self, B, m, n, fs, fte, fth, target, lr, want_grad=False):
+        """ibsn_ws_train_step: (loss, gradient or None)."""
+        import numpy as np
+        loss = ct.c_float()
+        grad = np.empty(self.count, dtype=np.float32) if want_grad else None
+        f32 = torch.float32
+        self.ctx.check(load().ibsn_ws_train_step(
+            self.ctx.h, self.h, B, m, n, _ptr(fs, B * m * 4, f32, "fs"),
+            _ptr(fte, B * n * 4, f32, "fte"), _ptr(fth, B * n * 4, f32, "fth"),
+            _ptr(target, B * n, f32, "target"), float(lr), ct.byref(loss),
+            grad.ctypes.data_as(ct.POINTER(ct.c_float)) if want_grad else None))
+        return loss.value, grad
+
+    def free(self):
+        if getattr(self, "h", None):
+            self._lib.ibsn_ws_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def default_options(**kw) -> Options:
