@@ -21,7 +21,9 @@ JSON line:
   time_to_1e-8_gap  the metric's time half at m = n = 10^4: wall time from X^0 to a
                  certified relative gap <= 1e-8, plain FP64 and the precision form (FP32
                  exponentials and sparse values with FP64 sums), each from zero
-                 initialisation; counts and the gap reached.
+                 initialisation, and both forms again from the learned warm start (its
+                 features and network forward pass inside the timed region) when trained
+                 weights are present; counts and the gap reached.
   cpu_baseline   the oracle's eval pass on the same instance, on the host's cores, for a
                  bounded time, in the unit of `value`.
 """
@@ -43,6 +45,8 @@ TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_uniform10000_hbm_counters.md")
 METRIC = ("time to 1e-8 OT gap at n=10k (plain vs warm-start+FP32); LSE-pass HBM GB/s")
 HBM_PEAK_GBS = 8000.0
 ETA = 1e-6
+# trained parameters of the learned warm start (paper_2603_07156_amd/train_warmstart.py)
+WS_WEIGHTS = os.path.join(ROOT, "paper_2603_07156_amd", "warmstart_uniform_eta1e-6.npz")
 
 
 def pass_bytes(m: int, n: int) -> float:
@@ -104,8 +108,9 @@ def kt_dict(kt):
             for k, v in kt.items() if v[1]}
 
 
-def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0=None):
-    """Wall time from X^0 (gamma0 or zero) to a certified relative gap <= `gap`."""
+def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0_fn=None):
+    """Wall time from X^0 to a certified relative gap <= `gap`, starting the first
+    subproblem from gamma = 0 or from gamma0_fn() (called inside the timed region)."""
     import torch
 
     pr = ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=precision)
@@ -113,6 +118,8 @@ def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0=N
     ctx.kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    gamma0 = gamma0_fn() if gamma0_fn else None
+    t_ws = time.perf_counter() - t0
     res = ibsn.solve(ctx, pr, opt, gamma0=gamma0, trace_cap=max_outer)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -129,7 +136,8 @@ def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0=N
             cum[str(t["k"] + 1)] = {"seconds": acc, "rel_gap": t["rel_gap"],
                                     "newton": t["newton"], "backtracks": t["backtracks"],
                                     "sinkhorn": t["sinkhorn"]}
-    return {"seconds": dt, "status": res["status"], "rel_gap": rep["rel_gap"],
+    return {"seconds": dt, "warm_start_seconds": t_ws if gamma0_fn else None,
+            "status": res["status"], "rel_gap": rep["rel_gap"],
             "by_outer": cum,
             "primal": rep["primal"], "dual": rep["dual"], "outer": rep["outer"],
             "newton": rep["newton"], "cg": rep["cg"], "sinkhorn": rep["sinkhorn"],
@@ -138,6 +146,30 @@ def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0=N
             "t_eval": rep["t_eval"], "t_sparsify": rep["t_sparsify"], "t_cg": rep["t_cg"],
             "t_linesearch": rep["t_linesearch"], "t_stop": rep["t_stop"],
             "kernel_ms": kt_dict(kt)}
+
+
+def warm_start_fn(ibsn, ctx, prob, inst):
+    """gamma0 of the first subproblem from the trained network (features, forward, centring
+    and scaling all in the library's kernels), or None when no trained weights exist."""
+    import numpy as np
+    import torch
+
+    if not os.path.exists(WS_WEIGHTS) or inst.x is None:
+        return None, None
+    d = np.load(WS_WEIGHTS)
+    ws = ibsn.WarmStart(ctx)
+    ws.set_params(d["params"])
+    x = torch.from_numpy(np.ascontiguousarray(inst.x)).to(prob.C.device)
+    y = torch.from_numpy(np.ascontiguousarray(inst.y)).to(prob.C.device)
+    m, n = inst.C.shape
+
+    def fn():
+        fs, fte, fth, scale = ws.features(prob, x, y)
+        return ws.predict(m, n, fs, fte, fth, scale)
+    info = {"weights": os.path.relpath(WS_WEIGHTS, ROOT), "trained_n": int(d["n"]),
+            "trained_eta": float(d["eta"]), "train_instances": int(d["train"]),
+            "val_r2": float(d["val_r2"])}
+    return fn, (ws, info)
 
 
 def batch_solves(ibsn, count: int, outer: int = 20):
@@ -266,6 +298,14 @@ def main() -> int:
         ttg["plain_f64"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_F64)
         ttg["mixed_fp32"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_MIXED)
         ttg["mixed_over_plain_time"] = ttg["mixed_fp32"]["seconds"] / ttg["plain_f64"]["seconds"]
+        fn, held = warm_start_fn(ibsn, ctx, prob, inst)
+        if fn:
+            ttg["warm_start"] = held[1]
+            ttg["warm_f64"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_F64, gamma0_fn=fn)
+            ttg["warm_mixed_fp32"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_MIXED, gamma0_fn=fn)
+            ttg["warm_mixed_over_plain_time"] = (ttg["warm_mixed_fp32"]["seconds"]
+                                                 / ttg["plain_f64"]["seconds"])
+            held[0].free()
         out["time_to_1e-8_gap"] = ttg
         mk = ttg["mixed_fp32"]["kernel_ms"].get("eval_mixed")
         if mk:

@@ -350,21 +350,24 @@ int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_
    gamma^{0,0} = 0; a starting dual only changes where the first subproblem's iteration
    begins, not what it converges to).
    A point-set network: a per-point MLP encoder (3 layers of width 256, ReLU) over the
-   sources and the targets, mean pooling per side, and a per-target head (3 layers) fed with
-   the target's features and the two pooled vectors.  Its output o_j is centred and scaled:
-   gamma_j = scale (o_j - mean o), scale = mean_j min_i C_ij.  Every matrix product runs as
+   sources and the targets, mean pooling per side into a context c = Wc [h_s; h_t] + bc
+   (256 values per instance), and a per-target head (2 layers of width 256, ReLU) over the
+   target's features whose output is read out against the context, o_j = z2_j . c + bo.
+   The output is centred and scaled: gamma_j = scale (o_j - mean o) with
+   scale = sqrt(mean_j min_i C_ij).  Every matrix product runs as
    BF16 MFMA with FP32 accumulation (operands rounded to BF16 where they enter a product);
    biases, activations, pooling, the loss and the Adam update are FP32.
    Features (ibsn_ws_features, 2-D points): sources (x_i1, x_i2, m a_i, 1) and targets
-   (y_j1, y_j2, n b_j, -1) for the encoder, (y_j1, y_j2, n b_j, min_i C_ij / scale) for the
-   head: FP32 device arrays fs (m x 4), fte (n x 4), fth (n x 4), row-major.
+   (y_j1, y_j2, n b_j, -1) for the encoder, (y_j1, y_j2, n b_j, min_i C_ij / mean_j min_i C_ij)
+   for the head: FP32 device arrays fs (m x 4), fte (n x 4), fth (n x 4), row-major.
    ------------------------------------------------------------------------------------ */
 typedef struct ibsn_ws_model ibsn_ws_model;
 
-/* Number of FP32 parameters (W1 b1 W2 b2 W3 b3 Wf Wc bf Wg bg wo bo, weights stored
+/* Number of FP32 parameters (W1 b1 W2 b2 W3 b3 Wf bf Wg bg Wc bc bo, weights stored
    inputs x outputs, row-major, concatenated in that order). */
 int64_t ibsn_ws_param_count(void);
-/* New model on the context's device, He-initialised from `seed`; free with ibsn_ws_free. */
+/* New model on the context's device, weights He-initialised from `seed`, biases zero; free
+   with ibsn_ws_free. */
 int ibsn_ws_create(ibsn_ctx *ctx, uint64_t seed, ibsn_ws_model **out);
 void ibsn_ws_free(ibsn_ws_model *model);
 /* Host copies of the FP32 parameters (count = ibsn_ws_param_count()).  set also resets the
@@ -372,7 +375,7 @@ void ibsn_ws_free(ibsn_ws_model *model);
 int ibsn_ws_get_params(ibsn_ctx *ctx, const ibsn_ws_model *model, float *host, int64_t count);
 int ibsn_ws_set_params(ibsn_ctx *ctx, ibsn_ws_model *model, const float *host, int64_t count);
 /* Features of one problem given its 2-D points x (m x 2) and y (n x 2) (device FP64);
-   scale_host receives mean_j min_i C_ij.  Synchronises. */
+   scale_host receives sqrt(mean_j min_i C_ij).  Synchronises. */
 int ibsn_ws_features(ibsn_ctx *ctx, const ibsn_problem *prob, const double *x, const double *y,
                      float *fs, float *fte, float *fth, double *scale_host);
 /* Raw outputs o (B n, FP32 device) for B instances of m sources and n targets, features

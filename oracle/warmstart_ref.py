@@ -2,14 +2,15 @@
 
 A plain NumPy (FP64) forward and backward pass of the point-set network that the library
 evaluates with BF16 MFMA kernels: per-point encoder (3 layers of width 256, ReLU between),
-mean pooling of the sources and of the targets, per-target head (3 layers), output centred
-per instance.  With ``bf16=True`` every operand of a matrix product is rounded to BF16
-(round to nearest even) where it enters the product, as the library does; the products
-themselves, biases, activations, pooling and the loss are exact FP64 here (the library
-accumulates in FP32).  ``bf16=False`` is the plain FP64 network, checked against finite
-differences in the tests.  Parameter order and shapes follow ``ibsn_ws_param_count``:
-W1 (4 x 256), b1, W2 (256 x 256), b2, W3, b3, Wf (4 x 256), Wc (512 x 256), bf, Wg, bg,
-wo (256 x 1), bo.
+mean pooling of the sources and of the targets into a context vector c = Wc [h_s; h_t] + bc,
+per-target head (2 layers) whose output is read out against the context, o_j = z2_j . c + bo,
+output centred per instance.  With ``bf16=True`` every operand of a matrix product is rounded
+to BF16 (round to nearest even) where it enters the product, as the library does; the
+products themselves, biases, activations, pooling and the loss are exact FP64 here (the
+library accumulates in FP32).  ``bf16=False`` is the plain FP64 network, checked against
+finite differences in the tests.  Parameter order and shapes follow ``ibsn_ws_param_count``:
+W1 (4 x 256), b1, W2 (256 x 256), b2, W3, b3, Wf (4 x 256), bf, Wg (256 x 256), bg,
+Wc (512 x 256), bc, bo.
 """
 from __future__ import annotations
 
@@ -17,8 +18,8 @@ import numpy as np
 
 WID, NF = 256, 4
 SHAPES = [("W1", NF, WID), ("b1", 1, WID), ("W2", WID, WID), ("b2", 1, WID), ("W3", WID, WID),
-          ("b3", 1, WID), ("Wf", NF, WID), ("Wc", 2 * WID, WID), ("bf", 1, WID),
-          ("Wg", WID, WID), ("bg", 1, WID), ("wo", WID, 1), ("bo", 1, 1)]
+          ("b3", 1, WID), ("Wf", NF, WID), ("bf", 1, WID), ("Wg", WID, WID), ("bg", 1, WID),
+          ("Wc", 2 * WID, WID), ("bc", 1, WID), ("bo", 1, 1)]
 
 
 def param_count() -> int:
@@ -64,12 +65,13 @@ def forward(flat, fs, fte, fth, B, m, n, bf16=True):
     hs = E[:B * m].reshape(B, m, WID).mean(1)
     ht = E[B * m:].reshape(B, n, WID).mean(1)
     CTX = np.concatenate([hs, ht], axis=1)
-    CB = _mm(CTX, p["Wc"], bf16) + p["bf"]
+    CB = _mm(CTX, p["Wc"], bf16) + p["bc"]
     XH = np.asarray(fth, np.float64)
-    Z1 = np.maximum(_mm(XH, p["Wf"], bf16) + np.repeat(CB, n, axis=0), 0.0)
+    Z1 = np.maximum(_mm(XH, p["Wf"], bf16) + p["bf"], 0.0)
     Z2 = np.maximum(_mm(Z1, p["Wg"], bf16) + p["bg"], 0.0)
-    O = (_mm(Z2, p["wo"], bf16) + p["bo"]).reshape(-1)
-    cache = dict(p=p, X=X, H1=H1, H2=H2, E=E, CTX=CTX, XH=XH, Z1=Z1, Z2=Z2)
+    O = np.concatenate([_mm(Z2[b * n:(b + 1) * n], CB[b][:, None], bf16).reshape(-1)
+                        for b in range(B)]) + p["bo"][0, 0]
+    cache = dict(p=p, X=X, H1=H1, H2=H2, E=E, CTX=CTX, CB=CB, XH=XH, Z1=Z1, Z2=Z2)
     return O, cache
 
 
@@ -90,15 +92,20 @@ def loss_and_grad(flat, fs, fte, fth, target, B, m, n, bf16=True):
     dO = (2.0 / (B * n)) * (d - d.mean(1, keepdims=True))
     dO = dO.reshape(-1, 1)
     g = {}
-    g["wo"] = _mm(c["Z2"].T, dO, bf16)
     g["bo"] = dO.sum(0, keepdims=True)
-    dZ2 = _mm(dO, p["wo"].T, bf16) * (c["Z2"] > 0)
+    dZ2 = np.zeros_like(c["Z2"])
+    dCB = np.zeros_like(c["CB"])
+    for b in range(B):
+        rows = slice(b * n, (b + 1) * n)
+        dZ2[rows] = _mm(dO[rows], c["CB"][b][None, :], bf16)
+        dCB[b] = _mm(dO[rows].T, c["Z2"][rows], bf16)[0]
+    dZ2 *= c["Z2"] > 0
     g["Wg"] = _mm(c["Z1"].T, dZ2, bf16)
     g["bg"] = dZ2.sum(0, keepdims=True)
     dZ1 = _mm(dZ2, p["Wg"].T, bf16) * (c["Z1"] > 0)
     g["Wf"] = _mm(c["XH"].T, dZ1, bf16)
-    dCB = dZ1.reshape(B, n, WID).sum(1)
-    g["bf"] = dCB.sum(0, keepdims=True)
+    g["bf"] = dZ1.sum(0, keepdims=True)
+    g["bc"] = dCB.sum(0, keepdims=True)
     g["Wc"] = _mm(c["CTX"].T, dCB, bf16)
     dCTX = _mm(dCB, p["Wc"].T, bf16)
     dE = np.concatenate([np.repeat(dCTX[:, :WID] / m, m, axis=0),
@@ -116,11 +123,12 @@ def loss_and_grad(flat, fs, fte, fth, target, B, m, n, bf16=True):
 
 def features(x, y, a, b, C):
     """Feature rows of one instance (FP64): fs (m x 4), fte, fth (n x 4), and the scale
-    mean_j min_i C_ij, as defined for ibsn_ws_features."""
+    sqrt(mean_j min_i C_ij), as defined for ibsn_ws_features."""
     m, n = len(a), len(b)
     cmin = np.asarray(C, np.float64).min(0)
-    scale = cmin.mean()
+    cmean = cmin.mean()
     fs = np.column_stack([x[:, 0], x[:, 1], m * np.asarray(a), np.ones(m)])
     fte = np.column_stack([y[:, 0], y[:, 1], n * np.asarray(b), -np.ones(n)])
-    fth = np.column_stack([y[:, 0], y[:, 1], n * np.asarray(b), cmin / scale])
+    fth = np.column_stack([y[:, 0], y[:, 1], n * np.asarray(b), cmin / cmean])
+    scale = float(np.sqrt(cmean))
     return fs, fte, fth, scale

@@ -7,15 +7,18 @@
 // Network (widths 256, ReLU):
 //   encoder   per point p (sources and targets alike), features f_p in R^4,
 //             e_p = W3 relu(W2 relu(W1 f_p + b1) + b2) + b3                    (3 layers)
-//   pooling   h_s = mean over the sources of e_p, h_t = mean over the targets
+//   pooling   h_s = mean over the sources of e_p, h_t = mean over the targets, and the
+//             instance's context c = Wc [h_s; h_t] + bc
 //   head      per target j, features u_j in R^4,
-//             z1 = relu(Wf u_j + Wc [h_s; h_t] + bf),  z2 = relu(Wg z1 + bg),
-//             o_j = wo . z2 + bo                                               (3 layers)
-//   output    gamma_j = scale * (o_j - mean_j o_j)   (the subproblem's dual is defined up
-//             to a constant; scale = the mean over targets of min_i C_ij, so the prediction
-//             follows the cost's scale)
+//             z1 = relu(Wf u_j + bf),  z2 = relu(Wg z1 + bg),  o_j = z2 . c + bo  (3 layers)
+//   output    gamma_j = scale (o_j - mean_j o_j)   (the subproblem's dual is defined up
+//             to a constant; scale = sqrt(mean over targets of min_i C_ij), the unit in
+//             which the first subproblem's dual varies at every size)
+// The readout o_j = z2 . c combines a learned basis of the target's position with
+// coefficients pooled from both point sets, which is the form of the dual's dependence on
+// the densities to first order.
 // Features: sources (x_i1, x_i2, m a_i, +1), targets (y_j1, y_j2, n b_j, -1) for the
-// encoder; (y_j1, y_j2, n b_j, min_i C_ij / scale) for the head.
+// encoder; (y_j1, y_j2, n b_j, min_i C_ij / mean_j min_i C_ij) for the head.
 //
 // Arithmetic: every matrix product is a BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
 // accumulation; its operands are rounded to BF16 (round to nearest even) where they enter
@@ -353,7 +356,7 @@ unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-// the model: parameters in a fixed order (W1 b1 W2 b2 W3 b3 Wf Wc bf Wg bg wo bo; a weight
+// the model: parameters in a fixed order (W1 b1 W2 b2 W3 b3 Wf bf Wg bg Wc bc bo; a weight
 // matrix is inputs x outputs, row-major), FP32 master copies, BF16 copies, Adam moments,
 // gradients, and grow-only activation buffers
 // ---------------------------------------------------------------------------------
@@ -363,10 +366,10 @@ struct Param {
     int64_t off;
 };
 constexpr int NPARAM = 13;
-enum { P_W1, P_B1, P_W2, P_B2, P_W3, P_B3, P_WF, P_WC, P_BF, P_WG, P_BG, P_WO, P_BO };
-const int SHAPES[NPARAM][2] = {{NF, WID},  {1, WID},   {WID, WID}, {1, WID}, {WID, WID},
-                               {1, WID},   {NF, WID},  {2 * WID, WID}, {1, WID}, {WID, WID},
-                               {1, WID},   {WID, 1},   {1, 1}};
+enum { P_W1, P_B1, P_W2, P_B2, P_W3, P_B3, P_WF, P_BF, P_WG, P_BG, P_WC, P_BC, P_BO };
+const int SHAPES[NPARAM][2] = {{NF, WID},  {1, WID}, {WID, WID}, {1, WID},      {WID, WID},
+                               {1, WID},   {NF, WID}, {1, WID},  {WID, WID},    {1, WID},
+                               {2 * WID, WID}, {1, WID}, {1, 1}};
 int64_t layout(Param *p)
 {
     int64_t off = 0;
@@ -472,6 +475,7 @@ int forward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n, c
     WNEED(md->a32[A_CTX], B * 2 * WID);
     WNEED(md->a16[A_CTX], B * 2 * WID);
     WNEED(md->a32[A_CB], B * WID);
+    WNEED(md->a16[A_CB], B * WID);
     WNEED(md->a32[A_TMP], B * WID);
     for (int a : {A_Z1, A_Z2}) {
         WNEED(md->a32[a], T * WID);
@@ -507,15 +511,18 @@ int forward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n, c
     }
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(B * 2 * WID)), dim3(256), 0, st, B * 2 * WID,
                        (const float *)ctxf, md->a16[A_CTX].p);
-    // head: per-instance bias CB = CTX Wc + bf, z1 = relu(u Wf + CB[instance]), z2, o
+    // context c = CTX Wc + bc (B x 256); head z1 = relu(u Wf + bf), z2 = relu(z1 Wg + bg);
+    // o_j = z2_j . c_b + bo, one product per instance
     WCK(gemm(st, false, B, WID, 2 * WID, md->a16[A_CTX].p, 2 * WID, 1, w16 + p[P_WC].off, WID, 1,
-             w + p[P_BF].off, nullptr, 1, md->a32[A_CB].p, nullptr, WID));
-    WCK(gemm(st, true, T, WID, NF, md->a16[A_XH].p, NF, 1, w16 + p[P_WF].off, WID, 1, nullptr,
-             md->a32[A_CB].p, n, md->a32[A_Z1].p, md->a16[A_Z1].p, WID));
+             w + p[P_BC].off, nullptr, 1, md->a32[A_CB].p, md->a16[A_CB].p, WID));
+    WCK(gemm(st, true, T, WID, NF, md->a16[A_XH].p, NF, 1, w16 + p[P_WF].off, WID, 1,
+             w + p[P_BF].off, nullptr, 1, md->a32[A_Z1].p, md->a16[A_Z1].p, WID));
     WCK(gemm(st, true, T, WID, WID, md->a16[A_Z1].p, WID, 1, w16 + p[P_WG].off, WID, 1,
              w + p[P_BG].off, nullptr, 1, md->a32[A_Z2].p, md->a16[A_Z2].p, WID));
-    WCK(gemm(st, false, T, 1, WID, md->a16[A_Z2].p, WID, 1, w16 + p[P_WO].off, 1, 1,
-             w + p[P_BO].off, nullptr, 1, md->a32[A_O].p, nullptr, 1));
+    for (int64_t b = 0; b < B; ++b)
+        WCK(gemm(st, false, n, 1, WID, md->a16[A_Z2].p + b * n * WID, WID, 1,
+                 md->a16[A_CB].p + b * WID, 1, 1, w + p[P_BO].off, nullptr, 1,
+                 md->a32[A_O].p + b * n, nullptr, 1));
     return IBSN_OK;
 }
 
@@ -548,12 +555,14 @@ int backward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n)
     const bf16 *w16 = md->w16.p;
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(T)), dim3(256), 0, st, T,
                        (const float *)md->d32[A_O].p, md->d16[A_O].p);
-    // output layer o = z2 wo + bo
-    WCK(gemm(st, false, WID, 1, T, md->a16[A_Z2].p, 1, WID, md->d16[A_O].p, 1, 1, nullptr,
-             nullptr, 1, g + p[P_WO].off, nullptr, 1));
+    // readout o_j = z2_j . c_b + bo: dz2_j = dO_j c_b, dc_b = sum_j dO_j z2_j
     WCK(colsum(st, T, 1, md->d32[A_O].p, g + p[P_BO].off));
-    WCK(gemm(st, false, T, WID, 1, md->d16[A_O].p, 1, 1, w16 + p[P_WO].off, 0, 1, nullptr,
-             nullptr, 1, md->d32[A_Z2].p, nullptr, WID));
+    for (int64_t b = 0; b < B; ++b) {
+        WCK(gemm(st, false, n, WID, 1, md->d16[A_O].p + b * n, 1, 1, md->a16[A_CB].p + b * WID, 0,
+                 1, nullptr, nullptr, 1, md->d32[A_Z2].p + b * n * WID, nullptr, WID));
+        WCK(gemm(st, false, 1, WID, n, md->d16[A_O].p + b * n, 0, 1, md->a16[A_Z2].p + b * n * WID,
+                 WID, 1, nullptr, nullptr, 1, md->d32[A_CB].p + b * WID, nullptr, WID));
+    }
     relu_bwd(st, md, A_Z2, T * WID);
     // z2 = relu(z1 Wg + bg)
     WCK(gemm(st, false, WID, WID, T, md->a16[A_Z1].p, 1, WID, md->d16[A_Z2].p, WID, 1, nullptr,
@@ -562,12 +571,12 @@ int backward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n)
     WCK(gemm(st, false, T, WID, WID, md->d16[A_Z2].p, WID, 1, w16 + p[P_WG].off, 1, WID, nullptr,
              nullptr, 1, md->d32[A_Z1].p, nullptr, WID));
     relu_bwd(st, md, A_Z1, T * WID);
-    // z1 = relu(u Wf + CB[instance]), CB = CTX Wc + bf
+    // z1 = relu(u Wf + bf)
     WCK(gemm(st, false, NF, WID, T, md->a16[A_XH].p, 1, NF, md->d16[A_Z1].p, WID, 1, nullptr,
              nullptr, 1, g + p[P_WF].off, nullptr, WID));
-    hipLaunchKernelGGL(k_group_sum, dim3(1, (unsigned)B), dim3(256), 0, st, (int)B, (int)n, WID,
-                       (const float *)md->d32[A_Z1].p, 1.0f, 0, md->d32[A_CB].p);
-    WCK(colsum(st, B, WID, md->d32[A_CB].p, g + p[P_BF].off));
+    WCK(colsum(st, T, WID, md->d32[A_Z1].p, g + p[P_BF].off));
+    // c = CTX Wc + bc
+    WCK(colsum(st, B, WID, md->d32[A_CB].p, g + p[P_BC].off));
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(B * WID)), dim3(256), 0, st, B * WID,
                        (const float *)md->d32[A_CB].p, md->d16[A_CB].p);
     WCK(gemm(st, false, 2 * WID, WID, B, md->a16[A_CTX].p, 1, 2 * WID, md->d16[A_CB].p, WID, 1,
@@ -641,7 +650,7 @@ int ibsn_ws_create(ibsn_ctx *ctx, uint64_t seed, ibsn_ws_model **out)
     std::mt19937_64 rng(seed);
     for (int i = 0; i < NPARAM; ++i) {
         const Param &p = md->prm[i];
-        if (p.rows == 1 && i != P_WO)
+        if (p.rows == 1)
             continue;
         std::normal_distribution<float> nd(0.0f, sqrtf(2.0f / (float)p.rows));
         for (int64_t k = 0; k < (int64_t)p.rows * p.cols; ++k)
@@ -730,9 +739,11 @@ int ibsn_ws_features(ibsn_ctx *ctx, const ibsn_problem *prob, const double *x, c
     hipLaunchKernelGGL(k_features, dim3(nblk(m > n ? m : n)), dim3(256), 0, st, (int)m, (int)n, x,
                        y, prob->a, prob->b, (const double *)cm, (const double *)(cm + n), fs, fte,
                        fth);
-    WCK(hipMemcpyAsync(scale_host, cm + n, sizeof(double), hipMemcpyDeviceToHost, st));
+    double cmean = 0.0;
+    WCK(hipMemcpyAsync(&cmean, cm + n, sizeof(double), hipMemcpyDeviceToHost, st));
     WCK(hipFreeAsync(cm, st));
     WCK(hipStreamSynchronize(st));
+    *scale_host = sqrt(cmean);
     return IBSN_OK;
 }
 
