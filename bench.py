@@ -50,10 +50,10 @@ WS_WEIGHTS = os.path.join(ROOT, "paper_2603_07156_amd", "warmstart_uniform_eta1e
 
 
 def pass_bytes(m: int, n: int) -> float:
-    """Algorithmic bytes of one dense pass: the FP64 cost once plus the m- and n-vectors
-    it reads or writes (w and its low parts, a, M, S, partial sums: 4 m-vectors and 5.5
-    n-vectors; the low parts are read as FP64 and staged as FP32)."""
-    return 8.0 * m * n + 8.0 * (4 * m + 5 * n) + 8.0 * n
+    """Algorithmic bytes of one dense pass (probe.algorithmic_bytes: the FP64 cost once,
+    4 m-vectors and 6 n-vectors)."""
+    import probe
+    return probe.algorithmic_bytes(m, n)
 
 
 def cg_roofline(m: int, n: int, rep: dict, kt: dict):

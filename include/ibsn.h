@@ -73,6 +73,19 @@ void ibsn_destroy(ibsn_ctx *ctx);
 const char *ibsn_last_error(const ibsn_ctx *ctx);
 /* Number of compute units of the context's device (host value). */
 int ibsn_num_cus(const ibsn_ctx *ctx);
+/* How the context runs CG (Algorithm 2, step 8; ibsn_cg and the Newton steps of the
+   solvers).  IBSN_CG_PERSISTENT: every iteration inside one cooperative launch of `blocks`
+   resident workgroups (0: chosen from the problem size) with two grid-wide barriers per
+   iteration; IBSN_CG_LAUNCHES: three kernel launches per iteration, the host following the
+   residual in chunks; IBSN_CG_AUTO (the default): persistent where the device supports
+   cooperative launches.  The two forms run the same recurrences; p.(H_rho + shift I)p is
+   taken as the quadratic form (sum d p^2 - sum a (P_rho p)^2)/eta + shift sum p^2 in the
+   persistent form and as the dot product of p with the computed product in the other, so
+   iterates agree to rounding.  IBSN_ERR_INVALID_ARG for an unknown mode or blocks outside
+   0..1024, IBSN_ERR_UNSUPPORTED for IBSN_CG_PERSISTENT without cooperative launches; a grid
+   larger than the device can hold resident makes the CG calls fail with IBSN_ERR_HIP. */
+enum { IBSN_CG_AUTO = 0, IBSN_CG_LAUNCHES = 1, IBSN_CG_PERSISTENT = 2 };
+int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks);
 
 typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1, IBSN_COST_POINTS = 2 } ibsn_cost_kind;
 
@@ -352,21 +365,35 @@ int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_
    A point-set network: a per-point MLP encoder (3 layers of width 256, ReLU) over the
    sources and the targets, mean pooling per side into a context c = Wc [h_s; h_t] + bc
    (256 values per instance), and a per-target head (2 layers of width 256, ReLU) over the
-   target's features whose output is read out against the context, o_j = z2_j . c + bo.
-   The output is centred and scaled: gamma_j = scale (o_j - mean o) with
-   scale = sqrt(mean_j min_i C_ij).  Every matrix product runs as
-   BF16 MFMA with FP32 accumulation (operands rounded to BF16 where they enter a product);
-   biases, activations, pooling, the loss and the Adam update are FP32.
-   Features (ibsn_ws_features, 2-D points): sources (x_i1, x_i2, m a_i, 1) and targets
-   (y_j1, y_j2, n b_j, -1) for the encoder, (y_j1, y_j2, n b_j, min_i C_ij / mean_j min_i C_ij)
-   for the head: FP32 device arrays fs (m x 4), fte (n x 4), fth (n x 4), row-major.
+   target's 8 features f_j whose output is read out against the context, plus a linear
+   path from the same features: o_j = z2_j . c + ws . f_j + bo.  The output is centred and
+   scaled: gamma_j = scale (o_j - mean o).  Every matrix product of the MLP runs as BF16
+   MFMA with FP32 accumulation (operands rounded to BF16 where they enter a product);
+   biases, activations, pooling, the linear path, the loss and the Adam update are FP32.
+   Features (ibsn_ws_features, 2-D points).  Coordinates are box coordinates: shifted by
+   the lower corner of the bounding box of all points and divided by its longer side L.
+   u = kappa L^2 is the cost of a unit box distance squared, kappa = sum_{i<K} C_ii /
+   sum_{i<K} |x_i - y_i|^2 over the first K = min(m, n, 4096) pairs (the points cost's
+   cost_scale for IBSN_COST_POINTS); s = sqrt(mean_j min_i C_ij / u), the typical
+   distance from a target to its nearest source in box units; scale = u s.
+     fs  (m x 4): (x~_i1, x~_i2, m a_i, 1)          encoder, sources
+     fte (n x 4): (y~_j1, y~_j2, n b_j, -1)         encoder, targets
+     fth (n x 8): (y~_j1, y~_j2, n b_j, min_i C_ij / mean_j min_i C_ij,
+                   (G_k(j) - mean_j G_k) / s, k = 1..4)
+   with G_k(j) = sum_i a_i g_k(x~_i, y~_j) - sum_l b_l g_k(y~_l, y~_j),
+   g_k(p, q) = log(|p - q|^2 + e_k^2) / 2 summed over the nine mirror images of p in the
+   box, e_k = 0.01, 0.02, 0.04, 0.08: the potential of the linearised Monge-Ampere equation
+   (its Laplacian is the difference of the two densities, smoothed at e_k, with a
+   reflecting boundary), computed with FP32 logarithms and FP64 sums.  FP32 device
+   arrays, row-major.
    ------------------------------------------------------------------------------------ */
 typedef struct ibsn_ws_model ibsn_ws_model;
 
-/* Number of FP32 parameters (W1 b1 W2 b2 W3 b3 Wf bf Wg bg Wc bc bo, weights stored
+/* Number of FP32 parameters (W1 b1 W2 b2 W3 b3 Wf bf Wg bg Wc bc ws bo, weights stored
    inputs x outputs, row-major, concatenated in that order). */
 int64_t ibsn_ws_param_count(void);
-/* New model on the context's device, weights He-initialised from `seed`, biases zero; free
+/* New model on the context's device, weight matrices He-initialised from `seed`; biases,
+   the linear path ws and the context map Wc start at zero (the output starts at 0).  Free
    with ibsn_ws_free. */
 int ibsn_ws_create(ibsn_ctx *ctx, uint64_t seed, ibsn_ws_model **out);
 void ibsn_ws_free(ibsn_ws_model *model);
@@ -375,11 +402,11 @@ void ibsn_ws_free(ibsn_ws_model *model);
 int ibsn_ws_get_params(ibsn_ctx *ctx, const ibsn_ws_model *model, float *host, int64_t count);
 int ibsn_ws_set_params(ibsn_ctx *ctx, ibsn_ws_model *model, const float *host, int64_t count);
 /* Features of one problem given its 2-D points x (m x 2) and y (n x 2) (device FP64);
-   scale_host receives sqrt(mean_j min_i C_ij).  Synchronises. */
+   scale_host receives u s (above).  Synchronises. */
 int ibsn_ws_features(ibsn_ctx *ctx, const ibsn_problem *prob, const double *x, const double *y,
                      float *fs, float *fte, float *fth, double *scale_host);
 /* Raw outputs o (B n, FP32 device) for B instances of m sources and n targets, features
-   stacked by instance (fs: B m x 4, fte and fth: B n x 4). */
+   stacked by instance (fs: B m x 4, fte: B n x 4, fth: B n x 8). */
 int ibsn_ws_forward(ibsn_ctx *ctx, ibsn_ws_model *model, int64_t B, int64_t m, int64_t n,
                     const float *fs, const float *fte, const float *fth, float *out);
 /* The warm start of one instance: gamma_out (n, FP64 device) = scale (o - mean o). */

@@ -1,0 +1,353 @@
+// cg_persistent.hip -- conjugate gradients (Algorithm 2, step 8) for
+// (H_rho + shift I) x = rhs in one cooperative launch on gfx950.
+//
+// Late in a solve the sparsified factor keeps a few entries per row, so one CG iteration
+// moves about a megabyte: it is bound by latency, and three launches per iteration cost
+// more than the work they carry.  Here every workgroup stays resident for the whole solve
+// (hipLaunchCooperativeKernel refuses a grid that cannot be) and the phases of an
+// iteration are separated by a grid-wide barrier instead of kernel boundaries.
+//
+// Two barriers per iteration.  With p = r + beta p_old formed on the fly wherever it is
+// read, phase A gathers the rows, u = a.(P_rho p), and the three sums that give
+//     p.(H_rho + shift I) p = (sum_j d_j p_j^2 - sum_i a_i (P_rho p)_i^2) / eta
+//                             + shift sum_j p_j^2
+// (H_rho = (diag(d) - P_rho^T diag(a) P_rho)/eta), so alpha is known once phase A ends.
+// Phase B gathers the columns, y = (H_rho + shift I) p, and applies the update at once:
+// p <- p, x += alpha p, r -= alpha y, and the partial sums of r.r.  The next phase A starts
+// from beta = r.r / r.r_old.
+//
+// Grid sums are per-workgroup partials added by every workgroup in index order (the same
+// value everywhere, so every workgroup takes the same decisions and leaves the loop
+// together).  The barrier is an arrival counter (zeroed before the launch, never reset):
+// barrier k returns once the counter reaches k * grid.  Every wave waits for its own
+// stores, then one wave per workgroup releases them at device scope (the L2 of each XCD
+// is written back) before arriving, and acquires after the wait, so the phase's writes of
+// every workgroup are seen by every other.  A release per wave instead of per workgroup
+// measured 27 us per iteration against 17 us at m = n = 10^4; 1024-thread workgroups were
+// slower too.  The wait is bounded: a workgroup that waits longer than BAR_SPIN polls raises
+// the error flag and leaves, so a fault in the barrier ends the kernel with an error instead
+// of a hang.
+#include "ibsn_internal.h"
+
+#include <math.h>
+
+namespace ibsn {
+namespace {
+
+constexpr int PT = 256;                  // threads per workgroup
+constexpr int64_t BAR_SPIN = 1ll << 22;  // polls (each after s_sleep) before giving up
+
+struct PersistArgs {
+    int m, n, maxit, star_chunk;
+    const int32_t *col;
+    const void *val;
+    const int32_t *len;
+    const int *istar_p;
+    const int64_t *colptr;
+    const int32_t *rowidx;
+    const void *cval;
+    const double *d, *a, *rhs;
+    double eta, shift, tol;
+    double *x, *r, *p, *au;
+    double *star_part, *part_a, *part_b;   // grid, 3 grid, grid
+    double *scal;                          // out: CG_IT0, CG_RR0, CG_DONE0, CG_BRK
+    unsigned *bar;                         // [0] arrivals, [1] error flag
+};
+
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sums of four values over the workgroup (valid in every thread), fixed order.
+__device__ __forceinline__ void block_sum4(double &v0, double &v1, double &v2, double &v3,
+                                           double *lds)
+{
+    v0 = wsum(v0);
+    v1 = wsum(v1);
+    v2 = wsum(v2);
+    v3 = wsum(v3);
+    const int w = threadIdx.x / 64;
+    __syncthreads();   // lds reuse across calls
+    if ((threadIdx.x & 63) == 0) {
+        lds[4 * w] = v0;
+        lds[4 * w + 1] = v1;
+        lds[4 * w + 2] = v2;
+        lds[4 * w + 3] = v3;
+    }
+    __syncthreads();
+    v0 = lds[0];
+    v1 = lds[1];
+    v2 = lds[2];
+    v3 = lds[3];
+#pragma unroll
+    for (int k = 1; k < PT / 64; ++k) {
+        v0 += lds[4 * k];
+        v1 += lds[4 * k + 1];
+        v2 += lds[4 * k + 2];
+        v3 += lds[4 * k + 3];
+    }
+}
+
+// Grid-wide barrier number `target / grid`; false (every thread) when it timed out or
+// another workgroup raised the error flag.  A workgroup barrier alone does not wait for
+// the other waves' stores, hence the wait in every wave first.
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned target, int *sflag)
+{
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        // one release per workgroup: writes the L2's dirty lines back for the other XCDs
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t k = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                ++k > BAR_SPIN) {
+                ok = 0;
+                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        // one acquire per workgroup: invalidates this CU's L1 and stale L2 lines
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *sflag = ok;
+    }
+    __syncthreads();
+    return *sflag != 0;
+}
+
+template <int L, typename VT>
+__global__ __launch_bounds__(PT) void k_cg_persist(PersistArgs A)
+{
+    __shared__ double lds[4 * (PT / 64)];
+    __shared__ int sflag;
+    const int G = (int)gridDim.x, b = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int m = A.m, n = A.n;
+    const VT *val = static_cast<const VT *>(A.val);
+    const VT *cval = static_cast<const VT *>(A.cval);
+    const int istar = *A.istar_p;
+    const VT *prow = istar >= 0 ? val + (int64_t)istar * n : nullptr;
+    constexpr int GPB = PT / L;   // rows (columns) per workgroup per sweep
+    const int l = t % L;
+    unsigned target = 0;
+
+    // x = 0, r = rhs, p = 0 (the first iteration forms p = r + 0 p); partials of r.r
+    {
+        double s0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+        for (int j = b * PT + t; j < n; j += G * PT) {
+            const double v = A.rhs[j];
+            A.x[j] = 0.0;
+            A.r[j] = v;
+            A.p[j] = 0.0;
+            s0 = fma(v, v, s0);
+        }
+        block_sum4(s0, z1, z2, z3, lds);
+        if (t == 0)
+            A.part_b[b] = s0;
+    }
+    target += (unsigned)G;
+    if (!grid_barrier(A.bar, target, &sflag))
+        return;
+
+    double rr = 0.0, rr_old = 1.0;
+    int it = 0;
+    bool brk = false;
+    for (;; ++it) {
+        // ---- phase A: beta, the rows u = a.(P p), the sums of p.(H + shift) p
+        {
+            double q0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+            for (int k = t; k < G; k += PT)
+                q0 += A.part_b[k];
+            block_sum4(q0, z1, z2, z3, lds);
+            rr = q0;
+        }
+        if (!(sqrt(rr) > A.tol) || it >= A.maxit)
+            break;
+        const double beta = it == 0 ? 0.0 : rr / rr_old;
+        double cd = 0.0, cp = 0.0, ca = 0.0, cs = 0.0;
+        for (int j = b * PT + t; j < n; j += G * PT) {
+            const double pj = fma(beta, A.p[j], A.r[j]);
+            const double pp = pj * pj;
+            cd = fma(A.d[j], pp, cd);
+            cp += pp;
+        }
+        if (prow) {
+            const int j0 = b * A.star_chunk, j1 = min(n, j0 + A.star_chunk);
+            for (int j = j0 + t; j < j1; j += PT)
+                cs = fma((double)prow[j], fma(beta, A.p[j], A.r[j]), cs);
+        }
+        for (int g = b * GPB + t / L; g < m; g += G * GPB) {
+            if (g == istar)
+                continue;   // the whole lane group skips together
+            const int len = A.len[g];
+            const int32_t *cr = A.col + (int64_t)g * n;
+            const VT *vr = val + (int64_t)g * n;
+            double s = 0.0;
+            for (int e = l; e < len; e += L) {
+                const int j = cr[e];
+                s = fma((double)vr[e], fma(beta, A.p[j], A.r[j]), s);
+            }
+#pragma unroll
+            for (int o = L / 2; o > 0; o >>= 1)
+                s += __shfl_xor(s, o, L);
+            if (l == 0) {
+                const double u = A.a[g] * s;
+                A.au[g] = u;
+                ca = fma(u, s, ca);
+            }
+        }
+        block_sum4(cd, cp, ca, cs, lds);
+        if (t == 0) {
+            A.part_a[3 * b] = cd;
+            A.part_a[3 * b + 1] = cp;
+            A.part_a[3 * b + 2] = ca;
+            A.star_part[b] = cs;
+        }
+        target += (unsigned)G;
+        if (!grid_barrier(A.bar, target, &sflag))
+            return;
+
+        // ---- phase B: alpha, the columns y = (H + shift) p, x += alpha p, r -= alpha y
+        double sd = 0.0, sp = 0.0, sa = 0.0, ss = 0.0;
+        for (int k = t; k < G; k += PT) {
+            sd += A.part_a[3 * k];
+            sp += A.part_a[3 * k + 1];
+            sa += A.part_a[3 * k + 2];
+            ss += A.star_part[k];
+        }
+        block_sum4(sd, sp, sa, ss, lds);
+        const double us = prow ? A.a[istar] * ss : 0.0;
+        const double pap = (sd - sa - us * ss) / A.eta + A.shift * sp;
+        if (!(pap > 0.0)) {
+            brk = true;   // no step; CG ends with the iterate it has
+            break;
+        }
+        const double alpha = rr / pap;
+        double rs = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+        for (int j = b * GPB + t / L; j < n; j += G * GPB) {
+            const int64_t e0 = A.colptr[j], e1 = A.colptr[j + 1];
+            double s = 0.0;
+            for (int64_t e = e0 + l; e < e1; e += L)
+                s = fma((double)cval[e], A.au[A.rowidx[e]], s);
+#pragma unroll
+            for (int o = L / 2; o > 0; o >>= 1)
+                s += __shfl_xor(s, o, L);
+            if (l == 0) {
+                if (prow)
+                    s = fma((double)prow[j], us, s);
+                const double pj = fma(beta, A.p[j], A.r[j]);
+                const double yj = (A.d[j] * pj - s) / A.eta + A.shift * pj;
+                A.p[j] = pj;
+                A.x[j] = fma(alpha, pj, A.x[j]);
+                const double rj = fma(-alpha, yj, A.r[j]);
+                A.r[j] = rj;
+                rs = fma(rj, rj, rs);
+            }
+        }
+        block_sum4(rs, z1, z2, z3, lds);
+        if (t == 0)
+            A.part_b[b] = rs;
+        rr_old = rr;
+        target += (unsigned)G;
+        if (!grid_barrier(A.bar, target, &sflag))
+            return;
+    }
+    if (b == 0 && t == 0) {
+        A.scal[CG_IT0] = (double)it;
+        A.scal[CG_RR0] = rr;
+        A.scal[CG_DONE0] = 1.0;
+        A.scal[CG_BRK] = brk ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_cg_persist_reset(unsigned *bar)
+{
+    bar[0] = 0u;
+    bar[1] = 0u;
+}
+
+template <int L, typename VT>
+hipError_t launch_l(int grid, PersistArgs &A, hipStream_t st)
+{
+    void *args[] = {&A};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_persist<L, VT>),
+                                      dim3((unsigned)grid), dim3(PT), args, 0, st);
+}
+
+}  // namespace
+
+CgPersistPlan cg_persist_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus,
+                              int blocks)
+{
+    CgPersistPlan pl;
+    const int64_t dense = istar >= 0 ? n : 0;
+    const int64_t rows = istar >= 0 ? m - 1 : m;
+    const double avg_row = rows > 0 ? (double)(nnz - dense) / (double)rows : 0.0;
+    const double avg_col = n > 0 ? (double)(nnz - dense) / (double)n : 0.0;
+    const double avg = avg_row > avg_col ? avg_row : avg_col;
+    pl.lanes = avg >= 96.0 ? 64 : (avg >= 12.0 ? 16 : 4);
+    if (blocks <= 0) {
+        // two sweeps of rows (columns) per workgroup
+        const int64_t per = 2 * (PT / pl.lanes);
+        const int64_t mx = m > n ? m : n;
+        int64_t g = (mx + per - 1) / per;
+        blocks = (int)(g < num_cus ? g : num_cus);
+    }
+    pl.blocks = blocks < 1 ? 1 : (blocks > CG_PERSIST_MAX_GRID ? CG_PERSIST_MAX_GRID : blocks);
+    return pl;
+}
+
+hipError_t launch_cg_persist(const CgPersistPlan &pl, const CsrView &c, const double *a,
+                             double eta, double shift, const double *rhs, double tol, int maxit,
+                             CgState &s, double *pp, hipStream_t st)
+{
+    const int G = pl.blocks;
+    PersistArgs A;
+    A.m = (int)c.m;
+    A.n = (int)c.n;
+    A.maxit = maxit;
+    A.star_chunk = (int)((c.n + G - 1) / G);
+    A.col = c.col;
+    A.val = c.val;
+    A.len = c.len;
+    A.istar_p = c.istar;
+    A.colptr = c.colptr;
+    A.rowidx = c.rowidx;
+    A.cval = c.cval;
+    A.d = c.d;
+    A.a = a;
+    A.rhs = rhs;
+    A.eta = eta;
+    A.shift = shift;
+    A.tol = tol;
+    A.x = s.x;
+    A.r = s.r;
+    A.p = s.p;
+    A.au = s.au;
+    A.star_part = pp;
+    A.part_a = pp + G;
+    A.part_b = pp + 4 * G;
+    A.scal = s.scal;
+    A.bar = reinterpret_cast<unsigned *>(pp + 5 * G);
+    hipLaunchKernelGGL(k_cg_persist_reset, dim3(1), dim3(1), 0, st, A.bar);
+    if (c.f32) {
+        if (pl.lanes == 64)
+            return launch_l<64, float>(G, A, st);
+        if (pl.lanes == 16)
+            return launch_l<16, float>(G, A, st);
+        return launch_l<4, float>(G, A, st);
+    }
+    if (pl.lanes == 64)
+        return launch_l<64, double>(G, A, st);
+    if (pl.lanes == 16)
+        return launch_l<16, double>(G, A, st);
+    return launch_l<4, double>(G, A, st);
+}
+
+}  // namespace ibsn

@@ -63,6 +63,10 @@ struct ibsn_ctx {
     DevBuf w, wlo, lcv, clpart, colpart, colpart2, rowpart, rowpart2, scal, colv, cvec, gvec, yv, ecv, psiv, zv;
     DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
+    DevBuf cg_pp;                  // partial sums and barrier state of the one-launch CG
+    int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT
+    int cg_blocks = 0;             // grid of the one-launch CG (0: from the problem size)
+    bool coop = false;             // the device supports cooperative launches
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
     double *cg_host = nullptr;     // pinned, 2 * CG_NSLOT: CG state records, double-buffered
     hipEvent_t cg_ev[2] = {nullptr, nullptr};
@@ -579,9 +583,34 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     s.pap_part = P<double>(ctx->cg_pap);
     s.rr_part = P<double>(ctx->cg_rr);
     s.scal = P<double>(ctx->cg_scal);
-    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->max_lds);
     const CsrView cv = csr_view(c);
     KTimer kt(ctx, IBSN_KT_CG);
+    // the barrier counter counts (2 maxit + 1) grids of arrivals in 32 bits
+    const bool fits = (2.0 * maxit + 1.0) * CG_PERSIST_MAX_GRID < 4294967295.0;
+    if (ctx->cg_mode != IBSN_CG_LAUNCHES && ctx->coop && fits) {
+        // one cooperative launch runs every iteration; one copy of its end state
+        const CgPersistPlan pl =
+            cg_persist_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->cg_blocks);
+        CKI(ensure(ctx, ctx->cg_pp, CG_PERSIST_SCRATCH(pl.blocks) * 8));
+        double *pp = P<double>(ctx->cg_pp);
+        CKH(launch_cg_persist(pl, cv, a, eta, shift, rhs, tol, maxit, s, pp, st));
+        double *h = ctx->cg_host;
+        CKH(hipMemcpyAsync(h, s.scal, sizeof(double) * CG_NSLOT, hipMemcpyDeviceToHost, st));
+        CKH(hipMemcpyAsync(h + CG_NSLOT, pp + 5 * (int64_t)pl.blocks, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+        CKH(hipStreamSynchronize(st));
+        unsigned flag[2];
+        memcpy(flag, h + CG_NSLOT, sizeof(flag));
+        if (flag[1] != 0u)
+            return fail(ctx, IBSN_ERR_HIP, "cg: a grid barrier of the one-launch CG timed out "
+                                           "(%d workgroups)", pl.blocks);
+        *iters = (int)h[CG_IT0];
+        return IBSN_OK;
+    }
+    if (ctx->cg_mode == IBSN_CG_PERSISTENT)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED,
+                    "cg: one-launch CG needs cooperative launches and maxit < 2^21");
+    const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->max_lds);
     CKH(launch_cg_init(c->n, rhs, tol, maxit, s, st));
     int launched = 0;
     // outstanding state records, oldest first: host buffer index and iteration count
@@ -690,7 +719,10 @@ int ibsn_create(ibsn_ctx **out, int device, void *hip_stream)
         delete ctx;
         return IBSN_ERR_HIP;
     }
-    if (hipHostMalloc((void **)&ctx->cg_host, sizeof(double) * 2 * CG_NSLOT) != hipSuccess ||
+    int coop = 0;
+    ctx->coop = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) ==
+                    hipSuccess && coop != 0;
+    if (hipHostMalloc((void **)&ctx->cg_host, sizeof(double) * (2 * CG_NSLOT + 1)) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->cg_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->cg_ev[1], hipEventDisableTiming) != hipSuccess) {
         ibsn_destroy(ctx);
@@ -773,6 +805,21 @@ int ibsn_kernel_times_get(ibsn_ctx *ctx, ibsn_kernel_times *out)
 const char *ibsn_last_error(const ibsn_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int ibsn_num_cus(const ibsn_ctx *ctx) { return ctx ? ctx->num_cus : 0; }
+
+int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (mode < IBSN_CG_AUTO || mode > IBSN_CG_PERSISTENT || blocks < 0 ||
+        blocks > CG_PERSIST_MAX_GRID)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "set_cg_kernel: mode 0..2, 0 <= blocks <= %d",
+                    CG_PERSIST_MAX_GRID);
+    if (mode == IBSN_CG_PERSISTENT && !ctx->coop)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "set_cg_kernel: no cooperative launches");
+    ctx->cg_mode = mode;
+    ctx->cg_blocks = blocks;
+    return IBSN_OK;
+}
 
 void ibsn_default_options(ibsn_options *o)
 {

@@ -189,6 +189,22 @@ hipError_t launch_cg_iteration(const GatherPlan &g, const CsrView &c, const doub
 // writes the state after `it` iterations to slot it&1 (rr, done, iteration count)
 hipError_t launch_cg_check(const GatherPlan &g, CgState &s, int it, int64_t n, hipStream_t st);
 
+// CG in one cooperative launch (cg_persistent.hip): `blocks` resident workgroups of 256
+// threads, `lanes` lanes per row and per column.  pp: CG_PERSIST_SCRATCH(blocks) doubles
+// of partial sums and barrier state.  Results in s.x and s.scal (slot 0: CG_IT0, CG_RR0,
+// CG_DONE0, CG_BRK); the error flag (a barrier wait that timed out) is the unsigned at
+// pp + 5 blocks + 1.
+constexpr int CG_PERSIST_MAX_GRID = 1024;
+#define CG_PERSIST_SCRATCH(blocks) (5 * (int64_t)(blocks) + 1)
+struct CgPersistPlan {
+    int blocks, lanes;
+};
+CgPersistPlan cg_persist_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num_cus,
+                              int blocks);
+hipError_t launch_cg_persist(const CgPersistPlan &pl, const CsrView &c, const double *a,
+                             double eta, double shift, const double *rhs, double tol, int maxit,
+                             CgState &s, double *pp, hipStream_t st);
+
 // export slotted CSR to standard CSR
 hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,

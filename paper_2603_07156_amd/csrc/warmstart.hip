@@ -9,22 +9,25 @@
 //             e_p = W3 relu(W2 relu(W1 f_p + b1) + b2) + b3                    (3 layers)
 //   pooling   h_s = mean over the sources of e_p, h_t = mean over the targets, and the
 //             instance's context c = Wc [h_s; h_t] + bc
-//   head      per target j, features u_j in R^4,
-//             z1 = relu(Wf u_j + bf),  z2 = relu(Wg z1 + bg),  o_j = z2 . c + bo  (3 layers)
+//   head      per target j, features u_j in R^8,
+//             z1 = relu(Wf u_j + bf),  z2 = relu(Wg z1 + bg),
+//             o_j = z2 . c + ws . u_j + bo                                     (3 layers)
 //   output    gamma_j = scale (o_j - mean_j o_j)   (the subproblem's dual is defined up
-//             to a constant; scale = sqrt(mean over targets of min_i C_ij), the unit in
-//             which the first subproblem's dual varies at every size)
-// The readout o_j = z2 . c combines a learned basis of the target's position with
-// coefficients pooled from both point sets, which is the form of the dual's dependence on
-// the densities to first order.
-// Features: sources (x_i1, x_i2, m a_i, +1), targets (y_j1, y_j2, n b_j, -1) for the
-// encoder; (y_j1, y_j2, n b_j, min_i C_ij / mean_j min_i C_ij) for the head.
+//             to a constant; scale = u s below, the unit in which the first subproblem's
+//             dual varies at every size)
+// Features: sources (x~_i1, x~_i2, m a_i, +1), targets (y~_j1, y~_j2, n b_j, -1) for the
+// encoder in box coordinates; for the head (y~_j1, y~_j2, n b_j, min_i C_ij / mean cmin)
+// and four potentials G_k of the linearised Monge-Ampere equation (the Laplacian of the
+// dual's potential is the difference of the two densities to first order), smoothed at
+// four lengths, with mirror images for the box.  At small eta the first subproblem's dual
+// is close to the optimal transport potential, and these four values alone carry most of
+// its variance; the network learns their combination and the rest.
 //
 // Arithmetic: every matrix product is a BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
 // accumulation; its operands are rounded to BF16 (round to nearest even) where they enter
 // a product: the weights (BF16 copies of FP32 master weights), the layer inputs and, in the
-// backward pass, the output gradients.  Biases, activations, pooling, the loss and the Adam
-// update are FP32.
+// backward pass, the output gradients.  Biases, activations, pooling, the linear path, the
+// loss and the Adam update are FP32.
 #include "../../include/ibsn.h"
 #include "ibsn_internal.h"
 
@@ -50,7 +53,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int WID = 256;   // width of every hidden layer
-constexpr int NF = 4;      // features per point
+constexpr int NF = 4;      // encoder features per point
+constexpr int NFH = 8;     // head features per target
 
 // ---------------------------------------------------------------------------------
 // C = act(A B + bias + rowbias[row / grp]) for A (M x K), B (K x N) in BF16 with general
@@ -303,6 +307,41 @@ __global__ void k_colmin_pts(int m, int n, int dim, const double *__restrict__ x
     out[j] = v;
 }
 
+// ol_t = sum_k ws_k f_tk (FP32, k in order)
+__global__ void k_lin_fwd(int64_t T, const float *__restrict__ f, const float *__restrict__ ws,
+                          float *__restrict__ ol)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= T)
+        return;
+    float v = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NFH; ++k)
+        v = fmaf(ws[k], f[t * NFH + k], v);
+    ol[t] = v;
+}
+
+// gws_k = sum_t dO_t f_tk, one workgroup per k (fixed order)
+__global__ __launch_bounds__(256) void k_lin_grad(int64_t T, const float *__restrict__ f,
+                                                  const float *__restrict__ dO,
+                                                  float *__restrict__ gws)
+{
+    __shared__ float red[256];
+    const int k = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t t = threadIdx.x; t < T; t += 256)
+        s = fmaf(dO[t], f[t * NFH + k], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        gws[k] = red[0];
+}
+
 // mean of an n-vector into out[0] (one workgroup)
 __global__ __launch_bounds__(256) void k_mean(int n, const double *__restrict__ x,
                                               double *__restrict__ out)
@@ -322,32 +361,219 @@ __global__ __launch_bounds__(256) void k_mean(int n, const double *__restrict__ 
         out[0] = red[0] / (double)n;
 }
 
-// features: fs (m x 4) = (x1, x2, m a, +1); fte (n x 4) = (y1, y2, n b, -1);
-// fth (n x 4) = (y1, y2, n b, cmin / mean cmin)
+// ---- features -----------------------------------------------------------------
+// Coordinates are taken in the bounding box of all points (shifted to the origin, divided
+// by its longer side L); u = kappa L^2 is the cost of a unit box distance squared (kappa =
+// C_ii / |x_i - y_i|^2 summed over the first K pairs, or the points cost's own scale) and
+// s = sqrt(mean_j min_i C_ij / u) the typical nearest-source distance in box units.
+// par: [0] lo1 [1] lo2 [2] L [3] hin1 [4] hin2 [5] kappa [6] u [7] mean cmin [8] s
+//      [9..12] mean_j G_k
+enum { PR_LO1, PR_LO2, PR_L, PR_HI1, PR_HI2, PR_KAPPA, PR_U, PR_CMEAN, PR_S, PR_GM, PR_N = 16 };
+constexpr int KAPPA_PAIRS = 4096;
+constexpr int NGREEN = 4;
+__constant__ float GREEN_EPS2[NGREEN] = {1e-4f, 4e-4f, 1.6e-3f, 6.4e-3f};   // (0.01 .. 0.08)^2
+
+__device__ __forceinline__ double blk_red(double v, double *red, int op)   // 0 sum 1 min 2 max
+{
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = red[threadIdx.x + w], c = red[threadIdx.x];
+            red[threadIdx.x] = op == 0 ? c + o : (op == 1 ? fmin(c, o) : fmax(c, o));
+        }
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// box, kappa, u (one workgroup of 1024 threads)
+template <typename CT>
+__global__ __launch_bounds__(1024) void k_box(int m, int n, const double *__restrict__ x,
+                                              const double *__restrict__ y, const CT *C,
+                                              int64_t ldc, double pts_scale,
+                                              double *__restrict__ par)
+{
+    __shared__ double red[1024];
+    double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
+    for (int t = threadIdx.x; t < m + n; t += 1024) {
+        const double *q = t < m ? x + 2 * (int64_t)t : y + 2 * (int64_t)(t - m);
+        for (int d = 0; d < 2; ++d) {
+            mn[d] = fmin(mn[d], q[d]);
+            mx[d] = fmax(mx[d], q[d]);
+        }
+    }
+    const int K = min(min(m, n), KAPPA_PAIRS);
+    double num = 0.0, den = 0.0;
+    for (int i = threadIdx.x; i < K; i += 1024) {
+        const double d0 = x[2 * i] - y[2 * i], d1 = x[2 * i + 1] - y[2 * i + 1];
+        den += d0 * d0 + d1 * d1;
+        if (C)
+            num += (double)C[(int64_t)i * ldc + i];
+    }
+    const double lo1 = blk_red(mn[0], red, 1), lo2 = blk_red(mn[1], red, 1);
+    const double hi1 = blk_red(mx[0], red, 2), hi2 = blk_red(mx[1], red, 2);
+    num = blk_red(num, red, 0);
+    den = blk_red(den, red, 0);
+    if (threadIdx.x == 0) {
+        double L = fmax(hi1 - lo1, hi2 - lo2);
+        L = L > 0.0 ? L : 1.0;
+        const double kappa = C ? (den > 0.0 ? num / den : 1.0) : pts_scale;
+        par[PR_LO1] = lo1;
+        par[PR_LO2] = lo2;
+        par[PR_L] = L;
+        par[PR_HI1] = (hi1 - lo1) / L;
+        par[PR_HI2] = (hi2 - lo2) / L;
+        par[PR_KAPPA] = kappa;
+        par[PR_U] = kappa * L * L;
+    }
+}
+
+// Potentials of the linearised Monge-Ampere equation:
+//   G_k(j) = sum_i a_i g_k(x_i, y_j) - sum_l b_l g_k(y_l, y_j),
+//   g_k(p, q) = log(|p - q|^2 + eps_k^2) / 2 summed over the nine mirror images of p in the
+// box (a reflecting boundary).  Grid (target blocks, point splits): thread j of split sp
+// adds the points [q0, q1) of the combined list (sources, then targets with weight -b),
+// staged 256 at a time in LDS as FP32 box coordinates; logs in FP32 (log2, scaled at the
+// end), each tile's sum in FP32, the tiles' sums in FP64.  gpart[sp][j][k].
+__global__ __launch_bounds__(256) void k_green(int m, int n, int per, const double *__restrict__ x,
+                                               const double *__restrict__ y,
+                                               const double *__restrict__ a,
+                                               const double *__restrict__ b,
+                                               const double *__restrict__ par,
+                                               double *__restrict__ gpart)
+{
+    __shared__ float px[256], py[256], pw[256];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int sp = blockIdx.y;
+    const int q0 = sp * per, q1 = min(m + n, q0 + per);
+    const double lo1 = par[PR_LO1], lo2 = par[PR_LO2], iL = 1.0 / par[PR_L];
+    const float h1 = (float)(2.0 * par[PR_HI1]), h2 = (float)(2.0 * par[PR_HI2]);
+    const int jc = j < n ? j : n - 1;
+    const float yj1 = (float)((y[2 * (int64_t)jc] - lo1) * iL);
+    const float yj2 = (float)((y[2 * (int64_t)jc + 1] - lo2) * iL);
+    double acc[NGREEN] = {0.0, 0.0, 0.0, 0.0};
+    for (int t0 = q0; t0 < q1; t0 += 256) {
+        __syncthreads();
+        {
+            const int q = t0 + threadIdx.x;
+            float u1 = 0.0f, u2 = 0.0f, w = 0.0f;
+            if (q < q1) {
+                const double *pt = q < m ? x + 2 * (int64_t)q : y + 2 * (int64_t)(q - m);
+                u1 = (float)((pt[0] - lo1) * iL);
+                u2 = (float)((pt[1] - lo2) * iL);
+                w = q < m ? (float)a[q] : -(float)b[q - m];
+            }
+            px[threadIdx.x] = u1;
+            py[threadIdx.x] = u2;
+            pw[threadIdx.x] = w;
+        }
+        __syncthreads();
+        const int cnt = min(256, q1 - t0);
+        float s[NGREEN] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int e = 0; e < cnt; ++e) {
+            const float p1 = px[e], p2 = py[e], w = pw[e];
+            const float ix[3] = {-p1 - yj1, p1 - yj1, h1 - p1 - yj1};
+            const float iy[3] = {-p2 - yj2, p2 - yj2, h2 - p2 - yj2};
+            float l[NGREEN] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const float D = fmaf(ix[u], ix[u], iy[v] * iy[v]);
+#pragma unroll
+                    for (int k = 0; k < NGREEN; ++k)
+                        l[k] += __log2f(D + GREEN_EPS2[k]);
+                }
+#pragma unroll
+            for (int k = 0; k < NGREEN; ++k)
+                s[k] = fmaf(w, l[k], s[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NGREEN; ++k)
+            acc[k] += (double)s[k];
+    }
+    if (j < n) {
+        constexpr double HALF_LN2 = 0.34657359027997264;   // log(2) / 2
+#pragma unroll
+        for (int k = 0; k < NGREEN; ++k)
+            gpart[((int64_t)sp * n + j) * NGREEN + k] = acc[k] * HALF_LN2;
+    }
+}
+
+// G (n x 4) = sum of the splits in order
+__global__ void k_green_sum(int n, int splits, const double *__restrict__ gpart,
+                            double *__restrict__ g)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n)
+        return;
+    for (int k = 0; k < NGREEN; ++k) {
+        double v = 0.0;
+        for (int sp = 0; sp < splits; ++sp)
+            v += gpart[((int64_t)sp * n + j) * NGREEN + k];
+        g[(int64_t)j * NGREEN + k] = v;
+    }
+}
+
+// means of cmin and of the G columns, and s (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void k_feat_means(int n, const double *__restrict__ cmin,
+                                                     const double *__restrict__ g,
+                                                     double *__restrict__ par)
+{
+    __shared__ double red[1024];
+    double c = 0.0, gs[NGREEN] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < n; j += 1024) {
+        c += cmin[j];
+        for (int k = 0; k < NGREEN; ++k)
+            gs[k] += g[(int64_t)j * NGREEN + k];
+    }
+    const double cm = blk_red(c, red, 0) / (double)n;
+    double gm[NGREEN];
+    for (int k = 0; k < NGREEN; ++k)
+        gm[k] = blk_red(gs[k], red, 0) / (double)n;
+    if (threadIdx.x == 0) {
+        const double u = par[PR_U];
+        par[PR_CMEAN] = cm;
+        par[PR_S] = u > 0.0 ? sqrt(fmax(cm / u, 1e-12)) : 1.0;
+        for (int k = 0; k < NGREEN; ++k)
+            par[PR_GM + k] = gm[k];
+    }
+}
+
+// fs (m x 4) = (x~1, x~2, m a, +1); fte (n x 4) = (y~1, y~2, n b, -1);
+// fth (n x 8) = (y~1, y~2, n b, cmin / mean cmin, (G_k - mean G_k) / s)
 __global__ void k_features(int m, int n, const double *__restrict__ x,
                            const double *__restrict__ y, const double *__restrict__ a,
                            const double *__restrict__ b, const double *__restrict__ cmin,
-                           const double *__restrict__ cmean, float *__restrict__ fs,
-                           float *__restrict__ fte, float *__restrict__ fth)
+                           const double *__restrict__ g, const double *__restrict__ par,
+                           float *__restrict__ fs, float *__restrict__ fte,
+                           float *__restrict__ fth)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
+    const double lo1 = par[PR_LO1], lo2 = par[PR_LO2], iL = 1.0 / par[PR_L];
     if (t < m) {
-        fs[4 * t + 0] = (float)x[2 * t];
-        fs[4 * t + 1] = (float)x[2 * t + 1];
+        fs[4 * t + 0] = (float)((x[2 * t] - lo1) * iL);
+        fs[4 * t + 1] = (float)((x[2 * t + 1] - lo2) * iL);
         fs[4 * t + 2] = (float)((double)m * a[t]);
         fs[4 * t + 3] = 1.0f;
     }
     if (t < n) {
-        const float y0 = (float)y[2 * t], y1 = (float)y[2 * t + 1];
+        const float y0 = (float)((y[2 * t] - lo1) * iL), y1 = (float)((y[2 * t + 1] - lo2) * iL);
         const float w = (float)((double)n * b[t]);
         fte[4 * t + 0] = y0;
         fte[4 * t + 1] = y1;
         fte[4 * t + 2] = w;
         fte[4 * t + 3] = -1.0f;
-        fth[4 * t + 0] = y0;
-        fth[4 * t + 1] = y1;
-        fth[4 * t + 2] = w;
-        fth[4 * t + 3] = (float)(cmin[t] / cmean[0]);
+        float *h = fth + (int64_t)NFH * t;
+        h[0] = y0;
+        h[1] = y1;
+        h[2] = w;
+        h[3] = (float)(cmin[t] / par[PR_CMEAN]);
+        const double is = 1.0 / par[PR_S];
+        for (int k = 0; k < NGREEN; ++k)
+            h[4 + k] = (float)((g[(int64_t)t * NGREEN + k] - par[PR_GM + k]) * is);
     }
 }
 
@@ -356,7 +582,7 @@ unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-// the model: parameters in a fixed order (W1 b1 W2 b2 W3 b3 Wf bf Wg bg Wc bc bo; a weight
+// the model: parameters in a fixed order (W1 b1 W2 b2 W3 b3 Wf bf Wg bg Wc bc ws bo; a weight
 // matrix is inputs x outputs, row-major), FP32 master copies, BF16 copies, Adam moments,
 // gradients, and grow-only activation buffers
 // ---------------------------------------------------------------------------------
@@ -365,11 +591,11 @@ struct Param {
     int rows, cols;
     int64_t off;
 };
-constexpr int NPARAM = 13;
-enum { P_W1, P_B1, P_W2, P_B2, P_W3, P_B3, P_WF, P_BF, P_WG, P_BG, P_WC, P_BC, P_BO };
-const int SHAPES[NPARAM][2] = {{NF, WID},  {1, WID}, {WID, WID}, {1, WID},      {WID, WID},
-                               {1, WID},   {NF, WID}, {1, WID},  {WID, WID},    {1, WID},
-                               {2 * WID, WID}, {1, WID}, {1, 1}};
+constexpr int NPARAM = 14;
+enum { P_W1, P_B1, P_W2, P_B2, P_W3, P_B3, P_WF, P_BF, P_WG, P_BG, P_WC, P_BC, P_WS, P_BO };
+const int SHAPES[NPARAM][2] = {{NF, WID},  {1, WID},  {WID, WID}, {1, WID},      {WID, WID},
+                               {1, WID},   {NFH, WID}, {1, WID},  {WID, WID},    {1, WID},
+                               {2 * WID, WID}, {1, WID}, {NFH, 1},  {1, 1}};
 int64_t layout(Param *p)
 {
     int64_t off = 0;
@@ -407,7 +633,7 @@ struct Buf {
 };
 
 // activations (FP32 and BF16) and their gradients
-enum { A_X, A_XH, A_H1, A_H2, A_E, A_CTX, A_CB, A_Z1, A_Z2, A_O, A_TMP, A_N };
+enum { A_X, A_XH, A_H1, A_H2, A_E, A_CTX, A_CB, A_Z1, A_Z2, A_O, A_OL, A_TMP, A_N };
 }  // namespace
 
 struct ibsn_ws_model {
@@ -470,8 +696,9 @@ int forward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n, c
         WNEED(md->a32[a], P * (a == A_X ? NF : WID));
     for (int a : {A_X, A_H1, A_H2})
         WNEED(md->a16[a], P * (a == A_X ? NF : WID));
-    WNEED(md->a32[A_XH], T * NF);
-    WNEED(md->a16[A_XH], T * NF);
+    WNEED(md->a32[A_XH], T * NFH);
+    WNEED(md->a16[A_XH], T * NFH);
+    WNEED(md->a32[A_OL], T);
     WNEED(md->a32[A_CTX], B * 2 * WID);
     WNEED(md->a16[A_CTX], B * 2 * WID);
     WNEED(md->a32[A_CB], B * WID);
@@ -488,7 +715,9 @@ int forward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n, c
                        st));
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(P * NF)), dim3(256), 0, st, P * NF, (const float *)x32,
                        md->a16[A_X].p);
-    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(T * NF)), dim3(256), 0, st, T * NF, fth,
+    WCK(hipMemcpyAsync(md->a32[A_XH].p, fth, sizeof(float) * T * NFH, hipMemcpyDeviceToDevice,
+                       st));
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(T * NFH)), dim3(256), 0, st, T * NFH, fth,
                        md->a16[A_XH].p);
     const float *w = md->w.p;
     const bf16 *w16 = md->w16.p;
@@ -515,13 +744,16 @@ int forward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n, c
     // o_j = z2_j . c_b + bo, one product per instance
     WCK(gemm(st, false, B, WID, 2 * WID, md->a16[A_CTX].p, 2 * WID, 1, w16 + p[P_WC].off, WID, 1,
              w + p[P_BC].off, nullptr, 1, md->a32[A_CB].p, md->a16[A_CB].p, WID));
-    WCK(gemm(st, true, T, WID, NF, md->a16[A_XH].p, NF, 1, w16 + p[P_WF].off, WID, 1,
+    WCK(gemm(st, true, T, WID, NFH, md->a16[A_XH].p, NFH, 1, w16 + p[P_WF].off, WID, 1,
              w + p[P_BF].off, nullptr, 1, md->a32[A_Z1].p, md->a16[A_Z1].p, WID));
     WCK(gemm(st, true, T, WID, WID, md->a16[A_Z1].p, WID, 1, w16 + p[P_WG].off, WID, 1,
              w + p[P_BG].off, nullptr, 1, md->a32[A_Z2].p, md->a16[A_Z2].p, WID));
+    // linear path ol_j = ws . f_j (FP32), added to the readout as a per-row bias
+    hipLaunchKernelGGL(k_lin_fwd, dim3(nblk(T)), dim3(256), 0, st, T,
+                       (const float *)md->a32[A_XH].p, w + p[P_WS].off, md->a32[A_OL].p);
     for (int64_t b = 0; b < B; ++b)
         WCK(gemm(st, false, n, 1, WID, md->a16[A_Z2].p + b * n * WID, WID, 1,
-                 md->a16[A_CB].p + b * WID, 1, 1, w + p[P_BO].off, nullptr, 1,
+                 md->a16[A_CB].p + b * WID, 1, 1, w + p[P_BO].off, md->a32[A_OL].p + b * n, 1,
                  md->a32[A_O].p + b * n, nullptr, 1));
     return IBSN_OK;
 }
@@ -555,8 +787,12 @@ int backward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n)
     const bf16 *w16 = md->w16.p;
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(T)), dim3(256), 0, st, T,
                        (const float *)md->d32[A_O].p, md->d16[A_O].p);
-    // readout o_j = z2_j . c_b + bo: dz2_j = dO_j c_b, dc_b = sum_j dO_j z2_j
+    // readout o_j = z2_j . c_b + ws . f_j + bo: dws = sum_j dO_j f_j, dz2_j = dO_j c_b,
+    // dc_b = sum_j dO_j z2_j
     WCK(colsum(st, T, 1, md->d32[A_O].p, g + p[P_BO].off));
+    hipLaunchKernelGGL(k_lin_grad, dim3(NFH), dim3(256), 0, st, T,
+                       (const float *)md->a32[A_XH].p, (const float *)md->d32[A_O].p,
+                       g + p[P_WS].off);
     for (int64_t b = 0; b < B; ++b) {
         WCK(gemm(st, false, n, WID, 1, md->d16[A_O].p + b * n, 1, 1, md->a16[A_CB].p + b * WID, 0,
                  1, nullptr, nullptr, 1, md->d32[A_Z2].p + b * n * WID, nullptr, WID));
@@ -572,7 +808,7 @@ int backward(ibsn_ctx *ctx, ibsn_ws_model *md, int64_t B, int64_t m, int64_t n)
              nullptr, 1, md->d32[A_Z1].p, nullptr, WID));
     relu_bwd(st, md, A_Z1, T * WID);
     // z1 = relu(u Wf + bf)
-    WCK(gemm(st, false, NF, WID, T, md->a16[A_XH].p, 1, NF, md->d16[A_Z1].p, WID, 1, nullptr,
+    WCK(gemm(st, false, NFH, WID, T, md->a16[A_XH].p, 1, NFH, md->d16[A_Z1].p, WID, 1, nullptr,
              nullptr, 1, g + p[P_WF].off, nullptr, WID));
     WCK(colsum(st, T, WID, md->d32[A_Z1].p, g + p[P_BF].off));
     // c = CTX Wc + bc
@@ -645,12 +881,14 @@ int ibsn_ws_create(ibsn_ctx *ctx, uint64_t seed, ibsn_ws_model **out)
         ibsn_ws_free(md);
         return ctx_fail(ctx, IBSN_ERR_OOM, "warm-start parameters: out of memory");
     }
-    // He initialisation of the matrices (normal, std sqrt(2 / inputs)), zero biases
+    // He initialisation of the matrices (normal, std sqrt(2 / inputs)); zero biases, a zero
+    // linear path and a zero context map Wc, so that the output starts at 0 and the first
+    // steps fit the linear path while the context grows from zero
     std::vector<float> h(N, 0.0f);
     std::mt19937_64 rng(seed);
     for (int i = 0; i < NPARAM; ++i) {
         const Param &p = md->prm[i];
-        if (p.rows == 1)
+        if (p.rows == 1 || i == P_WS || i == P_WC)
             continue;
         std::normal_distribution<float> nd(0.0f, sqrtf(2.0f / (float)p.rows));
         for (int64_t k = 0; k < (int64_t)p.rows * p.cols; ++k)
@@ -722,10 +960,29 @@ int ibsn_ws_features(ibsn_ctx *ctx, const ibsn_problem *prob, const double *x, c
     const int64_t m = prob->m, n = prob->n;
     if (m < 1 || n < 1 || !prob->C || !prob->a || !prob->b)
         return ctx_fail(ctx, IBSN_ERR_INVALID_ARG, "ws_features: invalid problem");
+    if (prob->cost_kind == IBSN_COST_POINTS && prob->ldc != 2)
+        return ctx_fail(ctx, IBSN_ERR_INVALID_ARG, "ws_features: 2-D points only");
     WCK(hipSetDevice(ctx_device(ctx)));
     hipStream_t st = ctx_stream(ctx);
-    double *cm = nullptr;
-    WCK(hipMallocAsync((void **)&cm, sizeof(double) * (n + 1), st));
+    // splits of the point list so that the potential kernel has about 2048 workgroups
+    const int64_t tb = (n + 255) / 256, npts = m + n;
+    int64_t splits = (2048 + tb - 1) / tb;
+    splits = splits < 1 ? 1 : (splits > 64 ? 64 : splits);
+    int64_t per = (npts + splits - 1) / splits;
+    per = (per + 255) / 256 * 256;
+    splits = (npts + per - 1) / per;
+    double *buf = nullptr;
+    const int64_t nbuf = PR_N + n + n * NGREEN + splits * n * NGREEN;
+    WCK(hipMallocAsync((void **)&buf, sizeof(double) * nbuf, st));
+    double *par = buf, *cm = buf + PR_N, *g = cm + n, *gpart = g + n * NGREEN;
+    const bool pts = prob->cost_kind == IBSN_COST_POINTS;
+    if (prob->cost_kind == IBSN_COST_F32)
+        hipLaunchKernelGGL(k_box<float>, dim3(1), dim3(1024), 0, st, (int)m, (int)n, x, y,
+                           (const float *)prob->C, prob->ldc, 0.0, par);
+    else
+        hipLaunchKernelGGL(k_box<double>, dim3(1), dim3(1024), 0, st, (int)m, (int)n, x, y,
+                           pts ? nullptr : (const double *)prob->C, prob->ldc, prob->cost_scale,
+                           par);
     if (prob->cost_kind == IBSN_COST_F64)
         hipLaunchKernelGGL(k_colmin<double>, dim3(nblk(n)), dim3(256), 0, st, (int)m, (int)n,
                            (const double *)prob->C, prob->ldc, cm);
@@ -735,15 +992,20 @@ int ibsn_ws_features(ibsn_ctx *ctx, const ibsn_problem *prob, const double *x, c
     else
         hipLaunchKernelGGL(k_colmin_pts, dim3(nblk(n)), dim3(256), 0, st, (int)m, (int)n,
                            (int)prob->ldc, (const double *)prob->C, prob->y, prob->cost_scale, cm);
-    hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, (int)n, (const double *)cm, cm + n);
+    hipLaunchKernelGGL(k_green, dim3((unsigned)tb, (unsigned)splits), dim3(256), 0, st, (int)m,
+                       (int)n, (int)per, x, y, prob->a, prob->b, (const double *)par, gpart);
+    hipLaunchKernelGGL(k_green_sum, dim3(nblk(n)), dim3(256), 0, st, (int)n, (int)splits,
+                       (const double *)gpart, g);
+    hipLaunchKernelGGL(k_feat_means, dim3(1), dim3(1024), 0, st, (int)n, (const double *)cm,
+                       (const double *)g, par);
     hipLaunchKernelGGL(k_features, dim3(nblk(m > n ? m : n)), dim3(256), 0, st, (int)m, (int)n, x,
-                       y, prob->a, prob->b, (const double *)cm, (const double *)(cm + n), fs, fte,
-                       fth);
-    double cmean = 0.0;
-    WCK(hipMemcpyAsync(&cmean, cm + n, sizeof(double), hipMemcpyDeviceToHost, st));
-    WCK(hipFreeAsync(cm, st));
+                       y, prob->a, prob->b, (const double *)cm, (const double *)g,
+                       (const double *)par, fs, fte, fth);
+    double ph[PR_N];
+    WCK(hipMemcpyAsync(ph, par, sizeof(ph), hipMemcpyDeviceToHost, st));
+    WCK(hipFreeAsync(buf, st));
     WCK(hipStreamSynchronize(st));
-    *scale_host = sqrt(cmean);
+    *scale_host = ph[PR_U] * ph[PR_S];
     return IBSN_OK;
 }
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import sys
 from dataclasses import dataclass
 
 import torch
@@ -24,6 +25,8 @@ IBSN_COST_F32 = 1
 IBSN_COST_POINTS = 2
 PREC_F64 = 0    # ibsn_precision
 PREC_MIXED = 1
+CG_AUTO, CG_LAUNCHES, CG_PERSISTENT = 0, 1, 2   # ibsn_set_cg_kernel
+WS_HEAD_FEATURES = 8   # per-target features of the learned warm start's head (fth columns)
 MAX_N_F64 = 10240
 
 
@@ -105,7 +108,7 @@ class _KernelTimes(ct.Structure):
 
 
 _lib = None
-EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus",
+EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus", "ibsn_set_cg_kernel",
            "ibsn_center_init", "ibsn_center_quantum", "ibsn_sinkhorn_step", "ibsn_outer_update", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
@@ -131,6 +134,7 @@ def load():
     L.ibsn_last_error.argtypes = [vp]
     L.ibsn_last_error.restype = ct.c_char_p
     L.ibsn_num_cus.argtypes = [vp]
+    L.ibsn_set_cg_kernel.argtypes = [vp, ct.c_int, ct.c_int]
     L.ibsn_center_init.argtypes = [vp, P, vp, vp]
     L.ibsn_center_quantum.argtypes = [vp, P, C, vp, ct.POINTER(dbl)]
     L.ibsn_subproblem_eval.argtypes = [vp, P, C, vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), vp]
@@ -215,6 +219,11 @@ class Context:
     def num_cus(self):
         return load().ibsn_num_cus(self.h)
 
+    def set_cg_kernel(self, mode: int = 0, blocks: int = 0):
+        """ibsn_set_cg_kernel: CG_AUTO, CG_LAUNCHES or CG_PERSISTENT, and the grid of the
+        one-launch form (0: from the problem size)."""
+        self.check(load().ibsn_set_cg_kernel(self.h, int(mode), int(blocks)))
+
     def kernel_timing(self, enable: bool = True):
         """ibsn_kernel_timing: enable (and clear) or disable HIP-event kernel timing."""
         self.check(load().ibsn_kernel_timing(self.h, 1 if enable else 0))
@@ -231,6 +240,10 @@ class Context:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the memory to
+        # the process's end rather than call into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -413,6 +426,10 @@ class Csr:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the memory to
+        # the process's end rather than call into it
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -511,7 +528,7 @@ class WarmStart:
         dev = prob.a.device
         fs = torch.empty((m, 4), dtype=torch.float32, device=dev)
         fte = torch.empty((n, 4), dtype=torch.float32, device=dev)
-        fth = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        fth = torch.empty((n, WS_HEAD_FEATURES), dtype=torch.float32, device=dev)
         sc = ct.c_double()
         self.ctx.check(load().ibsn_ws_features(
             self.ctx.h, ct.byref(prob.raw()), _ptr(x, 2 * m, name="x"), _ptr(y, 2 * n, name="y"),
@@ -525,7 +542,8 @@ class WarmStart:
         f32 = torch.float32
         self.ctx.check(load().ibsn_ws_forward(
             self.ctx.h, self.h, B, m, n, _ptr(fs, B * m * 4, f32, "fs"),
-            _ptr(fte, B * n * 4, f32, "fte"), _ptr(fth, B * n * 4, f32, "fth"), _ptr(out, dtype=f32)))
+            _ptr(fte, B * n * 4, f32, "fte"), _ptr(fth, B * n * WS_HEAD_FEATURES, f32, "fth"),
+            _ptr(out, dtype=f32)))
         return out
 
     def predict(self, m, n, fs, fte, fth, scale):
@@ -534,7 +552,7 @@ class WarmStart:
         f32 = torch.float32
         self.ctx.check(load().ibsn_ws_predict(
             self.ctx.h, self.h, m, n, _ptr(fs, m * 4, f32, "fs"), _ptr(fte, n * 4, f32, "fte"),
-            _ptr(fth, n * 4, f32, "fth"), float(scale), _ptr(g)))
+            _ptr(fth, n * WS_HEAD_FEATURES, f32, "fth"), float(scale), _ptr(g)))
         return g
 
     def train_step(self, B, m, n, fs, fte, fth, target, lr, want_grad=False):
@@ -545,7 +563,7 @@ class WarmStart:
         f32 = torch.float32
         self.ctx.check(load().ibsn_ws_train_step(
             self.ctx.h, self.h, B, m, n, _ptr(fs, B * m * 4, f32, "fs"),
-            _ptr(fte, B * n * 4, f32, "fte"), _ptr(fth, B * n * 4, f32, "fth"),
+            _ptr(fte, B * n * 4, f32, "fte"), _ptr(fth, B * n * WS_HEAD_FEATURES, f32, "fth"),
             _ptr(target, B * n, f32, "target"), float(lr), ct.byref(loss),
             grad.ctypes.data_as(ct.POINTER(ct.c_float)) if want_grad else None))
         return loss.value, grad
@@ -556,6 +574,10 @@ class WarmStart:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the memory to
+        # the process's end rather than call into it
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:

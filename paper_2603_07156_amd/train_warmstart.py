@@ -1,13 +1,14 @@
 """Train the learned warm start (ibsn_ws_*) on pairs the solver generates.
 
-    python -m paper_2603_07156_amd.train_warmstart --train 256 --out warmstart.npz
+    python -m paper_2603_07156_amd.train_warmstart --train 192 --out warmstart.npz
 
 Instances: uniform points in [0,1]^2 on both sides with uniform weights (the generator of the
 small configuration), m = n = --n (1024), eta = --eta; training seeds 10000.., validation
 seeds 900000...  Target of each instance: the dual gamma of its first proximal subproblem
 (ibsn_solve with one outer iteration from gamma = 0, centred), divided by the instance's
-scale (sqrt(mean_j min_i C_ij)), the unit the network predicts in.  Training: Adam on the
-per-instance centred squared error, batches of --batch instances, cosine learning-rate decay.
+scale (ibsn_ws_features: u s, the cost of the typical nearest-source distance), the unit
+the network predicts in.  Training: Adam on the per-instance centred squared error, batches
+of --batch instances, cosine learning-rate decay.
 Everything runs in the library's kernels (the solver for the targets, the BF16 MFMA network
 for the features, the forward and backward passes); this script only drives them.
 The parameters are written as a NumPy .npz (keys: params, eta, n, train, val_loss, val_r2).
@@ -82,11 +83,11 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--eta", type=float, default=1e-6)
-    ap.add_argument("--train", type=int, default=256)
+    ap.add_argument("--train", type=int, default=192)
     ap.add_argument("--val", type=int, default=16)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--contexts", type=int, default=4)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default=os.path.join(HERE, "warmstart_uniform_eta1e-6.npz"))
@@ -130,6 +131,10 @@ def main() -> int:
     np.savez(args.out, params=ws.params(), eta=args.eta, n=args.n, train=args.train,
              val_loss=vl, val_r2=r2)
     print(f"saved {args.out}: val_loss {vl:.4g} val_r2 {r2:.4f}", flush=True)
+    ws.free()
+    for c in ctxs:
+        c.close()
+    ctx.close()
     return 0
 
 

@@ -28,6 +28,15 @@ def ctx(ib):
     return ib.Context(0)
 
 
+@pytest.fixture(params=["launches", "persistent"])
+def cgctx(request, ib, ctx):
+    """The context with CG run as kernel launches per iteration, or in one cooperative
+    launch (the default where supported); restored to the default afterwards."""
+    ctx.set_cg_kernel(ib.CG_LAUNCHES if request.param == "launches" else ib.CG_PERSISTENT)
+    yield ctx
+    ctx.set_cg_kernel(ib.CG_AUTO)
+
+
 def dev(x, dtype=None):
     t = torch.from_numpy(np.ascontiguousarray(x))
     if dtype is not None:
@@ -279,7 +288,7 @@ def test_hvp_determinism_and_dense_row(ib, ctx):
     gcsr.free()
 
 
-def test_cg(ib, ctx):
+def test_cg(ib, ctx, cgctx):
     inst = W.gmm_points(500, 13, m=380)
     r, s, k, gamma = outer_state(inst, 3)
     ctr, q = center(ib, inst, r, s, k, gamma)
@@ -291,18 +300,18 @@ def test_cg(ib, ctx):
     ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
     shift = max(gn, 1e-2)
     tol = 1e-12 * gn
-    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
+    xg, itg = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
     assert itg < 500 and ito < 500
     np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
     assert abs(host(xg).sum()) <= 1e-10 * np.abs(xo).max()   # Lemma 4.1
     # maxit is respected and 0 iterations returns x = 0
-    x0, it0 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 0)
+    x0, it0 = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 0)
     assert it0 == 0 and float(x0.abs().max()) == 0.0
     gcsr.free()
 
 
-def test_cg_three_kernel_path(ib, ctx):
+def test_cg_three_kernel_path(ib, ctx, cgctx):
     """n > 4096 runs CG as three kernels per iteration (row gather, column gather, update);
     smaller n folds the update into the row gather.  Both against the oracle's CG."""
     m, n = 300, 5000
@@ -317,12 +326,12 @@ def test_cg_three_kernel_path(ib, ctx):
     ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
     shift = max(gn, 1e-2)
     tol = 1e-12 * gn
-    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
+    xg, itg = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
     assert itg < 500 and ito < 500
     np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
     # a cap of a few iterations stops both at the same iterate
-    x3, it3 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 3)
+    x3, it3 = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 3)
     xo3, ito3 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 3)
     assert it3 == ito3 == 3
     np.testing.assert_allclose(host(x3), xo3, rtol=0, atol=1e-9 * np.abs(xo3).max())
@@ -330,15 +339,55 @@ def test_cg_three_kernel_path(ib, ctx):
     # to rounding: with only the column order of this problem permuted, the oracle's own
     # 17th iterate moves by 5e-7 of max|x|.  One iteration more or less moves it by about
     # 4%, so a bound of 1e-5 tells a wrong iteration count from rounding.
-    x17, it17 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 17)
+    x17, it17 = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 17)
     xo17, ito17 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 17)
     assert it17 == ito17 == 17
     np.testing.assert_allclose(host(x17), xo17, rtol=0, atol=1e-5 * np.abs(xo17).max())
     gcsr.free()
 
 
+@pytest.mark.parametrize("blocks", [1, 2, 7, 300])
+def test_cg_persistent_grid_sizes(ib, ctx, blocks):
+    """The one-launch CG with grids that leave every workgroup several rows and columns
+    (1, 2, 7) or none at all (300 > rows / 8), a dense row split into one chunk per
+    workgroup, against the oracle's CG, converged and stopped after 5 iterations."""
+    inst = W.gmm_points(500, 13, m=380)
+    r, s, k, gamma = outer_state(inst, 3)
+    ctr, q = center(ib, inst, r, s, k, gamma)
+    ev = orc.eval_pass(inst.C, inst.a, inst.b, inst.eta, gamma, r=r, s=s, k=k, q=q)
+    gn = np.linalg.norm(ev.g)
+    rho = inst.eta * gn / (380 * 500)
+    pr = problem(ib, inst)
+    gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), rho)
+    ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, rho, s=s, k=k, q=q)
+    assert ocsr.istar >= 0
+    shift = max(gn, 1e-2)
+    tol = 1e-12 * gn
+    ctx.set_cg_kernel(ib.CG_PERSISTENT, blocks)
+    try:
+        xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
+        x5, it5 = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 5)
+    finally:
+        ctx.set_cg_kernel(ib.CG_AUTO)
+    xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
+    assert itg < 500 and ito < 500
+    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    xo5, ito5 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 5)
+    assert it5 == ito5 == 5
+    np.testing.assert_allclose(host(x5), xo5, rtol=0, atol=1e-9 * np.abs(xo5).max())
+    gcsr.free()
+
+
+def test_cg_kernel_mode_arguments(ib, ctx):
+    with pytest.raises(RuntimeError):
+        ctx.set_cg_kernel(3)
+    with pytest.raises(RuntimeError):
+        ctx.set_cg_kernel(ib.CG_PERSISTENT, 1025)
+    ctx.set_cg_kernel(ib.CG_AUTO)
+
+
 @pytest.mark.parametrize("maxit", [1, 2, 5, 9, 13])
-def test_cg_two_kernel_iterates(ib, ctx, maxit):
+def test_cg_two_kernel_iterates(ib, ctx, cgctx, maxit):
     """The folded update (n <= 4096) gives the same iterate as the oracle's CG after each
     number of iterations, across the host's chunk boundaries (chunks of 8 and 4 are queued
     before the first state record is read)."""
@@ -350,7 +399,7 @@ def test_cg_two_kernel_iterates(ib, ctx, maxit):
     gcsr = ib.sparsify(ctx, pr, ctr, dev(gamma), dev(ev.M), dev(ev.S), 1e-6)
     ocsr = orc.sparsify(inst.C, inst.a, inst.eta, gamma, ev.M, ev.S, 1e-6, s=s, k=k, q=q)
     shift = 1e-2
-    xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, maxit)
+    xg, itg = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, maxit)
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, maxit)
     assert itg == ito == maxit
     # Rounding of different summation orders, amplified by CG (cond ~5000 here).  With only
@@ -363,7 +412,7 @@ def test_cg_two_kernel_iterates(ib, ctx, maxit):
 
 
 @pytest.mark.parametrize("n,stop_at", [(600, 8), (600, 12), (5000, 8), (5000, 12)])
-def test_cg_converges_at_chunk_end(ib, ctx, n, stop_at):
+def test_cg_converges_at_chunk_end(ib, ctx, cgctx, n, stop_at):
     """CG that reaches its tolerance exactly where the host polls (after the first chunk of
     8 or the second of 4, with more iterations already queued behind the poll): the
     iterations queued after convergence must leave x alone.  The shift (1.0: condition
@@ -393,7 +442,7 @@ def test_cg_converges_at_chunk_end(ib, ctx, n, stop_at):
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, rhs, tol, 100)
     assert ito == stop_at
     for _ in range(2):   # the second solve starts from a context whose CG just ended
-        xg, itg = ib.cg(ctx, gcsr, pr.a, inst.eta, shift, dev(rhs), tol, 100)
+        xg, itg = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(rhs), tol, 100)
         assert itg == stop_at
         np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
     gcsr.free()
