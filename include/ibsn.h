@@ -81,9 +81,12 @@ int ibsn_num_cus(const ibsn_ctx *ctx);
    cooperative launches.  The two forms run the same recurrences; p.(H_rho + shift I)p is
    taken as the quadratic form (sum d p^2 - sum a (P_rho p)^2)/eta + shift sum p^2 in the
    persistent form and as the dot product of p with the computed product in the other, so
-   iterates agree to rounding.  IBSN_ERR_INVALID_ARG for an unknown mode or blocks outside
-   0..1024, IBSN_ERR_UNSUPPORTED for IBSN_CG_PERSISTENT without cooperative launches; a grid
-   larger than the device can hold resident makes the CG calls fail with IBSN_ERR_HIP. */
+   iterates agree to rounding.  ibsn_solve_batch with more than one context runs CG as
+   launches on every context (a cooperative grid assumes the device to itself) and restores
+   each context's mode afterwards.  IBSN_ERR_INVALID_ARG for an unknown mode or blocks
+   outside 0..1024, IBSN_ERR_UNSUPPORTED for IBSN_CG_PERSISTENT without cooperative
+   launches; a grid larger than the device can hold resident makes the CG calls fail with
+   IBSN_ERR_HIP. */
 enum { IBSN_CG_AUTO = 0, IBSN_CG_LAUNCHES = 1, IBSN_CG_PERSISTENT = 2 };
 int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks);
 

@@ -416,22 +416,37 @@ int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k
     return IBSN_OK;
 }
 
-// stop test + certificate at the state (w, M, S); out (device, 10 doubles)
+// stop test + certificate at the state (w, M, S); out (device, 10 doubles).
+// c_state: the state's column sums c = X^T 1 when the caller holds them (the solver does).
+// X = diag(a) P with P row-stochastic, so X 1 = a and Algorithm 3's first scaling is
+// z = min(a / X1, 1) = 1, F = X: pass 1 (which forms z and the column sums of X and F)
+// is then skipped, z is 1 and both column sums are c_state.  Without c_state pass 1 runs
+// as Algorithm 3 states it.
 int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
-             const double *gamma, const double *M, const double *S, double *xhat)
+             const double *gamma, const double *M, const double *S, double *xhat,
+             const double *c_state = nullptr)
 {
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q);
     double *scal = P<double>(ctx->scal);
-    double *colX = P<double>(ctx->cvec);   // reuse as column sums of X
-    double *colF = P<double>(ctx->colv);
-    {
-        KTimer kt(ctx, IBSN_KT_STOP1);
-        CKH(launch_stop1(rp, d, M, S, P<double>(ctx->zv), P<double>(ctx->colpart),
-                         P<double>(ctx->colpart2), P<double>(ctx->rowpart2), st));
+    const double *colX = P<double>(ctx->cvec);   // column sums of X
+    const double *colF = P<double>(ctx->colv);   // column sums of F = diag(z) X
+    int rowres_parts = rp.grid;                  // partials of sum_i (X1 - a)_i^2
+    if (c_state) {
+        CKH(sk_fill(p->m, 1.0, P<double>(ctx->zv), st));
+        colX = colF = c_state;
+        rowres_parts = 0;   // X1 = a
+    } else {
+        {
+            KTimer kt(ctx, IBSN_KT_STOP1);
+            CKH(launch_stop1(rp, d, M, S, P<double>(ctx->zv), P<double>(ctx->colpart),
+                             P<double>(ctx->colpart2), P<double>(ctx->rowpart2), st));
+        }
+        CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(ctx->cvec),
+                             nullptr, nullptr, st));
+        CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, p->n, P<double>(ctx->colv),
+                             nullptr, nullptr, st));
     }
-    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, colX, nullptr, nullptr, st));
-    CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, p->n, colF, nullptr, nullptr, st));
     CKH(sk_stop_prep(p->n, d.sigma, p->b, d.w, d.wlo, gamma, colX, colF, P<double>(ctx->yv),
                      P<double>(ctx->ecv), P<double>(ctx->psiv), scal, st));
     Stop2Vec v;
@@ -447,8 +462,8 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
         KTimer kt(ctx, IBSN_KT_STOP2);
         CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));
     }
-    CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), P<double>(ctx->rowpart2), rp.grid, scal,
-                      P<double>(ctx->stopout), st));
+    CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), P<double>(ctx->rowpart2), rowres_parts,
+                      scal, P<double>(ctx->stopout), st));
     return IBSN_OK;
 }
 
@@ -757,7 +772,7 @@ void ibsn_destroy(ibsn_ctx *ctx)
                       &ctx->cg_x, &ctx->cg_r, &ctx->cg_r2,
                       &ctx->cg_p,
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_star, &ctx->cg_pap, &ctx->cg_rr,
-                      &ctx->cg_scal, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
+                      &ctx->cg_scal, &ctx->cg_pp, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
                       &ctx->sv_S, &ctx->sv_Mt, &ctx->sv_St, &ctx->sv_ct, &ctx->sv_gt, &ctx->sv_D,
                       &ctx->sv_c, &ctx->sv_gv};
     for (DevBuf *b : bufs)
@@ -1508,7 +1523,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             if (!opt.eot && ctx->host_scal[SC_GN] < mu) {
                 ta = now_s();
                 CKSH(sk_gamma_of(n, eta, w, wlo, s, gamma, st));
-                CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
+                CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr, c));
                 R.passes += 2;
                 ++R.stop_tests;
                 CKSH(hipMemcpyAsync(stop_h, ctx->stopout.p, sizeof(stop_h), hipMemcpyDeviceToHost,
@@ -1528,7 +1543,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         CKSH(sk_gamma_of(n, eta, w, wlo, s, gamma, st));
         if (!stopped || opt.eot) {
             ta = now_s();
-            CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr));
+            CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr, c));
             R.passes += 2;
             ++R.stop_tests;
             CKSH(hipMemcpyAsync(stop_h, ctx->stopout.p, sizeof(stop_h), hipMemcpyDeviceToHost, st));
@@ -1548,7 +1563,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         if (opt.eot) {
             // (E)IBSN: one subproblem and no outer update; the centre stays (0, 0)
             if (plan_out) {
-                CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out));
+                CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out, c));
                 R.passes += 2;
             }
             R.status = R.grad_norm < opt.eot_tol ? IBSN_OK : IBSN_WARN_MAXITER;
@@ -1557,7 +1572,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             break;
         }
         if (plan_out && (done || k + 1 == k0 + opt.max_outer)) {
-            CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out));
+            CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, plan_out, c));
             R.passes += 2;
         }
         // step 13: X^{k+1} = X^{k,v+1}, i.e. r = log a - lse, s = w; k = k+1; gamma kept
@@ -1609,6 +1624,15 @@ int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
         return probs[x].m * probs[x].n > probs[y].m * probs[y].n;
     });
+    // Several contexts solve at once on their own streams: CG runs as kernel launches
+    // there, since a cooperative launch is sized for a device that its grid has to itself
+    // (another stream's kernels may hold the compute units its workgroups wait for).
+    std::vector<int> mode((size_t)nctx);
+    for (int w = 0; w < nctx; ++w) {
+        mode[(size_t)w] = ctxs[w]->cg_mode;
+        if (nctx > 1)
+            ctxs[w]->cg_mode = IBSN_CG_LAUNCHES;
+    }
     std::atomic<int64_t> next{0};
     auto worker = [&](int w) {
         for (;;) {
@@ -1628,6 +1652,8 @@ int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_
     worker(0);
     for (std::thread &t : pool)
         t.join();
+    for (int w = 0; w < nctx; ++w)
+        ctxs[w]->cg_mode = mode[(size_t)w];
     return IBSN_OK;
 }
 

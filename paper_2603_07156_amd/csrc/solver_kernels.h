@@ -50,6 +50,8 @@ hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *
                         const double *wlo, const double *gamma, const double *colX,
                         const double *colF, double *y, double *ec, double *psi, double *scal,
                         hipStream_t st);
+// x[0..n) = v (a kernel: safe under graph capture)
+hipError_t sk_fill(int64_t n, double v, double *x, hipStream_t st);
 // certificate and Delta_kkt from the stop passes' partials; needs scal[SC_AA], scal[SC_BB]
 hipError_t sk_stop_final(int G, const double *part, const double *rowres_part, int G1,
                          double *scal, double *out, hipStream_t st);

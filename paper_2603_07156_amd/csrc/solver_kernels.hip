@@ -294,6 +294,13 @@ __global__ __launch_bounds__(NT) void k_dot_slot(int n, const double *__restrict
         scal[slot] = s;
 }
 
+__global__ void k_fill(int n, double v, double *__restrict__ x)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n)
+        x[j] = v;
+}
+
 // Algorithm 3 vectors after pass 1: y_j = min(b_j / colX_j, 1), e_c = b - y.colF,
 // ||e_r||_1 = sum a - sum_j y_j colF_j (sum of the rows of F), psi_j = (w_j - log b_j)/sigma
 // with w = wh + wl, column residual sum_j (colX_j - b_j)^2, b^T gamma, b^T psi.
@@ -585,6 +592,11 @@ hipError_t sk_stop_prep(int64_t n, double sigma, const double *b, const double *
                         hipStream_t st)
 {
     L1(k_stop_prep, (int)n, sigma, b, w, wlo, gamma, colX, colF, y, ec, psi, scal);
+}
+hipError_t sk_fill(int64_t n, double v, double *x, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, st, (int)n, v, x);
+    return hipGetLastError();
 }
 hipError_t sk_stop_final(int G, const double *part, const double *rowres_part, int G1,
                          double *scal, double *out, hipStream_t st)

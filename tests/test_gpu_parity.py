@@ -725,15 +725,26 @@ def test_full_size_10k_passes(ib, ctx):
 
 def test_solve_batch_matches_sequential(ib, ctx):
     """The batched form (three worker contexts on their own streams) returns, for every
-    problem, bitwise the result of solving it alone: each solve is deterministic and the
-    workers share nothing.  One problem is also checked against the oracle's solve."""
+    problem, bitwise the result of solving it alone with the same CG form (several contexts
+    run CG as launches): each solve is deterministic and the workers share nothing.  One
+    problem is also checked against the oracle's solve."""
     batch = W.grid_histogram_batch(7, 301, lo=64, hi=600)
     probs = [problem(ib, inst) for inst in batch]
     opt = ib.default_options(max_outer=25, gap_tol=0.0, marg_tol=0.0)
     ctxs = [ib.Context(0, stream=torch.cuda.Stream()) for _ in range(3)]
+    for c in ctxs:
+        c.set_cg_kernel(ib.CG_PERSISTENT)   # restored by solve_batch after its launches
     out = ib.solve_batch(ctxs, probs, opt)
-    for inst, pr, o in zip(batch, probs, out):
-        ref = ib.solve(ctx, pr, opt)
+    ctx.set_cg_kernel(ib.CG_LAUNCHES)
+    refs = [ib.solve(ctx, pr, opt) for pr in probs]
+    ctx.set_cg_kernel(ib.CG_AUTO)
+    # one context keeps its own CG form (here one launch per CG solve)
+    one = ib.solve_batch([ctxs[0]], probs[:1], opt)[0]
+    ctx.set_cg_kernel(ib.CG_PERSISTENT)
+    ref1 = ib.solve(ctx, probs[0], opt)
+    ctx.set_cg_kernel(ib.CG_AUTO)
+    assert torch.equal(one["gamma"], ref1["gamma"])
+    for inst, pr, o, ref in zip(batch, probs, out, refs):
         assert o["status"] == ref["status"]
         assert torch.equal(o["gamma"], ref["gamma"]), inst.name
         for key in ("outer", "newton", "cg", "primal", "dual", "rel_gap"):
