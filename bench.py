@@ -212,6 +212,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-1e-8-gap runs")
+    ap.add_argument("--cg", choices=("auto", "launches", "persistent"), default="auto",
+                    help="CG form of the context (ibsn_set_cg_kernel; auto: one cooperative "
+                         "launch per CG solve where supported)")
     ap.add_argument("--batch", type=int, default=32,
                     help="problems of the batched grid-histogram workload (0 = skip)")
     args = ap.parse_args()
@@ -230,6 +233,8 @@ def main() -> int:
     inst = workloads.uniform_points(args.n, args.seed, eta=args.eta)
     m, n = inst.C.shape
     ctx = ibsn.Context(0)
+    ctx.set_cg_kernel({"auto": ibsn.CG_AUTO, "launches": ibsn.CG_LAUNCHES,
+                       "persistent": ibsn.CG_PERSISTENT}[args.cg])
     prob = ibsn.Problem(torch.from_numpy(inst.C).to(dev), torch.from_numpy(inst.a).to(dev),
                         torch.from_numpy(inst.b).to(dev), inst.eta)
     torch.cuda.synchronize()
@@ -278,7 +283,7 @@ def main() -> int:
         "config": {"workload": workload + f"; a step is one IBSN outer iteration "
                                f"(k = {k0}..{k0 + steps - 1}); value is the LSE (eval) pass's "
                                f"HBM throughput over the timed steps",
-                   "m": m, "n": n, "eta": inst.eta},
+                   "m": m, "n": n, "eta": inst.eta, "cg": args.cg},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": probe.read_traffic(TRAFFIC_MD) if args.n == 10000 else None,
