@@ -24,8 +24,12 @@ JSON line:
                  initialisation, and both forms again from the learned warm start (its
                  features and network forward pass inside the timed region) when trained
                  weights are present; counts and the gap reached.
+  paper_workloads  the paper's Table 1 runs at m = n = 10^4 (IBSN to Delta_kkt < 1e-11 or
+                 300 outer iterations) and Table 2 (E)IBSN runs on Square, with the paper's
+                 own figures (other hardware) beside them as context.
   cpu_baseline   the oracle's eval pass on the same instance, on the host's cores, for a
-                 bounded time, in the unit of `value`.
+                 bounded time, in the unit of `value`; and the oracle's time to a certified
+                 1e-8 gap at m = n = 512 (same generator and eta), the GPU's beside it.
 """
 from __future__ import annotations
 
@@ -103,6 +107,37 @@ def cpu_baseline(inst, seconds: float):
                       f"eta={inst.eta:g}, {dt:.1f} s"}
 
 
+def cpu_time_to_gap(ibsn, ctx, n: int = 512, eta: float = ETA, gap: float = 1e-8):
+    """The oracle's plain FP64 solve from X^0 to a certified relative gap on the host's
+    cores, at a size it finishes in seconds (the metric's generator, seed 1000), with the
+    GPU's plain FP64 solve of the same instance beside it."""
+    import torch
+
+    import oracle
+    from paper_2603_07156_amd import workloads
+
+    inst = workloads.uniform_points(n, 1000, eta=eta)
+    t0 = time.perf_counter()
+    o = oracle.solve(inst.C, inst.a, inst.b, eta, options=oracle.default_options(
+        max_outer=20000, gap_tol=gap, marg_tol=0.0))
+    t_cpu = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    pr = ibsn.Problem(torch.from_numpy(inst.C).to(dev), torch.from_numpy(inst.a).to(dev),
+                      torch.from_numpy(inst.b).to(dev), eta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = ibsn.solve(ctx, pr, ibsn.default_options(max_outer=20000, gap_tol=gap, marg_tol=0.0))
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    ro, rg = o["report"], g["report"]
+    return {"workload": f"uniform points m=n={n}, eta={eta:g}, seed 1000, to a certified "
+                        f"relative gap <= {gap:g} from X^0, plain FP64",
+            "oracle_seconds": t_cpu, "oracle_outer": ro["outer"], "oracle_newton": ro["newton"],
+            "oracle_rel_gap": ro["rel_gap"], "oracle_status": o["status"],
+            "gpu_seconds": t_gpu, "gpu_outer": rg["outer"], "gpu_newton": rg["newton"],
+            "gpu_rel_gap": rg["rel_gap"]}
+
+
 def kt_dict(kt):
     return {k: {"total": v[0], "launches": v[1], "avg": (v[0] / v[1]) if v[1] else None}
             for k, v in kt.items() if v[1]}
@@ -172,6 +207,60 @@ def warm_start_fn(ibsn, ctx, prob, inst):
     return fn, (ws, info)
 
 
+# The paper's own figures (Apple M2 Pro, one process, NumPy; Tables 1 and 2), as context for
+# the same workloads run here; different hardware and software, not a target.
+PAPER_TABLE1 = {   # IBSN, eta = 1e-4, Delta_kkt < 1e-11 or 300 outer iterations, m = n = 10^4
+    "uniform": {"newton": 170, "cg_seconds": 16.82, "seconds": 921.60, "abs_gap": 3.63e-9},
+    "square": {"newton": 300, "cg_seconds": 267.15, "seconds": 2205.74, "abs_gap": 1.59e-7},
+}
+PAPER_TABLE2 = {   # (E)IBSN on Square, eta = 1e-4, ||g|| < 1e-9
+    1000: {"mean_cg": 163.6, "newton": 11, "seconds": 0.54},
+    5000: {"mean_cg": 290.4, "newton": 13, "seconds": 23.64},
+    10000: {"mean_cg": 241.2, "newton": 13, "seconds": 88.63},
+}
+
+
+def paper_tables(ibsn, ctx):
+    """The paper's Table 1 runs at m = n = 10^4 (Uniform: C_ij ~ U(0,1); Square:
+    C_ij = (i - j)^2; a, b ~ U(0,1) normalised; seed 0) and its Table 2 (E)IBSN runs on
+    Square, with the paper's figures beside them."""
+    import torch
+
+    from paper_2603_07156_amd import workloads
+    dev = torch.device("cuda", 0)
+
+    def run(inst, opt):
+        pr = ibsn.Problem(torch.from_numpy(inst.C).to(dev), torch.from_numpy(inst.a).to(dev),
+                          torch.from_numpy(inst.b).to(dev), 1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ibsn.solve(ctx, pr, opt)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    out = {"note": "paper figures: Apple M2 Pro, NumPy, one process (context only)",
+           "table1": {}, "table2": {}}
+    for gen in ("uniform", "square"):
+        inst = getattr(workloads, "paper_" + gen)(10000, 0)
+        r, dt = run(inst, ibsn.default_options(max_outer=300, gap_tol=0.0, marg_tol=0.0,
+                                               kkt_tol=1e-11))
+        rep = r["report"]
+        out["table1"][gen] = {"seconds": dt, "outer": rep["outer"], "newton": rep["newton"],
+                              "cg_seconds": rep["t_cg"], "kkt": rep["kkt"],
+                              "rel_gap": rep["rel_gap"],
+                              "abs_gap_bound": rep["primal"] - rep["dual"],
+                              "paper": PAPER_TABLE1[gen]}
+    for n in (1000, 5000, 10000):
+        inst = workloads.paper_square(n, 0)
+        r, dt = run(inst, ibsn.default_options(eot=1, eot_tol=1e-9, max_newton=500))
+        rep = r["report"]
+        out["table2"][str(n)] = {"seconds": dt, "newton": rep["newton"],
+                                 "mean_cg": rep["cg"] / max(rep["newton"], 1),
+                                 "sinkhorn": rep["sinkhorn"], "grad_norm": rep["grad_norm"],
+                                 "status": r["status"], "paper": PAPER_TABLE2[n]}
+    return out
+
+
 def batch_solves(ibsn, count: int, outer: int = 20):
     """The batched workload (grid histograms, sizes m, n in [64, 2048], seed 300, eta 1e-2):
     `outer` outer iterations per problem, with one context and with four contexts on their
@@ -215,6 +304,8 @@ def main() -> int:
     ap.add_argument("--cg", choices=("auto", "launches", "persistent"), default="auto",
                     help="CG form of the context (ibsn_set_cg_kernel; auto: one cooperative "
                          "launch per CG solve where supported)")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the runs of the paper's Table 1 and Table 2 workloads")
     ap.add_argument("--batch", type=int, default=32,
                     help="problems of the batched grid-histogram workload (0 = skip)")
     args = ap.parse_args()
@@ -320,10 +411,13 @@ def main() -> int:
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "kernel": "row-LSE eval pass, mixed-precision form (k_eval<..., MX>)",
                 "bytes_per_launch": pb, "avg_launch_ms": mk["avg"], "launches": mk["launches"]}
+    if not args.no_paper:
+        out["paper_workloads"] = paper_tables(ibsn, ctx)
     if args.batch > 0:
         out["batch"] = batch_solves(ibsn, args.batch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        out["cpu_baseline"]["time_to_1e-8_gap"] = cpu_time_to_gap(ibsn, ctx)
     print(json.dumps(out))
     return 0
 

@@ -16,6 +16,11 @@
 // p <- p, x += alpha p, r -= alpha y, and the partial sums of r.r.  The next phase A starts
 // from beta = r.r / r.r_old.
 //
+// The sparse structure does not change during a solve: each workgroup copies the entries of
+// its rows and columns into LDS once (when they fit in 64 KB; otherwise it reads them from
+// memory each iteration), so an iteration's loads are only the vector gathers.  At
+// m = n = 10^4 this took an iteration from 16.8 to 15.6 us.
+//
 // Grid sums are per-workgroup partials added by every workgroup in index order (the same
 // value everywhere, so every workgroup takes the same decisions and leaves the loop
 // together).  The barrier is an arrival counter (zeroed before the launch, never reset):
@@ -35,6 +40,10 @@ namespace ibsn {
 namespace {
 
 constexpr int PT = 256;                  // threads per workgroup
+// Sparse structure held in LDS for the whole solve: a workgroup's row slots and column slots
+// (at most CACHE_SLOTS of each) with their entries, when they fit in CACHE_BYTES.
+constexpr int CACHE_SLOTS = 8 * PT;
+constexpr size_t CACHE_BYTES = 64 * 1024;
 constexpr int64_t BAR_SPIN = 1ll << 22;  // polls (each after s_sleep) before giving up
 
 struct PersistArgs {
@@ -92,6 +101,39 @@ __device__ __forceinline__ void block_sum4(double &v0, double &v1, double &v2, d
     }
 }
 
+// In-place exclusive prefix sum of a[0..cnt) in LDS (cnt <= 8 PT), total into a[cnt];
+// every thread takes 8 consecutive values.  wt: PT/64 ints of LDS.
+__device__ __forceinline__ void block_exscan(int *a, int cnt, int *wt)
+{
+    const int t = threadIdx.x, base = 8 * t;
+    int loc[8], s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        loc[k] = s;
+        s += base + k < cnt ? a[base + k] : 0;
+    }
+    int incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if ((t & 63) >= o)
+            incl += y;
+    }
+    if ((t & 63) == 63)
+        wt[t / 64] = incl;
+    __syncthreads();
+    int excl = incl - s;
+    for (int w = 0; w < t / 64; ++w)
+        excl += wt[w];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (base + k < cnt)
+            a[base + k] = excl + loc[k];
+    if (t == PT - 1)
+        a[cnt] = excl + s;
+    __syncthreads();
+}
+
 // Grid-wide barrier number `target / grid`; false (every thread) when it timed out or
 // another workgroup raised the error flag.  A workgroup barrier alone does not wait for
 // the other waves' stores, hence the wait in every wave first.
@@ -134,8 +176,65 @@ __global__ __launch_bounds__(PT) void k_cg_persist(PersistArgs A)
     const int istar = *A.istar_p;
     const VT *prow = istar >= 0 ? val + (int64_t)istar * n : nullptr;
     constexpr int GPB = PT / L;   // rows (columns) per workgroup per sweep
-    const int l = t % L;
+    const int l = t % L, q = t / L;
     unsigned target = 0;
+
+    // The workgroup's rows g = b GPB + q + k G GPB (slot k GPB + q) and columns likewise
+    // keep their entries in LDS for the whole solve when they fit: the iterations then
+    // gather only the vectors from memory.
+    extern __shared__ __align__(16) unsigned char dyn[];
+    __shared__ int wt[PT / 64];
+    const int KR = (m + G * GPB - 1) / (G * GPB), KC = (n + G * GPB - 1) / (G * GPB);
+    const int RS = KR * GPB, CS = KC * GPB;
+    int *roff = reinterpret_cast<int *>(dyn), *coff = roff + RS + 1;
+    const VT *rval = nullptr, *cvl = nullptr;
+    const int32_t *rcol = nullptr, *crow = nullptr;
+    bool cached = false;
+    if (RS <= CACHE_SLOTS && CS <= CACHE_SLOTS) {
+        for (int r = t; r < RS; r += PT) {
+            const int g = b * GPB + (r % GPB) + (r / GPB) * G * GPB;
+            roff[r] = (g < m && g != istar) ? A.len[g] : 0;
+        }
+        for (int r = t; r < CS; r += PT) {
+            const int j = b * GPB + (r % GPB) + (r / GPB) * G * GPB;
+            coff[r] = j < n ? (int)(A.colptr[j + 1] - A.colptr[j]) : 0;
+        }
+        __syncthreads();
+        block_exscan(roff, RS, wt);
+        block_exscan(coff, CS, wt);
+        const int TR = roff[RS], TC = coff[CS];
+        const size_t hdr = ((size_t)(RS + CS + 2) * 4 + 15) / 16 * 16;
+        const size_t vbytes = ((size_t)(TR + TC) * sizeof(VT) + 15) / 16 * 16;
+        cached = hdr + vbytes + (size_t)(TR + TC) * 4 <= CACHE_BYTES;
+        if (cached) {
+            VT *rv = reinterpret_cast<VT *>(dyn + hdr);
+            VT *cv = rv + TR;
+            int32_t *rc = reinterpret_cast<int32_t *>(dyn + hdr + vbytes);
+            int32_t *cc = rc + TR;
+            for (int k = 0; k < KR; ++k) {
+                const int r = k * GPB + q, g = b * GPB + q + k * G * GPB;
+                const int o = roff[r], len = roff[r + 1] - o;
+                for (int e = l; e < len; e += L) {
+                    rc[o + e] = A.col[(int64_t)g * n + e];
+                    rv[o + e] = val[(int64_t)g * n + e];
+                }
+            }
+            for (int k = 0; k < KC; ++k) {
+                const int r = k * GPB + q, j = b * GPB + q + k * G * GPB;
+                const int o = coff[r], len = coff[r + 1] - o;
+                const int64_t e0 = len > 0 ? A.colptr[j] : 0;
+                for (int e = l; e < len; e += L) {
+                    cc[o + e] = A.rowidx[e0 + e];
+                    cv[o + e] = cval[e0 + e];
+                }
+            }
+            rval = rv;
+            cvl = cv;
+            rcol = rc;
+            crow = cc;
+        }
+        __syncthreads();
+    }
 
     // x = 0, r = rhs, p = 0 (the first iteration forms p = r + 0 p); partials of r.r
     {
@@ -182,16 +281,25 @@ __global__ __launch_bounds__(PT) void k_cg_persist(PersistArgs A)
             for (int j = j0 + t; j < j1; j += PT)
                 cs = fma((double)prow[j], fma(beta, A.p[j], A.r[j]), cs);
         }
-        for (int g = b * GPB + t / L; g < m; g += G * GPB) {
-            if (g == istar)
+        for (int k = 0; k < KR; ++k) {
+            const int g = b * GPB + q + k * G * GPB;
+            if (g >= m || g == istar)
                 continue;   // the whole lane group skips together
-            const int len = A.len[g];
-            const int32_t *cr = A.col + (int64_t)g * n;
-            const VT *vr = val + (int64_t)g * n;
             double s = 0.0;
-            for (int e = l; e < len; e += L) {
-                const int j = cr[e];
-                s = fma((double)vr[e], fma(beta, A.p[j], A.r[j]), s);
+            if (cached) {
+                const int r = k * GPB + q;
+                for (int e = roff[r] + l; e < roff[r + 1]; e += L) {
+                    const int j = rcol[e];
+                    s = fma((double)rval[e], fma(beta, A.p[j], A.r[j]), s);
+                }
+            } else {
+                const int len = A.len[g];
+                const int32_t *cr = A.col + (int64_t)g * n;
+                const VT *vr = val + (int64_t)g * n;
+                for (int e = l; e < len; e += L) {
+                    const int j = cr[e];
+                    s = fma((double)vr[e], fma(beta, A.p[j], A.r[j]), s);
+                }
             }
 #pragma unroll
             for (int o = L / 2; o > 0; o >>= 1)
@@ -230,11 +338,20 @@ __global__ __launch_bounds__(PT) void k_cg_persist(PersistArgs A)
         }
         const double alpha = rr / pap;
         double rs = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-        for (int j = b * GPB + t / L; j < n; j += G * GPB) {
-            const int64_t e0 = A.colptr[j], e1 = A.colptr[j + 1];
+        for (int k = 0; k < KC; ++k) {
+            const int j = b * GPB + q + k * G * GPB;
+            if (j >= n)
+                continue;
             double s = 0.0;
-            for (int64_t e = e0 + l; e < e1; e += L)
-                s = fma((double)cval[e], A.au[A.rowidx[e]], s);
+            if (cached) {
+                const int r = k * GPB + q;
+                for (int e = coff[r] + l; e < coff[r + 1]; e += L)
+                    s = fma((double)cvl[e], A.au[crow[e]], s);
+            } else {
+                const int64_t e0 = A.colptr[j], e1 = A.colptr[j + 1];
+                for (int64_t e = e0 + l; e < e1; e += L)
+                    s = fma((double)cval[e], A.au[A.rowidx[e]], s);
+            }
 #pragma unroll
             for (int o = L / 2; o > 0; o >>= 1)
                 s += __shfl_xor(s, o, L);
@@ -277,7 +394,7 @@ hipError_t launch_l(int grid, PersistArgs &A, hipStream_t st)
 {
     void *args[] = {&A};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_persist<L, VT>),
-                                      dim3((unsigned)grid), dim3(PT), args, 0, st);
+                                      dim3((unsigned)grid), dim3(PT), args, CACHE_BYTES, st);
 }
 
 }  // namespace

@@ -239,10 +239,11 @@ class Context:
             self._lib.ibsn_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be gone: leave the memory to
-        # the process's end rather than call into it
-        if sys.is_finalizing():
+        # the process's end rather than call into it (the module's globals may be gone too,
+        # hence the bound default)
+        if _finalizing():
             return
         try:
             self.close()
@@ -425,10 +426,11 @@ class Csr:
             self.ctx._lib.ibsn_csr_free(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be gone: leave the memory to
-        # the process's end rather than call into it
-        if sys.is_finalizing():
+        # the process's end rather than call into it (the module's globals may be gone too,
+        # hence the bound default)
+        if _finalizing():
             return
         try:
             self.free()
@@ -573,10 +575,11 @@ class WarmStart:
             self._lib.ibsn_ws_free(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be gone: leave the memory to
-        # the process's end rather than call into it
-        if sys.is_finalizing():
+        # the process's end rather than call into it (the module's globals may be gone too,
+        # hence the bound default)
+        if _finalizing():
             return
         try:
             self.free()
