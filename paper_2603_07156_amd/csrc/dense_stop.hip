@@ -114,19 +114,19 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
         [&](int i, int slot, const auto *cst) {
         const double Mi = rM[slot], ai = rA[slot], aS = ai / rS[slot];
         double red[3] = {0.0, INFINITY, INFINITY};
-        // column loads kept in the row loop and one entry ahead, as in pass 2b
+        // column loads kept in the row loop and one entry ahead, as in pass 2b; y only
+        // where X_ij > 0 (a few entries per row once the plan is sparse)
         const double *yv = y, *gv = gamma, *pv = psi;
         asm volatile("" : "+s"(yv), "+s"(gv), "+s"(pv));
         int jn = slot_col<QF, NT, VEC>(0, n);
-        double ny = yv[jn], ng = gv[jn], np = pv[jn];
+        double ng = gv[jn], np = pv[jn];
 #pragma unroll 2
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
             const int j = jn;
-            const double yj = ny, gj = ng, pj = np;
+            const double gj = ng, pj = np;
             if (e + 1 < E) {
                 jn = slot_col<QF, NT, VEC>(e + 1, n);
-                ny = yv[jn];
                 ng = gv[jn];
                 np = pv[jn];
             }
@@ -134,7 +134,8 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
             const double Xv =
                 exp_tab_z(valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY,
                         etab) * aS;
-            red[0] = fma(Xv, yj, red[0]);
+            if (Xv > 0.0)
+                red[0] = fma(Xv, yv[j], red[0]);
             red[1] = fmin(red[1], valid ? c - gj : INFINITY);
             red[2] = fmin(red[2], valid ? c - pj : INFINITY);
         }
@@ -156,6 +157,11 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
 // Pass 2b, streaming: Xhat = z X y + e_r e_c^T / ||e_r||_1, D_phi(Xhat, X) in the log
 // domain (log X_ij = log a_i - log S_i + (theta_ij - M_i)), <C,Xhat>, <C,X>, min Xhat,
 // <X, U> with U_ij = C_ij - gamma_j - zg_i, and ||X||_F^2, ||C||_F^2 for Delta_kkt.
+// Where X_ij = 0 (all but a few entries of a row once the plan is sparse) Xhat_ij is the
+// rank-one term es_i e_c,j, and its D_phi term es_i e_c,j (log es_i + log e_c,j - log X_ij - 1)
+// is summed per row from three sums: of e_c,j and of e_c,j log e_c,j over the thread's
+// columns (fixed for the kernel, less the row's entries with X_ij > 0) and of e_c,j x_ij.
+// No logarithm is then taken per entry, and y and gamma are read only where X_ij > 0.
 template <int NT, int Q, int QF, int VEC, typename CT>
 __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
@@ -194,6 +200,16 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
            t_cf = 0.0;
     const double er1 = *er1p;   // written by the stop preparation kernel before this one
     const double inv_er1 = er1 > 0.0 ? 1.0 / er1 : 0.0;
+    // over this thread's columns (the same in every row): sum e_c,j and sum e_c,j log e_c,j
+    double t_sec = 0.0, t_slec = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (slot_valid<QF, NT, VEC>(e, n)) {
+            const double v = ec[col_of<NT, VEC>(e)];
+            t_sec += v;
+            t_slec += v > 0.0 ? v * log_tab(v, ltab) : 0.0;
+        }
+    }
     row_loop<NT, Q, QF, VEC, false, RC>(
         C, ldc, py, pscale, n, i0, i1,
         [&](int i) {
@@ -205,43 +221,59 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
         const double es = rE[slot] * inv_er1;   // rank-one factor e_r,i / ||e_r||_1
         const double zg = rG[slot];
         const double lr = log_tab(ai, ltab) - log_tab(rS[slot], ltab);   // per row, all threads
-        // A thread's columns are the same in every row, so the compiler would hoist all
-        // of their y, e_c, gamma loads out of the row loop and spill them at this register
-        // budget.  The pointers are made opaque per row to keep the loads in the loop, and
-        // the values of entry e + 1 are loaded while entry e is computed.
+        // A thread's columns are the same in every row, so the compiler would hoist their
+        // loads out of the row loop and spill them at this register budget.  The pointers
+        // are made opaque per row to keep the loads in the loop; e_c of entry e + 1 is loaded
+        // while entry e is computed, y and gamma only where X_ij > 0.
         const double *yv = y, *ecv = ec, *gv = gamma;
         asm volatile("" : "+s"(yv), "+s"(ecv), "+s"(gv));
         int jn = slot_col<QF, NT, VEC>(0, n);
-        double ny = yv[jn], nec = ecv[jn], ng = gv[jn];
+        double nec = ecv[jn];
+        // this row: sum of e_c,j x_ij where X_ij = 0; e_c and e_c log e_c where X_ij > 0
+        double u_ecxa = 0.0, x_ec = 0.0, x_lec = 0.0;
 #pragma unroll 2
         for (int e = 0; e < E; ++e) {
             const bool valid = slot_valid<QF, NT, VEC>(e, n);
             const int j = jn;
-            const double yj = ny, ecj = nec, gj = ng;
+            const double ecj = nec;
             if (e + 1 < E) {
                 jn = slot_col<QF, NT, VEC>(e + 1, n);
-                ny = yv[jn];
                 nec = ecv[jn];
-                ng = gv[jn];
             }
             const double c = valid ? (double)cst[e] : 0.0;
             const double xa = valid ? add_lo<LO>(fma(-sigma, c, wl[j] - Mi), wl, n, j) : -INFINITY;
             const double Xv = exp_tab_z(xa, etab) * aS;
-            const double f = (zi * Xv) * yj;
-            const double xh = valid ? fma(es, ecj, f) : 0.0;
-            const double lx = lr + xa;
-            const bool pos = xh > 0.0;
-            const double lxh = log_tab(pos ? xh : 1.0, ltab);
-            t_dphi += pos ? (xh * (lxh - lx) - xh) + Xv : Xv;
-            t_cxh = fma(c, xh, t_cxh);
-            t_cx = fma(c, Xv, t_cx);
-            t_xhmin = fmin(t_xhmin, valid ? xh : INFINITY);
-            t_xu = fma(Xv, (c - gj) - zg, t_xu);
-            t_xf = fma(Xv, Xv, t_xf);
             t_cf = fma(c, c, t_cf);
-            if (xhat && valid)
-                xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xh;
+            if (Xv > 0.0) {
+                // X_ij > 0 (valid): the full term
+                const double f = (zi * Xv) * yv[j];
+                const double xh = fma(es, ecj, f);   // >= f > 0
+                const double lx = lr + xa;
+                const double lxh = log_tab(xh, ltab);
+                t_dphi += (xh * (lxh - lx) - xh) + Xv;
+                t_cxh = fma(c, xh, t_cxh);
+                t_cx = fma(c, Xv, t_cx);
+                t_xhmin = fmin(t_xhmin, xh);
+                t_xu = fma(Xv, (c - gv[j]) - zg, t_xu);
+                t_xf = fma(Xv, Xv, t_xf);
+                x_ec += ecj;
+                x_lec += ecj > 0.0 ? ecj * log_tab(ecj, ltab) : 0.0;
+                if (xhat)
+                    xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xh;
+            } else if (valid) {
+                // X_ij = 0: Xhat_ij = es e_c,j, whose term es e_c,j (log es + log e_c,j - lr -
+                // x_ij - 1) is added once per row below
+                const double xr = es * ecj;
+                u_ecxa = fma(ecj, xa, u_ecxa);
+                t_cxh = fma(c, xr, t_cxh);
+                t_xhmin = fmin(t_xhmin, xr);
+                if (xhat)
+                    xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xr;
+            }
         }
+        if (es > 0.0)
+            t_dphi += es * ((log_tab(es, ltab) - lr - 1.0) * (t_sec - x_ec) + (t_slec - x_lec) -
+                            u_ecxa);
         });
     double fin[7] = {t_dphi, t_cxh, t_cx, t_xu, t_xhmin, t_xf, t_cf};
     RedEnd::run_once(fin, lds);
