@@ -304,6 +304,9 @@ def main() -> int:
     ap.add_argument("--cg", choices=("auto", "launches", "persistent"), default="auto",
                     help="CG form of the context (ibsn_set_cg_kernel; auto: one cooperative "
                          "launch per CG solve where supported)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the dense-pass tiles with ibsn_autotune on the metric instance "
+                         "before the timed runs (the choice is reported)")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the runs of the paper's Table 1 and Table 2 workloads")
     ap.add_argument("--batch", type=int, default=32,
@@ -328,6 +331,10 @@ def main() -> int:
                        "persistent": ibsn.CG_PERSISTENT}[args.cg])
     prob = ibsn.Problem(torch.from_numpy(inst.C).to(dev), torch.from_numpy(inst.a).to(dev),
                         torch.from_numpy(inst.b).to(dev), inst.eta)
+    tuned = None
+    if args.autotune:
+        tuned = ctx.autotune(prob)
+        ctx.autotune(ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=ibsn.PREC_MIXED))
     torch.cuda.synchronize()
     workload = (f"uniform points in [0,1]^2, m=n={n}, squared-Euclidean cost / max (FP64), "
                 f"uniform weights, eta={inst.eta:g}, seed {args.seed}")
@@ -374,7 +381,7 @@ def main() -> int:
         "config": {"workload": workload + f"; a step is one IBSN outer iteration "
                                f"(k = {k0}..{k0 + steps - 1}); value is the LSE (eval) pass's "
                                f"HBM throughput over the timed steps",
-                   "m": m, "n": n, "eta": inst.eta, "cg": args.cg},
+                   "m": m, "n": n, "eta": inst.eta, "cg": args.cg, "tiles": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": probe.read_traffic(TRAFFIC_MD) if args.n == 10000 else None,

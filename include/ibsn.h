@@ -127,6 +127,26 @@ typedef struct {
     double cost_scale;
 } ibsn_problem;
 
+/* Tiles of the dense passes: the light tile (eval, stop test: nt threads, q vector slots
+   per thread, the first qf of them inside the row), the heavy tile (trial, sparsify) and
+   the grid shared by all passes. */
+typedef struct {
+    int32_t nt, q, qf, nt_h, q_h, qf_h, grid, reserved;
+    double light_ms, heavy_ms;                 /* chosen tiles: eval + stop, trial + sparsify */
+    double default_light_ms, default_heavy_ms; /* the built-in table's tiles, same timings */
+} ibsn_tile;
+/* Autotuner of the dense-pass tiles (NEXT-3).  Times every compiled tile that can hold a
+   row of prob's n entries, on prob itself (the first subproblem's state at gamma = 0):
+   light tiles on one eval and one stop test, heavy tiles on one trial pass and one
+   sparsify pass, each the mean of three calls after one untimed, for grids of 1, 2 and 4
+   workgroups per compute unit.  Records the fastest combination for problems of the same
+   shape (m, n, cost kind, precision) on this context: later calls on the context with such
+   a problem (ibsn_solve, the pass entry points) use it; results then differ from the
+   default tiles' only by the order of summation.  out (host, optional): the choice and the
+   timings.  prob = NULL clears the context's records.  Synchronises; allocates the
+   solver's workspace for prob. */
+int ibsn_autotune(ibsn_ctx *ctx, const ibsn_problem *prob, ibsn_tile *out);
+
 /* Implicit prox centre X^k (see above): device r (m), s (n), and the grid spacing
    `quantum` (a power of two, at least DBL_MIN) of the potentials.  Every pass forms
    w_j = s_j + gamma_j/eta as two parts, wh_j = grid(s_j + gamma_j/eta) with

@@ -330,7 +330,9 @@ __global__ __launch_bounds__(NW *WAVE) void k_colreduce(const double *__restrict
 // static LDS, with 8- and 32-row chunks of row scalars, is sized for the light tile); the
 // heavy tile of the same row serves trial and sparsify, which keep more values live per
 // entry; both run on the same grid.  1024-thread tiles keep 10 entries per thread at
-// n <= 10240 (FP64), which leaves room for four waves per SIMD.
+// n <= 10240 (FP64), which leaves room for four waves per SIMD.  This table is the default;
+// ibsn_autotune times the other compiled tiles that hold the row (tile_candidates) and
+// grids of 1, 2 and 4 workgroups per CU on a problem, and records its choice per shape.
 struct TileRow {
     int cap;                  // largest n served
     int nt, q, qf;            // light tile
@@ -370,6 +372,26 @@ bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *p)
         }
     }
     return false;
+}
+
+int tile_candidates(int64_t n, int cost_kind, bool heavy, int (*out)[3], int cap)
+{
+    const int vec = cost_kind == 1 ? 4 : 2;
+    int cnt = 0;
+#define X(NT_, Q_, QF_)                                                                    \
+    if (cnt < cap && (int64_t)NT_ * Q_ * vec >= n && (int64_t)NT_ * QF_ * vec <= n) {      \
+        out[cnt][0] = NT_;                                                                 \
+        out[cnt][1] = Q_;                                                                  \
+        out[cnt][2] = QF_;                                                                 \
+        ++cnt;                                                                             \
+    }
+    if (heavy) {
+        IBSN_HEAVY_TILES(X)
+    } else {
+        IBSN_LIGHT_TILES(X)
+    }
+#undef X
+    return cnt;
 }
 
 RowPlan heavy_plan(const RowPlan &p)

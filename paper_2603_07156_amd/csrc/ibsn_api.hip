@@ -65,6 +65,12 @@ struct ibsn_ctx {
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     DevBuf cg_pp;                  // partial sums and barrier state of the one-launch CG
     int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT
+    struct Tuned {                 // plans chosen by ibsn_autotune, per problem shape
+        int64_t m, n;
+        int kind, mixed;
+        RowPlan rp;
+    };
+    std::vector<Tuned> tuned;
     int cg_blocks = 0;             // grid of the one-launch CG (0: from the problem size)
     bool coop = false;             // the device supports cooperative launches
     double *host_scal = nullptr;   // pinned, SC_NSLOT + 16
@@ -236,6 +242,12 @@ int plan_for(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *rp)
 {
     if (!plan_rows(p->m, p->n, p->cost_kind, ctx->num_cus, rp))
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "no row tile for n=%lld", (long long)p->n);
+    const int mixed = p->precision == IBSN_PREC_MIXED ? 1 : 0;
+    for (const auto &t : ctx->tuned)
+        if (t.m == p->m && t.n == p->n && t.kind == p->cost_kind && t.mixed == mixed) {
+            *rp = t.rp;
+            break;
+        }
     return IBSN_OK;
 }
 
@@ -678,6 +690,160 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     return IBSN_OK;
 }
 
+// Tile search for the dense passes (see ibsn_autotune): the first subproblem's state at
+// gamma = 0, every compiled light tile that holds the row timed on eval + stop test and
+// every heavy tile on trial + sparsify kernel, for grids of 1, 2 and 4 workgroups per CU;
+// the fastest light and heavy tile per grid, then the fastest grid.  A candidate whose
+// launch the runtime refuses (its LDS does not fit) is skipped.
+int tune_plan(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *best, double ms[4])
+{
+    hipStream_t st = ctx->stream;
+    const int64_t m = p->m, n = p->n;
+    const int mixed = p->precision == IBSN_PREC_MIXED ? 1 : 0;
+    RowPlan base;
+    if (!plan_rows(m, n, p->cost_kind, ctx->num_cus, &base))
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "no row tile for n=%lld", (long long)n);
+    int lt[16][3], ht[16][3];
+    const int nl = tile_candidates(n, p->cost_kind, false, lt, 16);
+    const int nh = tile_candidates(n, p->cost_kind, true, ht, 16);
+    int grids[3], ng = 0;
+    for (int per : {1, 2, 4}) {
+        const int g = (int)std::min<int64_t>((int64_t)ctx->num_cus * per, m);
+        if (ng == 0 || grids[ng - 1] != g)
+            grids[ng++] = g;
+    }
+    RowPlan big = base;
+    big.grid = std::max(base.grid, grids[ng - 1]);
+    CKI(ensure_ws(ctx, p, big));
+    for (DevBuf *b : {&ctx->sv_r, &ctx->sv_M, &ctx->sv_S, &ctx->sv_Mt, &ctx->sv_St})
+        CKI(ensure(ctx, *b, m * 8));
+    for (DevBuf *b : {&ctx->sv_s, &ctx->sv_g, &ctx->sv_c, &ctx->sv_gv, &ctx->sv_ct, &ctx->sv_gt,
+                      &ctx->sv_D})
+        CKI(ensure(ctx, *b, n * 8));
+    double *r = P<double>(ctx->sv_r), *s = P<double>(ctx->sv_s), *gamma = P<double>(ctx->sv_g);
+    double *M = P<double>(ctx->sv_M), *S = P<double>(ctx->sv_S), *Mt = P<double>(ctx->sv_Mt);
+    double *St = P<double>(ctx->sv_St), *c = P<double>(ctx->sv_c), *g = P<double>(ctx->sv_gv);
+    double *ct = P<double>(ctx->sv_ct), *gt = P<double>(ctx->sv_gt), *D = P<double>(ctx->sv_D);
+    double *scal = P<double>(ctx->scal);
+    if (!ctx->solver_csr) {
+        ctx->solver_csr = new ibsn_csr();
+        ctx->solver_csr->ctx = ctx;
+    }
+    ibsn_csr *csr = ctx->solver_csr;
+    CKI(csr_alloc(ctx, csr, m, n));
+    CKH(sk_problem_scalars(m, n, p->a, p->b, scal, P<int>(csr->istar_dev), st));
+    CKH(sk_dot_slot(m, p->a, p->a, SC_AA, scal, st));
+    CKH(sk_dot_slot(n, p->b, p->b, SC_BB, scal, st));
+    CKH(sk_init_center(m, n, p->a, p->b, r, s, st));
+    CKH(sk_fill(n, 0.0, gamma, st));
+    CKH(sk_fill(n, 0.0, D, st));
+    CKH(sk_cost_max(m, n, p->ldc, p->cost_kind, p->C, p->y, p->cost_scale,
+                    P<double>(ctx->rowpart2), big.grid, scal, st));
+    CKH(sk_wmax(n, s, gamma, p->eta, scal, st));
+    CKI(read_scal(ctx));
+    const double q = quantum_of(ctx->host_scal[SC_WMAX] + ctx->host_scal[SC_CMAX] / p->eta);
+    CKH(launch_make_w(s, gamma, q, p->eta, n, lo_split(p), P<double>(ctx->w),
+                      P<double>(ctx->wlo), st));
+    const DenseArgs d = dense_args(ctx, p, 0, q, mixed);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CKH(hipEventCreate(&e0));
+    CKH(hipEventCreate(&e1));
+    // ms per call of fn (three calls after one untimed), or infinity if a launch fails
+    auto timed = [&](auto &&fn) -> double {
+        if (fn() != IBSN_OK || hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            return INFINITY;
+        }
+        (void)hipEventRecord(e0, st);
+        for (int k = 0; k < 3; ++k)
+            if (fn() != IBSN_OK) {
+                (void)hipStreamSynchronize(st);
+                (void)hipGetLastError();
+                return INFINITY;
+            }
+        (void)hipEventRecord(e1, st);
+        float t = 0.0f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            return INFINITY;
+        return (double)t / 3.0;
+    };
+    auto light_ms = [&](const RowPlan &rp) -> double {
+        const double te = timed([&]() {
+            return run_eval(ctx, p, rp, 0, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr,
+                            mixed);
+        });
+        // the stop test (both passes, light tile) at the state the eval left
+        const double ts = std::isfinite(te) ? timed([&]() {
+            return run_stop(ctx, p, rp, 0, q, gamma, M, S, nullptr);
+        }) : INFINITY;
+        return te + ts;
+    };
+    auto heavy_ms = [&](const RowPlan &rp) -> double {
+        if (run_eval(ctx, p, base, 0, q, nullptr, nullptr, M, S, nullptr, c, g, nullptr, mixed) !=
+            IBSN_OK)
+            return INFINITY;
+        const double tt = timed([&]() {
+            return run_trial(ctx, p, rp, 0, q, M, D, 1.0, Mt, St, ct, gt, mixed);
+        });
+        const double tsp = std::isfinite(tt) ? timed([&]() -> int {
+            CKH(launch_sparsify(rp, d, M, S, 1e-3, P<int>(csr->istar_dev), P<int32_t>(csr->col),
+                                csr->val.p, P<int32_t>(csr->len), P<double>(ctx->colpart), st));
+            return IBSN_OK;
+        }) : INFINITY;
+        return tt + tsp;
+    };
+    double best_t = INFINITY;
+    *best = base;
+    ms[0] = light_ms(base);
+    ms[1] = heavy_ms(base);
+    ms[2] = ms[0];
+    ms[3] = ms[1];
+    for (int gi = 0; gi < ng; ++gi) {
+        RowPlan rp = base;
+        rp.grid = grids[gi];
+        double bl = INFINITY, bh = INFINITY;
+        RowPlan cand = rp;
+        for (int k = 0; k < nl; ++k) {
+            RowPlan t = rp;
+            t.nt = lt[k][0];
+            t.q = lt[k][1];
+            t.qf = lt[k][2];
+            const double v = light_ms(t);
+            if (v < bl) {
+                bl = v;
+                cand.nt = t.nt;
+                cand.q = t.q;
+                cand.qf = t.qf;
+            }
+        }
+        for (int k = 0; k < nh; ++k) {
+            RowPlan t = rp;
+            t.nt_h = ht[k][0];
+            t.q_h = ht[k][1];
+            t.qf_h = ht[k][2];
+            const double v = heavy_ms(t);
+            if (v < bh) {
+                bh = v;
+                cand.nt_h = t.nt_h;
+                cand.q_h = t.q_h;
+                cand.qf_h = t.qf_h;
+            }
+        }
+        if (bl + bh < best_t) {
+            best_t = bl + bh;
+            *best = cand;
+            ms[2] = bl;
+            ms[3] = bh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!std::isfinite(best_t))
+        return fail(ctx, IBSN_ERR_HIP, "autotune: no tile could be launched for n=%lld",
+                    (long long)n);
+    return IBSN_OK;
+}
+
 double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -820,6 +986,45 @@ int ibsn_kernel_times_get(ibsn_ctx *ctx, ibsn_kernel_times *out)
 const char *ibsn_last_error(const ibsn_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int ibsn_num_cus(const ibsn_ctx *ctx) { return ctx ? ctx->num_cus : 0; }
+
+int ibsn_autotune(ibsn_ctx *ctx, const ibsn_problem *prob, ibsn_tile *out)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (!prob) {
+        ctx->tuned.clear();
+        return IBSN_OK;
+    }
+    CKI(check_problem(ctx, prob));
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return fail(ctx, IBSN_ERR_HIP, "autotune: hipSetDevice failed");
+    // a shape tuned before is tuned again (the search runs on the default plan)
+    const int mixed = prob->precision == IBSN_PREC_MIXED ? 1 : 0;
+    std::vector<ibsn_ctx::Tuned> keep;
+    for (const auto &t : ctx->tuned)
+        if (!(t.m == prob->m && t.n == prob->n && t.kind == prob->cost_kind && t.mixed == mixed))
+            keep.push_back(t);
+    ctx->tuned.swap(keep);
+    RowPlan best;
+    double ms[4];
+    CKI(tune_plan(ctx, prob, &best, ms));
+    ctx->tuned.push_back({prob->m, prob->n, prob->cost_kind, mixed, best});
+    if (out) {
+        out->nt = best.nt;
+        out->q = best.q;
+        out->qf = best.qf;
+        out->nt_h = best.nt_h;
+        out->q_h = best.q_h;
+        out->qf_h = best.qf_h;
+        out->grid = best.grid;
+        out->reserved = 0;
+        out->default_light_ms = ms[0];
+        out->default_heavy_ms = ms[1];
+        out->light_ms = ms[2];
+        out->heavy_ms = ms[3];
+    }
+    return IBSN_OK;
+}
 
 int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks)
 {

@@ -13,15 +13,18 @@ struct RowPlan {
     int nt;              // threads per workgroup (eval, stop pass 1)
     int q;               // vector slots per thread (row held as q*vec values per thread)
     int qf;              // leading slabs that lie inside the row for every thread
-    int nt_h, q_h, qf_h; // the same for trial, sparsify and stop pass 2
+    int nt_h, q_h, qf_h; // the same for trial and sparsify
     int vec;             // elements per vector load (2 for FP64 cost, 4 for FP32)
     int grid;            // number of workgroups (all passes)
 };
 
 // Choose the register tile for a row of n entries; returns false if n is too large.
 bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *plan);
-// the same plan with the heavy tile (trial, sparsify, stop pass 2) as the tile
+// the same plan with the heavy tile (trial, sparsify) as the tile
 RowPlan heavy_plan(const RowPlan &p);
+// Compiled light (eval, stop) or heavy (trial, sparsify) tiles that can hold a row of n
+// entries with their first QF slabs inside it: up to cap rows {NT, Q, QF}; returns the count.
+int tile_candidates(int64_t n, int cost_kind, bool heavy, int (*out)[3], int cap);
 
 // Two-level potentials: w_j = wh_j + wl_j with wh on the grid of spacing q and wl the
 // remainder (|wl| <= q/2 plus rounding).  The dense passes stage wl as FP32 after the n

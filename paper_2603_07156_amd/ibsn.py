@@ -48,6 +48,16 @@ class _Center(ct.Structure):
                 ("quantum", ct.c_double)]
 
 
+class Tile(ct.Structure):
+    _fields_ = [("nt", ct.c_int32), ("q", ct.c_int32), ("qf", ct.c_int32), ("nt_h", ct.c_int32),
+                ("q_h", ct.c_int32), ("qf_h", ct.c_int32), ("grid", ct.c_int32),
+                ("reserved", ct.c_int32), ("light_ms", ct.c_double), ("heavy_ms", ct.c_double),
+                ("default_light_ms", ct.c_double), ("default_heavy_ms", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class Options(ct.Structure):
     _fields_ = [
         ("sigma_armijo", ct.c_double), ("beta", ct.c_double),
@@ -109,6 +119,7 @@ class _KernelTimes(ct.Structure):
 
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus", "ibsn_set_cg_kernel",
+           "ibsn_autotune",
            "ibsn_center_init", "ibsn_center_quantum", "ibsn_sinkhorn_step", "ibsn_outer_update", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
@@ -135,6 +146,7 @@ def load():
     L.ibsn_last_error.restype = ct.c_char_p
     L.ibsn_num_cus.argtypes = [vp]
     L.ibsn_set_cg_kernel.argtypes = [vp, ct.c_int, ct.c_int]
+    L.ibsn_autotune.argtypes = [vp, ct.c_void_p, ct.POINTER(Tile)]
     L.ibsn_center_init.argtypes = [vp, P, vp, vp]
     L.ibsn_center_quantum.argtypes = [vp, P, C, vp, ct.POINTER(dbl)]
     L.ibsn_subproblem_eval.argtypes = [vp, P, C, vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), vp]
@@ -223,6 +235,16 @@ class Context:
         """ibsn_set_cg_kernel: CG_AUTO, CG_LAUNCHES or CG_PERSISTENT, and the grid of the
         one-launch form (0: from the problem size)."""
         self.check(load().ibsn_set_cg_kernel(self.h, int(mode), int(blocks)))
+
+    def autotune(self, prob: "Problem | None"):
+        """ibsn_autotune: choose and record the dense-pass tiles for problems of prob's shape
+        on this context (None: clear the records); returns the choice and its timings."""
+        if prob is None:
+            self.check(load().ibsn_autotune(self.h, None, None))
+            return None
+        t = Tile()
+        self.check(load().ibsn_autotune(self.h, ct.byref(prob.raw()), ct.byref(t)))
+        return t.as_dict()
 
     def kernel_timing(self, enable: bool = True):
         """ibsn_kernel_timing: enable (and clear) or disable HIP-event kernel timing."""

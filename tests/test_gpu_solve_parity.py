@@ -104,3 +104,22 @@ def test_ibn_mode_to_1e12(ib, ctx):
     f = lsa_value(inst.C)
     assert abs(gr["primal"] - f) <= 1e-12 * f
     np.testing.assert_allclose(X, Xo, rtol=0, atol=1e-9)
+
+
+def test_gmm_4096_five_outer_iterations(ib, ctx):
+    """The second configuration's generator (Gaussian-mixture points, general weights,
+    4096^2, eta = 1e-2) for five outer iterations on both sides: after a fixed number of
+    inexact outer iterations the trajectories differ by rounding, but each certificate
+    brackets the same OT value (dual <= OT <= primal), so the primal values differ by at most
+    the larger certified gap and each dual stays below the other's primal."""
+    inst = W.gmm_points(4096, 7)
+    pr = ib.Problem(dev(inst.C), dev(inst.a), dev(inst.b), inst.eta)
+    opt_g = ib.default_options(max_outer=5, gap_tol=0.0, marg_tol=0.0)
+    g = ib.solve(ctx, pr, opt_g)["report"]
+    o = orc.solve(inst.C, inst.a, inst.b, inst.eta, options=orc.default_options(
+        max_outer=5, gap_tol=0.0, marg_tol=0.0))["report"]
+    assert g["outer"] == o["outer"] == 5
+    assert abs(g["primal"] - o["primal"]) <= max(g["primal"] - g["dual"], o["primal"] - o["dual"])
+    assert g["dual"] <= o["primal"] * (1 + 1e-13) and o["dual"] <= g["primal"] * (1 + 1e-13)
+    # the same path: each certified gap within a factor of the other's
+    assert 0.5 <= g["rel_gap"] / o["rel_gap"] <= 2.0, (g["rel_gap"], o["rel_gap"])
