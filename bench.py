@@ -46,6 +46,7 @@ if ROOT not in sys.path:
 # HBM counters of the LSE pass (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy of known
 # size); used only while they describe the dense-pass source that is built
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_uniform10000_hbm_counters.md")
+CG_TRAFFIC_MD = os.path.join(ROOT, "profiles", "cg_uniform10000_hbm_counters.md")
 METRIC = ("time to 1e-8 OT gap at n=10k (plain vs warm-start+FP32); LSE-pass HBM GB/s")
 HBM_PEAK_GBS = 8000.0
 ETA = 1e-6
@@ -74,11 +75,19 @@ def cg_roofline(m: int, n: int, rep: dict, kt: dict):
     per_iter = 24.0 * max(nnz - n, 0.0) + 16.0 * n + 8.0 * (6 * n + 2 * m)
     ms_per_iter = kt["cg"][0] / iters
     achieved = per_iter / (ms_per_iter * 1e-3) / 1e9
+    import probe_cg
+    counters = probe_cg.read_traffic(CG_TRAFFIC_MD)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "CG iteration (row gather + column gather + update)",
             "bytes_per_iteration": per_iter, "ms_per_iteration": ms_per_iter,
-            "nnz_mean": nnz}
+            "nnz_mean": nnz,
+            # HBM counters of the three-launch form at a late state of this instance (the
+            # one-launch form is a cooperative launch, which the profiler did not survive)
+            "counters_three_launch_form": None if counters is None else {
+                "traffic_bytes_per_iteration": counters[0],
+                "algorithmic_bytes_per_iteration": counters[1],
+                "summary": os.path.relpath(CG_TRAFFIC_MD, ROOT)}}
 
 
 def cpu_baseline(inst, seconds: float):

@@ -932,8 +932,16 @@ GatherPlan gather_plan(int64_t m, int64_t n, int64_t nnz, int64_t istar, int num
                        size_t max_lds)
 {
     GatherPlan g;
-    // the LDS-staged gathers hold an n-vector (rows) or an m-vector (columns) per workgroup
-    g.lds = (size_t)n * 8 + 256 <= max_lds && (size_t)m * 8 + 256 <= max_lds;
+    // the LDS-staged gathers hold an n-vector (rows) or an m-vector (columns) per workgroup;
+    // past the size of the two-kernel form, staging pays only when each workgroup then reads
+    // many entries from LDS: with fewer than about a quarter of the vector's length per
+    // workgroup (a sparse late factor) the staging is most of the traffic (at 10^4 and 3.4e4
+    // entries the staged gathers moved 9x the algorithmic bytes from HBM), and the gathers
+    // read the vectors directly
+    const int64_t dense_e = istar >= 0 ? n : 0;
+    const bool enough = n <= CG_FUSED_MAX_N ||
+                        (double)(nnz - dense_e) >= 0.25 * (double)num_cus * (double)std::max(m, n);
+    g.lds = enough && (size_t)n * 8 + 256 <= max_lds && (size_t)m * 8 + 256 <= max_lds;
     const int64_t dense = istar >= 0 ? n : 0;
     const int64_t rows = istar >= 0 ? m - 1 : m;
     const double avg_row = rows > 0 ? (double)(nnz - dense) / (double)rows : 0.0;

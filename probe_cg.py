@@ -36,6 +36,34 @@ KERNELS = (("row gather", "k_row_gather"), ("column gather", "k_col_gather"),
            ("update", "k_cg_update"))
 
 
+# the three-launch CG kernels are built from this file
+CG_SRC = os.path.join(HERE, "paper_2603_07156_amd", "csrc", "sparse_ops.hip")
+
+
+def source_hash() -> str:
+    import hashlib
+    with open(CG_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def read_traffic(md_path: str):
+    """(traffic, algorithmic) bytes per iteration from a summary written by --summarize, or
+    None if it is missing or was made for a different source of the CG kernels."""
+    if not os.path.exists(md_path):
+        return None
+    vals, h = {}, None
+    with open(md_path) as f:
+        for line in f:
+            for key in ("traffic_bytes_per_iteration", "algorithmic_bytes_per_iteration"):
+                if line.startswith(key + ":"):
+                    vals[key] = float(line.split(":", 1)[1])
+            if line.startswith("CG source sha256:"):
+                h = line.split(":", 1)[1].strip()
+    if h != source_hash() or len(vals) != 2:
+        return None
+    return vals["traffic_bytes_per_iteration"], vals["algorithmic_bytes_per_iteration"]
+
+
 def iteration_bytes(m: int, n: int, nnz: float) -> float:
     """Algorithmic bytes of one CG iteration (as bench.py's roofline_cg): 24 bytes per stored
     entry outside the dense row (index and value, in the rows and in the transpose), 16 per
@@ -145,7 +173,8 @@ def summarize(fetch_csv: str, write_csv: str) -> str:
     lines += [f"| one iteration (three launches): HBM bytes | {total:.4g} |",
               f"| one iteration: algorithmic bytes | {alg:.4g} |", "",
               f"traffic_bytes_per_iteration: {total:.6e}",
-              f"algorithmic_bytes_per_iteration: {alg:.6e}", ""]
+              f"algorithmic_bytes_per_iteration: {alg:.6e}",
+              f"CG source sha256: {source_hash()}", ""]
     return "\n".join(lines)
 
 
