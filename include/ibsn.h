@@ -57,8 +57,9 @@ enum {
     IBSN_ERR_UNSUPPORTED = -5     /* shape outside the compiled kernel range               */
 };
 
-/* Largest n of the dense row kernels: a workgroup holds one row of C in registers and
-   an n-vector of potentials in LDS (FP64 cost and points: 10240 columns; FP32 cost: 20000). */
+/* Widest row a dense kernel holds whole: a workgroup keeps one row of C in registers and
+   an n-vector of potentials in LDS (FP64 cost and points: 10240 columns; FP32 cost: 20000).
+   Wider rows are split into column blocks (ibsn_set_row_split). */
 #define IBSN_MAX_N_F64 10240
 #define IBSN_MAX_N_F32 20000
 
@@ -89,6 +90,18 @@ int ibsn_num_cus(const ibsn_ctx *ctx);
    IBSN_ERR_HIP. */
 enum { IBSN_CG_AUTO = 0, IBSN_CG_LAUNCHES = 1, IBSN_CG_PERSISTENT = 2 };
 int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks);
+/* Rows wider than a tile (the dense passes of eq. (6)-(8), Algorithm 1 and Algorithm 3).
+   cols = 0 (the default): rows of more than IBSN_MAX_N_F64 columns (FP64 cost, points) or
+   IBSN_MAX_N_F32 (FP32 cost) are split into equal column blocks of at most 10240 (FP64,
+   points) or 12288 (FP32) columns; cols > 0: rows of more than cols columns are split into
+   blocks of at most cols columns (a multiple of 64 in [256, IBSN_MAX_N_F64]).  Each pass then
+   runs its kernel per block and joins the blocks per row: the row maximum and sum of the
+   eval and trial passes combine across blocks, and their column sums take a second launch
+   per block (the cost is read twice); sparsify joins the blocks' kept entries per row and
+   forms d from the transpose; the stop test joins its per-row sums and minima.  Results
+   equal the whole-row passes to rounding.  ibsn_autotune refuses split problems.
+   IBSN_ERR_INVALID_ARG for another cols. */
+int ibsn_set_row_split(ibsn_ctx *ctx, int64_t cols);
 
 typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1, IBSN_COST_POINTS = 2 } ibsn_cost_kind;
 

@@ -9,8 +9,12 @@ namespace {
 // a_i P_ij, objective row terms a_i ((r_i + M_i) + log S_i).
 // MX (mixed precision): exp(theta_ij - m_w) in FP32 and held as FP32; the argument, the
 // shifts, S_i, the column partials and the objective stay FP64.
+// Column block of a split row (SPLIT): the first launch per block (colpart null) writes the
+// block's M and S; the second (Mfull given) takes the row's combined shift Mfull_i and the
+// factor f_i = a_i / S_i of the whole row, so that its column partials and plan entries
+// (row pitch ldp) are f_i exp(theta_ij - Mfull_i) = a_i P_ij; it writes no row outputs.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
+template <int NT, int Q, int QF, int VEC, typename CT, bool MX, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                              double sigma, double qg,
@@ -21,7 +25,9 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
                                              double *__restrict__ So, double *__restrict__ lse,
                                              double *__restrict__ plan,
                                              double *__restrict__ colpart,
-                                             double *__restrict__ rowpart)
+                                             double *__restrict__ rowpart, int64_t ldp,
+                                             const double *__restrict__ Mfull,
+                                             const double *__restrict__ fscale)
 {
     constexpr int E = Q * VEC;
     constexpr int NW = NT / WAVE;
@@ -52,7 +58,13 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         acc[e] = 0.0;
     double rowacc = 0.0;
     row_loop<NT, Q, QF, VEC>(
-        C, ldc, py, pscale, n, i0, i1, [&](int i) { stage_rows(i, i1, a, rA, r, rR, nullptr, nullptr); },
+        C, ldc, py, pscale, n, i0, i1,
+        [&](int i) {
+            if (SPLIT && Mfull)
+                stage_rows(i, i1, fscale, rA, Mfull, rR, nullptr, nullptr);
+            else
+                stage_rows(i, i1, a, rA, r, rR, nullptr, nullptr);
+        },
         [&](int i, int slot, const auto *xr) {
         // padding slots: theta = -inf, so they drop out of the max and p = 0; a wave
         // with no column in the row gets m_w = -inf, s_w = 0 and factor 0.  The shift is
@@ -93,7 +105,9 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
         const double term = lane < NW ? pr[NW + lane] * exp_tab(mk - M, etab) : 0.0;
         const double S = row0_red<OP_SUM>(term);
         const double ai = rA[slot];
-        const double sc = ai / S * exp_tab(mw - M, etab);   // a_i exp(m_w - M) / S
+        // a_i exp(m_w - M) / S, or f_i exp(m_w - Mfull_i) for the second launch of a block
+        const double sc = (SPLIT && Mfull) ? ai * exp_tab(mw - rR[slot], etab)
+                                           : ai / S * exp_tab(mw - M, etab);
 #pragma unroll
         for (int e = 0; e < E; ++e)
             acc[e] = fma(sc, (double)x[e], acc[e]);
@@ -102,10 +116,10 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
             for (int e = 0; e < E; ++e) {
                 const int j = col_of<NT, VEC>(e);
                 if (j < n)
-                    plan[(int64_t)i * n + j] = sc * (double)x[e];
+                    plan[(int64_t)i * (SPLIT ? ldp : n) + j] = sc * (double)x[e];
             }
         }
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && !(SPLIT && Mfull)) {
             const double ls = log_tab(S, ltab);
             Mo[i] = M;
             So[i] = S;
@@ -115,26 +129,36 @@ __global__ __launch_bounds__(NT) void k_eval(const CT *__restrict__ C, int64_t l
                 rowacc += ai * ((rR[slot] + M) + ls);
         }
         });
-    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
-    if (threadIdx.x == 0)
+    if (!SPLIT || colpart)
+        store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
+    if (threadIdx.x == 0 && (!SPLIT || rowpart))
         rowpart[blockIdx.x] = rowacc;
 }
 
 }  // namespace
 
 hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, double *M, double *S,
-                       double *lse, double *plan, double *colpart, double *rowpart, hipStream_t st)
+                       double *lse, double *plan, double *colpart, double *rowpart, hipStream_t st,
+                       const double *Mfull, const double *fscale)
 {
 #define BODY                                                                                     \
-    static LdsCache lc_; \
+    static LdsCache lc_, lcs_; \
     const size_t lds_ = lds_w2(d.n, lo_tile(NT, Q, VEC)); \
-    if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX>, lds_, lc_); e_ != hipSuccess) \
+    if (Mfull || !colpart) { \
+        if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX, true>, lds_, lcs_); e_ != hipSuccess) \
+            return e_; \
+        hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX, true>), dim3(p.grid), dim3(NT), lds_, st, \
+                           (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, \
+                           d.w, d.wlo, d.a, r, M, S, lse, plan, colpart, rowpart, d.ldo, Mfull, fscale); \
+        return hipGetLastError(); \
+    } \
+    if (hipError_t e_ = lds_check((const void *)k_eval<NT, Q, QF, VEC, CT, MX, false>, lds_, lc_); e_ != hipSuccess) \
         return e_; \
-    hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT),                     \
+    hipLaunchKernelGGL((k_eval<NT, Q, QF, VEC, CT, MX, false>), dim3(p.grid), dim3(NT),                     \
                        lds_, st,                                         \
                        (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, d.wlo, d.a, r, M, S, \
                        lse,                                                                      \
-                       plan, colpart, rowpart)
+                       plan, colpart, rowpart, d.ldo, Mfull, fscale)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)
 #undef X

@@ -13,8 +13,12 @@ namespace {
 // MX (mixed precision): p from the FP32 exponential (the threshold test is taken on that
 // value, widened), kept values stored as FP32; sums stay FP64, and d = P~^T (a o P~ 1) for
 // the stored factor P~.
+// Column block of a split row (SPLIT): the block's kept entries go to the row's slot from
+// column coff on (row pitch ldo), unnormalised, with the block's kept sum in ksum and its
+// count in len, and no column partials; the row's blocks are joined and normalised
+// afterwards.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT, bool MX>
+template <int NT, int Q, int QF, int VEC, typename CT, bool MX, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                                  double sigma, const double *__restrict__ w,
@@ -26,7 +30,8 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
                                                  int32_t *__restrict__ col,
                                                  xval_t<MX> *__restrict__ val,
                                                  int32_t *__restrict__ len,
-                                                 double *__restrict__ colpart)
+                                                 double *__restrict__ colpart, int64_t ldo,
+                                                 int coff, double *__restrict__ ksum)
 {
     constexpr int E = Q * VEC;
     constexpr int NW = NT / WAVE;
@@ -113,8 +118,10 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
         }
         const double ai = rA[slot];
         double rs = 0.0;   // MX: sum of the row's stored values
-        int32_t *crow = col + (int64_t)i * n;
-        xval_t<MX> *vrow = val + (int64_t)i * n;
+        const int64_t rbase = SPLIT ? (int64_t)i * ldo + coff : (int64_t)i * n;
+        int32_t *crow = col + rbase;
+        xval_t<MX> *vrow = val + rbase;
+        const bool asis = SPLIT || dense;   // stored without the division by the kept sum
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             int before = rank[q];
@@ -125,9 +132,9 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
                     // d = P_rho^T a from the values as stored, so that H_rho 1 = 0 holds
                     // for the factor the HVP reads
                     const xval_t<MX> pv =
-                        (xval_t<MX>)(dense ? (double)x[e] : (double)x[e] * ik);
+                        (xval_t<MX>)(asis ? (double)x[e] : (double)x[e] * ik);
                     const int pos = base[q] + before;
-                    crow[pos] = col_of<NT, VEC>(e);
+                    crow[pos] = col_of<NT, VEC>(e) + (SPLIT ? coff : 0);
                     vrow[pos] = pv;
                     if constexpr (MX) {
                         x[e] = pv;
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
                 }
             }
         }
-        if constexpr (MX) {
+        if (MX && !SPLIT) {
             // FP32 values make the stored row sum 1 + O(2^-24) rather than 1; with
             // d = P~^T (a o P~ 1) the stored factor P~ still gives H_rho 1 = 0 and a
             // positive semidefinite H_rho (Theorem 3.2)
@@ -151,27 +158,40 @@ __global__ __launch_bounds__(NT) void k_sparsify(const CT *__restrict__ C, int64
                 if (keepbits & (1ull << e))
                     acc[e] = fma(sc, (double)x[e], acc[e]);
         }
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             len[i] = running;
+            if (SPLIT)
+                ksum[i] = red[0];
+        }
         });
-    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
+    if (!SPLIT)
+        store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
 }
 
 }  // namespace
 
 hipError_t launch_sparsify(const RowPlan &p_in, const DenseArgs &d, const double *M, const double *S,
                            double rho, const int *istar, int32_t *col, void *val, int32_t *len,
-                           double *colpart, hipStream_t st)
+                           double *colpart, hipStream_t st, double *ksum)
 {
     const RowPlan p = heavy_plan(p_in);
 #define BODY                                                                                     \
-    static LdsCache lc_; \
+    static LdsCache lc_, lcs_; \
     const size_t lds_bytes = lds_w2(d.n, lo_tile(NT, Q, VEC)); \
-    if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX>, lds_bytes, lc_); e_ != hipSuccess) \
+    if (ksum) { \
+        if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX, true>, lds_bytes, lcs_); e_ != hipSuccess) \
+            return e_; \
+        hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX, true>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+                           (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, \
+                           d.wlo, d.a, M, S, rho, istar, col, (xval_t<MX> *)val, len, colpart, d.ldo, \
+                           (int)d.coff, ksum); \
+        return hipGetLastError(); \
+    } \
+    if (hipError_t e_ = lds_check((const void *)k_sparsify<NT, Q, QF, VEC, CT, MX, false>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
-    hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+    hipLaunchKernelGGL((k_sparsify<NT, Q, QF, VEC, CT, MX, false>), dim3(p.grid), dim3(NT), lds_bytes, st, \
                        (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, rho, \
-                       istar, col, (xval_t<MX> *)val, len, colpart)
+                       istar, col, (xval_t<MX> *)val, len, colpart, d.ldo, (int)d.coff, ksum)
 #define X(a, b, c) IBSN_DISPATCH_MX(a, b, c, BODY)
     IBSN_HEAVY_TILES(X)
 #undef X

@@ -7,8 +7,11 @@ namespace {
 
 // ---------------------------------------------------------------------------------
 // Stop test pass 1 (Algorithm 3, steps 2-8): X = a_i P; z_i; column sums of X and z X.
+// Column block of a split row: the first launch writes the block's row sums of X to rsum
+// (column sums of X as usual); the second takes z from zin for the column sums of z X.
+// Null outputs are not written.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT>
+template <int NT, int Q, int QF, int VEC, typename CT, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                               double sigma, const double *__restrict__ w,
@@ -18,7 +21,9 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
                                               const double *__restrict__ S,
                                               double *__restrict__ z, double *__restrict__ colpart,
                                               double *__restrict__ colpart2,
-                                              double *__restrict__ rowpart)
+                                              double *__restrict__ rowpart,
+                                              double *__restrict__ rsum,
+                                              const double *__restrict__ zin)
 {
     constexpr int E = Q * VEC;
     constexpr bool LO = lo_tile(NT, Q, VEC);
@@ -55,20 +60,25 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
             }
             RedSum::run(red, lds, parity);
             const double rs = red[0];
-            const double zi = fmin(ai / rs, 1.0);
+            const double zi = (SPLIT && zin) ? zin[i] : fmin(ai / rs, 1.0);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 ax[e] += x[e];
                 az[e] = fma(zi, x[e], az[e]);
             }
             if (threadIdx.x == 0) {
-                z[i] = zi;
+                if (!SPLIT)
+                    z[i] = zi;
+                else if (rsum)
+                    rsum[i] = rs;
                 rowacc += (rs - ai) * (rs - ai);
             }
         });
-    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, ax);
-    store_cols<NT, Q, VEC>(colpart2 + (int64_t)blockIdx.x * n, n, az);
-    if (threadIdx.x == 0)
+    if (!SPLIT || colpart)
+        store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, ax);
+    if (!SPLIT || colpart2)
+        store_cols<NT, Q, VEC>(colpart2 + (int64_t)blockIdx.x * n, n, az);
+    if (!SPLIT && threadIdx.x == 0)
         rowpart[blockIdx.x] = rowacc;
 }
 
@@ -78,6 +88,8 @@ __global__ __launch_bounds__(NT) void k_stop1(const CT *__restrict__ C, int64_t 
 // Pass 2a, per row: e_r,i = max(a_i - z_i sum_j X_ij y_j, 0) (exactly >= 0; the clamp
 // removes rounding), and the c-transforms zg_i = min_j (C_ij - gamma_j),
 // zp_i = min_j (C_ij - psi_j); per workgroup sum_i a_i zg_i and sum_i a_i zp_i.
+// Column block of a split row (rowred given): the block's sum_j X_ij y_j and the two minima
+// go to rowred (three arrays of m) instead, and nothing else is written.
 // ---------------------------------------------------------------------------------
 template <int NT, int Q, int QF, int VEC, typename CT>
 __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t ldc,
@@ -93,7 +105,8 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
                                                const double *__restrict__ z,
                                                double *__restrict__ er_row,
                                                double *__restrict__ zg_row,
-                                               double *__restrict__ rowpart)
+                                               double *__restrict__ rowpart,
+                                               double *__restrict__ rowred)
 {
     constexpr int E = Q * VEC;
     constexpr bool LO = lo_tile(NT, Q, VEC);
@@ -140,14 +153,18 @@ __global__ __launch_bounds__(NT) void k_stop2a(const CT *__restrict__ C, int64_t
             red[2] = fmin(red[2], valid ? c - pj : INFINITY);
         }
         Red3::template run_part<0>(red, lds, parity);   // used by thread 0 only
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && rowred) {
+            rowred[i] = red[0];
+            rowred[m + i] = red[1];
+            rowred[2 * (int64_t)m + i] = red[2];
+        } else if (threadIdx.x == 0) {
             er_row[i] = fmax(ai - rZ[slot] * red[0], 0.0);
             zg_row[i] = red[1];
             azg += ai * red[1];
             azp += ai * red[2];
         }
         });
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !rowred) {
         double *o = rowpart + (int64_t)blockIdx.x * STOP2_NSLOT;
         o[STOP2_AZG] = azg;
         o[STOP2_AZP] = azp;
@@ -178,7 +195,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
                                                const double *__restrict__ zg_row,
                                                const double *__restrict__ er1p,
                                                double *__restrict__ xhat,
-                                               double *__restrict__ rowpart)
+                                               double *__restrict__ rowpart, int64_t ldx)
 {
     constexpr int E = Q * VEC;
     constexpr bool LO = lo_tile(NT, Q, VEC);
@@ -259,7 +276,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
                 x_ec += ecj;
                 x_lec += ecj > 0.0 ? ecj * log_tab(ecj, ltab) : 0.0;
                 if (xhat)
-                    xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xh;
+                    xhat[(int64_t)i * ldx + col_of<NT, VEC>(e)] = xh;
             } else if (valid) {
                 // X_ij = 0: Xhat_ij = es e_c,j, whose term es e_c,j (log es + log e_c,j - lr -
                 // x_ij - 1) is added once per row below
@@ -268,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_stop2b(const CT *__restrict__ C, int64_t
                 t_cxh = fma(c, xr, t_cxh);
                 t_xhmin = fmin(t_xhmin, xr);
                 if (xhat)
-                    xhat[(int64_t)i * n + col_of<NT, VEC>(e)] = xr;
+                    xhat[(int64_t)i * ldx + col_of<NT, VEC>(e)] = xr;
             }
         }
         if (es > 0.0)
@@ -368,6 +385,8 @@ bool plan_rows(int64_t m, int64_t n, int cost_kind, int num_cus, RowPlan *p)
             p->vec = cost_kind == 1 ? 4 : 2;
             const int64_t g = (int64_t)num_cus * t[k].per_cu;
             p->grid = (int)(g < m ? g : m);
+            p->nb = 1;
+            p->bw = n;
             return true;
         }
     }
@@ -405,16 +424,24 @@ RowPlan heavy_plan(const RowPlan &p)
 
 hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
                         double *z, double *colpart, double *colpart2, double *rowpart,
-                        hipStream_t st)
+                        hipStream_t st, double *rsum, const double *zin)
 {
 #define BODY                                                                                     \
-    static LdsCache lc_; \
+    static LdsCache lc_, lcs_; \
     const size_t lds_bytes = lds_w2(d.n, lo_tile(NT, Q, VEC)); \
-    if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT>, lds_bytes, lc_); e_ != hipSuccess) \
+    if (rsum || zin) { \
+        if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT, true>, lds_bytes, lcs_); e_ != hipSuccess) \
+            return e_; \
+        hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT, true>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+                           (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, \
+                           d.wlo, d.a, M, S, z, colpart, colpart2, rowpart, rsum, zin); \
+        return hipGetLastError(); \
+    } \
+    if (hipError_t e_ = lds_check((const void *)k_stop1<NT, Q, QF, VEC, CT, false>, lds_bytes, lc_); e_ != hipSuccess) \
         return e_; \
-    hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
+    hipLaunchKernelGGL((k_stop1<NT, Q, QF, VEC, CT, false>), dim3(p.grid), dim3(NT), lds_bytes, st,                 \
                        (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, z,   \
-                       colpart, colpart2, rowpart)
+                       colpart, colpart2, rowpart, rsum, zin)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)
 #undef X
@@ -423,7 +450,8 @@ hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, c
 }
 
 hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
-                        const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st)
+                        const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st,
+                        int which, double *rowred)
 {
 #define BODY                                                                                      \
     static LdsCache lca_, lcb_;                                                                   \
@@ -434,12 +462,16 @@ hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, c
     if (hipError_t e_ = lds_check((const void *)k_stop2b<NT, Q, QF, VEC, CT>, lds_bytes, lcb_);   \
         e_ != hipSuccess)                                                                         \
         return e_;                                                                                \
-    hipLaunchKernelGGL((k_stop2a<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, \
-                       v.gamma, v.psi, v.y, v.z, v.er_row, v.zg_row, rowpart);                    \
-    hipLaunchKernelGGL((k_stop2b<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st,     \
-                       (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, d.wlo, d.a, M, S, \
-                       v.gamma, v.y, v.ec, v.z, v.er_row, v.zg_row, v.er1, xhat, rowpart)
+    if (which & 1)                                                                                \
+        hipLaunchKernelGGL((k_stop2a<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+                           (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, \
+                           d.wlo, d.a, M, S, v.gamma, v.psi, v.y, v.z, v.er_row, v.zg_row, rowpart, \
+                           rowred);                                                               \
+    if (which & 2)                                                                                \
+        hipLaunchKernelGGL((k_stop2b<NT, Q, QF, VEC, CT>), dim3(p.grid), dim3(NT), lds_bytes, st, \
+                           (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.w, \
+                           d.wlo, d.a, M, S, v.gamma, v.y, v.ec, v.z, v.er_row, v.zg_row, v.er1,  \
+                           xhat, rowpart, d.ldo)
 #define X(a, b, c) IBSN_DISPATCH(a, b, c, BODY)
     IBSN_LIGHT_TILES(X)
 #undef X

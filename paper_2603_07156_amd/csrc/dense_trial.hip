@@ -15,8 +15,12 @@ namespace {
 // with max tau <= 80 (q e^tau <= e^80 < FLT_MAX); larger steps go to the FP64 pass.
 // `flags` selects the steps a launch handles: bit f for scal[SC_BIG] == f (0: max tau <=
 // 80, 2: 80 < max tau <= 500, 1: larger, the shifted form).
+// Column block of a split row: the first launch per block writes the row sums Z, A, B and
+// the maximum of q e^tau over the block to rowred (four arrays of m) instead of the row
+// outputs; the second (fscale given) takes f_i = a_i / Z_i of the whole row for its column
+// partials and writes no row outputs.
 // ---------------------------------------------------------------------------------
-template <int NT, int Q, int QF, int VEC, typename CT, bool MX, int BIG>
+template <int NT, int Q, int QF, int VEC, typename CT, bool MX, int BIG, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t ldc,
                                               const double *__restrict__ py, double pscale, int m, int n,
                                               double sigma, double qg,
@@ -28,7 +32,9 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
                                               const double *__restrict__ scal,
                                               double *__restrict__ Mn, double *__restrict__ Sn,
                                               double *__restrict__ colpart,
-                                              double *__restrict__ rowpart, int flags)
+                                              double *__restrict__ rowpart, int flags,
+                                              double *__restrict__ rowred,
+                                              const double *__restrict__ fscale)
 {
     constexpr int E = Q * VEC;
     constexpr bool LO = lo_tile(NT, Q, VEC);
@@ -54,7 +60,9 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
     double rowacc = 0.0;
     row_loop<NT, Q, QF, VEC>(
         C, ldc, py, pscale, n, i0, i1,
-        [&](int i) { stage_rows(i, i1, Mb, rM, a, rA, nullptr, nullptr); },
+        [&](int i) {
+            stage_rows(i, i1, Mb, rM, (SPLIT && fscale) ? fscale : a, rA, nullptr, nullptr);
+        },
         [&](int i, int slot, const auto *xr) {
         const double Mi = rM[slot];
         // The staged column values are the same for every row; an index offset the compiler
@@ -86,11 +94,18 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
         Red::template run_part<1>(red, lds, parity);
         const double Z = red[0], A = red[1], B = red[2], mx = red[3];
         const double ai = rA[slot];
-        const double sc = ai / Z;
+        const double sc = (SPLIT && fscale) ? ai : ai / Z;
 #pragma unroll
         for (int e = 0; e < E; ++e)
             acc[e] = fma(sc, (double)x[e], acc[e]);
-        if (threadIdx.x == 0) {
+        if (SPLIT && threadIdx.x == 0) {
+            if (rowred) {
+                rowred[i] = Z;
+                rowred[m + i] = A;
+                rowred[2 * (int64_t)m + i] = B;
+                rowred[3 * (int64_t)m + i] = mx;
+            }
+        } else if (threadIdx.x == 0) {
             // a step that pushes a whole row below the FP64 range is not a decrease
             const double delta =
                 !(Z > 0.0) ? INFINITY : (BIG ? tau_shift + log(Z / A) : log1p(B / A));
@@ -102,8 +117,9 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
             Sn[i] = Z * exp((Mi - Mnew) + tau_shift);
         }
         });
-    store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
-    if (threadIdx.x == 0)
+    if (!SPLIT || colpart)
+        store_cols<NT, Q, VEC>(colpart + (int64_t)blockIdx.x * n, n, acc);
+    if (!SPLIT && threadIdx.x == 0)
         rowpart[blockIdx.x] = rowacc;
 }
 
@@ -111,22 +127,30 @@ __global__ __launch_bounds__(NT) void k_trial(const CT *__restrict__ C, int64_t 
 
 hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M, const double *colv,
                         const double *scal, double *M_new, double *S_new, double *colpart,
-                        double *rowpart, hipStream_t st)
+                        double *rowpart, hipStream_t st, double *rowred, const double *fscale)
 {
     const RowPlan p = heavy_plan(p_in);
+    const bool split = rowred || fscale;
 #define LAUNCH_TRIAL(MXV, BIGV, FLAGS, LC)                                                        \
-    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>,          \
+    if (split) {                                                                                  \
+        LAUNCH_TRIAL1(MXV, BIGV, FLAGS, LC##s, true);                                             \
+    } else {                                                                                      \
+        LAUNCH_TRIAL1(MXV, BIGV, FLAGS, LC, false);                                               \
+    }
+#define LAUNCH_TRIAL1(MXV, BIGV, FLAGS, LC, SPL)                                                  \
+    if (hipError_t e_ = lds_check((const void *)k_trial<NT, Q, QF, VEC, CT, MXV, BIGV, SPL>,     \
                                   lds_w2(d.n, lo_tile(NT, Q, VEC)), LC);                          \
         e_ != hipSuccess)                                                                         \
         return e_;                                                                                \
-    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MXV, BIGV>), dim3(p.grid), dim3(NT),         \
+    hipLaunchKernelGGL((k_trial<NT, Q, QF, VEC, CT, MXV, BIGV, SPL>), dim3(p.grid), dim3(NT),    \
                        lds_w2(d.n, lo_tile(NT, Q, VEC)), st,                                      \
                        (const CT *)d.C, d.ldc, d.py, d.pscale, (int)d.m, (int)d.n, d.sigma, d.q, d.w, \
-                       d.wlo, d.a, M, colv, scal, M_new, S_new, colpart, rowpart, FLAGS)
+                       d.wlo, d.a, M, colv, scal, M_new, S_new, colpart, rowpart, FLAGS, rowred, \
+                       fscale)
     // FP64: the small form for flags 0 and 2, the shifted form for flag 1.  Mixed: the FP32
     // small form for flag 0 only; flags 2 and 1 run the FP64 forms.
 #define BODY                                                                                      \
-    static LdsCache lc0_, lc1_, lc2_;                                                             \
+    static LdsCache lc0_, lc1_, lc2_, lc0_s, lc1_s, lc2_s;                                        \
     if constexpr (MX) {                                                                           \
         LAUNCH_TRIAL(true, 0, 1, lc2_);                                                           \
     }                                                                                             \
@@ -137,6 +161,7 @@ hipError_t launch_trial(const RowPlan &p_in, const DenseArgs &d, const double *M
 #undef X
 #undef BODY
 #undef LAUNCH_TRIAL
+#undef LAUNCH_TRIAL1
     return hipErrorInvalidValue;
 }
 

@@ -65,6 +65,8 @@ struct ibsn_ctx {
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     DevBuf cg_pp;                  // partial sums and barrier state of the one-launch CG
     int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT
+    int64_t split_cols = 0;        // rows wider than this are split (0: wider than a tile)
+    DevBuf wd_M, wd_S, wd_f, wd_rr, wd_len;   // per-block row arrays of split rows
     struct Tuned {                 // plans chosen by ibsn_autotune, per problem shape
         int64_t m, n;
         int kind, mixed;
@@ -159,6 +161,26 @@ T *P(DevBuf &b)
     return reinterpret_cast<T *>(b.p);
 }
 
+// Width of the column blocks of a split row, or 0 when rows are not split.  Rows are split
+// when they exceed the register tiles (10240 columns for an FP64 or points cost, 20000 for
+// an FP32 cost) or the width set by ibsn_set_row_split; blocks are then at most 10240
+// columns (FP64, points), 12288 (FP32, so that the low parts of w still fit) or the set
+// width, of equal width rounded up to a multiple of 64 except the last.
+int64_t split_width(const ibsn_ctx *ctx, const ibsn_problem *p)
+{
+    const int64_t n = p->n;
+    const int64_t narrow = p->cost_kind == IBSN_COST_F32 ? IBSN_MAX_N_F32 : IBSN_MAX_N_F64;
+    const int64_t lim = ctx->split_cols > 0 ? ctx->split_cols : narrow;
+    if (n <= lim)
+        return 0;
+    const int64_t blk = ctx->split_cols > 0 ? ctx->split_cols
+                        : (p->cost_kind == IBSN_COST_F32 ? (int64_t)LO_MAX_COLS
+                                                         : (int64_t)IBSN_MAX_N_F64);
+    const int64_t nb = (n + blk - 1) / blk;
+    const int64_t bw = ((n + nb - 1) / nb + 63) / 64 * 64;
+    return bw < blk ? bw : blk;
+}
+
 int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
 {
     if (!ctx)
@@ -188,12 +210,10 @@ int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
                         p->cost_scale);
         if (((uintptr_t)p->C % 8) != 0 || ((uintptr_t)p->y % 8) != 0)
             return fail(ctx, IBSN_ERR_INVALID_ARG, "x and y must be 8-byte aligned");
-        if (p->n > IBSN_MAX_N_F64)
-            return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld exceeds the register-tiled row kernels "
-                        "(max %d for points)", (long long)p->n, IBSN_MAX_N_F64);
-        if ((size_t)p->n * sizeof(double) + 3584 > ctx->max_lds)
+        const int64_t wp = split_width(ctx, p) ? split_width(ctx, p) : p->n;
+        if ((size_t)wp * sizeof(double) + 3584 > ctx->max_lds)
             return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld needs %zu bytes of LDS (device max %zu)",
-                        (long long)p->n, (size_t)p->n * 8 + 3584, ctx->max_lds);
+                        (long long)wp, (size_t)wp * 8 + 3584, ctx->max_lds);
         return IBSN_OK;
     }
     if (!p->C || !p->a || !p->b)
@@ -201,18 +221,16 @@ int check_problem(ibsn_ctx *ctx, const ibsn_problem *p)
     if (p->ldc < p->n)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "ldc=%lld < n=%lld", (long long)p->ldc,
                     (long long)p->n);
-    const int64_t maxn = p->cost_kind == IBSN_COST_F64 ? IBSN_MAX_N_F64 : IBSN_MAX_N_F32;
-    if (p->n > maxn)
-        return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld exceeds the register-tiled row kernels "
-                    "(max %lld for this cost type)", (long long)p->n, (long long)maxn);
+    // rows wider than the register tiles are split into column blocks (split_width)
+    const int64_t wmax = split_width(ctx, p) ? split_width(ctx, p) : p->n;
     const size_t es = p->cost_kind == IBSN_COST_F64 ? 8 : 4;
     if (((uintptr_t)p->C % es) != 0)
         return fail(ctx, IBSN_ERR_INVALID_ARG, "C must be aligned to its element size");
     // the row passes stage an n-vector in LDS beside at most 3.5 KB of their own (each
     // launch also checks its exact total against the device limit)
-    if ((size_t)p->n * sizeof(double) + 3584 > ctx->max_lds)
+    if ((size_t)wmax * sizeof(double) + 3584 > ctx->max_lds)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "n=%lld needs %zu bytes of LDS (device max %zu)",
-                    (long long)p->n, (size_t)p->n * 8 + 3584, ctx->max_lds);
+                    (long long)wmax, (size_t)wmax * 8 + 3584, ctx->max_lds);
     return IBSN_OK;
 }
 
@@ -240,6 +258,14 @@ double quantum_of(double B)
 
 int plan_for(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *rp)
 {
+    if (const int64_t bw = split_width(ctx, p)) {
+        if (!plan_rows(p->m, bw, p->cost_kind, ctx->num_cus, rp))
+            return fail(ctx, IBSN_ERR_UNSUPPORTED, "no row tile for blocks of %lld columns",
+                        (long long)bw);
+        rp->bw = bw;
+        rp->nb = (int)((p->n + bw - 1) / bw);
+        return IBSN_OK;
+    }
     if (!plan_rows(p->m, p->n, p->cost_kind, ctx->num_cus, rp))
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "no row tile for n=%lld", (long long)p->n);
     const int mixed = p->precision == IBSN_PREC_MIXED ? 1 : 0;
@@ -254,7 +280,15 @@ int plan_for(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *rp)
 // per-call workspace sized for (m, n, grid)
 int ensure_ws(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp)
 {
-    const size_t n = (size_t)p->n, m = (size_t)p->m, G = (size_t)rp.grid;
+    const size_t n = (size_t)p->n, m = (size_t)p->m, G = (size_t)rp.grid * (size_t)rp.nb;
+    if (rp.nb > 1) {
+        const size_t nb = (size_t)rp.nb;
+        CKI(ensure(ctx, ctx->wd_M, nb * m * 8));
+        CKI(ensure(ctx, ctx->wd_S, nb * m * 8));
+        CKI(ensure(ctx, ctx->wd_f, m * 8));
+        CKI(ensure(ctx, ctx->wd_rr, 4 * nb * m * 8));
+        CKI(ensure(ctx, ctx->wd_len, nb * m * 4));
+    }
     CKI(ensure(ctx, ctx->w, n * 8));
     CKI(ensure(ctx, ctx->wlo, n * 8));
     CKI(ensure(ctx, ctx->lcv, n * 8));
@@ -295,14 +329,18 @@ DenseArgs dense_args(ibsn_ctx *ctx, const ibsn_problem *p, int64_t k, double q, 
     d.w = P<double>(ctx->w);
     d.wlo = P<double>(ctx->wlo);
     d.a = p->a;
+    d.ldo = p->n;
+    d.coff = 0;
     return d;
 }
 
 // whether the dense passes of this problem carry the low parts of the potentials: every
-// tile except the FP32-cost ones wider than LO_MAX_COLS columns
-int lo_split(const ibsn_problem *p)
+// tile except the FP32-cost ones wider than LO_MAX_COLS columns (the block width of a
+// split row)
+int lo_split(const ibsn_ctx *ctx, const ibsn_problem *p)
 {
-    return (p->cost_kind != IBSN_COST_F32 || p->n <= LO_MAX_COLS) ? 1 : 0;
+    const int64_t bw = split_width(ctx, p);
+    return (p->cost_kind != IBSN_COST_F32 || (bw ? bw : p->n) <= LO_MAX_COLS) ? 1 : 0;
 }
 
 int read_scal(ibsn_ctx *ctx, int count = SC_NSLOT)
@@ -375,6 +413,37 @@ struct KTimer {
 // ---------------------------------------------------------------------------------
 // pass-level building blocks (also used by the solver)
 // ---------------------------------------------------------------------------------
+// Column block b of a split row: columns [j0, j0 + w), its tile plan (the last block's own
+// tile, on the same grid) and its pass arguments (cost, y, w and its low parts from column
+// j0; the m x n outputs keep the row pitch n).
+struct Block {
+    int64_t j0, w;
+    RowPlan rp;
+    DenseArgs d;
+};
+Block block_of(const ibsn_ctx *ctx, const RowPlan &rp, const DenseArgs &d, int b)
+{
+    Block k;
+    k.j0 = (int64_t)b * rp.bw;
+    k.w = std::min<int64_t>(rp.bw, d.n - k.j0);
+    k.rp = rp;
+    if (k.w != rp.bw) {
+        plan_rows(d.m, k.w, d.cost_kind, ctx->num_cus, &k.rp);
+        k.rp.grid = rp.grid;
+    }
+    k.d = d;
+    k.d.n = k.w;
+    k.d.ldo = d.n;
+    k.d.coff = k.j0;
+    if (d.cost_kind == IBSN_COST_POINTS)
+        k.d.py = d.py + k.j0 * d.pdim;
+    else
+        k.d.C = (const char *)d.C + k.j0 * (d.cost_kind == IBSN_COST_F32 ? 4 : 8);
+    k.d.w = d.w + k.j0;
+    k.d.wlo = d.wlo + k.j0;
+    return k;
+}
+
 // eval at the current ctx->w (already formed); writes M, S, lse, c, g, plan; objective to
 // scal[SC_OBJ] when r != null (needs gamma for b^T gamma); norms of g to scal.
 int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
@@ -383,12 +452,33 @@ int run_eval(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
 {
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q, mixed);
-    {
+    if (rp.nb > 1) {
+        // each block's (M, S), the rows joined, then each block's column partials from the
+        // whole row's shift and a_i / S_i
         KTimer kt(ctx, mixed ? IBSN_KT_EVAL_MIXED : IBSN_KT_EVAL);
-        CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart),
-                        P<double>(ctx->rowpart), st));
-    }
-    {
+        const int64_t m = p->m;
+        double *Mb = P<double>(ctx->wd_M), *Sb = P<double>(ctx->wd_S), *f = P<double>(ctx->wd_f);
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_eval(bk.rp, bk.d, nullptr, Mb + b * m, Sb + b * m, nullptr, nullptr,
+                            nullptr, nullptr, st));
+        }
+        CKH(launch_wide_eval_rows(m, rp.nb, Mb, Sb, p->a, r, M, S, lse, f,
+                                  P<double>(ctx->rowpart), rp.grid, st));
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_eval(bk.rp, bk.d, nullptr, nullptr, nullptr, nullptr,
+                            plan ? plan + bk.j0 : nullptr, P<double>(ctx->colpart), nullptr, st,
+                            M, f));
+            CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, bk.w, c + bk.j0,
+                                 p->b + bk.j0, g + bk.j0, st));
+        }
+    } else {
+        {
+            KTimer kt(ctx, mixed ? IBSN_KT_EVAL_MIXED : IBSN_KT_EVAL);
+            CKH(launch_eval(rp, d, r, M, S, lse, plan, P<double>(ctx->colpart),
+                            P<double>(ctx->rowpart), st));
+        }
         KTimer kt(ctx, IBSN_KT_COLRED);
         CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, c, p->b, g, st));
     }
@@ -410,14 +500,34 @@ int run_trial(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q, mixed);
     double *scal = P<double>(ctx->scal);
-    CKH(sk_trial_prep(p->n, t, p->eta, q, lo_split(p), Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
+    CKH(sk_trial_prep(p->n, t, p->eta, q, lo_split(ctx, p), Delta, p->b, P<double>(ctx->tauv), P<double>(ctx->colv),
                       scal, st));
-    {
+    if (rp.nb > 1) {
+        // each block's row sums, the rows joined (decrease, new state, a_i / Z_i), then each
+        // block's column partials
         KTimer kt(ctx, mixed ? IBSN_KT_TRIAL_MIXED : IBSN_KT_TRIAL);
-        CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
-                         P<double>(ctx->rowpart), st));
-    }
-    {
+        const int64_t m = p->m;
+        double *rr = P<double>(ctx->wd_rr), *f = P<double>(ctx->wd_f);
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_trial(bk.rp, bk.d, M, P<double>(ctx->colv) + bk.j0, scal, nullptr, nullptr,
+                             nullptr, nullptr, st, rr + 4 * m * b, nullptr));
+        }
+        CKH(launch_wide_trial_rows(m, rp.nb, rr, p->a, M, scal, q, Mn, Sn, f,
+                                   P<double>(ctx->rowpart), rp.grid, st));
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_trial(bk.rp, bk.d, M, P<double>(ctx->colv) + bk.j0, scal, nullptr, nullptr,
+                             P<double>(ctx->colpart), nullptr, st, nullptr, f));
+            CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, bk.w, cn + bk.j0,
+                                 p->b + bk.j0, gn + bk.j0, st));
+        }
+    } else {
+        {
+            KTimer kt(ctx, mixed ? IBSN_KT_TRIAL_MIXED : IBSN_KT_TRIAL);
+            CKH(launch_trial(rp, d, M, P<double>(ctx->colv), scal, Mn, Sn, P<double>(ctx->colpart),
+                             P<double>(ctx->rowpart), st));
+        }
         KTimer kt(ctx, IBSN_KT_COLRED);
         CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, cn, p->b, gn, st));
     }
@@ -444,10 +554,32 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     const double *colX = P<double>(ctx->cvec);   // column sums of X
     const double *colF = P<double>(ctx->colv);   // column sums of F = diag(z) X
     int rowres_parts = rp.grid;                  // partials of sum_i (X1 - a)_i^2
+    const int64_t m = p->m;
+    double *rr = P<double>(ctx->wd_rr);
     if (c_state) {
         CKH(sk_fill(p->m, 1.0, P<double>(ctx->zv), st));
         colX = colF = c_state;
         rowres_parts = 0;   // X1 = a
+    } else if (rp.nb > 1) {
+        // the blocks' row sums of X (and column sums of X), z from the joined rows, then the
+        // column sums of z X
+        KTimer kt(ctx, IBSN_KT_STOP1);
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_stop1(bk.rp, bk.d, M, S, nullptr, P<double>(ctx->colpart), nullptr, nullptr,
+                             st, rr + b * m, nullptr));
+            CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, bk.w,
+                                 P<double>(ctx->cvec) + bk.j0, nullptr, nullptr, st));
+        }
+        CKH(launch_wide_stop1_rows(m, rp.nb, rr, p->a, P<double>(ctx->zv),
+                                   P<double>(ctx->rowpart2), rp.grid, st));
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_stop1(bk.rp, bk.d, M, S, nullptr, nullptr, P<double>(ctx->colpart2), nullptr,
+                             st, nullptr, P<double>(ctx->zv)));
+            CKH(launch_colreduce(P<double>(ctx->colpart2), rp.grid, bk.w,
+                                 P<double>(ctx->colv) + bk.j0, nullptr, nullptr, st));
+        }
     } else {
         {
             KTimer kt(ctx, IBSN_KT_STOP1);
@@ -470,11 +602,36 @@ int run_stop(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k,
     v.er_row = P<double>(ctx->erv);
     v.zg_row = P<double>(ctx->zgv);
     v.er1 = scal + SC_ER1;   // read on the device: no host round trip
-    {
+    int parts = rp.grid;
+    if (rp.nb > 1) {
+        // pass 2a per block into per-row partials, the rows joined (e_r, zg and the dual
+        // sums over all nb * grid slots), then pass 2b per block into its own slots
+        KTimer kt(ctx, IBSN_KT_STOP2);
+        parts = rp.grid * rp.nb;
+        double *rp2 = P<double>(ctx->rowpart);
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            Stop2Vec vb = v;
+            vb.gamma += bk.j0;
+            vb.psi += bk.j0;
+            vb.y += bk.j0;
+            CKH(launch_stop2(bk.rp, bk.d, M, S, vb, nullptr, nullptr, st, 1, rr + 3 * m * b));
+        }
+        CKH(launch_wide_stop2a_rows(m, rp.nb, rr, p->a, v.z, v.er_row, v.zg_row, rp2, parts, st));
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            Stop2Vec vb = v;
+            vb.gamma += bk.j0;
+            vb.y += bk.j0;
+            vb.ec += bk.j0;
+            CKH(launch_stop2(bk.rp, bk.d, M, S, vb, xhat ? xhat + bk.j0 : nullptr,
+                             rp2 + (int64_t)b * rp.grid * STOP2_NSLOT, st, 2));
+        }
+    } else {
         KTimer kt(ctx, IBSN_KT_STOP2);
         CKH(launch_stop2(rp, d, M, S, v, xhat, P<double>(ctx->rowpart), st));
     }
-    CKH(sk_stop_final(rp.grid, P<double>(ctx->rowpart), P<double>(ctx->rowpart2), rowres_parts,
+    CKH(sk_stop_final(parts, P<double>(ctx->rowpart), P<double>(ctx->rowpart2), rowres_parts,
                       scal, P<double>(ctx->stopout), st));
     return IBSN_OK;
 }
@@ -507,6 +664,8 @@ void csr_release(ibsn_csr *c)
         release(*b);
 }
 
+CsrView csr_view(const ibsn_csr *c);
+
 // sparsify into c at the state (w formed), rho; istar on device in c->istar_dev
 int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_t k, double q,
                  const double *M, const double *S, double rho, ibsn_csr *c, int mixed)
@@ -514,13 +673,30 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     hipStream_t st = ctx->stream;
     DenseArgs d = dense_args(ctx, p, k, q, mixed);
     c->f32 = mixed;
-    {
+    const bool split = rp.nb > 1;
+    if (split) {
+        // each block's kept entries at its own offset of the row's slot, then the blocks
+        // joined per row; d follows from the transpose below
         KTimer kt(ctx, mixed ? IBSN_KT_SPARSIFY_MIXED : IBSN_KT_SPARSIFY);
-        CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
-                            c->val.p, P<int32_t>(c->len), P<double>(ctx->colpart), st));
+        const int64_t m = p->m;
+        for (int b = 0; b < rp.nb; ++b) {
+            const Block bk = block_of(ctx, rp, d, b);
+            CKH(launch_sparsify(bk.rp, bk.d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
+                                c->val.p, P<int32_t>(ctx->wd_len) + b * m, nullptr, st,
+                                P<double>(ctx->wd_rr) + b * m));
+        }
+        CKH(launch_wide_join(m, p->n, rp.nb, rp.bw, P<int32_t>(ctx->wd_len), P<double>(ctx->wd_rr),
+                             p->a, P<int>(c->istar_dev), P<int32_t>(c->col), c->val.p, c->f32,
+                             P<int32_t>(c->len), P<double>(ctx->wd_f), st));
+    } else {
+        {
+            KTimer kt(ctx, mixed ? IBSN_KT_SPARSIFY_MIXED : IBSN_KT_SPARSIFY);
+            CKH(launch_sparsify(rp, d, M, S, rho, P<int>(c->istar_dev), P<int32_t>(c->col),
+                                c->val.p, P<int32_t>(c->len), P<double>(ctx->colpart), st));
+        }
+        CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(c->d), nullptr,
+                             nullptr, st));
     }
-    CKH(launch_colreduce(P<double>(ctx->colpart), rp.grid, p->n, P<double>(c->d), nullptr,
-                         nullptr, st));
     CscWork cw;
     cw.colptr = P<int64_t>(c->colptr);
     cw.colcnt = P<int64_t>(c->colcnt);
@@ -536,6 +712,8 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
                              P<int32_t>(c->len), P<int>(c->istar_dev), cw,
                              P<int64_t>(c->nnz_dev), st));
     }
+    if (split)
+        CKH(launch_wide_d(csr_view(c), P<double>(ctx->wd_f), P<double>(c->d), st));
     int64_t hv[2];
     CKH(hipMemcpyAsync(hv, c->nnz_dev.p, 8, hipMemcpyDeviceToHost, st));
     CKH(hipMemcpyAsync(hv + 1, c->istar_dev.p, 4, hipMemcpyDeviceToHost, st));
@@ -742,7 +920,7 @@ int tune_plan(ibsn_ctx *ctx, const ibsn_problem *p, RowPlan *best, double ms[4])
     CKH(sk_wmax(n, s, gamma, p->eta, scal, st));
     CKI(read_scal(ctx));
     const double q = quantum_of(ctx->host_scal[SC_WMAX] + ctx->host_scal[SC_CMAX] / p->eta);
-    CKH(launch_make_w(s, gamma, q, p->eta, n, lo_split(p), P<double>(ctx->w),
+    CKH(launch_make_w(s, gamma, q, p->eta, n, lo_split(ctx, p), P<double>(ctx->w),
                       P<double>(ctx->wlo), st));
     const DenseArgs d = dense_args(ctx, p, 0, q, mixed);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -940,7 +1118,8 @@ void ibsn_destroy(ibsn_ctx *ctx)
                       &ctx->cg_Ap, &ctx->cg_au, &ctx->cg_star, &ctx->cg_pap, &ctx->cg_rr,
                       &ctx->cg_scal, &ctx->cg_pp, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
                       &ctx->sv_S, &ctx->sv_Mt, &ctx->sv_St, &ctx->sv_ct, &ctx->sv_gt, &ctx->sv_D,
-                      &ctx->sv_c, &ctx->sv_gv};
+                      &ctx->sv_c, &ctx->sv_gv, &ctx->wd_M, &ctx->wd_S, &ctx->wd_f, &ctx->wd_rr,
+                      &ctx->wd_len};
     for (DevBuf *b : bufs)
         release(*b);
     if (ctx->host_scal)
@@ -996,6 +1175,9 @@ int ibsn_autotune(ibsn_ctx *ctx, const ibsn_problem *prob, ibsn_tile *out)
         return IBSN_OK;
     }
     CKI(check_problem(ctx, prob));
+    if (split_width(ctx, prob))
+        return fail(ctx, IBSN_ERR_UNSUPPORTED, "autotune: rows split into column blocks "
+                    "(n=%lld) run on the built-in tiles", (long long)prob->n);
     if (hipSetDevice(ctx->device) != hipSuccess)
         return fail(ctx, IBSN_ERR_HIP, "autotune: hipSetDevice failed");
     // a shape tuned before is tuned again (the search runs on the default plan)
@@ -1038,6 +1220,17 @@ int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "set_cg_kernel: no cooperative launches");
     ctx->cg_mode = mode;
     ctx->cg_blocks = blocks;
+    return IBSN_OK;
+}
+
+int ibsn_set_row_split(ibsn_ctx *ctx, int64_t cols)
+{
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (cols != 0 && (cols < 256 || cols % 64 != 0 || cols > IBSN_MAX_N_F64))
+        return fail(ctx, IBSN_ERR_INVALID_ARG,
+                    "set_row_split: 0, or a multiple of 64 in [256, %d]", IBSN_MAX_N_F64);
+    ctx->split_cols = cols;
     return IBSN_OK;
 }
 
@@ -1116,7 +1309,7 @@ int ibsn_subproblem_eval(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cen
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(ctx, prob),
                       P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream));
     CKI(run_eval(ctx, prob, rp, ctr->k, ctr->quantum, obj_host ? ctr->r : nullptr, gamma, M, S,
                  lse, colmarg,
@@ -1142,7 +1335,7 @@ int ibsn_trial(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, 
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(ctx, prob),
                       P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream));
     CKI(run_trial(ctx, prob, rp, ctr->k, ctr->quantum, M, Delta, t, M_new, S_new, colmarg_new,
                   grad_new, prob->precision));
@@ -1165,7 +1358,7 @@ int ibsn_sinkhorn_step(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_cente
     CKI(ensure_ws(ctx, prob, rp));
     hipStream_t st = ctx->stream;
     const int64_t m = prob->m, n = prob->n;
-    const int split = lo_split(prob);
+    const int split = lo_split(ctx, prob);
     double *w = P<double>(ctx->w), *wlo = P<double>(ctx->wlo), *lc = P<double>(ctx->lcv);
     double *scal = P<double>(ctx->scal);
     CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, n, split, w, wlo, st));
@@ -1197,7 +1390,7 @@ int ibsn_outer_update(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
     double *w = P<double>(ctx->w), *wlo = P<double>(ctx->wlo);
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob), w, wlo,
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(ctx, prob), w, wlo,
                       ctx->stream));
     CKH(sk_outer_update(prob->m, prob->n, prob->a, M, S, w, wlo, r_out, s_out, ctx->stream));
     return IBSN_OK;
@@ -1243,7 +1436,7 @@ int ibsn_sparsify(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ct
             rc = hipStreamSynchronize(ctx->stream) == hipSuccess ? IBSN_OK : IBSN_ERR_HIP;
     }
     if (rc == IBSN_OK) {
-        if (launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+        if (launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(ctx, prob),
                           P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream) != hipSuccess)
             rc = fail(ctx, IBSN_ERR_HIP, "make_w failed");
     }
@@ -1385,7 +1578,7 @@ int ibsn_stop(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_center *ctr, c
     CKH(sk_dot_slot(prob->m, prob->a, nullptr, SC_SUMA, P<double>(ctx->scal), ctx->stream));
     CKH(sk_dot_slot(prob->m, prob->a, prob->a, SC_AA, P<double>(ctx->scal), ctx->stream));
     CKH(sk_dot_slot(prob->n, prob->b, prob->b, SC_BB, P<double>(ctx->scal), ctx->stream));
-    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(prob),
+    CKH(launch_make_w(ctr->s, gamma, ctr->quantum, prob->eta, prob->n, lo_split(ctx, prob),
                       P<double>(ctx->w), P<double>(ctx->wlo), ctx->stream));
     CKI(run_stop(ctx, prob, rp, ctr->k, ctr->quantum, gamma, M, S, xhat));
     CKH(hipMemcpyAsync(out_host, ctx->stopout.p, sizeof(double) * 10, hipMemcpyDeviceToHost,
@@ -1516,7 +1709,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     if (!std::isfinite(cmax))
         CKS(fail(ctx, IBSN_ERR_NUMERIC, "C has a NaN or infinite entry"));
     double *w = P<double>(ctx->w), *wlo = P<double>(ctx->wlo), *lc = P<double>(ctx->lcv);
-    const int split = lo_split(prob);
+    const int split = lo_split(ctx, prob);
     // Mixed precision: Newton steps run their passes (sparsify, trial) in the FP32 form
     // while ||g||_2 >= mixed_switch * eps32 * ||b||_2; below that, after a mixed-form line
     // search fails, and always for the Sinkhorn steps, the stop test and the outer update,

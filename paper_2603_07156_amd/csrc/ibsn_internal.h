@@ -16,6 +16,10 @@ struct RowPlan {
     int nt_h, q_h, qf_h; // the same for trial and sparsify
     int vec;             // elements per vector load (2 for FP64 cost, 4 for FP32)
     int grid;            // number of workgroups (all passes)
+    // rows split into nb column blocks of bw columns (the last one narrower); the tile
+    // fields then describe a block of bw columns.  nb = 1: whole rows (bw = n).
+    int nb = 1;
+    int64_t bw = 0;
 };
 
 // Choose the register tile for a row of n entries; returns false if n is too large.
@@ -49,15 +53,23 @@ struct DenseArgs {
     const double *a;        // m
     int mixed;              // 1: FP32 exponentials and FP32 sparse values (eval, trial,
                             // sparsify); sums, shifts and row state stay FP64
+    // column block of a split row (C, py, w and wlo then point at the block's first column
+    // and n is the block's width): row pitch of the m x n outputs (plan, rounded plan,
+    // sparse slots) and the block's first column in them
+    int64_t ldo;
+    int64_t coff;
 };
 
 // ---- eval (fresh row LSE) ------------------------------------------------------
 // Writes M (grid-rounded row maxima), S (and lse if non-null), plan (optional),
 // colpart[grid][n] = column partials of a_i P_ij,
 // rowpart[grid] = sum_i a_i ((r_i + M_i) + log S_i).
+// Null colpart / rowpart / M: not written.  Mfull, fscale: the second launch of a column
+// block of a split row (column partials and plan from the whole row's shift and a_i / S_i).
 hipError_t launch_eval(const RowPlan &p, const DenseArgs &d, const double *r, double *M, double *S,
                        double *lse, double *plan, double *colpart, double *rowpart,
-                       hipStream_t st);
+                       hipStream_t st, const double *Mfull = nullptr,
+                       const double *fscale = nullptr);
 
 // ---- column log-sum-exp (Sinkhorn step in the log domain) -----------------------
 // lc_j = log sum_i a_i exp(x_ij) / S_i from the row state (M, S) at w (lo: with the low
@@ -72,23 +84,29 @@ hipError_t launch_collse(const DenseArgs &d, int lo, const double *M, const doub
 // Writes M_new, S_new, colpart (a_i P'_ij), rowpart = sum a_i delta_i.
 // Launches both forms; each returns at once unless scal[SC_BIG] selects it, so the
 // choice needs no host round trip.  tau_shift is read from scal[SC_TAUSHIFT].
+// Null colpart / rowpart / M_new: not written.  rowred (4 m-vectors: Z, A, B, max q e^tau)
+// and fscale (a_i / Z_i of the whole row): the two launches of a column block of a split row.
 hipError_t launch_trial(const RowPlan &p, const DenseArgs &d, const double *M, const double *colv,
                         const double *scal, double *M_new, double *S_new, double *colpart,
-                        double *rowpart, hipStream_t st);
+                        double *rowpart, hipStream_t st, double *rowred = nullptr,
+                        const double *fscale = nullptr);
 
 // ---- sparsify (Algorithm 1) ----------------------------------------------------
 // Slotted CSR: row i's kept entries at [i*n, i*n + len_i), columns ascending.
 // colpart = column partials of a_i [P_rho]_ij (for d = P_rho^T a).
+// Null colpart: not written.  ksum: a column block of a split row (see k_sparsify).
 hipError_t launch_sparsify(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
                            double rho, const int *istar, int32_t *col, void *val, int32_t *len,
-                           double *colpart, hipStream_t st);
+                           double *colpart, hipStream_t st, double *ksum = nullptr);
 
 // ---- stop test, pass 1 (Algorithm 3 rows/columns) -------------------------------
 // z_i = min(a_i / sum_j X_ij, 1); colpart  = column partials of X;
 // colpart2 = column partials of z_i X_ij; rowpart = sum_i (sum_j X_ij - a_i)^2.
+// Null outputs are not written.  rsum (block row sums of X) and zin (z given): the two
+// launches of a column block of a split row.
 hipError_t launch_stop1(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
                         double *z, double *colpart, double *colpart2, double *rowpart,
-                        hipStream_t st);
+                        hipStream_t st, double *rsum = nullptr, const double *zin = nullptr);
 
 // ---- stop test, pass 2 (rounded plan, D_phi, certificate) -----------------------
 struct Stop2Vec {
@@ -99,13 +117,46 @@ struct Stop2Vec {
 // rowpart[grid * 10]: per-workgroup sums (see STOP2_* slots).
 enum { STOP2_DPHI = 0, STOP2_CXH, STOP2_AZG, STOP2_AZP, STOP2_CX, STOP2_XU, STOP2_XHMIN,
        STOP2_XF, STOP2_CF, STOP2_NEG, STOP2_NSLOT };
+// which: 1 pass 2a, 2 pass 2b, 3 both.  rowred (three m-vectors): pass 2a of a column block
+// of a split row writes its per-row partials there instead of e_r, zg and the sums.
 hipError_t launch_stop2(const RowPlan &p, const DenseArgs &d, const double *M, const double *S,
-                        const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st);
+                        const Stop2Vec &v, double *xhat, double *rowpart, hipStream_t st,
+                        int which = 3, double *rowred = nullptr);
 
 // ---- column reduction ----------------------------------------------------------
 // out_j = sum_g part[g][j] in a fixed order; if sub != null, out2_j = out_j - sub_j.
 hipError_t launch_colreduce(const double *part, int G, int64_t n, double *out, const double *sub,
                             double *out2, hipStream_t st);
+
+// ---- rows split into column blocks (dense_wide.hip) -------------------------------
+// Per-block row arrays: nb consecutive m-vectors.  G: workgroups, each joining a range of
+// rows and writing one partial sum per row range.
+// eval: M, S, lse (optional) of the whole row, f_i = a_i / S_i, rowpart[G] = objective
+// terms (r given).
+hipError_t launch_wide_eval_rows(int64_t m, int nb, const double *Mb, const double *Sb,
+                                 const double *a, const double *r, double *M, double *S,
+                                 double *lse, double *f, double *rowpart, int G, hipStream_t st);
+// trial: rr = per block 4 m-vectors (Z, A, B, max q e^tau); new row state, f_i = a_i / Z_i,
+// rowpart[G] = sum a_i delta_i
+hipError_t launch_wide_trial_rows(int64_t m, int nb, const double *rr, const double *a,
+                                  const double *M, const double *scal, double qg, double *Mn,
+                                  double *Sn, double *f, double *rowpart, int G, hipStream_t st);
+// sparsify: join the blocks' segments of each row (block b at column offset b bw of the
+// row's slot, lenb entries, kept sum ksb), normalise, write len and the row weights u of d
+hipError_t launch_wide_join(int64_t m, int64_t n, int nb, int64_t bw, const int32_t *lenb,
+                            const double *ksb, const double *a, const int *istar, int32_t *col,
+                            void *val, int f32, int32_t *len, double *u, hipStream_t st);
+struct CsrView;
+// d_j = sum_i u_i P_ij from the transpose and the dense row
+hipError_t launch_wide_d(const CsrView &c, const double *u, double *d, hipStream_t st);
+// stop pass 1: z from the blocks' row sums of X; rowpart[G] = sum (X1 - a)_i^2
+hipError_t launch_wide_stop1_rows(int64_t m, int nb, const double *rsb, const double *a, double *z,
+                                  double *rowpart, int G, hipStream_t st);
+// stop pass 2a: rr = per block 3 m-vectors (sum X y, min C - gamma, min C - psi); e_r, zg,
+// and the AZG / AZP slots of rowpart[G * STOP2_NSLOT]
+hipError_t launch_wide_stop2a_rows(int64_t m, int nb, const double *rr, const double *a,
+                                   const double *z, double *er, double *zg, double *rowpart,
+                                   int G, hipStream_t st);
 
 // ---- small vector / scalar kernels ----------------------------------------------
 // w = s + gamma/eta as a two-level potential (w on the grid of spacing q, wlo the rest);

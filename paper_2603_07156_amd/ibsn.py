@@ -119,7 +119,7 @@ class _KernelTimes(ct.Structure):
 
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus", "ibsn_set_cg_kernel",
-           "ibsn_autotune",
+           "ibsn_set_row_split", "ibsn_autotune",
            "ibsn_center_init", "ibsn_center_quantum", "ibsn_sinkhorn_step", "ibsn_outer_update", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
@@ -146,6 +146,7 @@ def load():
     L.ibsn_last_error.restype = ct.c_char_p
     L.ibsn_num_cus.argtypes = [vp]
     L.ibsn_set_cg_kernel.argtypes = [vp, ct.c_int, ct.c_int]
+    L.ibsn_set_row_split.argtypes = [vp, i64]
     L.ibsn_autotune.argtypes = [vp, ct.c_void_p, ct.POINTER(Tile)]
     L.ibsn_center_init.argtypes = [vp, P, vp, vp]
     L.ibsn_center_quantum.argtypes = [vp, P, C, vp, ct.POINTER(dbl)]
@@ -235,6 +236,12 @@ class Context:
         """ibsn_set_cg_kernel: CG_AUTO, CG_LAUNCHES or CG_PERSISTENT, and the grid of the
         one-launch form (0: from the problem size)."""
         self.check(load().ibsn_set_cg_kernel(self.h, int(mode), int(blocks)))
+
+    def set_row_split(self, cols: int = 0):
+        """ibsn_set_row_split: rows wider than `cols` columns run as column blocks of at most
+        `cols` (0: only rows wider than the register tiles, in blocks of 10240 columns for an
+        FP64 or points cost and 12288 for an FP32 cost)."""
+        self.check(load().ibsn_set_row_split(self.h, int(cols)))
 
     def autotune(self, prob: "Problem | None"):
         """ibsn_autotune: choose and record the dense-pass tiles for problems of prob's shape

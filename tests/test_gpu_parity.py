@@ -594,15 +594,13 @@ def test_invalid_arguments(ib, ctx):
     with pytest.raises(ib.IBSNError) as e:   # marginals that do not sum to 1
         ib.solve(ctx, ib.Problem(pr.C, pr.a * 2, pr.b, 0.01))
     assert e.value.code == -1
-    big = torch.zeros((2, 20481), dtype=torch.float64, device="cuda")
-    with pytest.raises(ib.IBSNError) as e:
-        ib.subproblem_eval(ctx, ib.Problem(big, pr.a[:2] * 8, torch.full((20481,), 1 / 20481,
-                                                                            dtype=torch.float64,
-                                                                            device="cuda"), 0.01),
-                           ib.Center(0, None, torch.zeros(20481, dtype=torch.float64,
-                                                          device="cuda"), 1.0),
-                           torch.zeros(20481, dtype=torch.float64, device="cuda"), want_obj=False)
-    assert e.value.code == -5
+    # rows wider than every tile run split into column blocks (tests/test_gpu_split.py);
+    # block widths outside [256, 10240] or not a multiple of 64 are rejected
+    for cols in (100, 300, 10304, -64):
+        with pytest.raises(ib.IBSNError) as e:
+            ctx.set_row_split(cols)
+        assert e.value.code == -1
+    ctx.set_row_split(0)
     with pytest.raises(ValueError):   # host tensor rejected by the binding
         ib.subproblem_eval(ctx, pr, ctr, torch.zeros(16, dtype=torch.float64))
     with pytest.raises(ib.IBSNError) as e:   # quantum not a power of two
