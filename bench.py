@@ -291,8 +291,14 @@ def batch_solves(ibsn, count: int, outer: int = 20, gap: float = 0.0, workers_li
         ctxs = [ibsn.Context(0, stream=torch.cuda.Stream()) for _ in range(workers)]
         ibsn.solve_batch(ctxs, probs[:workers], opt)   # warm the workspaces
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        outs = ibsn.solve_batch(ctxs, probs, opt)
+        # batches of more than 128 problems run in chunks of 128 calls of ibsn_solve_batch,
+        # each chunk's end reported as it comes (the workers idle at each chunk's tail)
+        outs, t0 = [], time.perf_counter()
+        for c0 in range(0, count, 128):
+            outs += ibsn.solve_batch(ctxs, probs[c0:c0 + 128], opt)
+            if count > 128:
+                print(f"batch: {len(outs)}/{count} problems, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
         dt = time.perf_counter() - t0
         res[f"contexts_{workers}"] = {"seconds": dt, "problems_per_s": count / dt,
                                       "failed": sum(1 for o in outs if o["status"] < 0),
@@ -304,6 +310,70 @@ def batch_solves(ibsn, count: int, outer: int = 20, gap: float = 0.0, workers_li
     if "contexts_1" in res and "contexts_4" in res:
         res["speedup_4_over_1"] = res["contexts_1"]["seconds"] / res["contexts_4"]["seconds"]
     return res
+
+
+def cfg3_legs(ibsn, ctx, outer: int = 5):
+    """The 20000 x 20000 configuration (3-D unit-cube points vs an 8-component mixture,
+    uniform weights, eta = 1e-2): `outer` outer iterations from X^0 with the cost formed from
+    the points in every pass (rows split into two column blocks) in the FP64 and the FP32
+    form, and with the cost stored in FP32 (1.6 GB) on whole rows and on split rows; the time
+    per outer iteration and each pass's mean time."""
+    import numpy as np
+    import torch
+
+    from paper_2603_07156_amd import workloads
+    dev = torch.device("cuda", 0)
+    N = 20000
+    rng = np.random.default_rng(200)
+    x = rng.random((N, 3))
+    y = workloads._gmm(rng, N, 8, 3, 0.08)
+    scale = workloads.points_scale(x, y)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    ab = torch.full((N,), 1.0 / N, dtype=torch.float64, device=dev)
+    # the stored FP32 cost: the same squared distances, formed on the device
+    C32 = torch.empty((N, N), dtype=torch.float32, device=dev)
+    for i0 in range(0, N, 2000):
+        d = xd[i0:i0 + 2000, None, :] - yd[None, :, :]
+        C32[i0:i0 + 2000] = ((d * d).sum(-1) * scale).to(torch.float32)
+    torch.cuda.synchronize()
+    legs = {}
+    cases = [("points_f64", ibsn.Problem.from_points(xd, yd, ab, ab, 1e-2, scale), 0),
+             ("points_mixed", ibsn.Problem.from_points(xd, yd, ab, ab, 1e-2, scale,
+                                                       ibsn.PREC_MIXED), 0),
+             ("stored_f32_mixed_whole_rows", ibsn.Problem(C32, ab, ab, 1e-2,
+                                                          precision=ibsn.PREC_MIXED), 0),
+             ("stored_f32_mixed_split_10240", ibsn.Problem(C32, ab, ab, 1e-2,
+                                                           precision=ibsn.PREC_MIXED), 10240)]
+    opt = ibsn.default_options(max_outer=outer, gap_tol=0.0, marg_tol=0.0)
+    for name, pr, cols in cases:
+        ctx.set_row_split(cols)
+        ibsn.solve(ctx, pr, ibsn.default_options(max_outer=1, gap_tol=0.0, marg_tol=0.0))
+        ctx.kernel_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ibsn.solve(ctx, pr, opt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = kt_dict(ctx.kernel_times())
+        ctx.kernel_timing(False)
+        rep = res["report"]
+        legs[name] = {"seconds": dt, "outer": rep["outer"], "s_per_outer": dt / rep["outer"],
+                      "newton": rep["newton"], "sinkhorn": rep["sinkhorn"],
+                      "rel_gap": rep["rel_gap"], "pass_ms": {k: v["avg"] for k, v in kt.items()}}
+        print(f"cfg3 {name}: {dt:.2f} s for {rep['outer']} outer iterations", file=sys.stderr,
+              flush=True)
+    ctx.set_row_split(0)
+    ev = legs["stored_f32_mixed_whole_rows"]["pass_ms"].get("eval_mixed")
+    evs = legs["stored_f32_mixed_split_10240"]["pass_ms"].get("eval_mixed")
+    alg = 4.0 * N * N + 8.0 * 10 * N   # the FP32 cost once and the row and column vectors
+    return {"workload": f"3-D unit-cube points (seed 200) vs an 8-component mixture, m=n={N}, "
+                        f"uniform weights, eta=1e-2, {outer} outer iterations from X^0",
+            "legs": legs,
+            "eval_mixed_stored_f32_GBs": {"whole_rows": alg / (ev * 1e-3) / 1e9 if ev else None,
+                                          "split_rows": alg / (evs * 1e-3) / 1e9 if evs else None,
+                                          "bytes": alg,
+                                          "note": "algorithmic bytes (the cost read once) over "
+                                                  "the pass time; split rows read the cost twice"}}
 
 
 def main() -> int:
@@ -328,6 +398,8 @@ def main() -> int:
     ap.add_argument("--batch-gap", type=float, default=0.0,
                     help="solve the batched problems to this certified gap instead of 20 outer "
                          "iterations (at most 5000), four contexts only")
+    ap.add_argument("--cfg3", action="store_true",
+                    help="also run the 20000 x 20000 points / FP32-cost configuration")
     ap.add_argument("--batch", type=int, default=32,
                     help="problems of the batched grid-histogram workload (0 = skip)")
     args = ap.parse_args()
@@ -439,6 +511,8 @@ def main() -> int:
                 "bytes_per_launch": pb, "avg_launch_ms": mk["avg"], "launches": mk["launches"]}
     if not args.no_paper:
         out["paper_workloads"] = paper_tables(ibsn, ctx)
+    if args.cfg3:
+        out["cfg3_20000"] = cfg3_legs(ibsn, ctx)
     if args.batch > 0:
         if args.batch_gap > 0:
             out["batch"] = batch_solves(ibsn, args.batch, outer=5000, gap=args.batch_gap,
