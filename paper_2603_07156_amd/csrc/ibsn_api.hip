@@ -64,7 +64,8 @@ struct ibsn_ctx {
     DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     DevBuf cg_pp;                  // partial sums and barrier state of the one-launch CG
-    int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT
+    int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT / _SINGLE
+    bool coop_off = false;         // no cooperative launches (several contexts at once)
     int64_t split_cols = 0;        // rows wider than this are split (0: wider than a tile)
     DevBuf wd_M, wd_S, wd_f, wd_rr, wd_len;   // per-block row arrays of split rows
     struct Tuned {                 // plans chosen by ibsn_autotune, per problem shape
@@ -790,9 +791,26 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     s.scal = P<double>(ctx->cg_scal);
     const CsrView cv = csr_view(c);
     KTimer kt(ctx, IBSN_KT_CG);
+    // one workgroup: forced, or automatic for a small factor whose vectors fit in LDS
+    const bool single_fits = cg_single_fits(c->m, c->n, ctx->max_lds);
+    if (ctx->cg_mode == IBSN_CG_SINGLE ||
+        (ctx->cg_mode == IBSN_CG_AUTO && single_fits && c->m <= CG_SINGLE_MAX_DIM &&
+         c->n <= CG_SINGLE_MAX_DIM &&
+         (double)c->nnz <= CG_SINGLE_ENTRIES_PER_LINE * (double)std::max(c->m, c->n))) {
+        if (!single_fits)
+            return fail(ctx, IBSN_ERR_UNSUPPORTED,
+                        "cg: one-workgroup CG needs n <= %d and (m + n) doubles of LDS",
+                        CG_SINGLE_MAX_COLS_PER_THREAD * 1024);
+        CKH(launch_cg_single(cv, a, eta, shift, rhs, tol, maxit, s, st));
+        double *h = ctx->cg_host;
+        CKH(hipMemcpyAsync(h, s.scal, sizeof(double) * CG_NSLOT, hipMemcpyDeviceToHost, st));
+        CKH(hipStreamSynchronize(st));
+        *iters = (int)h[CG_IT0];
+        return IBSN_OK;
+    }
     // the barrier counter counts (2 maxit + 1) grids of arrivals in 32 bits
     const bool fits = (2.0 * maxit + 1.0) * CG_PERSIST_MAX_GRID < 4294967295.0;
-    if (ctx->cg_mode != IBSN_CG_LAUNCHES && ctx->coop && fits) {
+    if (ctx->cg_mode != IBSN_CG_LAUNCHES && ctx->coop && !ctx->coop_off && fits) {
         // one cooperative launch runs every iteration; one copy of its end state
         const CgPersistPlan pl =
             cg_persist_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->cg_blocks);
@@ -812,7 +830,7 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
         *iters = (int)h[CG_IT0];
         return IBSN_OK;
     }
-    if (ctx->cg_mode == IBSN_CG_PERSISTENT)
+    if (ctx->cg_mode == IBSN_CG_PERSISTENT && !ctx->coop_off)
         return fail(ctx, IBSN_ERR_UNSUPPORTED,
                     "cg: one-launch CG needs cooperative launches and maxit < 2^21");
     const GatherPlan g = gather_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->max_lds);
@@ -1212,9 +1230,9 @@ int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks)
 {
     if (!ctx)
         return IBSN_ERR_INVALID_ARG;
-    if (mode < IBSN_CG_AUTO || mode > IBSN_CG_PERSISTENT || blocks < 0 ||
+    if (mode < IBSN_CG_AUTO || mode > IBSN_CG_SINGLE || blocks < 0 ||
         blocks > CG_PERSIST_MAX_GRID)
-        return fail(ctx, IBSN_ERR_INVALID_ARG, "set_cg_kernel: mode 0..2, 0 <= blocks <= %d",
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "set_cg_kernel: mode 0..3, 0 <= blocks <= %d",
                     CG_PERSIST_MAX_GRID);
     if (mode == IBSN_CG_PERSISTENT && !ctx->coop)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "set_cg_kernel: no cooperative launches");
@@ -2022,15 +2040,12 @@ int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
         return probs[x].m * probs[x].n > probs[y].m * probs[y].n;
     });
-    // Several contexts solve at once on their own streams: CG runs as kernel launches
-    // there, since a cooperative launch is sized for a device that its grid has to itself
-    // (another stream's kernels may hold the compute units its workgroups wait for).
-    std::vector<int> mode((size_t)nctx);
-    for (int w = 0; w < nctx; ++w) {
-        mode[(size_t)w] = ctxs[w]->cg_mode;
-        if (nctx > 1)
-            ctxs[w]->cg_mode = IBSN_CG_LAUNCHES;
-    }
+    // Several contexts solve at once on their own streams: no cooperative launches there,
+    // since a cooperative grid is sized for a device that it has to itself (another
+    // stream's kernels may hold the compute units its workgroups wait for).  CG runs in
+    // one workgroup where that applies, else as kernel launches.
+    for (int w = 0; w < nctx; ++w)
+        ctxs[w]->coop_off = nctx > 1;
     std::atomic<int64_t> next{0};
     auto worker = [&](int w) {
         for (;;) {
@@ -2051,7 +2066,7 @@ int ibsn_solve_batch(ibsn_ctx *const *ctxs, int nctx, int64_t nprob, const ibsn_
     for (std::thread &t : pool)
         t.join();
     for (int w = 0; w < nctx; ++w)
-        ctxs[w]->cg_mode = mode[(size_t)w];
+        ctxs[w]->coop_off = false;
     return IBSN_OK;
 }
 

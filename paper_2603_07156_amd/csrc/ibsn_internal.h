@@ -259,6 +259,24 @@ hipError_t launch_cg_persist(const CgPersistPlan &pl, const CsrView &c, const do
                              double eta, double shift, const double *rhs, double tol, int maxit,
                              CgState &s, double *pp, hipStream_t st);
 
+// CG in one workgroup of 1024 threads (cg_single.hip): p and u in LDS ((m + n) doubles),
+// at most CG_SINGLE_MAX_COLS_PER_THREAD columns per thread.  Results as launch_cg_persist.
+constexpr int CG_SINGLE_MAX_COLS_PER_THREAD = 10;
+// The automatic choice takes the one-workgroup CG for factors of at most
+// CG_SINGLE_ENTRIES_PER_LINE max(m, n) entries with m, n <= CG_SINGLE_MAX_DIM.  Each thread
+// walks the entries of its rows (and columns) one after another, so the iteration grows
+// with the entries per thread: measured per iteration at 2000^2 with 2 entries per row
+// 8.1 us against 10.7 (one cooperative launch) and 17.0 (three launches), at 10^4 45 us
+// against 15.3 and 15.5; on the early, denser factors of the batched workload it was
+// several times slower than the other forms.
+constexpr double CG_SINGLE_ENTRIES_PER_LINE = 3.0;
+constexpr int64_t CG_SINGLE_MAX_DIM = 4096;
+size_t cg_single_lds(int64_t m, int64_t n);
+bool cg_single_fits(int64_t m, int64_t n, size_t max_lds);
+hipError_t launch_cg_single(const CsrView &c, const double *a, double eta, double shift,
+                            const double *rhs, double tol, int maxit, CgState &s,
+                            hipStream_t st);
+
 // export slotted CSR to standard CSR
 hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,

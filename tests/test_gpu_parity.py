@@ -28,11 +28,12 @@ def ctx(ib):
     return ib.Context(0)
 
 
-@pytest.fixture(params=["launches", "persistent"])
+@pytest.fixture(params=["launches", "persistent", "single"])
 def cgctx(request, ib, ctx):
-    """The context with CG run as kernel launches per iteration, or in one cooperative
-    launch (the default where supported); restored to the default afterwards."""
-    ctx.set_cg_kernel(ib.CG_LAUNCHES if request.param == "launches" else ib.CG_PERSISTENT)
+    """The context with CG run as kernel launches per iteration, in one cooperative launch,
+    or in one workgroup; restored to the default afterwards."""
+    ctx.set_cg_kernel({"launches": ib.CG_LAUNCHES, "persistent": ib.CG_PERSISTENT,
+                       "single": ib.CG_SINGLE}[request.param])
     yield ctx
     ctx.set_cg_kernel(ib.CG_AUTO)
 
@@ -380,7 +381,7 @@ def test_cg_persistent_grid_sizes(ib, ctx, blocks):
 
 def test_cg_kernel_mode_arguments(ib, ctx):
     with pytest.raises(RuntimeError):
-        ctx.set_cg_kernel(3)
+        ctx.set_cg_kernel(4)
     with pytest.raises(RuntimeError):
         ctx.set_cg_kernel(ib.CG_PERSISTENT, 1025)
     ctx.set_cg_kernel(ib.CG_AUTO)
@@ -742,6 +743,16 @@ def test_solve_batch_matches_sequential(ib, ctx):
     ref1 = ib.solve(ctx, probs[0], opt)
     ctx.set_cg_kernel(ib.CG_AUTO)
     assert torch.equal(one["gamma"], ref1["gamma"])
+    # CG in one workgroup needs no cooperative launch: the batch keeps that form
+    for c in ctxs:
+        c.set_cg_kernel(ib.CG_SINGLE)
+    outs = ib.solve_batch(ctxs, probs[:4], opt)
+    ctx.set_cg_kernel(ib.CG_SINGLE)
+    for pr, o in zip(probs[:4], outs):
+        ref = ib.solve(ctx, pr, opt)
+        assert torch.equal(o["gamma"], ref["gamma"])
+        assert o["report"]["cg"] == ref["report"]["cg"]
+    ctx.set_cg_kernel(ib.CG_AUTO)
     for inst, pr, o, ref in zip(batch, probs, out, refs):
         assert o["status"] == ref["status"]
         assert torch.equal(o["gamma"], ref["gamma"]), inst.name
