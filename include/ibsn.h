@@ -80,18 +80,23 @@ int ibsn_num_cus(const ibsn_ctx *ctx);
    iteration; IBSN_CG_LAUNCHES: three kernel launches per iteration, the host following the
    residual in chunks; IBSN_CG_SINGLE: every iteration inside one workgroup of 1024 threads
    with p and a.(P_rho p) in LDS (needs n <= 10240 and (m + n) doubles of LDS, else
-   IBSN_ERR_UNSUPPORTED from the CG calls); IBSN_CG_AUTO (the default): one workgroup for a
-   factor of at most 3 max(m, n) stored entries with m, n <= 4096, else persistent where
-   the device supports cooperative launches, else launches.  The forms run the same recurrences;
+   IBSN_ERR_UNSUPPORTED from the CG calls); IBSN_CG_PIPE: one cooperative launch with one
+   grid-wide barrier per iteration, on M = P'^T diag(a) P' (the factor without its dense
+   row, formed once per CG solve; the dense row stays a rank-one term) and the pipelined CG
+   recurrences (Ghysels and Vanroose 2014); IBSN_CG_AUTO (the default): one workgroup for a
+   factor of at most 3 max(m, n) stored entries with m, n <= 4096, else, with cooperative
+   launches, the one-barrier form when M has at most 4 times the factor's entries plus n
+   and the persistent form otherwise, else launches.  The forms run the same recurrences;
    p.(H_rho + shift I)p is taken as the quadratic form (sum d p^2 - sum a (P_rho p)^2)/eta +
    shift sum p^2 in the persistent and one-workgroup forms and as the dot product of p with
    the computed product in the other, so iterates agree to rounding.  ibsn_solve_batch with
    more than one context makes no cooperative launches (a cooperative grid assumes the
    device to itself): CG runs in one workgroup where AUTO or SINGLE takes it, else as
    launches.  IBSN_ERR_INVALID_ARG for an unknown mode or blocks outside 0..1024,
-   IBSN_ERR_UNSUPPORTED for IBSN_CG_PERSISTENT without cooperative launches; a grid larger
+   IBSN_ERR_UNSUPPORTED for IBSN_CG_PERSISTENT or IBSN_CG_PIPE without cooperative launches; a grid larger
    than the device can hold resident makes the CG calls fail with IBSN_ERR_HIP. */
-enum { IBSN_CG_AUTO = 0, IBSN_CG_LAUNCHES = 1, IBSN_CG_PERSISTENT = 2, IBSN_CG_SINGLE = 3 };
+enum { IBSN_CG_AUTO = 0, IBSN_CG_LAUNCHES = 1, IBSN_CG_PERSISTENT = 2, IBSN_CG_SINGLE = 3,
+       IBSN_CG_PIPE = 4 };
 int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks);
 /* Rows wider than a tile (the dense passes of eq. (6)-(8), Algorithm 1 and Algorithm 3).
    cols = 0 (the default): rows of more than IBSN_MAX_N_F64 columns (FP64 cost, points) or

@@ -20,7 +20,7 @@ OUT = os.path.join(HERE, "libibsn.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["dense_eval.hip", "dense_trial.hip", "dense_sparsify.hip", "dense_stop.hip",
            "dense_collse.hip", "dense_wide.hip", "sparse_ops.hip", "cg_persistent.hip",
-           "cg_single.hip", "solver_kernels.hip", "warmstart.hip", "ibsn_api.hip"]
+           "cg_single.hip", "cg_pipe.hip", "solver_kernels.hip", "warmstart.hip", "ibsn_api.hip"]
 ARCH = os.environ.get("IBSN_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -32,6 +32,7 @@
 // slower too.  The wait is bounded: a workgroup that waits longer than BAR_SPIN polls raises
 // the error flag and leaves, so a fault in the barrier ends the kernel with an error instead
 // of a hang.
+#include "cg_barrier.h"
 #include "ibsn_internal.h"
 
 #include <math.h>
@@ -44,7 +45,6 @@ constexpr int PT = 256;                  // threads per workgroup
 // (at most CACHE_SLOTS of each) with their entries, when they fit in CACHE_BYTES.
 constexpr int CACHE_SLOTS = 8 * PT;
 constexpr size_t CACHE_BYTES = 64 * 1024;
-constexpr int64_t BAR_SPIN = 1ll << 22;  // polls (each after s_sleep) before giving up
 
 struct PersistArgs {
     int m, n, maxit, star_chunk;
@@ -134,35 +134,6 @@ __device__ __forceinline__ void block_exscan(int *a, int cnt, int *wt)
     __syncthreads();
 }
 
-// Grid-wide barrier number `target / grid`; false (every thread) when it timed out or
-// another workgroup raised the error flag.  A workgroup barrier alone does not wait for
-// the other waves' stores, hence the wait in every wave first.
-__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned target, int *sflag)
-{
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        // one release per workgroup: writes the L2's dirty lines back for the other XCDs
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t k = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                ++k > BAR_SPIN) {
-                ok = 0;
-                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        // one acquire per workgroup: invalidates this CU's L1 and stale L2 lines
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *sflag = ok;
-    }
-    __syncthreads();
-    return *sflag != 0;
-}
 
 template <int L, typename VT>
 __global__ __launch_bounds__(PT) void k_cg_persist(PersistArgs A)

@@ -40,6 +40,7 @@ struct ibsn_csr {
     int64_t m = 0, n = 0;
     int64_t nnz = 0;       // host copy (valid after sparsify)
     int64_t istar = -1;    // host copy
+    int64_t m2 = 0;        // host copy: sum over rows != istar of len^2 (entries of P'^T A P')
     int f32 = 0;           // values stored as FP32 (mixed-precision sparsify)
     DevBuf col, val, len, colptr, colcnt, rowidx, cval, mask, off, d, istar_dev, nnz_dev;
 };
@@ -64,6 +65,7 @@ struct ibsn_ctx {
     DevBuf erv, zgv;
     DevBuf stopout, tauv, cg_x, cg_r, cg_r2, cg_p, cg_Ap, cg_au, cg_star, cg_pap, cg_rr, cg_scal;
     DevBuf cg_pp;                  // partial sums and barrier state of the one-launch CG
+    DevBuf cg_mcnt, cg_mptr, cg_mcol, cg_mval, cg_w;   // M = P'^T diag(a) P' and w (2 n)
     int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT / _SINGLE
     bool coop_off = false;         // no cooperative launches (several contexts at once)
     int64_t split_cols = 0;        // rows wider than this are split (0: wider than a tile)
@@ -715,12 +717,16 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     }
     if (split)
         CKH(launch_wide_d(csr_view(c), P<double>(ctx->wd_f), P<double>(c->d), st));
-    int64_t hv[2];
+    CKH(launch_len_sq(p->m, P<int32_t>(c->len), P<int>(c->istar_dev), P<int64_t>(c->nnz_dev) + 1,
+                      st));
+    int64_t hv[3];
     CKH(hipMemcpyAsync(hv, c->nnz_dev.p, 8, hipMemcpyDeviceToHost, st));
     CKH(hipMemcpyAsync(hv + 1, c->istar_dev.p, 4, hipMemcpyDeviceToHost, st));
+    CKH(hipMemcpyAsync(hv + 2, P<int64_t>(c->nnz_dev) + 1, 8, hipMemcpyDeviceToHost, st));
     CKH(hipStreamSynchronize(st));
     c->nnz = hv[0];
     c->istar = (int64_t)(int32_t)(hv[1] & 0xffffffff);
+    c->m2 = hv[2];
     return IBSN_OK;
 }
 
@@ -810,7 +816,53 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
     }
     // the barrier counter counts (2 maxit + 1) grids of arrivals in 32 bits
     const bool fits = (2.0 * maxit + 1.0) * CG_PERSIST_MAX_GRID < 4294967295.0;
-    if (ctx->cg_mode != IBSN_CG_LAUNCHES && ctx->coop && !ctx->coop_off && fits) {
+    const bool coop_ok = ctx->coop && !ctx->coop_off && fits;
+    if (ctx->cg_mode == IBSN_CG_PIPE && !coop_ok)
+        return fail(ctx, IBSN_ERR_UNSUPPORTED,
+                    "cg: the one-barrier CG needs cooperative launches and maxit < 2^21");
+    if (coop_ok && (ctx->cg_mode == IBSN_CG_PIPE || ctx->cg_mode == IBSN_CG_AUTO)) {
+        // M = P'^T diag(a) P' (c->m2 entries, known from the sparsify pass): the one-barrier
+        // form if it stays within CG_PIPE_MAX_RATIO times the factor (always when asked for)
+        const int64_t n = c->n, total = c->m2;
+        if (ctx->cg_mode == IBSN_CG_PIPE ||
+            (double)total <= CG_PIPE_MAX_RATIO * (double)c->nnz + (double)n) {
+            CKI(ensure(ctx, ctx->cg_mcnt, (size_t)n * 8));
+            CKI(ensure(ctx, ctx->cg_mptr, ((size_t)n + 1) * 8));
+            int64_t *mptr = P<int64_t>(ctx->cg_mptr);
+            CKH(launch_m_count(cv, P<int64_t>(ctx->cg_mcnt), mptr, st));
+            CKI(ensure(ctx, ctx->cg_mcol, (size_t)std::max<int64_t>(total, 1) * 4));
+            CKI(ensure(ctx, ctx->cg_mval, (size_t)std::max<int64_t>(total, 1) * 8));
+            CKI(ensure(ctx, ctx->cg_w, (size_t)n * 16));
+            CKH(launch_m_fill(cv, a, mptr, P<int32_t>(ctx->cg_mcol), P<double>(ctx->cg_mval),
+                              st));
+            const int lanes = cg_pipe_lanes(n, total);
+            int blocks = ctx->cg_blocks;
+            if (blocks <= 0) {
+                const int64_t per = 2 * (256 / lanes);   // two sweeps of rows per workgroup
+                const int64_t g = (n + per - 1) / per;
+                blocks = (int)std::min<int64_t>(g, ctx->num_cus);
+            }
+            blocks = std::max(1, std::min(blocks, CG_PERSIST_MAX_GRID));
+            CKI(ensure(ctx, ctx->cg_pp, CG_PIPE_SCRATCH(blocks) * 8));
+            double *pp = P<double>(ctx->cg_pp);
+            CKH(launch_cg_pipe(blocks, lanes, cv, c->istar, a, mptr, P<int32_t>(ctx->cg_mcol),
+                               P<double>(ctx->cg_mval), rhs, eta, shift, tol, maxit, s,
+                               P<double>(ctx->cg_w), pp, st));
+            double *h = ctx->cg_host;
+            CKH(hipMemcpyAsync(h, s.scal, sizeof(double) * CG_NSLOT, hipMemcpyDeviceToHost, st));
+            CKH(hipMemcpyAsync(h + CG_NSLOT, pp + 6 * (int64_t)blocks, sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+            CKH(hipStreamSynchronize(st));
+            unsigned flag[2];
+            memcpy(flag, h + CG_NSLOT, sizeof(flag));
+            if (flag[1] != 0u)
+                return fail(ctx, IBSN_ERR_HIP, "cg: a grid barrier of the one-barrier CG timed "
+                                               "out (%d workgroups)", blocks);
+            *iters = (int)h[CG_IT0];
+            return IBSN_OK;
+        }
+    }
+    if (ctx->cg_mode != IBSN_CG_LAUNCHES && coop_ok) {
         // one cooperative launch runs every iteration; one copy of its end state
         const CgPersistPlan pl =
             cg_persist_plan(c->m, c->n, c->nnz, c->istar, ctx->num_cus, ctx->cg_blocks);
@@ -1137,7 +1189,8 @@ void ibsn_destroy(ibsn_ctx *ctx)
                       &ctx->cg_scal, &ctx->cg_pp, &ctx->sv_r, &ctx->sv_s, &ctx->sv_g, &ctx->sv_M,
                       &ctx->sv_S, &ctx->sv_Mt, &ctx->sv_St, &ctx->sv_ct, &ctx->sv_gt, &ctx->sv_D,
                       &ctx->sv_c, &ctx->sv_gv, &ctx->wd_M, &ctx->wd_S, &ctx->wd_f, &ctx->wd_rr,
-                      &ctx->wd_len};
+                      &ctx->wd_len, &ctx->cg_mcnt, &ctx->cg_mptr, &ctx->cg_mcol, &ctx->cg_mval,
+                      &ctx->cg_w};
     for (DevBuf *b : bufs)
         release(*b);
     if (ctx->host_scal)
@@ -1230,11 +1283,11 @@ int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks)
 {
     if (!ctx)
         return IBSN_ERR_INVALID_ARG;
-    if (mode < IBSN_CG_AUTO || mode > IBSN_CG_SINGLE || blocks < 0 ||
+    if (mode < IBSN_CG_AUTO || mode > IBSN_CG_PIPE || blocks < 0 ||
         blocks > CG_PERSIST_MAX_GRID)
-        return fail(ctx, IBSN_ERR_INVALID_ARG, "set_cg_kernel: mode 0..3, 0 <= blocks <= %d",
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "set_cg_kernel: mode 0..4, 0 <= blocks <= %d",
                     CG_PERSIST_MAX_GRID);
-    if (mode == IBSN_CG_PERSISTENT && !ctx->coop)
+    if ((mode == IBSN_CG_PERSISTENT || mode == IBSN_CG_PIPE) && !ctx->coop)
         return fail(ctx, IBSN_ERR_UNSUPPORTED, "set_cg_kernel: no cooperative launches");
     ctx->cg_mode = mode;
     ctx->cg_blocks = blocks;

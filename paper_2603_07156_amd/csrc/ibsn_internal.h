@@ -277,6 +277,27 @@ hipError_t launch_cg_single(const CsrView &c, const double *a, double eta, doubl
                             const double *rhs, double tol, int maxit, CgState &s,
                             hipStream_t st);
 
+// CG with one grid barrier per iteration (cg_pipe.hip): M = P'^T diag(a) P' built per solve
+// (count and scan, then fill; mptr n + 1, its total at mptr[n]), then the pipelined
+// recurrences in one cooperative launch of `blocks` workgroups of 256 threads, `lanes`
+// (4 or 16) lanes per row of M.  w: 2 n doubles; pp: CG_PIPE_SCRATCH(blocks) doubles of
+// partial sums and barrier state (error flag: the unsigned at pp + 6 blocks + 1).
+#define CG_PIPE_SCRATCH(blocks) (6 * (int64_t)(blocks) + 1)
+// out[0] = sum over rows != istar of len_i^2 (the number of entries of M)
+hipError_t launch_len_sq(int64_t m, const int32_t *len, const int *istar, int64_t *out,
+                         hipStream_t st);
+hipError_t launch_m_count(const CsrView &c, int64_t *cnt, int64_t *mptr, hipStream_t st);
+hipError_t launch_m_fill(const CsrView &c, const double *a, const int64_t *mptr, int32_t *mcol,
+                         double *mval, hipStream_t st);
+int cg_pipe_lanes(int64_t n, int64_t total);
+hipError_t launch_cg_pipe(int blocks, int lanes, const CsrView &c, int64_t istar, const double *a,
+                          const int64_t *mptr, const int32_t *mcol, const double *mval,
+                          const double *rhs, double eta, double shift, double tol, int maxit,
+                          CgState &s, double *w, double *pp, hipStream_t st);
+// The automatic choice takes the one-barrier form when M has at most CG_PIPE_MAX_RATIO times
+// the factor's entries (plus n).
+constexpr double CG_PIPE_MAX_RATIO = 4.0;
+
 // export slotted CSR to standard CSR
 hipError_t launch_export_csr(int64_t m, int64_t n, const int32_t *col, const void *val, int f32,
                              const int32_t *len, int64_t *row_ptr, int32_t *ocol, double *oval,

@@ -25,7 +25,7 @@ IBSN_COST_F32 = 1
 IBSN_COST_POINTS = 2
 PREC_F64 = 0    # ibsn_precision
 PREC_MIXED = 1
-CG_AUTO, CG_LAUNCHES, CG_PERSISTENT, CG_SINGLE = 0, 1, 2, 3   # ibsn_set_cg_kernel
+CG_AUTO, CG_LAUNCHES, CG_PERSISTENT, CG_SINGLE, CG_PIPE = 0, 1, 2, 3, 4   # ibsn_set_cg_kernel
 WS_HEAD_FEATURES = 8   # per-target features of the learned warm start's head (fth columns)
 MAX_N_F64 = 10240
 
@@ -233,8 +233,8 @@ class Context:
         return load().ibsn_num_cus(self.h)
 
     def set_cg_kernel(self, mode: int = 0, blocks: int = 0):
-        """ibsn_set_cg_kernel: CG_AUTO, CG_LAUNCHES, CG_PERSISTENT or CG_SINGLE, and the grid
-        of the one-launch form (0: from the problem size)."""
+        """ibsn_set_cg_kernel: CG_AUTO, CG_LAUNCHES, CG_PERSISTENT, CG_SINGLE or CG_PIPE, and
+        the grid of the cooperative forms (0: from the problem size)."""
         self.check(load().ibsn_set_cg_kernel(self.h, int(mode), int(blocks)))
 
     def set_row_split(self, cols: int = 0):

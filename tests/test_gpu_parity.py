@@ -28,14 +28,26 @@ def ctx(ib):
     return ib.Context(0)
 
 
-@pytest.fixture(params=["launches", "persistent", "single"])
+@pytest.fixture(params=["launches", "persistent", "single", "pipe"])
 def cgctx(request, ib, ctx):
-    """The context with CG run as kernel launches per iteration, in one cooperative launch,
+    """The context with CG run as kernel launches per iteration, in one cooperative launch
+    (two barriers per iteration, or one on P'^T diag(a) P' with the pipelined recurrences),
     or in one workgroup; restored to the default afterwards."""
     ctx.set_cg_kernel({"launches": ib.CG_LAUNCHES, "persistent": ib.CG_PERSISTENT,
-                       "single": ib.CG_SINGLE}[request.param])
+                       "single": ib.CG_SINGLE, "pipe": ib.CG_PIPE}[request.param])
+    ctx.cg_form = request.param
     yield ctx
     ctx.set_cg_kernel(ib.CG_AUTO)
+    ctx.cg_form = None
+
+
+def converged_bound(cgctx):
+    """Bound on |x - x_oracle| / max|x_oracle| for CG converged to 1e-12 ||g||.  The
+    pipelined form updates its residual by a recurrence whose gap to the true residual
+    grows with the iterations (Ghysels and Vanroose 2014, section 3), so its attainable
+    accuracy is lower than standard CG's: measured 3.4e-9 on the 300 x 5000 case.  The
+    solver asks CG for a relative residual of 1e-6 or more."""
+    return 1e-8 if getattr(cgctx, "cg_form", None) == "pipe" else 1e-9
 
 
 def dev(x, dtype=None):
@@ -304,7 +316,8 @@ def test_cg(ib, ctx, cgctx):
     xg, itg = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
     assert itg < 500 and ito < 500
-    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    np.testing.assert_allclose(host(xg), xo, rtol=0,
+                               atol=converged_bound(cgctx) * np.abs(xo).max())
     assert abs(host(xg).sum()) <= 1e-10 * np.abs(xo).max()   # Lemma 4.1
     # maxit is respected and 0 iterations returns x = 0
     x0, it0 = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 0)
@@ -330,7 +343,8 @@ def test_cg_three_kernel_path(ib, ctx, cgctx):
     xg, itg = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), tol, 500)
     xo, ito = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, tol, 500)
     assert itg < 500 and ito < 500
-    np.testing.assert_allclose(host(xg), xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+    np.testing.assert_allclose(host(xg), xo, rtol=0,
+                               atol=converged_bound(cgctx) * np.abs(xo).max())
     # a cap of a few iterations stops both at the same iterate
     x3, it3 = ib.cg(cgctx, gcsr, pr.a, inst.eta, shift, dev(-ev.g), 0.0, 3)
     xo3, ito3 = orc.cg(ocsr, inst.a, inst.eta, shift, -ev.g, 0.0, 3)
@@ -381,7 +395,7 @@ def test_cg_persistent_grid_sizes(ib, ctx, blocks):
 
 def test_cg_kernel_mode_arguments(ib, ctx):
     with pytest.raises(RuntimeError):
-        ctx.set_cg_kernel(4)
+        ctx.set_cg_kernel(5)
     with pytest.raises(RuntimeError):
         ctx.set_cg_kernel(ib.CG_PERSISTENT, 1025)
     ctx.set_cg_kernel(ib.CG_AUTO)
