@@ -23,10 +23,11 @@
 // automatic choice takes this form only when M stays small.
 //
 // The kernel is a cooperative launch of `blocks` workgroups of 256 threads, L lanes per row
-// of M; vectors of a workgroup's own rows (x, r, p, s, z) are touched only by it, w is
-// double-buffered by iteration parity (the product of one iteration reads w_i while the
-// update writes w_{i+1}), and so are the partial sums.  The barrier is the one of
-// cg_persistent.hip (arrival counter, device-scope release and acquire, bounded wait).
+// of M, at most CG_PIPE_MAX_ROWS rows per lane group; the vectors of a workgroup's own rows
+// (x, r, p, s, z, and d, P_* and w) stay in registers and its rows of M in LDS when they
+// fit, since every barrier's acquire drops the caches.  w is published double-buffered by
+// iteration parity (the product of one iteration reads w_i while the update writes
+// w_{i+1}), and so are the partial sums.  The barrier is cg_barrier.h's.
 #include "cg_barrier.h"
 #include "ibsn_internal.h"
 
@@ -195,50 +196,126 @@ __device__ __forceinline__ void grid_sums(const double *part, int G, int par, do
     block_sum3(g0, g1, g2, lds);
 }
 
-// (A v)_j for the row j of M: (d_j v_j - (M v)_j - a_* P_*j zeta) / eta + shift v_j, with the
-// L lanes of the row's group summing (M v)_j; valid in lane 0
-template <int L, typename VT>
-__device__ __forceinline__ double apply_row(const PipeArgs &A, int j, int l, const double *v,
-                                            double as, double zeta)
+// In-place exclusive prefix sum of a[0..cnt) in LDS (cnt <= 8 PT), total into a[cnt];
+// every thread takes 8 consecutive values.  wt: PT/64 ints of LDS.
+__device__ __forceinline__ void block_exscan(int *a, int cnt, int *wt)
 {
-    double sm = 0.0;
-    for (int64_t e = A.mptr[j] + l; e < A.mptr[j + 1]; e += L)
-        sm = fma(A.mval[e], v[A.mcol[e]], sm);
+    const int t = threadIdx.x, base = 8 * t;
+    int loc[8], s = 0;
 #pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1)
-        sm += __shfl_xor(sm, o, L);
-    const double ps = A.prow ? (double)static_cast<const VT *>(A.prow)[j] : 0.0;
-    return (A.d[j] * v[j] - sm - as * ps * zeta) / A.eta + A.shift * v[j];
+    for (int k = 0; k < 8; ++k) {
+        loc[k] = s;
+        s += base + k < cnt ? a[base + k] : 0;
+    }
+    int incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if ((t & 63) >= o)
+            incl += y;
+    }
+    if ((t & 63) == 63)
+        wt[t / 64] = incl;
+    __syncthreads();
+    int excl = incl - s;
+    for (int w = 0; w < t / 64; ++w)
+        excl += wt[w];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (base + k < cnt)
+            a[base + k] = excl + loc[k];
+    if (t == PT - 1)
+        a[cnt] = excl + s;
+    __syncthreads();
 }
 
-template <int L, typename VT>
+// The workgroup's rows j_k = b GPB + q + k G GPB (k < KR) keep x, r, p, s, z, d, P_*j and
+// their own w in registers (lane 0 of the row's lane group uses them), and, when they fit in
+// CACHE_BYTES of LDS, the entries of their rows of M: after each barrier's acquire an
+// iteration then reads from memory only the published w and the partial sums.
+constexpr size_t CACHE_BYTES = 64 * 1024;
+constexpr int CACHE_ROWS = 8 * PT;
+
+template <int L, int KR, typename VT>
 __global__ __launch_bounds__(PT) void k_cg_pipe(PipeArgs A)
 {
     __shared__ double lds[3 * (PT / 64)];
     __shared__ int sflag;
+    __shared__ int wt[PT / 64];
+    extern __shared__ __align__(16) unsigned char dyn[];
     const int G = (int)gridDim.x, b = (int)blockIdx.x, t = (int)threadIdx.x;
     const int n = A.n;
     constexpr int GPB = PT / L;
     const int l = t % L, q = t / L;
-    const int KR = (n + G * GPB - 1) / (G * GPB);
     const VT *prow = static_cast<const VT *>(A.prow);
     const int istar = *A.istar_p;
     const double as = istar >= 0 ? A.a[istar] : 0.0;
     unsigned target = 0;
     double *w0 = A.w, *w1 = A.w + n;
 
+    // rows of M in LDS: row slot r = k GPB + q
+    constexpr int RS = KR * GPB;
+    static_assert(RS <= CACHE_ROWS, "row offsets of the cache");
+    int *roff = reinterpret_cast<int *>(dyn);
+    for (int r = t; r < RS; r += PT) {
+        const int j = b * GPB + (r % GPB) + (r / GPB) * G * GPB;
+        roff[r] = j < n ? (int)(A.mptr[j + 1] - A.mptr[j]) : 0;
+    }
+    __syncthreads();
+    block_exscan(roff, RS, wt);
+    const int TR = roff[RS];
+    const size_t hdr = ((size_t)(RS + 1) * 4 + 15) / 16 * 16;
+    const bool cached = hdr + (size_t)TR * 12 <= CACHE_BYTES;
+    double *mv = reinterpret_cast<double *>(dyn + hdr);
+    int32_t *mc = reinterpret_cast<int32_t *>(dyn + hdr + (size_t)TR * 8);
+    if (cached) {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int r = k * GPB + q, j = b * GPB + q + k * G * GPB;
+            const int o = roff[r], len = roff[r + 1] - o;
+            const int64_t e0 = len > 0 ? A.mptr[j] : 0;
+            for (int e = l; e < len; e += L) {
+                mc[o + e] = A.mcol[e0 + e];
+                mv[o + e] = A.mval[e0 + e];
+            }
+        }
+    }
+    __syncthreads();
+    // (A v)_j for own row k: (d_j v_j - (M v)_j - a_* P_*j zeta) / eta + shift v_j, the L
+    // lanes of the group summing (M v)_j; valid in lane 0
+    auto apply = [&](int k, int j, const double *v, double vj, double dj, double pj_star,
+                     double zeta) -> double {
+        double sm = 0.0;
+        if (cached) {
+            const int r = k * GPB + q;
+            for (int e = roff[r] + l; e < roff[r + 1]; e += L)
+                sm = fma(mv[e], v[mc[e]], sm);
+        } else {
+            for (int64_t e = A.mptr[j] + l; e < A.mptr[j + 1]; e += L)
+                sm = fma(A.mval[e], v[A.mcol[e]], sm);
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1)
+            sm += __shfl_xor(sm, o, L);
+        return (dj * vj - sm - as * pj_star * zeta) / A.eta + A.shift * vj;
+    };
+
+    double rx[KR], rr[KR], rp[KR], rs[KR], rz[KR], rd[KR], rps[KR], rw[KR];
     // x = 0, r = rhs; publish r (in w0) with the partial of P_* . r
     {
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+#pragma unroll
         for (int k = 0; k < KR; ++k) {
             const int j = b * GPB + q + k * G * GPB;
-            if (j < n && l == 0) {
-                const double v = A.rhs[j];
-                A.x[j] = 0.0;
-                A.r[j] = v;
-                w0[j] = v;
-                if (prow)
-                    c2 = fma((double)prow[j], v, c2);
+            rx[k] = rr[k] = rp[k] = rs[k] = rz[k] = rd[k] = rps[k] = rw[k] = 0.0;
+            if (j < n) {
+                rr[k] = A.rhs[j];
+                rd[k] = A.d[j];
+                rps[k] = prow ? (double)prow[j] : 0.0;
+                if (l == 0) {
+                    w0[j] = rr[k];
+                    c2 = fma(rps[k], rr[k], c2);
+                }
             }
         }
         block_sum3(c0, c1, c2, lds);
@@ -257,18 +334,17 @@ __global__ __launch_bounds__(PT) void k_cg_pipe(PipeArgs A)
         double g0, g1, zeta;
         grid_sums(A.part, G, 0, g0, g1, zeta, lds);
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+#pragma unroll
         for (int k = 0; k < KR; ++k) {
             const int j = b * GPB + q + k * G * GPB;
             if (j >= n)
                 continue;
-            const double wj = apply_row<L, VT>(A, j, l, w0, as, zeta);
+            rw[k] = apply(k, j, w0, rr[k], rd[k], rps[k], zeta);
             if (l == 0) {
-                const double rj = A.r[j];
-                w1[j] = wj;
-                c0 = fma(rj, rj, c0);
-                c1 = fma(wj, rj, c1);
-                if (prow)
-                    c2 = fma((double)prow[j], wj, c2);
+                w1[j] = rw[k];
+                c0 = fma(rr[k], rr[k], c0);
+                c1 = fma(rw[k], rr[k], c1);
+                c2 = fma(rps[k], rw[k], c2);
             }
         }
         block_sum3(c0, c1, c2, lds);
@@ -290,9 +366,9 @@ __global__ __launch_bounds__(PT) void k_cg_pipe(PipeArgs A)
     bool brk = false;
     double gam = 0.0;
     for (;; ++it) {
-        const int rd = (it + 1) & 1, wr = it & 1;
+        const int rd_ = (it + 1) & 1, wr = it & 1;
         double delta, zeta;
-        grid_sums(A.part, G, rd, gam, delta, zeta, lds);
+        grid_sums(A.part, G, rd_, gam, delta, zeta, lds);
         if (!(sqrt(gam) > A.tol) || it >= A.maxit)
             break;
         const double beta = it == 0 ? 0.0 : gam / gamma_old;
@@ -302,31 +378,26 @@ __global__ __launch_bounds__(PT) void k_cg_pipe(PipeArgs A)
             break;
         }
         const double alpha = gam / den;
-        const double *wi = rd ? w1 : w0;
+        const double *wi = rd_ ? w1 : w0;
         double *wn = wr ? w1 : w0;
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+#pragma unroll
         for (int k = 0; k < KR; ++k) {
             const int j = b * GPB + q + k * G * GPB;
             if (j >= n)
                 continue;
-            const double nj = apply_row<L, VT>(A, j, l, wi, as, zeta);
+            const double nj = apply(k, j, wi, rw[k], rd[k], rps[k], zeta);
+            rz[k] = it == 0 ? nj : fma(beta, rz[k], nj);
+            rs[k] = it == 0 ? rw[k] : fma(beta, rs[k], rw[k]);
+            rp[k] = it == 0 ? rr[k] : fma(beta, rp[k], rr[k]);
+            rx[k] = fma(alpha, rp[k], rx[k]);
+            rr[k] = fma(-alpha, rs[k], rr[k]);
+            rw[k] = fma(-alpha, rz[k], rw[k]);
             if (l == 0) {
-                const double wj = wi[j];
-                const double zj = it == 0 ? nj : fma(beta, A.z[j], nj);
-                const double sj = it == 0 ? wj : fma(beta, A.s[j], wj);
-                const double pj = it == 0 ? A.r[j] : fma(beta, A.p[j], A.r[j]);
-                A.z[j] = zj;
-                A.s[j] = sj;
-                A.p[j] = pj;
-                A.x[j] = fma(alpha, pj, A.x[j]);
-                const double rj = fma(-alpha, sj, A.r[j]);
-                A.r[j] = rj;
-                const double wnj = fma(-alpha, zj, wj);
-                wn[j] = wnj;
-                c0 = fma(rj, rj, c0);
-                c1 = fma(wnj, rj, c1);
-                if (prow)
-                    c2 = fma((double)prow[j], wnj, c2);
+                wn[j] = rw[k];
+                c0 = fma(rr[k], rr[k], c0);
+                c1 = fma(rw[k], rr[k], c1);
+                c2 = fma(rps[k], rw[k], c2);
             }
         }
         block_sum3(c0, c1, c2, lds);
@@ -342,6 +413,14 @@ __global__ __launch_bounds__(PT) void k_cg_pipe(PipeArgs A)
         if (!grid_barrier(A.bar, target, &sflag))
             return;
     }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int j = b * GPB + q + k * G * GPB;
+        if (j < n && l == 0) {
+            A.x[j] = rx[k];
+            A.r[j] = rr[k];
+        }
+    }
     if (b == 0 && t == 0) {
         A.scal[CG_IT0] = (double)it;
         A.scal[CG_RR0] = gam;
@@ -356,12 +435,24 @@ __global__ void k_pipe_reset(unsigned *bar)
     bar[1] = 0u;
 }
 
-template <int L, typename VT>
+template <int L, int KR, typename VT>
 hipError_t launch_l(int grid, PipeArgs &A, hipStream_t st)
 {
     void *args[] = {&A};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_pipe<L, VT>),
-                                      dim3((unsigned)grid), dim3(PT), args, 0, st);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_pipe<L, KR, VT>),
+                                      dim3((unsigned)grid), dim3(PT), args, CACHE_BYTES, st);
+}
+
+template <int L, typename VT>
+hipError_t launch_kr(int grid, int kr, PipeArgs &A, hipStream_t st)
+{
+    if (kr <= 1)
+        return launch_l<L, 1, VT>(grid, A, st);
+    if (kr <= 2)
+        return launch_l<L, 2, VT>(grid, A, st);
+    if (kr <= 4)
+        return launch_l<L, 4, VT>(grid, A, st);
+    return launch_l<L, CG_PIPE_MAX_ROWS, VT>(grid, A, st);
 }
 
 }  // namespace
@@ -394,6 +485,12 @@ hipError_t launch_m_fill(const CsrView &c, const double *a, const int64_t *mptr,
                            (const double *)c.cval, c.col, (const double *)c.val, c.len, a, mptr,
                            mcol, mval);
     return hipGetLastError();
+}
+
+int cg_pipe_rows(int64_t n, int blocks, int lanes)
+{
+    const int64_t per = (int64_t)blocks * (PT / lanes);
+    return (int)((n + per - 1) / per);
 }
 
 int cg_pipe_lanes(int64_t n, int64_t total)
@@ -433,10 +530,15 @@ hipError_t launch_cg_pipe(int blocks, int lanes, const CsrView &c, int64_t istar
     A.part = pp;
     A.scal = s.scal;
     A.bar = reinterpret_cast<unsigned *>(pp + 6 * (int64_t)blocks);
+    const int kr = cg_pipe_rows(c.n, blocks, lanes);
+    if (kr > CG_PIPE_MAX_ROWS)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pipe_reset, dim3(1), dim3(1), 0, st, A.bar);
     if (c.f32)
-        return lanes == 16 ? launch_l<16, float>(blocks, A, st) : launch_l<4, float>(blocks, A, st);
-    return lanes == 16 ? launch_l<16, double>(blocks, A, st) : launch_l<4, double>(blocks, A, st);
+        return lanes == 16 ? launch_kr<16, float>(blocks, kr, A, st)
+                           : launch_kr<4, float>(blocks, kr, A, st);
+    return lanes == 16 ? launch_kr<16, double>(blocks, kr, A, st)
+                       : launch_kr<4, double>(blocks, kr, A, st);
 }
 
 }  // namespace ibsn

@@ -824,8 +824,21 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
         // M = P'^T diag(a) P' (c->m2 entries, known from the sparsify pass): the one-barrier
         // form if it stays within CG_PIPE_MAX_RATIO times the factor (always when asked for)
         const int64_t n = c->n, total = c->m2;
-        if (ctx->cg_mode == IBSN_CG_PIPE ||
-            (double)total <= CG_PIPE_MAX_RATIO * (double)c->nnz + (double)n) {
+        const int lanes = cg_pipe_lanes(n, total);
+        int blocks = ctx->cg_blocks;
+        if (blocks <= 0) {
+            const int64_t per = 2 * (256 / lanes);   // two sweeps of rows per workgroup
+            const int64_t g = (n + per - 1) / per;
+            blocks = (int)std::min<int64_t>(g, ctx->num_cus);
+        }
+        blocks = std::max(1, std::min(blocks, CG_PERSIST_MAX_GRID));
+        const bool rows_fit = cg_pipe_rows(n, blocks, lanes) <= CG_PIPE_MAX_ROWS;
+        if (ctx->cg_mode == IBSN_CG_PIPE && !rows_fit)
+            return fail(ctx, IBSN_ERR_UNSUPPORTED, "cg: the one-barrier CG takes at most %d "
+                        "rows per lane group (n=%lld on %d workgroups)", CG_PIPE_MAX_ROWS,
+                        (long long)n, blocks);
+        if (rows_fit && (ctx->cg_mode == IBSN_CG_PIPE ||
+                         (double)total <= CG_PIPE_MAX_RATIO * (double)c->nnz + (double)n)) {
             CKI(ensure(ctx, ctx->cg_mcnt, (size_t)n * 8));
             CKI(ensure(ctx, ctx->cg_mptr, ((size_t)n + 1) * 8));
             int64_t *mptr = P<int64_t>(ctx->cg_mptr);
@@ -835,14 +848,6 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
             CKI(ensure(ctx, ctx->cg_w, (size_t)n * 16));
             CKH(launch_m_fill(cv, a, mptr, P<int32_t>(ctx->cg_mcol), P<double>(ctx->cg_mval),
                               st));
-            const int lanes = cg_pipe_lanes(n, total);
-            int blocks = ctx->cg_blocks;
-            if (blocks <= 0) {
-                const int64_t per = 2 * (256 / lanes);   // two sweeps of rows per workgroup
-                const int64_t g = (n + per - 1) / per;
-                blocks = (int)std::min<int64_t>(g, ctx->num_cus);
-            }
-            blocks = std::max(1, std::min(blocks, CG_PERSIST_MAX_GRID));
             CKI(ensure(ctx, ctx->cg_pp, CG_PIPE_SCRATCH(blocks) * 8));
             double *pp = P<double>(ctx->cg_pp);
             CKH(launch_cg_pipe(blocks, lanes, cv, c->istar, a, mptr, P<int32_t>(ctx->cg_mcol),

@@ -290,6 +290,9 @@ hipError_t launch_m_count(const CsrView &c, int64_t *cnt, int64_t *mptr, hipStre
 hipError_t launch_m_fill(const CsrView &c, const double *a, const int64_t *mptr, int32_t *mcol,
                          double *mval, hipStream_t st);
 int cg_pipe_lanes(int64_t n, int64_t total);
+// rows of M per lane group for a grid; at most CG_PIPE_MAX_ROWS (held in registers)
+constexpr int CG_PIPE_MAX_ROWS = 8;
+int cg_pipe_rows(int64_t n, int blocks, int lanes);
 hipError_t launch_cg_pipe(int blocks, int lanes, const CsrView &c, int64_t istar, const double *a,
                           const int64_t *mptr, const int32_t *mcol, const double *mval,
                           const double *rhs, double eta, double shift, double tol, int maxit,
