@@ -67,7 +67,9 @@ def cg_roofline(m: int, n: int, rep: dict, kt: dict):
     transpose (int32 row + FP64 value), i.e. 24 bytes per stored entry outside the dense
     row, 8 bytes per dense-row entry read twice, plus the n- and m-vectors they read and
     write (8 (6n + 2m) bytes).  Time per iteration from the CG solves' HIP events (host
-    polling between chunks of iterations included)."""
+    polling between chunks of iterations included), in the form the automatic choice took
+    for each solve (late in a solve one barrier per iteration on P'^T diag(a) P', whose
+    entries stay in LDS; the bytes above are those of the two-hop product)."""
     iters = rep["cg"]
     if not iters or not kt.get("cg", (0, 0))[1]:
         return None
@@ -79,7 +81,8 @@ def cg_roofline(m: int, n: int, rep: dict, kt: dict):
     counters = probe_cg.read_traffic(CG_TRAFFIC_MD)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "CG iteration (row gather + column gather + update)",
+            "kernel": "CG iteration (automatic form: one barrier on P'^T diag(a) P' late in "
+                      "a solve, two on the row and column gathers before)",
             "bytes_per_iteration": per_iter, "ms_per_iteration": ms_per_iter,
             "nnz_mean": nnz,
             # HBM counters of the three-launch form at a late state of this instance (the
