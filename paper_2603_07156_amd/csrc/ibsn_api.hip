@@ -1908,6 +1908,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         }
         R.t_eval += now_s() - ta;
         bool stopped = false;
+        bool tested = false;   // stop_h holds the stop pass at the current iterate
         int stalls = 0;
         for (int v = 0; v < opt.max_newton; ++v) {
             if (state_mx && (fp64_lock || ctx->host_scal[SC_GN] < mx_thr))
@@ -1988,6 +1989,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
             std::swap(c, ct);
             std::swap(g, gt);
             state_mx = mxs != 0;
+            tested = false;
             ++R.newton;
             R.t_linesearch += now_s() - ta;
             // step 12 with the practical schedule: gradient gate, then D_phi test (on an
@@ -2004,6 +2006,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
                                     st));
                 CKSH(hipStreamSynchronize(st));
                 R.t_stop += now_s() - ta;
+                tested = true;
                 if (stop_h[0] <= (double)std::min(m, n) * mu) {
                     stopped = true;
                     break;
@@ -2015,7 +2018,10 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
         if (state_mx)
             CKS(refresh());
         CKSH(sk_gamma_of(n, eta, w, wlo, s, gamma, st));
-        if (!stopped || opt.eot) {
+        // the certificate at the final iterate; when the inner loop ended on a failed test
+        // (the stall rule, or a line search that found no step after it) the test already
+        // computed it at this iterate
+        if ((!stopped && !tested) || opt.eot) {
             ta = now_s();
             CKS(run_stop(ctx, prob, rp, k, q, gamma, M, S, nullptr, c));
             R.passes += 2;
