@@ -346,7 +346,7 @@ typedef struct {
     double cg_forcing_max;               /* CG stops at ||r|| <= max(min(0.1, ||g||), */
     int32_t rho_mode;                    /*   cg_rtol_min) ||g||; rho_mode 0: rho =       */
     double cg_rtol_min;                  /*   eta ||g|| / (m n), 1: rho = 0; 1e-6          */
-    int32_t stall_limit;                 /* 3: failed D_phi tests (gate passed) that end   */
+    int32_t stall_limit;                 /* 1: failed D_phi tests (gate passed) that end   */
                                          /*    the inner loop of one outer iteration       */
     int32_t eot;                         /* 1: (E)IBSN of appendix C.4: prox centre 1 1^T,  */
     double eot_tol;                      /*    one subproblem until ||g|| < eot_tol (1e-9) */

@@ -793,7 +793,7 @@ typedef struct {
     double cg_forcing_max;            /* 0.1 */
     int rho_mode;                     /* 0 paper rule, 1 rho = 0 (no sparsification) */
     double cg_rtol_min;               /* 1e-6: floor of the CG relative residual */
-    int stall_limit;                  /* 3 failed D_phi tests after the gate end the inner loop */
+    int stall_limit;                  /* 1 failed D_phi test after the gate ends the inner loop */
     int eot;                          /* 1: (E)IBSN of appendix C.4: centre 1 1^T, one subproblem */
     double eot_tol;                   /* (E)IBSN stops at ||g|| < eot_tol (1e-9, appendix C.4) */
     int armijo_warm;                  /* 1: each line search starts at min(1, t_prev / beta),
@@ -824,7 +824,7 @@ void orc_default_options(orc_options *o)
     o->cg_forcing_max = 0.1;
     o->rho_mode = 0;
     o->cg_rtol_min = 1e-6;
-    o->stall_limit = 3;
+    o->stall_limit = 1;
     o->eot = 0;
     o->eot_tol = 1e-9;
     o->armijo_warm = 1;

@@ -1330,7 +1330,7 @@ void ibsn_default_options(ibsn_options *o)
     o->cg_forcing_max = 0.1;
     o->rho_mode = 0;
     o->cg_rtol_min = 1e-6;
-    o->stall_limit = 3;
+    o->stall_limit = 1;
     o->eot = 0;
     o->eot_tol = 1e-9;
     o->mixed_switch = 64.0;
