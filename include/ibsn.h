@@ -342,7 +342,7 @@ typedef struct {
     int32_t sinkhorn_maxit;              /* 10000 */
     double mu0, mu_floor;                /* mu_k = max(mu0/(k+1)^2, mu_floor): 1e-4, 1e-11 */
     double gap_tol, marg_tol, kkt_tol;   /* 1e-8 relative gap, 1e-9 ||X^T1-b||_1, 0 = off */
-    int32_t max_outer, max_newton, max_backtrack, cg_maxit; /* 300, 1000, 60, 0 = min(n,100) */
+    int32_t max_outer, max_newton, max_backtrack, cg_maxit; /* 300, 1000, 60, 0 = min(n,70) */
     double cg_forcing_max;               /* CG stops at ||r|| <= max(min(0.1, ||g||), */
     int32_t rho_mode;                    /*   cg_rtol_min) ||g||; rho_mode 0: rho =       */
     double cg_rtol_min;                  /*   eta ||g|| / (m n), 1: rho = 0; 1e-6          */

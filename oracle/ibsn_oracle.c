@@ -789,7 +789,7 @@ typedef struct {
     int sinkhorn_maxit;               /* 10000 */
     double mu0, mu_floor;             /* 1e-4, 1e-11 */
     double gap_tol, marg_tol, kkt_tol; /* 1e-8, 1e-9, 0 (off) */
-    int max_outer, max_newton, max_backtrack, cg_maxit; /* cg_maxit <= 0 -> min(n, 100) */
+    int max_outer, max_newton, max_backtrack, cg_maxit; /* cg_maxit <= 0 -> min(n, 70) */
     double cg_forcing_max;            /* 0.1 */
     int rho_mode;                     /* 0 paper rule, 1 rho = 0 (no sparsification) */
     double cg_rtol_min;               /* 1e-6: floor of the CG relative residual */
@@ -872,7 +872,7 @@ int orc_solve(int64_t m, int64_t n, const void *C, int kind, int64_t ldc, const 
         opt = *opt_in;
     else
         orc_default_options(&opt);
-    int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)(n < 100 ? n : 100);
+    int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)(n < 70 ? n : 70);
 
     double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * n);
     double *gamma = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);

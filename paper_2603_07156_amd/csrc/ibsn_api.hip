@@ -1692,7 +1692,7 @@ int ibsn_solve(ibsn_ctx *ctx, const ibsn_problem *prob, const ibsn_options *opt_
     RowPlan rp;
     CKI(plan_for(ctx, prob, &rp));
     CKI(ensure_ws(ctx, prob, rp));
-    const int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)std::min<int64_t>(n, 100);
+    const int cg_maxit = opt.cg_maxit > 0 ? opt.cg_maxit : (int)std::min<int64_t>(n, 70);
 
     // solver state buffers (context-owned, grow-only: no allocation once warm)
     DevBuf &rB = ctx->sv_r, &sB = ctx->sv_s, &gB = ctx->sv_g, &MB = ctx->sv_M, &SB = ctx->sv_S,
