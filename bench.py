@@ -155,12 +155,15 @@ def kt_dict(kt):
             for k, v in kt.items() if v[1]}
 
 
-def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0_fn=None):
+def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0_fn=None,
+                 problem=None):
     """Wall time from X^0 to a certified relative gap <= `gap`, starting the first
-    subproblem from gamma = 0 or from gamma0_fn() (called inside the timed region)."""
+    subproblem from gamma = 0 or from gamma0_fn() (called inside the timed region).
+    `problem`: a prepared problem to solve instead of prob's stored cost in `precision`."""
     import torch
 
-    pr = ibsn.Problem(prob.C, prob.a, prob.b, prob.eta, precision=precision)
+    pr = problem if problem is not None else ibsn.Problem(prob.C, prob.a, prob.b, prob.eta,
+                                                          precision=precision)
     opt = ibsn.default_options(max_outer=max_outer, gap_tol=gap, marg_tol=0.0)
     ctx.kernel_timing(True)
     torch.cuda.synchronize()
@@ -193,6 +196,20 @@ def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0_f
             "t_eval": rep["t_eval"], "t_sparsify": rep["t_sparsify"], "t_cg": rep["t_cg"],
             "t_linesearch": rep["t_linesearch"], "t_stop": rep["t_stop"],
             "kernel_ms": kt_dict(kt)}
+
+
+def points_problem(ibsn, inst, prob, precision):
+    """The same instance with its cost formed from the points in every pass (no m x n
+    array): C_ij = scale |x_i - y_j|^2 with scale = 1 / max, the stored cost to rounding."""
+    import numpy as np
+    import torch
+
+    from paper_2603_07156_amd import workloads
+    dev = prob.C.device
+    x = torch.from_numpy(np.ascontiguousarray(inst.x)).to(dev)
+    y = torch.from_numpy(np.ascontiguousarray(inst.y)).to(dev)
+    return ibsn.Problem.from_points(x, y, prob.a, prob.b, prob.eta,
+                                    workloads.points_scale(inst.x, inst.y), precision)
 
 
 def warm_start_fn(ibsn, ctx, prob, inst):
@@ -502,6 +519,18 @@ def main() -> int:
             ttg["warm_mixed_fp32"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_MIXED, gamma0_fn=fn)
             ttg["warm_mixed_over_plain_time"] = (ttg["warm_mixed_fp32"]["seconds"]
                                                  / ttg["plain_f64"]["seconds"])
+            # the FP32 form with the cost formed from the points: no 800 MB FP64 stream
+            pts = points_problem(ibsn, inst, prob, ibsn.PREC_MIXED)
+            fn_pts, held_pts = warm_start_fn(ibsn, ctx, pts, inst)
+            ttg["warm_mixed_fp32_points"] = solve_to_gap(ibsn, ctx, prob, ibsn.PREC_MIXED,
+                                                         gamma0_fn=fn_pts, problem=pts)
+            ttg["warm_mixed_fp32_points"]["cost"] = ("formed from the points in every pass "
+                                                     "(scale = 1 / max |x_i - y_j|^2)")
+            ttg["warm_f64_points"] = solve_to_gap(
+                ibsn, ctx, prob, ibsn.PREC_F64, gamma0_fn=fn_pts,
+                problem=points_problem(ibsn, inst, prob, ibsn.PREC_F64))
+            ttg["warm_f64_points"]["cost"] = ttg["warm_mixed_fp32_points"]["cost"]
+            held_pts[0].free()
             held[0].free()
         out["time_to_1e-8_gap"] = ttg
         mk = ttg["mixed_fp32"]["kernel_ms"].get("eval_mixed")
