@@ -837,7 +837,11 @@ int run_cg(ibsn_ctx *ctx, const ibsn_csr *c, const double *a, double eta, double
             return fail(ctx, IBSN_ERR_UNSUPPORTED, "cg: the one-barrier CG takes at most %d "
                         "rows per lane group (n=%lld on %d workgroups)", CG_PIPE_MAX_ROWS,
                         (long long)n, blocks);
-        if (rows_fit && (ctx->cg_mode == IBSN_CG_PIPE ||
+        // a workgroup's entry offsets into M are 32-bit
+        if (ctx->cg_mode == IBSN_CG_PIPE && total > (int64_t)INT32_MAX)
+            return fail(ctx, IBSN_ERR_UNSUPPORTED, "cg: the one-barrier CG holds at most "
+                        "2^31 - 1 entries of P'^T diag(a) P' (%lld here)", (long long)total);
+        if (rows_fit && total <= (int64_t)INT32_MAX && (ctx->cg_mode == IBSN_CG_PIPE ||
                          (double)total <= CG_PIPE_MAX_RATIO * (double)c->nnz + (double)n)) {
             CKI(ensure(ctx, ctx->cg_mcnt, (size_t)n * 8));
             CKI(ensure(ctx, ctx->cg_mptr, ((size_t)n + 1) * 8));
