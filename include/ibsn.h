@@ -110,6 +110,15 @@ int ibsn_set_cg_kernel(ibsn_ctx *ctx, int mode, int blocks);
    equal the whole-row passes to rounding.  ibsn_autotune refuses split problems.
    IBSN_ERR_INVALID_ARG for another cols. */
 int ibsn_set_row_split(ibsn_ctx *ctx, int64_t cols);
+/* The transpose of the sparsified factor (Algorithm 1's P_rho, read by the column products
+   of Algorithm 2, step 8) is written by one of two fills with the same result, bit for bit:
+   IBSN_CSC_ENTRY scatters entry by entry; IBSN_CSC_BLOCK stages blocks of 32 rows by column
+   tiles in LDS and writes each column's entries of the block as one contiguous run.
+   IBSN_CSC_AUTO (the default) takes the block fill once the factor stores at least m n / 32
+   entries, decided on the device from the entry count.  IBSN_ERR_INVALID_ARG for another
+   mode. */
+enum { IBSN_CSC_AUTO = 0, IBSN_CSC_ENTRY = 1, IBSN_CSC_BLOCK = 2 };
+int ibsn_set_csc_fill(ibsn_ctx *ctx, int mode);
 
 typedef enum { IBSN_COST_F64 = 0, IBSN_COST_F32 = 1, IBSN_COST_POINTS = 2 } ibsn_cost_kind;
 

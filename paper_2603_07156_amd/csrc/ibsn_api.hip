@@ -69,6 +69,7 @@ struct ibsn_ctx {
     int cg_mode = 0;               // IBSN_CG_AUTO / _LAUNCHES / _PERSISTENT / _SINGLE
     bool coop_off = false;         // no cooperative launches (several contexts at once)
     int64_t split_cols = 0;        // rows wider than this are split (0: wider than a tile)
+    int csc_fill = IBSN_CSC_AUTO;  // fill of the transpose (ibsn_set_csc_fill)
     DevBuf wd_M, wd_S, wd_f, wd_rr, wd_len;   // per-block row arrays of split rows
     struct Tuned {                 // plans chosen by ibsn_autotune, per problem shape
         int64_t m, n;
@@ -709,6 +710,7 @@ int run_sparsify(ibsn_ctx *ctx, const ibsn_problem *p, const RowPlan &rp, int64_
     cw.off = P<int32_t>(c->off);
     // lanes per row of the fill from the previous factor's mean row length (64 at first)
     cw.lpc = (c->nnz > 0 && (double)c->nnz / (double)c->m < 96.0) ? 16 : 64;
+    cw.fill = ctx->csc_fill;
     {
         KTimer kt(ctx, IBSN_KT_CSC);
         CKH(launch_build_csc(p->m, p->n, P<int32_t>(c->col), c->val.p, c->f32,
@@ -1311,6 +1313,20 @@ int ibsn_set_row_split(ibsn_ctx *ctx, int64_t cols)
         return fail(ctx, IBSN_ERR_INVALID_ARG,
                     "set_row_split: 0, or a multiple of 64 in [256, %d]", IBSN_MAX_N_F64);
     ctx->split_cols = cols;
+    return IBSN_OK;
+}
+
+int ibsn_set_csc_fill(ibsn_ctx *ctx, int mode)
+{
+    static_assert(IBSN_CSC_AUTO == CSC_FILL_AUTO && IBSN_CSC_ENTRY == CSC_FILL_ENTRY &&
+                      IBSN_CSC_BLOCK == CSC_FILL_BLOCK,
+                  "fill modes of the ABI and the kernels");
+    if (!ctx)
+        return IBSN_ERR_INVALID_ARG;
+    if (mode != IBSN_CSC_AUTO && mode != IBSN_CSC_ENTRY && mode != IBSN_CSC_BLOCK)
+        return fail(ctx, IBSN_ERR_INVALID_ARG, "set_csc_fill: IBSN_CSC_AUTO, IBSN_CSC_ENTRY or "
+                                               "IBSN_CSC_BLOCK");
+    ctx->csc_fill = mode;
     return IBSN_OK;
 }
 

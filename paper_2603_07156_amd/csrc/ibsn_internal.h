@@ -177,7 +177,12 @@ struct CscWork {
     uint32_t *mask;      // csc_row_blocks(m) * n: rows of a 32-row block keeping column j
     int32_t *off;        // csc_row_blocks(m) * n: exclusive scan of the mask popcounts
     int lpc;             // lanes per row of the fill (16 or 64)
+    int fill = 0;        // CSC_FILL_AUTO, CSC_FILL_ENTRY or CSC_FILL_BLOCK
 };
+// the transpose's fill: chosen on the device from the stored entries (from
+// CSC_BLOCK_MIN_DENSITY m n on by row block), or forced
+enum { CSC_FILL_AUTO = 0, CSC_FILL_ENTRY = 1, CSC_FILL_BLOCK = 2 };
+constexpr double CSC_BLOCK_MIN_DENSITY = 1.0 / 32.0;
 // number of 32-row blocks of the transpose
 int csc_row_blocks(int64_t m);
 // transpose of the slotted rows without the dense row istar (device scalar)

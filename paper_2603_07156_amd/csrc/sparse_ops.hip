@@ -209,7 +209,16 @@ __global__ __launch_bounds__(1024) void k_scan32(int n, const int32_t *__restric
     }
 }
 
-// fill: LPC lanes per row, every entry independently (see the position formula above)
+// Two fills write the same transpose (the position formula above); the factor's stored
+// entries, known on the device once the column pointers are scanned, choose between them:
+// one entry at a time while the factor is sparse, by row block from big_at entries on
+// (CSC_FILL_ENTRY or CSC_FILL_BLOCK force one).  Both are launched; the other returns.
+__device__ __forceinline__ bool csc_by_block(int mode, int64_t total, int64_t big_at)
+{
+    return mode == CSC_FILL_BLOCK || (mode == CSC_FILL_AUTO && total >= big_at);
+}
+
+// fill: LPC lanes per row, every entry independently
 template <int LPC, typename VT>
 __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *__restrict__ col,
                                                   const VT *__restrict__ val,
@@ -218,9 +227,13 @@ __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *_
                                                   const int64_t *__restrict__ colptr,
                                                   const uint32_t *__restrict__ mask,
                                                   const int32_t *__restrict__ off,
+                                                  const int64_t *__restrict__ total,
+                                                  int64_t big_at, int mode,
                                                   int32_t *__restrict__ rowidx,
                                                   VT *__restrict__ cval)
 {
+    if (csc_by_block(mode, *total, big_at))
+        return;
     const int i = (blockIdx.x * 256 + threadIdx.x) / LPC;
     const int l = threadIdx.x % LPC;
     if (i >= m || i == *istar_p)
@@ -237,6 +250,89 @@ __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *_
         const int64_t pos = colptr[j] + ob[j] + __popc(mb[j] & below);
         rowidx[pos] = i;
         cval[pos] = vr[e];
+    }
+}
+
+// fill by row block, for factors with many entries per row: one workgroup per block of
+// CSC_RB rows, the columns in tiles of CSC_TILE.  Each row's entries in the tile (a run of
+// its ascending slot, from a cursor kept per row) are staged in LDS at (column, row); then
+// thread (c, r) writes the entry of row r in column j0 + c, if the row keeps it, so that
+// the block's entries of a column go out as one contiguous run where the per-entry fill
+// scatters them one by one.  Wave w stages rows w CSC_RPW .. w CSC_RPW + CSC_RPW - 1, all
+// of their windows of WAVE entries loaded before any is used.
+constexpr int CSC_TILE = 256;
+constexpr int CSC_RPW = CSC_RB / (256 / WAVE);
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_csc_fill_block(int m, int n,
+                                                        const int32_t *__restrict__ col,
+                                                        const VT *__restrict__ val,
+                                                        const int32_t *__restrict__ len,
+                                                        const int *__restrict__ istar_p,
+                                                        const int64_t *__restrict__ colptr,
+                                                        const uint32_t *__restrict__ mask,
+                                                        const int32_t *__restrict__ off,
+                                                        const int64_t *__restrict__ total,
+                                                        int64_t big_at, int mode,
+                                                        int32_t *__restrict__ rowidx,
+                                                        VT *__restrict__ cval)
+{
+    if (!csc_by_block(mode, *total, big_at))
+        return;
+    extern __shared__ __align__(16) unsigned char csc_lds[];
+    VT *tile = reinterpret_cast<VT *>(csc_lds);   // [column in tile][row in block]
+    const int b = blockIdx.x, i0 = b * CSC_RB;
+    const int istar = *istar_p;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int rw0 = wv * CSC_RPW;   // the wave's first row in the block
+    const uint32_t *mb = mask + (int64_t)b * n;
+    const int32_t *ob = off + (int64_t)b * n;
+    // per row: entries consumed so far (all with columns below the current tile) and length;
+    // the same in every lane
+    int cur[CSC_RPW], rl[CSC_RPW];
+#pragma unroll
+    for (int k = 0; k < CSC_RPW; ++k) {
+        const int i = i0 + rw0 + k;
+        cur[k] = 0;
+        rl[k] = (i < m && i != istar) ? len[i] : 0;
+    }
+    const int r = threadIdx.x % CSC_RB;
+    const uint32_t below = (1u << r) - 1u;
+    for (int j0 = 0; j0 < n; j0 += CSC_TILE) {
+        const int j1 = min(n, j0 + CSC_TILE);
+        // stage: the entries with columns in [j0, j1) are a prefix of each row's remainder
+        bool more = true;
+        while (more) {
+            more = false;
+            int cj[CSC_RPW];
+#pragma unroll
+            for (int k = 0; k < CSC_RPW; ++k) {
+                const int e = cur[k] + lane;
+                cj[k] = e < rl[k] ? col[(int64_t)(i0 + rw0 + k) * n + e] : n;
+            }
+#pragma unroll
+            for (int k = 0; k < CSC_RPW; ++k) {
+                const bool in = cj[k] < j1;
+                if (in)
+                    tile[(cj[k] - j0) * CSC_RB + rw0 + k] =
+                        val[(int64_t)(i0 + rw0 + k) * n + cur[k] + lane];
+                const int cnt = (int)__popcll(__ballot(in));
+                cur[k] += cnt;
+                more |= cnt == WAVE;
+            }
+        }
+        __syncthreads();
+        // write: 256 / CSC_RB columns per pass, the rows of a column in consecutive lanes
+        for (int c = threadIdx.x / CSC_RB; c < j1 - j0; c += 256 / CSC_RB) {
+            const int j = j0 + c;
+            const uint32_t mk = mb[j];
+            if ((mk >> r) & 1u) {
+                const int64_t pos = colptr[j] + ob[j] + __popc(mk & below);
+                rowidx[pos] = i0 + r;
+                cval[pos] = tile[c * CSC_RB + r];
+            }
+        }
+        __syncthreads();   // the tile is staged again
     }
 }
 
@@ -994,21 +1090,37 @@ hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const void
                        istar);
     const int lpc = w.lpc;
     const unsigned blocks = (unsigned)((m * lpc + 255) / 256);
+    const int64_t big_at = std::max<int64_t>(1, (int64_t)(CSC_BLOCK_MIN_DENSITY * (double)m *
+                                                          (double)n));
 #define FILL(L_, VT_)                                                                          \
     hipLaunchKernelGGL((k_csc_fill<L_, VT_>), dim3(blocks), dim3(256), 0, st, (int)m, (int)n, col, \
-                       (const VT_ *)val, len, istar, w.colptr, w.mask, w.off, w.rowidx,           \
-                       (VT_ *)w.cval)
+                       (const VT_ *)val, len, istar, w.colptr, w.mask, w.off, nnz_dev, big_at, \
+                       w.fill, w.rowidx, (VT_ *)w.cval)
+#define FILLB(VT_)                                                                             \
+    hipLaunchKernelGGL((k_csc_fill_block<VT_>), dim3((unsigned)rb), dim3(256),                   \
+                       (size_t)CSC_TILE * CSC_RB * sizeof(VT_), st, (int)m, (int)n, col,          \
+                       (const VT_ *)val, len, istar, w.colptr, w.mask, w.off, nnz_dev, big_at, \
+                       w.fill, w.rowidx, (VT_ *)w.cval)
     if (f32) {
-        if (lpc >= 64)
-            FILL(64, float);
-        else
-            FILL(16, float);
+        if (w.fill != CSC_FILL_BLOCK) {
+            if (lpc >= 64)
+                FILL(64, float);
+            else
+                FILL(16, float);
+        }
+        if (w.fill != CSC_FILL_ENTRY)
+            FILLB(float);
     } else {
-        if (lpc >= 64)
-            FILL(64, double);
-        else
-            FILL(16, double);
+        if (w.fill != CSC_FILL_BLOCK) {
+            if (lpc >= 64)
+                FILL(64, double);
+            else
+                FILL(16, double);
+        }
+        if (w.fill != CSC_FILL_ENTRY)
+            FILLB(double);
     }
+#undef FILLB
 #undef FILL
     return hipGetLastError();
 }

@@ -26,6 +26,7 @@ IBSN_COST_POINTS = 2
 PREC_F64 = 0    # ibsn_precision
 PREC_MIXED = 1
 CG_AUTO, CG_LAUNCHES, CG_PERSISTENT, CG_SINGLE, CG_PIPE = 0, 1, 2, 3, 4   # ibsn_set_cg_kernel
+CSC_AUTO, CSC_ENTRY, CSC_BLOCK = 0, 1, 2   # ibsn_set_csc_fill
 WS_HEAD_FEATURES = 8   # per-target features of the learned warm start's head (fth columns)
 MAX_N_F64 = 10240
 
@@ -119,7 +120,7 @@ class _KernelTimes(ct.Structure):
 
 _lib = None
 EXPORTS = ("ibsn_create", "ibsn_destroy", "ibsn_last_error", "ibsn_num_cus", "ibsn_set_cg_kernel",
-           "ibsn_set_row_split", "ibsn_autotune",
+           "ibsn_set_row_split", "ibsn_set_csc_fill", "ibsn_autotune",
            "ibsn_center_init", "ibsn_center_quantum", "ibsn_sinkhorn_step", "ibsn_outer_update", "ibsn_subproblem_eval", "ibsn_trial", "ibsn_sparsify", "ibsn_csr_info",
            "ibsn_csr_export", "ibsn_csr_free", "ibsn_hvp", "ibsn_cg", "ibsn_stop",
            "ibsn_default_options", "ibsn_solve", "ibsn_kernel_timing", "ibsn_kernel_times_get",
@@ -147,6 +148,7 @@ def load():
     L.ibsn_num_cus.argtypes = [vp]
     L.ibsn_set_cg_kernel.argtypes = [vp, ct.c_int, ct.c_int]
     L.ibsn_set_row_split.argtypes = [vp, i64]
+    L.ibsn_set_csc_fill.argtypes = [vp, ct.c_int]
     L.ibsn_autotune.argtypes = [vp, ct.c_void_p, ct.POINTER(Tile)]
     L.ibsn_center_init.argtypes = [vp, P, vp, vp]
     L.ibsn_center_quantum.argtypes = [vp, P, C, vp, ct.POINTER(dbl)]
@@ -242,6 +244,10 @@ class Context:
         `cols` (0: only rows wider than the register tiles, in blocks of 10240 columns for an
         FP64 or points cost and 12288 for an FP32 cost)."""
         self.check(load().ibsn_set_row_split(self.h, int(cols)))
+
+    def set_csc_fill(self, mode: int = 0):
+        """ibsn_set_csc_fill: CSC_AUTO, CSC_ENTRY or CSC_BLOCK (the transpose's fill)."""
+        self.check(load().ibsn_set_csc_fill(self.h, int(mode)))
 
     def autotune(self, prob: "Problem | None"):
         """ibsn_autotune: choose and record the dense-pass tiles for problems of prob's shape
