@@ -253,14 +253,16 @@ __global__ __launch_bounds__(256) void k_csc_fill(int m, int n, const int32_t *_
     }
 }
 
-// fill by row block, for factors with many entries per row: one workgroup per block of
-// CSC_RB rows, the columns in tiles of CSC_TILE.  Each row's entries in the tile (a run of
-// its ascending slot, from a cursor kept per row) are staged in LDS at (column, row); then
-// thread (c, r) writes the entry of row r in column j0 + c, if the row keeps it, so that
-// the block's entries of a column go out as one contiguous run where the per-entry fill
-// scatters them one by one.  Wave w stages rows w CSC_RPW .. w CSC_RPW + CSC_RPW - 1, all
-// of their windows of WAVE entries loaded before any is used.
-constexpr int CSC_TILE = 256;
+// fill by row block, for factors with many entries per row: workgroup (b, y) takes the rows
+// of block b and the columns [y CSC_CHUNK, (y + 1) CSC_CHUNK), in tiles of CSC_TILE.  Each
+// row's entries in a tile (a run of its ascending slot, from a cursor kept per row and
+// started by a binary search for the chunk's first column) are staged in LDS at (column,
+// row); then thread (c, r) writes the entry of row r in column j0 + c, if the row keeps it,
+// so that the block's entries of a column go out as one contiguous run where the per-entry
+// fill scatters them one by one.  Wave w stages rows w CSC_RPW .. w CSC_RPW + CSC_RPW - 1,
+// all of their windows of WAVE entries loaded before any is used.
+constexpr int CSC_TILE = 128;
+constexpr int CSC_CHUNK = 1024;
 constexpr int CSC_RPW = CSC_RB / (256 / WAVE);
 
 template <typename VT>
@@ -281,10 +283,30 @@ __global__ __launch_bounds__(256) void k_csc_fill_block(int m, int n,
         return;
     extern __shared__ __align__(16) unsigned char csc_lds[];
     VT *tile = reinterpret_cast<VT *>(csc_lds);   // [column in tile][row in block]
+    __shared__ int start[CSC_RB];
     const int b = blockIdx.x, i0 = b * CSC_RB;
+    const int jb = (int)blockIdx.y * CSC_CHUNK, je = min(n, jb + CSC_CHUNK);
     const int istar = *istar_p;
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int rw0 = wv * CSC_RPW;   // the wave's first row in the block
+    // each row's first entry with a column >= jb
+    if (threadIdx.x < CSC_RB) {
+        const int i = i0 + (int)threadIdx.x;
+        int lo = 0, hi = 0;
+        if (i < m && i != istar) {
+            hi = len[i];
+            const int32_t *cr = col + (int64_t)i * n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cr[mid] < jb)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+        }
+        start[threadIdx.x] = lo;
+    }
+    __syncthreads();
     const uint32_t *mb = mask + (int64_t)b * n;
     const int32_t *ob = off + (int64_t)b * n;
     // per row: entries consumed so far (all with columns below the current tile) and length;
@@ -293,13 +315,13 @@ __global__ __launch_bounds__(256) void k_csc_fill_block(int m, int n,
 #pragma unroll
     for (int k = 0; k < CSC_RPW; ++k) {
         const int i = i0 + rw0 + k;
-        cur[k] = 0;
+        cur[k] = start[rw0 + k];
         rl[k] = (i < m && i != istar) ? len[i] : 0;
     }
     const int r = threadIdx.x % CSC_RB;
     const uint32_t below = (1u << r) - 1u;
-    for (int j0 = 0; j0 < n; j0 += CSC_TILE) {
-        const int j1 = min(n, j0 + CSC_TILE);
+    for (int j0 = jb; j0 < je; j0 += CSC_TILE) {
+        const int j1 = min(je, j0 + CSC_TILE);
         // stage: the entries with columns in [j0, j1) are a prefix of each row's remainder
         bool more = true;
         while (more) {
@@ -1097,7 +1119,8 @@ hipError_t launch_build_csc(int64_t m, int64_t n, const int32_t *col, const void
                        (const VT_ *)val, len, istar, w.colptr, w.mask, w.off, nnz_dev, big_at, \
                        w.fill, w.rowidx, (VT_ *)w.cval)
 #define FILLB(VT_)                                                                             \
-    hipLaunchKernelGGL((k_csc_fill_block<VT_>), dim3((unsigned)rb), dim3(256),                   \
+    hipLaunchKernelGGL((k_csc_fill_block<VT_>),                                                \
+                       dim3((unsigned)rb, (unsigned)((n + CSC_CHUNK - 1) / CSC_CHUNK)), dim3(256), \
                        (size_t)CSC_TILE * CSC_RB * sizeof(VT_), st, (int)m, (int)n, col,          \
                        (const VT_ *)val, len, istar, w.colptr, w.mask, w.off, nnz_dev, big_at, \
                        w.fill, w.rowidx, (VT_ *)w.cval)
