@@ -424,9 +424,9 @@ def main() -> int:
                     help="problems of the batched grid-histogram workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
-              "build (see the design notes for how it would shard); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the hot path on one GPU and "
+              "does not shard it across GPUs (the design notes say how it would); run with "
+              "--gpus 1", file=sys.stderr)
         return 2
 
     import torch
