@@ -80,3 +80,31 @@ def test_struct_layouts_match_header(tmp_path):
     assert offs[:no] == [getattr(ibsn.Options, f).offset for f in fields_o]
     assert offs[no:no + nr] == [getattr(ibsn.Report, f).offset for f in fields_r]
     assert offs[no + nr:] == [getattr(ibsn.IterRecord, f).offset for f in fields_t]
+
+
+def test_constants_match_header(tmp_path):
+    """The binding's mode and kind constants equal the header's enumerators, compiled from
+    the header with the host C compiler."""
+    import shutil
+    import subprocess
+    from paper_2603_07156_amd import ibsn
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"IBSN_OK": ibsn.IBSN_OK, "IBSN_WARN_MAXITER": ibsn.IBSN_WARN_MAXITER,
+             "IBSN_NOALLOC_MAX_M": ibsn.NOALLOC_MAX_M, "IBSN_COST_POINTS": ibsn.IBSN_COST_POINTS,
+             "IBSN_PREC_F64": ibsn.PREC_F64, "IBSN_PREC_MIXED": ibsn.PREC_MIXED,
+             "IBSN_CG_AUTO": ibsn.CG_AUTO, "IBSN_CG_LAUNCHES": ibsn.CG_LAUNCHES,
+             "IBSN_CG_PERSISTENT": ibsn.CG_PERSISTENT, "IBSN_CG_SINGLE": ibsn.CG_SINGLE,
+             "IBSN_CG_PIPE": ibsn.CG_PIPE, "IBSN_CSC_AUTO": ibsn.CSC_AUTO,
+             "IBSN_CSC_ENTRY": ibsn.CSC_ENTRY, "IBSN_CSC_BLOCK": ibsn.CSC_BLOCK}
+    nl = "\\n"
+    src = ['#include <stdio.h>', '#include "ibsn.h"', "int main(void) {"]
+    src += [f'printf("%lld{nl}", (long long)({k}));' for k in pairs]
+    src += ["return 0; }"]
+    c = tmp_path / "consts.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "consts"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert [int(x) for x in out] == list(pairs.values())
