@@ -198,7 +198,7 @@ def solve_to_gap(ibsn, ctx, prob, precision, gap=1e-8, max_outer=20000, gamma0_f
             "kernel_ms": kt_dict(kt)}
 
 
-def points_problem(ibsn, inst, prob, precision):
+def points_problem(ibsn, inst, prob, precision, scale=None):
     """The same instance with its cost formed from the points in every pass (no m x n
     array): C_ij = scale |x_i - y_j|^2 with scale = 1 / max, the stored cost to rounding."""
     import numpy as np
@@ -208,8 +208,9 @@ def points_problem(ibsn, inst, prob, precision):
     dev = prob.C.device
     x = torch.from_numpy(np.ascontiguousarray(inst.x)).to(dev)
     y = torch.from_numpy(np.ascontiguousarray(inst.y)).to(dev)
-    return ibsn.Problem.from_points(x, y, prob.a, prob.b, prob.eta,
-                                    workloads.points_scale(inst.x, inst.y), precision)
+    if scale is None:
+        scale = workloads.points_scale(inst.x, inst.y)
+    return ibsn.Problem.from_points(x, y, prob.a, prob.b, prob.eta, scale, precision)
 
 
 def warm_start_fn(ibsn, ctx, prob, inst):
@@ -528,7 +529,7 @@ def main() -> int:
                                                      "(scale = 1 / max |x_i - y_j|^2)")
             ttg["warm_f64_points"] = solve_to_gap(
                 ibsn, ctx, prob, ibsn.PREC_F64, gamma0_fn=fn_pts,
-                problem=points_problem(ibsn, inst, prob, ibsn.PREC_F64))
+                problem=points_problem(ibsn, inst, prob, ibsn.PREC_F64, pts.cost_scale))
             ttg["warm_f64_points"]["cost"] = ttg["warm_mixed_fp32_points"]["cost"]
             held_pts[0].free()
             held[0].free()
